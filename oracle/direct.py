@@ -1,0 +1,125 @@
+"""Definition-level solves: real-space stencils and a sparse direct solver.
+
+No Fourier transform appears here.  The forward-difference gradient of
+Sec. 2.5 is the periodic stencil (f(x + h e_a) - f(x)) / h, assembled as a
+sparse matrix B_a; its transpose is the (negative) divergence.  Each discrete
+problem of the path is written as the stationarity condition it encodes and
+solved with ``scipy.sparse.linalg.spsolve``:
+
+* mechanics (Sec. 2.3): minimise sum_x (E0 + sym grad u) : gC : (E0 + sym grad u)
+  over periodic u, E0 = eps_mac - e I; the range of the projection of App. A is
+  exactly {grad u}, so this is the solution the projected CG reaches;
+* phase field (Sec. 2.4): [diag(Gc/(2 l0) + H) + (Gc l0/2) sum_a B_a^T B_a] d = H;
+* diffusion step: [diag(1/dt + k_r) + sum_a B_a^T diag(D) B_a] c = c^n/dt on the
+  free voxels, with c = c_dir held on the Dirichlet band.
+"""
+import numpy as np
+import scipy.sparse as sps
+import scipy.sparse.linalg as spla
+
+from . import material as _mat
+from . import mech as _mech
+
+
+def fwd_diff_matrix(grid, alpha, h):
+    grid = tuple(grid)
+    dim = len(grid)
+    N = int(np.prod(grid))
+    idx = np.arange(N).reshape(grid)
+    nbr = np.roll(idx, -1, axis=dim - 1 - alpha)
+    S = sps.csr_matrix((np.ones(N), (idx.ravel(), nbr.ravel())), shape=(N, N))
+    return ((S - sps.identity(N, format="csr")) / h).tocsr()
+
+
+def _stiffness_matrix(glam, gmu):
+    """Sparse map eps -> sigma on tensor fields stored [i][j][x]."""
+    dim = glam.ndim
+    N = glam.size
+    Lam = sps.diags(glam.ravel())
+    Mu2 = sps.diags(2.0 * gmu.ravel())
+    blocks = [[None] * (dim * dim) for _ in range(dim * dim)]
+    Z = sps.csr_matrix((N, N))
+    for i in range(dim):
+        for j in range(dim):
+            for k in range(dim):
+                for l in range(dim):
+                    m = Z
+                    if i == j and k == l:
+                        m = m + Lam
+                    if i == k and j == l:
+                        m = m + Mu2
+                    blocks[i * dim + j][k * dim + l] = m
+    return sps.bmat(blocks, format="csr")
+
+
+def _symgrad_matrix(grid, h):
+    """Sparse map u (stored [i][x]) -> sym(grad u) (stored [i][j][x])."""
+    dim = len(grid)
+    N = int(np.prod(grid))
+    B = [fwd_diff_matrix(grid, a, h) for a in range(dim)]
+    Z = sps.csr_matrix((N, N))
+    rows = []
+    for i in range(dim):
+        for j in range(dim):
+            row = [Z] * dim
+            row[i] = row[i] + 0.5 * B[j]
+            row[j] = row[j] + 0.5 * B[i]
+            rows.append(row)
+    return sps.bmat(rows, format="csr")
+
+
+def mech_direct(phase, E_tab, nu_tab, eps_mac, h, d=None, kappa=0.0, e=None,
+                E_field=None, nu=None):
+    phase = np.asarray(phase)
+    grid = phase.shape
+    dim = phase.ndim
+    N = phase.size
+    lam, mu = _mech.voxel_lame(phase, E_tab, nu_tab, E_field, nu)
+    g = np.ones(grid) if d is None else _mat.degradation(np.asarray(d), kappa)
+    C = _stiffness_matrix(g * lam, g * mu)
+    L = _symgrad_matrix(grid, h)
+    E0 = _mech.macro_tensor(eps_mac, dim, grid) - _mech.eigen_tensor(e, dim, grid)
+    K = (L.T @ C @ L).tocsc()
+    f = -(L.T @ (C @ E0.reshape(-1)))
+    # rigid translations: pin u_i at voxel 0
+    keep = np.ones(dim * N, dtype=bool)
+    keep[[i * N for i in range(dim)]] = False
+    u = np.zeros(dim * N)
+    u[keep] = spla.spsolve(K[keep][:, keep], f[keep])
+    eps = _mech.macro_tensor(eps_mac, dim, grid) + (L @ u).reshape((dim, dim) + grid)
+    el = eps - _mech.eigen_tensor(e, dim, grid)
+    sig = _mat.stress(el, g * lam, g * mu)
+    return dict(strain=_mat.to_voigt(eps), stress=_mat.to_voigt(sig),
+                mean_stress=np.array([np.mean(s) for s in _mat.to_voigt(sig)]),
+                energy=0.5 * h ** dim * float(np.sum(el * sig)))
+
+
+def phasefield_direct(H, Gc, l0, h):
+    H = np.asarray(H, dtype=np.float64)
+    grid = H.shape
+    B = [fwd_diff_matrix(grid, a, h) for a in range(H.ndim)]
+    A = sps.diags((Gc / (2.0 * l0) + H).ravel())
+    for Ba in B:
+        A = A + 0.5 * Gc * l0 * (Ba.T @ Ba)
+    return spla.spsolve(A.tocsc(), H.ravel()).reshape(grid)
+
+
+def diffusion_direct(c_n, Dfield, react, dt, h, band=None, c_dir=1.0):
+    c_n = np.asarray(c_n, dtype=np.float64)
+    grid = c_n.shape
+    B = [fwd_diff_matrix(grid, a, h) for a in range(c_n.ndim)]
+    Dd = sps.diags(np.broadcast_to(Dfield, grid).ravel())
+    A = sps.diags((1.0 / dt + np.broadcast_to(react, grid)).ravel())
+    for Ba in B:
+        A = A + Ba.T @ Dd @ Ba
+    A = A.tocsr()
+    rhs = c_n.ravel() / dt
+    if band is None:
+        return spla.spsolve(A.tocsc(), rhs).reshape(grid)
+    band = np.asarray(band, dtype=bool).ravel()
+    free = ~band
+    cB = np.where(band, c_dir, 0.0)
+    rhsF = rhs[free] - A[free][:, band] @ cB[band]
+    c = cB.copy()
+    c[free] = spla.spsolve(A[free][:, free].tocsc(), rhsF)
+    return c.reshape(grid)
