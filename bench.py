@@ -1,0 +1,167 @@
+"""Benchmark: FP64 staggered corrosion-fracture steps on a 1024^2 fractal.
+
+Workload (one "step" = one pass of the whole hot path): a 2D 1024 x 1024
+periodic grid, h = 5 um, with a seeded box-removal fractal pore mask (8
+levels, number-size exponent 1.8, porosity 0.3); one staggered step =
+transient ferrous-ion diffusion (D = 1e-9 / 1e-12 m^2/s in pores / solid,
+Dirichlet band x < 16 px, sink k = 1e-3 /s in pores, dt = 40 s) ->
+precipitation and pore eigenstrain (0.5 % per unit precipitate) ->
+projected-CG mechanics (E = 30 GPa / 3 MPa, nu = 0.2, degraded by the
+damage) -> history update -> AT2 phase field (Gc = 50 J/m^2, l0 = 2 px), all
+CG tolerances 1e-8, FP64.  Synthetic inputs, resident in HBM before timing.
+
+value = total voxel-CG-iterations (all three solvers) / wall time of the
+timed steps.  The roofline block reports the dominant kernel (largest summed
+device time of the mechanics passes) from HIP events recorded on the
+library's stream around every launch of that kernel during the timed steps;
+its algorithmic bytes per voxel are listed in ALGO_BYTES.  The CPU baseline
+times the FP64 oracle on two mechanics CG iterations of the same 1024^2
+problem.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_SIDE = 1024
+H = 5e-6
+HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes per voxel per launch of the FP64 mechanics CG passes
+# (n_c = 4 gradient components, n_s = 3 stress components, 16-byte complex
+# half spectrum of 513 x 1024 modes = 8.0156 B per voxel per component):
+#   row_fwd: read r, p (64) + phase (1) + damage (8), write p (32), write 3 spectra (24.05)
+#   col    : read 3 spectra (24.05), write 4 spectra (32.06)
+#   row_inv: read 4 spectra (32.06), read x, r, p (96), write x, r (64)
+SPEC_B = 16.0 * (N_SIDE // 2 + 1) / N_SIDE
+ALGO_BYTES = {
+    "mech_row_fwd": 64 + 1 + 8 + 32 + 3 * SPEC_B,
+    "mech_col": 3 * SPEC_B + 4 * SPEC_B,
+    "mech_row_inv": 4 * SPEC_B + 96 + 64,
+}
+
+
+def c2_params():
+    return dict(E_tab=(3e6, 30e9), nu_tab=(0.2, 0.2), D_tab=(1e-9, 1e-12), k_tab=(1e-3, 0.0), band_width=16,
+                c_dir=1.0, dt=40.0, e_per_f=0.005, Gc=50.0, l0=2 * H, kappa=1e-6, eps_mac=(0.0, 0.0, 0.0),
+                tol_diff=1e-8, tol_mech=1e-8, tol_pf=1e-8, maxit=200000, diffuse=1)
+
+
+def cpu_baseline(phase):
+    """FP64 oracle: two mechanics CG iterations at 1024^2 (the same operator)."""
+    from oracle import cg as ocg, mech as omech, spectral as osp
+
+    e = np.where(phase == 0, 1e-3, 0.0)
+    lam, mu = omech.voxel_lame(phase, (3e6, 30e9), (0.2, 0.2))
+    D = osp.grad_symbols(phase.shape, H)
+    E0 = omech.macro_tensor((0.0, 0.0, 0.0), 2, phase.shape) - omech.eigen_tensor(e, 2, phase.shape)
+    b = -omech.mech_operator(E0, lam, mu, D, "full")
+    A = lambda p: omech.mech_operator(p, lam, mu, D, "full")
+    iters = 2
+    t0 = time.perf_counter()
+    ocg.cg(A, b, fixed_iters=iters)
+    dt = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"value": phase.size * iters / dt, "unit": "voxel-CG-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"2 FP64 mechanics CG iterations of the oracle (naive recursive DFT) at 1024^2, "
+                      f"{dt:.1f} s, single thread (host has {cores} cores available)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (this build has no "
+              f"multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2305_13081_amd import fgcg, inputs
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    phase_np, finfo = inputs.c2_microstructure(N_SIDE)
+    phase = torch.from_numpy(phase_np).to(dev)
+    ctx = fgcg.Context(N_SIDE, N_SIDE, H)
+    prm = c2_params()
+    state = ctx.new_state(band_width=prm["band_width"], c_dir=prm["c_dir"])
+    for w in range(args.warmup):
+        info = ctx.staggered_step(state, phase, prm)
+        print(f"warmup step {w}: iters diff {info['diff']['iters']} mech {info['mech']['iters']} "
+              f"pf {info['pf']['iters']}", file=sys.stderr, flush=True)
+    mech_kinds = ["mech_row_fwd", "mech_col", "mech_row_inv"]
+    ctx.profile(mech_kinds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(args.steps):
+        infos.append(ctx.staggered_step(state, phase, prm))
+        i = infos[-1]
+        print(f"step {k}: iters diff {i['diff']['iters']} mech {i['mech']['iters']} pf {i['pf']['iters']} "
+              f"({i['diff']['seconds']:.3f}/{i['mech']['seconds']:.3f}/{i['pf']['seconds']:.3f} s) "
+              f"max d {i['max_d']:.3e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    nvox = N_SIDE * N_SIDE
+    it = {s: sum(i[s]["iters"] for i in infos) for s in ("diff", "mech", "pf")}
+    secs = {s: sum(i[s]["seconds"] for i in infos) for s in ("diff", "mech", "pf")}
+    total_iters = sum(it.values())
+    value = nvox * total_iters / elapsed
+    prof = {k: ctx.profile_read(k) for k in mech_kinds}
+    dom = max(mech_kinds, key=lambda k: prof[k][0])
+    ms, launches, kname = prof[dom]
+    avg_s = ms / 1e3 / max(launches, 1)
+    achieved = ALGO_BYTES[dom] * nvox / avg_s / 1e9
+    per_kernel = {k: {"avg_us": prof[k][0] * 1e3 / max(prof[k][1], 1), "launches": prof[k][1],
+                      "algo_bytes_per_voxel": round(ALGO_BYTES[k], 3),
+                      "achieved_GBs": ALGO_BYTES[k] * nvox / (prof[k][0] / 1e3 / max(prof[k][1], 1)) / 1e9,
+                      "kernel": prof[k][2]} for k in mech_kinds}
+    out = {
+        "metric": "voxel-CG-iters/s",
+        "value": value,
+        "unit": "voxel-CG-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D 1024x1024 box-removal fractal (8 levels, D 1.8, porosity 0.3), FP64 "
+                               "staggered step: diffusion + mechanics + AT2 phase field, CG tol 1e-8",
+                   "grid": [N_SIDE, N_SIDE], "h": H, "porosity": finfo["porosity"],
+                   "parallelism": "single GPU"},
+        "breakdown": {
+            "iters": it, "seconds": secs,
+            "voxel_cg_iters_per_s": {s: (nvox * it[s] / secs[s] if secs[s] > 0 else None) for s in it},
+            "mech_kernels": per_kernel,
+        },
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
+                     "algo_bytes_per_launch": ALGO_BYTES[dom] * nvox, "avg_launch_us": avg_s * 1e6},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(phase_np)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

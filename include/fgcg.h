@@ -1,0 +1,206 @@
+/*
+ * fgcg -- Fourier-Galerkin projected conjugate gradients on MI355X (gfx950).
+ *
+ * C ABI of the hot path of the FFT-based corrosion-fracture framework of
+ * Pundir, Kammer and Angst (arXiv 2305.13081):
+ *
+ *   mechanics   Sec. 2.3, eq. solid / eq. solid-final, projection of App. A:
+ *               div( g(d) C(x) : (eps - e I) ) = 0, <eps> = eps_mac
+ *   phase field Sec. 2.4, eq. crack / eq. crack-fft (AT2, history field H)
+ *   diffusion   Sec. 2.1 (Fick's law, D mixed per phase), here one implicit
+ *               time step with a first-order sink and a Dirichlet source band
+ *   staggered   Alg. 1: diffusion -> precipitation/eigenstrain -> mechanics ->
+ *               history -> phase field
+ *
+ * Every gradient is the forward difference of Sec. 2.5,
+ * D_a(k) = (exp(2 pi i k_a / n_a) - 1) / h.
+ *
+ * Conventions
+ *   - Grids are periodic, 2D with n[0] = nx (fastest) and n[1] = ny; every
+ *     axis length is 2^a 3^b between 8 and 2048.
+ *   - Field pointers are DEVICE pointers owned by the caller, contiguous,
+ *     component-major: [comp][ny][nx].  Host pointers are marked "host".
+ *   - Strain and stress use Voigt order (11, 22, 12) with TENSOR shear
+ *     (eps_12, not gamma_12); phase ids are uint8 (0 = pore, 1 = solid, up to
+ *     FGCG_MAX_PHASES phases).
+ *   - All work is enqueued on the context's HIP stream; calls that return an
+ *     fgcg_info or host scalars return after the stream has finished them.
+ *   - The context owns every workspace buffer; solves allocate nothing.
+ *   - Errors are returned as status codes, never thrown.  A detail string for
+ *     the last error of the calling thread is available from fgcg_last_error.
+ *   - A context may be used by one thread at a time.
+ */
+#ifndef FGCG_H
+#define FGCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FGCG_MAX_PHASES 8
+
+typedef enum {
+  FGCG_OK = 0,
+  FGCG_NOT_CONVERGED = 1, /* warning: outputs hold the last iterate */
+  FGCG_EINVAL = -1,       /* null required pointer, bad size, tol < 0, ... */
+  FGCG_EDOMAIN = -2,      /* E <= 0, nu outside (-1, 0.5), dt/l0/Gc/h <= 0, non-finite input */
+  FGCG_EBREAKDOWN = -3,   /* CG breakdown: p.Ap <= 0 or a non-finite scalar */
+  FGCG_ENOMEM = -4,
+  FGCG_EHIP = -5,         /* a HIP runtime call failed */
+  FGCG_EUNSUPPORTED = -6  /* valid request this build does not implement */
+} fgcg_status;
+
+typedef enum { FGCG_FP64 = 0, FGCG_FP32_MIXED = 1 } fgcg_precision;
+
+typedef struct {
+  int ndim;      /* 2 */
+  int n[3];      /* n[0] = nx, n[1] = ny, n[2] = nz (unused in 2D) */
+  double h;      /* voxel size, > 0 */
+  int precision; /* fgcg_precision */
+} fgcg_grid;
+
+/* Isotropic elastic material mixed voxel by voxel (Sec. 2.3):
+ * C(x) = lambda(x) I (x) I + 2 mu(x) II, plane strain in 2D. */
+typedef struct {
+  const uint8_t* phase;  /* device [N], phase id per voxel */
+  int nphase;            /* 1..FGCG_MAX_PHASES */
+  const double* E_tab;   /* host [nphase], Young's modulus per phase (Pa) */
+  const double* nu_tab;  /* host [nphase], Poisson ratio per phase */
+  const double* E_field; /* device [N] or NULL: per-voxel Young's modulus, overrides E_tab */
+  double nu_field;       /* uniform Poisson ratio used with E_field */
+} fgcg_material;
+
+typedef struct {
+  int iters;           /* CG iterations taken */
+  int status;          /* fgcg_status of this solve */
+  double rel_res;      /* ||r_k|| / ||b|| from the CG recurrence */
+  double bnorm;        /* ||b|| */
+  double seconds;      /* wall time of the solve (host clock) */
+} fgcg_info;
+
+typedef struct fgcg_ctx fgcg_ctx;
+
+/* Create a context for one grid.  hip_stream: a hipStream_t or NULL (the
+ * null stream).  Allocates all workspace.  Returns EINVAL for unsupported
+ * sizes, EDOMAIN for h <= 0. */
+int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out);
+void fgcg_destroy(fgcg_ctx* ctx);
+int fgcg_set_stream(fgcg_ctx* ctx, void* hip_stream);
+const char* fgcg_strerror(int status);
+const char* fgcg_last_error(void);
+
+/* Mechanical equilibrium with isotropic eigenstrain e(x) I (Sec. 2.3,
+ * eq. solid): solves G[g C : sym(x)] = -G[g C : (eps_mac - e I)] for the
+ * compatible fluctuation x (full displacement gradient, 4 components) by CG
+ * from x = 0, stopping when ||r|| <= tol ||b|| or after maxit iterations
+ * (tol = 0 runs exactly maxit iterations).
+ *   d        device [N] damage or NULL (d = 0); g = (1 - d)^2 + kappa
+ *   eig      device [N] scalar eigenstrain e or NULL (0)
+ *   eps_mac  host [3] macroscopic strain (Voigt, tensor shear)
+ *   strain   device [3][N] out: eps = eps_mac + sym(x)
+ *   stress   device [3][N] out or NULL: sigma = g C : (eps - e I)
+ *   mean_stress host [3] out or NULL: mean of sigma over all voxels
+ *   energy   host out or NULL: W = h^2/2 sum_x (eps - e I) : sigma
+ */
+int fgcg_mech_solve(fgcg_ctx* ctx, const fgcg_material* mat, const double* d, double kappa,
+                    const double* eig, const double* eps_mac, double tol, int maxit,
+                    double* strain, double* stress, double* mean_stress, double* energy,
+                    fgcg_info* info);
+
+/* AT2 phase field (Sec. 2.4, eq. crack-fft) with the Laplacian taken as
+ * -D^H D: [(Gc/(2 l0) + H) + (Gc l0 / 2) F^-1 |D|^2 F] d = H, solved by CG
+ * starting from the d passed in (in: d^n, out: d^{n+1}).  H device [N]. */
+int fgcg_phasefield_solve(fgcg_ctx* ctx, const double* H, double Gc, double l0, double* d,
+                          double tol, int maxit, fgcg_info* info);
+
+/* One backward-Euler step of dc/dt = div(D(x) grad c) - k(x) c (Sec. 2.1
+ * flux with per-phase D and sink k): [(1/dt + k) - div D grad] c = c^n/dt.
+ * Voxels with x index < band_width hold c = c_dir (Dirichlet source band);
+ * CG runs on the free voxels from c^n.  c: device [N], in c^n, out c^{n+1}.
+ * D_tab, k_tab: host [nphase]. */
+int fgcg_diffusion_step(fgcg_ctx* ctx, const uint8_t* phase, int nphase, const double* D_tab,
+                        const double* k_tab, int band_width, double c_dir, double dt, double* c,
+                        double tol, int maxit, fgcg_info* info);
+
+/* Staggered corrosion-fracture step (Alg. 1).  State fields are device [N]
+ * (strain: [3][N]) owned by the caller and updated in place. */
+typedef struct {
+  double* c;      /* ferrous-ion concentration (normalised) */
+  double* f;      /* precipitate volume fraction */
+  double* e;      /* isotropic eigenstrain */
+  double* H;      /* history field max psi+ */
+  double* d;      /* damage */
+  double* strain; /* [3][N] last total strain */
+  int step;
+} fgcg_state;
+
+typedef struct {
+  fgcg_material mat;
+  const double* D_tab; /* host [nphase] diffusion coefficient per phase */
+  const double* k_tab; /* host [nphase] first-order precipitation rate per phase */
+  int band_width;      /* Dirichlet band x < band_width, c = c_dir */
+  double c_dir;
+  double dt;
+  double e_per_f;      /* eigenstrain per unit precipitate fraction (pores only) */
+  double Gc, l0, kappa;
+  double eps_mac[3];
+  double tol_diff, tol_mech, tol_pf;
+  int maxit;
+  int diffuse;         /* 0: skip diffusion, prescribe e = e_ramp (step+1)/n_ramp in pores */
+  double e_ramp;
+  int n_ramp;
+} fgcg_params;
+
+typedef struct {
+  fgcg_info diff, mech, pf;
+  double mean_stress[3];
+  double energy;
+  double max_d;
+  double damaged_fraction;   /* share of solid voxels with d > 0.9 */
+  double porosity_increase;  /* sum of d over solid voxels / N */
+  double total_precipitate;  /* sum of f */
+} fgcg_step_info;
+
+int fgcg_staggered_step(fgcg_ctx* ctx, fgcg_state* state, const fgcg_params* prm,
+                        fgcg_step_info* info);
+
+/* ---- kernel-level test hooks ------------------------------------------ */
+/* q = G[g C : sym(p)] for a full gradient p (device [4][N] each). */
+int fgcg_mech_apply(fgcg_ctx* ctx, const fgcg_material* mat, const double* d, double kappa,
+                    const double* p, double* q);
+/* q = (Gc/(2 l0) + H) v + (Gc l0/2) F^-1 |D|^2 F v. */
+int fgcg_phasefield_apply(fgcg_ctx* ctx, const double* H, double Gc, double l0, const double* v,
+                          double* q);
+/* q = (1/dt + k) v + sum_a F^-1 conj(D_a) F D(x) F^-1 D_a F v (no band). */
+int fgcg_diffusion_apply(fgcg_ctx* ctx, const uint8_t* phase, int nphase, const double* D_tab,
+                         const double* k_tab, double dt, const double* v, double* q);
+
+/* ---- profiling -------------------------------------------------------- */
+/* Kernel kinds that can be timed with HIP events around every launch. */
+enum {
+  FGCG_K_MECH_ROW_FWD = 0,
+  FGCG_K_MECH_COL = 1,
+  FGCG_K_MECH_ROW_INV = 2,
+  FGCG_K_PF_ROW_FWD = 3,
+  FGCG_K_PF_COL = 4,
+  FGCG_K_PF_ROW_INV = 5,
+  FGCG_K_DIFF_ROW_FWD = 6,
+  FGCG_K_DIFF_COL_GRAD = 7,
+  FGCG_K_DIFF_ROW_MID = 8,
+  FGCG_K_DIFF_COL_DIV = 9,
+  FGCG_K_DIFF_ROW_INV = 10,
+  FGCG_K_NKINDS = 11
+};
+/* mask: bit k enables event timing of kind k (0 disables); resets counters. */
+int fgcg_profile(fgcg_ctx* ctx, unsigned mask);
+/* Accumulated device time (ms) and launch count of kind k since fgcg_profile. */
+int fgcg_profile_read(fgcg_ctx* ctx, int kind, double* ms, long long* launches);
+/* Kernel symbol name of kind k (for matching profiler output). */
+const char* fgcg_kernel_name(fgcg_ctx* ctx, int kind);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

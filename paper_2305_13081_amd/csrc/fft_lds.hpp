@@ -1,0 +1,201 @@
+// LDS-staged Stockham autosort FFT for gfx950 (64-lane wavefronts).
+//
+// A workgroup transforms NSIG contiguous signals of length N held in LDS.
+// Each stage of radix R reads R strided values per butterfly, applies the
+// twiddles exp(-2 pi i k r / (Ns R)) (k = position inside the current
+// sub-transform of length Ns), runs an R-point DFT in registers and writes
+// the results to their self-sorted positions (j / Ns) * Ns * R + k + r * Ns.
+// The transform is in place: every thread loads all of its butterflies into
+// registers, the workgroup synchronises, then stores.  Twiddles come from a
+// per-length table tw[t] = exp(-2 pi i t / N) built once on the host in FP64.
+//
+// Radix plan for N = 3^a 2^b: the 3s first, then radix 8, with 8*2 -> 4*4 and
+// a single trailing 4 so that no radix-2 pass is needed for b >= 2.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fgcg {
+
+template <typename T> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C> __device__ __forceinline__ C cconj(C a) { return C{a.x, -a.y}; }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename C> __device__ __forceinline__ C cmul_mi(C a) {
+  return INV ? C{-a.y, a.x} : C{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------- radix plan
+constexpr int count3(int n) { return n % 3 == 0 ? 1 + count3(n / 3) : 0; }
+constexpr int pow3(int a) { return a == 0 ? 1 : 3 * pow3(a - 1); }
+constexpr int log2i(int n) { return n <= 1 ? 0 : 1 + log2i(n / 2); }
+
+struct Plan {
+  int n;
+  int nst;
+  int r[16];
+};
+
+constexpr Plan make_plan(int N) {
+  Plan p{N, 0, {0}};
+  int a = count3(N);
+  int b = log2i(N / pow3(a));
+  for (int i = 0; i < a; ++i) p.r[p.nst++] = 3;
+  int n8 = b / 3, rem = b % 3;
+  int n4 = 0, n2 = 0;
+  if (rem == 2) n4 = 1;
+  if (rem == 1) {
+    if (n8 > 0) { n8 -= 1; n4 = 2; } else { n2 = 1; }
+  }
+  for (int i = 0; i < n8; ++i) p.r[p.nst++] = 8;
+  for (int i = 0; i < n4; ++i) p.r[p.nst++] = 4;
+  for (int i = 0; i < n2; ++i) p.r[p.nst++] = 2;
+  return p;
+}
+
+constexpr bool fft_size_ok(int N) {
+  return N >= 2 && (N / pow3(count3(N))) * pow3(count3(N)) == N &&
+         ((N / pow3(count3(N))) & ((N / pow3(count3(N))) - 1)) == 0;
+}
+
+// ----------------------------------------------------------- small DFTs
+template <int R, bool INV, typename T> struct Dft;
+
+template <bool INV, typename T> struct Dft<2, INV, T> {
+  using C = typename cvec<T>::type;
+  static __device__ __forceinline__ void run(C* v) {
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <bool INV, typename T> struct Dft<3, INV, T> {
+  using C = typename cvec<T>::type;
+  static __device__ __forceinline__ void run(C* v) {
+    const T s = (T)0.86602540378443864676372317075294;  // sin(2 pi / 3)
+    C a0 = v[0], a1 = v[1], a2 = v[2];
+    C sum = cadd(a1, a2);
+    C dif = csub(a1, a2);
+    C t = C{a0.x - (T)0.5 * sum.x, a0.y - (T)0.5 * sum.y};
+    // forward: -i s (a1 - a2); inverse: +i s (a1 - a2)
+    C u = cmul_mi<INV>(C{s * dif.x, s * dif.y});
+    v[0] = cadd(a0, sum);
+    v[1] = cadd(t, u);
+    v[2] = csub(t, u);
+  }
+};
+
+template <bool INV, typename T> struct Dft<4, INV, T> {
+  using C = typename cvec<T>::type;
+  static __device__ __forceinline__ void run(C* v) {
+    C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    C s13 = cadd(v[1], v[3]), d13 = cmul_mi<INV>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+  }
+};
+
+template <bool INV, typename T> struct Dft<8, INV, T> {
+  using C = typename cvec<T>::type;
+  static __device__ __forceinline__ void run(C* v) {
+    const T r2 = (T)0.70710678118654752440084436210485;
+    C e[4] = {v[0], v[2], v[4], v[6]};
+    C o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<4, INV, T>::run(e);
+    Dft<4, INV, T>::run(o);
+    // o[k] *= exp(-+ 2 pi i k / 8)
+    C o1 = o[1], o3 = o[3];
+    if (!INV) {
+      o[1] = C{r2 * (o1.x + o1.y), r2 * (o1.y - o1.x)};
+      o[3] = C{r2 * (o3.y - o3.x), -r2 * (o3.x + o3.y)};
+    } else {
+      o[1] = C{r2 * (o1.x - o1.y), r2 * (o1.x + o1.y)};
+      o[3] = C{-r2 * (o3.x + o3.y), r2 * (o3.x - o3.y)};
+    }
+    o[2] = cmul_mi<INV>(o[2]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = cadd(e[k], o[k]);
+      v[k + 4] = csub(e[k], o[k]);
+    }
+  }
+};
+
+// ------------------------------------------------------------ one stage
+template <typename T, int N, int R, int NS, int NSIG, int NT, bool INV>
+__device__ __forceinline__ void stockham_stage(typename cvec<T>::type* buf,
+                                               const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  constexpr int M = N / R;
+  constexpr int TOT = NSIG * M;
+  constexpr int PER = (TOT + NT - 1) / NT;
+  constexpr int TSTEP = N / (NS * R);
+  C v[PER][R];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + q * NT;
+    if (TOT % NT == 0 || b < TOT) {
+      const int sig = b / M, j = b - sig * M;
+      const C* s = buf + sig * N;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = s[j + r * M];
+      if (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C w = tw[k * r * TSTEP];
+          if (INV) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+      Dft<R, INV, T>::run(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + q * NT;
+    if (TOT % NT == 0 || b < TOT) {
+      const int sig = b / M, j = b - sig * M;
+      const int k = j % NS;
+      C* s = buf + sig * N + (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[r * NS] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int N, int NSIG, int NT, bool INV, int ST, int NS>
+struct StageRunner {
+  static __device__ __forceinline__ void run(typename cvec<T>::type* buf,
+                                             const typename cvec<T>::type* __restrict__ tw) {
+    constexpr Plan p = make_plan(N);
+    if constexpr (ST < p.nst) {
+      constexpr int R = p.r[ST];
+      stockham_stage<T, N, R, NS, NSIG, NT, INV>(buf, tw);
+      StageRunner<T, N, NSIG, NT, INV, ST + 1, NS * R>::run(buf, tw);
+    }
+  }
+};
+
+// Transform NSIG signals of length N in LDS; callers synchronise before.
+// Forward uses exp(-2 pi i k x / N); inverse uses exp(+...) without 1/N.
+template <typename T, int N, int NSIG, int NT, bool INV>
+__device__ __forceinline__ void fft_lds(typename cvec<T>::type* buf,
+                                        const typename cvec<T>::type* __restrict__ tw) {
+  static_assert(fft_size_ok(N), "FFT length must be 2^a 3^b");
+  StageRunner<T, N, NSIG, NT, INV, 0, 1>::run(buf, tw);
+}
+
+}  // namespace fgcg

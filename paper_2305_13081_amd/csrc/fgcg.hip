@@ -1,0 +1,765 @@
+// Host engine of the fgcg C ABI: context and workspace, pass launches, the
+// chunked CG driver, and the entry points declared in include/fgcg.h.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+#include "fgcg.h"
+#include "pointwise.hpp"
+
+using namespace fgcg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess) return fail(FGCG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T> using CT = typename cvec<T>::type;
+
+// Supported axis lengths (2^a 3^b).  Each length instantiates the pass kernels.
+#define FGCG_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(2048)
+
+template <class F> bool with_n(int n, F&& f) {
+  switch (n) {
+#define FGCG_CASE(N)                       \
+  case N:                                  \
+    f(std::integral_constant<int, N>{});   \
+    return true;
+    FGCG_SIZES(FGCG_CASE)
+#undef FGCG_CASE
+    default:
+      return false;
+  }
+}
+
+bool size_supported(int n) {
+  return with_n(n, [](auto) {});
+}
+
+}  // namespace
+
+struct fgcg_ctx {
+  int nx = 0, ny = 0, nxh = 0;
+  long long n = 0;
+  double h = 0;
+  int prec = FGCG_FP64;
+  hipStream_t stream = nullptr;
+  void* twx = nullptr;  // CT<T>[nx]
+  void* twy = nullptr;  // CT<T>[ny]
+  double2* Dx = nullptr;
+  double2* Dy = nullptr;
+  void* x = nullptr;
+  void* r = nullptr;
+  void* p = nullptr;
+  void* tmp = nullptr;
+  void* spec = nullptr;
+  CgState* st = nullptr;
+  CgState* h_st = nullptr;
+  double* part_a = nullptr;
+  double* part_rr = nullptr;
+  double* part_b = nullptr;
+  double* part_post = nullptr;
+  double* h_part = nullptr;
+  int nrow = 0, ncol = 0, npost = 0;
+  unsigned prof_mask = 0;
+  double prof_ms[FGCG_K_NKINDS] = {0};
+  long long prof_n[FGCG_K_NKINDS] = {0};
+  std::string kname[FGCG_K_NKINDS];
+  std::vector<hipEvent_t> pool;
+  struct Pending {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  hipEvent_t cur = nullptr;
+};
+
+namespace {
+
+int prof_begin(fgcg_ctx* c, int kind) {
+  if (!(c->prof_mask & (1u << kind))) return 0;
+  if (c->pool.size() < 2) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      c->pool.push_back(e);
+    }
+  }
+  c->cur = c->pool.back();
+  c->pool.pop_back();
+  HIPCHK(hipEventRecord(c->cur, c->stream));
+  return 0;
+}
+
+int prof_end(fgcg_ctx* c, int kind) {
+  if (!(c->prof_mask & (1u << kind))) return 0;
+  hipEvent_t e = c->pool.back();
+  c->pool.pop_back();
+  HIPCHK(hipEventRecord(e, c->stream));
+  c->pending.push_back({kind, c->cur, e});
+  return 0;
+}
+
+// Call after the stream has been synchronised.
+int prof_flush(fgcg_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    c->prof_ms[p.kind] += ms;
+    c->prof_n[p.kind] += 1;
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+  return 0;
+}
+
+template <typename T> const char* tname() { return std::is_same<T, double>::value ? "double" : "float"; }
+
+void set_kname(fgcg_ctx* c, int kind, const char* fmt, const char* t, int n) {
+  if (!c->kname[kind].empty()) return;
+  char b[256];
+  snprintf(b, sizeof b, fmt, t, n);
+  c->kname[kind] = b;
+}
+
+template <typename T, int NOUT, class Pro>
+int launch_row_fwd(fgcg_ctx* c, int kind, const Pro& pro, CT<T>* spec, int nsamp = 1, long long ss = 0) {
+  int rc = 0;
+  with_n(c->nx, [&](auto NXc) {
+    constexpr int NX = decltype(NXc)::value;
+    constexpr int R = rows_for(NX);
+    dim3 g((c->ny + R - 1) / R, nsamp);
+    if (kind >= 0) set_kname(c, kind, "k_row_fwd<%s, %d", tname<T>(), NX);
+    if (kind >= 0) rc |= prof_begin(c, kind);
+    hipLaunchKernelGGL((k_row_fwd<T, NX, NOUT, Pro>), g, dim3(NT), 0, c->stream, pro, spec, c->ny, ss,
+                       (const CT<T>*)c->twx);
+    if (kind >= 0) rc |= prof_end(c, kind);
+  });
+  return rc;
+}
+
+template <typename T, int NIN, int NOUT, class Sym>
+int launch_col(fgcg_ctx* c, int kind, const Sym& sym, const CT<T>* in, CT<T>* out, int nsamp = 1,
+               long long ss = 0) {
+  int rc = 0;
+  with_n(c->ny, [&](auto NYc) {
+    constexpr int NY = decltype(NYc)::value;
+    dim3 g(c->nxh, nsamp);
+    if (kind >= 0) set_kname(c, kind, "k_col<%s, %d", tname<T>(), NY);
+    if (kind >= 0) rc |= prof_begin(c, kind);
+    hipLaunchKernelGGL((k_col<T, NY, NIN, NOUT, Sym>), g, dim3(NT), 0, c->stream, sym, in, out, c->nxh, ss,
+                       ss, (const CT<T>*)c->twy);
+    if (kind >= 0) rc |= prof_end(c, kind);
+  });
+  return rc;
+}
+
+template <typename T, int NIN, class Epi>
+int launch_row_inv(fgcg_ctx* c, int kind, const Epi& epi, const CT<T>* spec, int nsamp = 1,
+                   long long ss = 0) {
+  int rc = 0;
+  with_n(c->nx, [&](auto NXc) {
+    constexpr int NX = decltype(NXc)::value;
+    constexpr int R = rows_for(NX);
+    dim3 g((c->ny + R - 1) / R, nsamp);
+    if (kind >= 0) set_kname(c, kind, "k_row_inv<%s, %d", tname<T>(), NX);
+    if (kind >= 0) rc |= prof_begin(c, kind);
+    hipLaunchKernelGGL((k_row_inv<T, NX, NIN, Epi>), g, dim3(NT), 0, c->stream, epi, spec, c->ny, ss,
+                       (const CT<T>*)c->twx);
+    if (kind >= 0) rc |= prof_end(c, kind);
+  });
+  return rc;
+}
+
+template <typename T, int NIN, int NOUT, class Mid>
+int launch_row_mid(fgcg_ctx* c, int kind, const Mid& mid, CT<T>* spec, int nsamp = 1, long long ss = 0) {
+  int rc = 0;
+  with_n(c->nx, [&](auto NXc) {
+    constexpr int NX = decltype(NXc)::value;
+    constexpr int R = rows_for(NX);
+    dim3 g((c->ny + R - 1) / R, nsamp);
+    if (kind >= 0) set_kname(c, kind, "k_row_mid<%s, %d", tname<T>(), NX);
+    if (kind >= 0) rc |= prof_begin(c, kind);
+    hipLaunchKernelGGL((k_row_mid<T, NX, NIN, NOUT, Mid>), g, dim3(NT), 0, c->stream, mid, spec, c->ny, ss,
+                       (const CT<T>*)c->twx);
+    if (kind >= 0) rc |= prof_end(c, kind);
+  });
+  return rc;
+}
+
+// Chunked CG driver: enqueue chunks of iterations; each pass exits at once
+// when the device state says the solve has ended; the host reads the state
+// once per chunk.
+template <class F> int run_cg(fgcg_ctx* c, F&& iter, int maxit) {
+  long long k = 0;
+  int chunk = 2;
+  for (;;) {
+    HIPCHK(hipMemcpyAsync(c->h_st, c->st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    int rc = prof_flush(c);
+    if (rc) return rc;
+    if (c->h_st->done) return 0;
+    if (k > (long long)maxit + 1) return fail(FGCG_EHIP, "CG driver overran the iteration limit");
+    for (int j = 0; j < chunk; ++j) {
+      rc = iter((int)k++);
+      if (rc) return rc;
+    }
+    HIPCHK(hipGetLastError());
+    chunk = chunk < 32 ? chunk * 2 : 32;
+  }
+}
+
+int status_of(const CgState& s) {
+  switch (s.done) {
+    case 1: return FGCG_OK;
+    case 2: return FGCG_NOT_CONVERGED;
+    case 3: return FGCG_EBREAKDOWN;
+    case 4: return FGCG_EDOMAIN;
+    default: return FGCG_EHIP;
+  }
+}
+
+void fill_info(fgcg_info* info, const CgState& s, double secs) {
+  if (!info) return;
+  info->iters = s.iter;
+  info->status = status_of(s);
+  info->bnorm = std::sqrt(s.bnorm2);
+  info->rel_res = s.bnorm2 > 0 ? std::sqrt(s.rr_final / s.bnorm2) : 0.0;
+  info->seconds = secs;
+}
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int make_mech_mat(const fgcg_ctx* c, const fgcg_material* mat, const double* d, double kappa, MechMat* m) {
+  if (!mat) return fail(FGCG_EINVAL, "material is NULL");
+  std::memset(m, 0, sizeof *m);
+  m->d = d;
+  m->kappa = kappa;
+  m->ss = c->n;
+  if (!(kappa >= 0.0) || !std::isfinite(kappa)) return fail(FGCG_EDOMAIN, "kappa must be finite and >= 0");
+  if (mat->E_field) {
+    const double nu = mat->nu_field;
+    if (!(nu > -1.0 && nu < 0.5)) return fail(FGCG_EDOMAIN, "nu_field outside (-1, 0.5)");
+    m->Efield = mat->E_field;
+    m->lam_per_E = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    m->mu_per_E = 1.0 / (2.0 * (1.0 + nu));
+    return 0;
+  }
+  if (!mat->phase || !mat->E_tab || !mat->nu_tab) return fail(FGCG_EINVAL, "phase/E_tab/nu_tab is NULL");
+  if (mat->nphase < 1 || mat->nphase > FGCG_MAX_PHASES) return fail(FGCG_EINVAL, "nphase outside 1..8");
+  m->phase = mat->phase;
+  for (int i = 0; i < mat->nphase; ++i) {
+    const double E = mat->E_tab[i], nu = mat->nu_tab[i];
+    if (!(E > 0.0) || !std::isfinite(E)) return fail(FGCG_EDOMAIN, "E <= 0 or not finite");
+    if (!(nu > -1.0 && nu < 0.5)) return fail(FGCG_EDOMAIN, "nu outside (-1, 0.5)");
+    m->lm.a[i] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    m->lm.b[i] = E / (2.0 * (1.0 + nu));
+  }
+  return 0;
+}
+
+int check_solver_args(double tol, int maxit) {
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(FGCG_EINVAL, "tol must be finite and >= 0");
+  if (maxit < 0) return fail(FGCG_EINVAL, "maxit < 0");
+  return 0;
+}
+
+// ----------------------------------------------------------------- mech
+template <typename T>
+int mech_solve_t(fgcg_ctx* c, const MechMat& m, const double* eig, const double* em, double tol, int maxit,
+                 double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
+  const double t0 = now();
+  CT<T>* spec = (CT<T>*)c->spec;
+  Field<T> X{(T*)c->x, c->n, 0}, R{(T*)c->r, c->n, 0}, P{(T*)c->p, c->n, 0};
+  int rc;
+  // b = -G[g C : (eps_mac - e I)], x = 0
+  MechSrcPro<T> src{m, eig, Field<T>{nullptr, c->n, 0}, {em[0], em[1], em[2]}, c->nx};
+  if ((rc = launch_row_fwd<T, 3>(c, -1, src, spec))) return rc;
+  MechProj<T> proj0{c->Dx, c->Dy, 1.0 / (double)c->n, nullptr};
+  if ((rc = launch_col<T, 3, 4>(c, -1, proj0, spec, spec))) return rc;
+  StoreEpi<T, 4> st0{R, X, (T)-1, c->nx, c->part_rr, 0};
+  if ((rc = launch_row_inv<T, 4>(c, -1, st0, spec))) return rc;
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_rr, c->nrow, 0, tol, maxit);
+  auto iter = [&](int k) -> int {
+    CgCtl cc{c->st, c->part_a, c->part_rr, c->nrow, c->nrow, 0, 0, k};
+    MechCgPro<T> pro{P, R, c->nx, m, cc};
+    int r = launch_row_fwd<T, 3>(c, FGCG_K_MECH_ROW_FWD, pro, spec);
+    MechProj<T> proj{c->Dx, c->Dy, 1.0 / (double)c->n, c->st};
+    r |= launch_col<T, 3, 4>(c, FGCG_K_MECH_COL, proj, spec, spec);
+    MechCgEpi<T> epi{X, R, P, c->nx, cc};
+    r |= launch_row_inv<T, 4>(c, FGCG_K_MECH_ROW_INV, epi, spec);
+    return r;
+  };
+  if ((rc = run_cg(c, iter, maxit))) return rc;
+  const CgState s = *c->h_st;
+  hipLaunchKernelGGL((k_mech_post<T>), dim3(c->npost), dim3(PT), 0, c->stream, m, (const T*)c->x, c->n, eig,
+                     em[0], em[1], em[2], strain, stress, c->part_post);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->h_part, c->part_post, sizeof(double) * 4 * c->npost, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double acc[4] = {0, 0, 0, 0};
+  for (int b = 0; b < c->npost; ++b)
+    for (int j = 0; j < 4; ++j) acc[j] += c->h_part[4 * b + j];
+  if (mean_stress)
+    for (int j = 0; j < 3; ++j) mean_stress[j] = acc[j] / (double)c->n;
+  if (energy) *energy = 0.5 * c->h * c->h * acc[3];
+  fill_info(info, s, now() - t0);
+  return status_of(s);
+}
+
+// ------------------------------------------------------------ phase field
+template <typename T> struct PfApplyEpi {
+  Field<T> v, q;
+  const double* H;
+  double a;
+  int nx;
+  __device__ bool begin(int, double*, double&) const { return true; }
+  __device__ void point(int s, int y, int xx, const T* l, double&, double) const {
+    const long long i = (long long)y * nx + xx;
+    q.at(s, 0, i) = (T)(a + H[i]) * v.at(s, 0, i) + l[0];
+  }
+  __device__ void partial(int, double) const {}
+};
+
+template <typename T>
+int pf_solve_t(fgcg_ctx* c, const double* H, double Gc, double l0, double* d, double tol, int maxit,
+               fgcg_info* info) {
+  const double t0 = now();
+  CT<T>* spec = (CT<T>*)c->spec;
+  Field<T> X{(T*)c->x, c->n, 0}, R{(T*)c->r, c->n, 0}, P{(T*)c->p, c->n, 0};
+  const double a = Gc / (2.0 * l0);
+  const double cl = 0.5 * Gc * l0 / (double)c->n;
+  int rc;
+  hipLaunchKernelGGL((k_convert<T, double>), dim3(c->npost), dim3(PT), 0, c->stream, (T*)c->x, d, c->n);
+  hipLaunchKernelGGL(k_norm2, dim3(c->npost), dim3(PT), 0, c->stream, H, c->n, c->part_b);
+  // r = H - A x0
+  CopyPro<T> cp{X, c->nx};
+  if ((rc = launch_row_fwd<T, 1>(c, -1, cp, spec))) return rc;
+  PfLap<T> lap0{c->Dx, c->Dy, cl, c->nx, nullptr, nullptr, 0, 0};
+  if ((rc = launch_col<T, 1, 1>(c, -1, lap0, spec, spec))) return rc;
+  PfResEpi<T> res{X, R, H, 0, a, c->nx, c->part_rr, 0};
+  if ((rc = launch_row_inv<T, 1>(c, -1, res, spec))) return rc;
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_b, c->npost, 0, tol, maxit);
+  auto iter = [&](int k) -> int {
+    CgCtl cc{c->st, c->part_a, c->part_rr, c->nrow + c->ncol, c->nrow, 0, 0, k};
+    PfCgPro<T> pro{P, R, H, 0, a, c->nx, cc};
+    int r = launch_row_fwd<T, 1>(c, FGCG_K_PF_ROW_FWD, pro, spec);
+    PfLap<T> lap{c->Dx, c->Dy, cl, c->nx, c->st, c->part_a, 0, c->nrow};
+    r |= launch_col<T, 1, 1>(c, FGCG_K_PF_COL, lap, spec, spec);
+    PfCgEpi<T> epi{X, R, P, H, 0, a, c->nx, cc};
+    r |= launch_row_inv<T, 1>(c, FGCG_K_PF_ROW_INV, epi, spec);
+    return r;
+  };
+  if ((rc = run_cg(c, iter, maxit))) return rc;
+  const CgState s = *c->h_st;
+  if (s.zero_rhs) HIPCHK(hipMemsetAsync(c->x, 0, sizeof(T) * c->n, c->stream));
+  hipLaunchKernelGGL((k_convert<double, T>), dim3(c->npost), dim3(PT), 0, c->stream, d, (const T*)c->x, c->n);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  fill_info(info, s, now() - t0);
+  return status_of(s);
+}
+
+// -------------------------------------------------------------- diffusion
+template <typename T> struct DiffApplyEpi {
+  Field<T> v, q;
+  DiffCoef co;
+  int nx;
+  __device__ bool begin(int, double*, double&) const { return true; }
+  __device__ void point(int s, int y, int xx, const T* l, double&, double) const {
+    const long long i = (long long)y * nx + xx;
+    double D, kr;
+    pick(co.dk, co.phase[i], D, kr);
+    q.at(s, 0, i) = (T)(co.inv_dt + kr) * v.at(s, 0, i) + l[0];
+  }
+  __device__ void partial(int, double) const {}
+};
+
+int make_diff_coef(const uint8_t* phase, int nphase, const double* D_tab, const double* k_tab, double dt,
+                   int band, long long n, DiffCoef* co) {
+  if (!phase || !D_tab || !k_tab) return fail(FGCG_EINVAL, "phase/D_tab/k_tab is NULL");
+  if (nphase < 1 || nphase > FGCG_MAX_PHASES) return fail(FGCG_EINVAL, "nphase outside 1..8");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FGCG_EDOMAIN, "dt <= 0");
+  std::memset(co, 0, sizeof *co);
+  co->phase = phase;
+  co->ss = n;
+  co->inv_dt = 1.0 / dt;
+  co->band = band;
+  for (int i = 0; i < nphase; ++i) {
+    if (!(D_tab[i] >= 0.0) || !std::isfinite(D_tab[i])) return fail(FGCG_EDOMAIN, "D < 0");
+    if (!(k_tab[i] >= 0.0) || !std::isfinite(k_tab[i])) return fail(FGCG_EDOMAIN, "k < 0");
+    co->dk.a[i] = D_tab[i];
+    co->dk.b[i] = k_tab[i];
+  }
+  return 0;
+}
+
+template <typename T>
+int diff_pipeline_apply(fgcg_ctx* c, const DiffCoef& co, CT<T>* spec, const CgState* st, double* part_mid,
+                        int poff, const int* kinds) {
+  const double inv_n = 1.0 / (double)c->n;
+  int rc = 0;
+  DiffGrad<T> grad{c->Dx, c->Dy, inv_n, st};
+  rc |= launch_col<T, 1, 2>(c, kinds ? kinds[0] : -1, grad, spec, spec);
+  DiffMid<T> mid{co, c->nx, st, part_mid, 0, poff};
+  rc |= launch_row_mid<T, 2, 2>(c, kinds ? kinds[1] : -1, mid, spec);
+  DiffDiv<T> div{c->Dx, c->Dy, inv_n, st};
+  rc |= launch_col<T, 2, 1>(c, kinds ? kinds[2] : -1, div, spec, spec);
+  return rc;
+}
+
+template <typename T>
+int diff_step_t(fgcg_ctx* c, const DiffCoef& co, double c_dir, double* cfield, double tol, int maxit,
+                fgcg_info* info) {
+  const double t0 = now();
+  CT<T>* spec = (CT<T>*)c->spec;
+  Field<T> X{(T*)c->x, c->n, 0}, R{(T*)c->r, c->n, 0}, P{(T*)c->p, c->n, 0}, TM{(T*)c->tmp, c->n, 0};
+  int rc;
+  // b_F = M (c^n/dt - A c_B): only its norm is needed
+  BandSrcPro<T> sb{nullptr, 0, co.band, c_dir, c->nx};
+  if ((rc = launch_row_fwd<T, 1>(c, -1, sb, spec))) return rc;
+  if ((rc = diff_pipeline_apply<T>(c, co, spec, nullptr, nullptr, 0, nullptr))) return rc;
+  DiffResEpi<T> eb{TM, Field<T>{nullptr, c->n, 0}, cfield, nullptr, 0, co, c_dir, c->nx, c->part_b, 0};
+  if ((rc = launch_row_inv<T, 1>(c, -1, eb, spec))) return rc;
+  // r0 = M (c^n/dt - A c~), x0 = M c^n, c~ = c^n with the band set to c_dir
+  BandSrcPro<T> sc{cfield, 0, co.band, c_dir, c->nx};
+  if ((rc = launch_row_fwd<T, 1>(c, -1, sc, spec))) return rc;
+  if ((rc = diff_pipeline_apply<T>(c, co, spec, nullptr, nullptr, 0, nullptr))) return rc;
+  DiffResEpi<T> er{R, X, cfield, cfield, 0, co, c_dir, c->nx, c->part_rr, 0};
+  if ((rc = launch_row_inv<T, 1>(c, -1, er, spec))) return rc;
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_b, c->nrow, 0, tol, maxit);
+  static const int kinds[3] = {FGCG_K_DIFF_COL_GRAD, FGCG_K_DIFF_ROW_MID, FGCG_K_DIFF_COL_DIV};
+  auto iter = [&](int k) -> int {
+    CgCtl cc{c->st, c->part_a, c->part_rr, 2 * c->nrow, c->nrow, 0, 0, k};
+    DiffCgPro<T> pro{P, R, co, c->nx, cc};
+    int r = launch_row_fwd<T, 1>(c, FGCG_K_DIFF_ROW_FWD, pro, spec);
+    r |= diff_pipeline_apply<T>(c, co, spec, c->st, c->part_a, c->nrow, kinds);
+    DiffCgEpi<T> epi{X, R, P, co, c->nx, cc};
+    r |= launch_row_inv<T, 1>(c, FGCG_K_DIFF_ROW_INV, epi, spec);
+    return r;
+  };
+  if ((rc = run_cg(c, iter, maxit))) return rc;
+  const CgState s = *c->h_st;
+  if (s.zero_rhs) HIPCHK(hipMemsetAsync(c->x, 0, sizeof(T) * c->n, c->stream));
+  hipLaunchKernelGGL((k_diff_finish<T>), dim3(c->npost), dim3(PT), 0, c->stream, cfield, (const T*)c->x, c->n,
+                     c->nx, co.band, c_dir);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  fill_info(info, s, now() - t0);
+  return status_of(s);
+}
+
+template <typename T> int alloc_workspace(fgcg_ctx* c) {
+  const size_t nr = sizeof(T) * 4 * (size_t)c->n;
+  HIPCHK(hipMalloc(&c->x, nr));
+  HIPCHK(hipMalloc(&c->r, nr));
+  HIPCHK(hipMalloc(&c->p, nr));
+  HIPCHK(hipMalloc(&c->tmp, nr));
+  HIPCHK(hipMalloc(&c->spec, sizeof(CT<T>) * 4 * (size_t)c->nxh * c->ny));
+  std::vector<CT<T>> tx(c->nx), ty(c->ny);
+  for (int t = 0; t < c->nx; ++t) {
+    const double th = 2.0 * M_PI * (double)t / (double)c->nx;
+    tx[t] = CT<T>{(T)std::cos(th), (T)-std::sin(th)};
+  }
+  for (int t = 0; t < c->ny; ++t) {
+    const double th = 2.0 * M_PI * (double)t / (double)c->ny;
+    ty[t] = CT<T>{(T)std::cos(th), (T)-std::sin(th)};
+  }
+  HIPCHK(hipMalloc(&c->twx, sizeof(CT<T>) * c->nx));
+  HIPCHK(hipMalloc(&c->twy, sizeof(CT<T>) * c->ny));
+  HIPCHK(hipMemcpy(c->twx, tx.data(), sizeof(CT<T>) * c->nx, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->twy, ty.data(), sizeof(CT<T>) * c->ny, hipMemcpyHostToDevice));
+  return 0;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* fgcg_strerror(int status) {
+  switch (status) {
+    case FGCG_OK: return "ok";
+    case FGCG_NOT_CONVERGED: return "not converged within maxit";
+    case FGCG_EINVAL: return "invalid argument";
+    case FGCG_EDOMAIN: return "argument outside its domain";
+    case FGCG_EBREAKDOWN: return "CG breakdown";
+    case FGCG_ENOMEM: return "out of memory";
+    case FGCG_EHIP: return "HIP runtime error";
+    case FGCG_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* fgcg_last_error(void) { return g_err.c_str(); }
+
+int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out) {
+  if (!grid || !out) return fail(FGCG_EINVAL, "grid/out is NULL");
+  *out = nullptr;
+  if (grid->ndim != 2) return fail(FGCG_EUNSUPPORTED, "only 2D grids are built");
+  if (!(grid->h > 0.0) || !std::isfinite(grid->h)) return fail(FGCG_EDOMAIN, "h <= 0");
+  if (!size_supported(grid->n[0]) || !size_supported(grid->n[1]))
+    return fail(FGCG_EINVAL, "axis length must be one of 8..2048 of the form 2^a 3^b");
+  if (grid->precision != FGCG_FP64) return fail(FGCG_EUNSUPPORTED, "precision not built");
+  fgcg_ctx* c = new fgcg_ctx();
+  c->nx = grid->n[0];
+  c->ny = grid->n[1];
+  c->nxh = c->nx / 2 + 1;
+  c->n = (long long)c->nx * c->ny;
+  c->h = grid->h;
+  c->prec = grid->precision;
+  c->stream = (hipStream_t)hip_stream;
+  with_n(c->nx, [&](auto NXc) {
+    constexpr int R = rows_for(decltype(NXc)::value);
+    c->nrow = (c->ny + R - 1) / R;
+  });
+  c->ncol = c->nxh;
+  c->npost = (int)std::min<long long>((c->n + PT - 1) / PT, 1024);
+  int rc = alloc_workspace<double>(c);
+  auto chk = [&](hipError_t e) {
+    if (e != hipSuccess && !rc) rc = fail(FGCG_ENOMEM, std::string("allocation failed: ") + hipGetErrorString(e));
+  };
+  if (!rc) {
+    chk(hipMalloc(&c->Dx, sizeof(double2) * c->nxh));
+    chk(hipMalloc(&c->Dy, sizeof(double2) * c->ny));
+    chk(hipMalloc(&c->st, sizeof(CgState) * 1));
+    chk(hipHostMalloc(&c->h_st, sizeof(CgState) * 1, hipHostMallocDefault));
+    const int npa = c->nrow + std::max(c->ncol, c->nrow);
+    chk(hipMalloc(&c->part_a, sizeof(double) * npa));
+    chk(hipMalloc(&c->part_rr, sizeof(double) * c->nrow));
+    chk(hipMalloc(&c->part_b, sizeof(double) * std::max(c->nrow, c->npost)));
+    chk(hipMalloc(&c->part_post, sizeof(double) * 5 * c->npost));
+    chk(hipHostMalloc(&c->h_part, sizeof(double) * 5 * c->npost, hipHostMallocDefault));
+  }
+  if (!rc) {
+    // forward-difference symbols D(k) = (exp(i theta) - 1)/h = (-2 sin^2(theta/2) + i sin theta)/h
+    std::vector<double2> dx(c->nxh), dy(c->ny);
+    for (int k = 0; k < c->nxh; ++k) {
+      const double th = 2.0 * M_PI * k / c->nx, sh = std::sin(0.5 * th);
+      dx[k] = double2{-2.0 * sh * sh / c->h, std::sin(th) / c->h};
+    }
+    for (int k = 0; k < c->ny; ++k) {
+      const double th = 2.0 * M_PI * k / c->ny, sh = std::sin(0.5 * th);
+      dy[k] = double2{-2.0 * sh * sh / c->h, std::sin(th) / c->h};
+    }
+    chk(hipMemcpy(c->Dx, dx.data(), sizeof(double2) * c->nxh, hipMemcpyHostToDevice));
+    chk(hipMemcpy(c->Dy, dy.data(), sizeof(double2) * c->ny, hipMemcpyHostToDevice));
+  }
+  if (rc) {
+    fgcg_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return FGCG_OK;
+}
+
+void fgcg_destroy(fgcg_ctx* c) {
+  if (!c) return;
+  void* dev[] = {c->twx, c->twy, c->Dx, c->Dy, c->x, c->r, c->p, c->tmp, c->spec, c->st,
+                 c->part_a, c->part_rr, c->part_b, c->part_post};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  if (c->h_st) (void)hipHostFree(c->h_st);
+  if (c->h_part) (void)hipHostFree(c->h_part);
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int fgcg_set_stream(fgcg_ctx* c, void* s) {
+  if (!c) return fail(FGCG_EINVAL, "ctx is NULL");
+  c->stream = (hipStream_t)s;
+  return FGCG_OK;
+}
+
+int fgcg_mech_solve(fgcg_ctx* c, const fgcg_material* mat, const double* d, double kappa, const double* eig,
+                    const double* eps_mac, double tol, int maxit, double* strain, double* stress,
+                    double* mean_stress, double* energy, fgcg_info* info) {
+  if (!c || !eps_mac || !strain) return fail(FGCG_EINVAL, "ctx/eps_mac/strain is NULL");
+  int rc;
+  if ((rc = check_solver_args(tol, maxit))) return rc;
+  for (int j = 0; j < 3; ++j)
+    if (!std::isfinite(eps_mac[j])) return fail(FGCG_EDOMAIN, "eps_mac not finite");
+  MechMat m;
+  if ((rc = make_mech_mat(c, mat, d, kappa, &m))) return rc;
+  return mech_solve_t<double>(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
+}
+
+int fgcg_phasefield_solve(fgcg_ctx* c, const double* H, double Gc, double l0, double* d, double tol, int maxit,
+                          fgcg_info* info) {
+  if (!c || !H || !d) return fail(FGCG_EINVAL, "ctx/H/d is NULL");
+  int rc;
+  if ((rc = check_solver_args(tol, maxit))) return rc;
+  if (!(Gc > 0.0) || !std::isfinite(Gc)) return fail(FGCG_EDOMAIN, "Gc <= 0");
+  if (!(l0 > 0.0) || !std::isfinite(l0)) return fail(FGCG_EDOMAIN, "l0 <= 0");
+  return pf_solve_t<double>(c, H, Gc, l0, d, tol, maxit, info);
+}
+
+int fgcg_diffusion_step(fgcg_ctx* c, const uint8_t* phase, int nphase, const double* D_tab, const double* k_tab,
+                        int band_width, double c_dir, double dt, double* cfield, double tol, int maxit,
+                        fgcg_info* info) {
+  if (!c || !cfield) return fail(FGCG_EINVAL, "ctx/c is NULL");
+  int rc;
+  if ((rc = check_solver_args(tol, maxit))) return rc;
+  if (band_width < 0 || band_width >= c->nx) return fail(FGCG_EINVAL, "band_width outside [0, nx)");
+  if (!std::isfinite(c_dir)) return fail(FGCG_EDOMAIN, "c_dir not finite");
+  DiffCoef co;
+  if ((rc = make_diff_coef(phase, nphase, D_tab, k_tab, dt, band_width, c->n, &co))) return rc;
+  return diff_step_t<double>(c, co, c_dir, cfield, tol, maxit, info);
+}
+
+int fgcg_staggered_step(fgcg_ctx* c, fgcg_state* s, const fgcg_params* p, fgcg_step_info* info) {
+  if (!c || !s || !p || !info) return fail(FGCG_EINVAL, "ctx/state/params/info is NULL");
+  if (!s->c || !s->f || !s->e || !s->H || !s->d || !s->strain) return fail(FGCG_EINVAL, "state field is NULL");
+  if (!p->mat.phase) return fail(FGCG_EINVAL, "params.mat.phase is NULL");
+  if (!(p->dt > 0.0)) return fail(FGCG_EDOMAIN, "dt <= 0");
+  std::memset(info, 0, sizeof *info);
+  int rc;
+  if (p->diffuse) {
+    rc = fgcg_diffusion_step(c, p->mat.phase, p->mat.nphase, p->D_tab, p->k_tab, p->band_width, p->c_dir, p->dt,
+                             s->c, p->tol_diff, p->maxit, &info->diff);
+    if (rc < 0) return rc;
+  }
+  const double e_pres = p->n_ramp > 0 ? p->e_ramp * (double)(s->step + 1) / (double)p->n_ramp : 0.0;
+  const double kp = (p->diffuse && p->k_tab) ? p->k_tab[0] : 0.0;
+  hipLaunchKernelGGL(k_precip, dim3(c->npost), dim3(PT), 0, c->stream, p->mat.phase, s->c, s->f, s->e, c->n,
+                     p->dt * kp, p->e_per_f, p->diffuse, e_pres);
+  HIPCHK(hipGetLastError());
+  rc = fgcg_mech_solve(c, &p->mat, s->d, p->kappa, s->e, p->eps_mac, p->tol_mech, p->maxit, s->strain, nullptr,
+                       info->mean_stress, &info->energy, &info->mech);
+  if (rc < 0) return rc;
+  MechMat m0;
+  if ((rc = make_mech_mat(c, &p->mat, nullptr, 0.0, &m0))) return rc;
+  hipLaunchKernelGGL(k_history, dim3(c->npost), dim3(PT), 0, c->stream, m0, s->strain, s->e, s->H, c->n);
+  HIPCHK(hipGetLastError());
+  rc = fgcg_phasefield_solve(c, s->H, p->Gc, p->l0, s->d, p->tol_pf, p->maxit, &info->pf);
+  if (rc < 0) return rc;
+  hipLaunchKernelGGL(k_observe, dim3(c->npost), dim3(PT), 0, c->stream, p->mat.phase, s->d, s->f, c->n,
+                     c->part_post);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->h_part, c->part_post, sizeof(double) * 5 * c->npost, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double mx = 0, cnt = 0, sd = 0, sf = 0, ns = 0;
+  for (int b = 0; b < c->npost; ++b) {
+    mx = std::max(mx, c->h_part[5 * b]);
+    cnt += c->h_part[5 * b + 1];
+    sd += c->h_part[5 * b + 2];
+    sf += c->h_part[5 * b + 3];
+    ns += c->h_part[5 * b + 4];
+  }
+  info->max_d = mx;
+  info->damaged_fraction = ns > 0 ? cnt / ns : 0.0;
+  info->porosity_increase = sd / (double)c->n;
+  info->total_precipitate = sf;
+  s->step += 1;
+  int worst = FGCG_OK;
+  for (const fgcg_info* i : {&info->diff, &info->mech, &info->pf})
+    if (i->status == FGCG_NOT_CONVERGED) worst = FGCG_NOT_CONVERGED;
+  return worst;
+}
+
+int fgcg_mech_apply(fgcg_ctx* c, const fgcg_material* mat, const double* d, double kappa, const double* p,
+                    double* q) {
+  if (!c || !p || !q) return fail(FGCG_EINVAL, "ctx/p/q is NULL");
+  MechMat m;
+  int rc;
+  if ((rc = make_mech_mat(c, mat, d, kappa, &m))) return rc;
+  CT<double>* spec = (CT<double>*)c->spec;
+  MechSrcPro<double> src{m, nullptr, Field<double>{(double*)p, c->n, 0}, {0, 0, 0}, c->nx};
+  if ((rc = launch_row_fwd<double, 3>(c, -1, src, spec))) return rc;
+  MechProj<double> proj{c->Dx, c->Dy, 1.0 / (double)c->n, nullptr};
+  if ((rc = launch_col<double, 3, 4>(c, -1, proj, spec, spec))) return rc;
+  StoreEpi<double, 4> st{Field<double>{q, c->n, 0}, Field<double>{nullptr, c->n, 0}, 1.0, c->nx, nullptr, 0};
+  if ((rc = launch_row_inv<double, 4>(c, -1, st, spec))) return rc;
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return FGCG_OK;
+}
+
+int fgcg_phasefield_apply(fgcg_ctx* c, const double* H, double Gc, double l0, const double* v, double* q) {
+  if (!c || !H || !v || !q) return fail(FGCG_EINVAL, "ctx/H/v/q is NULL");
+  if (!(Gc > 0.0) || !(l0 > 0.0)) return fail(FGCG_EDOMAIN, "Gc/l0 <= 0");
+  CT<double>* spec = (CT<double>*)c->spec;
+  int rc;
+  CopyPro<double> cp{Field<double>{(double*)v, c->n, 0}, c->nx};
+  if ((rc = launch_row_fwd<double, 1>(c, -1, cp, spec))) return rc;
+  PfLap<double> lap{c->Dx, c->Dy, 0.5 * Gc * l0 / (double)c->n, c->nx, nullptr, nullptr, 0, 0};
+  if ((rc = launch_col<double, 1, 1>(c, -1, lap, spec, spec))) return rc;
+  PfApplyEpi<double> ep{Field<double>{(double*)v, c->n, 0}, Field<double>{q, c->n, 0}, H, Gc / (2.0 * l0), c->nx};
+  if ((rc = launch_row_inv<double, 1>(c, -1, ep, spec))) return rc;
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return FGCG_OK;
+}
+
+int fgcg_diffusion_apply(fgcg_ctx* c, const uint8_t* phase, int nphase, const double* D_tab, const double* k_tab,
+                         double dt, const double* v, double* q) {
+  if (!c || !v || !q) return fail(FGCG_EINVAL, "ctx/v/q is NULL");
+  DiffCoef co;
+  int rc;
+  if ((rc = make_diff_coef(phase, nphase, D_tab, k_tab, dt, 0, c->n, &co))) return rc;
+  CT<double>* spec = (CT<double>*)c->spec;
+  CopyPro<double> cp{Field<double>{(double*)v, c->n, 0}, c->nx};
+  if ((rc = launch_row_fwd<double, 1>(c, -1, cp, spec))) return rc;
+  if ((rc = diff_pipeline_apply<double>(c, co, spec, nullptr, nullptr, 0, nullptr))) return rc;
+  DiffApplyEpi<double> ep{Field<double>{(double*)v, c->n, 0}, Field<double>{q, c->n, 0}, co, c->nx};
+  if ((rc = launch_row_inv<double, 1>(c, -1, ep, spec))) return rc;
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return FGCG_OK;
+}
+
+int fgcg_profile(fgcg_ctx* c, unsigned mask) {
+  if (!c) return fail(FGCG_EINVAL, "ctx is NULL");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  int rc = prof_flush(c);
+  if (rc) return rc;
+  c->prof_mask = mask;
+  for (int k = 0; k < FGCG_K_NKINDS; ++k) {
+    c->prof_ms[k] = 0;
+    c->prof_n[k] = 0;
+  }
+  return FGCG_OK;
+}
+
+int fgcg_profile_read(fgcg_ctx* c, int kind, double* ms, long long* launches) {
+  if (!c || kind < 0 || kind >= FGCG_K_NKINDS) return fail(FGCG_EINVAL, "bad ctx/kind");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  int rc = prof_flush(c);
+  if (rc) return rc;
+  if (ms) *ms = c->prof_ms[kind];
+  if (launches) *launches = c->prof_n[kind];
+  return FGCG_OK;
+}
+
+const char* fgcg_kernel_name(fgcg_ctx* c, int kind) {
+  if (!c || kind < 0 || kind >= FGCG_K_NKINDS) return "";
+  return c->kname[kind].c_str();
+}
+
+}  // extern "C"

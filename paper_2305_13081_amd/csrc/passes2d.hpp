@@ -1,0 +1,302 @@
+// Fused 2D FFT passes: the building blocks of every operator application.
+//
+// Real fields are stored component-major, [sample][comp][ny][nx] with x
+// fastest.  Half spectra are stored TRANSPOSED, [sample][comp][nx/2+1][ny], so
+// that the y-direction (column) transforms read and write contiguous memory.
+//
+//   row_fwd : per block ROWS rows.  A pointwise prologue functor produces NOUT
+//             real values per voxel (e.g. the stress of a CG direction), the
+//             rows are packed two by two into complex signals z = a + i b,
+//             transformed along x in LDS, unpacked into the half spectra of a
+//             and b, and stored transposed.
+//   col     : per block one kx column.  NIN spectra are transformed along y,
+//             a per-mode symbol functor maps them to NOUT spectra (projection,
+//             Laplacian, gradient, divergence; the 1/N of the inverse is folded
+//             in here), and NOUT inverse transforms along y follow.
+//   row_inv : per block ROWS rows.  NIN half spectra are rebuilt into full
+//             Hermitian spectra two rows at a time, inverse-transformed along x,
+//             and an epilogue functor consumes the NIN real values per voxel
+//             (e.g. the CG update x += alpha p, r -= alpha q).
+//   row_mid : inverse x transform, pointwise map, forward x transform in one
+//             block (the D(x) multiplication of the diffusion operator).
+//
+// Functors are immutable and expose begin(s, red, sc) (uniform: false = the
+// whole block exits; may set the block scalar sc, e.g. the CG beta or alpha),
+// point(..., acc, sc) and partial(s, value) (block-reduced FP64 sum, thread 0
+// stores).
+#pragma once
+#include "fft_lds.hpp"
+
+namespace fgcg {
+
+constexpr int NT = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic block sum (fixed order) of one value per thread.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+// Deterministic block sum of an array of partial sums.
+__device__ __forceinline__ double block_sum_array(const double* a, int n, double* red) {
+  double t = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) t += a[i];
+  return block_sum(t, red);
+}
+
+constexpr int rows_for(int nx) {
+  return nx >= 2048 ? 2 : nx >= 1024 ? 4 : nx >= 384 ? 8 : 16;
+}
+
+template <typename T>
+__device__ __forceinline__ T* as_real(typename cvec<T>::type* p) { return reinterpret_cast<T*>(p); }
+
+// -------------------------------------------------------------- row forward
+template <typename T, int NX, int NOUT, class Pro>
+__global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type* spec, int ny,
+                                                long long spec_ss,
+                                                const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  constexpr int ROWS = rows_for(NX);
+  constexpr int NP = ROWS / 2;
+  constexpr int NXH = NX / 2 + 1;
+  constexpr int VOX = ROWS * NX;
+  constexpr int VPT = (VOX + NT - 1) / NT;
+  __shared__ C buf[NP * NX];
+  __shared__ double red[NT / 64];
+  const int s = blockIdx.y;
+  const int tid = threadIdx.x;
+  double sc = 0.0;
+  if (!pro.begin(s, red, sc)) return;
+  const int y0 = blockIdx.x * ROWS;
+  T vals[VPT][NOUT];
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const int v = tid + i * NT;
+    const int row = v / NX, x = v - (v / NX) * NX;
+    if ((VOX % NT == 0 || v < VOX) && y0 + row < ny) {
+      pro.point(s, y0 + row, x, vals[i], acc, sc);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NOUT; ++c) vals[i][c] = (T)0;
+    }
+  }
+  pro.partial(s, block_sum(acc, red));
+  C* out = spec + s * spec_ss;
+  T* rb = as_real<T>(buf);
+#pragma unroll
+  for (int c = 0; c < NOUT; ++c) {
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int v = tid + i * NT;
+      if (VOX % NT == 0 || v < VOX) {
+        const int row = v / NX, x = v - (v / NX) * NX;
+        rb[2 * ((row >> 1) * NX + x) + (row & 1)] = vals[i][c];
+      }
+    }
+    __syncthreads();
+    fft_lds<T, NX, NP, NT, false>(buf, tw);
+    for (int idx = tid; idx < NXH * NP; idx += NT) {
+      const int pair = idx % NP, kx = idx / NP;
+      const C z = buf[pair * NX + kx];
+      const C zm = buf[pair * NX + (NX - kx) % NX];
+      const C a = C{(T)0.5 * (z.x + zm.x), (T)0.5 * (z.y - zm.y)};
+      const C b = C{(T)0.5 * (z.y + zm.y), (T)0.5 * (zm.x - z.x)};
+      const int y = y0 + 2 * pair;
+      C* o = out + ((long long)c * NXH + kx) * ny;
+      if (y < ny) o[y] = a;
+      if (y + 1 < ny) o[y + 1] = b;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ column
+template <typename T, int NY, int NIN, int NOUT, class Sym>
+__global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::type* spec_in,
+                                            typename cvec<T>::type* spec_out, int nxh,
+                                            long long ss_in, long long ss_out,
+                                            const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  constexpr int NB = NIN > NOUT ? NIN : NOUT;
+  __shared__ C buf[NB * NY];
+  __shared__ double red[NT / 64];
+  const int s = blockIdx.y;
+  const int kx = blockIdx.x;
+  const int tid = threadIdx.x;
+  double sc = 0.0;
+  if (!sym.begin(s, red, sc)) return;
+  const C* in = spec_in + s * ss_in;
+  for (int idx = tid; idx < NIN * NY; idx += NT) {
+    const int c = idx / NY, y = idx - (idx / NY) * NY;
+    buf[c * NY + y] = in[((long long)c * nxh + kx) * NY + y];
+  }
+  __syncthreads();
+  fft_lds<T, NY, NIN, NT, false>(buf, tw);
+  double acc = 0.0;
+  for (int ky = tid; ky < NY; ky += NT) {
+    C a[NIN], b[NOUT];
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) a[c] = buf[c * NY + ky];
+    sym.mode(s, kx, ky, a, b, acc, sc);
+#pragma unroll
+    for (int c = 0; c < NOUT; ++c) buf[c * NY + ky] = b[c];
+  }
+  __syncthreads();
+  sym.partial(s, block_sum(acc, red));
+  fft_lds<T, NY, NOUT, NT, true>(buf, tw);
+  C* out = spec_out + s * ss_out;
+  for (int idx = tid; idx < NOUT * NY; idx += NT) {
+    const int c = idx / NY, y = idx - (idx / NY) * NY;
+    out[((long long)c * nxh + kx) * NY + y] = buf[c * NY + y];
+  }
+}
+
+// Load NIN half spectra of ROWS rows, inverse transform, into registers.
+template <typename T, int NX, int NIN>
+__device__ __forceinline__ void rows_inverse(
+    const typename cvec<T>::type* in, int ny, int y0, typename cvec<T>::type* buf,
+    T (*vals)[NIN], const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  constexpr int ROWS = rows_for(NX);
+  constexpr int NP = ROWS / 2;
+  constexpr int NXH = NX / 2 + 1;
+  constexpr int VOX = ROWS * NX;
+  constexpr int VPT = (VOX + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  T* rb = as_real<T>(buf);
+#pragma unroll
+  for (int c = 0; c < NIN; ++c) {
+    for (int idx = tid; idx < NXH * NP; idx += NT) {
+      const int pair = idx % NP, kx = idx / NP;
+      const int y = y0 + 2 * pair;
+      const C* o = in + ((long long)c * NXH + kx) * ny;
+      C a = y < ny ? o[y] : C{(T)0, (T)0};
+      C b = y + 1 < ny ? o[y + 1] : C{(T)0, (T)0};
+      if (kx == 0 || 2 * kx == NX) {
+        a.y = (T)0;
+        b.y = (T)0;
+      }
+      buf[pair * NX + kx] = C{a.x - b.y, a.y + b.x};
+      if (kx > 0 && 2 * kx < NX) buf[pair * NX + NX - kx] = C{a.x + b.y, b.x - a.y};
+    }
+    __syncthreads();
+    fft_lds<T, NX, NP, NT, true>(buf, tw);
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int v = tid + i * NT;
+      if (VOX % NT == 0 || v < VOX) {
+        const int row = v / NX, x = v - (v / NX) * NX;
+        vals[i][c] = rb[2 * ((row >> 1) * NX + x) + (row & 1)];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// -------------------------------------------------------------- row inverse
+template <typename T, int NX, int NIN, class Epi>
+__global__ void __launch_bounds__(NT) k_row_inv(Epi epi, const typename cvec<T>::type* spec, int ny,
+                                                long long spec_ss,
+                                                const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  constexpr int ROWS = rows_for(NX);
+  constexpr int NP = ROWS / 2;
+  constexpr int VOX = ROWS * NX;
+  constexpr int VPT = (VOX + NT - 1) / NT;
+  __shared__ C buf[NP * NX];
+  __shared__ double red[NT / 64];
+  const int s = blockIdx.y;
+  const int tid = threadIdx.x;
+  double sc = 0.0;
+  if (!epi.begin(s, red, sc)) return;
+  const int y0 = blockIdx.x * ROWS;
+  T vals[VPT][NIN];
+  rows_inverse<T, NX, NIN>(spec + s * spec_ss, ny, y0, buf, vals, tw);
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const int v = tid + i * NT;
+    const int row = v / NX, x = v - (v / NX) * NX;
+    if ((VOX % NT == 0 || v < VOX) && y0 + row < ny) epi.point(s, y0 + row, x, vals[i], acc, sc);
+  }
+  epi.partial(s, block_sum(acc, red));
+}
+
+// -------------------------------------------------- row inverse + forward
+template <typename T, int NX, int NIN, int NOUT, class Mid>
+__global__ void __launch_bounds__(NT) k_row_mid(Mid mid, typename cvec<T>::type* spec, int ny,
+                                                long long spec_ss,
+                                                const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  constexpr int ROWS = rows_for(NX);
+  constexpr int NP = ROWS / 2;
+  constexpr int NXH = NX / 2 + 1;
+  constexpr int VOX = ROWS * NX;
+  constexpr int VPT = (VOX + NT - 1) / NT;
+  __shared__ C buf[NP * NX];
+  __shared__ double red[NT / 64];
+  const int s = blockIdx.y;
+  const int tid = threadIdx.x;
+  double sc = 0.0;
+  if (!mid.begin(s, red, sc)) return;
+  const int y0 = blockIdx.x * ROWS;
+  T vin[VPT][NIN];
+  T vout[VPT][NOUT];
+  C* sp = spec + s * spec_ss;
+  rows_inverse<T, NX, NIN>(sp, ny, y0, buf, vin, tw);
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const int v = tid + i * NT;
+    const int row = v / NX, x = v - (v / NX) * NX;
+    if ((VOX % NT == 0 || v < VOX) && y0 + row < ny) {
+      mid.point(s, y0 + row, x, vin[i], vout[i], acc, sc);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NOUT; ++c) vout[i][c] = (T)0;
+    }
+  }
+  mid.partial(s, block_sum(acc, red));
+  T* rb = as_real<T>(buf);
+#pragma unroll
+  for (int c = 0; c < NOUT; ++c) {
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int v = tid + i * NT;
+      if (VOX % NT == 0 || v < VOX) {
+        const int row = v / NX, x = v - (v / NX) * NX;
+        rb[2 * ((row >> 1) * NX + x) + (row & 1)] = vout[i][c];
+      }
+    }
+    __syncthreads();
+    fft_lds<T, NX, NP, NT, false>(buf, tw);
+    for (int idx = tid; idx < NXH * NP; idx += NT) {
+      const int pair = idx % NP, kx = idx / NP;
+      const C z = buf[pair * NX + kx];
+      const C zm = buf[pair * NX + (NX - kx) % NX];
+      const C a = C{(T)0.5 * (z.x + zm.x), (T)0.5 * (z.y - zm.y)};
+      const C b = C{(T)0.5 * (z.y + zm.y), (T)0.5 * (zm.x - z.x)};
+      const int y = y0 + 2 * pair;
+      C* o = sp + ((long long)c * NXH + kx) * ny;
+      if (y < ny) o[y] = a;
+      if (y + 1 < ny) o[y + 1] = b;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace fgcg

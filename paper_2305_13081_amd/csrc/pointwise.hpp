@@ -1,0 +1,168 @@
+// Pointwise kernels of the path (no transforms): CG set-up, post-processing,
+// precipitation/eigenstrain, history update, observables.
+#pragma once
+#include "ops2d.hpp"
+
+namespace fgcg {
+
+constexpr int PT = 256;
+
+// Sum the partial array of ||b||^2, set the CG state of sample s (one block
+// per sample).  done = 1 with zero_rhs = 1 when b = 0; done = 4 when ||b|| is
+// not finite.
+__global__ void __launch_bounds__(NT) k_cg_init(CgState* st, const double* part_b, int np,
+                                                int pstride, double tol, int maxit) {
+  __shared__ double red[NT / 64];
+  const int s = blockIdx.x;
+  const double b2 = block_sum_array(part_b + (long long)s * pstride, np, red);
+  if (threadIdx.x == 0) {
+    CgState t;
+    t.rr[0] = t.rr[1] = 0.0;
+    t.bnorm2 = b2;
+    t.thr = tol * tol * b2;
+    t.rr_final = b2;
+    t.maxit = maxit;
+    t.iter = 0;
+    t.zero_rhs = b2 == 0.0;
+    t.done = !isfinite(b2) ? 4 : (b2 == 0.0 ? 1 : 0);
+    st[s] = t;
+  }
+}
+
+// Block partial sums of |v|^2 for a double field of n voxels.
+__global__ void __launch_bounds__(PT) k_norm2(const double* v, long long n, double* part) {
+  __shared__ double red[NT / 64];
+  double a = 0.0;
+  for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT)
+    a += v[i] * v[i];
+  const double t = block_sum(a, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <typename TO, typename TI>
+__global__ void __launch_bounds__(PT) k_convert(TO* out, const TI* in, long long n) {
+  for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT)
+    out[i] = (TO)in[i];
+}
+
+// c = c_dir on the band, x elsewhere
+template <typename T>
+__global__ void __launch_bounds__(PT) k_diff_finish(double* c, const T* x, long long n, int nx,
+                                                    int band, double c_dir) {
+  for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT)
+    c[i] = (int)(i % nx) < band ? c_dir : (double)x[i];
+}
+
+// Post-processing of a mechanical solve: eps = eps_mac + sym(x),
+// sigma = g C : (eps - e I); partial sums of sigma (3) and (eps - eI):sigma.
+template <typename T>
+__global__ void __launch_bounds__(PT) k_mech_post(MechMat m, const T* x, long long n,
+                                                  const double* eig, double em0, double em1,
+                                                  double em2, double* strain, double* stress,
+                                                  double* part) {
+  __shared__ double red[NT / 64];
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT) {
+    const double e11 = em0 + (double)x[i];
+    const double e22 = em1 + (double)x[3 * n + i];
+    const double e12 = em2 + 0.5 * ((double)x[n + i] + (double)x[2 * n + i]);
+    strain[i] = e11;
+    strain[n + i] = e22;
+    strain[2 * n + i] = e12;
+    const double e = eig ? eig[i] : 0.0;
+    double lam, mu;
+    m.get(0, i, lam, mu);
+    const double l11 = e11 - e, l22 = e22 - e;
+    const double tr = l11 + l22;
+    const double s11 = lam * tr + 2.0 * mu * l11;
+    const double s22 = lam * tr + 2.0 * mu * l22;
+    const double s12 = 2.0 * mu * e12;
+    if (stress) {
+      stress[i] = s11;
+      stress[n + i] = s22;
+      stress[2 * n + i] = s12;
+    }
+    a0 += s11;
+    a1 += s22;
+    a2 += s12;
+    a3 += l11 * s11 + l22 * s22 + 2.0 * e12 * s12;
+  }
+  const double t0 = block_sum(a0, red), t1 = block_sum(a1, red), t2 = block_sum(a2, red),
+               t3 = block_sum(a3, red);
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x + 0] = t0;
+    part[4 * blockIdx.x + 1] = t1;
+    part[4 * blockIdx.x + 2] = t2;
+    part[4 * blockIdx.x + 3] = t3;
+  }
+}
+
+// Precipitation in the pores (phase 0): f = min(1, f + dt k c); e = e_per_f f.
+// With diffuse = 0 the eigenstrain follows the prescribed ramp value e_pres.
+__global__ void __launch_bounds__(PT) k_precip(const uint8_t* phase, const double* c, double* f,
+                                               double* e, long long n, double dtk, double e_per_f,
+                                               int diffuse, double e_pres) {
+  for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT) {
+    const bool pore = phase[i] == 0;
+    if (diffuse) {
+      const double fv = pore ? fmin(1.0, f[i] + dtk * c[i]) : 0.0;
+      f[i] = fv;
+      e[i] = pore ? e_per_f * fv : 0.0;
+    } else {
+      e[i] = pore ? e_pres : 0.0;
+    }
+  }
+}
+
+// H = max(H, psi+(eps - e I)) with the undegraded Lame constants (Sec. 2.4,
+// eq. energy, 2D): psi+ = (lambda + mu)/2 <tr>_+^2 + mu dev:dev.
+__global__ void __launch_bounds__(PT) k_history(MechMat m, const double* strain, const double* e,
+                                                double* H, long long n) {
+  for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT) {
+    double lam, mu;
+    m.get(0, i, lam, mu);  // m.d is null here: undegraded
+    const double ev = e[i];
+    const double l11 = strain[i] - ev, l22 = strain[n + i] - ev, l12 = strain[2 * n + i];
+    const double tr = l11 + l22;
+    const double trp = 0.5 * (tr + fabs(tr));
+    const double d11 = l11 - 0.5 * tr, d22 = l22 - 0.5 * tr;
+    const double devdev = d11 * d11 + d22 * d22 + 2.0 * l12 * l12;
+    const double psi = 0.5 * (lam + mu) * trp * trp + mu * devdev;
+    H[i] = fmax(H[i], psi);
+  }
+}
+
+// Observables: partial [max d, count(solid & d > 0.9), sum_solid d, sum f, count solid]
+__global__ void __launch_bounds__(PT) k_observe(const uint8_t* phase, const double* d,
+                                                const double* f, long long n, double* part) {
+  __shared__ double red[NT / 64];
+  __shared__ double redm[NT];
+  double mx = 0.0, cnt = 0.0, sd = 0.0, sf = 0.0, ns = 0.0;
+  for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT) {
+    const double dv = d[i];
+    mx = fmax(mx, dv);
+    sf += f[i];
+    if (phase[i] != 0) {
+      ns += 1.0;
+      sd += dv;
+      cnt += dv > 0.9 ? 1.0 : 0.0;
+    }
+  }
+  redm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) redm[threadIdx.x] = fmax(redm[threadIdx.x], redm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double t1 = block_sum(cnt, red), t2 = block_sum(sd, red), t3 = block_sum(sf, red),
+               t4 = block_sum(ns, red);
+  if (threadIdx.x == 0) {
+    part[5 * blockIdx.x + 0] = redm[0];
+    part[5 * blockIdx.x + 1] = t1;
+    part[5 * blockIdx.x + 2] = t2;
+    part[5 * blockIdx.x + 3] = t3;
+    part[5 * blockIdx.x + 4] = t4;
+  }
+}
+
+}  // namespace fgcg

@@ -1,0 +1,339 @@
+"""Thin Python binding of the fgcg C ABI (include/fgcg.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libfgcg.so``.  PyTorch provides device memory and the current stream.  The
+binding checks shapes, dtypes, devices and contiguity of every tensor before
+handing raw pointers to the library, and raises ``FgcgError`` for any status
+other than OK (NOT_CONVERGED is reported in the returned info instead).  If
+the library is missing, every call raises: there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfgcg.so")
+
+FGCG_OK, FGCG_NOT_CONVERGED = 0, 1
+FP64, FP32_MIXED = 0, 1
+MAX_PHASES = 8
+KINDS = {
+    "mech_row_fwd": 0, "mech_col": 1, "mech_row_inv": 2,
+    "pf_row_fwd": 3, "pf_col": 4, "pf_row_inv": 5,
+    "diff_row_fwd": 6, "diff_col_grad": 7, "diff_row_mid": 8, "diff_col_div": 9, "diff_row_inv": 10,
+}
+
+
+class FgcgError(RuntimeError):
+    def __init__(self, status, where, detail):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
+                ("precision", ctypes.c_int)]
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("phase", ctypes.c_void_p), ("nphase", ctypes.c_int), ("E_tab", ctypes.POINTER(ctypes.c_double)),
+                ("nu_tab", ctypes.POINTER(ctypes.c_double)), ("E_field", ctypes.c_void_p),
+                ("nu_field", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("rel_res", ctypes.c_double),
+                ("bnorm", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return dict(iters=self.iters, status=self.status, rel_res=self.rel_res, bnorm=self.bnorm,
+                    seconds=self.seconds)
+
+
+class State(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_void_p), ("f", ctypes.c_void_p), ("e", ctypes.c_void_p), ("H", ctypes.c_void_p),
+                ("d", ctypes.c_void_p), ("strain", ctypes.c_void_p), ("step", ctypes.c_int)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("mat", Material), ("D_tab", ctypes.POINTER(ctypes.c_double)),
+                ("k_tab", ctypes.POINTER(ctypes.c_double)), ("band_width", ctypes.c_int), ("c_dir", ctypes.c_double),
+                ("dt", ctypes.c_double), ("e_per_f", ctypes.c_double), ("Gc", ctypes.c_double),
+                ("l0", ctypes.c_double), ("kappa", ctypes.c_double), ("eps_mac", ctypes.c_double * 3),
+                ("tol_diff", ctypes.c_double), ("tol_mech", ctypes.c_double), ("tol_pf", ctypes.c_double),
+                ("maxit", ctypes.c_int), ("diffuse", ctypes.c_int), ("e_ramp", ctypes.c_double),
+                ("n_ramp", ctypes.c_int)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("diff", Info), ("mech", Info), ("pf", Info), ("mean_stress", ctypes.c_double * 3),
+                ("energy", ctypes.c_double), ("max_d", ctypes.c_double), ("damaged_fraction", ctypes.c_double),
+                ("porosity_increase", ctypes.c_double), ("total_precipitate", ctypes.c_double)]
+
+    def as_dict(self):
+        return dict(diff=self.diff.as_dict(), mech=self.mech.as_dict(), pf=self.pf.as_dict(),
+                    mean_stress=list(self.mean_stress), energy=self.energy, max_d=self.max_d,
+                    damaged_fraction=self.damaged_fraction, porosity_increase=self.porosity_increase,
+                    total_precipitate=self.total_precipitate)
+
+
+_lib = None
+_vp, _dp, _ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+_SIGS = {
+    "fgcg_create": (_ip, [ctypes.POINTER(Grid), _vp, ctypes.POINTER(_vp)]),
+    "fgcg_destroy": (None, [_vp]),
+    "fgcg_set_stream": (_ip, [_vp, _vp]),
+    "fgcg_strerror": (ctypes.c_char_p, [_ip]),
+    "fgcg_last_error": (ctypes.c_char_p, []),
+    "fgcg_mech_solve": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _dp, ctypes.c_double, _ip,
+                              _vp, _vp, _dp, _dp, ctypes.POINTER(Info)]),
+    "fgcg_phasefield_solve": (_ip, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, ctypes.c_double, _ip,
+                                    ctypes.POINTER(Info)]),
+    "fgcg_diffusion_step": (_ip, [_vp, _vp, _ip, _dp, _dp, _ip, ctypes.c_double, ctypes.c_double, _vp,
+                                  ctypes.c_double, _ip, ctypes.POINTER(Info)]),
+    "fgcg_staggered_step": (_ip, [_vp, ctypes.POINTER(State), ctypes.POINTER(Params), ctypes.POINTER(StepInfo)]),
+    "fgcg_mech_apply": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _vp]),
+    "fgcg_phasefield_apply": (_ip, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]),
+    "fgcg_diffusion_apply": (_ip, [_vp, _vp, _ip, _dp, _dp, ctypes.c_double, _vp, _vp]),
+    "fgcg_profile": (_ip, [_vp, ctypes.c_uint]),
+    "fgcg_profile_read": (_ip, [_vp, _ip, _dp, ctypes.POINTER(ctypes.c_longlong)]),
+    "fgcg_kernel_name": (ctypes.c_char_p, [_vp, _ip]),
+}
+EXPORTS = tuple(_SIGS)
+
+
+def load_library(path=LIB_PATH):
+    """Load libfgcg.so and declare every exported signature (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FgcgError(-5, "load", f"{path} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status, where, allow_nc=False):
+    if status == FGCG_OK or (allow_nc and status == FGCG_NOT_CONVERGED):
+        return status
+    lib = load_library()
+    raise FgcgError(status, where, lib.fgcg_strerror(status).decode() + ": " + lib.fgcg_last_error().decode())
+
+
+def _dvec(vals):
+    arr = (ctypes.c_double * len(vals))(*[float(v) for v in vals])
+    return arr
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """One fgcg context (workspace for one grid).  Fields are torch CUDA
+    tensors shaped (ny, nx) (scalars) or (comp, ny, nx)."""
+
+    def __init__(self, nx, ny, h, precision=FP64, device=None):
+        torch = _torch()
+        self.lib = load_library()
+        self.nx, self.ny, self.h = int(nx), int(ny), float(h)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        g = Grid(2, (ctypes.c_int * 3)(self.nx, self.ny, 1), self.h, int(precision))
+        out = _vp()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(self.lib.fgcg_create(ctypes.byref(g), _vp(stream), ctypes.byref(out)), "fgcg_create")
+        self.ptr = out
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            self.lib.fgcg_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------- helpers
+    def _sync_stream(self):
+        torch = _torch()
+        _check(self.lib.fgcg_set_stream(self.ptr, _vp(torch.cuda.current_stream(self.device).cuda_stream)),
+               "fgcg_set_stream")
+
+    def _t(self, t, name, dtype, comps=None, allow_none=False):
+        torch = _torch()
+        if t is None:
+            if allow_none:
+                return None
+            raise FgcgError(-1, name, "required tensor is None")
+        shape = (self.ny, self.nx) if comps is None else (comps, self.ny, self.nx)
+        if not isinstance(t, torch.Tensor):
+            raise FgcgError(-1, name, "expected a torch tensor")
+        if t.device != self.device:
+            raise FgcgError(-1, name, f"tensor on {t.device}, context on {self.device}")
+        if t.dtype != dtype:
+            raise FgcgError(-1, name, f"dtype {t.dtype}, expected {dtype}")
+        if tuple(t.shape) != shape:
+            raise FgcgError(-1, name, f"shape {tuple(t.shape)}, expected {shape}")
+        if not t.is_contiguous():
+            raise FgcgError(-1, name, "tensor must be contiguous")
+        return t
+
+    def _ptr(self, t):
+        return None if t is None else _vp(t.data_ptr())
+
+    def _material(self, phase, E_tab, nu_tab, E_field=None, nu_field=0.2):
+        torch = _torch()
+        keep = []
+        if E_field is not None:
+            self._t(E_field, "E_field", torch.float64)
+            m = Material(None, 0, None, None, _vp(E_field.data_ptr()), float(nu_field))
+        else:
+            self._t(phase, "phase", torch.uint8)
+            E_tab = list(E_tab)
+            nu_tab = list(nu_tab)
+            if not (1 <= len(E_tab) <= MAX_PHASES and len(E_tab) == len(nu_tab)):
+                raise FgcgError(-1, "material", "E_tab/nu_tab must have equal length 1..8")
+            Ea, na = _dvec(E_tab), _dvec(nu_tab)
+            keep = [Ea, na]
+            m = Material(_vp(phase.data_ptr()), len(E_tab), Ea, na, None, 0.0)
+        return m, keep
+
+    # ---------------------------------------------------------- entries
+    def mech_solve(self, phase, E_tab, nu_tab, eps_mac, d=None, kappa=0.0, eig=None, tol=1e-10, maxit=20000,
+                   want_stress=True, E_field=None, nu_field=0.2, strain=None, stress=None):
+        torch = _torch()
+        m, keep = self._material(phase, E_tab, nu_tab, E_field, nu_field)
+        self._t(d, "d", torch.float64, allow_none=True)
+        self._t(eig, "eig", torch.float64, allow_none=True)
+        if strain is None:
+            strain = torch.empty((3, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        self._t(strain, "strain", torch.float64, comps=3)
+        if want_stress and stress is None:
+            stress = torch.empty((3, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        self._t(stress, "stress", torch.float64, comps=3, allow_none=True)
+        em = _dvec(eps_mac)
+        mean = (ctypes.c_double * 3)()
+        energy = ctypes.c_double()
+        info = Info()
+        self._sync_stream()
+        st = self.lib.fgcg_mech_solve(self.ptr, ctypes.byref(m), self._ptr(d), float(kappa), self._ptr(eig), em,
+                                      float(tol), int(maxit), self._ptr(strain), self._ptr(stress), mean,
+                                      ctypes.byref(energy), ctypes.byref(info))
+        _check(st, "fgcg_mech_solve", allow_nc=True)
+        del keep
+        return dict(strain=strain, stress=stress, mean_stress=np.array(list(mean)), energy=energy.value,
+                    info=info.as_dict())
+
+    def phasefield_solve(self, H, Gc, l0, d, tol=1e-10, maxit=20000):
+        torch = _torch()
+        self._t(H, "H", torch.float64)
+        self._t(d, "d", torch.float64)
+        info = Info()
+        self._sync_stream()
+        st = self.lib.fgcg_phasefield_solve(self.ptr, self._ptr(H), float(Gc), float(l0), self._ptr(d), float(tol),
+                                            int(maxit), ctypes.byref(info))
+        _check(st, "fgcg_phasefield_solve", allow_nc=True)
+        return info.as_dict()
+
+    def diffusion_step(self, phase, D_tab, k_tab, band_width, c_dir, dt, c, tol=1e-10, maxit=20000):
+        torch = _torch()
+        self._t(phase, "phase", torch.uint8)
+        self._t(c, "c", torch.float64)
+        if len(D_tab) != len(k_tab) or not 1 <= len(D_tab) <= MAX_PHASES:
+            raise FgcgError(-1, "diffusion_step", "D_tab/k_tab must have equal length 1..8")
+        info = Info()
+        self._sync_stream()
+        st = self.lib.fgcg_diffusion_step(self.ptr, self._ptr(phase), len(D_tab), _dvec(D_tab), _dvec(k_tab),
+                                          int(band_width), float(c_dir), float(dt), self._ptr(c), float(tol),
+                                          int(maxit), ctypes.byref(info))
+        _check(st, "fgcg_diffusion_step", allow_nc=True)
+        return info.as_dict()
+
+    def new_state(self, band_width=0, c_dir=1.0):
+        torch = _torch()
+        z = lambda *s: torch.zeros(s, dtype=torch.float64, device=self.device)
+        st = dict(c=z(self.ny, self.nx), f=z(self.ny, self.nx), e=z(self.ny, self.nx), H=z(self.ny, self.nx),
+                  d=z(self.ny, self.nx), strain=z(3, self.ny, self.nx), step=0)
+        if band_width > 0:
+            st["c"][:, :band_width] = c_dir
+        return st
+
+    def staggered_step(self, state, phase, prm):
+        """prm: dict with the fields of fgcg_params (see oracle.staggered.Params)."""
+        torch = _torch()
+        for k in ("c", "f", "e", "H", "d"):
+            self._t(state[k], k, torch.float64)
+        self._t(state["strain"], "strain", torch.float64, comps=3)
+        m, keep = self._material(phase, prm["E_tab"], prm["nu_tab"])
+        Dt, kt = _dvec(prm["D_tab"]), _dvec(prm["k_tab"])
+        if len(prm["D_tab"]) != m.nphase or len(prm["k_tab"]) != m.nphase:
+            raise FgcgError(-1, "staggered_step", "D_tab/k_tab length must equal nphase")
+        p = Params(m, Dt, kt, int(prm["band_width"]), float(prm["c_dir"]), float(prm["dt"]), float(prm["e_per_f"]),
+                   float(prm["Gc"]), float(prm["l0"]), float(prm["kappa"]), (ctypes.c_double * 3)(*prm["eps_mac"]),
+                   float(prm["tol_diff"]), float(prm["tol_mech"]), float(prm["tol_pf"]), int(prm["maxit"]),
+                   int(prm["diffuse"]), float(prm.get("e_ramp", 0.0)), int(prm.get("n_ramp", 0)))
+        s = State(*[_vp(state[k].data_ptr()) for k in ("c", "f", "e", "H", "d", "strain")], int(state["step"]))
+        info = StepInfo()
+        self._sync_stream()
+        st = self.lib.fgcg_staggered_step(self.ptr, ctypes.byref(s), ctypes.byref(p), ctypes.byref(info))
+        _check(st, "fgcg_staggered_step", allow_nc=True)
+        state["step"] = s.step
+        del keep
+        return info.as_dict()
+
+    # ------------------------------------------------------- test hooks
+    def mech_apply(self, phase, E_tab, nu_tab, p, d=None, kappa=0.0, E_field=None, nu_field=0.2):
+        torch = _torch()
+        m, keep = self._material(phase, E_tab, nu_tab, E_field, nu_field)
+        self._t(p, "p", torch.float64, comps=4)
+        self._t(d, "d", torch.float64, allow_none=True)
+        q = torch.empty_like(p)
+        self._sync_stream()
+        _check(self.lib.fgcg_mech_apply(self.ptr, ctypes.byref(m), self._ptr(d), float(kappa), self._ptr(p),
+                                        self._ptr(q)), "fgcg_mech_apply")
+        return q
+
+    def phasefield_apply(self, H, Gc, l0, v):
+        torch = _torch()
+        self._t(H, "H", torch.float64)
+        self._t(v, "v", torch.float64)
+        q = torch.empty_like(v)
+        self._sync_stream()
+        _check(self.lib.fgcg_phasefield_apply(self.ptr, self._ptr(H), float(Gc), float(l0), self._ptr(v),
+                                              self._ptr(q)), "fgcg_phasefield_apply")
+        return q
+
+    def diffusion_apply(self, phase, D_tab, k_tab, dt, v):
+        torch = _torch()
+        self._t(phase, "phase", torch.uint8)
+        self._t(v, "v", torch.float64)
+        q = torch.empty_like(v)
+        self._sync_stream()
+        _check(self.lib.fgcg_diffusion_apply(self.ptr, self._ptr(phase), len(D_tab), _dvec(D_tab), _dvec(k_tab),
+                                             float(dt), self._ptr(v), self._ptr(q)), "fgcg_diffusion_apply")
+        return q
+
+    # --------------------------------------------------------- profiling
+    def profile(self, kinds):
+        mask = 0
+        for k in kinds:
+            mask |= 1 << KINDS[k]
+        _check(self.lib.fgcg_profile(self.ptr, mask), "fgcg_profile")
+
+    def profile_read(self, kind):
+        ms = ctypes.c_double()
+        n = ctypes.c_longlong()
+        _check(self.lib.fgcg_profile_read(self.ptr, KINDS[kind], ctypes.byref(ms), ctypes.byref(n)),
+               "fgcg_profile_read")
+        name = self.lib.fgcg_kernel_name(self.ptr, KINDS[kind]).decode()
+        return ms.value, n.value, name
