@@ -31,6 +31,13 @@ template <bool INV, typename C> __device__ __forceinline__ C cmul_mi(C a) {
   return INV ? C{-a.y, a.x} : C{a.y, -a.x};
 }
 
+// LDS index of complex element i: one 16-byte pad per 8 elements.  With it the
+// R-strided Stockham writes of the first stages (lane l writes 8 l + r, or
+// 64 (l / 8) + l % 8 + 8 r) land on 8 distinct 16-byte bank groups for every
+// 8 consecutive lanes, and contiguous accesses stay conflict-free.
+__device__ __forceinline__ int lds(int i) { return i + (i >> 3); }
+constexpr int lds_size(int n) { return n + n / 8 + 1; }
+
 // ---------------------------------------------------------------- radix plan
 constexpr int count3(int n) { return n % 3 == 0 ? 1 + count3(n / 3) : 0; }
 constexpr int pow3(int a) { return a == 0 ? 1 : 3 * pow3(a - 1); }
@@ -146,9 +153,8 @@ __device__ __forceinline__ void stockham_stage(typename cvec<T>::type* buf,
     const int b = tid + q * NT;
     if (TOT % NT == 0 || b < TOT) {
       const int sig = b / M, j = b - sig * M;
-      const C* s = buf + sig * N;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = s[j + r * M];
+      for (int r = 0; r < R; ++r) v[q][r] = buf[lds(sig * N + j + r * M)];
       if (NS > 1) {
         const int k = j % NS;
 #pragma unroll
@@ -168,9 +174,9 @@ __device__ __forceinline__ void stockham_stage(typename cvec<T>::type* buf,
     if (TOT % NT == 0 || b < TOT) {
       const int sig = b / M, j = b - sig * M;
       const int k = j % NS;
-      C* s = buf + sig * N + (j / NS) * NS * R + k;
+      const int base = sig * N + (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) s[r * NS] = v[q][r];
+      for (int r = 0; r < R; ++r) buf[lds(base + r * NS)] = v[q][r];
     }
   }
   __syncthreads();
@@ -189,7 +195,8 @@ struct StageRunner {
   }
 };
 
-// Transform NSIG signals of length N in LDS; callers synchronise before.
+// Transform NSIG signals of length N in LDS (element i of signal g at
+// lds(g N + i)); callers synchronise before.
 // Forward uses exp(-2 pi i k x / N); inverse uses exp(+...) without 1/N.
 template <typename T, int N, int NSIG, int NT, bool INV>
 __device__ __forceinline__ void fft_lds(typename cvec<T>::type* buf,

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <type_traits>
@@ -60,7 +61,16 @@ struct fgcg_ctx {
   long long n = 0;
   double h = 0;
   int prec = FGCG_FP64;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;       // context-owned stream: every launch goes here
+  hipStream_t user_stream = nullptr;  // caller's stream; work on it is waited for at entry
+  hipEvent_t ev_in = nullptr;
+  hipEvent_t ev_done[2] = {nullptr, nullptr};
+  bool use_graphs = true;
+  bool building = false;            // launches become nodes of `graph`
+  bool build_timed = false;         // add event-record nodes while building
+  hipGraph_t graph = nullptr;
+  hipGraphNode_t last = nullptr;
+  int chunk = 16;  // CG iterations per captured graph
   void* twx = nullptr;  // CT<T>[nx]
   void* twy = nullptr;  // CT<T>[ny]
   double2* Dx = nullptr;
@@ -89,6 +99,15 @@ struct fgcg_ctx {
   };
   std::vector<Pending> pending;
   hipEvent_t cur = nullptr;
+  struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    std::vector<Pending> ev;  // timing events recorded inside this instance
+  };
+  struct CgGraph {
+    std::vector<char> key;
+    GraphSlot slot[2];
+  };
+  CgGraph graphs[3];  // mechanics, phase field, diffusion
 };
 
 namespace {
@@ -131,6 +150,54 @@ int prof_flush(fgcg_ctx* c) {
   return 0;
 }
 
+int prof_reserve(fgcg_ctx* c, size_t n) {
+  while (c->pool.size() < n) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->pool.push_back(e);
+  }
+  return 0;
+}
+
+int prof_read_slot(fgcg_ctx* c, fgcg_ctx::GraphSlot& sl) {
+  for (auto& p : sl.ev) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    c->prof_ms[p.kind] += ms;
+    c->prof_n[p.kind] += 1;
+  }
+  return 0;
+}
+
+void release_graph(fgcg_ctx* c, fgcg_ctx::CgGraph& g) {
+  for (auto& sl : g.slot) {
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    sl.exec = nullptr;
+    for (auto& p : sl.ev) {
+      c->pool.push_back(p.a);
+      c->pool.push_back(p.b);
+    }
+    sl.ev.clear();
+  }
+  g.key.clear();
+}
+
+int enter(fgcg_ctx* c) {
+  HIPCHK(hipEventRecord(c->ev_in, c->user_stream));
+  HIPCHK(hipStreamWaitEvent(c->stream, c->ev_in, 0));
+  return 0;
+}
+
+// Byte key of the values an iteration chunk was captured with.
+struct Key {
+  std::vector<char> b;
+  template <typename V> Key& add(const V& v) {
+    const char* p = reinterpret_cast<const char*>(&v);
+    b.insert(b.end(), p, p + sizeof(V));
+    return *this;
+  }
+};
+
 template <typename T> const char* tname() { return std::is_same<T, double>::value ? "double" : "float"; }
 
 void set_kname(fgcg_ctx* c, int kind, const char* fmt, const char* t, int n) {
@@ -138,6 +205,48 @@ void set_kname(fgcg_ctx* c, int kind, const char* fmt, const char* t, int n) {
   char b[256];
   snprintf(b, sizeof b, fmt, t, n);
   c->kname[kind] = b;
+}
+
+// One launch: a plain stream launch (timed with events when its kind is
+// profiled), or, while a chunk graph is being built, a kernel node appended to
+// the chain (between two event-record nodes when profiled).
+template <typename... A>
+int launch(fgcg_ctx* c, int kind, const void* fn, dim3 grid, A... args) {
+  void* ptrs[] = {(void*)&args...};
+  const bool prof = kind >= 0 && (c->prof_mask & (1u << kind)) && (!c->building || c->build_timed);
+  if (!c->building) {
+    int rc = prof ? prof_begin(c, kind) : 0;
+    if (rc) return rc;
+    HIPCHK(hipLaunchKernel(fn, grid, dim3(NT), ptrs, 0, c->stream));
+    return prof ? prof_end(c, kind) : 0;
+  }
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (prof) {
+    ea = c->pool.back();
+    c->pool.pop_back();
+    eb = c->pool.back();
+    c->pool.pop_back();
+    hipGraphNode_t n;
+    HIPCHK(hipGraphAddEventRecordNode(&n, c->graph, c->last ? &c->last : nullptr, c->last ? 1 : 0, ea));
+    c->last = n;
+  }
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(fn);
+  kp.gridDim = grid;
+  kp.blockDim = dim3(NT);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = ptrs;
+  kp.extra = nullptr;
+  hipGraphNode_t kn;
+  HIPCHK(hipGraphAddKernelNode(&kn, c->graph, c->last ? &c->last : nullptr, c->last ? 1 : 0, &kp));
+  c->last = kn;
+  if (prof) {
+    hipGraphNode_t n;
+    HIPCHK(hipGraphAddEventRecordNode(&n, c->graph, &c->last, 1, eb));
+    c->last = n;
+    c->pending.push_back({kind, ea, eb});
+  }
+  return 0;
 }
 
 template <typename T, int NOUT, class Pro>
@@ -148,10 +257,8 @@ int launch_row_fwd(fgcg_ctx* c, int kind, const Pro& pro, CT<T>* spec, int nsamp
     constexpr int R = rows_for(NX);
     dim3 g((c->ny + R - 1) / R, nsamp);
     if (kind >= 0) set_kname(c, kind, "k_row_fwd<%s, %d", tname<T>(), NX);
-    if (kind >= 0) rc |= prof_begin(c, kind);
-    hipLaunchKernelGGL((k_row_fwd<T, NX, NOUT, Pro>), g, dim3(NT), 0, c->stream, pro, spec, c->ny, ss,
-                       (const CT<T>*)c->twx);
-    if (kind >= 0) rc |= prof_end(c, kind);
+    rc = launch(c, kind, (const void*)&k_row_fwd<T, NX, NOUT, Pro>, g, pro, spec, c->ny, ss,
+                (const CT<T>*)c->twx);
   });
   return rc;
 }
@@ -164,10 +271,8 @@ int launch_col(fgcg_ctx* c, int kind, const Sym& sym, const CT<T>* in, CT<T>* ou
     constexpr int NY = decltype(NYc)::value;
     dim3 g(c->nxh, nsamp);
     if (kind >= 0) set_kname(c, kind, "k_col<%s, %d", tname<T>(), NY);
-    if (kind >= 0) rc |= prof_begin(c, kind);
-    hipLaunchKernelGGL((k_col<T, NY, NIN, NOUT, Sym>), g, dim3(NT), 0, c->stream, sym, in, out, c->nxh, ss,
-                       ss, (const CT<T>*)c->twy);
-    if (kind >= 0) rc |= prof_end(c, kind);
+    rc = launch(c, kind, (const void*)&k_col<T, NY, NIN, NOUT, Sym>, g, sym, in, out, c->nxh, ss, ss,
+                (const CT<T>*)c->twy);
   });
   return rc;
 }
@@ -181,10 +286,8 @@ int launch_row_inv(fgcg_ctx* c, int kind, const Epi& epi, const CT<T>* spec, int
     constexpr int R = rows_for(NX);
     dim3 g((c->ny + R - 1) / R, nsamp);
     if (kind >= 0) set_kname(c, kind, "k_row_inv<%s, %d", tname<T>(), NX);
-    if (kind >= 0) rc |= prof_begin(c, kind);
-    hipLaunchKernelGGL((k_row_inv<T, NX, NIN, Epi>), g, dim3(NT), 0, c->stream, epi, spec, c->ny, ss,
-                       (const CT<T>*)c->twx);
-    if (kind >= 0) rc |= prof_end(c, kind);
+    rc = launch(c, kind, (const void*)&k_row_inv<T, NX, NIN, Epi>, g, epi, spec, c->ny, ss,
+                (const CT<T>*)c->twx);
   });
   return rc;
 }
@@ -197,18 +300,24 @@ int launch_row_mid(fgcg_ctx* c, int kind, const Mid& mid, CT<T>* spec, int nsamp
     constexpr int R = rows_for(NX);
     dim3 g((c->ny + R - 1) / R, nsamp);
     if (kind >= 0) set_kname(c, kind, "k_row_mid<%s, %d", tname<T>(), NX);
-    if (kind >= 0) rc |= prof_begin(c, kind);
-    hipLaunchKernelGGL((k_row_mid<T, NX, NIN, NOUT, Mid>), g, dim3(NT), 0, c->stream, mid, spec, c->ny, ss,
-                       (const CT<T>*)c->twx);
-    if (kind >= 0) rc |= prof_end(c, kind);
+    rc = launch(c, kind, (const void*)&k_row_mid<T, NX, NIN, NOUT, Mid>, g, mid, spec, c->ny, ss,
+                (const CT<T>*)c->twx);
   });
   return rc;
 }
 
-// Chunked CG driver: enqueue chunks of iterations; each pass exits at once
-// when the device state says the solve has ended; the host reads the state
-// once per chunk.
-template <class F> int run_cg(fgcg_ctx* c, F&& iter, int maxit) {
+// CG drivers.  Every pass exits at once when the device state says the
+// solve has ended, so chunks of iterations can be enqueued blindly and the
+// host reads the state once per chunk.
+//
+// Graph mode (default): a chunk of K iterations is built once into two graph
+// instances (rebuilt only when the values the kernels were given change); the
+// instances are replayed alternately so that one is always queued while the
+// host checks the state left by the other.  Event-record nodes around the
+// profiled kernel nodes of the first instance time those launches inside the
+// graph (an event node costs about 10 us of idle time, so the second instance
+// carries none and profiling samples every other chunk).
+template <class F> int run_cg_plain(fgcg_ctx* c, F&& iter, int maxit) {
   long long k = 0;
   int chunk = 2;
   for (;;) {
@@ -218,13 +327,77 @@ template <class F> int run_cg(fgcg_ctx* c, F&& iter, int maxit) {
     if (rc) return rc;
     if (c->h_st->done) return 0;
     if (k > (long long)maxit + 1) return fail(FGCG_EHIP, "CG driver overran the iteration limit");
-    for (int j = 0; j < chunk; ++j) {
-      rc = iter((int)k++);
+    for (int j = 0; j < chunk; ++j, ++k) {
+      rc = iter();
       if (rc) return rc;
     }
     HIPCHK(hipGetLastError());
     chunk = chunk < 32 ? chunk * 2 : 32;
   }
+}
+
+template <class F> int build_chunk(fgcg_ctx* c, fgcg_ctx::GraphSlot& sl, F& iter, int K, bool timed) {
+  c->pending.clear();
+  HIPCHK(hipGraphCreate(&c->graph, 0));
+  c->building = true;
+  c->build_timed = timed;
+  c->last = nullptr;
+  int rc = 0;
+  for (int j = 0; j < K && !rc; ++j) rc = iter();
+  c->building = false;
+  hipGraph_t g = c->graph;
+  c->graph = nullptr;
+  if (!rc) {
+    const hipError_t ei = hipGraphInstantiate(&sl.exec, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) rc = fail(FGCG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  (void)hipGraphDestroy(g);
+  sl.ev.swap(c->pending);
+  c->pending.clear();
+  return rc;
+}
+
+template <class F> int run_cg(fgcg_ctx* c, int which, const Key& key, F&& iter, int maxit) {
+  if (!c->use_graphs) return run_cg_plain(c, iter, maxit);
+  HIPCHK(hipMemcpyAsync(c->h_st, c->st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  int rc = prof_flush(c);
+  if (rc) return rc;
+  if (c->h_st->done) return 0;
+  const int K = c->chunk;
+  fgcg_ctx::CgGraph& G = c->graphs[which];
+  Key full = key;
+  full.add(c->prof_mask);
+  if (G.key != full.b || !G.slot[0].exec || !G.slot[1].exec) {
+    release_graph(c, G);
+    if ((rc = prof_reserve(c, 4 * (size_t)K * FGCG_K_NKINDS))) return rc;
+    for (int i = 0; i < 2; ++i)
+      if ((rc = build_chunk(c, G.slot[i], iter, K, i == 0))) return rc;
+    G.key = full.b;
+  }
+  CgState* hs = c->h_st;  // two pinned slots
+  long long launched = 0;
+  auto go = [&](int i) -> int {
+    HIPCHK(hipGraphLaunch(G.slot[i].exec, c->stream));
+    HIPCHK(hipMemcpyAsync(hs + i, c->st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipEventRecord(c->ev_done[i], c->stream));
+    launched += K;
+    return 0;
+  };
+  if ((rc = go(0)) || (rc = go(1))) return rc;
+  int i = 0;
+  for (;;) {
+    HIPCHK(hipEventSynchronize(c->ev_done[i]));
+    if ((rc = prof_read_slot(c, G.slot[i]))) return rc;
+    if (hs[i].done) break;
+    if (launched > (long long)maxit + 4LL * K) return fail(FGCG_EHIP, "CG driver overran the iteration limit");
+    if ((rc = go(i))) return rc;
+    i ^= 1;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if ((rc = prof_read_slot(c, G.slot[i ^ 1]))) return rc;
+  if (i != 0) hs[0] = hs[i];
+  return 0;
 }
 
 int status_of(const CgState& s) {
@@ -300,17 +473,19 @@ int mech_solve_t(fgcg_ctx* c, const MechMat& m, const double* eig, const double*
   StoreEpi<T, 4> st0{R, X, (T)-1, c->nx, c->part_rr, 0};
   if ((rc = launch_row_inv<T, 4>(c, -1, st0, spec))) return rc;
   hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_rr, c->nrow, 0, tol, maxit);
-  auto iter = [&](int k) -> int {
-    CgCtl cc{c->st, c->part_a, c->part_rr, c->nrow, c->nrow, 0, 0, k};
-    MechCgPro<T> pro{P, R, c->nx, m, cc};
+  const CgCtl cc{c->st, c->part_a, c->part_rr, c->nrow, c->nrow, 0, 0};
+  const MechCgPro<T> pro{P, R, c->nx, m, cc};
+  const MechProj<T> proj{c->Dx, c->Dy, 1.0 / (double)c->n, c->st};
+  const MechCgEpi<T> epi{X, R, P, c->nx, cc};
+  auto iter = [&]() -> int {
     int r = launch_row_fwd<T, 3>(c, FGCG_K_MECH_ROW_FWD, pro, spec);
-    MechProj<T> proj{c->Dx, c->Dy, 1.0 / (double)c->n, c->st};
     r |= launch_col<T, 3, 4>(c, FGCG_K_MECH_COL, proj, spec, spec);
-    MechCgEpi<T> epi{X, R, P, c->nx, cc};
     r |= launch_row_inv<T, 4>(c, FGCG_K_MECH_ROW_INV, epi, spec);
     return r;
   };
-  if ((rc = run_cg(c, iter, maxit))) return rc;
+  Key key;
+  key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm);
+  if ((rc = run_cg(c, 0, key, iter, maxit))) return rc;
   const CgState s = *c->h_st;
   hipLaunchKernelGGL((k_mech_post<T>), dim3(c->npost), dim3(PT), 0, c->stream, m, (const T*)c->x, c->n, eig,
                      em[0], em[1], em[2], strain, stress, c->part_post);
@@ -361,17 +536,19 @@ int pf_solve_t(fgcg_ctx* c, const double* H, double Gc, double l0, double* d, do
   PfResEpi<T> res{X, R, H, 0, a, c->nx, c->part_rr, 0};
   if ((rc = launch_row_inv<T, 1>(c, -1, res, spec))) return rc;
   hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_b, c->npost, 0, tol, maxit);
-  auto iter = [&](int k) -> int {
-    CgCtl cc{c->st, c->part_a, c->part_rr, c->nrow + c->ncol, c->nrow, 0, 0, k};
-    PfCgPro<T> pro{P, R, H, 0, a, c->nx, cc};
+  const CgCtl cc{c->st, c->part_a, c->part_rr, c->nrow + c->ncol, c->nrow, 0, 0};
+  const PfCgPro<T> pro{P, R, H, 0, a, c->nx, cc};
+  const PfLap<T> lap{c->Dx, c->Dy, cl, c->nx, c->st, c->part_a, 0, c->nrow};
+  const PfCgEpi<T> epi{X, R, P, H, 0, a, c->nx, cc};
+  auto iter = [&]() -> int {
     int r = launch_row_fwd<T, 1>(c, FGCG_K_PF_ROW_FWD, pro, spec);
-    PfLap<T> lap{c->Dx, c->Dy, cl, c->nx, c->st, c->part_a, 0, c->nrow};
     r |= launch_col<T, 1, 1>(c, FGCG_K_PF_COL, lap, spec, spec);
-    PfCgEpi<T> epi{X, R, P, H, 0, a, c->nx, cc};
     r |= launch_row_inv<T, 1>(c, FGCG_K_PF_ROW_INV, epi, spec);
     return r;
   };
-  if ((rc = run_cg(c, iter, maxit))) return rc;
+  Key key;
+  key.add(H).add(a).add(cl);
+  if ((rc = run_cg(c, 1, key, iter, maxit))) return rc;
   const CgState s = *c->h_st;
   if (s.zero_rhs) HIPCHK(hipMemsetAsync(c->x, 0, sizeof(T) * c->n, c->stream));
   hipLaunchKernelGGL((k_convert<double, T>), dim3(c->npost), dim3(PT), 0, c->stream, d, (const T*)c->x, c->n);
@@ -450,16 +627,18 @@ int diff_step_t(fgcg_ctx* c, const DiffCoef& co, double c_dir, double* cfield, d
   if ((rc = launch_row_inv<T, 1>(c, -1, er, spec))) return rc;
   hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_b, c->nrow, 0, tol, maxit);
   static const int kinds[3] = {FGCG_K_DIFF_COL_GRAD, FGCG_K_DIFF_ROW_MID, FGCG_K_DIFF_COL_DIV};
-  auto iter = [&](int k) -> int {
-    CgCtl cc{c->st, c->part_a, c->part_rr, 2 * c->nrow, c->nrow, 0, 0, k};
-    DiffCgPro<T> pro{P, R, co, c->nx, cc};
+  const CgCtl cc{c->st, c->part_a, c->part_rr, 2 * c->nrow, c->nrow, 0, 0};
+  const DiffCgPro<T> pro{P, R, co, c->nx, cc};
+  const DiffCgEpi<T> epi{X, R, P, co, c->nx, cc};
+  auto iter = [&]() -> int {
     int r = launch_row_fwd<T, 1>(c, FGCG_K_DIFF_ROW_FWD, pro, spec);
     r |= diff_pipeline_apply<T>(c, co, spec, c->st, c->part_a, c->nrow, kinds);
-    DiffCgEpi<T> epi{X, R, P, co, c->nx, cc};
     r |= launch_row_inv<T, 1>(c, FGCG_K_DIFF_ROW_INV, epi, spec);
     return r;
   };
-  if ((rc = run_cg(c, iter, maxit))) return rc;
+  Key key;
+  key.add(co.phase).add(co.dk).add(co.inv_dt).add(co.band);
+  if ((rc = run_cg(c, 2, key, iter, maxit))) return rc;
   const CgState s = *c->h_st;
   if (s.zero_rhs) HIPCHK(hipMemsetAsync(c->x, 0, sizeof(T) * c->n, c->stream));
   hipLaunchKernelGGL((k_diff_finish<T>), dim3(c->npost), dim3(PT), 0, c->stream, cfield, (const T*)c->x, c->n,
@@ -529,22 +708,31 @@ int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out) {
   c->n = (long long)c->nx * c->ny;
   c->h = grid->h;
   c->prec = grid->precision;
-  c->stream = (hipStream_t)hip_stream;
+  c->user_stream = (hipStream_t)hip_stream;
+  {
+    const char* ng = std::getenv("FGCG_NO_GRAPH");
+    c->use_graphs = !(ng && ng[0] == '1');
+  }
   with_n(c->nx, [&](auto NXc) {
     constexpr int R = rows_for(decltype(NXc)::value);
     c->nrow = (c->ny + R - 1) / R;
   });
   c->ncol = c->nxh;
   c->npost = (int)std::min<long long>((c->n + PT - 1) / PT, 1024);
-  int rc = alloc_workspace<double>(c);
+  int rc = 0;
   auto chk = [&](hipError_t e) {
     if (e != hipSuccess && !rc) rc = fail(FGCG_ENOMEM, std::string("allocation failed: ") + hipGetErrorString(e));
   };
+  chk(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+  chk(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+  chk(hipEventCreateWithFlags(&c->ev_done[0], hipEventDisableTiming));
+  chk(hipEventCreateWithFlags(&c->ev_done[1], hipEventDisableTiming));
+  if (!rc) rc = alloc_workspace<double>(c);
   if (!rc) {
     chk(hipMalloc(&c->Dx, sizeof(double2) * c->nxh));
     chk(hipMalloc(&c->Dy, sizeof(double2) * c->ny));
     chk(hipMalloc(&c->st, sizeof(CgState) * 1));
-    chk(hipHostMalloc(&c->h_st, sizeof(CgState) * 1, hipHostMallocDefault));
+    chk(hipHostMalloc(&c->h_st, sizeof(CgState) * 2, hipHostMallocDefault));
     const int npa = c->nrow + std::max(c->ncol, c->nrow);
     chk(hipMalloc(&c->part_a, sizeof(double) * npa));
     chk(hipMalloc(&c->part_rr, sizeof(double) * c->nrow));
@@ -582,17 +770,21 @@ void fgcg_destroy(fgcg_ctx* c) {
     if (p) (void)hipFree(p);
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_part) (void)hipHostFree(c->h_part);
+  for (auto& g : c->graphs) release_graph(c, g);
   for (auto& p : c->pending) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
   }
   for (auto e : c->pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : {c->ev_in, c->ev_done[0], c->ev_done[1]})
+    if (e) (void)hipEventDestroy(e);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
 int fgcg_set_stream(fgcg_ctx* c, void* s) {
   if (!c) return fail(FGCG_EINVAL, "ctx is NULL");
-  c->stream = (hipStream_t)s;
+  c->user_stream = (hipStream_t)s;
   return FGCG_OK;
 }
 
@@ -606,6 +798,7 @@ int fgcg_mech_solve(fgcg_ctx* c, const fgcg_material* mat, const double* d, doub
     if (!std::isfinite(eps_mac[j])) return fail(FGCG_EDOMAIN, "eps_mac not finite");
   MechMat m;
   if ((rc = make_mech_mat(c, mat, d, kappa, &m))) return rc;
+  if ((rc = enter(c))) return rc;
   return mech_solve_t<double>(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
 }
 
@@ -616,6 +809,7 @@ int fgcg_phasefield_solve(fgcg_ctx* c, const double* H, double Gc, double l0, do
   if ((rc = check_solver_args(tol, maxit))) return rc;
   if (!(Gc > 0.0) || !std::isfinite(Gc)) return fail(FGCG_EDOMAIN, "Gc <= 0");
   if (!(l0 > 0.0) || !std::isfinite(l0)) return fail(FGCG_EDOMAIN, "l0 <= 0");
+  if ((rc = enter(c))) return rc;
   return pf_solve_t<double>(c, H, Gc, l0, d, tol, maxit, info);
 }
 
@@ -629,6 +823,7 @@ int fgcg_diffusion_step(fgcg_ctx* c, const uint8_t* phase, int nphase, const dou
   if (!std::isfinite(c_dir)) return fail(FGCG_EDOMAIN, "c_dir not finite");
   DiffCoef co;
   if ((rc = make_diff_coef(phase, nphase, D_tab, k_tab, dt, band_width, c->n, &co))) return rc;
+  if ((rc = enter(c))) return rc;
   return diff_step_t<double>(c, co, c_dir, cfield, tol, maxit, info);
 }
 
@@ -639,6 +834,7 @@ int fgcg_staggered_step(fgcg_ctx* c, fgcg_state* s, const fgcg_params* p, fgcg_s
   if (!(p->dt > 0.0)) return fail(FGCG_EDOMAIN, "dt <= 0");
   std::memset(info, 0, sizeof *info);
   int rc;
+  if ((rc = enter(c))) return rc;
   if (p->diffuse) {
     rc = fgcg_diffusion_step(c, p->mat.phase, p->mat.nphase, p->D_tab, p->k_tab, p->band_width, p->c_dir, p->dt,
                              s->c, p->tol_diff, p->maxit, &info->diff);
@@ -689,6 +885,7 @@ int fgcg_mech_apply(fgcg_ctx* c, const fgcg_material* mat, const double* d, doub
   MechMat m;
   int rc;
   if ((rc = make_mech_mat(c, mat, d, kappa, &m))) return rc;
+  if ((rc = enter(c))) return rc;
   CT<double>* spec = (CT<double>*)c->spec;
   MechSrcPro<double> src{m, nullptr, Field<double>{(double*)p, c->n, 0}, {0, 0, 0}, c->nx};
   if ((rc = launch_row_fwd<double, 3>(c, -1, src, spec))) return rc;
@@ -706,6 +903,7 @@ int fgcg_phasefield_apply(fgcg_ctx* c, const double* H, double Gc, double l0, co
   if (!(Gc > 0.0) || !(l0 > 0.0)) return fail(FGCG_EDOMAIN, "Gc/l0 <= 0");
   CT<double>* spec = (CT<double>*)c->spec;
   int rc;
+  if ((rc = enter(c))) return rc;
   CopyPro<double> cp{Field<double>{(double*)v, c->n, 0}, c->nx};
   if ((rc = launch_row_fwd<double, 1>(c, -1, cp, spec))) return rc;
   PfLap<double> lap{c->Dx, c->Dy, 0.5 * Gc * l0 / (double)c->n, c->nx, nullptr, nullptr, 0, 0};
@@ -723,6 +921,7 @@ int fgcg_diffusion_apply(fgcg_ctx* c, const uint8_t* phase, int nphase, const do
   DiffCoef co;
   int rc;
   if ((rc = make_diff_coef(phase, nphase, D_tab, k_tab, dt, 0, c->n, &co))) return rc;
+  if ((rc = enter(c))) return rc;
   CT<double>* spec = (CT<double>*)c->spec;
   CopyPro<double> cp{Field<double>{(double*)v, c->n, 0}, c->nx};
   if ((rc = launch_row_fwd<double, 1>(c, -1, cp, spec))) return rc;

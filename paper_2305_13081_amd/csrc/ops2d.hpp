@@ -31,23 +31,29 @@
 namespace fgcg {
 
 struct CgState {
-  double rr[2];
-  double thr;
+  double rr_cur;   // r.r of the current iteration (written by the forward pass)
+  double rr_prev;  // r.r of the previous iteration (written by the inverse pass)
+  double thr;      // tol^2 ||b||^2
   double bnorm2;
   double rr_final;
   int maxit;
-  int iter;
-  int done;  // 0 running, 1 converged, 2 iteration limit, 3 breakdown
+  int k;           // iteration counter, advanced by the inverse pass
+  int iter;        // iterations taken when the solve ended
+  int done;        // 0 running, 1 converged, 2 iteration limit, 3 breakdown, 4 non-finite rhs
   int zero_rhs;
+  int pad;
 };
 
+// The iteration number lives in device memory so that a chunk of iterations
+// can be captured once in a graph and replayed.  Within one launch only the
+// lead thread of block 0 writes the state, and it writes fields that no other
+// block of that launch reads.
 struct CgCtl {
   CgState* st;
   double* part_a;   // p.Ap partial sums
   double* part_rr;  // r.r partial sums
   int np_a, np_rr;
   int pa_stride, prr_stride;
-  int k;
 };
 
 __device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
@@ -56,41 +62,50 @@ __device__ __forceinline__ bool cg_running(const CgState* st, int s) {
   return !__syncthreads_or(st[s].done != 0);
 }
 
+// Forward pass of an iteration: beta (0 on the first iteration, which the
+// prologues use to take p = r), convergence and iteration-limit tests.
 __device__ __forceinline__ bool cg_begin_dir(const CgCtl& c, int s, double* red, double& beta) {
   CgState* st = c.st + s;
   if (!cg_running(c.st, s)) return false;
+  const int k = st->k;
   const double rr = block_sum_array(c.part_rr + (long long)s * c.prr_stride, c.np_rr, red);
   int code = 0;
   if (!isfinite(rr)) code = 3;
   else if (rr <= st->thr) code = 1;
-  else if (c.k >= st->maxit) code = 2;
+  else if (k >= st->maxit) code = 2;
   if (code) {
     if (lead()) {
       st->done = code;
-      st->iter = c.k;
+      st->iter = k;
       st->rr_final = rr;
     }
     return false;
   }
-  beta = c.k == 0 ? 0.0 : rr / st->rr[(c.k - 1) & 1];
-  if (lead()) st->rr[c.k & 1] = rr;
+  beta = k == 0 ? 0.0 : rr / st->rr_prev;
+  if (lead()) st->rr_cur = rr;
   return true;
 }
 
+// Inverse pass of an iteration: alpha = r.r / p.Ap, breakdown test, and the
+// lead thread advances the iteration counter.
 __device__ __forceinline__ bool cg_begin_step(const CgCtl& c, int s, double* red, double& alpha) {
   CgState* st = c.st + s;
   if (!cg_running(c.st, s)) return false;
   const double pap = block_sum_array(c.part_a + (long long)s * c.pa_stride, c.np_a, red);
-  const double rr = st->rr[c.k & 1];
+  const double rr = st->rr_cur;
   if (!(pap > 0.0) || !isfinite(pap)) {
     if (lead()) {
       st->done = 3;
-      st->iter = c.k;
+      st->iter = st->k;
       st->rr_final = rr;
     }
     return false;
   }
   alpha = rr / pap;
+  if (lead()) {
+    st->rr_prev = rr;
+    st->k = st->k + 1;
+  }
   return true;
 }
 
@@ -173,7 +188,7 @@ template <typename T> struct MechCgPro {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const T rv = r.at(s, q, i);
-      const T pp = c.k == 0 ? rv : rv + (T)sc * p.at(s, q, i);
+      const T pp = sc == 0.0 ? rv : rv + (T)sc * p.at(s, q, i);
       p.at(s, q, i) = pp;
       pv[q] = pp;
     }
@@ -294,7 +309,7 @@ template <typename T> struct PfCgPro {
   __device__ void point(int s, int y, int x, T* out, double& acc, double sc) const {
     const long long i = (long long)y * nx + x;
     const T rv = r.at(s, 0, i);
-    const T pp = c.k == 0 ? rv : rv + (T)sc * p.at(s, 0, i);
+    const T pp = sc == 0.0 ? rv : rv + (T)sc * p.at(s, 0, i);
     p.at(s, 0, i) = pp;
     out[0] = pp;
     acc += (a + H[s * ss + i]) * (double)pp * (double)pp;
@@ -392,7 +407,7 @@ template <typename T> struct DiffCgPro {
   __device__ void point(int s, int y, int x, T* out, double& acc, double sc) const {
     const long long i = (long long)y * nx + x;
     const T rv = r.at(s, 0, i);
-    const T pp = c.k == 0 ? rv : rv + (T)sc * p.at(s, 0, i);
+    const T pp = sc == 0.0 ? rv : rv + (T)sc * p.at(s, 0, i);
     p.at(s, 0, i) = pp;
     out[0] = pp;
     double D, kr;

@@ -56,8 +56,20 @@ __device__ __forceinline__ double block_sum_array(const double* a, int n, double
   return block_sum(t, red);
 }
 
+// Rows per block of the row passes: about 2048 voxels per block, so a 1024^2
+// grid gives 512 blocks (two per CU) instead of one block per CU.
 constexpr int rows_for(int nx) {
-  return nx >= 2048 ? 2 : nx >= 1024 ? 4 : nx >= 384 ? 8 : 16;
+  return nx >= 768 ? 2 : nx >= 384 ? 4 : nx >= 256 ? 8 : 16;
+}
+
+// The hardware hands block b to XCD b % 8.  Give every XCD a contiguous
+// range of logical row blocks, so the blocks that share the 128-byte lines of
+// a transposed spectrum column (ROWS * 16 bytes each) meet in the same L2.
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int x = b & 7, q = b >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  return x * per + (x < rem ? x : rem) + q;
 }
 
 template <typename T>
@@ -74,13 +86,13 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type*
   constexpr int NXH = NX / 2 + 1;
   constexpr int VOX = ROWS * NX;
   constexpr int VPT = (VOX + NT - 1) / NT;
-  __shared__ C buf[NP * NX];
+  __shared__ C buf[lds_size(NP * NX)];
   __shared__ double red[NT / 64];
   const int s = blockIdx.y;
   const int tid = threadIdx.x;
   double sc = 0.0;
   if (!pro.begin(s, red, sc)) return;
-  const int y0 = blockIdx.x * ROWS;
+  const int y0 = xcd_block() * ROWS;
   T vals[VPT][NOUT];
   double acc = 0.0;
 #pragma unroll
@@ -104,15 +116,15 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type*
       const int v = tid + i * NT;
       if (VOX % NT == 0 || v < VOX) {
         const int row = v / NX, x = v - (v / NX) * NX;
-        rb[2 * ((row >> 1) * NX + x) + (row & 1)] = vals[i][c];
+        rb[2 * lds((row >> 1) * NX + x) + (row & 1)] = vals[i][c];
       }
     }
     __syncthreads();
     fft_lds<T, NX, NP, NT, false>(buf, tw);
     for (int idx = tid; idx < NXH * NP; idx += NT) {
       const int pair = idx % NP, kx = idx / NP;
-      const C z = buf[pair * NX + kx];
-      const C zm = buf[pair * NX + (NX - kx) % NX];
+      const C z = buf[lds(pair * NX + kx)];
+      const C zm = buf[lds(pair * NX + (NX - kx) % NX)];
       const C a = C{(T)0.5 * (z.x + zm.x), (T)0.5 * (z.y - zm.y)};
       const C b = C{(T)0.5 * (z.y + zm.y), (T)0.5 * (zm.x - z.x)};
       const int y = y0 + 2 * pair;
@@ -132,7 +144,7 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
                                             const typename cvec<T>::type* __restrict__ tw) {
   using C = typename cvec<T>::type;
   constexpr int NB = NIN > NOUT ? NIN : NOUT;
-  __shared__ C buf[NB * NY];
+  __shared__ C buf[lds_size(NB * NY)];
   __shared__ double red[NT / 64];
   const int s = blockIdx.y;
   const int kx = blockIdx.x;
@@ -142,7 +154,7 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
   const C* in = spec_in + s * ss_in;
   for (int idx = tid; idx < NIN * NY; idx += NT) {
     const int c = idx / NY, y = idx - (idx / NY) * NY;
-    buf[c * NY + y] = in[((long long)c * nxh + kx) * NY + y];
+    buf[lds(c * NY + y)] = in[((long long)c * nxh + kx) * NY + y];
   }
   __syncthreads();
   fft_lds<T, NY, NIN, NT, false>(buf, tw);
@@ -150,10 +162,10 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
   for (int ky = tid; ky < NY; ky += NT) {
     C a[NIN], b[NOUT];
 #pragma unroll
-    for (int c = 0; c < NIN; ++c) a[c] = buf[c * NY + ky];
+    for (int c = 0; c < NIN; ++c) a[c] = buf[lds(c * NY + ky)];
     sym.mode(s, kx, ky, a, b, acc, sc);
 #pragma unroll
-    for (int c = 0; c < NOUT; ++c) buf[c * NY + ky] = b[c];
+    for (int c = 0; c < NOUT; ++c) buf[lds(c * NY + ky)] = b[c];
   }
   __syncthreads();
   sym.partial(s, block_sum(acc, red));
@@ -161,7 +173,7 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
   C* out = spec_out + s * ss_out;
   for (int idx = tid; idx < NOUT * NY; idx += NT) {
     const int c = idx / NY, y = idx - (idx / NY) * NY;
-    out[((long long)c * nxh + kx) * NY + y] = buf[c * NY + y];
+    out[((long long)c * nxh + kx) * NY + y] = buf[lds(c * NY + y)];
   }
 }
 
@@ -190,8 +202,8 @@ __device__ __forceinline__ void rows_inverse(
         a.y = (T)0;
         b.y = (T)0;
       }
-      buf[pair * NX + kx] = C{a.x - b.y, a.y + b.x};
-      if (kx > 0 && 2 * kx < NX) buf[pair * NX + NX - kx] = C{a.x + b.y, b.x - a.y};
+      buf[lds(pair * NX + kx)] = C{a.x - b.y, a.y + b.x};
+      if (kx > 0 && 2 * kx < NX) buf[lds(pair * NX + NX - kx)] = C{a.x + b.y, b.x - a.y};
     }
     __syncthreads();
     fft_lds<T, NX, NP, NT, true>(buf, tw);
@@ -200,7 +212,7 @@ __device__ __forceinline__ void rows_inverse(
       const int v = tid + i * NT;
       if (VOX % NT == 0 || v < VOX) {
         const int row = v / NX, x = v - (v / NX) * NX;
-        vals[i][c] = rb[2 * ((row >> 1) * NX + x) + (row & 1)];
+        vals[i][c] = rb[2 * lds((row >> 1) * NX + x) + (row & 1)];
       }
     }
     __syncthreads();
@@ -217,13 +229,13 @@ __global__ void __launch_bounds__(NT) k_row_inv(Epi epi, const typename cvec<T>:
   constexpr int NP = ROWS / 2;
   constexpr int VOX = ROWS * NX;
   constexpr int VPT = (VOX + NT - 1) / NT;
-  __shared__ C buf[NP * NX];
+  __shared__ C buf[lds_size(NP * NX)];
   __shared__ double red[NT / 64];
   const int s = blockIdx.y;
   const int tid = threadIdx.x;
   double sc = 0.0;
   if (!epi.begin(s, red, sc)) return;
-  const int y0 = blockIdx.x * ROWS;
+  const int y0 = xcd_block() * ROWS;
   T vals[VPT][NIN];
   rows_inverse<T, NX, NIN>(spec + s * spec_ss, ny, y0, buf, vals, tw);
   double acc = 0.0;
@@ -247,13 +259,13 @@ __global__ void __launch_bounds__(NT) k_row_mid(Mid mid, typename cvec<T>::type*
   constexpr int NXH = NX / 2 + 1;
   constexpr int VOX = ROWS * NX;
   constexpr int VPT = (VOX + NT - 1) / NT;
-  __shared__ C buf[NP * NX];
+  __shared__ C buf[lds_size(NP * NX)];
   __shared__ double red[NT / 64];
   const int s = blockIdx.y;
   const int tid = threadIdx.x;
   double sc = 0.0;
   if (!mid.begin(s, red, sc)) return;
-  const int y0 = blockIdx.x * ROWS;
+  const int y0 = xcd_block() * ROWS;
   T vin[VPT][NIN];
   T vout[VPT][NOUT];
   C* sp = spec + s * spec_ss;
@@ -279,15 +291,15 @@ __global__ void __launch_bounds__(NT) k_row_mid(Mid mid, typename cvec<T>::type*
       const int v = tid + i * NT;
       if (VOX % NT == 0 || v < VOX) {
         const int row = v / NX, x = v - (v / NX) * NX;
-        rb[2 * ((row >> 1) * NX + x) + (row & 1)] = vout[i][c];
+        rb[2 * lds((row >> 1) * NX + x) + (row & 1)] = vout[i][c];
       }
     }
     __syncthreads();
     fft_lds<T, NX, NP, NT, false>(buf, tw);
     for (int idx = tid; idx < NXH * NP; idx += NT) {
       const int pair = idx % NP, kx = idx / NP;
-      const C z = buf[pair * NX + kx];
-      const C zm = buf[pair * NX + (NX - kx) % NX];
+      const C z = buf[lds(pair * NX + kx)];
+      const C zm = buf[lds(pair * NX + (NX - kx) % NX)];
       const C a = C{(T)0.5 * (z.x + zm.x), (T)0.5 * (z.y - zm.y)};
       const C b = C{(T)0.5 * (z.y + zm.y), (T)0.5 * (zm.x - z.x)};
       const int y = y0 + 2 * pair;

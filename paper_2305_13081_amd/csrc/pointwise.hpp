@@ -17,14 +17,16 @@ __global__ void __launch_bounds__(NT) k_cg_init(CgState* st, const double* part_
   const double b2 = block_sum_array(part_b + (long long)s * pstride, np, red);
   if (threadIdx.x == 0) {
     CgState t;
-    t.rr[0] = t.rr[1] = 0.0;
+    t.rr_cur = t.rr_prev = 0.0;
     t.bnorm2 = b2;
     t.thr = tol * tol * b2;
     t.rr_final = b2;
     t.maxit = maxit;
+    t.k = 0;
     t.iter = 0;
     t.zero_rhs = b2 == 0.0;
     t.done = !isfinite(b2) ? 4 : (b2 == 0.0 ? 1 : 0);
+    t.pad = 0;
     st[s] = t;
   }
 }
