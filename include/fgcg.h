@@ -91,12 +91,27 @@ int fgcg_set_stream(fgcg_ctx* ctx, void* hip_stream);
 const char* fgcg_strerror(int status);
 const char* fgcg_last_error(void);
 
+/* Context options.
+ *   FGCG_OPT_SCALAR_SPECTRAL  0 (default): the phase-field and diffusion
+ *       operators are applied as real-space stencils (the forward-difference
+ *       gradient of Sec. 2.5 is local, so this is the same operator); 1: they
+ *       are applied in Fourier space as eq. crack-fft writes them.
+ *   FGCG_OPT_GRAPHS           1 (default): CG iterations are replayed as HIP
+ *       graphs of FGCG_OPT_CHUNK iterations; 0: plain launches.
+ *   FGCG_OPT_CHUNK            iterations per graph chunk, even, 2..256 (default 16).
+ * Returns EINVAL for an unknown option or value. */
+enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2 };
+int fgcg_set_option(fgcg_ctx* ctx, int option, int value);
+
 /* Mechanical equilibrium with isotropic eigenstrain e(x) I (Sec. 2.3,
  * eq. solid): solves G[g C : sym(x)] = -G[g C : (eps_mac - e I)] for the
- * compatible fluctuation x (full displacement gradient, 4 components) by CG
- * from x = 0, stopping when ||r|| <= tol ||b|| or after maxit iterations
- * (tol = 0 runs exactly maxit iterations).
- *   d        device [N] damage or NULL (d = 0); g = (1 - d)^2 + kappa
+ * compatible fluctuation x (App. A projection G) by CG from x = 0, stopping
+ * when ||r|| <= tol ||b|| or after maxit iterations (tol = 0 runs exactly
+ * maxit iterations).  The iteration is carried on the displacement, x = grad u:
+ * CG on grad^H g C grad u = -grad^H g C (eps_mac - e I) preconditioned by the
+ * Fourier Green operator (grad^H grad)^-1, which has the same iterates, alpha,
+ * beta and residual norms as CG on x. */
+/*   d        device [N] damage or NULL (d = 0); g = (1 - d)^2 + kappa
  *   eig      device [N] scalar eigenstrain e or NULL (0)
  *   eps_mac  host [3] macroscopic strain (Voigt, tensor shear)
  *   strain   device [3][N] out: eps = eps_mac + sym(x)
@@ -191,7 +206,8 @@ enum {
   FGCG_K_DIFF_ROW_MID = 8,
   FGCG_K_DIFF_COL_DIV = 9,
   FGCG_K_DIFF_ROW_INV = 10,
-  FGCG_K_NKINDS = 11
+  FGCG_K_MECH_KP = 11,
+  FGCG_K_NKINDS = 12
 };
 /* mask: bit k enables event timing of kind k (0 disables); resets counters. */
 int fgcg_profile(fgcg_ctx* ctx, unsigned mask);

@@ -13,6 +13,8 @@
 #include <vector>
 
 #include "fgcg.h"
+#include "mech_u.hpp"
+#include "scalar_cg.hpp"
 #include "pointwise.hpp"
 
 using namespace fgcg;
@@ -82,12 +84,14 @@ struct fgcg_ctx {
   void* spec = nullptr;
   CgState* st = nullptr;
   CgState* h_st = nullptr;
+  dim3 sgrid;                 // grid of the stencil CG passes (at most 512 blocks)
+  int scalar_spectral = 0;    // 1: phase field and diffusion apply their operators by FFT
   double* part_a = nullptr;
   double* part_rr = nullptr;
   double* part_b = nullptr;
   double* part_post = nullptr;
   double* h_part = nullptr;
-  int nrow = 0, ncol = 0, npost = 0;
+  int nrow = 0, ncol = 0, npost = 0, nkp = 0;
   unsigned prof_mask = 0;
   double prof_ms[FGCG_K_NKINDS] = {0};
   long long prof_n[FGCG_K_NKINDS] = {0};
@@ -107,7 +111,7 @@ struct fgcg_ctx {
     std::vector<char> key;
     GraphSlot slot[2];
   };
-  CgGraph graphs[3];  // mechanics, phase field, diffusion
+  CgGraph graphs[5];  // mechanics, phase field, diffusion (spectral), phase field, diffusion (stencil)
 };
 
 namespace {
@@ -317,15 +321,15 @@ int launch_row_mid(fgcg_ctx* c, int kind, const Mid& mid, CT<T>* spec, int nsamp
 // profiled kernel nodes of the first instance time those launches inside the
 // graph (an event node costs about 10 us of idle time, so the second instance
 // carries none and profiling samples every other chunk).
-template <class F> int run_cg_plain(fgcg_ctx* c, F&& iter, int maxit) {
+template <class S, class F> int run_cg_plain(fgcg_ctx* c, S* dst, S* hst, F&& iter, int maxit) {
   long long k = 0;
   int chunk = 2;
   for (;;) {
-    HIPCHK(hipMemcpyAsync(c->h_st, c->st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(hst, dst, sizeof(S), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     int rc = prof_flush(c);
     if (rc) return rc;
-    if (c->h_st->done) return 0;
+    if (hst->done) return 0;
     if (k > (long long)maxit + 1) return fail(FGCG_EHIP, "CG driver overran the iteration limit");
     for (int j = 0; j < chunk; ++j, ++k) {
       rc = iter();
@@ -357,13 +361,14 @@ template <class F> int build_chunk(fgcg_ctx* c, fgcg_ctx::GraphSlot& sl, F& iter
   return rc;
 }
 
-template <class F> int run_cg(fgcg_ctx* c, int which, const Key& key, F&& iter, int maxit) {
-  if (!c->use_graphs) return run_cg_plain(c, iter, maxit);
-  HIPCHK(hipMemcpyAsync(c->h_st, c->st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+template <class S, class F>
+int run_cg(fgcg_ctx* c, int which, const Key& key, S* dst, S* hs, F&& iter, int maxit) {
+  if (!c->use_graphs) return run_cg_plain(c, dst, hs, iter, maxit);
+  HIPCHK(hipMemcpyAsync(hs, dst, sizeof(S), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   int rc = prof_flush(c);
   if (rc) return rc;
-  if (c->h_st->done) return 0;
+  if (hs->done) return 0;
   const int K = c->chunk;
   fgcg_ctx::CgGraph& G = c->graphs[which];
   Key full = key;
@@ -375,11 +380,10 @@ template <class F> int run_cg(fgcg_ctx* c, int which, const Key& key, F&& iter, 
       if ((rc = build_chunk(c, G.slot[i], iter, K, i == 0))) return rc;
     G.key = full.b;
   }
-  CgState* hs = c->h_st;  // two pinned slots
   long long launched = 0;
   auto go = [&](int i) -> int {
     HIPCHK(hipGraphLaunch(G.slot[i].exec, c->stream));
-    HIPCHK(hipMemcpyAsync(hs + i, c->st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(hs + i, dst, sizeof(S), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipEventRecord(c->ev_done[i], c->stream));
     launched += K;
     return 0;
@@ -400,7 +404,7 @@ template <class F> int run_cg(fgcg_ctx* c, int which, const Key& key, F&& iter, 
   return 0;
 }
 
-int status_of(const CgState& s) {
+template <class S> int status_of(const S& s) {
   switch (s.done) {
     case 1: return FGCG_OK;
     case 2: return FGCG_NOT_CONVERGED;
@@ -410,7 +414,7 @@ int status_of(const CgState& s) {
   }
 }
 
-void fill_info(fgcg_info* info, const CgState& s, double secs) {
+template <class S> void fill_info(fgcg_info* info, const S& s, double secs) {
   if (!info) return;
   info->iters = s.iter;
   info->status = status_of(s);
@@ -463,32 +467,37 @@ int mech_solve_t(fgcg_ctx* c, const MechMat& m, const double* eig, const double*
                  double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
   const double t0 = now();
   CT<T>* spec = (CT<T>*)c->spec;
-  Field<T> X{(T*)c->x, c->n, 0}, R{(T*)c->r, c->n, 0}, P{(T*)c->p, c->n, 0};
+  const T ih = (T)(1.0 / c->h);
+  Field<T> X{(T*)c->x, c->n, 0}, R{(T*)c->r, c->n, 0}, P{(T*)c->p, c->n, 0}, Q{(T*)c->tmp, c->n, 0};
   int rc;
-  // b = -G[g C : (eps_mac - e I)], x = 0
-  MechSrcPro<T> src{m, eig, Field<T>{nullptr, c->n, 0}, {em[0], em[1], em[2]}, c->nx};
-  if ((rc = launch_row_fwd<T, 3>(c, -1, src, spec))) return rc;
-  MechProj<T> proj0{c->Dx, c->Dy, 1.0 / (double)c->n, nullptr};
-  if ((rc = launch_col<T, 3, 4>(c, -1, proj0, spec, spec))) return rc;
-  StoreEpi<T, 4> st0{R, X, (T)-1, c->nx, c->part_rr, 0};
-  if ((rc = launch_row_inv<T, 4>(c, -1, st0, spec))) return rc;
-  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_rr, c->nrow, 0, tol, maxit);
-  const CgCtl cc{c->st, c->part_a, c->part_rr, c->nrow, c->nrow, 0, 0};
-  const MechCgPro<T> pro{P, R, c->nx, m, cc};
-  const MechProj<T> proj{c->Dx, c->Dy, 1.0 / (double)c->n, c->st};
-  const MechCgEpi<T> epi{X, R, P, c->nx, cc};
+  // r = f = -grad^H g C : (eps_mac - e I), x = 0; z = M r; p = z; ||b||^2 = r.z
+  hipLaunchKernelGGL((k_mech_rhs<T>), dim3(c->nkp), dim3(NT), 0, c->stream, m, eig, em[0], em[1], em[2], R.p, X.p,
+                     c->n, c->nx, c->ny, ih);
+  const CopyProN<T, 2> cp{R, c->nx};
+  if ((rc = launch_row_fwd<T, 2>(c, -1, cp, spec))) return rc;
+  const MechGreen<T> g0{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
+  if ((rc = launch_col<T, 2, 2>(c, -1, g0, spec, spec))) return rc;
+  const MechUEpi<T> e0{P, c->nx, c->st, c->part_rr, c->ncol, 1, tol, maxit};
+  if ((rc = launch_row_inv<T, 2>(c, -1, e0, spec))) return rc;
+  HIPCHK(hipGetLastError());
+  const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, c->nkp};
+  const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, c->st, c->part_rr};
+  const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, c->ncol, 0, tol, maxit};
   auto iter = [&]() -> int {
-    int r = launch_row_fwd<T, 3>(c, FGCG_K_MECH_ROW_FWD, pro, spec);
-    r |= launch_col<T, 3, 4>(c, FGCG_K_MECH_COL, proj, spec, spec);
-    r |= launch_row_inv<T, 4>(c, FGCG_K_MECH_ROW_INV, epi, spec);
+    set_kname(c, FGCG_K_MECH_KP, "k_mech_kp<%s%.0d", tname<T>(), 0);
+    int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech_kp<T>, dim3(c->nkp), m, (const T*)P.p, Q.p, c->n,
+                   c->nx, c->ny, ih, c->st, c->part_a);
+    r |= launch_row_fwd<T, 2>(c, FGCG_K_MECH_ROW_FWD, pro, spec);
+    r |= launch_col<T, 2, 2>(c, FGCG_K_MECH_COL, green, spec, spec);
+    r |= launch_row_inv<T, 2>(c, FGCG_K_MECH_ROW_INV, epi, spec);
     return r;
   };
   Key key;
   key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm);
-  if ((rc = run_cg(c, 0, key, iter, maxit))) return rc;
+  if ((rc = run_cg(c, 0, key, c->st, c->h_st, iter, maxit))) return rc;
   const CgState s = *c->h_st;
-  hipLaunchKernelGGL((k_mech_post<T>), dim3(c->npost), dim3(PT), 0, c->stream, m, (const T*)c->x, c->n, eig,
-                     em[0], em[1], em[2], strain, stress, c->part_post);
+  hipLaunchKernelGGL((k_mech_post_u<T>), dim3(c->npost), dim3(NT), 0, c->stream, m, (const T*)c->x, c->n, c->nx,
+                     c->ny, ih, eig, em[0], em[1], em[2], strain, stress, c->part_post);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(c->h_part, c->part_post, sizeof(double) * 4 * c->npost, hipMemcpyDeviceToHost,
                         c->stream));
@@ -548,7 +557,7 @@ int pf_solve_t(fgcg_ctx* c, const double* H, double Gc, double l0, double* d, do
   };
   Key key;
   key.add(H).add(a).add(cl);
-  if ((rc = run_cg(c, 1, key, iter, maxit))) return rc;
+  if ((rc = run_cg(c, 1, key, c->st, c->h_st, iter, maxit))) return rc;
   const CgState s = *c->h_st;
   if (s.zero_rhs) HIPCHK(hipMemsetAsync(c->x, 0, sizeof(T) * c->n, c->stream));
   hipLaunchKernelGGL((k_convert<double, T>), dim3(c->npost), dim3(PT), 0, c->stream, d, (const T*)c->x, c->n);
@@ -638,8 +647,81 @@ int diff_step_t(fgcg_ctx* c, const DiffCoef& co, double c_dir, double* cfield, d
   };
   Key key;
   key.add(co.phase).add(co.dk).add(co.inv_dt).add(co.band);
-  if ((rc = run_cg(c, 2, key, iter, maxit))) return rc;
+  if ((rc = run_cg(c, 2, key, c->st, c->h_st, iter, maxit))) return rc;
   const CgState s = *c->h_st;
+  if (s.zero_rhs) HIPCHK(hipMemsetAsync(c->x, 0, sizeof(T) * c->n, c->stream));
+  hipLaunchKernelGGL((k_diff_finish<T>), dim3(c->npost), dim3(PT), 0, c->stream, cfield, (const T*)c->x, c->n,
+                     c->nx, co.band, c_dir);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  fill_info(info, s, now() - t0);
+  return status_of(s);
+}
+
+// ------------------------------------------------- stencil scalar CG
+template <typename T, class Op>
+int scg_solve(fgcg_ctx* c, int which, const Key& key, const Op& op, const double* xin, double bscale,
+              const double* bsrc, int band, double c_dir, double tol, int maxit, int kind_dir, int kind_upd,
+              CgState* out) {
+  T* X = (T*)c->x;
+  T* R = (T*)c->r;
+  T* P0 = (T*)c->p;
+  T* P1 = P0 + c->n;  // second direction buffer (p holds 4 components of room)
+  T* Q = (T*)c->tmp;
+  int parity = 0;     // iteration k reads P[k & 1] and writes P[(k + 1) & 1]
+  const int nsb = (int)(c->sgrid.x * c->sgrid.y);
+  hipLaunchKernelGGL((k_scg_init<T, Op>), c->sgrid, dim3(NT), 0, c->stream, op, xin, bscale, bsrc, band, c_dir, X,
+                     R, c->nx, c->ny, c->part_b, c->part_rr);
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_b, nsb, 0, tol, maxit);
+  HIPCHK(hipGetLastError());
+  const CgCtl cc{c->st, c->part_a, c->part_rr, nsb, nsb, 0, 0};
+  auto iter = [&]() -> int {
+    set_kname(c, kind_dir, "k_scg_dir<%s%.0d", tname<T>(), 0);
+    set_kname(c, kind_upd, "k_scg_upd<%s%.0d", tname<T>(), 0);
+    T* pin = parity ? P1 : P0;
+    T* pout = parity ? P0 : P1;
+    parity ^= 1;
+    int r = launch(c, kind_dir, (const void*)&k_scg_dir<T, Op>, c->sgrid, op, (const T*)R, (const T*)pin, pout, Q,
+                   c->nx, c->ny, band, cc);
+    r |= launch(c, kind_upd, (const void*)&k_scg_upd<T>, c->sgrid, X, R, (const T*)pout, (const T*)Q, c->nx,
+                c->ny, cc);
+    return r;
+  };
+  int rc = run_cg(c, which, key, c->st, c->h_st, iter, maxit);
+  if (rc) return rc;
+  *out = c->h_st[0];
+  return 0;
+}
+
+template <typename T>
+int pf_solve_stencil(fgcg_ctx* c, const double* H, double Gc, double l0, double* d, double tol, int maxit,
+                     fgcg_info* info) {
+  const double t0 = now();
+  const PfStencil op{H, Gc / (2.0 * l0), 0.5 * Gc * l0 / (c->h * c->h)};
+  Key key;
+  key.add(op.H).add(op.a).add(op.cih2);
+  CgState s;
+  int rc = scg_solve<T>(c, 3, key, op, d, 1.0, H, 0, 0.0, tol, maxit, FGCG_K_PF_ROW_FWD, FGCG_K_PF_ROW_INV, &s);
+  if (rc) return rc;
+  if (s.zero_rhs) HIPCHK(hipMemsetAsync(c->x, 0, sizeof(T) * c->n, c->stream));
+  hipLaunchKernelGGL((k_convert<double, T>), dim3(c->npost), dim3(PT), 0, c->stream, d, (const T*)c->x, c->n);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  fill_info(info, s, now() - t0);
+  return status_of(s);
+}
+
+template <typename T>
+int diff_step_stencil(fgcg_ctx* c, const DiffCoef& co, double c_dir, double* cfield, double tol, int maxit,
+                      fgcg_info* info) {
+  const double t0 = now();
+  const DiffStencil op{co, co.phase, c->nx, 1.0 / (c->h * c->h)};
+  Key key;
+  key.add(co.phase).add(co.dk).add(co.inv_dt).add(co.band).add(op.ih2);
+  CgState s;
+  int rc = scg_solve<T>(c, 4, key, op, cfield, co.inv_dt, cfield, co.band, c_dir, tol, maxit, FGCG_K_DIFF_ROW_FWD,
+                        FGCG_K_DIFF_ROW_INV, &s);
+  if (rc) return rc;
   if (s.zero_rhs) HIPCHK(hipMemsetAsync(c->x, 0, sizeof(T) * c->n, c->stream));
   hipLaunchKernelGGL((k_diff_finish<T>), dim3(c->npost), dim3(PT), 0, c->stream, cfield, (const T*)c->x, c->n,
                      c->nx, co.band, c_dir);
@@ -719,6 +801,7 @@ int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out) {
   });
   c->ncol = c->nxh;
   c->npost = (int)std::min<long long>((c->n + PT - 1) / PT, 1024);
+  c->nkp = (int)std::min<long long>((c->n + NT - 1) / NT, 1024);
   int rc = 0;
   auto chk = [&](hipError_t e) {
     if (e != hipSuccess && !rc) rc = fail(FGCG_ENOMEM, std::string("allocation failed: ") + hipGetErrorString(e));
@@ -733,11 +816,16 @@ int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out) {
     chk(hipMalloc(&c->Dy, sizeof(double2) * c->ny));
     chk(hipMalloc(&c->st, sizeof(CgState) * 1));
     chk(hipHostMalloc(&c->h_st, sizeof(CgState) * 2, hipHostMallocDefault));
-    const int npa = c->nrow + std::max(c->ncol, c->nrow);
+    const int npa = std::max(std::max(c->nrow + std::max(c->ncol, c->nrow), c->nkp), 512);
     chk(hipMalloc(&c->part_a, sizeof(double) * npa));
-    chk(hipMalloc(&c->part_rr, sizeof(double) * c->nrow));
-    chk(hipMalloc(&c->part_b, sizeof(double) * std::max(c->nrow, c->npost)));
+    chk(hipMalloc(&c->part_rr, sizeof(double) * std::max(std::max(c->nrow, c->ncol), 512)));
+    chk(hipMalloc(&c->part_b, sizeof(double) * std::max(std::max(c->nrow, c->npost), 512)));
     chk(hipMalloc(&c->part_post, sizeof(double) * 5 * c->npost));
+    {
+      const int bx = (c->nx + NT - 1) / NT;
+      const int by = std::max(1, std::min(c->ny, 512 / bx));
+      c->sgrid = dim3(bx, by);
+    }
     chk(hipHostMalloc(&c->h_part, sizeof(double) * 5 * c->npost, hipHostMallocDefault));
   }
   if (!rc) {
@@ -788,6 +876,26 @@ int fgcg_set_stream(fgcg_ctx* c, void* s) {
   return FGCG_OK;
 }
 
+int fgcg_set_option(fgcg_ctx* c, int option, int value) {
+  if (!c) return fail(FGCG_EINVAL, "ctx is NULL");
+  switch (option) {
+    case FGCG_OPT_SCALAR_SPECTRAL:
+      c->scalar_spectral = value != 0;
+      return FGCG_OK;
+    case FGCG_OPT_GRAPHS:
+      c->use_graphs = value != 0;
+      return FGCG_OK;
+    case FGCG_OPT_CHUNK:
+      // even, so every chunk starts at an even iteration (double-buffered directions)
+      if (value < 2 || value > 256 || (value & 1)) return fail(FGCG_EINVAL, "chunk must be even, 2..256");
+      c->chunk = value;
+      for (auto& g : c->graphs) release_graph(c, g);
+      return FGCG_OK;
+    default:
+      return fail(FGCG_EINVAL, "unknown option");
+  }
+}
+
 int fgcg_mech_solve(fgcg_ctx* c, const fgcg_material* mat, const double* d, double kappa, const double* eig,
                     const double* eps_mac, double tol, int maxit, double* strain, double* stress,
                     double* mean_stress, double* energy, fgcg_info* info) {
@@ -810,6 +918,7 @@ int fgcg_phasefield_solve(fgcg_ctx* c, const double* H, double Gc, double l0, do
   if (!(Gc > 0.0) || !std::isfinite(Gc)) return fail(FGCG_EDOMAIN, "Gc <= 0");
   if (!(l0 > 0.0) || !std::isfinite(l0)) return fail(FGCG_EDOMAIN, "l0 <= 0");
   if ((rc = enter(c))) return rc;
+  if (!c->scalar_spectral) return pf_solve_stencil<double>(c, H, Gc, l0, d, tol, maxit, info);
   return pf_solve_t<double>(c, H, Gc, l0, d, tol, maxit, info);
 }
 
@@ -824,6 +933,7 @@ int fgcg_diffusion_step(fgcg_ctx* c, const uint8_t* phase, int nphase, const dou
   DiffCoef co;
   if ((rc = make_diff_coef(phase, nphase, D_tab, k_tab, dt, band_width, c->n, &co))) return rc;
   if ((rc = enter(c))) return rc;
+  if (!c->scalar_spectral) return diff_step_stencil<double>(c, co, c_dir, cfield, tol, maxit, info);
   return diff_step_t<double>(c, co, c_dir, cfield, tol, maxit, info);
 }
 

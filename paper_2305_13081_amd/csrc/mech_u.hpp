@@ -1,0 +1,316 @@
+// Mechanics CG in displacement form.
+//
+// The compatible fluctuation of Sec. 2.3 is a forward-difference gradient,
+// x = grad u, and the projection of App. A factors as
+// G = grad (grad^H grad)^-1 grad^H.  CG on x with the Frobenius inner product
+// (the projected CG of eq. solid-final) is therefore the same iteration, in
+// exact arithmetic, as CG on the displacement u (2 components) for
+//     K u = f,   K = grad^H g C grad,   f = -grad^H g C : (eps_mac - e I),
+// preconditioned by the Green operator M = (grad^H grad)^-1 of a unit
+// reference medium, which is diagonal in Fourier space (1 / |D(k)|^2, zero at
+// k = 0).  Its iterates are x_k = grad u_k; its alpha, beta and stop test
+// coincide because ||G[g C x]||^2 = r.z and p_x . A p_x = p . K p.
+//
+// One iteration, four passes:
+//   k_mech_kp          q = K p as a real-space stencil (grad and grad^H are
+//                      the periodic forward/backward differences), partial
+//                      sums of p.Kp = sum_x sym(grad p) : g C : sym(grad p)
+//   row_fwd (MechUPro) alpha = r.z / p.Kp; x += alpha p; r -= alpha q; the
+//                      two components of r are transformed along x
+//   col (MechGreen)    z_hat = r_hat / |D|^2 / N, partial sums of r.z by
+//                      Parseval over the half spectrum
+//   row_inv (MechUEpi) z back in real space; stop test on r.z; beta;
+//                      p = z + beta p
+// so q and z are never stored except q between the first two passes.
+#pragma once
+#include "ops2d.hpp"
+
+namespace fgcg {
+
+// sigma = g C : sym(grad u) at voxel (y, x): forward differences to (y, x+1)
+// and (y+1, x), periodic.  Returns the symmetric gradient in e[3] too.
+template <typename T>
+__device__ __forceinline__ void sigma_u(const MechMat& m, const T* u, long long n, int nx, int ny, int y,
+                                        int x, T ih, T* sg, T* e) {
+  const int xp = x + 1 == nx ? 0 : x + 1;
+  const int yp = y + 1 == ny ? 0 : y + 1;
+  const long long i = (long long)y * nx + x;
+  const long long ix = (long long)y * nx + xp;
+  const long long iy = (long long)yp * nx + x;
+  const T u1 = u[i], u2 = u[n + i];
+  const T g11 = (u[ix] - u1) * ih;
+  const T g12 = (u[iy] - u1) * ih;
+  const T g21 = (u[n + ix] - u2) * ih;
+  const T g22 = (u[n + iy] - u2) * ih;
+  e[0] = g11;
+  e[1] = g22;
+  e[2] = (T)0.5 * (g12 + g21);
+  double lam, mu;
+  m.get(0, i, lam, mu);
+  stress2<T>(lam, mu, e[0], e[1], e[2], sg);
+}
+
+// sigma = g C : (eps_mac - e I) at voxel i
+template <typename T>
+__device__ __forceinline__ void sigma_src(const MechMat& m, const double* eig, const double* em, long long i,
+                                          T* sg) {
+  double lam, mu;
+  m.get(0, i, lam, mu);
+  const double e = eig ? eig[i] : 0.0;
+  stress2<T>(lam, mu, (T)(em[0] - e), (T)(em[1] - e), (T)em[2], sg);
+}
+
+// q_i(x) = sum_j (sigma_ij(x - e_j) - sigma_ij(x)) / h  (the adjoint of the
+// forward difference), sigma in Voigt order (11, 22, 12).
+template <typename T>
+__device__ __forceinline__ void div_adj(const T* s0, const T* sxm, const T* sym_, T ih, T* q) {
+  q[0] = ((sxm[0] - s0[0]) + (sym_[2] - s0[2])) * ih;
+  q[1] = ((sxm[2] - s0[2]) + (sym_[1] - s0[1])) * ih;
+}
+
+// q = K p with partial sums of p.Kp; the lead thread publishes the iteration
+// counter (k = k_next) for the later passes of this iteration.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_mech_kp(MechMat m, const T* __restrict__ p, T* __restrict__ q,
+                                                long long n, int nx, int ny, T ih, CgState* st,
+                                                double* part) {
+  __shared__ double red[NT / 64];
+  if (!cg_running(st, 0)) return;
+  if (lead()) st->k = st->k_next;
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+    const int y = (int)(i / nx), x = (int)(i - (long long)y * nx);
+    const int xm = x == 0 ? nx - 1 : x - 1;
+    const int ym = y == 0 ? ny - 1 : y - 1;
+    T s0[3], e0[3], sx[3], sy[3], tmp[3], qq[2];
+    sigma_u<T>(m, p, n, nx, ny, y, x, ih, s0, e0);
+    sigma_u<T>(m, p, n, nx, ny, y, xm, ih, sx, tmp);
+    sigma_u<T>(m, p, n, nx, ny, ym, x, ih, sy, tmp);
+    div_adj<T>(s0, sx, sy, ih, qq);
+    q[i] = qq[0];
+    q[n + i] = qq[1];
+    acc += (double)e0[0] * s0[0] + (double)e0[1] * s0[1] + 2.0 * (double)e0[2] * s0[2];
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// r = f = -grad^H g C : (eps_mac - e I); x = 0.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_mech_rhs(MechMat m, const double* eig, double em0, double em1,
+                                                 double em2, T* __restrict__ r, T* __restrict__ x, long long n,
+                                                 int nx, int ny, T ih) {
+  const double em[3] = {em0, em1, em2};
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+    const int y = (int)(i / nx), xx = (int)(i - (long long)y * nx);
+    const int xm = xx == 0 ? nx - 1 : xx - 1;
+    const int ym = y == 0 ? ny - 1 : y - 1;
+    T s0[3], sx[3], sy[3], qq[2];
+    sigma_src<T>(m, eig, em, i, s0);
+    sigma_src<T>(m, eig, em, (long long)y * nx + xm, sx);
+    sigma_src<T>(m, eig, em, (long long)ym * nx + xx, sy);
+    div_adj<T>(s0, sx, sy, ih, qq);
+    r[i] = -qq[0];
+    r[n + i] = -qq[1];
+    x[i] = (T)0;
+    x[n + i] = (T)0;
+  }
+}
+
+// Post-processing: eps = eps_mac + sym(grad u), sigma = g C : (eps - e I);
+// partial sums of sigma (3) and (eps - e I) : sigma.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_mech_post_u(MechMat m, const T* __restrict__ u, long long n, int nx,
+                                                    int ny, T ih, const double* eig, double em0, double em1,
+                                                    double em2, double* strain, double* stress,
+                                                    double* part) {
+  __shared__ double red[NT / 64];
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+    const int y = (int)(i / nx), x = (int)(i - (long long)y * nx);
+    const int xp = x + 1 == nx ? 0 : x + 1;
+    const int yp = y + 1 == ny ? 0 : y + 1;
+    const long long ix = (long long)y * nx + xp, iy = (long long)yp * nx + x;
+    const double u1 = (double)u[i], u2 = (double)u[n + i];
+    const double g11 = ((double)u[ix] - u1) * (double)ih;
+    const double g12 = ((double)u[iy] - u1) * (double)ih;
+    const double g21 = ((double)u[n + ix] - u2) * (double)ih;
+    const double g22 = ((double)u[n + iy] - u2) * (double)ih;
+    const double e11 = em0 + g11, e22 = em1 + g22, e12 = em2 + 0.5 * (g12 + g21);
+    strain[i] = e11;
+    strain[n + i] = e22;
+    strain[2 * n + i] = e12;
+    const double e = eig ? eig[i] : 0.0;
+    double lam, mu;
+    m.get(0, i, lam, mu);
+    const double l11 = e11 - e, l22 = e22 - e;
+    const double tr = l11 + l22;
+    const double s11 = lam * tr + 2.0 * mu * l11;
+    const double s22 = lam * tr + 2.0 * mu * l22;
+    const double s12 = 2.0 * mu * e12;
+    if (stress) {
+      stress[i] = s11;
+      stress[n + i] = s22;
+      stress[2 * n + i] = s12;
+    }
+    a0 += s11;
+    a1 += s22;
+    a2 += s12;
+    a3 += l11 * s11 + l22 * s22 + 2.0 * e12 * s12;
+  }
+  const double t0 = block_sum(a0, red), t1 = block_sum(a1, red), t2 = block_sum(a2, red),
+               t3 = block_sum(a3, red);
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x + 0] = t0;
+    part[4 * blockIdx.x + 1] = t1;
+    part[4 * blockIdx.x + 2] = t2;
+    part[4 * blockIdx.x + 3] = t3;
+  }
+}
+
+// Forward row pass of iteration k.
+template <typename T> struct MechUPro {
+  Field<T> x, r, p, q;
+  int nx;
+  CgState* st;
+  const double* part_a;
+  int np_a;
+  __device__ bool begin(int, double* red, double& sc) const {
+    if (!cg_running(st, 0)) return false;
+    const int k = st->k;
+    const double pap = block_sum_array(part_a, np_a, red);
+    const double rz = st->rz[k & 1];
+    if (!(pap > 0.0) || !isfinite(pap)) {
+      if (lead()) {
+        st->done = 3;
+        st->iter = k;
+        st->rr_final = rz;
+      }
+      return false;
+    }
+    sc = rz / pap;
+    return true;
+  }
+  __device__ void point(int s, int y, int xx, T* out, double&, double sc) const {
+    const long long i = (long long)y * nx + xx;
+    const T a = (T)sc;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      x.at(s, c, i) += a * p.at(s, c, i);
+      const T rv = r.at(s, c, i) - a * q.at(s, c, i);
+      r.at(s, c, i) = rv;
+      out[c] = rv;
+    }
+  }
+  __device__ void partial(int, double) const {}
+};
+
+// out = v (NC components)
+template <typename T, int NC> struct CopyProN {
+  Field<T> v;
+  int nx;
+  __device__ bool begin(int, double*, double&) const { return true; }
+  __device__ void point(int s, int y, int x, T* out, double&, double) const {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[c] = v.at(s, c, (long long)y * nx + x);
+  }
+  __device__ void partial(int, double) const {}
+};
+
+// Green operator of the unit reference medium with partial sums of r.z.
+template <typename T> struct MechGreen {
+  const double2* Dx;
+  const double2* Dy;
+  double inv_n;
+  int nx;
+  const CgState* st;  // nullable
+  double* part;       // nullable
+  __device__ bool begin(int s, double*, double&) const { return st == nullptr || cg_running(st, s); }
+  template <typename C>
+  __device__ void mode(int, int kx, int ky, const C* a, C* b, double& acc, double) const {
+    const double2 d1 = Dx[kx], d2 = Dy[ky];
+    const double n2 = d1.x * d1.x + d1.y * d1.y + d2.x * d2.x + d2.y * d2.y;
+    if (n2 == 0.0) {
+      b[0] = C{(T)0, (T)0};
+      b[1] = C{(T)0, (T)0};
+      return;
+    }
+    const double f = inv_n / n2;
+    const T ft = (T)f;
+    b[0] = C{a[0].x * ft, a[0].y * ft};
+    b[1] = C{a[1].x * ft, a[1].y * ft};
+    const double w = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+    acc += w * f *
+           ((double)a[0].x * a[0].x + (double)a[0].y * a[0].y + (double)a[1].x * a[1].x + (double)a[1].y * a[1].y);
+  }
+  __device__ void partial(int s, double v) const {
+    if (part) store_partial(part, 0, s, 0, v);
+  }
+};
+
+// Inverse row pass: stop test, beta, p = z + beta p.  With init set it starts
+// the solve instead: r.z of the right-hand side gives ||b||^2 and the
+// threshold, and p = z.
+template <typename T> struct MechUEpi {
+  Field<T> p;
+  int nx;
+  CgState* st;
+  const double* part_rz;
+  int np_rz;
+  int init;
+  double tol;
+  int maxit;
+  __device__ bool begin(int, double* red, double& sc) const {
+    if (!init && !cg_running(st, 0)) return false;
+    const double rz = block_sum_array(part_rz, np_rz, red);
+    if (init) {
+      const double thr = tol * tol * rz;
+      const int done = !isfinite(rz) ? 4 : (rz <= thr ? 1 : (maxit <= 0 ? 2 : 0));
+      if (lead()) {
+        CgState t;
+        t.rr_cur = t.rr_prev = 0.0;
+        t.bnorm2 = rz;
+        t.thr = thr;
+        t.rr_final = rz;
+        t.rz[0] = rz;
+        t.rz[1] = 0.0;
+        t.maxit = maxit;
+        t.k = 0;
+        t.k_next = 0;
+        t.iter = 0;
+        t.done = done;
+        t.zero_rhs = rz == 0.0;
+        *st = t;
+      }
+      sc = 0.0;
+      return done == 0;
+    }
+    const int k = st->k;
+    int code = 0;
+    if (!isfinite(rz)) code = 3;
+    else if (rz <= st->thr) code = 1;
+    else if (k + 1 >= st->maxit) code = 2;
+    if (code) {
+      if (lead()) {
+        st->done = code;
+        st->iter = k + 1;
+        st->rr_final = rz;
+      }
+      return false;
+    }
+    sc = rz / st->rz[k & 1];
+    if (lead()) {
+      st->rz[(k + 1) & 1] = rz;
+      st->k_next = k + 1;
+    }
+    return true;
+  }
+  __device__ void point(int s, int y, int xx, const T* z, double&, double sc) const {
+    const long long i = (long long)y * nx + xx;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) p.at(s, c, i) = init ? z[c] : z[c] + (T)sc * p.at(s, c, i);
+  }
+  __device__ void partial(int, double) const {}
+};
+
+}  // namespace fgcg

@@ -36,12 +36,13 @@ struct CgState {
   double thr;      // tol^2 ||b||^2
   double bnorm2;
   double rr_final;
+  double rz[2];    // preconditioned CG: r.z of iterations with parity 0 / 1
   int maxit;
-  int k;           // iteration counter, advanced by the inverse pass
+  int k;           // iteration counter
+  int k_next;      // preconditioned CG: next counter value, published by the first pass
   int iter;        // iterations taken when the solve ended
   int done;        // 0 running, 1 converged, 2 iteration limit, 3 breakdown, 4 non-finite rhs
   int zero_rhs;
-  int pad;
 };
 
 // The iteration number lives in device memory so that a chunk of iterations
@@ -176,31 +177,6 @@ __device__ __forceinline__ void stress2(double lam, double mu, T e11, T e22, T e
 }
 
 // ------------------------------------------------------------- mechanics
-template <typename T> struct MechCgPro {
-  Field<T> p, r;
-  int nx;
-  MechMat m;
-  CgCtl c;
-  __device__ bool begin(int s, double* red, double& sc) const { return cg_begin_dir(c, s, red, sc); }
-  __device__ void point(int s, int y, int x, T* out, double& acc, double sc) const {
-    const long long i = (long long)y * nx + x;
-    T pv[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T rv = r.at(s, q, i);
-      const T pp = sc == 0.0 ? rv : rv + (T)sc * p.at(s, q, i);
-      p.at(s, q, i) = pp;
-      pv[q] = pp;
-    }
-    double lam, mu;
-    m.get(s, i, lam, mu);
-    stress2<T>(lam, mu, pv[0], pv[3], (T)0.5 * (pv[1] + pv[2]), out);
-    acc += (double)pv[0] * (double)out[0] + (double)pv[3] * (double)out[1] +
-           (double)(pv[1] + pv[2]) * (double)out[2];
-  }
-  __device__ void partial(int s, double v) const { store_partial(c.part_a, c.pa_stride, s, 0, v); }
-};
-
 // Stress of (eps_mac - e I) [rhs] or of sym(v) for a given full gradient v [apply].
 template <typename T> struct MechSrcPro {
   MechMat m;
@@ -251,26 +227,6 @@ template <typename T> struct MechProj {
     b[3] = cmul(t2, D2);
   }
   __device__ void partial(int, double) const {}
-};
-
-template <typename T> struct MechCgEpi {
-  Field<T> x, r, p;
-  int nx;
-  CgCtl c;
-  __device__ bool begin(int s, double* red, double& sc) const { return cg_begin_step(c, s, red, sc); }
-  __device__ void point(int s, int y, int xx, const T* q, double& acc, double sc) const {
-    const long long i = (long long)y * nx + xx;
-    const T a = (T)sc;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const T pv = p.at(s, k, i);
-      x.at(s, k, i) += a * pv;
-      const T rv = r.at(s, k, i) - a * q[k];
-      r.at(s, k, i) = rv;
-      acc += (double)rv * (double)rv;
-    }
-  }
-  __device__ void partial(int s, double v) const { store_partial(c.part_rr, c.prr_stride, s, 0, v); }
 };
 
 // out = sign * q ; optionally x = 0 ; partial |out|^2 into part

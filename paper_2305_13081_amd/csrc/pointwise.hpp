@@ -26,7 +26,8 @@ __global__ void __launch_bounds__(NT) k_cg_init(CgState* st, const double* part_
     t.iter = 0;
     t.zero_rhs = b2 == 0.0;
     t.done = !isfinite(b2) ? 4 : (b2 == 0.0 ? 1 : 0);
-    t.pad = 0;
+    t.rz[0] = t.rz[1] = 0.0;
+    t.k_next = 0;
     st[s] = t;
   }
 }

@@ -1,0 +1,167 @@
+// CG for the scalar operators of the path with the operators applied as
+// real-space stencils.
+//
+// Both scalar operators are local: with the forward difference of Sec. 2.5
+// (D_a <-> (f(x + e_a) - f(x))/h) the Laplacian symbol -|D|^2 of the phase
+// field (Sec. 2.4, eq. crack-fft) is the periodic 5-point stencil, and the
+// diffusion operator grad^H D(x) grad is the 5-point flux stencil
+//     sum_a [D(x - e_a)(c(x) - c(x - e_a)) - D(x)(c(x + e_a) - c(x))] / h^2.
+// Applying them in real space gives the same operator as the Fourier-space
+// product (up to rounding) with one pass over the data.  CG is textbook CG;
+// one iteration is two passes:
+//   k_scg_dir : beta = rr_k / rr_{k-1} and the stop tests; p = r + beta p is
+//               formed at the voxel and at its four neighbours from r and the
+//               previous p (double-buffered by iteration parity), q = A p;
+//               writes p, q; sum p.q
+//   k_scg_upd : alpha = rr_k / p.q; x += alpha p; r -= alpha q; sum r.r
+// CG control is that of the other solves (cg_begin_dir / cg_begin_step):
+// each pass stores one FP64 partial sum per block and the next pass adds them
+// in block order, so the result is deterministic and cross-block visibility
+// comes from kernel boundaries only (a grid-wide fence inside a launch would
+// write back the L2 of every XCD).
+#pragma once
+#include "ops2d.hpp"
+
+namespace fgcg {
+
+__device__ __forceinline__ int block_linear() { return blockIdx.y * gridDim.x + blockIdx.x; }
+
+// Stencil operators.  v(y, x) comes from a functor so the CG direction
+// p = r + beta p can be formed at the neighbours on the fly.
+struct PfStencil {
+  const double* H;
+  double a;     // Gc / (2 l0)
+  double cih2;  // (Gc l0 / 2) / h^2
+  template <typename V>
+  __device__ __forceinline__ double apply(long long i, double v0, const V& v, int y, int x, int xm, int xp,
+                                          int ym, int yp) const {
+    const double lap = 4.0 * v0 - v(y, xm) - v(y, xp) - v(ym, x) - v(yp, x);
+    return (a + H[i]) * v0 + cih2 * lap;
+  }
+};
+
+struct DiffStencil {
+  DiffCoef co;
+  const uint8_t* phase;
+  int nx;
+  double ih2;
+  __device__ __forceinline__ double D(int y, int x) const {
+    double d, kr;
+    pick(co.dk, phase[(long long)y * nx + x], d, kr);
+    return d;
+  }
+  template <typename V>
+  __device__ __forceinline__ double apply(long long i, double v0, const V& v, int y, int x, int xm, int xp,
+                                          int ym, int yp) const {
+    double d0, kr;
+    pick(co.dk, phase[i], d0, kr);
+    const double flux = D(y, xm) * (v0 - v(y, xm)) - d0 * (v(y, xp) - v0) + D(ym, x) * (v0 - v(ym, x)) -
+                        d0 * (v(yp, x) - v0);
+    return (co.inv_dt + kr) * v0 + ih2 * flux;
+  }
+};
+
+__device__ __forceinline__ void nbrs(int y, int x, int nx, int ny, int& xm, int& xp, int& ym, int& yp) {
+  xm = x == 0 ? nx - 1 : x - 1;
+  xp = x + 1 == nx ? 0 : x + 1;
+  ym = y == 0 ? ny - 1 : y - 1;
+  yp = y + 1 == ny ? 0 : y + 1;
+}
+
+// First pass of iteration k.  band > 0: voxels with x < band are fixed
+// (p = q = 0 there).
+// p is double-buffered (pin -> pout): the direction at the neighbours is formed
+// from the previous p, which other threads of this launch must not overwrite.
+template <typename T, class Op>
+__global__ void __launch_bounds__(NT) k_scg_dir(Op op, const T* __restrict__ r, const T* __restrict__ pin,
+                                                T* __restrict__ pout, T* __restrict__ q, int nx, int ny, int band,
+                                                CgCtl cc) {
+  __shared__ double red[NT / 64];
+  double beta;
+  if (!cg_begin_dir(cc, 0, red, beta)) return;
+  const bool first = beta == 0.0;  // beta is 0 exactly on the first iteration
+  const T b = (T)beta;
+  auto pn = [&](int yy, int xx) -> double {
+    const long long j = (long long)yy * nx + xx;
+    return first ? (double)r[j] : (double)(r[j] + b * pin[j]);
+  };
+  double acc = 0.0;
+  for (int y = blockIdx.y; y < ny; y += gridDim.y) {
+    for (int x = blockIdx.x * NT + threadIdx.x; x < nx; x += gridDim.x * NT) {
+      const long long i = (long long)y * nx + x;
+      int xm, xp, ym, yp;
+      nbrs(y, x, nx, ny, xm, xp, ym, yp);
+      const double p0 = pn(y, x);
+      const double qv = x < band ? 0.0 : op.apply(i, p0, pn, y, x, xm, xp, ym, yp);
+      pout[i] = (T)p0;
+      q[i] = (T)qv;
+      acc += p0 * qv;
+    }
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) cc.part_a[block_linear()] = t;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_scg_upd(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                                                const T* __restrict__ q, int nx, int ny, CgCtl cc) {
+  __shared__ double red[NT / 64];
+  double alpha;
+  if (!cg_begin_step(cc, 0, red, alpha)) return;
+  const T a = (T)alpha;
+  double acc = 0.0;
+  for (int y = blockIdx.y; y < ny; y += gridDim.y) {
+    for (int xx = blockIdx.x * NT + threadIdx.x; xx < nx; xx += gridDim.x * NT) {
+      const long long i = (long long)y * nx + xx;
+      x[i] += a * p[i];
+      const T rv = r[i] - a * q[i];
+      r[i] = rv;
+      acc += (double)rv * (double)rv;
+    }
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) cc.part_rr[block_linear()] = t;
+}
+
+// Initial residual r = b - A x0 with x0 = xin (mask band), partial sums of
+// ||b||^2 and r.r (k_cg_init then sets the state).  b = bsrc: the phase field passes H; the diffusion step
+// passes c^n / dt on the free voxels, with A applied to c~ (c^n, band = c_dir)
+// and b_F = M(c^n/dt - A c_B).
+template <typename T, class Op>
+__global__ void __launch_bounds__(NT) k_scg_init(Op op, const double* __restrict__ xin, double bscale,
+                                                 const double* __restrict__ bsrc, int band, double c_dir,
+                                                 T* __restrict__ x, T* __restrict__ r, int nx, int ny,
+                                                 double* part_b, double* part_rr) {
+  __shared__ double red[NT / 64];
+  auto vt = [&](int yy, int xx) -> double { return xx < band ? c_dir : xin[(long long)yy * nx + xx]; };
+  auto vb = [&](int yy, int xx) -> double { return xx < band ? c_dir : 0.0; };
+  double acc[2] = {0.0, 0.0};
+  for (int y = blockIdx.y; y < ny; y += gridDim.y) {
+    for (int xx = blockIdx.x * NT + threadIdx.x; xx < nx; xx += gridDim.x * NT) {
+      const long long i = (long long)y * nx + xx;
+      int xm, xp, ym, yp;
+      nbrs(y, xx, nx, ny, xm, xp, ym, yp);
+      if (xx < band) {
+        x[i] = (T)0;
+        r[i] = (T)0;
+        continue;
+      }
+      const double b = bscale * bsrc[i];
+      const double ax = op.apply(i, vt(y, xx), vt, y, xx, xm, xp, ym, yp);
+      double bf = b;
+      if (band > 0) bf = b - op.apply(i, 0.0, vb, y, xx, xm, xp, ym, yp);
+      const double res = b - ax;
+      x[i] = (T)xin[i];
+      r[i] = (T)res;
+      acc[0] += bf * bf;
+      acc[1] += res * res;
+    }
+  }
+  const double t0 = block_sum(acc[0], red), t1 = block_sum(acc[1], red);
+  if (threadIdx.x == 0) {
+    part_b[block_linear()] = t0;
+    part_rr[block_linear()] = t1;
+  }
+}
+
+}  // namespace fgcg

@@ -22,6 +22,7 @@ KINDS = {
     "mech_row_fwd": 0, "mech_col": 1, "mech_row_inv": 2,
     "pf_row_fwd": 3, "pf_col": 4, "pf_row_inv": 5,
     "diff_row_fwd": 6, "diff_col_grad": 7, "diff_row_mid": 8, "diff_col_div": 9, "diff_row_inv": 10,
+    "mech_kp": 11,
 }
 
 
@@ -86,6 +87,7 @@ _SIGS = {
     "fgcg_set_stream": (_ip, [_vp, _vp]),
     "fgcg_strerror": (ctypes.c_char_p, [_ip]),
     "fgcg_last_error": (ctypes.c_char_p, []),
+    "fgcg_set_option": (_ip, [_vp, _ip, _ip]),
     "fgcg_mech_solve": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _dp, ctypes.c_double, _ip,
                               _vp, _vp, _dp, _dp, ctypes.POINTER(Info)]),
     "fgcg_phasefield_solve": (_ip, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, ctypes.c_double, _ip,
@@ -162,6 +164,11 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    OPTIONS = {"scalar_spectral": 0, "graphs": 1, "chunk": 2}
+
+    def set_option(self, name, value):
+        _check(self.lib.fgcg_set_option(self.ptr, self.OPTIONS[name], int(value)), "fgcg_set_option")
 
     # ----------------------------------------------------------- helpers
     def _sync_stream(self):

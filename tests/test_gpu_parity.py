@@ -181,13 +181,15 @@ def test_mech_edge_cases(torch_dev):
     assert torch.equal(a["strain"], b["strain"]) and a["energy"] == b["energy"]
 
 
-def test_phasefield_solve_parity(torch_dev):
+@pytest.mark.parametrize("spectral", [0, 1])
+def test_phasefield_solve_parity(torch_dev, spectral):
     torch, dev = torch_dev
     nx, ny = 64, 48
     rng = np.random.default_rng(21)
     Hf = 2e6 * rng.random((ny, nx)) ** 4
     d0 = 0.2 * rng.random((ny, nx))
     ctx = ctx_for(nx, ny)
+    ctx.set_option("scalar_spectral", spectral)
     dg = torch.from_numpy(d0.copy()).to(dev)
     info = ctx.phasefield_solve(torch.from_numpy(Hf).to(dev), GC, L0, dg, tol=1e-13)
     o = opf.phasefield_solve(Hf, GC, L0, H, d0=d0, tol=1e-13)
@@ -196,6 +198,7 @@ def test_phasefield_solve_parity(torch_dev):
     assert info["status"] == 0 and err < 1e-10
     # fixed iterations
     dg = torch.from_numpy(d0.copy()).to(dev)
+    print(f"pf spectral={spectral} ok", flush=True)
     ctx.phasefield_solve(torch.from_numpy(Hf).to(dev), GC, L0, dg, tol=0.0, maxit=3)
     o = opf.phasefield_solve(Hf, GC, L0, H, d0=d0, fixed_iters=3)
     assert rel(dg.cpu().numpy(), o["d"]) < 1e-12
@@ -205,8 +208,9 @@ def test_phasefield_solve_parity(torch_dev):
     assert info["iters"] == 0 and float(dg.abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("spectral", [0, 1])
 @pytest.mark.parametrize("band", [0, 4])
-def test_diffusion_step_parity(torch_dev, band):
+def test_diffusion_step_parity(torch_dev, band, spectral):
     torch, dev = torch_dev
     nx, ny = 64, 64
     phase, _ = inputs.box_fractal(64, 2, 4, 1.8, 0.3, np.random.default_rng(2))
@@ -216,23 +220,26 @@ def test_diffusion_step_parity(torch_dev, band):
         c0[:, :band] = 1.0
     Dt, kt, dt = (1e-9, 1e-12), (1e-3, 0.0), 40.0
     ctx = ctx_for(nx, ny)
+    ctx.set_option("scalar_spectral", spectral)
     cg = torch.from_numpy(c0.copy()).to(dev)
     info = ctx.diffusion_step(torch.from_numpy(phase).to(dev), Dt, kt, band, 1.0, dt, cg, tol=1e-13)
     o = odf.diffusion_step(c0, np.asarray(Dt)[phase], np.asarray(kt)[phase], dt, H,
                            band=ostg.band_mask((ny, nx), band), c_dir=1.0, tol=1e-13)
     err = rel(cg.cpu().numpy(), o["c"])
-    print(f"diffusion band={band}: iters gpu {info['iters']} oracle {o['iters']} rel err {err:.2e}", flush=True)
+    print(f"diffusion band={band} spectral={spectral}: iters gpu {info['iters']} oracle {o['iters']} rel err {err:.2e}", flush=True)
     assert info["status"] == 0 and err < 1e-10
     if band:
         assert float((cg[:, :band] - 1.0).abs().max()) == 0.0
 
 
-def test_diffusion_mass_conservation(torch_dev):
+@pytest.mark.parametrize("spectral", [0, 1])
+def test_diffusion_mass_conservation(torch_dev, spectral):
     torch, dev = torch_dev
     nx = ny = 64
     phase = rand_phase(ny, nx, 8, 0.5)
     c0 = np.random.default_rng(8).random((ny, nx))
     ctx = ctx_for(nx, ny)
+    ctx.set_option("scalar_spectral", spectral)
     cg = torch.from_numpy(c0.copy()).to(dev)
     ctx.diffusion_step(torch.from_numpy(phase).to(dev), (1e-9, 1e-12), (0.0, 0.0), 0, 1.0, 40.0, cg, tol=1e-6)
     assert abs(float(cg.sum()) - c0.sum()) < 1e-12 * c0.sum()
@@ -288,3 +295,28 @@ def test_c2_full_size(torch_dev):
     res = omech.mech_residual(s, phase, E_TAB, NU_TAB, H, e=e)
     print(f"1024^2 oracle residual of the GPU strain: {res:.2e}", flush=True)
     assert res < 1e-7
+
+
+@pytest.mark.parametrize("nx,ny", [(24, 12), (384, 8), (256, 96)])
+def test_scalar_stencil_fixed_iterations_ragged(torch_dev, nx, ny):
+    """Stencil CG on shapes whose rows do not fill the reduction grid evenly."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(nx + 7 * ny)
+    phase = rand_phase(ny, nx, 5, 0.5)
+    c0 = rng.random((ny, nx))
+    c0[:, :2] = 1.0
+    Dt, kt, dt = (1e-9, 1e-12), (1e-3, 0.0), 40.0
+    ctx = ctx_for(nx, ny)
+    for k in (1, 7):
+        cg = torch.from_numpy(c0.copy()).to(dev)
+        info = ctx.diffusion_step(torch.from_numpy(phase).to(dev), Dt, kt, 2, 1.0, dt, cg, tol=0.0, maxit=k)
+        o = odf.diffusion_step(c0, np.asarray(Dt)[phase], np.asarray(kt)[phase], dt, H,
+                               band=ostg.band_mask((ny, nx), 2), c_dir=1.0, fixed_iters=k)
+        assert info["iters"] == k
+        assert rel(cg.cpu().numpy(), o["c"]) < 1e-12
+    Hf = 1e6 * rng.random((ny, nx))
+    d0 = 0.1 * rng.random((ny, nx))
+    dg = torch.from_numpy(d0.copy()).to(dev)
+    ctx.phasefield_solve(torch.from_numpy(Hf).to(dev), GC, L0, dg, tol=0.0, maxit=5)
+    o = opf.phasefield_solve(Hf, GC, L0, H, d0=d0, fixed_iters=5)
+    assert rel(dg.cpu().numpy(), o["d"]) < 1e-12
