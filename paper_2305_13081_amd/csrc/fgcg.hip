@@ -73,8 +73,12 @@ struct fgcg_ctx {
   hipGraph_t graph = nullptr;
   hipGraphNode_t last = nullptr;
   int chunk = 16;  // CG iterations per captured graph
-  void* twx = nullptr;  // CT<T>[nx]
-  void* twy = nullptr;  // CT<T>[ny]
+  void* twx = nullptr;    // double2[nx] twiddles
+  void* twy = nullptr;    // double2[ny]
+  void* twx32 = nullptr;  // float2[nx] (FP32-mixed contexts)
+  void* twy32 = nullptr;  // float2[ny]
+  double* xh = nullptr;   // FP32-mixed: FP64 solution (2 components)
+  double* fh = nullptr;   // FP32-mixed: FP64 right-hand side (2 components)
   double2* Dx = nullptr;
   double2* Dy = nullptr;
   void* x = nullptr;
@@ -111,7 +115,8 @@ struct fgcg_ctx {
     std::vector<char> key;
     GraphSlot slot[2];
   };
-  CgGraph graphs[5];  // mechanics, phase field, diffusion (spectral), phase field, diffusion (stencil)
+  CgGraph graphs[6];  // mechanics, phase field, diffusion (spectral), phase field, diffusion (stencil),
+                      // mechanics FP32-mixed
 };
 
 namespace {
@@ -202,6 +207,13 @@ struct Key {
   }
 };
 
+template <typename T> const CT<T>* tw_x(const fgcg_ctx* c) {
+  return (const CT<T>*)(std::is_same<T, double>::value ? c->twx : c->twx32);
+}
+template <typename T> const CT<T>* tw_y(const fgcg_ctx* c) {
+  return (const CT<T>*)(std::is_same<T, double>::value ? c->twy : c->twy32);
+}
+
 template <typename T> const char* tname() { return std::is_same<T, double>::value ? "double" : "float"; }
 
 void set_kname(fgcg_ctx* c, int kind, const char* fmt, const char* t, int n) {
@@ -262,7 +274,7 @@ int launch_row_fwd(fgcg_ctx* c, int kind, const Pro& pro, CT<T>* spec, int nsamp
     dim3 g((c->ny + R - 1) / R, nsamp);
     if (kind >= 0) set_kname(c, kind, "k_row_fwd<%s, %d", tname<T>(), NX);
     rc = launch(c, kind, (const void*)&k_row_fwd<T, NX, NOUT, Pro>, g, pro, spec, c->ny, ss,
-                (const CT<T>*)c->twx);
+                tw_x<T>(c));
   });
   return rc;
 }
@@ -276,7 +288,7 @@ int launch_col(fgcg_ctx* c, int kind, const Sym& sym, const CT<T>* in, CT<T>* ou
     dim3 g(c->nxh, nsamp);
     if (kind >= 0) set_kname(c, kind, "k_col<%s, %d", tname<T>(), NY);
     rc = launch(c, kind, (const void*)&k_col<T, NY, NIN, NOUT, Sym>, g, sym, in, out, c->nxh, ss, ss,
-                (const CT<T>*)c->twy);
+                tw_y<T>(c));
   });
   return rc;
 }
@@ -291,7 +303,7 @@ int launch_row_inv(fgcg_ctx* c, int kind, const Epi& epi, const CT<T>* spec, int
     dim3 g((c->ny + R - 1) / R, nsamp);
     if (kind >= 0) set_kname(c, kind, "k_row_inv<%s, %d", tname<T>(), NX);
     rc = launch(c, kind, (const void*)&k_row_inv<T, NX, NIN, Epi>, g, epi, spec, c->ny, ss,
-                (const CT<T>*)c->twx);
+                tw_x<T>(c));
   });
   return rc;
 }
@@ -305,7 +317,7 @@ int launch_row_mid(fgcg_ctx* c, int kind, const Mid& mid, CT<T>* spec, int nsamp
     dim3 g((c->ny + R - 1) / R, nsamp);
     if (kind >= 0) set_kname(c, kind, "k_row_mid<%s, %d", tname<T>(), NX);
     rc = launch(c, kind, (const void*)&k_row_mid<T, NX, NIN, NOUT, Mid>, g, mid, spec, c->ny, ss,
-                (const CT<T>*)c->twx);
+                tw_x<T>(c));
   });
   return rc;
 }
@@ -362,17 +374,17 @@ template <class F> int build_chunk(fgcg_ctx* c, fgcg_ctx::GraphSlot& sl, F& iter
 }
 
 template <class S, class F>
-int run_cg(fgcg_ctx* c, int which, const Key& key, S* dst, S* hs, F&& iter, int maxit) {
+int run_cg(fgcg_ctx* c, int which, const Key& key, S* dst, S* hs, F&& iter, int maxit, int K = 0) {
   if (!c->use_graphs) return run_cg_plain(c, dst, hs, iter, maxit);
+  if (K <= 0) K = c->chunk;
   HIPCHK(hipMemcpyAsync(hs, dst, sizeof(S), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   int rc = prof_flush(c);
   if (rc) return rc;
   if (hs->done) return 0;
-  const int K = c->chunk;
   fgcg_ctx::CgGraph& G = c->graphs[which];
   Key full = key;
-  full.add(c->prof_mask);
+  full.add(c->prof_mask).add(K);
   if (G.key != full.b || !G.slot[0].exec || !G.slot[1].exec) {
     release_graph(c, G);
     if ((rc = prof_reserve(c, 4 * (size_t)K * FGCG_K_NKINDS))) return rc;
@@ -507,6 +519,76 @@ int mech_solve_t(fgcg_ctx* c, const MechMat& m, const double* eig, const double*
     for (int j = 0; j < 4; ++j) acc[j] += c->h_part[4 * b + j];
   if (mean_stress)
     for (int j = 0; j < 3; ++j) mean_stress[j] = acc[j] / (double)c->n;
+  if (energy) *energy = 0.5 * c->h * c->h * acc[3];
+  fill_info(info, s, now() - t0);
+  return status_of(s);
+}
+
+// FP32-mixed mechanics: FFT, Green-operator and constitutive passes in FP32,
+// every reduction in FP64, and every tenth iteration a reliable update: the
+// FP32 increments are folded into the FP64 solution and the residual is
+// recomputed as r = f - K x with the FP64 operator (p is kept).
+constexpr int RELIABLE_EVERY = 10;
+
+int mech_solve_mixed(fgcg_ctx* c, const MechMat& m, const double* eig, const double* em, double tol, int maxit,
+                     double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
+  using T = float;
+  const double t0 = now();
+  CT<T>* spec = (CT<T>*)c->spec;
+  const T ih = (T)(1.0 / c->h);
+  Field<T> X{(T*)c->x, c->n, 0}, R{(T*)c->r, c->n, 0}, P{(T*)c->p, c->n, 0}, Q{(T*)c->tmp, c->n, 0};
+  int rc;
+  hipLaunchKernelGGL((k_mech_rhs<double>), dim3(c->nkp), dim3(NT), 0, c->stream, m, eig, em[0], em[1], em[2], c->fh,
+                     c->xh, c->n, c->nx, c->ny, 1.0 / c->h);
+  hipLaunchKernelGGL((k_convert<T, double>), dim3(c->npost), dim3(PT), 0, c->stream, R.p, (const double*)c->fh,
+                     2 * c->n);
+  HIPCHK(hipMemsetAsync(X.p, 0, sizeof(T) * 2 * c->n, c->stream));
+  const CopyProN<T, 2> cp{R, c->nx};
+  if ((rc = launch_row_fwd<T, 2>(c, -1, cp, spec))) return rc;
+  const MechGreen<T> g0{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
+  if ((rc = launch_col<T, 2, 2>(c, -1, g0, spec, spec))) return rc;
+  const MechUEpi<T> e0{P, c->nx, c->st, c->part_rr, c->ncol, 1, tol, maxit};
+  if ((rc = launch_row_inv<T, 2>(c, -1, e0, spec))) return rc;
+  HIPCHK(hipGetLastError());
+  const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, c->nkp};
+  const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, c->st, c->part_rr};
+  const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, c->ncol, 0, tol, maxit};
+  int j = 0;  // position inside the period of RELIABLE_EVERY iterations
+  auto iter = [&]() -> int {
+    set_kname(c, FGCG_K_MECH_KP, "k_mech_kp<%s%.0d", tname<T>(), 0);
+    const bool reliable = j == RELIABLE_EVERY - 1;
+    j = reliable ? 0 : j + 1;
+    int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech_kp<T>, dim3(c->nkp), m, (const T*)P.p, Q.p, c->n,
+                   c->nx, c->ny, ih, c->st, c->part_a);
+    if (!reliable) {
+      r |= launch_row_fwd<T, 2>(c, FGCG_K_MECH_ROW_FWD, pro, spec);
+    } else {
+      r |= launch(c, -1, (const void*)&k_mech_fold<T>, dim3(c->npost), X.p, c->xh, (const T*)P.p, 2 * c->n, c->st,
+                  (const double*)c->part_a, c->nkp);
+      r |= launch(c, -1, (const void*)&k_mech_true_res<T>, dim3(c->nkp), m, (const double*)c->xh,
+                  (const double*)c->fh, R.p, c->n, c->nx, c->ny, 1.0 / c->h, (const CgState*)c->st);
+      r |= launch_row_fwd<T, 2>(c, -1, cp, spec);
+    }
+    r |= launch_col<T, 2, 2>(c, FGCG_K_MECH_COL, green, spec, spec);
+    r |= launch_row_inv<T, 2>(c, FGCG_K_MECH_ROW_INV, epi, spec);
+    return r;
+  };
+  Key key;
+  key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm);
+  if ((rc = run_cg(c, 5, key, c->st, c->h_st, iter, maxit, 2 * RELIABLE_EVERY))) return rc;
+  const CgState s = *c->h_st;
+  hipLaunchKernelGGL((k_fold_final<T>), dim3(c->npost), dim3(PT), 0, c->stream, (const T*)X.p, c->xh, 2 * c->n);
+  hipLaunchKernelGGL((k_mech_post_u<double>), dim3(c->npost), dim3(NT), 0, c->stream, m, (const double*)c->xh, c->n,
+                     c->nx, c->ny, 1.0 / c->h, eig, em[0], em[1], em[2], strain, stress, c->part_post);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->h_part, c->part_post, sizeof(double) * 4 * c->npost, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double acc[4] = {0, 0, 0, 0};
+  for (int b = 0; b < c->npost; ++b)
+    for (int q = 0; q < 4; ++q) acc[q] += c->h_part[4 * b + q];
+  if (mean_stress)
+    for (int q = 0; q < 3; ++q) mean_stress[q] = acc[q] / (double)c->n;
   if (energy) *energy = 0.5 * c->h * c->h * acc[3];
   fill_info(info, s, now() - t0);
   return status_of(s);
@@ -731,6 +813,17 @@ int diff_step_stencil(fgcg_ctx* c, const DiffCoef& co, double c_dir, double* cfi
   return status_of(s);
 }
 
+template <typename T> int make_twiddles(int n, void** out) {
+  std::vector<CT<T>> t(n);
+  for (int k = 0; k < n; ++k) {
+    const double th = 2.0 * M_PI * (double)k / (double)n;
+    t[k] = CT<T>{(T)std::cos(th), (T)-std::sin(th)};
+  }
+  HIPCHK(hipMalloc(out, sizeof(CT<T>) * n));
+  HIPCHK(hipMemcpy(*out, t.data(), sizeof(CT<T>) * n, hipMemcpyHostToDevice));
+  return 0;
+}
+
 template <typename T> int alloc_workspace(fgcg_ctx* c) {
   const size_t nr = sizeof(T) * 4 * (size_t)c->n;
   HIPCHK(hipMalloc(&c->x, nr));
@@ -738,19 +831,13 @@ template <typename T> int alloc_workspace(fgcg_ctx* c) {
   HIPCHK(hipMalloc(&c->p, nr));
   HIPCHK(hipMalloc(&c->tmp, nr));
   HIPCHK(hipMalloc(&c->spec, sizeof(CT<T>) * 4 * (size_t)c->nxh * c->ny));
-  std::vector<CT<T>> tx(c->nx), ty(c->ny);
-  for (int t = 0; t < c->nx; ++t) {
-    const double th = 2.0 * M_PI * (double)t / (double)c->nx;
-    tx[t] = CT<T>{(T)std::cos(th), (T)-std::sin(th)};
+  int rc;
+  if ((rc = make_twiddles<double>(c->nx, &c->twx)) || (rc = make_twiddles<double>(c->ny, &c->twy))) return rc;
+  if (c->prec == FGCG_FP32_MIXED) {
+    if ((rc = make_twiddles<float>(c->nx, &c->twx32)) || (rc = make_twiddles<float>(c->ny, &c->twy32))) return rc;
+    HIPCHK(hipMalloc(&c->xh, sizeof(double) * 2 * (size_t)c->n));
+    HIPCHK(hipMalloc(&c->fh, sizeof(double) * 2 * (size_t)c->n));
   }
-  for (int t = 0; t < c->ny; ++t) {
-    const double th = 2.0 * M_PI * (double)t / (double)c->ny;
-    ty[t] = CT<T>{(T)std::cos(th), (T)-std::sin(th)};
-  }
-  HIPCHK(hipMalloc(&c->twx, sizeof(CT<T>) * c->nx));
-  HIPCHK(hipMalloc(&c->twy, sizeof(CT<T>) * c->ny));
-  HIPCHK(hipMemcpy(c->twx, tx.data(), sizeof(CT<T>) * c->nx, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->twy, ty.data(), sizeof(CT<T>) * c->ny, hipMemcpyHostToDevice));
   return 0;
 }
 
@@ -782,7 +869,8 @@ int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out) {
   if (!(grid->h > 0.0) || !std::isfinite(grid->h)) return fail(FGCG_EDOMAIN, "h <= 0");
   if (!size_supported(grid->n[0]) || !size_supported(grid->n[1]))
     return fail(FGCG_EINVAL, "axis length must be one of 8..2048 of the form 2^a 3^b");
-  if (grid->precision != FGCG_FP64) return fail(FGCG_EUNSUPPORTED, "precision not built");
+  if (grid->precision != FGCG_FP64 && grid->precision != FGCG_FP32_MIXED)
+    return fail(FGCG_EINVAL, "unknown precision");
   fgcg_ctx* c = new fgcg_ctx();
   c->nx = grid->n[0];
   c->ny = grid->n[1];
@@ -852,7 +940,7 @@ int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out) {
 
 void fgcg_destroy(fgcg_ctx* c) {
   if (!c) return;
-  void* dev[] = {c->twx, c->twy, c->Dx, c->Dy, c->x, c->r, c->p, c->tmp, c->spec, c->st,
+  void* dev[] = {c->twx, c->twy, c->twx32, c->twy32, c->xh, c->fh, c->Dx, c->Dy, c->x, c->r, c->p, c->tmp, c->spec, c->st,
                  c->part_a, c->part_rr, c->part_b, c->part_post};
   for (void* p : dev)
     if (p) (void)hipFree(p);
@@ -907,6 +995,8 @@ int fgcg_mech_solve(fgcg_ctx* c, const fgcg_material* mat, const double* d, doub
   MechMat m;
   if ((rc = make_mech_mat(c, mat, d, kappa, &m))) return rc;
   if ((rc = enter(c))) return rc;
+  if (c->prec == FGCG_FP32_MIXED)
+    return mech_solve_mixed(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
   return mech_solve_t<double>(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
 }
 

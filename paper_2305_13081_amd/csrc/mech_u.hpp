@@ -168,6 +168,67 @@ __global__ void __launch_bounds__(NT) k_mech_post_u(MechMat m, const T* __restri
   }
 }
 
+// alpha = r.z / p.Kp of iteration k with the breakdown test (uniform per block).
+__device__ __forceinline__ bool mech_alpha(CgState* st, const double* part_a, int np_a, double* red,
+                                           double& alpha) {
+  if (!cg_running(st, 0)) return false;
+  const int k = st->k;
+  const double pap = block_sum_array(part_a, np_a, red);
+  const double rz = st->rz[k & 1];
+  if (!(pap > 0.0) || !isfinite(pap)) {
+    if (lead()) {
+      st->done = 3;
+      st->iter = k;
+      st->rr_final = rz;
+    }
+    return false;
+  }
+  alpha = rz / pap;
+  return true;
+}
+
+// Mixed precision, reliable update (every tenth iteration): fold the FP32
+// increments into the FP64 solution, x_hi += x_lo + alpha p, x_lo = 0.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_mech_fold(T* __restrict__ xlo, double* __restrict__ xhi,
+                                                  const T* __restrict__ p, long long n2, CgState* st,
+                                                  const double* part_a, int np_a) {
+  __shared__ double red[NT / 64];
+  double alpha;
+  if (!mech_alpha(st, part_a, np_a, red, alpha)) return;
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n2; i += (long long)gridDim.x * NT) {
+    xhi[i] += (double)xlo[i] + alpha * (double)p[i];
+    xlo[i] = (T)0;
+  }
+}
+
+// Mixed precision: the true residual r = f - K x_hi with the FP64 operator.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_mech_true_res(MechMat m, const double* __restrict__ xhi,
+                                                      const double* __restrict__ f, T* __restrict__ r, long long n,
+                                                      int nx, int ny, double ih, const CgState* st) {
+  if (!cg_running(st, 0)) return;
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+    const int y = (int)(i / nx), x = (int)(i - (long long)y * nx);
+    const int xm = x == 0 ? nx - 1 : x - 1;
+    const int ym = y == 0 ? ny - 1 : y - 1;
+    double s0[3], sx[3], sy[3], e[3], qq[2];
+    sigma_u<double>(m, xhi, n, nx, ny, y, x, ih, s0, e);
+    sigma_u<double>(m, xhi, n, nx, ny, y, xm, ih, sx, e);
+    sigma_u<double>(m, xhi, n, nx, ny, ym, x, ih, sy, e);
+    div_adj<double>(s0, sx, sy, ih, qq);
+    r[i] = (T)(f[i] - qq[0]);
+    r[n + i] = (T)(f[n + i] - qq[1]);
+  }
+}
+
+// x_hi += x_lo (end of a mixed-precision solve)
+template <typename T>
+__global__ void __launch_bounds__(NT) k_fold_final(const T* __restrict__ xlo, double* __restrict__ xhi, long long n2) {
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n2; i += (long long)gridDim.x * NT)
+    xhi[i] += (double)xlo[i];
+}
+
 // Forward row pass of iteration k.
 template <typename T> struct MechUPro {
   Field<T> x, r, p, q;
@@ -175,22 +236,7 @@ template <typename T> struct MechUPro {
   CgState* st;
   const double* part_a;
   int np_a;
-  __device__ bool begin(int, double* red, double& sc) const {
-    if (!cg_running(st, 0)) return false;
-    const int k = st->k;
-    const double pap = block_sum_array(part_a, np_a, red);
-    const double rz = st->rz[k & 1];
-    if (!(pap > 0.0) || !isfinite(pap)) {
-      if (lead()) {
-        st->done = 3;
-        st->iter = k;
-        st->rr_final = rz;
-      }
-      return false;
-    }
-    sc = rz / pap;
-    return true;
-  }
+  __device__ bool begin(int, double* red, double& sc) const { return mech_alpha(st, part_a, np_a, red, sc); }
   __device__ void point(int s, int y, int xx, T* out, double&, double sc) const {
     const long long i = (long long)y * nx + xx;
     const T a = (T)sc;

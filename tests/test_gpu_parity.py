@@ -320,3 +320,65 @@ def test_scalar_stencil_fixed_iterations_ragged(torch_dev, nx, ny):
     ctx.phasefield_solve(torch.from_numpy(Hf).to(dev), GC, L0, dg, tol=0.0, maxit=5)
     o = opf.phasefield_solve(Hf, GC, L0, H, d0=d0, fixed_iters=5)
     assert rel(dg.cpu().numpy(), o["d"]) < 1e-12
+
+
+def _ctx_prec(nx, ny, prec):
+    from paper_2305_13081_amd import fgcg
+    return fgcg.Context(nx, ny, H, precision=prec)
+
+
+def test_fp32_mixed_c1_against_fp64_oracle(torch_dev):
+    """FP32 transforms and constitutive passes, FP64 reductions and true
+    residual every 10 iterations: converges to tol 1e-10 and stays within
+    1e-5 of the FP64 oracle."""
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    phase, e = _c1()
+    ctx = _ctx_prec(64, 64, fgcg.FP32_MIXED)
+    r = ctx.mech_solve(torch.from_numpy(phase).to(dev), E_TAB, NU_TAB, (0, 0, 0), eig=torch.from_numpy(e).to(dev),
+                       tol=1e-10, maxit=20000)
+    o = omech.mech_solve(phase, E_TAB, NU_TAB, (0, 0, 0), H, e=e, tol=1e-12, maxit=50000)
+    es = rel(r["strain"].cpu().numpy(), o["strain"])
+    ee = abs(r["energy"] - o["energy"]) / abs(o["energy"])
+    print(f"C1 FP32-mixed: iters {r['info']['iters']} (FP64 oracle {o['iters']}), strain rel err {es:.2e}, "
+          f"energy rel err {ee:.2e}", flush=True)
+    assert r["info"]["status"] == 0
+    assert es < 1e-5 and ee < 1e-5
+
+
+def test_fp32_mixed_fractal_macro_strain(torch_dev):
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    n = 128
+    phase, _ = inputs.box_fractal(n, 2, 5, 1.7, 0.25, np.random.default_rng(31))
+    em = (1e-3, 0.0, 0.0)
+    ctx = _ctx_prec(n, n, fgcg.FP32_MIXED)
+    r = ctx.mech_solve(torch.from_numpy(phase).to(dev), E_TAB, NU_TAB, em, tol=1e-8, maxit=50000)
+    o = omech.mech_solve(phase, E_TAB, NU_TAB, em, H, tol=1e-12, maxit=50000)
+    es = rel(r["strain"].cpu().numpy(), o["strain"])
+    ms = abs(r["mean_stress"][0] - o["mean_stress"][0]) / abs(o["mean_stress"][0])
+    print(f"128^2 fractal FP32-mixed: iters {r['info']['iters']} (oracle {o['iters']}), strain rel err {es:.2e}, "
+          f"C11 rel err {ms:.2e}", flush=True)
+    assert r["info"]["status"] == 0
+    assert es < 1e-5 and ms < 1e-5
+
+
+def test_fp32_mixed_full_size(torch_dev):
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    phase, _ = inputs.c2_microstructure(1024)
+    rng = np.random.default_rng(77)
+    e = np.where(phase == 0, 1e-3 * rng.random(phase.shape), 0.0)
+    ph = torch.from_numpy(phase).to(dev)
+    eg = torch.from_numpy(e).to(dev)
+    r32 = _ctx_prec(1024, 1024, fgcg.FP32_MIXED).mech_solve(ph, E_TAB, NU_TAB, (1e-4, 0, 0), eig=eg, tol=1e-8,
+                                                           maxit=100000)
+    r64 = _ctx_prec(1024, 1024, fgcg.FP64).mech_solve(ph, E_TAB, NU_TAB, (1e-4, 0, 0), eig=eg, tol=1e-8,
+                                                     maxit=100000)
+    s32 = r32["strain"].cpu().numpy()
+    d = rel(s32, r64["strain"].cpu().numpy())
+    res = omech.mech_residual(s32, phase, E_TAB, NU_TAB, H, e=e)
+    print(f"1024^2 FP32-mixed: iters {r32['info']['iters']} (FP64 {r64['info']['iters']}), vs FP64 GPU {d:.2e}, "
+          f"oracle residual {res:.2e}", flush=True)
+    assert r32["info"]["status"] == 0
+    assert d < 1e-5 and res < 1e-7
