@@ -124,6 +124,27 @@ int fgcg_mech_solve(fgcg_ctx* ctx, const fgcg_material* mat, const double* d, do
                     double* strain, double* stress, double* mean_stress, double* energy,
                     fgcg_info* info);
 
+/* Gradient of a mechanical objective J with respect to the per-voxel Young's
+ * modulus (FP64 contexts).  The forward solve of fgcg_mech_solve is recomputed
+ * (no CG history is stored); with G = dJ/deps the adjoint lam solves
+ * K lam = grad^H G on the same preconditioned CG engine (K symmetric), and
+ *     grad_E[x] = dJ/dE_x|_eps - sym(grad lam)_x : sigma_x / E_x
+ * (dC_x/dE_x = C_x / E_x; E_x is the undegraded modulus of voxel x).
+ *   objective  FGCG_J_USER: dJ_dstrain (device [3][N], tensor components
+ *              G11, G22, G12 with dJ = sum_x G11 de11 + G22 de22 + 2 G12 de12)
+ *              required, no explicit part, *J untouched;
+ *              FGCG_J_ENERGY: J = W (the energy of fgcg_mech_solve); lam = 0 by
+ *              the envelope theorem, so no second solve is run;
+ *              FGCG_J_C11: J = <sigma_11> / eps_mac[0] (eps_mac[0] != 0).
+ *   grad_E     device [N] out.   J  host out or NULL.
+ *   info_fwd / info_adj  the two solves (info_adj->iters = 0 for the energy).
+ * Returns EUNSUPPORTED in FP32-mixed contexts, EINVAL/EDOMAIN as mech_solve. */
+enum { FGCG_J_USER = 0, FGCG_J_ENERGY = 1, FGCG_J_C11 = 2 };
+int fgcg_mech_adjoint(fgcg_ctx* ctx, const fgcg_material* mat, const double* d, double kappa,
+                      const double* eig, const double* eps_mac, const double* dJ_dstrain, int objective,
+                      double tol, int maxit, double* grad_E, double* J, fgcg_info* info_fwd,
+                      fgcg_info* info_adj);
+
 /* AT2 phase field (Sec. 2.4, eq. crack-fft) with the Laplacian taken as
  * -D^H D: [(Gc/(2 l0) + H) + (Gc l0 / 2) F^-1 |D|^2 F] d = H, solved by CG
  * starting from the d passed in (in: d^n, out: d^{n+1}).  H device [N]. */

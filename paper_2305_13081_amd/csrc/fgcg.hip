@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "fgcg.h"
+#include "adjoint.hpp"
 #include "mech_u.hpp"
 #include "scalar_cg.hpp"
 #include "pointwise.hpp"
@@ -79,6 +80,7 @@ struct fgcg_ctx {
   void* twy32 = nullptr;  // float2[ny]
   double* xh = nullptr;   // FP32-mixed: FP64 solution (2 components)
   double* fh = nullptr;   // FP32-mixed: FP64 right-hand side (2 components)
+  double* aux = nullptr;  // adjoint: forward strain (3 components) and dJ/deps (3 components)
   double2* Dx = nullptr;
   double2* Dy = nullptr;
   void* x = nullptr;
@@ -474,17 +476,13 @@ int check_solver_args(double tol, int maxit) {
 }
 
 // ----------------------------------------------------------------- mech
-template <typename T>
-int mech_solve_t(fgcg_ctx* c, const MechMat& m, const double* eig, const double* em, double tol, int maxit,
-                 double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
-  const double t0 = now();
+// Preconditioned CG on K u = f for the displacement: R holds f, X holds 0.
+template <typename T> int mech_pcg(fgcg_ctx* c, const MechMat& m, double tol, int maxit, CgState* out) {
   CT<T>* spec = (CT<T>*)c->spec;
   const T ih = (T)(1.0 / c->h);
   Field<T> X{(T*)c->x, c->n, 0}, R{(T*)c->r, c->n, 0}, P{(T*)c->p, c->n, 0}, Q{(T*)c->tmp, c->n, 0};
   int rc;
-  // r = f = -grad^H g C : (eps_mac - e I), x = 0; z = M r; p = z; ||b||^2 = r.z
-  hipLaunchKernelGGL((k_mech_rhs<T>), dim3(c->nkp), dim3(NT), 0, c->stream, m, eig, em[0], em[1], em[2], R.p, X.p,
-                     c->n, c->nx, c->ny, ih);
+  // z = M r; p = z; ||b||^2 = r.z
   const CopyProN<T, 2> cp{R, c->nx};
   if ((rc = launch_row_fwd<T, 2>(c, -1, cp, spec))) return rc;
   const MechGreen<T> g0{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
@@ -507,9 +505,17 @@ int mech_solve_t(fgcg_ctx* c, const MechMat& m, const double* eig, const double*
   Key key;
   key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm);
   if ((rc = run_cg(c, 0, key, c->st, c->h_st, iter, maxit))) return rc;
-  const CgState s = *c->h_st;
-  hipLaunchKernelGGL((k_mech_post_u<T>), dim3(c->npost), dim3(NT), 0, c->stream, m, (const T*)c->x, c->n, c->nx,
-                     c->ny, ih, eig, em[0], em[1], em[2], strain, stress, c->part_post);
+  *out = *c->h_st;
+  return 0;
+}
+
+// eps = eps_mac + sym(grad u), sigma, mean stress and energy from the
+// displacement u (FP64 or FP32 storage).
+template <typename U>
+int mech_post(fgcg_ctx* c, const MechMat& m, const U* u, const double* eig, const double* em, double* strain,
+              double* stress, double* mean_stress, double* energy) {
+  hipLaunchKernelGGL((k_mech_post_u<U>), dim3(c->npost), dim3(NT), 0, c->stream, m, u, c->n, c->nx, c->ny,
+                     (U)(1.0 / c->h), eig, em[0], em[1], em[2], strain, stress, c->part_post);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(c->h_part, c->part_post, sizeof(double) * 4 * c->npost, hipMemcpyDeviceToHost,
                         c->stream));
@@ -520,8 +526,65 @@ int mech_solve_t(fgcg_ctx* c, const MechMat& m, const double* eig, const double*
   if (mean_stress)
     for (int j = 0; j < 3; ++j) mean_stress[j] = acc[j] / (double)c->n;
   if (energy) *energy = 0.5 * c->h * c->h * acc[3];
+  return 0;
+}
+
+template <typename T>
+int mech_solve_t(fgcg_ctx* c, const MechMat& m, const double* eig, const double* em, double tol, int maxit,
+                 double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
+  const double t0 = now();
+  const T ih = (T)(1.0 / c->h);
+  // r = f = -grad^H g C : (eps_mac - e I), x = 0
+  hipLaunchKernelGGL((k_mech_rhs<T>), dim3(c->nkp), dim3(NT), 0, c->stream, m, eig, em[0], em[1], em[2],
+                     (T*)c->r, (T*)c->x, c->n, c->nx, c->ny, ih);
+  CgState s;
+  int rc = mech_pcg<T>(c, m, tol, maxit, &s);
+  if (rc) return rc;
+  if ((rc = mech_post<T>(c, m, (const T*)c->x, eig, em, strain, stress, mean_stress, energy))) return rc;
   fill_info(info, s, now() - t0);
   return status_of(s);
+}
+
+// Adjoint gradient dJ/dE_x (FP64): forward solve (strain recomputed), the
+// objective's G = dJ/deps, a second PCG solve K lam = grad^H G (skipped for
+// the energy, where lam = 0), and the gradient assembly.
+int mech_adjoint_t(fgcg_ctx* c, const MechMat& m, const double* eig, const double* em, const double* dJ,
+                   int objective, double tol, int maxit, double* grad, double* J, fgcg_info* info_fwd,
+                   fgcg_info* info_adj) {
+  double* strain = c->aux;
+  double* G = c->aux + 3 * c->n;
+  double mean[3], energy;
+  int rc = mech_solve_t<double>(c, m, eig, em, tol, maxit, strain, nullptr, mean, &energy, info_fwd);
+  if (rc < 0) return rc;
+  const int fwd_status = rc;
+  const double N = (double)c->n;
+  double scale = 0.0;
+  if (objective == ADJ_ENERGY) scale = c->h * c->h;
+  if (objective == ADJ_C11) scale = 1.0 / (N * em[0]);
+  if (J) *J = objective == ADJ_ENERGY ? energy : (objective == ADJ_C11 ? mean[0] / em[0] : 0.0);
+  const double t0 = now();
+  CgState s{};
+  int have_lam = 0;
+  if (objective != ADJ_ENERGY) {
+    hipLaunchKernelGGL(k_adj_g, dim3(c->nkp), dim3(NT), 0, c->stream, m, (const double*)strain, eig, dJ, objective,
+                       scale, c->n, G);
+    hipLaunchKernelGGL(k_adj_rhs, dim3(c->nkp), dim3(NT), 0, c->stream, (const double*)G, (double*)c->r,
+                       (double*)c->x, c->n, c->nx, c->ny, 1.0 / c->h);
+    HIPCHK(hipGetLastError());
+    if ((rc = mech_pcg<double>(c, m, tol, maxit, &s))) return rc;
+    have_lam = 1;
+  } else {
+    s.done = 1;
+  }
+  hipLaunchKernelGGL(k_adj_grad, dim3(c->nkp), dim3(NT), 0, c->stream, m, (const double*)strain, eig,
+                     (const double*)c->x, objective, objective == ADJ_ENERGY ? c->h * c->h : scale, have_lam, c->n,
+                     c->nx, c->ny, 1.0 / c->h, grad);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  fill_info(info_adj, s, now() - t0);
+  const int adj_status = status_of(s);
+  if (adj_status < 0) return adj_status;
+  return (fwd_status == FGCG_NOT_CONVERGED || adj_status == FGCG_NOT_CONVERGED) ? FGCG_NOT_CONVERGED : FGCG_OK;
 }
 
 // FP32-mixed mechanics: FFT, Green-operator and constitutive passes in FP32,
@@ -578,18 +641,7 @@ int mech_solve_mixed(fgcg_ctx* c, const MechMat& m, const double* eig, const dou
   if ((rc = run_cg(c, 5, key, c->st, c->h_st, iter, maxit, 2 * RELIABLE_EVERY))) return rc;
   const CgState s = *c->h_st;
   hipLaunchKernelGGL((k_fold_final<T>), dim3(c->npost), dim3(PT), 0, c->stream, (const T*)X.p, c->xh, 2 * c->n);
-  hipLaunchKernelGGL((k_mech_post_u<double>), dim3(c->npost), dim3(NT), 0, c->stream, m, (const double*)c->xh, c->n,
-                     c->nx, c->ny, 1.0 / c->h, eig, em[0], em[1], em[2], strain, stress, c->part_post);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(c->h_part, c->part_post, sizeof(double) * 4 * c->npost, hipMemcpyDeviceToHost,
-                        c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  double acc[4] = {0, 0, 0, 0};
-  for (int b = 0; b < c->npost; ++b)
-    for (int q = 0; q < 4; ++q) acc[q] += c->h_part[4 * b + q];
-  if (mean_stress)
-    for (int q = 0; q < 3; ++q) mean_stress[q] = acc[q] / (double)c->n;
-  if (energy) *energy = 0.5 * c->h * c->h * acc[3];
+  if ((rc = mech_post<double>(c, m, (const double*)c->xh, eig, em, strain, stress, mean_stress, energy))) return rc;
   fill_info(info, s, now() - t0);
   return status_of(s);
 }
@@ -837,6 +889,8 @@ template <typename T> int alloc_workspace(fgcg_ctx* c) {
     if ((rc = make_twiddles<float>(c->nx, &c->twx32)) || (rc = make_twiddles<float>(c->ny, &c->twy32))) return rc;
     HIPCHK(hipMalloc(&c->xh, sizeof(double) * 2 * (size_t)c->n));
     HIPCHK(hipMalloc(&c->fh, sizeof(double) * 2 * (size_t)c->n));
+  } else {
+    HIPCHK(hipMalloc(&c->aux, sizeof(double) * 6 * (size_t)c->n));
   }
   return 0;
 }
@@ -940,7 +994,7 @@ int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out) {
 
 void fgcg_destroy(fgcg_ctx* c) {
   if (!c) return;
-  void* dev[] = {c->twx, c->twy, c->twx32, c->twy32, c->xh, c->fh, c->Dx, c->Dy, c->x, c->r, c->p, c->tmp, c->spec, c->st,
+  void* dev[] = {c->twx, c->twy, c->twx32, c->twy32, c->xh, c->fh, c->aux, c->Dx, c->Dy, c->x, c->r, c->p, c->tmp, c->spec, c->st,
                  c->part_a, c->part_rr, c->part_b, c->part_post};
   for (void* p : dev)
     if (p) (void)hipFree(p);
@@ -998,6 +1052,23 @@ int fgcg_mech_solve(fgcg_ctx* c, const fgcg_material* mat, const double* d, doub
   if (c->prec == FGCG_FP32_MIXED)
     return mech_solve_mixed(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
   return mech_solve_t<double>(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
+}
+
+int fgcg_mech_adjoint(fgcg_ctx* c, const fgcg_material* mat, const double* d, double kappa, const double* eig,
+                      const double* eps_mac, const double* dJ_dstrain, int objective, double tol, int maxit,
+                      double* grad_E, double* J, fgcg_info* info_fwd, fgcg_info* info_adj) {
+  if (!c || !eps_mac || !grad_E) return fail(FGCG_EINVAL, "ctx/eps_mac/grad_E is NULL");
+  if (c->prec != FGCG_FP64) return fail(FGCG_EUNSUPPORTED, "the adjoint runs in FP64 contexts");
+  if (objective != ADJ_USER && objective != ADJ_ENERGY && objective != ADJ_C11)
+    return fail(FGCG_EINVAL, "unknown objective");
+  if (objective == ADJ_USER && !dJ_dstrain) return fail(FGCG_EINVAL, "dJ_dstrain is NULL");
+  if (objective == ADJ_C11 && !(eps_mac[0] != 0.0)) return fail(FGCG_EDOMAIN, "C11 needs eps_mac[0] != 0");
+  int rc;
+  if ((rc = check_solver_args(tol, maxit))) return rc;
+  MechMat m;
+  if ((rc = make_mech_mat(c, mat, d, kappa, &m))) return rc;
+  if ((rc = enter(c))) return rc;
+  return mech_adjoint_t(c, m, eig, eps_mac, dJ_dstrain, objective, tol, maxit, grad_E, J, info_fwd, info_adj);
 }
 
 int fgcg_phasefield_solve(fgcg_ctx* c, const double* H, double Gc, double l0, double* d, double tol, int maxit,

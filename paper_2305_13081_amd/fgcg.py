@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfgcg.so")
 
 FGCG_OK, FGCG_NOT_CONVERGED = 0, 1
 FP64, FP32_MIXED = 0, 1
+J_USER, J_ENERGY, J_C11 = 0, 1, 2
 MAX_PHASES = 8
 KINDS = {
     "mech_row_fwd": 0, "mech_col": 1, "mech_row_inv": 2,
@@ -90,6 +91,8 @@ _SIGS = {
     "fgcg_set_option": (_ip, [_vp, _ip, _ip]),
     "fgcg_mech_solve": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _dp, ctypes.c_double, _ip,
                               _vp, _vp, _dp, _dp, ctypes.POINTER(Info)]),
+    "fgcg_mech_adjoint": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _dp, _vp, _ip,
+                                ctypes.c_double, _ip, _vp, _dp, ctypes.POINTER(Info), ctypes.POINTER(Info)]),
     "fgcg_phasefield_solve": (_ip, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, ctypes.c_double, _ip,
                                     ctypes.POINTER(Info)]),
     "fgcg_diffusion_step": (_ip, [_vp, _vp, _ip, _dp, _dp, _ip, ctypes.c_double, ctypes.c_double, _vp,
@@ -240,6 +243,27 @@ class Context:
         del keep
         return dict(strain=strain, stress=stress, mean_stress=np.array(list(mean)), energy=energy.value,
                     info=info.as_dict())
+
+    def mech_adjoint(self, E_field, nu, eps_mac, objective=J_ENERGY, dJ_dstrain=None, d=None, kappa=0.0,
+                     eig=None, tol=1e-12, maxit=50000, phase=None, E_tab=None, nu_tab=None):
+        """dJ/dE per voxel.  With E_field given the material is (E_field, nu);
+        otherwise (phase, E_tab, nu_tab).  Returns (grad_E, J, info_fwd, info_adj)."""
+        torch = _torch()
+        m, keep = self._material(phase, E_tab, nu_tab, E_field, nu)
+        self._t(d, "d", torch.float64, allow_none=True)
+        self._t(eig, "eig", torch.float64, allow_none=True)
+        self._t(dJ_dstrain, "dJ_dstrain", torch.float64, comps=3, allow_none=True)
+        grad = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        J = ctypes.c_double(0.0)
+        i1, i2 = Info(), Info()
+        self._sync_stream()
+        st = self.lib.fgcg_mech_adjoint(self.ptr, ctypes.byref(m), self._ptr(d), float(kappa), self._ptr(eig),
+                                        _dvec(eps_mac), self._ptr(dJ_dstrain), int(objective), float(tol),
+                                        int(maxit), self._ptr(grad), ctypes.byref(J), ctypes.byref(i1),
+                                        ctypes.byref(i2))
+        _check(st, "fgcg_mech_adjoint", allow_nc=True)
+        del keep
+        return grad, J.value, i1.as_dict(), i2.as_dict()
 
     def phasefield_solve(self, H, Gc, l0, d, tol=1e-10, maxit=20000):
         torch = _torch()
