@@ -145,6 +145,28 @@ int fgcg_mech_adjoint(fgcg_ctx* ctx, const fgcg_material* mat, const double* d, 
                       double tol, int maxit, double* grad_E, double* J, fgcg_info* info_fwd,
                       fgcg_info* info_adj);
 
+/* Batched mechanics: many microstructures of uneven sizes solved together.
+ * fgcg_batch_create groups the nb samples by grid size (nx[i], ny[i], each
+ * 2^a 3^b in 8..2048, voxel size h for all) and allocates their workspace.
+ * fgcg_mech_solve_batched solves, for every sample i, the problem of
+ * fgcg_mech_solve with phase field phases[i] (device [ny_i][nx_i]), the shared
+ * tables E_tab/nu_tab (host [nphase]), no damage or eigenstrain, and macro
+ * strain eps_mac[3 i .. 3 i + 2] (host).  All samples iterate in one graph
+ * launch per chunk (one chain of passes per size group, each pass covering
+ * every sample of its group); a converged sample's blocks exit at once, so
+ * samples stop independently, each on its own tolerance test.
+ *   strains      host array of nb device pointers ([3][N_i] out), entries may be NULL
+ *   mean_stress  host [nb][3] out or NULL;  energy host [nb] or NULL
+ *   infos        host [nb] or NULL
+ * Returns the worst status over the samples. */
+typedef struct fgcg_batch fgcg_batch;
+int fgcg_batch_create(int nb, const int* nx, const int* ny, double h, int precision, void* hip_stream,
+                      fgcg_batch** out);
+void fgcg_batch_destroy(fgcg_batch* batch);
+int fgcg_mech_solve_batched(fgcg_batch* batch, const uint8_t* const* phases, int nphase, const double* E_tab,
+                            const double* nu_tab, const double* eps_mac, double tol, int maxit,
+                            double* const* strains, double* mean_stress, double* energy, fgcg_info* infos);
+
 /* AT2 phase field (Sec. 2.4, eq. crack-fft) with the Laplacian taken as
  * -D^H D: [(Gc/(2 l0) + H) + (Gc l0 / 2) F^-1 |D|^2 F] d = H, solved by CG
  * starting from the d passed in (in: d^n, out: d^{n+1}).  H device [N]. */

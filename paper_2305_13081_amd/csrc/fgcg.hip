@@ -65,6 +65,7 @@ struct fgcg_ctx {
   double h = 0;
   int prec = FGCG_FP64;
   hipStream_t stream = nullptr;       // context-owned stream: every launch goes here
+  bool own_stream = true;             // false for the groups of a batch after the first
   hipStream_t user_stream = nullptr;  // caller's stream; work on it is waited for at entry
   hipEvent_t ev_in = nullptr;
   hipEvent_t ev_done[2] = {nullptr, nullptr};
@@ -98,6 +99,11 @@ struct fgcg_ctx {
   double* part_post = nullptr;
   double* h_part = nullptr;
   int nrow = 0, ncol = 0, npost = 0, nkp = 0;
+  int nsamp = 1;            // samples of this grid size (batches)
+  double* ems = nullptr;    // device [nsamp][3] macro strains
+  bool batch = false;            // member of a batch (owns the gather buffers below)
+  uint8_t* phase_buf = nullptr;  // batches: gathered phase fields [nsamp][N]
+  double* strain_buf = nullptr;  // batches: strains [nsamp][3][N]
   unsigned prof_mask = 0;
   double prof_ms[FGCG_K_NKINDS] = {0};
   long long prof_n[FGCG_K_NKINDS] = {0};
@@ -476,71 +482,160 @@ int check_solver_args(double tol, int maxit) {
 }
 
 // ----------------------------------------------------------------- mech
-// Preconditioned CG on K u = f for the displacement: R holds f, X holds 0.
-template <typename T> int mech_pcg(fgcg_ctx* c, const MechMat& m, double tol, int maxit, CgState* out) {
+// ---------------------------------------------------------- mechanics
+// Every context holds nsamp samples of one grid size (1 outside a batch);
+// sample s of a 2-component field starts at s * 2n, of a spectrum at
+// s * 2 nxh ny, and kernels take the sample from blockIdx.y.
+constexpr int RELIABLE_EVERY = 10;  // FP32-mixed: true residual every tenth iteration
+
+template <typename T> Field<T> fld(void* p, const fgcg_ctx* c) { return Field<T>{(T*)p, c->n, 2 * c->n}; }
+inline long long spec_ss(const fgcg_ctx* c) { return 2LL * c->nxh * c->ny; }
+
+// z = M r, p = z, r.z and the CG state of every sample (R holds f, X holds 0).
+template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
   CT<T>* spec = (CT<T>*)c->spec;
-  const T ih = (T)(1.0 / c->h);
-  Field<T> X{(T*)c->x, c->n, 0}, R{(T*)c->r, c->n, 0}, P{(T*)c->p, c->n, 0}, Q{(T*)c->tmp, c->n, 0};
+  const int ns = c->nsamp;
+  const long long ss = spec_ss(c);
   int rc;
-  // z = M r; p = z; ||b||^2 = r.z
-  const CopyProN<T, 2> cp{R, c->nx};
-  if ((rc = launch_row_fwd<T, 2>(c, -1, cp, spec))) return rc;
+  const CopyProN<T, 2> cp{fld<T>(c->r, c), c->nx};
+  if ((rc = launch_row_fwd<T, 2>(c, -1, cp, spec, ns, ss))) return rc;
   const MechGreen<T> g0{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
-  if ((rc = launch_col<T, 2, 2>(c, -1, g0, spec, spec))) return rc;
-  const MechUEpi<T> e0{P, c->nx, c->st, c->part_rr, c->ncol, 1, tol, maxit};
-  if ((rc = launch_row_inv<T, 2>(c, -1, e0, spec))) return rc;
+  if ((rc = launch_col<T, 2, 2>(c, -1, g0, spec, spec, ns, ss))) return rc;
+  const MechUEpi<T> e0{fld<T>(c->p, c), c->nx, c->st, c->part_rr, c->ncol, 1, tol, maxit};
+  if ((rc = launch_row_inv<T, 2>(c, -1, e0, spec, ns, ss))) return rc;
   HIPCHK(hipGetLastError());
-  const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, c->nkp};
-  const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, c->st, c->part_rr};
-  const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, c->ncol, 0, tol, maxit};
-  auto iter = [&]() -> int {
-    set_kname(c, FGCG_K_MECH_KP, "k_mech_kp<%s%.0d", tname<T>(), 0);
-    int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech_kp<T>, dim3(c->nkp), m, (const T*)P.p, Q.p, c->n,
-                   c->nx, c->ny, ih, c->st, c->part_a);
-    r |= launch_row_fwd<T, 2>(c, FGCG_K_MECH_ROW_FWD, pro, spec);
-    r |= launch_col<T, 2, 2>(c, FGCG_K_MECH_COL, green, spec, spec);
-    r |= launch_row_inv<T, 2>(c, FGCG_K_MECH_ROW_INV, epi, spec);
-    return r;
-  };
-  Key key;
-  key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm);
-  if ((rc = run_cg(c, 0, key, c->st, c->h_st, iter, maxit))) return rc;
-  *out = *c->h_st;
   return 0;
 }
 
-// eps = eps_mac + sym(grad u), sigma, mean stress and energy from the
-// displacement u (FP64 or FP32 storage).
-template <typename U>
-int mech_post(fgcg_ctx* c, const MechMat& m, const U* u, const double* eig, const double* em, double* strain,
-              double* stress, double* mean_stress, double* energy) {
-  hipLaunchKernelGGL((k_mech_post_u<U>), dim3(c->npost), dim3(NT), 0, c->stream, m, u, c->n, c->nx, c->ny,
-                     (U)(1.0 / c->h), eig, em[0], em[1], em[2], strain, stress, c->part_post);
+// The launches of one CG iteration (all samples).  reliable: FP32-mixed
+// reliable update (fold into the FP64 solution, FP64 true residual).
+template <typename T> int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, int maxit, bool reliable) {
+  CT<T>* spec = (CT<T>*)c->spec;
+  const int ns = c->nsamp;
+  const long long ss = spec_ss(c);
+  const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
+  set_kname(c, FGCG_K_MECH_KP, "k_mech_kp<%s%.0d", tname<T>(), 0);
+  int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech_kp<T>, dim3(c->nkp, ns), m, (const T*)P.p, Q.p, c->n,
+                 c->nx, c->ny, (T)(1.0 / c->h), c->st, c->part_a);
+  if (!reliable) {
+    const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, c->nkp};
+    r |= launch_row_fwd<T, 2>(c, FGCG_K_MECH_ROW_FWD, pro, spec, ns, ss);
+  } else {
+    r |= launch(c, -1, (const void*)&k_mech_fold<T>, dim3(c->npost, ns), X.p, c->xh, (const T*)P.p, 2 * c->n, c->st,
+                (const double*)c->part_a, c->nkp);
+    r |= launch(c, -1, (const void*)&k_mech_true_res<T>, dim3(c->nkp, ns), m, (const double*)c->xh,
+                (const double*)c->fh, R.p, c->n, c->nx, c->ny, 1.0 / c->h, (const CgState*)c->st);
+    const CopyProN<T, 2> cp{R, c->nx};
+    r |= launch_row_fwd<T, 2>(c, -1, cp, spec, ns, ss);
+  }
+  const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, c->st, c->part_rr};
+  r |= launch_col<T, 2, 2>(c, FGCG_K_MECH_COL, green, spec, spec, ns, ss);
+  const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, c->ncol, 0, tol, maxit};
+  r |= launch_row_inv<T, 2>(c, FGCG_K_MECH_ROW_INV, epi, spec, ns, ss);
+  return r;
+}
+
+// r = f = -grad^H g C : (eps_mac_s - e I), x = 0 for every sample (FP64
+// right-hand side and solution in FP32-mixed contexts, with r rounded to FP32).
+int mech_rhs(fgcg_ctx* c, const MechMat& m, const double* eig) {
+  const int ns = c->nsamp;
+  if (c->prec == FGCG_FP64) {
+    hipLaunchKernelGGL((k_mech_rhs<double>), dim3(c->nkp, ns), dim3(NT), 0, c->stream, m, eig, (const double*)c->ems,
+                       (double*)c->r, (double*)c->x, c->n, c->nx, c->ny, 1.0 / c->h);
+  } else {
+    hipLaunchKernelGGL((k_mech_rhs<double>), dim3(c->nkp, ns), dim3(NT), 0, c->stream, m, eig, (const double*)c->ems,
+                       c->fh, c->xh, c->n, c->nx, c->ny, 1.0 / c->h);
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(c->npost), dim3(PT), 0, c->stream, (float*)c->r,
+                       (const double*)c->fh, 2 * c->n * ns);
+    HIPCHK(hipMemsetAsync(c->x, 0, sizeof(float) * 2 * c->n * ns, c->stream));
+  }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(c->h_part, c->part_post, sizeof(double) * 4 * c->npost, hipMemcpyDeviceToHost,
+  return 0;
+}
+
+Key mech_key(const fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
+  Key key;
+  key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm).add(c->prec);
+  key.add(tol).add(maxit);
+  return key;
+}
+
+// Builds the iteration closure of a context (period RELIABLE_EVERY in FP32-mixed).
+struct MechIterFn {
+  fgcg_ctx* c;
+  MechMat m;
+  double tol;
+  int maxit;
+  int j = 0;
+  int operator()() {
+    if (c->prec == FGCG_FP64) return mech_iter<double>(c, m, tol, maxit, false);
+    const bool rel = j == RELIABLE_EVERY - 1;
+    j = rel ? 0 : j + 1;
+    return mech_iter<float>(c, m, tol, maxit, rel);
+  }
+};
+
+// Solve from the right-hand side in R (X = 0); the result stays in X (FP64)
+// or X + XH (FP32-mixed, folded into XH at the end).
+int mech_pcg(fgcg_ctx* c, const MechMat& m, double tol, int maxit, CgState* out) {
+  int rc = c->prec == FGCG_FP64 ? mech_init<double>(c, m, tol, maxit) : mech_init<float>(c, m, tol, maxit);
+  if (rc) return rc;
+  MechIterFn it{c, m, tol, maxit};
+  const int K = c->prec == FGCG_FP64 ? c->chunk : 2 * RELIABLE_EVERY;
+  if ((rc = run_cg(c, c->prec == FGCG_FP64 ? 0 : 5, mech_key(c, m, tol, maxit), c->st, c->h_st, it, maxit, K)))
+    return rc;
+  *out = *c->h_st;
+  if (c->prec != FGCG_FP64) {
+    hipLaunchKernelGGL((k_fold_final<float>), dim3(c->npost, c->nsamp), dim3(PT), 0, c->stream,
+                       (const float*)c->x, c->xh, 2 * c->n);
+    HIPCHK(hipGetLastError());
+  }
+  return 0;
+}
+
+// eps = eps_mac + sym(grad u), sigma, and per sample the mean stress and the
+// energy (host arrays [nsamp][3], [nsamp]) from the final displacement.
+int mech_post(fgcg_ctx* c, const MechMat& m, const double* eig, double* strain, double* stress,
+              double* mean_stress, double* energy) {
+  const int ns = c->nsamp;
+  if (c->prec == FGCG_FP64)
+    hipLaunchKernelGGL((k_mech_post_u<double>), dim3(c->npost, ns), dim3(NT), 0, c->stream, m,
+                       (const double*)c->x, c->n, c->nx, c->ny, 1.0 / c->h, eig, (const double*)c->ems, strain,
+                       stress, c->part_post);
+  else
+    hipLaunchKernelGGL((k_mech_post_u<double>), dim3(c->npost, ns), dim3(NT), 0, c->stream, m,
+                       (const double*)c->xh, c->n, c->nx, c->ny, 1.0 / c->h, eig, (const double*)c->ems, strain,
+                       stress, c->part_post);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->h_part, c->part_post, sizeof(double) * 4 * c->npost * ns, hipMemcpyDeviceToHost,
                         c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  double acc[4] = {0, 0, 0, 0};
-  for (int b = 0; b < c->npost; ++b)
-    for (int j = 0; j < 4; ++j) acc[j] += c->h_part[4 * b + j];
-  if (mean_stress)
-    for (int j = 0; j < 3; ++j) mean_stress[j] = acc[j] / (double)c->n;
-  if (energy) *energy = 0.5 * c->h * c->h * acc[3];
+  for (int s = 0; s < ns; ++s) {
+    double acc[4] = {0, 0, 0, 0};
+    const double* pp = c->h_part + 4LL * c->npost * s;
+    for (int b = 0; b < c->npost; ++b)
+      for (int j = 0; j < 4; ++j) acc[j] += pp[4 * b + j];
+    if (mean_stress)
+      for (int j = 0; j < 3; ++j) mean_stress[3 * s + j] = acc[j] / (double)c->n;
+    if (energy) energy[s] = 0.5 * c->h * c->h * acc[3];
+  }
   return 0;
 }
 
-template <typename T>
-int mech_solve_t(fgcg_ctx* c, const MechMat& m, const double* eig, const double* em, double tol, int maxit,
-                 double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
+int upload_ems(fgcg_ctx* c, const double* em_host) {
+  HIPCHK(hipMemcpyAsync(c->ems, em_host, sizeof(double) * 3 * c->nsamp, hipMemcpyHostToDevice, c->stream));
+  return 0;
+}
+
+int mech_solve_single(fgcg_ctx* c, const MechMat& m, const double* eig, const double* em, double tol, int maxit,
+                      double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
   const double t0 = now();
-  const T ih = (T)(1.0 / c->h);
-  // r = f = -grad^H g C : (eps_mac - e I), x = 0
-  hipLaunchKernelGGL((k_mech_rhs<T>), dim3(c->nkp), dim3(NT), 0, c->stream, m, eig, em[0], em[1], em[2],
-                     (T*)c->r, (T*)c->x, c->n, c->nx, c->ny, ih);
+  int rc;
+  if ((rc = upload_ems(c, em)) || (rc = mech_rhs(c, m, eig))) return rc;
   CgState s;
-  int rc = mech_pcg<T>(c, m, tol, maxit, &s);
-  if (rc) return rc;
-  if ((rc = mech_post<T>(c, m, (const T*)c->x, eig, em, strain, stress, mean_stress, energy))) return rc;
+  if ((rc = mech_pcg(c, m, tol, maxit, &s))) return rc;
+  double e;
+  if ((rc = mech_post(c, m, eig, strain, stress, mean_stress, energy ? energy : &e))) return rc;
   fill_info(info, s, now() - t0);
   return status_of(s);
 }
@@ -554,7 +649,7 @@ int mech_adjoint_t(fgcg_ctx* c, const MechMat& m, const double* eig, const doubl
   double* strain = c->aux;
   double* G = c->aux + 3 * c->n;
   double mean[3], energy;
-  int rc = mech_solve_t<double>(c, m, eig, em, tol, maxit, strain, nullptr, mean, &energy, info_fwd);
+  int rc = mech_solve_single(c, m, eig, em, tol, maxit, strain, nullptr, mean, &energy, info_fwd);
   if (rc < 0) return rc;
   const int fwd_status = rc;
   const double N = (double)c->n;
@@ -571,7 +666,7 @@ int mech_adjoint_t(fgcg_ctx* c, const MechMat& m, const double* eig, const doubl
     hipLaunchKernelGGL(k_adj_rhs, dim3(c->nkp), dim3(NT), 0, c->stream, (const double*)G, (double*)c->r,
                        (double*)c->x, c->n, c->nx, c->ny, 1.0 / c->h);
     HIPCHK(hipGetLastError());
-    if ((rc = mech_pcg<double>(c, m, tol, maxit, &s))) return rc;
+    if ((rc = mech_pcg(c, m, tol, maxit, &s))) return rc;
     have_lam = 1;
   } else {
     s.done = 1;
@@ -585,65 +680,6 @@ int mech_adjoint_t(fgcg_ctx* c, const MechMat& m, const double* eig, const doubl
   const int adj_status = status_of(s);
   if (adj_status < 0) return adj_status;
   return (fwd_status == FGCG_NOT_CONVERGED || adj_status == FGCG_NOT_CONVERGED) ? FGCG_NOT_CONVERGED : FGCG_OK;
-}
-
-// FP32-mixed mechanics: FFT, Green-operator and constitutive passes in FP32,
-// every reduction in FP64, and every tenth iteration a reliable update: the
-// FP32 increments are folded into the FP64 solution and the residual is
-// recomputed as r = f - K x with the FP64 operator (p is kept).
-constexpr int RELIABLE_EVERY = 10;
-
-int mech_solve_mixed(fgcg_ctx* c, const MechMat& m, const double* eig, const double* em, double tol, int maxit,
-                     double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
-  using T = float;
-  const double t0 = now();
-  CT<T>* spec = (CT<T>*)c->spec;
-  const T ih = (T)(1.0 / c->h);
-  Field<T> X{(T*)c->x, c->n, 0}, R{(T*)c->r, c->n, 0}, P{(T*)c->p, c->n, 0}, Q{(T*)c->tmp, c->n, 0};
-  int rc;
-  hipLaunchKernelGGL((k_mech_rhs<double>), dim3(c->nkp), dim3(NT), 0, c->stream, m, eig, em[0], em[1], em[2], c->fh,
-                     c->xh, c->n, c->nx, c->ny, 1.0 / c->h);
-  hipLaunchKernelGGL((k_convert<T, double>), dim3(c->npost), dim3(PT), 0, c->stream, R.p, (const double*)c->fh,
-                     2 * c->n);
-  HIPCHK(hipMemsetAsync(X.p, 0, sizeof(T) * 2 * c->n, c->stream));
-  const CopyProN<T, 2> cp{R, c->nx};
-  if ((rc = launch_row_fwd<T, 2>(c, -1, cp, spec))) return rc;
-  const MechGreen<T> g0{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
-  if ((rc = launch_col<T, 2, 2>(c, -1, g0, spec, spec))) return rc;
-  const MechUEpi<T> e0{P, c->nx, c->st, c->part_rr, c->ncol, 1, tol, maxit};
-  if ((rc = launch_row_inv<T, 2>(c, -1, e0, spec))) return rc;
-  HIPCHK(hipGetLastError());
-  const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, c->nkp};
-  const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, c->st, c->part_rr};
-  const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, c->ncol, 0, tol, maxit};
-  int j = 0;  // position inside the period of RELIABLE_EVERY iterations
-  auto iter = [&]() -> int {
-    set_kname(c, FGCG_K_MECH_KP, "k_mech_kp<%s%.0d", tname<T>(), 0);
-    const bool reliable = j == RELIABLE_EVERY - 1;
-    j = reliable ? 0 : j + 1;
-    int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech_kp<T>, dim3(c->nkp), m, (const T*)P.p, Q.p, c->n,
-                   c->nx, c->ny, ih, c->st, c->part_a);
-    if (!reliable) {
-      r |= launch_row_fwd<T, 2>(c, FGCG_K_MECH_ROW_FWD, pro, spec);
-    } else {
-      r |= launch(c, -1, (const void*)&k_mech_fold<T>, dim3(c->npost), X.p, c->xh, (const T*)P.p, 2 * c->n, c->st,
-                  (const double*)c->part_a, c->nkp);
-      r |= launch(c, -1, (const void*)&k_mech_true_res<T>, dim3(c->nkp), m, (const double*)c->xh,
-                  (const double*)c->fh, R.p, c->n, c->nx, c->ny, 1.0 / c->h, (const CgState*)c->st);
-      r |= launch_row_fwd<T, 2>(c, -1, cp, spec);
-    }
-    r |= launch_col<T, 2, 2>(c, FGCG_K_MECH_COL, green, spec, spec);
-    r |= launch_row_inv<T, 2>(c, FGCG_K_MECH_ROW_INV, epi, spec);
-    return r;
-  };
-  Key key;
-  key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm);
-  if ((rc = run_cg(c, 5, key, c->st, c->h_st, iter, maxit, 2 * RELIABLE_EVERY))) return rc;
-  const CgState s = *c->h_st;
-  hipLaunchKernelGGL((k_fold_final<T>), dim3(c->npost), dim3(PT), 0, c->stream, (const T*)X.p, c->xh, 2 * c->n);
-  if ((rc = mech_post<double>(c, m, (const double*)c->xh, eig, em, strain, stress, mean_stress, energy))) return rc;
-  fill_info(info, s, now() - t0);
-  return status_of(s);
 }
 
 // ------------------------------------------------------------ phase field
@@ -877,19 +913,25 @@ template <typename T> int make_twiddles(int n, void** out) {
 }
 
 template <typename T> int alloc_workspace(fgcg_ctx* c) {
-  const size_t nr = sizeof(T) * 4 * (size_t)c->n;
+  const size_t ns = (size_t)c->nsamp;
+  const size_t nr = sizeof(T) * 4 * (size_t)c->n * ns;
   HIPCHK(hipMalloc(&c->x, nr));
   HIPCHK(hipMalloc(&c->r, nr));
   HIPCHK(hipMalloc(&c->p, nr));
   HIPCHK(hipMalloc(&c->tmp, nr));
-  HIPCHK(hipMalloc(&c->spec, sizeof(CT<T>) * 4 * (size_t)c->nxh * c->ny));
+  HIPCHK(hipMalloc(&c->spec, sizeof(CT<T>) * 4 * (size_t)c->nxh * c->ny * ns));
+  HIPCHK(hipMalloc(&c->ems, sizeof(double) * 3 * ns));
+  if (c->batch) {
+    HIPCHK(hipMalloc(&c->phase_buf, (size_t)c->n * ns));
+    HIPCHK(hipMalloc(&c->strain_buf, sizeof(double) * 3 * (size_t)c->n * ns));
+  }
   int rc;
   if ((rc = make_twiddles<double>(c->nx, &c->twx)) || (rc = make_twiddles<double>(c->ny, &c->twy))) return rc;
   if (c->prec == FGCG_FP32_MIXED) {
     if ((rc = make_twiddles<float>(c->nx, &c->twx32)) || (rc = make_twiddles<float>(c->ny, &c->twy32))) return rc;
-    HIPCHK(hipMalloc(&c->xh, sizeof(double) * 2 * (size_t)c->n));
-    HIPCHK(hipMalloc(&c->fh, sizeof(double) * 2 * (size_t)c->n));
-  } else {
+    HIPCHK(hipMalloc(&c->xh, sizeof(double) * 2 * (size_t)c->n * ns));
+    HIPCHK(hipMalloc(&c->fh, sizeof(double) * 2 * (size_t)c->n * ns));
+  } else if (ns == 1) {
     HIPCHK(hipMalloc(&c->aux, sizeof(double) * 6 * (size_t)c->n));
   }
   return 0;
@@ -916,7 +958,13 @@ const char* fgcg_strerror(int status) {
 
 const char* fgcg_last_error(void) { return g_err.c_str(); }
 
+static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool batch, fgcg_ctx** out);
+
 int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out) {
+  return create_ctx(grid, hip_stream, 1, false, out);
+}
+
+static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool batch, fgcg_ctx** out) {
   if (!grid || !out) return fail(FGCG_EINVAL, "grid/out is NULL");
   *out = nullptr;
   if (grid->ndim != 2) return fail(FGCG_EUNSUPPORTED, "only 2D grids are built");
@@ -932,6 +980,8 @@ int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out) {
   c->n = (long long)c->nx * c->ny;
   c->h = grid->h;
   c->prec = grid->precision;
+  c->nsamp = nsamp;
+  c->batch = batch;
   c->user_stream = (hipStream_t)hip_stream;
   {
     const char* ng = std::getenv("FGCG_NO_GRAPH");
@@ -956,19 +1006,20 @@ int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out) {
   if (!rc) {
     chk(hipMalloc(&c->Dx, sizeof(double2) * c->nxh));
     chk(hipMalloc(&c->Dy, sizeof(double2) * c->ny));
-    chk(hipMalloc(&c->st, sizeof(CgState) * 1));
-    chk(hipHostMalloc(&c->h_st, sizeof(CgState) * 2, hipHostMallocDefault));
+    const size_t ns = (size_t)nsamp;
+    chk(hipMalloc(&c->st, sizeof(CgState) * ns));
+    chk(hipHostMalloc(&c->h_st, sizeof(CgState) * 2 * ns, hipHostMallocDefault));
     const int npa = std::max(std::max(c->nrow + std::max(c->ncol, c->nrow), c->nkp), 512);
-    chk(hipMalloc(&c->part_a, sizeof(double) * npa));
-    chk(hipMalloc(&c->part_rr, sizeof(double) * std::max(std::max(c->nrow, c->ncol), 512)));
+    chk(hipMalloc(&c->part_a, sizeof(double) * npa * ns));
+    chk(hipMalloc(&c->part_rr, sizeof(double) * std::max(std::max(c->nrow, c->ncol), 512) * ns));
     chk(hipMalloc(&c->part_b, sizeof(double) * std::max(std::max(c->nrow, c->npost), 512)));
-    chk(hipMalloc(&c->part_post, sizeof(double) * 5 * c->npost));
+    chk(hipMalloc(&c->part_post, sizeof(double) * 5 * c->npost * ns));
     {
       const int bx = (c->nx + NT - 1) / NT;
       const int by = std::max(1, std::min(c->ny, 512 / bx));
       c->sgrid = dim3(bx, by);
     }
-    chk(hipHostMalloc(&c->h_part, sizeof(double) * 5 * c->npost, hipHostMallocDefault));
+    chk(hipHostMalloc(&c->h_part, sizeof(double) * 5 * c->npost * ns, hipHostMallocDefault));
   }
   if (!rc) {
     // forward-difference symbols D(k) = (exp(i theta) - 1)/h = (-2 sin^2(theta/2) + i sin theta)/h
@@ -994,7 +1045,7 @@ int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out) {
 
 void fgcg_destroy(fgcg_ctx* c) {
   if (!c) return;
-  void* dev[] = {c->twx, c->twy, c->twx32, c->twy32, c->xh, c->fh, c->aux, c->Dx, c->Dy, c->x, c->r, c->p, c->tmp, c->spec, c->st,
+  void* dev[] = {c->ems, c->phase_buf, c->strain_buf, c->twx, c->twy, c->twx32, c->twy32, c->xh, c->fh, c->aux, c->Dx, c->Dy, c->x, c->r, c->p, c->tmp, c->spec, c->st,
                  c->part_a, c->part_rr, c->part_b, c->part_post};
   for (void* p : dev)
     if (p) (void)hipFree(p);
@@ -1008,7 +1059,7 @@ void fgcg_destroy(fgcg_ctx* c) {
   for (auto e : c->pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : {c->ev_in, c->ev_done[0], c->ev_done[1]})
     if (e) (void)hipEventDestroy(e);
-  if (c->stream) (void)hipStreamDestroy(c->stream);
+  if (c->stream && c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
@@ -1049,9 +1100,7 @@ int fgcg_mech_solve(fgcg_ctx* c, const fgcg_material* mat, const double* d, doub
   MechMat m;
   if ((rc = make_mech_mat(c, mat, d, kappa, &m))) return rc;
   if ((rc = enter(c))) return rc;
-  if (c->prec == FGCG_FP32_MIXED)
-    return mech_solve_mixed(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
-  return mech_solve_t<double>(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
+  return mech_solve_single(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
 }
 
 int fgcg_mech_adjoint(fgcg_ctx* c, const fgcg_material* mat, const double* d, double kappa, const double* eig,
@@ -1230,6 +1279,194 @@ int fgcg_profile_read(fgcg_ctx* c, int kind, double* ms, long long* launches) {
 const char* fgcg_kernel_name(fgcg_ctx* c, int kind) {
   if (!c || kind < 0 || kind >= FGCG_K_NKINDS) return "";
   return c->kname[kind].c_str();
+}
+
+
+// ------------------------------------------------------------ batches
+struct fgcg_batch {
+  int nb = 0;
+  std::vector<fgcg_ctx*> groups;
+  std::vector<std::vector<int>> members;  // sample ids of each group
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  std::vector<char> key;
+  hipEvent_t ev_done[2] = {nullptr, nullptr};
+};
+
+void fgcg_batch_destroy(fgcg_batch* b) {
+  if (!b) return;
+  for (auto& e : b->exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  for (auto& e : b->ev_done)
+    if (e) (void)hipEventDestroy(e);
+  for (fgcg_ctx* c : b->groups) fgcg_destroy(c);
+  delete b;
+}
+
+int fgcg_batch_create(int nb, const int* nx, const int* ny, double h, int precision, void* hip_stream,
+                      fgcg_batch** out) {
+  if (!out || !nx || !ny || nb < 1) return fail(FGCG_EINVAL, "nb < 1 or NULL arrays");
+  *out = nullptr;
+  fgcg_batch* b = new fgcg_batch();
+  b->nb = nb;
+  std::vector<std::pair<int, int>> sizes;
+  for (int i = 0; i < nb; ++i) {
+    int g = -1;
+    for (size_t k = 0; k < sizes.size(); ++k)
+      if (sizes[k].first == nx[i] && sizes[k].second == ny[i]) g = (int)k;
+    if (g < 0) {
+      sizes.push_back({nx[i], ny[i]});
+      b->members.push_back({});
+      g = (int)sizes.size() - 1;
+    }
+    b->members[g].push_back(i);
+  }
+  int rc = 0;
+  for (size_t g = 0; g < sizes.size() && !rc; ++g) {
+    fgcg_grid grid{2, {sizes[g].first, sizes[g].second, 1}, h, precision};
+    fgcg_ctx* c = nullptr;
+    rc = create_ctx(&grid, hip_stream, (int)b->members[g].size(), true, &c);
+    if (!rc) {
+      if (g > 0) {  // every group runs on the first group's stream
+        (void)hipStreamDestroy(c->stream);
+        c->stream = b->groups[0]->stream;
+        c->own_stream = false;
+      }
+      b->groups.push_back(c);
+    }
+  }
+  if (!rc && hipEventCreateWithFlags(&b->ev_done[0], hipEventDisableTiming) != hipSuccess) rc = FGCG_EHIP;
+  if (!rc && hipEventCreateWithFlags(&b->ev_done[1], hipEventDisableTiming) != hipSuccess) rc = FGCG_EHIP;
+  if (rc) {
+    fgcg_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return FGCG_OK;
+}
+
+int fgcg_mech_solve_batched(fgcg_batch* b, const uint8_t* const* phases, int nphase, const double* E_tab,
+                            const double* nu_tab, const double* eps_mac, double tol, int maxit,
+                            double* const* strains, double* mean_stress, double* energy, fgcg_info* infos) {
+  if (!b || !phases || !eps_mac) return fail(FGCG_EINVAL, "batch/phases/eps_mac is NULL");
+  int rc;
+  if ((rc = check_solver_args(tol, maxit))) return rc;
+  for (int i = 0; i < b->nb; ++i)
+    if (!phases[i]) return fail(FGCG_EINVAL, "phase pointer is NULL");
+  const double t0 = now();
+  fgcg_ctx* c0 = b->groups[0];
+  hipStream_t st = c0->stream;
+  if ((rc = enter(c0))) return rc;
+  std::vector<MechMat> mats(b->groups.size());
+  for (size_t g = 0; g < b->groups.size(); ++g) {
+    fgcg_ctx* c = b->groups[g];
+    const std::vector<int>& mem = b->members[g];
+    fgcg_material mat{c->phase_buf, nphase, E_tab, nu_tab, nullptr, 0.0};
+    if ((rc = make_mech_mat(c, &mat, nullptr, 0.0, &mats[g]))) return rc;
+    std::vector<double> em(3 * mem.size());
+    for (size_t s = 0; s < mem.size(); ++s) {
+      HIPCHK(hipMemcpyAsync(c->phase_buf + (size_t)c->n * s, phases[mem[s]], (size_t)c->n, hipMemcpyDeviceToDevice,
+                            st));
+      for (int j = 0; j < 3; ++j) em[3 * s + j] = eps_mac[3 * mem[s] + j];
+    }
+    if ((rc = upload_ems(c, em.data())) || (rc = mech_rhs(c, mats[g], nullptr))) return rc;
+    rc = c->prec == FGCG_FP64 ? mech_init<double>(c, mats[g], tol, maxit) : mech_init<float>(c, mats[g], tol, maxit);
+    if (rc) return rc;
+  }
+  auto all_done = [&](int slot) {
+    for (fgcg_ctx* c : b->groups)
+      for (int s = 0; s < c->nsamp; ++s)
+        if (!c->h_st[slot * c->nsamp + s].done) return false;
+    return true;
+  };
+  auto copy_states = [&](int slot) -> int {
+    for (fgcg_ctx* c : b->groups)
+      HIPCHK(hipMemcpyAsync(c->h_st + slot * c->nsamp, c->st, sizeof(CgState) * c->nsamp, hipMemcpyDeviceToHost, st));
+    return 0;
+  };
+  if ((rc = copy_states(0))) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  int last = 0;
+  if (!all_done(0)) {
+    const int K = c0->prec == FGCG_FP64 ? c0->chunk : 2 * RELIABLE_EVERY;
+    Key key = mech_key(c0, mats[0], tol, maxit);
+    key.add(K);
+    if (key.b != b->key || !b->exec[0] || !b->exec[1]) {
+      for (auto& e : b->exec)
+        if (e) (void)hipGraphExecDestroy(e);
+      b->exec[0] = b->exec[1] = nullptr;
+      for (int i = 0; i < 2; ++i) {
+        hipGraph_t graph;
+        HIPCHK(hipGraphCreate(&graph, 0));
+        for (size_t g = 0; g < b->groups.size() && !rc; ++g) {
+          fgcg_ctx* c = b->groups[g];
+          c->graph = graph;
+          c->building = true;
+          c->build_timed = false;
+          c->last = nullptr;  // an independent chain per size group
+          MechIterFn it{c, mats[g], tol, maxit};
+          for (int j = 0; j < K && !rc; ++j) rc = it();
+          c->building = false;
+          c->graph = nullptr;
+          c->pending.clear();
+        }
+        if (!rc && hipGraphInstantiate(&b->exec[i], graph, nullptr, nullptr, 0) != hipSuccess)
+          rc = fail(FGCG_EHIP, "hipGraphInstantiate failed");
+        (void)hipGraphDestroy(graph);
+        if (rc) return rc;
+      }
+      b->key = key.b;
+    }
+    long long launched = 0;
+    auto go = [&](int i) -> int {
+      HIPCHK(hipGraphLaunch(b->exec[i], st));
+      int r = copy_states(i);
+      if (r) return r;
+      HIPCHK(hipEventRecord(b->ev_done[i], st));
+      launched += K;
+      return 0;
+    };
+    if ((rc = go(0)) || (rc = go(1))) return rc;
+    int i = 0;
+    for (;;) {
+      HIPCHK(hipEventSynchronize(b->ev_done[i]));
+      if (all_done(i)) break;
+      if (launched > (long long)maxit + 4LL * K) return fail(FGCG_EHIP, "batched CG driver overran the iteration limit");
+      if ((rc = go(i))) return rc;
+      i ^= 1;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    last = i;
+  }
+  int worst = FGCG_OK;
+  std::vector<double> means, ens;
+  for (size_t g = 0; g < b->groups.size(); ++g) {
+    fgcg_ctx* c = b->groups[g];
+    const std::vector<int>& mem = b->members[g];
+    if (c->prec != FGCG_FP64) {
+      hipLaunchKernelGGL((k_fold_final<float>), dim3(c->npost, c->nsamp), dim3(PT), 0, st, (const float*)c->x, c->xh,
+                         2 * c->n);
+      HIPCHK(hipGetLastError());
+    }
+    means.assign(3 * mem.size(), 0.0);
+    ens.assign(mem.size(), 0.0);
+    if ((rc = mech_post(c, mats[g], nullptr, c->strain_buf, nullptr, means.data(), ens.data()))) return rc;
+    for (size_t s = 0; s < mem.size(); ++s) {
+      const int id = mem[s];
+      if (strains && strains[id])
+        HIPCHK(hipMemcpyAsync(strains[id], c->strain_buf + 3 * (size_t)c->n * s, sizeof(double) * 3 * c->n,
+                              hipMemcpyDeviceToDevice, st));
+      if (mean_stress)
+        for (int j = 0; j < 3; ++j) mean_stress[3 * id + j] = means[3 * s + j];
+      if (energy) energy[id] = ens[s];
+      const CgState& cs = c->h_st[last * c->nsamp + s];
+      if (infos) fill_info(&infos[id], cs, now() - t0);
+      const int stt = status_of(cs);
+      if (stt < 0 && worst >= 0) worst = stt;
+      if (stt == FGCG_NOT_CONVERGED && worst == FGCG_OK) worst = FGCG_NOT_CONVERGED;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return worst;
 }
 
 }  // extern "C"

@@ -30,7 +30,7 @@ namespace fgcg {
 // sigma = g C : sym(grad u) at voxel (y, x): forward differences to (y, x+1)
 // and (y+1, x), periodic.  Returns the symmetric gradient in e[3] too.
 template <typename T>
-__device__ __forceinline__ void sigma_u(const MechMat& m, const T* u, long long n, int nx, int ny, int y,
+__device__ __forceinline__ void sigma_u(const MechMat& m, int s, const T* u, long long n, int nx, int ny, int y,
                                         int x, T ih, T* sg, T* e) {
   const int xp = x + 1 == nx ? 0 : x + 1;
   const int yp = y + 1 == ny ? 0 : y + 1;
@@ -46,17 +46,17 @@ __device__ __forceinline__ void sigma_u(const MechMat& m, const T* u, long long 
   e[1] = g22;
   e[2] = (T)0.5 * (g12 + g21);
   double lam, mu;
-  m.get(0, i, lam, mu);
+  m.get(s, i, lam, mu);
   stress2<T>(lam, mu, e[0], e[1], e[2], sg);
 }
 
 // sigma = g C : (eps_mac - e I) at voxel i
 template <typename T>
-__device__ __forceinline__ void sigma_src(const MechMat& m, const double* eig, const double* em, long long i,
+__device__ __forceinline__ void sigma_src(const MechMat& m, int s, const double* eig, const double* em, long long i,
                                           T* sg) {
   double lam, mu;
-  m.get(0, i, lam, mu);
-  const double e = eig ? eig[i] : 0.0;
+  m.get(s, i, lam, mu);
+  const double e = eig ? eig[m.ss * s + i] : 0.0;
   stress2<T>(lam, mu, (T)(em[0] - e), (T)(em[1] - e), (T)em[2], sg);
 }
 
@@ -75,6 +75,10 @@ __global__ void __launch_bounds__(NT) k_mech_kp(MechMat m, const T* __restrict__
                                                 long long n, int nx, int ny, T ih, CgState* st,
                                                 double* part) {
   __shared__ double red[NT / 64];
+  const int s = blockIdx.y;  // sample of a batch
+  st += s;
+  p += 2 * n * s;
+  q += 2 * n * s;
   if (!cg_running(st, 0)) return;
   if (lead()) st->k = st->k_next;
   double acc = 0.0;
@@ -83,32 +87,36 @@ __global__ void __launch_bounds__(NT) k_mech_kp(MechMat m, const T* __restrict__
     const int xm = x == 0 ? nx - 1 : x - 1;
     const int ym = y == 0 ? ny - 1 : y - 1;
     T s0[3], e0[3], sx[3], sy[3], tmp[3], qq[2];
-    sigma_u<T>(m, p, n, nx, ny, y, x, ih, s0, e0);
-    sigma_u<T>(m, p, n, nx, ny, y, xm, ih, sx, tmp);
-    sigma_u<T>(m, p, n, nx, ny, ym, x, ih, sy, tmp);
+    sigma_u<T>(m, s, p, n, nx, ny, y, x, ih, s0, e0);
+    sigma_u<T>(m, s, p, n, nx, ny, y, xm, ih, sx, tmp);
+    sigma_u<T>(m, s, p, n, nx, ny, ym, x, ih, sy, tmp);
     div_adj<T>(s0, sx, sy, ih, qq);
     q[i] = qq[0];
     q[n + i] = qq[1];
     acc += (double)e0[0] * s0[0] + (double)e0[1] * s0[1] + 2.0 * (double)e0[2] * s0[2];
   }
   const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (threadIdx.x == 0) part[(long long)s * gridDim.x + blockIdx.x] = t;
 }
 
-// r = f = -grad^H g C : (eps_mac - e I); x = 0.
+// r = f = -grad^H g C : (eps_mac - e I); x = 0.  Sample s = blockIdx.y uses
+// em[3 s .. 3 s + 2].
 template <typename T>
-__global__ void __launch_bounds__(NT) k_mech_rhs(MechMat m, const double* eig, double em0, double em1,
-                                                 double em2, T* __restrict__ r, T* __restrict__ x, long long n,
-                                                 int nx, int ny, T ih) {
-  const double em[3] = {em0, em1, em2};
+__global__ void __launch_bounds__(NT) k_mech_rhs(MechMat m, const double* eig, const double* __restrict__ ems,
+                                                 T* __restrict__ r, T* __restrict__ x, long long n, int nx, int ny,
+                                                 T ih) {
+  const int s = blockIdx.y;
+  const double em[3] = {ems[3 * s], ems[3 * s + 1], ems[3 * s + 2]};
+  r += 2 * n * s;
+  x += 2 * n * s;
   for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
     const int y = (int)(i / nx), xx = (int)(i - (long long)y * nx);
     const int xm = xx == 0 ? nx - 1 : xx - 1;
     const int ym = y == 0 ? ny - 1 : y - 1;
     T s0[3], sx[3], sy[3], qq[2];
-    sigma_src<T>(m, eig, em, i, s0);
-    sigma_src<T>(m, eig, em, (long long)y * nx + xm, sx);
-    sigma_src<T>(m, eig, em, (long long)ym * nx + xx, sy);
+    sigma_src<T>(m, s, eig, em, i, s0);
+    sigma_src<T>(m, s, eig, em, (long long)y * nx + xm, sx);
+    sigma_src<T>(m, s, eig, em, (long long)ym * nx + xx, sy);
     div_adj<T>(s0, sx, sy, ih, qq);
     r[i] = -qq[0];
     r[n + i] = -qq[1];
@@ -121,10 +129,14 @@ __global__ void __launch_bounds__(NT) k_mech_rhs(MechMat m, const double* eig, d
 // partial sums of sigma (3) and (eps - e I) : sigma.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_mech_post_u(MechMat m, const T* __restrict__ u, long long n, int nx,
-                                                    int ny, T ih, const double* eig, double em0, double em1,
-                                                    double em2, double* strain, double* stress,
-                                                    double* part) {
+                                                    int ny, T ih, const double* eig, const double* __restrict__ ems,
+                                                    double* strain, double* stress, double* part) {
   __shared__ double red[NT / 64];
+  const int s = blockIdx.y;
+  const double em0 = ems[3 * s], em1 = ems[3 * s + 1], em2 = ems[3 * s + 2];
+  u += 2 * n * s;
+  strain += 3 * n * s;
+  if (stress) stress += 3 * n * s;
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
     const int y = (int)(i / nx), x = (int)(i - (long long)y * nx);
@@ -140,9 +152,9 @@ __global__ void __launch_bounds__(NT) k_mech_post_u(MechMat m, const T* __restri
     strain[i] = e11;
     strain[n + i] = e22;
     strain[2 * n + i] = e12;
-    const double e = eig ? eig[i] : 0.0;
+    const double e = eig ? eig[m.ss * s + i] : 0.0;
     double lam, mu;
-    m.get(0, i, lam, mu);
+    m.get(s, i, lam, mu);
     const double l11 = e11 - e, l22 = e22 - e;
     const double tr = l11 + l22;
     const double s11 = lam * tr + 2.0 * mu * l11;
@@ -161,10 +173,11 @@ __global__ void __launch_bounds__(NT) k_mech_post_u(MechMat m, const T* __restri
   const double t0 = block_sum(a0, red), t1 = block_sum(a1, red), t2 = block_sum(a2, red),
                t3 = block_sum(a3, red);
   if (threadIdx.x == 0) {
-    part[4 * blockIdx.x + 0] = t0;
-    part[4 * blockIdx.x + 1] = t1;
-    part[4 * blockIdx.x + 2] = t2;
-    part[4 * blockIdx.x + 3] = t3;
+    double* pp = part + 4 * ((long long)s * gridDim.x + blockIdx.x);
+    pp[0] = t0;
+    pp[1] = t1;
+    pp[2] = t2;
+    pp[3] = t3;
   }
 }
 
@@ -194,8 +207,12 @@ __global__ void __launch_bounds__(NT) k_mech_fold(T* __restrict__ xlo, double* _
                                                   const T* __restrict__ p, long long n2, CgState* st,
                                                   const double* part_a, int np_a) {
   __shared__ double red[NT / 64];
+  const int s = blockIdx.y;
+  xlo += n2 * s;
+  xhi += n2 * s;
+  p += n2 * s;
   double alpha;
-  if (!mech_alpha(st, part_a, np_a, red, alpha)) return;
+  if (!mech_alpha(st + s, part_a + (long long)s * np_a, np_a, red, alpha)) return;
   for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n2; i += (long long)gridDim.x * NT) {
     xhi[i] += (double)xlo[i] + alpha * (double)p[i];
     xlo[i] = (T)0;
@@ -207,15 +224,19 @@ template <typename T>
 __global__ void __launch_bounds__(NT) k_mech_true_res(MechMat m, const double* __restrict__ xhi,
                                                       const double* __restrict__ f, T* __restrict__ r, long long n,
                                                       int nx, int ny, double ih, const CgState* st) {
-  if (!cg_running(st, 0)) return;
+  const int s = blockIdx.y;
+  xhi += 2 * n * s;
+  f += 2 * n * s;
+  r += 2 * n * s;
+  if (!cg_running(st, s)) return;
   for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
     const int y = (int)(i / nx), x = (int)(i - (long long)y * nx);
     const int xm = x == 0 ? nx - 1 : x - 1;
     const int ym = y == 0 ? ny - 1 : y - 1;
     double s0[3], sx[3], sy[3], e[3], qq[2];
-    sigma_u<double>(m, xhi, n, nx, ny, y, x, ih, s0, e);
-    sigma_u<double>(m, xhi, n, nx, ny, y, xm, ih, sx, e);
-    sigma_u<double>(m, xhi, n, nx, ny, ym, x, ih, sy, e);
+    sigma_u<double>(m, s, xhi, n, nx, ny, y, x, ih, s0, e);
+    sigma_u<double>(m, s, xhi, n, nx, ny, y, xm, ih, sx, e);
+    sigma_u<double>(m, s, xhi, n, nx, ny, ym, x, ih, sy, e);
     div_adj<double>(s0, sx, sy, ih, qq);
     r[i] = (T)(f[i] - qq[0]);
     r[n + i] = (T)(f[n + i] - qq[1]);
@@ -225,6 +246,8 @@ __global__ void __launch_bounds__(NT) k_mech_true_res(MechMat m, const double* _
 // x_hi += x_lo (end of a mixed-precision solve)
 template <typename T>
 __global__ void __launch_bounds__(NT) k_fold_final(const T* __restrict__ xlo, double* __restrict__ xhi, long long n2) {
+  xlo += n2 * blockIdx.y;
+  xhi += n2 * blockIdx.y;
   for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n2; i += (long long)gridDim.x * NT)
     xhi[i] += (double)xlo[i];
 }
@@ -236,7 +259,9 @@ template <typename T> struct MechUPro {
   CgState* st;
   const double* part_a;
   int np_a;
-  __device__ bool begin(int, double* red, double& sc) const { return mech_alpha(st, part_a, np_a, red, sc); }
+  __device__ bool begin(int s, double* red, double& sc) const {
+    return mech_alpha(st + s, part_a + (long long)s * np_a, np_a, red, sc);
+  }
   __device__ void point(int s, int y, int xx, T* out, double&, double sc) const {
     const long long i = (long long)y * nx + xx;
     const T a = (T)sc;
@@ -270,7 +295,7 @@ template <typename T> struct MechGreen {
   double inv_n;
   int nx;
   const CgState* st;  // nullable
-  double* part;       // nullable
+  double* part;       // nullable; per sample, gridDim.x partials
   __device__ bool begin(int s, double*, double&) const { return st == nullptr || cg_running(st, s); }
   template <typename C>
   __device__ void mode(int, int kx, int ky, const C* a, C* b, double& acc, double) const {
@@ -290,7 +315,7 @@ template <typename T> struct MechGreen {
            ((double)a[0].x * a[0].x + (double)a[0].y * a[0].y + (double)a[1].x * a[1].x + (double)a[1].y * a[1].y);
   }
   __device__ void partial(int s, double v) const {
-    if (part) store_partial(part, 0, s, 0, v);
+    if (part && threadIdx.x == 0) part[(long long)s * gridDim.x + blockIdx.x] = v;
   }
 };
 
@@ -306,9 +331,10 @@ template <typename T> struct MechUEpi {
   int init;
   double tol;
   int maxit;
-  __device__ bool begin(int, double* red, double& sc) const {
-    if (!init && !cg_running(st, 0)) return false;
-    const double rz = block_sum_array(part_rz, np_rz, red);
+  __device__ bool begin(int s, double* red, double& sc) const {
+    CgState* S = st + s;
+    if (!init && !cg_running(st, s)) return false;
+    const double rz = block_sum_array(part_rz + (long long)s * np_rz, np_rz, red);
     if (init) {
       const double thr = tol * tol * rz;
       const int done = !isfinite(rz) ? 4 : (rz <= thr ? 1 : (maxit <= 0 ? 2 : 0));
@@ -326,28 +352,28 @@ template <typename T> struct MechUEpi {
         t.iter = 0;
         t.done = done;
         t.zero_rhs = rz == 0.0;
-        *st = t;
+        *S = t;
       }
       sc = 0.0;
       return done == 0;
     }
-    const int k = st->k;
+    const int k = S->k;
     int code = 0;
     if (!isfinite(rz)) code = 3;
-    else if (rz <= st->thr) code = 1;
-    else if (k + 1 >= st->maxit) code = 2;
+    else if (rz <= S->thr) code = 1;
+    else if (k + 1 >= S->maxit) code = 2;
     if (code) {
       if (lead()) {
-        st->done = code;
-        st->iter = k + 1;
-        st->rr_final = rz;
+        S->done = code;
+        S->iter = k + 1;
+        S->rr_final = rz;
       }
       return false;
     }
-    sc = rz / st->rz[k & 1];
+    sc = rz / S->rz[k & 1];
     if (lead()) {
-      st->rz[(k + 1) & 1] = rz;
-      st->k_next = k + 1;
+      S->rz[(k + 1) & 1] = rz;
+      S->k_next = k + 1;
     }
     return true;
   }

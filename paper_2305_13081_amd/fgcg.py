@@ -93,6 +93,11 @@ _SIGS = {
                               _vp, _vp, _dp, _dp, ctypes.POINTER(Info)]),
     "fgcg_mech_adjoint": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _dp, _vp, _ip,
                                 ctypes.c_double, _ip, _vp, _dp, ctypes.POINTER(Info), ctypes.POINTER(Info)]),
+    "fgcg_batch_create": (_ip, [_ip, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.c_double, _ip,
+                                _vp, ctypes.POINTER(_vp)]),
+    "fgcg_batch_destroy": (None, [_vp]),
+    "fgcg_mech_solve_batched": (_ip, [_vp, ctypes.POINTER(_vp), _ip, _dp, _dp, _dp, ctypes.c_double, _ip,
+                                      ctypes.POINTER(_vp), _dp, _dp, ctypes.POINTER(Info)]),
     "fgcg_phasefield_solve": (_ip, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, ctypes.c_double, _ip,
                                     ctypes.POINTER(Info)]),
     "fgcg_diffusion_step": (_ip, [_vp, _vp, _ip, _dp, _dp, _ip, ctypes.c_double, ctypes.c_double, _vp,
@@ -368,3 +373,58 @@ class Context:
                "fgcg_profile_read")
         name = self.lib.fgcg_kernel_name(self.ptr, KINDS[kind]).decode()
         return ms.value, n.value, name
+
+
+class Batch:
+    """Many 2D microstructures of uneven sizes solved together
+    (fgcg_batch_create / fgcg_mech_solve_batched)."""
+
+    def __init__(self, sizes, h, precision=FP64, device=None):
+        torch = _torch()
+        self.lib = load_library()
+        self.sizes = [(int(nx), int(ny)) for nx, ny in sizes]
+        self.nb = len(self.sizes)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        nx = (ctypes.c_int * self.nb)(*[s[0] for s in self.sizes])
+        ny = (ctypes.c_int * self.nb)(*[s[1] for s in self.sizes])
+        out = _vp()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(self.lib.fgcg_batch_create(self.nb, nx, ny, float(h), int(precision), _vp(stream), ctypes.byref(out)),
+               "fgcg_batch_create")
+        self.ptr = out
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            self.lib.fgcg_batch_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mech_solve(self, phases, E_tab, nu_tab, eps_mac, tol=1e-10, maxit=50000, want_strain=True):
+        torch = _torch()
+        if len(phases) != self.nb or len(eps_mac) != self.nb:
+            raise FgcgError(-1, "Batch.mech_solve", "need one phase field and one macro strain per sample")
+        for (nx, ny), ph in zip(self.sizes, phases):
+            if not (isinstance(ph, torch.Tensor) and ph.dtype == torch.uint8 and ph.device == self.device
+                    and tuple(ph.shape) == (ny, nx) and ph.is_contiguous()):
+                raise FgcgError(-1, "Batch.mech_solve", f"phase must be a contiguous uint8 ({ny}, {nx}) tensor")
+        if not (1 <= len(E_tab) <= MAX_PHASES and len(E_tab) == len(nu_tab)):
+            raise FgcgError(-1, "Batch.mech_solve", "E_tab/nu_tab must have equal length 1..8")
+        strains = [torch.empty((3, ny, nx), dtype=torch.float64, device=self.device) for nx, ny in self.sizes] \
+            if want_strain else None
+        ph = (_vp * self.nb)(*[p.data_ptr() for p in phases])
+        sp = (_vp * self.nb)(*[t.data_ptr() for t in strains]) if strains else None
+        em = _dvec([v for e in eps_mac for v in e])
+        mean = (ctypes.c_double * (3 * self.nb))()
+        en = (ctypes.c_double * self.nb)()
+        infos = (Info * self.nb)()
+        st = self.lib.fgcg_mech_solve_batched(self.ptr, ph, len(E_tab), _dvec(E_tab), _dvec(nu_tab), em, float(tol),
+                                              int(maxit), sp, mean, en, infos)
+        _check(st, "fgcg_mech_solve_batched", allow_nc=True)
+        return dict(strains=strains, mean_stress=np.array(list(mean)).reshape(self.nb, 3),
+                    energy=np.array(list(en)), infos=[i.as_dict() for i in infos])
