@@ -12,17 +12,20 @@
  *   staggered   Alg. 1: diffusion -> precipitation/eigenstrain -> mechanics ->
  *               history -> phase field
  *
- * Every gradient is the forward difference of Sec. 2.5,
+ * Every gradient is the forward difference of Sec. 2.6,
  * D_a(k) = (exp(2 pi i k_a / n_a) - 1) / h.
  *
  * Conventions
- *   - Grids are periodic, 2D with n[0] = nx (fastest) and n[1] = ny; every
- *     axis length is 2^a 3^b between 8 and 2048.
+ *   - Grids are periodic, 2D with n[0] = nx (fastest) and n[1] = ny, or 3D
+ *     with n[2] = nz as well; every axis length is 2^a 3^b, 8..2048 in 2D and
+ *     8..512 in 3D.  N is the number of voxels.
  *   - Field pointers are DEVICE pointers owned by the caller, contiguous,
- *     component-major: [comp][ny][nx].  Host pointers are marked "host".
- *   - Strain and stress use Voigt order (11, 22, 12) with TENSOR shear
- *     (eps_12, not gamma_12); phase ids are uint8 (0 = pore, 1 = solid, up to
- *     FGCG_MAX_PHASES phases).
+ *     component-major: [comp][ny][nx] or [comp][nz][ny][nx].  Host pointers
+ *     are marked "host".
+ *   - Strain and stress use Voigt order with TENSOR shear (eps_12, not
+ *     gamma_12): n_s = 3 components (11, 22, 12) in 2D (plane strain), n_s = 6
+ *     components (11, 22, 33, 23, 13, 12) in 3D.  Index 1 is the x axis.
+ *     Phase ids are uint8 (0 = pore, 1 = solid, up to FGCG_MAX_PHASES phases).
  *   - All work is enqueued on the context's HIP stream; calls that return an
  *     fgcg_info or host scalars return after the stream has finished them.
  *   - The context owns every workspace buffer; solves allocate nothing.
@@ -55,7 +58,7 @@ typedef enum {
 typedef enum { FGCG_FP64 = 0, FGCG_FP32_MIXED = 1 } fgcg_precision;
 
 typedef struct {
-  int ndim;      /* 2 */
+  int ndim;      /* 2 or 3 */
   int n[3];      /* n[0] = nx, n[1] = ny, n[2] = nz (unused in 2D) */
   double h;      /* voxel size, > 0 */
   int precision; /* fgcg_precision */
@@ -94,7 +97,7 @@ const char* fgcg_last_error(void);
 /* Context options.
  *   FGCG_OPT_SCALAR_SPECTRAL  0 (default): the phase-field and diffusion
  *       operators are applied as real-space stencils (the forward-difference
- *       gradient of Sec. 2.5 is local, so this is the same operator); 1: they
+ *       gradient of Sec. 2.6 is local, so this is the same operator); 1: they
  *       are applied in Fourier space as eq. crack-fft writes them.
  *   FGCG_OPT_GRAPHS           1 (default): CG iterations are replayed as HIP
  *       graphs of FGCG_OPT_CHUNK iterations; 0: plain launches.
@@ -113,11 +116,13 @@ int fgcg_set_option(fgcg_ctx* ctx, int option, int value);
  * beta and residual norms as CG on x. */
 /*   d        device [N] damage or NULL (d = 0); g = (1 - d)^2 + kappa
  *   eig      device [N] scalar eigenstrain e or NULL (0)
- *   eps_mac  host [3] macroscopic strain (Voigt, tensor shear)
- *   strain   device [3][N] out: eps = eps_mac + sym(x)
- *   stress   device [3][N] out or NULL: sigma = g C : (eps - e I)
- *   mean_stress host [3] out or NULL: mean of sigma over all voxels
- *   energy   host out or NULL: W = h^2/2 sum_x (eps - e I) : sigma
+ *   eps_mac  host [n_s] macroscopic strain (Voigt, tensor shear)
+ *   strain   device [n_s][N] out: eps = eps_mac + sym(x)
+ *   stress   device [n_s][N] out or NULL: sigma = g C : (eps - e I)
+ *   mean_stress host [n_s] out or NULL: mean of sigma over all voxels
+ *   energy   host out or NULL: W = h^dim/2 sum_x (eps - e I) : sigma
+ * 3D grids: the same method with 3 displacement components and the 3D
+ * transforms; fgcg_material.E_field is not supported there (EUNSUPPORTED).
  */
 int fgcg_mech_solve(fgcg_ctx* ctx, const fgcg_material* mat, const double* d, double kappa,
                     const double* eig, const double* eps_mac, double tol, int maxit,
@@ -138,7 +143,8 @@ int fgcg_mech_solve(fgcg_ctx* ctx, const fgcg_material* mat, const double* d, do
  *              FGCG_J_C11: J = <sigma_11> / eps_mac[0] (eps_mac[0] != 0).
  *   grad_E     device [N] out.   J  host out or NULL.
  *   info_fwd / info_adj  the two solves (info_adj->iters = 0 for the energy).
- * Returns EUNSUPPORTED in FP32-mixed contexts, EINVAL/EDOMAIN as mech_solve. */
+ * Returns EUNSUPPORTED in FP32-mixed contexts and on 3D grids, EINVAL/EDOMAIN
+ * as mech_solve. */
 enum { FGCG_J_USER = 0, FGCG_J_ENERGY = 1, FGCG_J_C11 = 2 };
 int fgcg_mech_adjoint(fgcg_ctx* ctx, const fgcg_material* mat, const double* d, double kappa,
                       const double* eig, const double* eps_mac, const double* dJ_dstrain, int objective,
@@ -183,14 +189,15 @@ int fgcg_diffusion_step(fgcg_ctx* ctx, const uint8_t* phase, int nphase, const d
                         double tol, int maxit, fgcg_info* info);
 
 /* Staggered corrosion-fracture step (Alg. 1).  State fields are device [N]
- * (strain: [3][N]) owned by the caller and updated in place. */
+ * (strain: [n_s][N]) owned by the caller and updated in place.  On 3D grids
+ * the diffusion step and the phase field run as real-space stencil CG. */
 typedef struct {
   double* c;      /* ferrous-ion concentration (normalised) */
   double* f;      /* precipitate volume fraction */
   double* e;      /* isotropic eigenstrain */
   double* H;      /* history field max psi+ */
   double* d;      /* damage */
-  double* strain; /* [3][N] last total strain */
+  double* strain; /* [n_s][N] last total strain */
   int step;
 } fgcg_state;
 
@@ -203,7 +210,7 @@ typedef struct {
   double dt;
   double e_per_f;      /* eigenstrain per unit precipitate fraction (pores only) */
   double Gc, l0, kappa;
-  double eps_mac[3];
+  double eps_mac[6];   /* n_s entries used */
   double tol_diff, tol_mech, tol_pf;
   int maxit;
   int diffuse;         /* 0: skip diffusion, prescribe e = e_ramp (step+1)/n_ramp in pores */
@@ -213,7 +220,7 @@ typedef struct {
 
 typedef struct {
   fgcg_info diff, mech, pf;
-  double mean_stress[3];
+  double mean_stress[6]; /* n_s entries used */
   double energy;
   double max_d;
   double damaged_fraction;   /* share of solid voxels with d > 0.9 */
@@ -225,7 +232,8 @@ int fgcg_staggered_step(fgcg_ctx* ctx, fgcg_state* state, const fgcg_params* prm
                         fgcg_step_info* info);
 
 /* ---- kernel-level test hooks ------------------------------------------ */
-/* q = G[g C : sym(p)] for a full gradient p (device [4][N] each). */
+/* 2D grids only (EUNSUPPORTED in 3D).
+ * q = G[g C : sym(p)] for a full gradient p (device [4][N] each). */
 int fgcg_mech_apply(fgcg_ctx* ctx, const fgcg_material* mat, const double* d, double kappa,
                     const double* p, double* q);
 /* q = (Gc/(2 l0) + H) v + (Gc l0/2) F^-1 |D|^2 F v. */
@@ -234,6 +242,15 @@ int fgcg_phasefield_apply(fgcg_ctx* ctx, const double* H, double Gc, double l0, 
 /* q = (1/dt + k) v + sum_a F^-1 conj(D_a) F D(x) F^-1 D_a F v (no band). */
 int fgcg_diffusion_apply(fgcg_ctx* ctx, const uint8_t* phase, int nphase, const double* D_tab,
                          const double* k_tab, double dt, const double* v, double* q);
+
+/* Real-input discrete Fourier transform of one field (exp(-2 pi i k.x / n),
+ * the transform of Sec. 2.1) through the transform passes of the solvers, FP64.
+ *   dir > 0: in device [N] real -> out device [nz][ny][nx/2+1] complex
+ *            (interleaved re, im; nz = 1 in 2D), unnormalised;
+ *   dir < 0: in that half spectrum -> out [N] real, with the factor 1/N.
+ * A kernel-level test hook: the forward output has the layout of the usual
+ * real-input FFT routines.  Returns EINVAL for NULL pointers. */
+int fgcg_debug_fft(fgcg_ctx* ctx, int dir, const double* in, double* out);
 
 /* ---- profiling -------------------------------------------------------- */
 /* Kernel kinds that can be timed with HIP events around every launch. */
@@ -250,8 +267,12 @@ enum {
   FGCG_K_DIFF_COL_DIV = 9,
   FGCG_K_DIFF_ROW_INV = 10,
   FGCG_K_MECH_KP = 11,
-  FGCG_K_NKINDS = 12
+  FGCG_K_MECH_Y_FWD = 12, /* 3D: y transforms of the Green operator */
+  FGCG_K_MECH_Y_INV = 13,
+  FGCG_K_NKINDS = 14
 };
+/* On 3D grids FGCG_K_MECH_COL times the z pass (forward z transform, Green
+ * symbol, inverse z transform). */
 /* mask: bit k enables event timing of kind k (0 disables); resets counters. */
 int fgcg_profile(fgcg_ctx* ctx, unsigned mask);
 /* Accumulated device time (ms) and launch count of kind k since fgcg_profile. */

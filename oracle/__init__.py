@@ -9,7 +9,7 @@ Two levels, following the paper (Pundir, Kammer, Angst, arXiv 2305.13081):
 
 * algorithm level -- plain NumPy FP64 versions of the steps the GPU path takes:
   a naive recursive mixed-radix DFT (``fft``), the forward-difference gradient
-  symbol of Sec. 2.5, the projection operators of App. A (eq. g-42), the
+  symbol of Sec. 2.6, the projection operators of App. A (eq. g-42), the
   constitutive law of Sec. 2.3, the AT2 phase-field operator of Sec. 2.4
   (eq. crack-fft), the transient heterogeneous diffusion operator, textbook CG,
   and the staggered scheme of Alg. 1;

@@ -1,7 +1,7 @@
 """Transient heterogeneous diffusion-reaction step (test infrastructure).
 
 Flux j = -D(x) grad c with D mixed per phase (Sec. 2.1); the gradient is the
-forward difference of Sec. 2.5, so the divergence is its adjoint,
+forward difference of Sec. 2.6, so the divergence is its adjoint,
 -div = D^H.  One backward-Euler step of dc/dt = div(D grad c) - k_r(x) c reads
 
     A c = (1/dt + k_r(x)) c + sum_a F^-1[ conj(D_a) F[ D(x) F^-1[ D_a F[c] ] ] ]

@@ -1,7 +1,7 @@
 """Definition-level solves: real-space stencils and a sparse direct solver.
 
 No Fourier transform appears here.  The forward-difference gradient of
-Sec. 2.5 is the periodic stencil (f(x + h e_a) - f(x)) / h, assembled as a
+Sec. 2.6 is the periodic stencil (f(x + h e_a) - f(x)) / h, assembled as a
 sparse matrix B_a; its transpose is the (negative) divergence.  Each discrete
 problem of the path is written as the stationarity condition it encodes and
 solved with ``scipy.sparse.linalg.spsolve``:

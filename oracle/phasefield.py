@@ -5,7 +5,7 @@ Sec. 2.4, eq. crack and eq. crack-fft:
     -(Gc l0 / 2) lap(d) + (Gc / (2 l0)) d + H d = H,
 
 with the Laplacian applied in Fourier space.  With the forward-difference
-gradient D of Sec. 2.5 the Laplacian symbol is taken as -D^H D = -|D|^2 (the
+gradient D of Sec. 2.6 the Laplacian symbol is taken as -D^H D = -|D|^2 (the
 reading that keeps the operator symmetric positive definite),
 so the operator is
 

@@ -5,7 +5,7 @@ Grid convention: a scalar field on an n_y x n_x grid is an array of shape
 array axis.  Tensor fields carry their tensor indices first: a second-order
 field has shape (dim, dim) + grid, index [i, j] meaning component x_i x_j.
 
-* Forward-difference gradient symbol, Sec. 2.5: D_a(k) = (exp(i theta_a) - 1)/h
+* Forward-difference gradient symbol, Sec. 2.6: D_a(k) = (exp(i theta_a) - 1)/h
   with theta_a = 2 pi k_a / n_a, which is the transform of the stencil
   (f(x + h e_a) - f(x)) / h under the forward DFT sign of ``oracle.fft``.
 * Inverse gradient, App. A eq. g-42: (iXi)^{-1} = conj(D) / (D . conj(D)),
@@ -22,7 +22,7 @@ import numpy as np
 
 
 def diff_symbol_1d(n, h):
-    """Forward-difference symbol on n points of spacing h (Sec. 2.5)."""
+    """Forward-difference symbol on n points of spacing h (Sec. 2.6)."""
     k = np.arange(n)
     theta = 2.0 * np.pi * k / n
     return (np.exp(1j * theta) - 1.0) / h

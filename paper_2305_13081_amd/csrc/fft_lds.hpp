@@ -38,6 +38,18 @@ template <bool INV, typename C> __device__ __forceinline__ C cmul_mi(C a) {
 __device__ __forceinline__ int lds(int i) { return i + (i >> 3); }
 constexpr int lds_size(int n) { return n + n / 8 + 1; }
 
+// LDS position of element x of signal sig.  FlatIdx: the signals back to back
+// in one padded array (lds(sig N + x)).  PitchIdx: signals P apart with P odd,
+// so that the 16 (FP64) or 32 (FP32) lanes that write element x of
+// consecutive signals (a transposing load) hit distinct banks.
+template <int N> struct FlatIdx {
+  static __device__ __forceinline__ int at(int sig, int x) { return lds(sig * N + x); }
+};
+constexpr int pitch_for(int n) { return (n + n / 8) | 1; }
+template <int N> struct PitchIdx {
+  static __device__ __forceinline__ int at(int sig, int x) { return sig * pitch_for(N) + lds(x); }
+};
+
 // ---------------------------------------------------------------- radix plan
 constexpr int count3(int n) { return n % 3 == 0 ? 1 + count3(n / 3) : 0; }
 constexpr int pow3(int a) { return a == 0 ? 1 : 3 * pow3(a - 1); }
@@ -138,7 +150,7 @@ template <bool INV, typename T> struct Dft<8, INV, T> {
 };
 
 // ------------------------------------------------------------ one stage
-template <typename T, int N, int R, int NS, int NSIG, int NT, bool INV>
+template <typename T, int N, int R, int NS, int NSIG, int NT, bool INV, class Idx>
 __device__ __forceinline__ void stockham_stage(typename cvec<T>::type* buf,
                                                const typename cvec<T>::type* __restrict__ tw) {
   using C = typename cvec<T>::type;
@@ -154,7 +166,7 @@ __device__ __forceinline__ void stockham_stage(typename cvec<T>::type* buf,
     if (TOT % NT == 0 || b < TOT) {
       const int sig = b / M, j = b - sig * M;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[lds(sig * N + j + r * M)];
+      for (int r = 0; r < R; ++r) v[q][r] = buf[Idx::at(sig, j + r * M)];
       if (NS > 1) {
         const int k = j % NS;
 #pragma unroll
@@ -174,35 +186,35 @@ __device__ __forceinline__ void stockham_stage(typename cvec<T>::type* buf,
     if (TOT % NT == 0 || b < TOT) {
       const int sig = b / M, j = b - sig * M;
       const int k = j % NS;
-      const int base = sig * N + (j / NS) * NS * R + k;
+      const int base = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lds(base + r * NS)] = v[q][r];
+      for (int r = 0; r < R; ++r) buf[Idx::at(sig, base + r * NS)] = v[q][r];
     }
   }
   __syncthreads();
 }
 
-template <typename T, int N, int NSIG, int NT, bool INV, int ST, int NS>
+template <typename T, int N, int NSIG, int NT, bool INV, int ST, int NS, class Idx>
 struct StageRunner {
   static __device__ __forceinline__ void run(typename cvec<T>::type* buf,
                                              const typename cvec<T>::type* __restrict__ tw) {
     constexpr Plan p = make_plan(N);
     if constexpr (ST < p.nst) {
       constexpr int R = p.r[ST];
-      stockham_stage<T, N, R, NS, NSIG, NT, INV>(buf, tw);
-      StageRunner<T, N, NSIG, NT, INV, ST + 1, NS * R>::run(buf, tw);
+      stockham_stage<T, N, R, NS, NSIG, NT, INV, Idx>(buf, tw);
+      StageRunner<T, N, NSIG, NT, INV, ST + 1, NS * R, Idx>::run(buf, tw);
     }
   }
 };
 
 // Transform NSIG signals of length N in LDS (element i of signal g at
-// lds(g N + i)); callers synchronise before.
+// Idx::at(g, i), by default lds(g N + i)); callers synchronise before.
 // Forward uses exp(-2 pi i k x / N); inverse uses exp(+...) without 1/N.
-template <typename T, int N, int NSIG, int NT, bool INV>
+template <typename T, int N, int NSIG, int NT, bool INV, class Idx = FlatIdx<N>>
 __device__ __forceinline__ void fft_lds(typename cvec<T>::type* buf,
                                         const typename cvec<T>::type* __restrict__ tw) {
   static_assert(fft_size_ok(N), "FFT length must be 2^a 3^b");
-  StageRunner<T, N, NSIG, NT, INV, 0, 1>::run(buf, tw);
+  StageRunner<T, N, NSIG, NT, INV, 0, 1, Idx>::run(buf, tw);
 }
 
 }  // namespace fgcg

@@ -1,485 +1,11 @@
-// Host engine of the fgcg C ABI: context and workspace, pass launches, the
-// chunked CG driver, and the entry points declared in include/fgcg.h.
-#include <hip/hip_runtime.h>
-
-#include <chrono>
-#include <cmath>
-#include <cstdio>
-#include <cstdlib>
-#include <cstring>
-#include <string>
-#include <type_traits>
-#include <utility>
-#include <vector>
-
-#include "fgcg.h"
+// Entry points of the fgcg C ABI declared in include/fgcg.h and the 2D
+// solvers (3D grids are handled in fgcg3d.hip).
 #include "adjoint.hpp"
-#include "mech_u.hpp"
-#include "scalar_cg.hpp"
-#include "pointwise.hpp"
+#include "engine.hpp"
 
 using namespace fgcg;
 
 namespace {
-
-thread_local std::string g_err;
-
-int fail(int code, const std::string& msg) {
-  g_err = msg;
-  return code;
-}
-
-#define HIPCHK(call)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (call);                                                              \
-    if (e_ != hipSuccess) return fail(FGCG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-template <typename T> using CT = typename cvec<T>::type;
-
-// Supported axis lengths (2^a 3^b).  Each length instantiates the pass kernels.
-#define FGCG_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(2048)
-
-template <class F> bool with_n(int n, F&& f) {
-  switch (n) {
-#define FGCG_CASE(N)                       \
-  case N:                                  \
-    f(std::integral_constant<int, N>{});   \
-    return true;
-    FGCG_SIZES(FGCG_CASE)
-#undef FGCG_CASE
-    default:
-      return false;
-  }
-}
-
-bool size_supported(int n) {
-  return with_n(n, [](auto) {});
-}
-
-}  // namespace
-
-struct fgcg_ctx {
-  int nx = 0, ny = 0, nxh = 0;
-  long long n = 0;
-  double h = 0;
-  int prec = FGCG_FP64;
-  hipStream_t stream = nullptr;       // context-owned stream: every launch goes here
-  bool own_stream = true;             // false for the groups of a batch after the first
-  hipStream_t user_stream = nullptr;  // caller's stream; work on it is waited for at entry
-  hipEvent_t ev_in = nullptr;
-  hipEvent_t ev_done[2] = {nullptr, nullptr};
-  bool use_graphs = true;
-  bool building = false;            // launches become nodes of `graph`
-  bool build_timed = false;         // add event-record nodes while building
-  hipGraph_t graph = nullptr;
-  hipGraphNode_t last = nullptr;
-  int chunk = 16;  // CG iterations per captured graph
-  void* twx = nullptr;    // double2[nx] twiddles
-  void* twy = nullptr;    // double2[ny]
-  void* twx32 = nullptr;  // float2[nx] (FP32-mixed contexts)
-  void* twy32 = nullptr;  // float2[ny]
-  double* xh = nullptr;   // FP32-mixed: FP64 solution (2 components)
-  double* fh = nullptr;   // FP32-mixed: FP64 right-hand side (2 components)
-  double* aux = nullptr;  // adjoint: forward strain (3 components) and dJ/deps (3 components)
-  double2* Dx = nullptr;
-  double2* Dy = nullptr;
-  void* x = nullptr;
-  void* r = nullptr;
-  void* p = nullptr;
-  void* tmp = nullptr;
-  void* spec = nullptr;
-  CgState* st = nullptr;
-  CgState* h_st = nullptr;
-  dim3 sgrid;                 // grid of the stencil CG passes (at most 512 blocks)
-  int scalar_spectral = 0;    // 1: phase field and diffusion apply their operators by FFT
-  double* part_a = nullptr;
-  double* part_rr = nullptr;
-  double* part_b = nullptr;
-  double* part_post = nullptr;
-  double* h_part = nullptr;
-  int nrow = 0, ncol = 0, npost = 0, nkp = 0;
-  int nsamp = 1;            // samples of this grid size (batches)
-  double* ems = nullptr;    // device [nsamp][3] macro strains
-  bool batch = false;            // member of a batch (owns the gather buffers below)
-  uint8_t* phase_buf = nullptr;  // batches: gathered phase fields [nsamp][N]
-  double* strain_buf = nullptr;  // batches: strains [nsamp][3][N]
-  unsigned prof_mask = 0;
-  double prof_ms[FGCG_K_NKINDS] = {0};
-  long long prof_n[FGCG_K_NKINDS] = {0};
-  std::string kname[FGCG_K_NKINDS];
-  std::vector<hipEvent_t> pool;
-  struct Pending {
-    int kind;
-    hipEvent_t a, b;
-  };
-  std::vector<Pending> pending;
-  hipEvent_t cur = nullptr;
-  struct GraphSlot {
-    hipGraphExec_t exec = nullptr;
-    std::vector<Pending> ev;  // timing events recorded inside this instance
-  };
-  struct CgGraph {
-    std::vector<char> key;
-    GraphSlot slot[2];
-  };
-  CgGraph graphs[6];  // mechanics, phase field, diffusion (spectral), phase field, diffusion (stencil),
-                      // mechanics FP32-mixed
-};
-
-namespace {
-
-int prof_begin(fgcg_ctx* c, int kind) {
-  if (!(c->prof_mask & (1u << kind))) return 0;
-  if (c->pool.size() < 2) {
-    for (int i = 0; i < 64; ++i) {
-      hipEvent_t e;
-      HIPCHK(hipEventCreate(&e));
-      c->pool.push_back(e);
-    }
-  }
-  c->cur = c->pool.back();
-  c->pool.pop_back();
-  HIPCHK(hipEventRecord(c->cur, c->stream));
-  return 0;
-}
-
-int prof_end(fgcg_ctx* c, int kind) {
-  if (!(c->prof_mask & (1u << kind))) return 0;
-  hipEvent_t e = c->pool.back();
-  c->pool.pop_back();
-  HIPCHK(hipEventRecord(e, c->stream));
-  c->pending.push_back({kind, c->cur, e});
-  return 0;
-}
-
-// Call after the stream has been synchronised.
-int prof_flush(fgcg_ctx* c) {
-  for (auto& p : c->pending) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
-    c->prof_ms[p.kind] += ms;
-    c->prof_n[p.kind] += 1;
-    c->pool.push_back(p.a);
-    c->pool.push_back(p.b);
-  }
-  c->pending.clear();
-  return 0;
-}
-
-int prof_reserve(fgcg_ctx* c, size_t n) {
-  while (c->pool.size() < n) {
-    hipEvent_t e;
-    HIPCHK(hipEventCreate(&e));
-    c->pool.push_back(e);
-  }
-  return 0;
-}
-
-int prof_read_slot(fgcg_ctx* c, fgcg_ctx::GraphSlot& sl) {
-  for (auto& p : sl.ev) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
-    c->prof_ms[p.kind] += ms;
-    c->prof_n[p.kind] += 1;
-  }
-  return 0;
-}
-
-void release_graph(fgcg_ctx* c, fgcg_ctx::CgGraph& g) {
-  for (auto& sl : g.slot) {
-    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
-    sl.exec = nullptr;
-    for (auto& p : sl.ev) {
-      c->pool.push_back(p.a);
-      c->pool.push_back(p.b);
-    }
-    sl.ev.clear();
-  }
-  g.key.clear();
-}
-
-int enter(fgcg_ctx* c) {
-  HIPCHK(hipEventRecord(c->ev_in, c->user_stream));
-  HIPCHK(hipStreamWaitEvent(c->stream, c->ev_in, 0));
-  return 0;
-}
-
-// Byte key of the values an iteration chunk was captured with.
-struct Key {
-  std::vector<char> b;
-  template <typename V> Key& add(const V& v) {
-    const char* p = reinterpret_cast<const char*>(&v);
-    b.insert(b.end(), p, p + sizeof(V));
-    return *this;
-  }
-};
-
-template <typename T> const CT<T>* tw_x(const fgcg_ctx* c) {
-  return (const CT<T>*)(std::is_same<T, double>::value ? c->twx : c->twx32);
-}
-template <typename T> const CT<T>* tw_y(const fgcg_ctx* c) {
-  return (const CT<T>*)(std::is_same<T, double>::value ? c->twy : c->twy32);
-}
-
-template <typename T> const char* tname() { return std::is_same<T, double>::value ? "double" : "float"; }
-
-void set_kname(fgcg_ctx* c, int kind, const char* fmt, const char* t, int n) {
-  if (!c->kname[kind].empty()) return;
-  char b[256];
-  snprintf(b, sizeof b, fmt, t, n);
-  c->kname[kind] = b;
-}
-
-// One launch: a plain stream launch (timed with events when its kind is
-// profiled), or, while a chunk graph is being built, a kernel node appended to
-// the chain (between two event-record nodes when profiled).
-template <typename... A>
-int launch(fgcg_ctx* c, int kind, const void* fn, dim3 grid, A... args) {
-  void* ptrs[] = {(void*)&args...};
-  const bool prof = kind >= 0 && (c->prof_mask & (1u << kind)) && (!c->building || c->build_timed);
-  if (!c->building) {
-    int rc = prof ? prof_begin(c, kind) : 0;
-    if (rc) return rc;
-    HIPCHK(hipLaunchKernel(fn, grid, dim3(NT), ptrs, 0, c->stream));
-    return prof ? prof_end(c, kind) : 0;
-  }
-  hipEvent_t ea = nullptr, eb = nullptr;
-  if (prof) {
-    ea = c->pool.back();
-    c->pool.pop_back();
-    eb = c->pool.back();
-    c->pool.pop_back();
-    hipGraphNode_t n;
-    HIPCHK(hipGraphAddEventRecordNode(&n, c->graph, c->last ? &c->last : nullptr, c->last ? 1 : 0, ea));
-    c->last = n;
-  }
-  hipKernelNodeParams kp{};
-  kp.func = const_cast<void*>(fn);
-  kp.gridDim = grid;
-  kp.blockDim = dim3(NT);
-  kp.sharedMemBytes = 0;
-  kp.kernelParams = ptrs;
-  kp.extra = nullptr;
-  hipGraphNode_t kn;
-  HIPCHK(hipGraphAddKernelNode(&kn, c->graph, c->last ? &c->last : nullptr, c->last ? 1 : 0, &kp));
-  c->last = kn;
-  if (prof) {
-    hipGraphNode_t n;
-    HIPCHK(hipGraphAddEventRecordNode(&n, c->graph, &c->last, 1, eb));
-    c->last = n;
-    c->pending.push_back({kind, ea, eb});
-  }
-  return 0;
-}
-
-template <typename T, int NOUT, class Pro>
-int launch_row_fwd(fgcg_ctx* c, int kind, const Pro& pro, CT<T>* spec, int nsamp = 1, long long ss = 0) {
-  int rc = 0;
-  with_n(c->nx, [&](auto NXc) {
-    constexpr int NX = decltype(NXc)::value;
-    constexpr int R = rows_for(NX);
-    dim3 g((c->ny + R - 1) / R, nsamp);
-    if (kind >= 0) set_kname(c, kind, "k_row_fwd<%s, %d", tname<T>(), NX);
-    rc = launch(c, kind, (const void*)&k_row_fwd<T, NX, NOUT, Pro>, g, pro, spec, c->ny, ss,
-                tw_x<T>(c));
-  });
-  return rc;
-}
-
-template <typename T, int NIN, int NOUT, class Sym>
-int launch_col(fgcg_ctx* c, int kind, const Sym& sym, const CT<T>* in, CT<T>* out, int nsamp = 1,
-               long long ss = 0) {
-  int rc = 0;
-  with_n(c->ny, [&](auto NYc) {
-    constexpr int NY = decltype(NYc)::value;
-    dim3 g(c->nxh, nsamp);
-    if (kind >= 0) set_kname(c, kind, "k_col<%s, %d", tname<T>(), NY);
-    rc = launch(c, kind, (const void*)&k_col<T, NY, NIN, NOUT, Sym>, g, sym, in, out, c->nxh, ss, ss,
-                tw_y<T>(c));
-  });
-  return rc;
-}
-
-template <typename T, int NIN, class Epi>
-int launch_row_inv(fgcg_ctx* c, int kind, const Epi& epi, const CT<T>* spec, int nsamp = 1,
-                   long long ss = 0) {
-  int rc = 0;
-  with_n(c->nx, [&](auto NXc) {
-    constexpr int NX = decltype(NXc)::value;
-    constexpr int R = rows_for(NX);
-    dim3 g((c->ny + R - 1) / R, nsamp);
-    if (kind >= 0) set_kname(c, kind, "k_row_inv<%s, %d", tname<T>(), NX);
-    rc = launch(c, kind, (const void*)&k_row_inv<T, NX, NIN, Epi>, g, epi, spec, c->ny, ss,
-                tw_x<T>(c));
-  });
-  return rc;
-}
-
-template <typename T, int NIN, int NOUT, class Mid>
-int launch_row_mid(fgcg_ctx* c, int kind, const Mid& mid, CT<T>* spec, int nsamp = 1, long long ss = 0) {
-  int rc = 0;
-  with_n(c->nx, [&](auto NXc) {
-    constexpr int NX = decltype(NXc)::value;
-    constexpr int R = rows_for(NX);
-    dim3 g((c->ny + R - 1) / R, nsamp);
-    if (kind >= 0) set_kname(c, kind, "k_row_mid<%s, %d", tname<T>(), NX);
-    rc = launch(c, kind, (const void*)&k_row_mid<T, NX, NIN, NOUT, Mid>, g, mid, spec, c->ny, ss,
-                tw_x<T>(c));
-  });
-  return rc;
-}
-
-// CG drivers.  Every pass exits at once when the device state says the
-// solve has ended, so chunks of iterations can be enqueued blindly and the
-// host reads the state once per chunk.
-//
-// Graph mode (default): a chunk of K iterations is built once into two graph
-// instances (rebuilt only when the values the kernels were given change); the
-// instances are replayed alternately so that one is always queued while the
-// host checks the state left by the other.  Event-record nodes around the
-// profiled kernel nodes of the first instance time those launches inside the
-// graph (an event node costs about 10 us of idle time, so the second instance
-// carries none and profiling samples every other chunk).
-template <class S, class F> int run_cg_plain(fgcg_ctx* c, S* dst, S* hst, F&& iter, int maxit) {
-  long long k = 0;
-  int chunk = 2;
-  for (;;) {
-    HIPCHK(hipMemcpyAsync(hst, dst, sizeof(S), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    int rc = prof_flush(c);
-    if (rc) return rc;
-    if (hst->done) return 0;
-    if (k > (long long)maxit + 1) return fail(FGCG_EHIP, "CG driver overran the iteration limit");
-    for (int j = 0; j < chunk; ++j, ++k) {
-      rc = iter();
-      if (rc) return rc;
-    }
-    HIPCHK(hipGetLastError());
-    chunk = chunk < 32 ? chunk * 2 : 32;
-  }
-}
-
-template <class F> int build_chunk(fgcg_ctx* c, fgcg_ctx::GraphSlot& sl, F& iter, int K, bool timed) {
-  c->pending.clear();
-  HIPCHK(hipGraphCreate(&c->graph, 0));
-  c->building = true;
-  c->build_timed = timed;
-  c->last = nullptr;
-  int rc = 0;
-  for (int j = 0; j < K && !rc; ++j) rc = iter();
-  c->building = false;
-  hipGraph_t g = c->graph;
-  c->graph = nullptr;
-  if (!rc) {
-    const hipError_t ei = hipGraphInstantiate(&sl.exec, g, nullptr, nullptr, 0);
-    if (ei != hipSuccess) rc = fail(FGCG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
-  }
-  (void)hipGraphDestroy(g);
-  sl.ev.swap(c->pending);
-  c->pending.clear();
-  return rc;
-}
-
-template <class S, class F>
-int run_cg(fgcg_ctx* c, int which, const Key& key, S* dst, S* hs, F&& iter, int maxit, int K = 0) {
-  if (!c->use_graphs) return run_cg_plain(c, dst, hs, iter, maxit);
-  if (K <= 0) K = c->chunk;
-  HIPCHK(hipMemcpyAsync(hs, dst, sizeof(S), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  int rc = prof_flush(c);
-  if (rc) return rc;
-  if (hs->done) return 0;
-  fgcg_ctx::CgGraph& G = c->graphs[which];
-  Key full = key;
-  full.add(c->prof_mask).add(K);
-  if (G.key != full.b || !G.slot[0].exec || !G.slot[1].exec) {
-    release_graph(c, G);
-    if ((rc = prof_reserve(c, 4 * (size_t)K * FGCG_K_NKINDS))) return rc;
-    for (int i = 0; i < 2; ++i)
-      if ((rc = build_chunk(c, G.slot[i], iter, K, i == 0))) return rc;
-    G.key = full.b;
-  }
-  long long launched = 0;
-  auto go = [&](int i) -> int {
-    HIPCHK(hipGraphLaunch(G.slot[i].exec, c->stream));
-    HIPCHK(hipMemcpyAsync(hs + i, dst, sizeof(S), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipEventRecord(c->ev_done[i], c->stream));
-    launched += K;
-    return 0;
-  };
-  if ((rc = go(0)) || (rc = go(1))) return rc;
-  int i = 0;
-  for (;;) {
-    HIPCHK(hipEventSynchronize(c->ev_done[i]));
-    if ((rc = prof_read_slot(c, G.slot[i]))) return rc;
-    if (hs[i].done) break;
-    if (launched > (long long)maxit + 4LL * K) return fail(FGCG_EHIP, "CG driver overran the iteration limit");
-    if ((rc = go(i))) return rc;
-    i ^= 1;
-  }
-  HIPCHK(hipStreamSynchronize(c->stream));
-  if ((rc = prof_read_slot(c, G.slot[i ^ 1]))) return rc;
-  if (i != 0) hs[0] = hs[i];
-  return 0;
-}
-
-template <class S> int status_of(const S& s) {
-  switch (s.done) {
-    case 1: return FGCG_OK;
-    case 2: return FGCG_NOT_CONVERGED;
-    case 3: return FGCG_EBREAKDOWN;
-    case 4: return FGCG_EDOMAIN;
-    default: return FGCG_EHIP;
-  }
-}
-
-template <class S> void fill_info(fgcg_info* info, const S& s, double secs) {
-  if (!info) return;
-  info->iters = s.iter;
-  info->status = status_of(s);
-  info->bnorm = std::sqrt(s.bnorm2);
-  info->rel_res = s.bnorm2 > 0 ? std::sqrt(s.rr_final / s.bnorm2) : 0.0;
-  info->seconds = secs;
-}
-
-double now() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-int make_mech_mat(const fgcg_ctx* c, const fgcg_material* mat, const double* d, double kappa, MechMat* m) {
-  if (!mat) return fail(FGCG_EINVAL, "material is NULL");
-  std::memset(m, 0, sizeof *m);
-  m->d = d;
-  m->kappa = kappa;
-  m->ss = c->n;
-  if (!(kappa >= 0.0) || !std::isfinite(kappa)) return fail(FGCG_EDOMAIN, "kappa must be finite and >= 0");
-  if (mat->E_field) {
-    const double nu = mat->nu_field;
-    if (!(nu > -1.0 && nu < 0.5)) return fail(FGCG_EDOMAIN, "nu_field outside (-1, 0.5)");
-    m->Efield = mat->E_field;
-    m->lam_per_E = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-    m->mu_per_E = 1.0 / (2.0 * (1.0 + nu));
-    return 0;
-  }
-  if (!mat->phase || !mat->E_tab || !mat->nu_tab) return fail(FGCG_EINVAL, "phase/E_tab/nu_tab is NULL");
-  if (mat->nphase < 1 || mat->nphase > FGCG_MAX_PHASES) return fail(FGCG_EINVAL, "nphase outside 1..8");
-  m->phase = mat->phase;
-  for (int i = 0; i < mat->nphase; ++i) {
-    const double E = mat->E_tab[i], nu = mat->nu_tab[i];
-    if (!(E > 0.0) || !std::isfinite(E)) return fail(FGCG_EDOMAIN, "E <= 0 or not finite");
-    if (!(nu > -1.0 && nu < 0.5)) return fail(FGCG_EDOMAIN, "nu outside (-1, 0.5)");
-    m->lm.a[i] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-    m->lm.b[i] = E / (2.0 * (1.0 + nu));
-  }
-  return 0;
-}
-
-int check_solver_args(double tol, int maxit) {
-  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(FGCG_EINVAL, "tol must be finite and >= 0");
-  if (maxit < 0) return fail(FGCG_EINVAL, "maxit < 0");
-  return 0;
-}
 
 // ----------------------------------------------------------------- mech
 // ---------------------------------------------------------- mechanics
@@ -841,7 +367,7 @@ int scg_solve(fgcg_ctx* c, int which, const Key& key, const Op& op, const double
   int parity = 0;     // iteration k reads P[k & 1] and writes P[(k + 1) & 1]
   const int nsb = (int)(c->sgrid.x * c->sgrid.y);
   hipLaunchKernelGGL((k_scg_init<T, Op>), c->sgrid, dim3(NT), 0, c->stream, op, xin, bscale, bsrc, band, c_dir, X,
-                     R, c->nx, c->ny, c->part_b, c->part_rr);
+                     R, c->nx, c->ny, c->nz, c->part_b, c->part_rr);
   hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_b, nsb, 0, tol, maxit);
   HIPCHK(hipGetLastError());
   const CgCtl cc{c->st, c->part_a, c->part_rr, nsb, nsb, 0, 0};
@@ -852,9 +378,9 @@ int scg_solve(fgcg_ctx* c, int which, const Key& key, const Op& op, const double
     T* pout = parity ? P0 : P1;
     parity ^= 1;
     int r = launch(c, kind_dir, (const void*)&k_scg_dir<T, Op>, c->sgrid, op, (const T*)R, (const T*)pin, pout, Q,
-                   c->nx, c->ny, band, cc);
+                   c->nx, c->ny, c->nz, band, cc);
     r |= launch(c, kind_upd, (const void*)&k_scg_upd<T>, c->sgrid, X, R, (const T*)pout, (const T*)Q, c->nx,
-                c->ny, cc);
+                c->rows, cc);
     return r;
   };
   int rc = run_cg(c, which, key, c->st, c->h_st, iter, maxit);
@@ -885,7 +411,7 @@ template <typename T>
 int diff_step_stencil(fgcg_ctx* c, const DiffCoef& co, double c_dir, double* cfield, double tol, int maxit,
                       fgcg_info* info) {
   const double t0 = now();
-  const DiffStencil op{co, co.phase, c->nx, 1.0 / (c->h * c->h)};
+  const DiffStencil op{co, co.phase, 1.0 / (c->h * c->h)};
   Key key;
   key.add(co.phase).add(co.dk).add(co.inv_dt).add(co.band).add(op.ih2);
   CgState s;
@@ -919,7 +445,7 @@ template <typename T> int alloc_workspace(fgcg_ctx* c) {
   HIPCHK(hipMalloc(&c->r, nr));
   HIPCHK(hipMalloc(&c->p, nr));
   HIPCHK(hipMalloc(&c->tmp, nr));
-  HIPCHK(hipMalloc(&c->spec, sizeof(CT<T>) * 4 * (size_t)c->nxh * c->ny * ns));
+  HIPCHK(hipMalloc(&c->spec, sizeof(CT<T>) * 4 * (size_t)c->nxh * c->rows * ns));
   HIPCHK(hipMalloc(&c->ems, sizeof(double) * 3 * ns));
   if (c->batch) {
     HIPCHK(hipMalloc(&c->phase_buf, (size_t)c->n * ns));
@@ -929,9 +455,10 @@ template <typename T> int alloc_workspace(fgcg_ctx* c) {
   if ((rc = make_twiddles<double>(c->nx, &c->twx)) || (rc = make_twiddles<double>(c->ny, &c->twy))) return rc;
   if (c->prec == FGCG_FP32_MIXED) {
     if ((rc = make_twiddles<float>(c->nx, &c->twx32)) || (rc = make_twiddles<float>(c->ny, &c->twy32))) return rc;
-    HIPCHK(hipMalloc(&c->xh, sizeof(double) * 2 * (size_t)c->n * ns));
-    HIPCHK(hipMalloc(&c->fh, sizeof(double) * 2 * (size_t)c->n * ns));
-  } else if (ns == 1) {
+    const size_t nu = c->ndim == 3 ? 3 : 2;  // displacement components
+    HIPCHK(hipMalloc(&c->xh, sizeof(double) * nu * (size_t)c->n * ns));
+    HIPCHK(hipMalloc(&c->fh, sizeof(double) * nu * (size_t)c->n * ns));
+  } else if (ns == 1 && c->ndim == 2) {
     HIPCHK(hipMalloc(&c->aux, sizeof(double) * 6 * (size_t)c->n));
   }
   return 0;
@@ -967,17 +494,24 @@ int fgcg_create(const fgcg_grid* grid, void* hip_stream, fgcg_ctx** out) {
 static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool batch, fgcg_ctx** out) {
   if (!grid || !out) return fail(FGCG_EINVAL, "grid/out is NULL");
   *out = nullptr;
-  if (grid->ndim != 2) return fail(FGCG_EUNSUPPORTED, "only 2D grids are built");
+  if (grid->ndim != 2 && grid->ndim != 3) return fail(FGCG_EINVAL, "ndim must be 2 or 3");
+  if (grid->ndim == 3 && (nsamp != 1 || batch)) return fail(FGCG_EUNSUPPORTED, "batches are 2D");
   if (!(grid->h > 0.0) || !std::isfinite(grid->h)) return fail(FGCG_EDOMAIN, "h <= 0");
-  if (!size_supported(grid->n[0]) || !size_supported(grid->n[1]))
+  if (grid->ndim == 2 && (!size_supported(grid->n[0]) || !size_supported(grid->n[1])))
     return fail(FGCG_EINVAL, "axis length must be one of 8..2048 of the form 2^a 3^b");
+  if (grid->ndim == 3 &&
+      (!size3_supported(grid->n[0]) || !size3_supported(grid->n[1]) || !size3_supported(grid->n[2])))
+    return fail(FGCG_EINVAL, "3D axis length must be one of 8..512 of the form 2^a 3^b");
   if (grid->precision != FGCG_FP64 && grid->precision != FGCG_FP32_MIXED)
     return fail(FGCG_EINVAL, "unknown precision");
   fgcg_ctx* c = new fgcg_ctx();
+  c->ndim = grid->ndim;
   c->nx = grid->n[0];
   c->ny = grid->n[1];
+  c->nz = grid->ndim == 3 ? grid->n[2] : 1;
+  c->rows = c->ny * c->nz;
   c->nxh = c->nx / 2 + 1;
-  c->n = (long long)c->nx * c->ny;
+  c->n = (long long)c->nx * c->rows;
   c->h = grid->h;
   c->prec = grid->precision;
   c->nsamp = nsamp;
@@ -989,7 +523,7 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
   }
   with_n(c->nx, [&](auto NXc) {
     constexpr int R = rows_for(decltype(NXc)::value);
-    c->nrow = (c->ny + R - 1) / R;
+    c->nrow = (c->rows + R - 1) / R;
   });
   c->ncol = c->nxh;
   c->npost = (int)std::min<long long>((c->n + PT - 1) / PT, 1024);
@@ -1009,17 +543,19 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
     const size_t ns = (size_t)nsamp;
     chk(hipMalloc(&c->st, sizeof(CgState) * ns));
     chk(hipHostMalloc(&c->h_st, sizeof(CgState) * 2 * ns, hipHostMallocDefault));
-    const int npa = std::max(std::max(c->nrow + std::max(c->ncol, c->nrow), c->nkp), 512);
+    const int npa = std::max(std::max(c->nrow + std::max(c->ncol, c->nrow), c->nkp), 1024);
     chk(hipMalloc(&c->part_a, sizeof(double) * npa * ns));
     chk(hipMalloc(&c->part_rr, sizeof(double) * std::max(std::max(c->nrow, c->ncol), 512) * ns));
     chk(hipMalloc(&c->part_b, sizeof(double) * std::max(std::max(c->nrow, c->npost), 512)));
-    chk(hipMalloc(&c->part_post, sizeof(double) * 5 * c->npost * ns));
+    // post-processing partials: 4-5 per block (2D), 7 per stencil block (3D, at most 1024 blocks)
+    const size_t npp = std::max<size_t>(5 * (size_t)c->npost * ns, 7 * 1024);
+    chk(hipMalloc(&c->part_post, sizeof(double) * npp));
     {
       const int bx = (c->nx + NT - 1) / NT;
-      const int by = std::max(1, std::min(c->ny, 512 / bx));
+      const int by = std::max(1, std::min(c->rows, 512 / bx));
       c->sgrid = dim3(bx, by);
     }
-    chk(hipHostMalloc(&c->h_part, sizeof(double) * 5 * c->npost * ns, hipHostMallocDefault));
+    chk(hipHostMalloc(&c->h_part, sizeof(double) * npp, hipHostMallocDefault));
   }
   if (!rc) {
     // forward-difference symbols D(k) = (exp(i theta) - 1)/h = (-2 sin^2(theta/2) + i sin theta)/h
@@ -1035,6 +571,7 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
     chk(hipMemcpy(c->Dx, dx.data(), sizeof(double2) * c->nxh, hipMemcpyHostToDevice));
     chk(hipMemcpy(c->Dy, dy.data(), sizeof(double2) * c->ny, hipMemcpyHostToDevice));
   }
+  if (!rc && c->ndim == 3) rc = alloc3d(c);
   if (rc) {
     fgcg_destroy(c);
     return rc;
@@ -1045,8 +582,10 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
 
 void fgcg_destroy(fgcg_ctx* c) {
   if (!c) return;
-  void* dev[] = {c->ems, c->phase_buf, c->strain_buf, c->twx, c->twy, c->twx32, c->twy32, c->xh, c->fh, c->aux, c->Dx, c->Dy, c->x, c->r, c->p, c->tmp, c->spec, c->st,
-                 c->part_a, c->part_rr, c->part_b, c->part_post};
+  void* dev[] = {c->ems,  c->phase_buf, c->strain_buf, c->twx,    c->twy,    c->twx32,  c->twy32, c->twz,
+                 c->twz32, c->Dz,       c->red,        c->part_z, c->xh,     c->fh,     c->aux,   c->Dx,
+                 c->Dy,   c->x,         c->r,          c->p,      c->tmp,    c->spec,   c->st,    c->part_a,
+                 c->part_rr, c->part_b, c->part_post};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (c->h_st) (void)hipHostFree(c->h_st);
@@ -1095,11 +634,16 @@ int fgcg_mech_solve(fgcg_ctx* c, const fgcg_material* mat, const double* d, doub
   if (!c || !eps_mac || !strain) return fail(FGCG_EINVAL, "ctx/eps_mac/strain is NULL");
   int rc;
   if ((rc = check_solver_args(tol, maxit))) return rc;
-  for (int j = 0; j < 3; ++j)
+  const int ns = c->ndim == 3 ? 6 : 3;
+  for (int j = 0; j < ns; ++j)
     if (!std::isfinite(eps_mac[j])) return fail(FGCG_EDOMAIN, "eps_mac not finite");
   MechMat m;
   if ((rc = make_mech_mat(c, mat, d, kappa, &m))) return rc;
   if ((rc = enter(c))) return rc;
+  if (c->ndim == 3) {
+    if (m.Efield) return fail(FGCG_EUNSUPPORTED, "per-voxel E fields are 2D only");
+    return mech3_solve(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
+  }
   return mech_solve_single(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
 }
 
@@ -1108,6 +652,7 @@ int fgcg_mech_adjoint(fgcg_ctx* c, const fgcg_material* mat, const double* d, do
                       double* grad_E, double* J, fgcg_info* info_fwd, fgcg_info* info_adj) {
   if (!c || !eps_mac || !grad_E) return fail(FGCG_EINVAL, "ctx/eps_mac/grad_E is NULL");
   if (c->prec != FGCG_FP64) return fail(FGCG_EUNSUPPORTED, "the adjoint runs in FP64 contexts");
+  if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "the adjoint is 2D only");
   if (objective != ADJ_USER && objective != ADJ_ENERGY && objective != ADJ_C11)
     return fail(FGCG_EINVAL, "unknown objective");
   if (objective == ADJ_USER && !dJ_dstrain) return fail(FGCG_EINVAL, "dJ_dstrain is NULL");
@@ -1128,6 +673,7 @@ int fgcg_phasefield_solve(fgcg_ctx* c, const double* H, double Gc, double l0, do
   if (!(Gc > 0.0) || !std::isfinite(Gc)) return fail(FGCG_EDOMAIN, "Gc <= 0");
   if (!(l0 > 0.0) || !std::isfinite(l0)) return fail(FGCG_EDOMAIN, "l0 <= 0");
   if ((rc = enter(c))) return rc;
+  if (c->scalar_spectral && c->ndim == 3) return fail(FGCG_EUNSUPPORTED, "spectral scalar operators are 2D only");
   if (!c->scalar_spectral) return pf_solve_stencil<double>(c, H, Gc, l0, d, tol, maxit, info);
   return pf_solve_t<double>(c, H, Gc, l0, d, tol, maxit, info);
 }
@@ -1143,6 +689,7 @@ int fgcg_diffusion_step(fgcg_ctx* c, const uint8_t* phase, int nphase, const dou
   DiffCoef co;
   if ((rc = make_diff_coef(phase, nphase, D_tab, k_tab, dt, band_width, c->n, &co))) return rc;
   if ((rc = enter(c))) return rc;
+  if (c->scalar_spectral && c->ndim == 3) return fail(FGCG_EUNSUPPORTED, "spectral scalar operators are 2D only");
   if (!c->scalar_spectral) return diff_step_stencil<double>(c, co, c_dir, cfield, tol, maxit, info);
   return diff_step_t<double>(c, co, c_dir, cfield, tol, maxit, info);
 }
@@ -1170,8 +717,12 @@ int fgcg_staggered_step(fgcg_ctx* c, fgcg_state* s, const fgcg_params* p, fgcg_s
   if (rc < 0) return rc;
   MechMat m0;
   if ((rc = make_mech_mat(c, &p->mat, nullptr, 0.0, &m0))) return rc;
-  hipLaunchKernelGGL(k_history, dim3(c->npost), dim3(PT), 0, c->stream, m0, s->strain, s->e, s->H, c->n);
-  HIPCHK(hipGetLastError());
+  if (c->ndim == 3) {
+    if ((rc = history3(c, m0, s->strain, s->e, s->H))) return rc;
+  } else {
+    hipLaunchKernelGGL(k_history, dim3(c->npost), dim3(PT), 0, c->stream, m0, s->strain, s->e, s->H, c->n);
+    HIPCHK(hipGetLastError());
+  }
   rc = fgcg_phasefield_solve(c, s->H, p->Gc, p->l0, s->d, p->tol_pf, p->maxit, &info->pf);
   if (rc < 0) return rc;
   hipLaunchKernelGGL(k_observe, dim3(c->npost), dim3(PT), 0, c->stream, p->mat.phase, s->d, s->f, c->n,
@@ -1202,6 +753,7 @@ int fgcg_staggered_step(fgcg_ctx* c, fgcg_state* s, const fgcg_params* p, fgcg_s
 int fgcg_mech_apply(fgcg_ctx* c, const fgcg_material* mat, const double* d, double kappa, const double* p,
                     double* q) {
   if (!c || !p || !q) return fail(FGCG_EINVAL, "ctx/p/q is NULL");
+  if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "the apply hooks are 2D only");
   MechMat m;
   int rc;
   if ((rc = make_mech_mat(c, mat, d, kappa, &m))) return rc;
@@ -1220,6 +772,7 @@ int fgcg_mech_apply(fgcg_ctx* c, const fgcg_material* mat, const double* d, doub
 
 int fgcg_phasefield_apply(fgcg_ctx* c, const double* H, double Gc, double l0, const double* v, double* q) {
   if (!c || !H || !v || !q) return fail(FGCG_EINVAL, "ctx/H/v/q is NULL");
+  if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "the apply hooks are 2D only");
   if (!(Gc > 0.0) || !(l0 > 0.0)) return fail(FGCG_EDOMAIN, "Gc/l0 <= 0");
   CT<double>* spec = (CT<double>*)c->spec;
   int rc;
@@ -1238,6 +791,7 @@ int fgcg_phasefield_apply(fgcg_ctx* c, const double* H, double Gc, double l0, co
 int fgcg_diffusion_apply(fgcg_ctx* c, const uint8_t* phase, int nphase, const double* D_tab, const double* k_tab,
                          double dt, const double* v, double* q) {
   if (!c || !v || !q) return fail(FGCG_EINVAL, "ctx/v/q is NULL");
+  if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "the apply hooks are 2D only");
   DiffCoef co;
   int rc;
   if ((rc = make_diff_coef(phase, nphase, D_tab, k_tab, dt, 0, c->n, &co))) return rc;
@@ -1251,6 +805,14 @@ int fgcg_diffusion_apply(fgcg_ctx* c, const uint8_t* phase, int nphase, const do
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   return FGCG_OK;
+}
+
+int fgcg_debug_fft(fgcg_ctx* c, int dir, const double* in, double* out) {
+  if (!c || !in || !out) return fail(FGCG_EINVAL, "ctx/in/out is NULL");
+  if (dir == 0) return fail(FGCG_EINVAL, "dir must be nonzero");
+  int rc;
+  if ((rc = enter(c))) return rc;
+  return debug_fft(c, dir, in, out);
 }
 
 int fgcg_profile(fgcg_ctx* c, unsigned mask) {

@@ -1,0 +1,292 @@
+// 3D grids: workspace, the y/z transform passes, the mechanics PCG in
+// displacement form (FP64 and FP32-mixed with reliable updates), the 3D
+// history update and the transform test hook.  The phase-field and diffusion
+// solves use the stencil CG of the 2D engine, which handles both.
+#include "engine.hpp"
+#include "mech3.hpp"
+#include "passes3d.hpp"
+
+namespace fgcg {
+
+namespace {
+
+// Axis lengths of 3D grids.
+#define FGCG_SIZES3(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+
+template <class F> bool with_n3(int n, F&& f) {
+  switch (n) {
+#define FGCG_CASE3(N)                      \
+  case N:                                  \
+    f(std::integral_constant<int, N>{});   \
+    return true;
+    FGCG_SIZES3(FGCG_CASE3)
+#undef FGCG_CASE3
+    default:
+      return false;
+  }
+}
+
+constexpr int RELIABLE_EVERY3 = 10;  // FP32-mixed: true residual every tenth iteration
+
+template <typename T> const CT<T>* tw_z(const fgcg_ctx* c) {
+  return (const CT<T>*)(std::is_same<T, double>::value ? c->twz : c->twz32);
+}
+
+Grid3 grid3(const fgcg_ctx* c) { return Grid3{c->nx, c->ny, c->nz, c->n}; }
+
+// Blocks of the slab-walking stencil kernels: a multiple of 8, at most 1024.
+int nslab(const fgcg_ctx* c) {
+  const int rows = c->ny * c->nz;
+  return std::max(8, std::min(1024, rows) & ~7);
+}
+
+int ztiles(const fgcg_ctx* c) {
+  int nty = 0;
+  with_n3(c->nz, [&](auto NZc) {
+    constexpr int YT = ztile_for(decltype(NZc)::value);
+    nty = (c->ny + YT - 1) / YT;
+  });
+  return nty;
+}
+
+template <typename T, int NC>
+int launch_ypass(fgcg_ctx* c, int kind, bool inv, const CgState* st, CT<T>* spec) {
+  int rc = 0;
+  const int nlines = c->nxh * c->nz;
+  with_n3(c->ny, [&](auto NYc) {
+    constexpr int NY = decltype(NYc)::value;
+    constexpr int LPB = ylines_for(NY, NC);
+    dim3 g((nlines + LPB - 1) / LPB);
+    if (kind >= 0) set_kname(c, kind, inv ? "k_ypass<%s, %d, 3, true" : "k_ypass<%s, %d, 3, false", tname<T>(), NY);
+    if (inv)
+      rc = launch(c, kind, (const void*)&k_ypass<T, NY, NC, true>, g, st, spec, nlines, tw_y<T>(c));
+    else
+      rc = launch(c, kind, (const void*)&k_ypass<T, NY, NC, false>, g, st, spec, nlines, tw_y<T>(c));
+  });
+  return rc;
+}
+
+template <typename T, bool FWD, bool INV, class Sym>
+int launch_zpass(fgcg_ctx* c, int kind, const Sym& sym, CT<T>* spec, int ncomp) {
+  int rc = 0;
+  const int nty = ztiles(c);
+  with_n3(c->nz, [&](auto NZc) {
+    constexpr int NZ = decltype(NZc)::value;
+    dim3 g(ncomp * c->nxh * nty);
+    if (kind >= 0) set_kname(c, kind, "k_zpass<%s, %d", tname<T>(), NZ);
+    rc = launch(c, kind, (const void*)&k_zpass<T, NZ, FWD, INV, Sym>, g, sym, spec, c->nxh, c->ny, tw_z<T>(c));
+  });
+  return rc;
+}
+
+int launch_reduce(fgcg_ctx* c, const double* part, int np, double* out) {
+  return launch(c, -1, (const void*)&k_reduce, dim3(1), part, np, out);
+}
+
+template <typename T> Field<T> fld3(void* p, const fgcg_ctx* c) { return Field<T>{(T*)p, c->n, 3 * c->n}; }
+
+// z = M r (the Green operator by x, y, z transforms), r.z reduced into red[1].
+template <typename T, class Pro> int green3(fgcg_ctx* c, const Pro& pro, const CgState* st, bool timed) {
+  CT<T>* spec = (CT<T>*)c->spec;
+  int r = launch_row_fwd<T, 3>(c, timed ? FGCG_K_MECH_ROW_FWD : -1, pro, spec);
+  r |= launch_ypass<T, 3>(c, timed ? FGCG_K_MECH_Y_FWD : -1, false, st, spec);
+  const Green3<T> g{c->Dx, c->Dy, c->Dz, 1.0 / (double)c->n, c->nx, st, c->part_z};
+  r |= launch_zpass<T, true, true>(c, timed ? FGCG_K_MECH_COL : -1, g, spec, 3);
+  r |= launch_reduce(c, c->part_z, c->nzb, c->red + 1);
+  r |= launch_ypass<T, 3>(c, timed ? FGCG_K_MECH_Y_INV : -1, true, st, spec);
+  return r;
+}
+
+template <typename T> int mech3_init(fgcg_ctx* c, double tol, int maxit) {
+  const CopyProN<T, 3> cp{fld3<T>(c->r, c), c->nx};
+  int r = green3<T>(c, cp, nullptr, false);
+  const MechUEpi<T, 3> e0{fld3<T>(c->p, c), c->nx, c->st, c->red + 1, 1, 1, tol, maxit};
+  r |= launch_row_inv<T, 3>(c, -1, e0, (const CT<T>*)c->spec);
+  HIPCHK(hipGetLastError());
+  return r;
+}
+
+template <typename T> int mech3_iter(fgcg_ctx* c, const MechMat& m, double tol, int maxit, bool reliable) {
+  const Field<T> X = fld3<T>(c->x, c), R = fld3<T>(c->r, c), P = fld3<T>(c->p, c), Q = fld3<T>(c->tmp, c);
+  const Grid3 g = grid3(c);
+  const int nb = nslab(c);
+  set_kname(c, FGCG_K_MECH_KP, "k_mech3_kp<%s%.0d", tname<T>(), 0);
+  int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech3_kp<T>, dim3(nb), m, (const T*)P.p, Q.p, g,
+                 (T)(1.0 / c->h), c->st, c->part_a);
+  r |= launch_reduce(c, c->part_a, nb, c->red);
+  if (!reliable) {
+    const MechUPro<T, 3> pro{X, R, P, Q, c->nx, c->st, c->red, 1};
+    r |= green3<T>(c, pro, c->st, true);
+  } else {
+    r |= launch(c, -1, (const void*)&k_mech_fold<T>, dim3(c->npost), X.p, c->xh, (const T*)P.p, 3 * c->n, c->st,
+                (const double*)c->red, 1);
+    r |= launch(c, -1, (const void*)&k_mech3_true_res<T>, dim3(nb), m, (const double*)c->xh, (const double*)c->fh,
+                R.p, g, 1.0 / c->h, (const CgState*)c->st);
+    const CopyProN<T, 3> cp{R, c->nx};
+    r |= green3<T>(c, cp, c->st, false);
+  }
+  const MechUEpi<T, 3> epi{P, c->nx, c->st, c->red + 1, 1, 0, tol, maxit};
+  r |= launch_row_inv<T, 3>(c, FGCG_K_MECH_ROW_INV, epi, (const CT<T>*)c->spec);
+  return r;
+}
+
+struct Mech3IterFn {
+  fgcg_ctx* c;
+  MechMat m;
+  double tol;
+  int maxit;
+  int j = 0;
+  int operator()() {
+    if (c->prec == FGCG_FP64) return mech3_iter<double>(c, m, tol, maxit, false);
+    const bool rel = j == RELIABLE_EVERY3 - 1;
+    j = rel ? 0 : j + 1;
+    return mech3_iter<float>(c, m, tol, maxit, rel);
+  }
+};
+
+}  // namespace
+
+bool size3_supported(int n) {
+  return with_n3(n, [](auto) {});
+}
+
+int alloc3d(fgcg_ctx* c) {
+  auto tw = [&](int n, bool f32, void** out) -> int {
+    if (f32) {
+      std::vector<float2> t(n);
+      for (int k = 0; k < n; ++k) {
+        const double th = 2.0 * M_PI * (double)k / (double)n;
+        t[k] = float2{(float)std::cos(th), (float)-std::sin(th)};
+      }
+      HIPCHK(hipMalloc(out, sizeof(float2) * n));
+      HIPCHK(hipMemcpy(*out, t.data(), sizeof(float2) * n, hipMemcpyHostToDevice));
+    } else {
+      std::vector<double2> t(n);
+      for (int k = 0; k < n; ++k) {
+        const double th = 2.0 * M_PI * (double)k / (double)n;
+        t[k] = double2{std::cos(th), -std::sin(th)};
+      }
+      HIPCHK(hipMalloc(out, sizeof(double2) * n));
+      HIPCHK(hipMemcpy(*out, t.data(), sizeof(double2) * n, hipMemcpyHostToDevice));
+    }
+    return 0;
+  };
+  int rc;
+  if ((rc = tw(c->nz, false, &c->twz))) return rc;
+  if (c->prec == FGCG_FP32_MIXED && (rc = tw(c->nz, true, &c->twz32))) return rc;
+  std::vector<double2> dz(c->nz);
+  for (int k = 0; k < c->nz; ++k) {
+    const double th = 2.0 * M_PI * k / c->nz, sh = std::sin(0.5 * th);
+    dz[k] = double2{-2.0 * sh * sh / c->h, std::sin(th) / c->h};
+  }
+  HIPCHK(hipMalloc(&c->Dz, sizeof(double2) * c->nz));
+  HIPCHK(hipMemcpy(c->Dz, dz.data(), sizeof(double2) * c->nz, hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc(&c->red, sizeof(double) * 8));
+  HIPCHK(hipMemset(c->red, 0, sizeof(double) * 8));
+  c->nzb = 3 * c->nxh * ztiles(c);
+  HIPCHK(hipMalloc(&c->part_z, sizeof(double) * c->nzb));
+  c->nslab = nslab(c);
+  return 0;
+}
+
+int mech3_solve(fgcg_ctx* c, const MechMat& m, const double* eig, const double* em, double tol, int maxit,
+                double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
+  const double t0 = now();
+  const Grid3 g = grid3(c);
+  const int nb = nslab(c);
+  Em6 e6;
+  for (int j = 0; j < 6; ++j) e6.v[j] = em[j];
+  // right-hand side f = -grad^H g C : (eps_mac - e I), x = 0
+  if (c->prec == FGCG_FP64) {
+    hipLaunchKernelGGL((k_mech3_rhs<double>), dim3(nb), dim3(NT), 0, c->stream, m, eig, e6, (double*)c->r,
+                       (double*)c->x, g, 1.0 / c->h);
+  } else {
+    hipLaunchKernelGGL((k_mech3_rhs<double>), dim3(nb), dim3(NT), 0, c->stream, m, eig, e6, c->fh, c->xh, g,
+                       1.0 / c->h);
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(c->npost), dim3(PT), 0, c->stream, (float*)c->r,
+                       (const double*)c->fh, 3 * c->n);
+    HIPCHK(hipMemsetAsync(c->x, 0, sizeof(float) * 3 * c->n, c->stream));
+  }
+  HIPCHK(hipGetLastError());
+  int rc = c->prec == FGCG_FP64 ? mech3_init<double>(c, tol, maxit) : mech3_init<float>(c, tol, maxit);
+  if (rc) return rc;
+  Mech3IterFn it{c, m, tol, maxit};
+  const int K = c->prec == FGCG_FP64 ? c->chunk : 2 * RELIABLE_EVERY3;
+  Key key;
+  key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm).add(c->prec);
+  key.add(tol).add(maxit);
+  if ((rc = run_cg(c, c->prec == FGCG_FP64 ? 0 : 5, key, c->st, c->h_st, it, maxit, K))) return rc;
+  const CgState s = *c->h_st;
+  const double* u = (const double*)c->x;
+  if (c->prec != FGCG_FP64) {
+    hipLaunchKernelGGL((k_fold_final<float>), dim3(c->npost), dim3(PT), 0, c->stream, (const float*)c->x, c->xh,
+                       3 * c->n);
+    u = c->xh;
+  }
+  hipLaunchKernelGGL(k_mech3_post, dim3(nb), dim3(NT), 0, c->stream, m, u, g, 1.0 / c->h, eig, e6, strain, stress,
+                     c->part_post);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->h_part, c->part_post, sizeof(double) * 7 * nb, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < nb; ++b)
+    for (int j = 0; j < 7; ++j) acc[j] += c->h_part[7 * b + j];
+  if (mean_stress)
+    for (int j = 0; j < 6; ++j) mean_stress[j] = acc[j] / (double)c->n;
+  if (energy) *energy = 0.5 * c->h * c->h * c->h * acc[6];
+  fill_info(info, s, now() - t0);
+  return status_of(s);
+}
+
+int history3(fgcg_ctx* c, const MechMat& m0, const double* strain, const double* e, double* H) {
+  hipLaunchKernelGGL(k_history3, dim3(c->npost), dim3(NT), 0, c->stream, m0, strain, e, H, c->n);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+// Real-input transform of one field, FP64, through the passes the solvers use.
+// dir > 0: in real [N] -> out half spectrum [nz][ny][nx/2+1] (complex,
+// unnormalised); dir < 0: the inverse with the 1/N factor.
+int debug_fft(fgcg_ctx* c, int dir, const double* in, double* out) {
+  CT<double>* spec = (CT<double>*)c->spec;
+  const long long nh = (long long)c->nxh * c->ny * c->nz;
+  const int nb = (int)std::min<long long>((nh + NT - 1) / NT, 4096);
+  int rc = 0;
+  bool ok = true;
+  auto ypass = [&](bool inv) {
+    const int nlines = c->nxh * c->nz;
+    ok &= with_n(c->ny, [&](auto NYc) {
+      constexpr int NY = decltype(NYc)::value;
+      constexpr int LPB = ylines_for(NY, 1);
+      const dim3 g((nlines + LPB - 1) / LPB);
+      if (inv)
+        rc |= launch(c, -1, (const void*)&k_ypass<double, NY, 1, true>, g, (const CgState*)nullptr, spec, nlines,
+                     tw_y<double>(c));
+      else
+        rc |= launch(c, -1, (const void*)&k_ypass<double, NY, 1, false>, g, (const CgState*)nullptr, spec, nlines,
+                     tw_y<double>(c));
+    });
+  };
+  if (dir > 0) {
+    const CopyProN<double, 1> cp{Field<double>{(double*)in, c->n, 0}, c->nx};
+    rc |= launch_row_fwd<double, 1>(c, -1, cp, spec);
+    ypass(false);
+    if (c->ndim == 3) rc |= launch_zpass<double, true, false>(c, -1, NoSym{}, spec, 1);
+    hipLaunchKernelGGL(k_spec_out, dim3(nb), dim3(NT), 0, c->stream, (const double2*)spec, (double2*)out, c->nxh,
+                       c->ny, c->nz);
+  } else {
+    hipLaunchKernelGGL(k_spec_in, dim3(nb), dim3(NT), 0, c->stream, (const double2*)in, (double2*)spec, c->nxh,
+                       c->ny, c->nz);
+    if (c->ndim == 3) rc |= launch_zpass<double, false, true>(c, -1, NoSym{}, spec, 1);
+    ypass(true);
+    const StoreEpi<double, 1> st{Field<double>{out, c->n, 0}, Field<double>{nullptr, c->n, 0},
+                                 1.0 / (double)c->n, c->nx, nullptr, 0};
+    rc |= launch_row_inv<double, 1>(c, -1, st, spec);
+  }
+  if (!ok) return fail(FGCG_EUNSUPPORTED, "axis length without a transform kernel");
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return rc;
+}
+
+}  // namespace fgcg

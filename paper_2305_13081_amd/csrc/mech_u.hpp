@@ -252,8 +252,8 @@ __global__ void __launch_bounds__(NT) k_fold_final(const T* __restrict__ xlo, do
     xhi[i] += (double)xlo[i];
 }
 
-// Forward row pass of iteration k.
-template <typename T> struct MechUPro {
+// Forward row pass of iteration k (NC displacement components).
+template <typename T, int NC = 2> struct MechUPro {
   Field<T> x, r, p, q;
   int nx;
   CgState* st;
@@ -266,7 +266,7 @@ template <typename T> struct MechUPro {
     const long long i = (long long)y * nx + xx;
     const T a = (T)sc;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < NC; ++c) {
       x.at(s, c, i) += a * p.at(s, c, i);
       const T rv = r.at(s, c, i) - a * q.at(s, c, i);
       r.at(s, c, i) = rv;
@@ -322,7 +322,7 @@ template <typename T> struct MechGreen {
 // Inverse row pass: stop test, beta, p = z + beta p.  With init set it starts
 // the solve instead: r.z of the right-hand side gives ||b||^2 and the
 // threshold, and p = z.
-template <typename T> struct MechUEpi {
+template <typename T, int NC = 2> struct MechUEpi {
   Field<T> p;
   int nx;
   CgState* st;
@@ -380,7 +380,7 @@ template <typename T> struct MechUEpi {
   __device__ void point(int s, int y, int xx, const T* z, double&, double sc) const {
     const long long i = (long long)y * nx + xx;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) p.at(s, c, i) = init ? z[c] : z[c] + (T)sc * p.at(s, c, i);
+    for (int c = 0; c < NC; ++c) p.at(s, c, i) = init ? z[c] : z[c] + (T)sc * p.at(s, c, i);
   }
   __device__ void partial(int, double) const {}
 };

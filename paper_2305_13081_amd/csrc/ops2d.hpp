@@ -4,7 +4,7 @@
 // components [F11, F12, F21, F22] with F_ij = d u_i / d x_j; stress Voigt
 // [s11, s22, s12]; sigma = g(d) (lambda tr(e) I + 2 mu e), g = (1-d)^2 + kappa
 // (Sec. 2.4); projection F_ij(k) = D_j(k) sum_l conj(D_l(k)) s_il(k) / |D(k)|^2,
-// zero at |D| = 0, with the forward-difference symbol of Sec. 2.5.
+// zero at |D| = 0, with the forward-difference symbol of Sec. 2.6.
 //
 // Phase field (Sec. 2.4, eq. crack-fft): A d = (Gc/(2 l0) + H) d
 // + (Gc l0 / 2) F^-1[|D|^2 F d].

@@ -1,0 +1,135 @@
+// Transforms along y and z of the half spectra of 3D grids.
+//
+// The x-direction passes of the 2D engine (k_row_fwd / k_row_inv) run
+// unchanged on a 3D grid taken as ny nz rows of length nx, and leave the half
+// spectra as [comp][kx][z][y] with y contiguous.  Two more passes complete the
+// transform:
+//   k_ypass : in-place transforms of the y lines (contiguous), several lines
+//             per block for short lines;
+//   k_zpass : a block loads a tile of YT consecutive ky values over all z
+//             (YT contiguous complex values per z, so the loads stay
+//             coalesced), transforms along z in LDS with a bank-conflict-free
+//             signal pitch, applies a per-mode symbol (the Green operator),
+//             transforms back and stores the tile in place.
+// A CG iteration of the 3D mechanics is then x-fwd, y-fwd, z (fwd + symbol +
+// inv), y-inv, x-inv around the real-space stencil pass.
+#pragma once
+#include "ops2d.hpp"
+
+namespace fgcg {
+
+// y lines per block: at least about 1024 complex values per block.
+constexpr int ylines_for(int ny, int nc) { return nc * ny >= 1024 ? 1 : 1024 / (nc * ny); }
+// ky values per z tile: 16 (256 contiguous bytes in FP64), 8 for long z lines.
+constexpr int ztile_for(int nz) { return nz > 256 ? 8 : 16; }
+
+// Deterministic single-block sum of np partial sums into out[0].
+__global__ void __launch_bounds__(NT) k_reduce(const double* __restrict__ part, int np, double* out) {
+  __shared__ double red[NT / 64];
+  const double t = block_sum_array(part, np, red);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+// NC spectra, lines [c][line][y] with nlines lines per component.
+// st (nullable): the whole pass is skipped once the CG solve has ended.
+template <typename T, int NY, int NC, bool INV>
+__global__ void __launch_bounds__(NT) k_ypass(const CgState* st, typename cvec<T>::type* spec, int nlines,
+                                              const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  constexpr int LPB = ylines_for(NY, NC);
+  constexpr int NS = LPB * NC;
+  __shared__ C buf[lds_size(NS * NY)];
+  if (st && !cg_running(st, 0)) return;
+  const int l0 = blockIdx.x * LPB;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < NS * NY; idx += NT) {
+    const int sig = idx / NY, y = idx - sig * NY;
+    const int c = sig / LPB, l = sig - c * LPB;
+    buf[lds(idx)] = l0 + l < nlines ? spec[((long long)c * nlines + l0 + l) * NY + y] : C{(T)0, (T)0};
+  }
+  __syncthreads();
+  fft_lds<T, NY, NS, NT, INV>(buf, tw);
+  for (int idx = tid; idx < NS * NY; idx += NT) {
+    const int sig = idx / NY, y = idx - sig * NY;
+    const int c = sig / LPB, l = sig - c * LPB;
+    if (l0 + l < nlines) spec[((long long)c * nlines + l0 + l) * NY + y] = buf[lds(idx)];
+  }
+}
+
+// Blocks: (component, kx, ky tile), tile fastest.  FWD / INV select the
+// transforms (the debug hook uses one of them alone); the symbol is applied
+// between them and may reduce one FP64 partial sum per block.
+template <typename T, int NZ, bool FWD, bool INV, class Sym>
+__global__ void __launch_bounds__(NT) k_zpass(Sym sym, typename cvec<T>::type* spec, int nxh, int ny,
+                                              const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  using Idx = PitchIdx<NZ>;
+  constexpr int YT = ztile_for(NZ);
+  __shared__ C buf[YT * pitch_for(NZ)];
+  __shared__ double red[NT / 64];
+  if (!sym.begin()) return;
+  const int nty = (ny + YT - 1) / YT;
+  const int t = blockIdx.x % nty;
+  const int ckx = blockIdx.x / nty;
+  const int kx = ckx % nxh;
+  const int ky0 = t * YT;
+  C* base = spec + (long long)ckx * NZ * ny;  // the [z][y] plane of (component, kx)
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < YT * NZ; idx += NT) {
+    const int z = idx / YT, l = idx - z * YT;
+    buf[Idx::at(l, z)] = ky0 + l < ny ? base[(long long)z * ny + ky0 + l] : C{(T)0, (T)0};
+  }
+  __syncthreads();
+  if (FWD) fft_lds<T, NZ, YT, NT, false, Idx>(buf, tw);
+  double acc = 0.0;
+  for (int idx = tid; idx < YT * NZ; idx += NT) {
+    const int l = idx / NZ, kz = idx - l * NZ;
+    if (ky0 + l < ny) {
+      C& a = buf[Idx::at(l, kz)];
+      a = sym.mode(kx, ky0 + l, kz, a, acc);
+    }
+  }
+  __syncthreads();
+  sym.partial(block_sum(acc, red));
+  if (INV) fft_lds<T, NZ, YT, NT, true, Idx>(buf, tw);
+  for (int idx = tid; idx < YT * NZ; idx += NT) {
+    const int z = idx / YT, l = idx - z * YT;
+    if (ky0 + l < ny) base[(long long)z * ny + ky0 + l] = buf[Idx::at(l, z)];
+  }
+}
+
+// Green operator of the unit reference medium on a 3D grid,
+// z_hat = r_hat / (N |D(k)|^2) (0 at k = 0), with the Parseval partial sum of
+// r.z over the half spectrum (weight 2 except on the kx = 0 and Nyquist planes).
+template <typename T> struct Green3 {
+  const double2* Dx;
+  const double2* Dy;
+  const double2* Dz;
+  double inv_n;
+  int nx;
+  const CgState* st;  // nullable
+  double* part;       // nullable; one partial per block
+  __device__ bool begin() const { return st == nullptr || cg_running(st, 0); }
+  template <typename C> __device__ C mode(int kx, int ky, int kz, C a, double& acc) const {
+    const double2 d1 = Dx[kx], d2 = Dy[ky], d3 = Dz[kz];
+    const double n2 = d1.x * d1.x + d1.y * d1.y + d2.x * d2.x + d2.y * d2.y + d3.x * d3.x + d3.y * d3.y;
+    if (n2 == 0.0) return C{(T)0, (T)0};
+    const double f = inv_n / n2;
+    const double w = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+    acc += w * f * ((double)a.x * a.x + (double)a.y * a.y);
+    const T ft = (T)f;
+    return C{a.x * ft, a.y * ft};
+  }
+  __device__ void partial(double v) const {
+    if (part && threadIdx.x == 0) part[blockIdx.x] = v;
+  }
+};
+
+// Identity symbol (the debug transforms).
+struct NoSym {
+  __device__ bool begin() const { return true; }
+  template <typename C> __device__ C mode(int, int, int, C a, double&) const { return a; }
+  __device__ void partial(double) const {}
+};
+
+}  // namespace fgcg

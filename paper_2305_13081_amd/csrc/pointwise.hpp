@@ -1,5 +1,7 @@
 // Pointwise kernels of the path (no transforms): CG set-up, post-processing,
-// precipitation/eigenstrain, history update, observables.
+// precipitation/eigenstrain, history update, observables.  The non-template
+// kernels have internal linkage: every translation unit that includes this
+// header launches its own copy.
 #pragma once
 #include "ops2d.hpp"
 
@@ -10,7 +12,7 @@ constexpr int PT = 256;
 // Sum the partial array of ||b||^2, set the CG state of sample s (one block
 // per sample).  done = 1 with zero_rhs = 1 when b = 0; done = 4 when ||b|| is
 // not finite.
-__global__ void __launch_bounds__(NT) k_cg_init(CgState* st, const double* part_b, int np,
+static __global__ void __launch_bounds__(NT) k_cg_init(CgState* st, const double* part_b, int np,
                                                 int pstride, double tol, int maxit) {
   __shared__ double red[NT / 64];
   const int s = blockIdx.x;
@@ -33,7 +35,7 @@ __global__ void __launch_bounds__(NT) k_cg_init(CgState* st, const double* part_
 }
 
 // Block partial sums of |v|^2 for a double field of n voxels.
-__global__ void __launch_bounds__(PT) k_norm2(const double* v, long long n, double* part) {
+static __global__ void __launch_bounds__(PT) k_norm2(const double* v, long long n, double* part) {
   __shared__ double red[NT / 64];
   double a = 0.0;
   for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT)
@@ -102,7 +104,7 @@ __global__ void __launch_bounds__(PT) k_mech_post(MechMat m, const T* x, long lo
 
 // Precipitation in the pores (phase 0): f = min(1, f + dt k c); e = e_per_f f.
 // With diffuse = 0 the eigenstrain follows the prescribed ramp value e_pres.
-__global__ void __launch_bounds__(PT) k_precip(const uint8_t* phase, const double* c, double* f,
+static __global__ void __launch_bounds__(PT) k_precip(const uint8_t* phase, const double* c, double* f,
                                                double* e, long long n, double dtk, double e_per_f,
                                                int diffuse, double e_pres) {
   for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT) {
@@ -119,7 +121,7 @@ __global__ void __launch_bounds__(PT) k_precip(const uint8_t* phase, const doubl
 
 // H = max(H, psi+(eps - e I)) with the undegraded Lame constants (Sec. 2.4,
 // eq. energy, 2D): psi+ = (lambda + mu)/2 <tr>_+^2 + mu dev:dev.
-__global__ void __launch_bounds__(PT) k_history(MechMat m, const double* strain, const double* e,
+static __global__ void __launch_bounds__(PT) k_history(MechMat m, const double* strain, const double* e,
                                                 double* H, long long n) {
   for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT) {
     double lam, mu;
@@ -136,7 +138,7 @@ __global__ void __launch_bounds__(PT) k_history(MechMat m, const double* strain,
 }
 
 // Observables: partial [max d, count(solid & d > 0.9), sum_solid d, sum f, count solid]
-__global__ void __launch_bounds__(PT) k_observe(const uint8_t* phase, const double* d,
+static __global__ void __launch_bounds__(PT) k_observe(const uint8_t* phase, const double* d,
                                                 const double* f, long long n, double* part) {
   __shared__ double red[NT / 64];
   __shared__ double redm[NT];

@@ -1,11 +1,12 @@
 // CG for the scalar operators of the path with the operators applied as
-// real-space stencils.
+// real-space stencils (2D and 3D grids).
 //
-// Both scalar operators are local: with the forward difference of Sec. 2.5
+// Both scalar operators are local: with the forward difference of Sec. 2.6
 // (D_a <-> (f(x + e_a) - f(x))/h) the Laplacian symbol -|D|^2 of the phase
 // field (Sec. 2.4, eq. crack-fft) is the periodic 5-point stencil, and the
 // diffusion operator grad^H D(x) grad is the 5-point flux stencil
-//     sum_a [D(x - e_a)(c(x) - c(x - e_a)) - D(x)(c(x + e_a) - c(x))] / h^2.
+//     sum_a [D(x - e_a)(c(x) - c(x - e_a)) - D(x)(c(x + e_a) - c(x))] / h^2
+// (7-point stencils on 3D grids).
 // Applying them in real space gives the same operator as the Fourier-space
 // product (up to rounding) with one pass over the data.  CG is textbook CG;
 // one iteration is two passes:
@@ -26,47 +27,71 @@ namespace fgcg {
 
 __device__ __forceinline__ int block_linear() { return blockIdx.y * gridDim.x + blockIdx.x; }
 
-// Stencil operators.  v(y, x) comes from a functor so the CG direction
-// p = r + beta p can be formed at the neighbours on the fly.
+// Neighbours of voxel (z, y, x) on the periodic grid, as linear indices
+// (row = z ny + y; nz = 1 for 2D grids).  x, xm, xp are the x coordinates of
+// the voxel and its x neighbours (the other neighbours share x).
+struct Nbr {
+  long long i, ixm, ixp, iym, iyp, izm, izp;
+  int x, xm, xp;
+  bool three;
+};
+
+__device__ __forceinline__ Nbr nbrs(int row, int x, int nx, int ny, int nz) {
+  Nbr b;
+  const int y = nz == 1 ? row : row % ny;
+  const int z = nz == 1 ? 0 : row / ny;
+  const long long rb = (long long)row * nx;
+  b.i = rb + x;
+  b.x = x;
+  b.xm = x == 0 ? nx - 1 : x - 1;
+  b.xp = x + 1 == nx ? 0 : x + 1;
+  b.ixm = rb + b.xm;
+  b.ixp = rb + b.xp;
+  const long long zb = (long long)z * ny;
+  b.iym = (zb + (y == 0 ? ny - 1 : y - 1)) * nx + x;
+  b.iyp = (zb + (y + 1 == ny ? 0 : y + 1)) * nx + x;
+  b.three = nz > 1;
+  b.izm = ((long long)(z == 0 ? nz - 1 : z - 1) * ny + y) * nx + x;
+  b.izp = ((long long)(z + 1 == nz ? 0 : z + 1) * ny + y) * nx + x;
+  return b;
+}
+
+// Stencil operators.  v(j, x) is the value at linear index j (x coordinate x)
+// from a functor, so the CG direction p = r + beta p can be formed at the
+// neighbours on the fly.
 struct PfStencil {
   const double* H;
   double a;     // Gc / (2 l0)
   double cih2;  // (Gc l0 / 2) / h^2
   template <typename V>
-  __device__ __forceinline__ double apply(long long i, double v0, const V& v, int y, int x, int xm, int xp,
-                                          int ym, int yp) const {
-    const double lap = 4.0 * v0 - v(y, xm) - v(y, xp) - v(ym, x) - v(yp, x);
-    return (a + H[i]) * v0 + cih2 * lap;
+  __device__ __forceinline__ double apply(double v0, const V& v, const Nbr& b) const {
+    double lap = (b.three ? 6.0 : 4.0) * v0 - v(b.ixm, b.xm) - v(b.ixp, b.xp) - v(b.iym, b.x) - v(b.iyp, b.x);
+    if (b.three) lap = lap - v(b.izm, b.x) - v(b.izp, b.x);
+    return (a + H[b.i]) * v0 + cih2 * lap;
   }
 };
 
 struct DiffStencil {
   DiffCoef co;
   const uint8_t* phase;
-  int nx;
   double ih2;
-  __device__ __forceinline__ double D(int y, int x) const {
+  __device__ __forceinline__ double D(long long j) const {
     double d, kr;
-    pick(co.dk, phase[(long long)y * nx + x], d, kr);
+    pick(co.dk, phase[j], d, kr);
     return d;
   }
   template <typename V>
-  __device__ __forceinline__ double apply(long long i, double v0, const V& v, int y, int x, int xm, int xp,
-                                          int ym, int yp) const {
+  __device__ __forceinline__ double apply(double v0, const V& v, const Nbr& b) const {
     double d0, kr;
-    pick(co.dk, phase[i], d0, kr);
-    const double flux = D(y, xm) * (v0 - v(y, xm)) - d0 * (v(y, xp) - v0) + D(ym, x) * (v0 - v(ym, x)) -
-                        d0 * (v(yp, x) - v0);
+    pick(co.dk, phase[b.i], d0, kr);
+    double flux = D(b.ixm) * (v0 - v(b.ixm, b.xm)) - d0 * (v(b.ixp, b.xp) - v0) + D(b.iym) * (v0 - v(b.iym, b.x)) -
+                  d0 * (v(b.iyp, b.x) - v0);
+    if (b.three) flux = flux + D(b.izm) * (v0 - v(b.izm, b.x)) - d0 * (v(b.izp, b.x) - v0);
     return (co.inv_dt + kr) * v0 + ih2 * flux;
   }
 };
 
-__device__ __forceinline__ void nbrs(int y, int x, int nx, int ny, int& xm, int& xp, int& ym, int& yp) {
-  xm = x == 0 ? nx - 1 : x - 1;
-  xp = x + 1 == nx ? 0 : x + 1;
-  ym = y == 0 ? ny - 1 : y - 1;
-  yp = y + 1 == ny ? 0 : y + 1;
-}
+// Rows (z ny + y) are distributed over blockIdx.y, x over blockIdx.x.
 
 // First pass of iteration k.  band > 0: voxels with x < band are fixed
 // (p = q = 0 there).
@@ -74,27 +99,23 @@ __device__ __forceinline__ void nbrs(int y, int x, int nx, int ny, int& xm, int&
 // from the previous p, which other threads of this launch must not overwrite.
 template <typename T, class Op>
 __global__ void __launch_bounds__(NT) k_scg_dir(Op op, const T* __restrict__ r, const T* __restrict__ pin,
-                                                T* __restrict__ pout, T* __restrict__ q, int nx, int ny, int band,
-                                                CgCtl cc) {
+                                                T* __restrict__ pout, T* __restrict__ q, int nx, int ny, int nz,
+                                                int band, CgCtl cc) {
   __shared__ double red[NT / 64];
   double beta;
   if (!cg_begin_dir(cc, 0, red, beta)) return;
   const bool first = beta == 0.0;  // beta is 0 exactly on the first iteration
   const T b = (T)beta;
-  auto pn = [&](int yy, int xx) -> double {
-    const long long j = (long long)yy * nx + xx;
-    return first ? (double)r[j] : (double)(r[j] + b * pin[j]);
-  };
+  auto pn = [&](long long j, int) -> double { return first ? (double)r[j] : (double)(r[j] + b * pin[j]); };
+  const int rows = ny * nz;
   double acc = 0.0;
-  for (int y = blockIdx.y; y < ny; y += gridDim.y) {
+  for (int row = blockIdx.y; row < rows; row += gridDim.y) {
     for (int x = blockIdx.x * NT + threadIdx.x; x < nx; x += gridDim.x * NT) {
-      const long long i = (long long)y * nx + x;
-      int xm, xp, ym, yp;
-      nbrs(y, x, nx, ny, xm, xp, ym, yp);
-      const double p0 = pn(y, x);
-      const double qv = x < band ? 0.0 : op.apply(i, p0, pn, y, x, xm, xp, ym, yp);
-      pout[i] = (T)p0;
-      q[i] = (T)qv;
+      const Nbr nb = nbrs(row, x, nx, ny, nz);
+      const double p0 = pn(nb.i, x);
+      const double qv = x < band ? 0.0 : op.apply(p0, pn, nb);
+      pout[nb.i] = (T)p0;
+      q[nb.i] = (T)qv;
       acc += p0 * qv;
     }
   }
@@ -104,13 +125,13 @@ __global__ void __launch_bounds__(NT) k_scg_dir(Op op, const T* __restrict__ r, 
 
 template <typename T>
 __global__ void __launch_bounds__(NT) k_scg_upd(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-                                                const T* __restrict__ q, int nx, int ny, CgCtl cc) {
+                                                const T* __restrict__ q, int nx, int rows, CgCtl cc) {
   __shared__ double red[NT / 64];
   double alpha;
   if (!cg_begin_step(cc, 0, red, alpha)) return;
   const T a = (T)alpha;
   double acc = 0.0;
-  for (int y = blockIdx.y; y < ny; y += gridDim.y) {
+  for (int y = blockIdx.y; y < rows; y += gridDim.y) {
     for (int xx = blockIdx.x * NT + threadIdx.x; xx < nx; xx += gridDim.x * NT) {
       const long long i = (long long)y * nx + xx;
       x[i] += a * p[i];
@@ -130,26 +151,26 @@ __global__ void __launch_bounds__(NT) k_scg_upd(T* __restrict__ x, T* __restrict
 template <typename T, class Op>
 __global__ void __launch_bounds__(NT) k_scg_init(Op op, const double* __restrict__ xin, double bscale,
                                                  const double* __restrict__ bsrc, int band, double c_dir,
-                                                 T* __restrict__ x, T* __restrict__ r, int nx, int ny,
+                                                 T* __restrict__ x, T* __restrict__ r, int nx, int ny, int nz,
                                                  double* part_b, double* part_rr) {
   __shared__ double red[NT / 64];
-  auto vt = [&](int yy, int xx) -> double { return xx < band ? c_dir : xin[(long long)yy * nx + xx]; };
-  auto vb = [&](int yy, int xx) -> double { return xx < band ? c_dir : 0.0; };
+  auto vt = [&](long long j, int xx) -> double { return xx < band ? c_dir : xin[j]; };
+  auto vb = [&](long long, int xx) -> double { return xx < band ? c_dir : 0.0; };
+  const int rows = ny * nz;
   double acc[2] = {0.0, 0.0};
-  for (int y = blockIdx.y; y < ny; y += gridDim.y) {
+  for (int row = blockIdx.y; row < rows; row += gridDim.y) {
     for (int xx = blockIdx.x * NT + threadIdx.x; xx < nx; xx += gridDim.x * NT) {
-      const long long i = (long long)y * nx + xx;
-      int xm, xp, ym, yp;
-      nbrs(y, xx, nx, ny, xm, xp, ym, yp);
+      const Nbr nb = nbrs(row, xx, nx, ny, nz);
+      const long long i = nb.i;
       if (xx < band) {
         x[i] = (T)0;
         r[i] = (T)0;
         continue;
       }
       const double b = bscale * bsrc[i];
-      const double ax = op.apply(i, vt(y, xx), vt, y, xx, xm, xp, ym, yp);
+      const double ax = op.apply(vt(i, xx), vt, nb);
       double bf = b;
-      if (band > 0) bf = b - op.apply(i, 0.0, vb, y, xx, xm, xp, ym, yp);
+      if (band > 0) bf = b - op.apply(0.0, vb, nb);
       const double res = b - ax;
       x[i] = (T)xin[i];
       r[i] = (T)res;

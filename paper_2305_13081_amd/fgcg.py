@@ -23,7 +23,7 @@ KINDS = {
     "mech_row_fwd": 0, "mech_col": 1, "mech_row_inv": 2,
     "pf_row_fwd": 3, "pf_col": 4, "pf_row_inv": 5,
     "diff_row_fwd": 6, "diff_col_grad": 7, "diff_row_mid": 8, "diff_col_div": 9, "diff_row_inv": 10,
-    "mech_kp": 11,
+    "mech_kp": 11, "mech_y_fwd": 12, "mech_y_inv": 13,
 }
 
 
@@ -62,14 +62,14 @@ class Params(ctypes.Structure):
     _fields_ = [("mat", Material), ("D_tab", ctypes.POINTER(ctypes.c_double)),
                 ("k_tab", ctypes.POINTER(ctypes.c_double)), ("band_width", ctypes.c_int), ("c_dir", ctypes.c_double),
                 ("dt", ctypes.c_double), ("e_per_f", ctypes.c_double), ("Gc", ctypes.c_double),
-                ("l0", ctypes.c_double), ("kappa", ctypes.c_double), ("eps_mac", ctypes.c_double * 3),
+                ("l0", ctypes.c_double), ("kappa", ctypes.c_double), ("eps_mac", ctypes.c_double * 6),
                 ("tol_diff", ctypes.c_double), ("tol_mech", ctypes.c_double), ("tol_pf", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("diffuse", ctypes.c_int), ("e_ramp", ctypes.c_double),
                 ("n_ramp", ctypes.c_int)]
 
 
 class StepInfo(ctypes.Structure):
-    _fields_ = [("diff", Info), ("mech", Info), ("pf", Info), ("mean_stress", ctypes.c_double * 3),
+    _fields_ = [("diff", Info), ("mech", Info), ("pf", Info), ("mean_stress", ctypes.c_double * 6),
                 ("energy", ctypes.c_double), ("max_d", ctypes.c_double), ("damaged_fraction", ctypes.c_double),
                 ("porosity_increase", ctypes.c_double), ("total_precipitate", ctypes.c_double)]
 
@@ -106,6 +106,7 @@ _SIGS = {
     "fgcg_mech_apply": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _vp]),
     "fgcg_phasefield_apply": (_ip, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]),
     "fgcg_diffusion_apply": (_ip, [_vp, _vp, _ip, _dp, _dp, ctypes.c_double, _vp, _vp]),
+    "fgcg_debug_fft": (_ip, [_vp, _ip, _vp, _vp]),
     "fgcg_profile": (_ip, [_vp, ctypes.c_uint]),
     "fgcg_profile_read": (_ip, [_vp, _ip, _dp, ctypes.POINTER(ctypes.c_longlong)]),
     "fgcg_kernel_name": (ctypes.c_char_p, [_vp, _ip]),
@@ -148,14 +149,20 @@ def _torch():
 
 class Context:
     """One fgcg context (workspace for one grid).  Fields are torch CUDA
-    tensors shaped (ny, nx) (scalars) or (comp, ny, nx)."""
+    tensors shaped (ny, nx) or (nz, ny, nx) (scalars), or with a leading
+    component axis.  nz given: a 3D grid (strain/stress with 6 components)."""
 
-    def __init__(self, nx, ny, h, precision=FP64, device=None):
+    def __init__(self, nx, ny, h, precision=FP64, device=None, nz=None):
         torch = _torch()
         self.lib = load_library()
         self.nx, self.ny, self.h = int(nx), int(ny), float(h)
+        self.nz = None if nz is None else int(nz)
+        self.ndim = 2 if nz is None else 3
+        self.shape = (self.ny, self.nx) if nz is None else (self.nz, self.ny, self.nx)
+        self.ns = 3 if nz is None else 6
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        g = Grid(2, (ctypes.c_int * 3)(self.nx, self.ny, 1), self.h, int(precision))
+        g = Grid(self.ndim, (ctypes.c_int * 3)(self.nx, self.ny, 1 if nz is None else self.nz), self.h,
+                 int(precision))
         out = _vp()
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream().cuda_stream
@@ -190,7 +197,7 @@ class Context:
             if allow_none:
                 return None
             raise FgcgError(-1, name, "required tensor is None")
-        shape = (self.ny, self.nx) if comps is None else (comps, self.ny, self.nx)
+        shape = self.shape if comps is None else (comps,) + self.shape
         if not isinstance(t, torch.Tensor):
             raise FgcgError(-1, name, "expected a torch tensor")
         if t.device != self.device:
@@ -230,14 +237,17 @@ class Context:
         m, keep = self._material(phase, E_tab, nu_tab, E_field, nu_field)
         self._t(d, "d", torch.float64, allow_none=True)
         self._t(eig, "eig", torch.float64, allow_none=True)
+        ns = self.ns
+        if len(eps_mac) != ns:
+            raise FgcgError(-1, "mech_solve", f"eps_mac needs {ns} Voigt components")
         if strain is None:
-            strain = torch.empty((3, self.ny, self.nx), dtype=torch.float64, device=self.device)
-        self._t(strain, "strain", torch.float64, comps=3)
+            strain = torch.empty((ns,) + self.shape, dtype=torch.float64, device=self.device)
+        self._t(strain, "strain", torch.float64, comps=ns)
         if want_stress and stress is None:
-            stress = torch.empty((3, self.ny, self.nx), dtype=torch.float64, device=self.device)
-        self._t(stress, "stress", torch.float64, comps=3, allow_none=True)
+            stress = torch.empty((ns,) + self.shape, dtype=torch.float64, device=self.device)
+        self._t(stress, "stress", torch.float64, comps=ns, allow_none=True)
         em = _dvec(eps_mac)
-        mean = (ctypes.c_double * 3)()
+        mean = (ctypes.c_double * ns)()
         energy = ctypes.c_double()
         info = Info()
         self._sync_stream()
@@ -298,10 +308,10 @@ class Context:
     def new_state(self, band_width=0, c_dir=1.0):
         torch = _torch()
         z = lambda *s: torch.zeros(s, dtype=torch.float64, device=self.device)
-        st = dict(c=z(self.ny, self.nx), f=z(self.ny, self.nx), e=z(self.ny, self.nx), H=z(self.ny, self.nx),
-                  d=z(self.ny, self.nx), strain=z(3, self.ny, self.nx), step=0)
+        st = dict(c=z(*self.shape), f=z(*self.shape), e=z(*self.shape), H=z(*self.shape), d=z(*self.shape),
+                  strain=z(self.ns, *self.shape), step=0)
         if band_width > 0:
-            st["c"][:, :band_width] = c_dir
+            st["c"][..., :band_width] = c_dir
         return st
 
     def staggered_step(self, state, phase, prm):
@@ -309,13 +319,14 @@ class Context:
         torch = _torch()
         for k in ("c", "f", "e", "H", "d"):
             self._t(state[k], k, torch.float64)
-        self._t(state["strain"], "strain", torch.float64, comps=3)
+        self._t(state["strain"], "strain", torch.float64, comps=self.ns)
         m, keep = self._material(phase, prm["E_tab"], prm["nu_tab"])
         Dt, kt = _dvec(prm["D_tab"]), _dvec(prm["k_tab"])
         if len(prm["D_tab"]) != m.nphase or len(prm["k_tab"]) != m.nphase:
             raise FgcgError(-1, "staggered_step", "D_tab/k_tab length must equal nphase")
         p = Params(m, Dt, kt, int(prm["band_width"]), float(prm["c_dir"]), float(prm["dt"]), float(prm["e_per_f"]),
-                   float(prm["Gc"]), float(prm["l0"]), float(prm["kappa"]), (ctypes.c_double * 3)(*prm["eps_mac"]),
+                   float(prm["Gc"]), float(prm["l0"]), float(prm["kappa"]),
+                   (ctypes.c_double * 6)(*(list(prm["eps_mac"]) + [0.0] * (6 - len(prm["eps_mac"])))),
                    float(prm["tol_diff"]), float(prm["tol_mech"]), float(prm["tol_pf"]), int(prm["maxit"]),
                    int(prm["diffuse"]), float(prm.get("e_ramp", 0.0)), int(prm.get("n_ramp", 0)))
         s = State(*[_vp(state[k].data_ptr()) for k in ("c", "f", "e", "H", "d", "strain")], int(state["step"]))
@@ -325,9 +336,29 @@ class Context:
         _check(st, "fgcg_staggered_step", allow_nc=True)
         state["step"] = s.step
         del keep
-        return info.as_dict()
+        out = info.as_dict()
+        out["mean_stress"] = out["mean_stress"][:self.ns]
+        return out
 
     # ------------------------------------------------------- test hooks
+    def debug_fft(self, x, inverse=False):
+        """Real-input transform of one field through the solver passes:
+        forward (nz, ny, nx) float64 -> (nz, ny, nx//2+1) complex128 half
+        spectrum (no nz axis in 2D); inverse maps it back with 1/N."""
+        torch = _torch()
+        half = self.shape[:-1] + (self.nx // 2 + 1,)
+        if not inverse:
+            self._t(x, "x", torch.float64)
+            out = torch.empty(half, dtype=torch.complex128, device=self.device)
+        else:
+            if not (isinstance(x, torch.Tensor) and x.dtype == torch.complex128 and tuple(x.shape) == half
+                    and x.device == self.device and x.is_contiguous()):
+                raise FgcgError(-1, "debug_fft", f"expected a contiguous complex128 tensor of shape {half}")
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        _check(self.lib.fgcg_debug_fft(self.ptr, -1 if inverse else 1, self._ptr(x), self._ptr(out)),
+               "fgcg_debug_fft")
+        return out
     def mech_apply(self, phase, E_tab, nu_tab, p, d=None, kappa=0.0, E_field=None, nu_field=0.2):
         torch = _torch()
         m, keep = self._material(phase, E_tab, nu_tab, E_field, nu_field)

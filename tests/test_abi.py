@@ -56,5 +56,9 @@ def test_create_rejects_bad_grids_without_gpu(lib):
     assert L.fgcg_create(ctypes.byref(g), None, ctypes.byref(out)) == -1
     g = fgcg.Grid(2, (ctypes.c_int * 3)(64, 64, 1), -1.0, 0)
     assert L.fgcg_create(ctypes.byref(g), None, ctypes.byref(out)) == -2
-    g = fgcg.Grid(3, (ctypes.c_int * 3)(64, 64, 64), 1.0, 0)
-    assert L.fgcg_create(ctypes.byref(g), None, ctypes.byref(out)) in (-1, -6)
+    g = fgcg.Grid(3, (ctypes.c_int * 3)(64, 64, 1024), 1.0, 0)  # 3D axes stop at 512
+    assert L.fgcg_create(ctypes.byref(g), None, ctypes.byref(out)) == -1
+    g = fgcg.Grid(3, (ctypes.c_int * 3)(64, 100, 64), 1.0, 0)
+    assert L.fgcg_create(ctypes.byref(g), None, ctypes.byref(out)) == -1
+    g = fgcg.Grid(4, (ctypes.c_int * 3)(64, 64, 64), 1.0, 0)
+    assert L.fgcg_create(ctypes.byref(g), None, ctypes.byref(out)) == -1

@@ -2,7 +2,7 @@
 
 FFT: brute-force double sums on tiny inputs, round trip, Parseval, and the
 library ``numpy.fft`` as an independent check.  Symbols: the inverse transform
-of D_a f_hat equals the periodic forward-difference stencil of Sec. 2.5.
+of D_a f_hat equals the periodic forward-difference stencil of Sec. 2.6.
 Projections (App. A): idempotent, self-adjoint, identity on gradients, zero on
 constants, real output for real input.
 """
