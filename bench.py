@@ -19,7 +19,13 @@ are listed in ALGO_BYTES.  The CPU baseline
 times the FP64 oracle on two mechanics CG iterations of the same 1024^2
 problem.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+The "variants" block reports the other workloads of the method on the same
+GPU: 64^2 single-pore latency, the 1024^2 adjoint against the forward solve,
+256 batched uneven-size samples (FP64 and FP32-mixed) against the same solves
+one at a time, and the 256^3 3D staggered loop in FP32-mixed against plain
+FP64, each with its accuracy relative to the plain FP64 GPU result.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-variants]
 """
 import argparse
 import json
@@ -52,6 +58,20 @@ ALGO_BYTES = {
 }
 
 
+# 3D (256^3) mechanics passes, bytes per voxel with w-byte words (3
+# displacement components; half spectrum 129/256 of a word per component and
+# direction of storage, complex = 2 words): kp reads p, phase, damage and
+# writes q; row_fwd reads x, r, p, q, writes x, r and 3 spectra; the y and z
+# passes read and write 3 spectra; row_inv reads 3 spectra and p, writes p.
+def algo_bytes_3d(w, n=256):
+    sp = 3 * 2 * w * (n // 2 + 1) / n
+    return {"mech_kp": 6 * w + 1 + 8, "mech_row_fwd": 18 * w + sp, "mech_y_fwd": 2 * sp, "mech_col": 2 * sp,
+            "mech_y_inv": 2 * sp, "mech_row_inv": sp + 6 * w}
+
+
+KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "mech_row_inv"]
+
+
 def c2_params():
     return dict(E_tab=(3e6, 30e9), nu_tab=(0.2, 0.2), D_tab=(1e-9, 1e-12), k_tab=(1e-3, 0.0), band_width=16,
                 c_dir=1.0, dt=40.0, e_per_f=0.005, Gc=50.0, l0=2 * H, kappa=1e-6, eps_mac=(0.0, 0.0, 0.0),
@@ -81,12 +101,173 @@ def cpu_baseline(phase):
                       f"{dt:.1f} s, single thread (host has {cores} cores available)"}
 
 
+def c5_variant(torch, fgcg, inputs, dev, steps=2):
+    """256^3 Menger-type fractal, mechanics + AT2 phase field with the pore
+    eigenstrain ramp, FP32-mixed against plain FP64 (same GPU, same steps)."""
+    n = 256
+    phase_np, info = inputs.c5_microstructure(n)
+    phase = torch.from_numpy(phase_np).to(dev)
+    prm = dict(E_tab=(3e6, 30e9), nu_tab=(0.2, 0.2), D_tab=(1e-9, 1e-12), k_tab=(1e-3, 0.0), band_width=0,
+               c_dir=1.0, dt=40.0, e_per_f=0.005, Gc=50.0, l0=2 * H, kappa=1e-6, eps_mac=(0.0,) * 6,
+               tol_diff=1e-8, tol_mech=1e-8, tol_pf=1e-8, maxit=200000, diffuse=0, e_ramp=1e-3, n_ramp=20)
+    out, fields = {}, {}
+    for prec, name in ((fgcg.FP32_MIXED, "fp32_mixed"), (fgcg.FP64, "fp64")):
+        ctx = fgcg.Context(n, n, H, precision=prec, nz=n)
+        st = ctx.new_state()
+        ctx.profile(KINDS_3D)
+        ctx.staggered_step(st, phase, prm)  # warm-up step (graphs built), all passes timed
+        prof = {k: ctx.profile_read(k) for k in KINDS_3D}
+        ctx.profile([])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [ctx.staggered_step(st, phase, prm) for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        it = {s: sum(i[s]["iters"] for i in infos) for s in ("mech", "pf")}
+        secs = {s: sum(i[s]["seconds"] for i in infos) for s in ("mech", "pf")}
+        ab = algo_bytes_3d(8 if prec == fgcg.FP64 else 4, n)
+        kern = {}
+        for k in KINDS_3D:
+            ms, nl, kn = prof[k]
+            us = ms * 1e3 / max(nl, 1)
+            kern[k] = {"avg_us": us, "launches": nl, "algo_bytes_per_voxel": round(ab[k], 3),
+                       "achieved_GBs": ab[k] * n ** 3 / (us * 1e-6) / 1e9 if us > 0 else None, "kernel": kn}
+        out[name] = {"voxel_cg_iters_per_s": n ** 3 * sum(it.values()) / el, "steps": steps, "seconds": el,
+                     "iters": it, "mech_voxel_cg_iters_per_s": n ** 3 * it["mech"] / secs["mech"],
+                     "pf_voxel_cg_iters_per_s": n ** 3 * it["pf"] / secs["pf"],
+                     "kernels_warmup_step": kern, "max_d": infos[-1]["max_d"]}
+        fields[name] = (st["strain"].cpu().numpy(), st["d"].cpu().numpy())
+        del ctx, st
+        torch.cuda.empty_cache()
+    a, b = fields["fp32_mixed"], fields["fp64"]
+    out["fp32_vs_fp64_rel_diff"] = {
+        "strain": float(np.linalg.norm(a[0] - b[0]) / np.linalg.norm(b[0])),
+        "d": float(np.linalg.norm(a[1] - b[1]) / np.linalg.norm(b[1])) if np.linalg.norm(b[1]) > 0 else 0.0}
+    out["speedup_fp32_mixed_vs_fp64"] = (out["fp32_mixed"]["voxel_cg_iters_per_s"] /
+                                         out["fp64"]["voxel_cg_iters_per_s"])
+    out["workload"] = (f"3D {n}^3 Menger-type fractal (b 3, 4 levels, D 2.7, porosity {info['porosity']:.4f}), "
+                       f"{steps} timed staggered steps (mechanics + AT2 phase field, pore eigenstrain ramp "
+                       f"1e-3 over 20 steps) after 1 warm-up step, CG tol 1e-8")
+    return out
+
+
+def c3_variant(torch, fgcg, inputs, dev, count=256):
+    """256 fractal samples of uneven sizes: one batched solve vs the same
+    solves one sample at a time (plain FP64 contexts), FP64 and FP32-mixed."""
+    samples = inputs.c3_samples(count)
+    sizes = [(p.shape[1], p.shape[0]) for p, _ in samples]
+    phases = [torch.from_numpy(p).to(dev) for p, _ in samples]
+    E_tab, nu_tab, em = (3e6, 30e9), (0.2, 0.2), (1e-3, 0.0, 0.0)
+    nvox = np.array([nx * ny for nx, ny in sizes], dtype=np.float64)
+    out, strains = {}, {}
+    for prec, name in ((fgcg.FP64, "batched_fp64"), (fgcg.FP32_MIXED, "batched_fp32_mixed")):
+        b = fgcg.Batch(sizes, H, precision=prec)
+        b.mech_solve(phases, E_tab, nu_tab, [em] * count, tol=1e-8, maxit=100000, want_strain=False)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = b.mech_solve(phases, E_tab, nu_tab, [em] * count, tol=1e-8, maxit=100000)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        its = np.array([i["iters"] for i in r["infos"]], dtype=np.float64)
+        out[name] = {"voxel_cg_iters_per_s": float((nvox * its).sum() / el), "seconds": el,
+                     "iters_min": int(its.min()), "iters_max": int(its.max())}
+        strains[name] = [s.cpu().numpy() for s in r["strains"]]
+        b.close()
+        del b, r
+    ctxs = {}
+    t_el, work = 0.0, 0.0
+    plain = []
+    for i, (nx, ny) in enumerate(sizes):
+        if (nx, ny) not in ctxs:
+            ctxs[(nx, ny)] = fgcg.Context(nx, ny, H)
+            ctxs[(nx, ny)].mech_solve(phases[i], E_tab, nu_tab, em, tol=1e-8, maxit=100000, want_stress=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, (nx, ny) in enumerate(sizes):
+        r = ctxs[(nx, ny)].mech_solve(phases[i], E_tab, nu_tab, em, tol=1e-8, maxit=100000, want_stress=False)
+        work += nvox[i] * r["info"]["iters"]
+        plain.append(r["strain"].cpu().numpy() if i < 16 else None)
+    torch.cuda.synchronize()
+    t_el = time.perf_counter() - t0
+    out["plain_fp64_one_at_a_time"] = {"voxel_cg_iters_per_s": work / t_el, "seconds": t_el}
+    out["batched_vs_plain_fp64"] = out["batched_fp64"]["voxel_cg_iters_per_s"] / (work / t_el)
+    out["batched_fp64_vs_plain_max_rel_diff_first16"] = max(
+        float(np.linalg.norm(strains["batched_fp64"][i] - plain[i]) / np.linalg.norm(plain[i])) for i in range(16))
+    out["fp32_mixed_vs_fp64_max_rel_diff"] = max(
+        float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        for a, b in zip(strains["batched_fp32_mixed"], strains["batched_fp64"]))
+    out["workload"] = (f"{count} 2D box-removal fractals, n in {{128, 256, 384, 512}}, "
+                       f"{int(nvox.sum())} voxels, eps11 = 1e-3, CG tol 1e-8")
+    return out
+
+
+def c4_variant(torch, fgcg, inputs, dev):
+    """1024^2 fractal, E field 30 GPa / 3 MPa: forward solve vs adjoint
+    gradient of C11 (forward + adjoint solve) and of the energy (lam = 0)."""
+    phase_np, _ = inputs.c2_microstructure(N_SIDE)
+    E = torch.from_numpy(np.where(phase_np == 0, 3e6, 30e9)).to(dev)
+    em = (1e-3, 0.0, 0.0)
+    ctx = fgcg.Context(N_SIDE, N_SIDE, H)
+    ctx.mech_solve(None, None, None, em, E_field=E, nu_field=0.2, tol=1e-8, maxit=200000)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fw = ctx.mech_solve(None, None, None, em, E_field=E, nu_field=0.2, tol=1e-8, maxit=200000)
+    torch.cuda.synchronize()
+    t_fw = time.perf_counter() - t0
+    ctx.mech_adjoint(E, 0.2, em, objective=fgcg.J_C11, tol=1e-8, maxit=200000)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, J, i1, i2 = ctx.mech_adjoint(E, 0.2, em, objective=fgcg.J_C11, tol=1e-8, maxit=200000)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    # Hill-Mandel closed form of dC11/dE from the forward strain (GPU, FP64)
+    s = fw["strain"]
+    sg = fw["stress"]
+    dens = s[0] * sg[0] + s[1] * sg[1] + 2 * s[2] * sg[2]
+    closed = dens / (N_SIDE * N_SIDE * em[0] ** 2 * E)
+    err = float((g - closed).norm() / closed.norm())
+    nv = N_SIDE * N_SIDE
+    return {"forward": {"seconds": t_fw, "iters": fw["info"]["iters"],
+                        "voxel_cg_iters_per_s": nv * fw["info"]["iters"] / t_fw},
+            "adjoint_C11": {"seconds": t_adj, "iters_fwd": i1["iters"], "iters_adj": i2["iters"],
+                            "voxel_cg_iters_per_s": nv * (i1["iters"] + i2["iters"]) / t_adj},
+            "adjoint_over_forward_time": t_adj / t_fw,
+            "grad_C11_vs_hill_mandel_closed_form_rel_err": err, "C11": J,
+            "workload": "2D 1024^2 box-removal fractal, E 30 GPa / 3 MPa per voxel, nu 0.2, eps11 1e-3, "
+                        "CG tol 1e-8, FP64"}
+
+
+def c1_variant(torch, fgcg, inputs, dev, reps=20):
+    """64^2 single circular pore, FP64, tol 1e-10: latency per solve."""
+    phase_np = inputs.circle_pore(64)
+    phase = torch.from_numpy(phase_np).to(dev)
+    e = torch.from_numpy(np.where(phase_np == 0, 1e-3, 0.0)).to(dev)
+    ctx = fgcg.Context(64, 64, H)
+    r = ctx.mech_solve(phase, (3e6, 30e9), (0.2, 0.2), (0.0, 0.0, 0.0), eig=e, tol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = ctx.mech_solve(phase, (3e6, 30e9), (0.2, 0.2), (0.0, 0.0, 0.0), eig=e, tol=1e-10)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    return {"us_per_solve": el * 1e6, "iters": r["info"]["iters"], "us_per_iter": el * 1e6 / r["info"]["iters"],
+            "workload": "2D 64^2 plane strain, one circular pore (316 voxels, E 3 MPa, eigenstrain 1e-3), "
+                        "matrix 30 GPa, FP64, tol 1e-10"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variant", default=None,
+                    help="run only this variant (c1_latency_64, c4_adjoint_1024, c3_batched_256, c5_3d_256) and "
+                         "print its JSON")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-MiB FP64 buffer 5 times with an elementwise kernel (reads "
+                         "and writes MIB MiB each): the reference for scaling HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (this build has no "
@@ -99,6 +280,12 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.variant:
+        fn = {"c1_latency_64": c1_variant, "c4_adjoint_1024": c4_variant, "c3_batched_256": c3_variant,
+              "c5_3d_256": c5_variant}[args.variant]
+        print(json.dumps({args.variant: fn(torch, fgcg, inputs, dev)}), flush=True)
+        copy_probe(torch, dev, args.copy_probe)
+        return
     phase_np, finfo = inputs.c2_microstructure(N_SIDE)
     phase = torch.from_numpy(phase_np).to(dev)
     ctx = fgcg.Context(N_SIDE, N_SIDE, H)
@@ -168,9 +355,33 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
                      "algo_bytes_per_launch": ALGO_BYTES[dom] * nvox, "avg_launch_us": avg_s * 1e6},
     }
+    if not args.no_variants:
+        del ctx, state
+        torch.cuda.empty_cache()
+        variants = {}
+        for name, fn in (("c1_latency_64", c1_variant), ("c4_adjoint_1024", c4_variant),
+                         ("c3_batched_256", c3_variant), ("c5_3d_256", c5_variant)):
+            print(f"variant {name} ...", file=sys.stderr, flush=True)
+            t0 = time.perf_counter()
+            variants[name] = fn(torch, fgcg, inputs, dev)
+            print(f"variant {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+        out["variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(phase_np)
     print(json.dumps(out), flush=True)
+    copy_probe(torch, dev, args.copy_probe)
+
+
+def copy_probe(torch, dev, mib):
+    if mib <= 0:
+        return
+    x = torch.rand(mib * 2 ** 20 // 8, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(5):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(f"copy probe: 5 x {mib} MiB read + {mib} MiB written", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":
