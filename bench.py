@@ -14,8 +14,11 @@ value = total voxel-CG-iterations (all three solvers) / wall time of the
 timed steps.  The roofline block reports the dominant kernel (largest summed
 device time of the three mechanics passes in the last warm-up step) from HIP
 events recorded, on the library's stream, around the launches of that kernel
-in every other graph chunk of the timed steps; its algorithmic bytes per voxel
-are listed in ALGO_BYTES.  The CPU baseline
+in every other graph chunk of the timed steps, less the dispatch gap that the event-record nodes add (an empty
+kernel timed the same way); its algorithmic bytes per voxel are listed in
+ALGO_BYTES.  traffic is the counter-measured HBM bytes per launch recorded
+under profiles/, reported only while the kernel sources are the ones it was
+measured on.  The CPU baseline
 times the FP64 oracle on two mechanics CG iterations of the same 1024^2
 problem.
 
@@ -70,6 +73,23 @@ def algo_bytes_3d(w, n=256):
 
 
 KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "mech_row_inv"]
+
+# HBM traffic per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# recorded under profiles/ (scaled by the copy probe), valid only for the
+# kernel sources they were taken with: the key is the SHA-256 of csrc/.
+MEASURED_TRAFFIC = {
+    # source hash -> {kernel kind: bytes per launch}
+}
+
+
+def csrc_hash():
+    import hashlib
+    d = os.path.join(ROOT, "paper_2305_13081_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
 
 
 def c2_params():
@@ -300,9 +320,10 @@ def main():
               f"pf {info['pf']['iters']}", file=sys.stderr, flush=True)
     warm = {k: ctx.profile_read(k) for k in mech_kinds}
     dom = max(mech_kinds, key=lambda k: warm[k][0]) if args.warmup > 0 else "mech_row_fwd"
-    # time only the dominant pass during the timed steps: every event-record
-    # node adds idle time, so the other passes are reported from the warm-up
-    ctx.profile([dom])
+    # time only the dominant pass during the timed steps (every event-record
+    # node adds idle time, so the other passes are reported from the warm-up),
+    # and an empty kernel timed the same way: the dispatch gap of the events
+    ctx.profile([dom, "event_gap"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
@@ -322,8 +343,12 @@ def main():
     value = nvox * total_iters / elapsed
     prof = {k: (ctx.profile_read(k) if k == dom else warm[k]) for k in mech_kinds}
     ms, launches, kname = prof[dom]
-    avg_s = ms / 1e3 / max(launches, 1)
+    raw_s = ms / 1e3 / max(launches, 1)
+    gms, gn, _ = ctx.profile_read("event_gap")
+    gap_s = gms / 1e3 / max(gn, 1)
+    avg_s = raw_s - gap_s if gn > 0 and raw_s > 2 * gap_s else raw_s
     achieved = ALGO_BYTES[dom] * nvox / avg_s / 1e9
+    tr = MEASURED_TRAFFIC.get(csrc_hash(), {}).get(dom)
     per_kernel = {k: {"avg_us": prof[k][0] * 1e3 / max(prof[k][1], 1), "launches": prof[k][1],
                       "timed_in": "timed steps" if k == dom else "last warm-up step",
                       "algo_bytes_per_voxel": round(ALGO_BYTES[k], 3),
@@ -352,8 +377,12 @@ def main():
             "mech_kernels": per_kernel,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
-                     "algo_bytes_per_launch": ALGO_BYTES[dom] * nvox, "avg_launch_us": avg_s * 1e6},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kname,
+                     "algo_bytes_per_launch": ALGO_BYTES[dom] * nvox, "avg_launch_us": avg_s * 1e6,
+                     "avg_launch_us_event_raw": raw_s * 1e6, "event_gap_us": gap_s * 1e6,
+                     "timing": "HIP events on the library stream around every launch of the kernel in the "
+                               "first of the two alternating graph instances during the timed steps, minus "
+                               "the event gap (an empty kernel timed the same way in the same graphs)"},
     }
     if not args.no_variants:
         del ctx, state

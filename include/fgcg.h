@@ -269,8 +269,13 @@ enum {
   FGCG_K_MECH_KP = 11,
   FGCG_K_MECH_Y_FWD = 12, /* 3D: y transforms of the Green operator */
   FGCG_K_MECH_Y_INV = 13,
-  FGCG_K_NKINDS = 14
+  FGCG_K_EVENT_GAP = 14, /* an empty one-block kernel (see below) */
+  FGCG_K_NKINDS = 15
 };
+/* While FGCG_K_EVENT_GAP is profiled, every CG iteration of a graph chunk ends
+ * with an empty one-block kernel node, timed like the others: its duration is
+ * the dispatch gap that the two event-record nodes around a kernel node add to
+ * that kernel's event-timed duration. */
 /* On 3D grids FGCG_K_MECH_COL times the z pass (forward z transform, Green
  * symbol, inverse z transform). */
 /* mask: bit k enables event timing of kind k (0 disables); resets counters. */

@@ -375,7 +375,12 @@ template <class F> int build_chunk(fgcg_ctx* c, fgcg_ctx::GraphSlot& sl, F& iter
   c->build_timed = timed;
   c->last = nullptr;
   int rc = 0;
-  for (int j = 0; j < K && !rc; ++j) rc = iter();
+  const bool gap = timed && (c->prof_mask & (1u << FGCG_K_EVENT_GAP));
+  if (gap) set_kname(c, FGCG_K_EVENT_GAP, "k_noop%.0s%.0d", "", 0);
+  for (int j = 0; j < K && !rc; ++j) {
+    rc = iter();
+    if (!rc && gap) rc = launch(c, FGCG_K_EVENT_GAP, (const void*)&k_noop, dim3(1), 0);
+  }
   c->building = false;
   hipGraph_t g = c->graph;
   c->graph = nullptr;

@@ -102,6 +102,9 @@ __global__ void __launch_bounds__(PT) k_mech_post(MechMat m, const T* x, long lo
   }
 }
 
+// Empty kernel (the event-gap calibration of the profiling hooks).
+static __global__ void __launch_bounds__(NT) k_noop(int) {}
+
 // Precipitation in the pores (phase 0): f = min(1, f + dt k c); e = e_per_f f.
 // With diffuse = 0 the eigenstrain follows the prescribed ramp value e_pres.
 static __global__ void __launch_bounds__(PT) k_precip(const uint8_t* phase, const double* c, double* f,

@@ -23,7 +23,7 @@ KINDS = {
     "mech_row_fwd": 0, "mech_col": 1, "mech_row_inv": 2,
     "pf_row_fwd": 3, "pf_col": 4, "pf_row_inv": 5,
     "diff_row_fwd": 6, "diff_col_grad": 7, "diff_row_mid": 8, "diff_col_div": 9, "diff_row_inv": 10,
-    "mech_kp": 11, "mech_y_fwd": 12, "mech_y_inv": 13,
+    "mech_kp": 11, "mech_y_fwd": 12, "mech_y_inv": 13, "event_gap": 14,
 }
 
 
