@@ -99,7 +99,7 @@ struct fgcg_ctx {
   void* spec = nullptr;
   fgcg::CgState* st = nullptr;
   fgcg::CgState* h_st = nullptr;
-  dim3 sgrid;                 // grid of the stencil CG passes (at most 512 blocks)
+  dim3 sgrid;                 // grid of the stencil CG passes (8..512 blocks, a multiple of 8)
   int scalar_spectral = 0;    // 1: phase field and diffusion apply their operators by FFT
   double* part_a = nullptr;
   double* part_rr = nullptr;
@@ -107,6 +107,7 @@ struct fgcg_ctx {
   double* part_post = nullptr;
   double* h_part = nullptr;
   int nrow = 0, ncol = 0, npost = 0, nkp = 0;
+  int nkpt = 0;  // blocks of the tiled 2D stiffness pass (one partial sum each)
   int nsamp = 1;            // samples of this grid size (batches)
   double* ems = nullptr;    // device [nsamp][3] macro strains
   bool batch = false;            // member of a batch (owns the gather buffers below)

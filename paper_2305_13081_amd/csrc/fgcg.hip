@@ -26,8 +26,8 @@ template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, i
   const CopyProN<T, 2> cp{fld<T>(c->r, c), c->nx};
   if ((rc = launch_row_fwd<T, 2>(c, -1, cp, spec, ns, ss))) return rc;
   const MechGreen<T> g0{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
-  if ((rc = launch_col<T, 2, 2>(c, -1, g0, spec, spec, ns, ss))) return rc;
-  const MechUEpi<T> e0{fld<T>(c->p, c), c->nx, c->st, c->part_rr, c->ncol, 1, tol, maxit};
+  if ((rc = launch_col<T, 1, 1>(c, -1, g0, spec, spec, 2 * ns, ss / 2))) return rc;
+  const MechUEpi<T> e0{fld<T>(c->p, c), c->nx, c->st, c->part_rr, 2 * c->ncol, 1, tol, maxit};
   if ((rc = launch_row_inv<T, 2>(c, -1, e0, spec, ns, ss))) return rc;
   HIPCHK(hipGetLastError());
   return 0;
@@ -41,22 +41,22 @@ template <typename T> int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, i
   const long long ss = spec_ss(c);
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
   set_kname(c, FGCG_K_MECH_KP, "k_mech_kp<%s%.0d", tname<T>(), 0);
-  int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech_kp<T>, dim3(c->nkp, ns), m, (const T*)P.p, Q.p, c->n,
+  int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech_kp<T>, dim3(c->nkpt, ns), m, (const T*)P.p, Q.p, c->n,
                  c->nx, c->ny, (T)(1.0 / c->h), c->st, c->part_a);
   if (!reliable) {
-    const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, c->nkp};
+    const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt};
     r |= launch_row_fwd<T, 2>(c, FGCG_K_MECH_ROW_FWD, pro, spec, ns, ss);
   } else {
     r |= launch(c, -1, (const void*)&k_mech_fold<T>, dim3(c->npost, ns), X.p, c->xh, (const T*)P.p, 2 * c->n, c->st,
-                (const double*)c->part_a, c->nkp);
+                (const double*)c->part_a, c->nkpt);
     r |= launch(c, -1, (const void*)&k_mech_true_res<T>, dim3(c->nkp, ns), m, (const double*)c->xh,
                 (const double*)c->fh, R.p, c->n, c->nx, c->ny, 1.0 / c->h, (const CgState*)c->st);
     const CopyProN<T, 2> cp{R, c->nx};
     r |= launch_row_fwd<T, 2>(c, -1, cp, spec, ns, ss);
   }
   const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, c->st, c->part_rr};
-  r |= launch_col<T, 2, 2>(c, FGCG_K_MECH_COL, green, spec, spec, ns, ss);
-  const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, c->ncol, 0, tol, maxit};
+  r |= launch_col<T, 1, 1>(c, FGCG_K_MECH_COL, green, spec, spec, 2 * ns, ss / 2);
+  const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, tol, maxit};
   r |= launch_row_inv<T, 2>(c, FGCG_K_MECH_ROW_INV, epi, spec, ns, ss);
   return r;
 }
@@ -527,7 +527,12 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
   });
   c->ncol = c->nxh;
   c->npost = (int)std::min<long long>((c->n + PT - 1) / PT, 1024);
-  c->nkp = (int)std::min<long long>((c->n + NT - 1) / NT, 1024);
+  // slab-walking kernels: a multiple of 8 blocks (one slab per XCD)
+  const auto slab_blocks = [&](long long cap) {
+    return (int)std::max<long long>(8, std::min<long long>((c->n + NT - 1) / NT, cap) & ~7LL);
+  };
+  c->nkp = slab_blocks(1024);
+  c->nkpt = std::min(kp_tiles(c->nx, c->rows), 1024);
   int rc = 0;
   auto chk = [&](hipError_t e) {
     if (e != hipSuccess && !rc) rc = fail(FGCG_ENOMEM, std::string("allocation failed: ") + hipGetErrorString(e));
@@ -543,18 +548,14 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
     const size_t ns = (size_t)nsamp;
     chk(hipMalloc(&c->st, sizeof(CgState) * ns));
     chk(hipHostMalloc(&c->h_st, sizeof(CgState) * 2 * ns, hipHostMallocDefault));
-    const int npa = std::max(std::max(c->nrow + std::max(c->ncol, c->nrow), c->nkp), 1024);
+    const int npa = std::max(std::max(c->nrow + std::max(c->ncol, c->nrow), c->nkp), 4096);
     chk(hipMalloc(&c->part_a, sizeof(double) * npa * ns));
-    chk(hipMalloc(&c->part_rr, sizeof(double) * std::max(std::max(c->nrow, c->ncol), 512) * ns));
+    chk(hipMalloc(&c->part_rr, sizeof(double) * std::max(std::max(c->nrow, 2 * c->ncol), 512) * ns));
     chk(hipMalloc(&c->part_b, sizeof(double) * std::max(std::max(c->nrow, c->npost), 512)));
     // post-processing partials: 4-5 per block (2D), 7 per stencil block (3D, at most 1024 blocks)
     const size_t npp = std::max<size_t>(5 * (size_t)c->npost * ns, 7 * 1024);
     chk(hipMalloc(&c->part_post, sizeof(double) * npp));
-    {
-      const int bx = (c->nx + NT - 1) / NT;
-      const int by = std::max(1, std::min(c->rows, 512 / bx));
-      c->sgrid = dim3(bx, by);
-    }
+    c->sgrid = dim3(slab_blocks(512));
     chk(hipHostMalloc(&c->h_part, sizeof(double) * npp, hipHostMallocDefault));
   }
   if (!rc) {

@@ -27,6 +27,7 @@ template <class F> bool with_n3(int n, F&& f) {
 }
 
 constexpr int RELIABLE_EVERY3 = 10;  // FP32-mixed: true residual every tenth iteration
+constexpr int KP3_MAX_BLOCKS = 4096;  // blocks of the tiled stiffness pass (partial sums in part_a)
 
 template <typename T> const CT<T>* tw_z(const fgcg_ctx* c) {
   return (const CT<T>*)(std::is_same<T, double>::value ? c->twz : c->twz32);
@@ -110,10 +111,11 @@ template <typename T> int mech3_iter(fgcg_ctx* c, const MechMat& m, double tol, 
   const Field<T> X = fld3<T>(c->x, c), R = fld3<T>(c->r, c), P = fld3<T>(c->p, c), Q = fld3<T>(c->tmp, c);
   const Grid3 g = grid3(c);
   const int nb = nslab(c);
+  const int nkp = std::min(kp3_chunks(c->nx, c->ny, c->nz), KP3_MAX_BLOCKS);
   set_kname(c, FGCG_K_MECH_KP, "k_mech3_kp<%s%.0d", tname<T>(), 0);
-  int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech3_kp<T>, dim3(nb), m, (const T*)P.p, Q.p, g,
+  int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech3_kp<T>, dim3(nkp), m, (const T*)P.p, Q.p, g,
                  (T)(1.0 / c->h), c->st, c->part_a);
-  r |= launch_reduce(c, c->part_a, nb, c->red);
+  r |= launch_reduce(c, c->part_a, nkp, c->red);
   if (!reliable) {
     const MechUPro<T, 3> pro{X, R, P, Q, c->nx, c->st, c->red, 1};
     r |= green3<T>(c, pro, c->st, true);

@@ -18,7 +18,8 @@
 //   row_fwd (MechUPro) alpha = r.z / p.Kp; x += alpha p; r -= alpha q; the
 //                      two components of r are transformed along x
 //   col (MechGreen)    z_hat = r_hat / |D|^2 / N, partial sums of r.z by
-//                      Parseval over the half spectrum
+//                      Parseval over the half spectrum (one component per
+//                      block)
 //   row_inv (MechUEpi) z back in real space; stop test on r.z; beta;
 //                      p = z + beta p
 // so q and z are never stored except q between the first two passes.
@@ -70,10 +71,23 @@ __device__ __forceinline__ void div_adj(const T* s0, const T* sxm, const T* sym_
 
 // q = K p with partial sums of p.Kp; the lead thread publishes the iteration
 // counter (k = k_next) for the later passes of this iteration.
+//
+// Tiled: a tile of KP_TX x KP_TY voxels computes the stress once per voxel of
+// the tile and of its halo column x0 - 1 and halo row y0 - 1 (1.08 stress
+// evaluations per voxel instead of 3), keeps it in LDS, and takes the
+// divergence from there.  Each block walks a contiguous range of tiles
+// (row-major, x fastest), the ranges laid out XCD by XCD (xcd_block), so the
+// rows a tile shares with the tiles beside it meet in one L2.
+constexpr int KP_TX = 64, KP_TY = 16;
+
+inline int kp_tiles(int nx, int ny) { return ((nx + KP_TX - 1) / KP_TX) * ((ny + KP_TY - 1) / KP_TY); }
+
 template <typename T>
 __global__ void __launch_bounds__(NT) k_mech_kp(MechMat m, const T* __restrict__ p, T* __restrict__ q,
                                                 long long n, int nx, int ny, T ih, CgState* st,
                                                 double* part) {
+  constexpr int HX = KP_TX + 1, HY = KP_TY + 1, HP = HX * HY;
+  __shared__ T sg[3][HP];
   __shared__ double red[NT / 64];
   const int s = blockIdx.y;  // sample of a batch
   st += s;
@@ -81,22 +95,48 @@ __global__ void __launch_bounds__(NT) k_mech_kp(MechMat m, const T* __restrict__
   q += 2 * n * s;
   if (!cg_running(st, 0)) return;
   if (lead()) st->k = st->k_next;
+  const int ntx = (nx + KP_TX - 1) / KP_TX;
+  const int ntiles = ntx * ((ny + KP_TY - 1) / KP_TY);
+  const int lb = xcd_block(), nb = gridDim.x;
+  const int t0 = (int)((long long)ntiles * lb / nb), t1 = (int)((long long)ntiles * (lb + 1) / nb);
+  const int tx = threadIdx.x & (KP_TX - 1), ty = threadIdx.x / KP_TX;
   double acc = 0.0;
-  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
-    const int y = (int)(i / nx), x = (int)(i - (long long)y * nx);
-    const int xm = x == 0 ? nx - 1 : x - 1;
-    const int ym = y == 0 ? ny - 1 : y - 1;
-    T s0[3], e0[3], sx[3], sy[3], tmp[3], qq[2];
-    sigma_u<T>(m, s, p, n, nx, ny, y, x, ih, s0, e0);
-    sigma_u<T>(m, s, p, n, nx, ny, y, xm, ih, sx, tmp);
-    sigma_u<T>(m, s, p, n, nx, ny, ym, x, ih, sy, tmp);
-    div_adj<T>(s0, sx, sy, ih, qq);
-    q[i] = qq[0];
-    q[n + i] = qq[1];
-    acc += (double)e0[0] * s0[0] + (double)e0[1] * s0[1] + 2.0 * (double)e0[2] * s0[2];
+  for (int t = t0; t < t1; ++t) {
+    const int x0 = (t % ntx) * KP_TX, y0 = (t / ntx) * KP_TY;
+    for (int hp = threadIdx.x; hp < HP; hp += NT) {
+      const int hy = hp / HX, hx = hp - hy * HX;
+      int x = x0 - 1 + hx, y = y0 - 1 + hy;
+      if (x >= nx || y >= ny) continue;  // past the edge of a partial tile: never read
+      if (x < 0) x += nx;
+      if (y < 0) y += ny;
+      T sv[3], e[3];
+      sigma_u<T>(m, s, p, n, nx, ny, y, x, ih, sv, e);
+      sg[0][hp] = sv[0];
+      sg[1][hp] = sv[1];
+      sg[2][hp] = sv[2];
+      if (hx >= 1 && hy >= 1) acc += (double)e[0] * sv[0] + (double)e[1] * sv[1] + 2.0 * (double)e[2] * sv[2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KP_TY / (NT / KP_TX); ++k) {
+      const int yy = ty + k * (NT / KP_TX);
+      const int x = x0 + tx, y = y0 + yy;
+      if (x < nx && y < ny) {
+        const int hp = (yy + 1) * HX + tx + 1;
+        const T s0[3] = {sg[0][hp], sg[1][hp], sg[2][hp]};
+        const T sx[3] = {sg[0][hp - 1], sg[1][hp - 1], sg[2][hp - 1]};
+        const T sy[3] = {sg[0][hp - HX], sg[1][hp - HX], sg[2][hp - HX]};
+        T qq[2];
+        div_adj<T>(s0, sx, sy, ih, qq);
+        const long long i = (long long)y * nx + x;
+        q[i] = qq[0];
+        q[n + i] = qq[1];
+      }
+    }
+    __syncthreads();
   }
-  const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) part[(long long)s * gridDim.x + blockIdx.x] = t;
+  const double tsum = block_sum(acc, red);
+  if (threadIdx.x == 0) part[(long long)s * gridDim.x + blockIdx.x] = tsum;
 }
 
 // r = f = -grad^H g C : (eps_mac - e I); x = 0.  Sample s = blockIdx.y uses
@@ -109,8 +149,9 @@ __global__ void __launch_bounds__(NT) k_mech_rhs(MechMat m, const double* eig, c
   const double em[3] = {ems[3 * s], ems[3 * s + 1], ems[3 * s + 2]};
   r += 2 * n * s;
   x += 2 * n * s;
-  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
-    const int y = (int)(i / nx), xx = (int)(i - (long long)y * nx);
+  const SlabIter it(nx, ny);
+  for (long long i = it.v0; i < it.v1; i += it.step) {
+    const int y = (int)((unsigned)i / (unsigned)nx), xx = (int)(i - (long long)y * nx);
     const int xm = xx == 0 ? nx - 1 : xx - 1;
     const int ym = y == 0 ? ny - 1 : y - 1;
     T s0[3], sx[3], sy[3], qq[2];
@@ -229,8 +270,9 @@ __global__ void __launch_bounds__(NT) k_mech_true_res(MechMat m, const double* _
   f += 2 * n * s;
   r += 2 * n * s;
   if (!cg_running(st, s)) return;
-  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
-    const int y = (int)(i / nx), x = (int)(i - (long long)y * nx);
+  const SlabIter it(nx, ny);
+  for (long long i = it.v0; i < it.v1; i += it.step) {
+    const int y = (int)((unsigned)i / (unsigned)nx), x = (int)(i - (long long)y * nx);
     const int xm = x == 0 ? nx - 1 : x - 1;
     const int ym = y == 0 ? ny - 1 : y - 1;
     double s0[3], sx[3], sy[3], e[3], qq[2];
@@ -288,34 +330,34 @@ template <typename T, int NC> struct CopyProN {
   __device__ void partial(int, double) const {}
 };
 
-// Green operator of the unit reference medium with partial sums of r.z.
+// Green operator of the unit reference medium with partial sums of r.z, one
+// displacement component per block: the column pass runs over (sample,
+// component) pairs s2 = 2 s + c (component stride nxh ny), and the partial sums
+// of sample s fill part[2 s gridDim.x .. (2 s + 2) gridDim.x).
 template <typename T> struct MechGreen {
   const double2* Dx;
   const double2* Dy;
   double inv_n;
   int nx;
   const CgState* st;  // nullable
-  double* part;       // nullable; per sample, gridDim.x partials
-  __device__ bool begin(int s, double*, double&) const { return st == nullptr || cg_running(st, s); }
+  double* part;       // nullable
+  __device__ bool begin(int s2, double*, double&) const { return st == nullptr || cg_running(st, s2 >> 1); }
   template <typename C>
   __device__ void mode(int, int kx, int ky, const C* a, C* b, double& acc, double) const {
     const double2 d1 = Dx[kx], d2 = Dy[ky];
     const double n2 = d1.x * d1.x + d1.y * d1.y + d2.x * d2.x + d2.y * d2.y;
     if (n2 == 0.0) {
       b[0] = C{(T)0, (T)0};
-      b[1] = C{(T)0, (T)0};
       return;
     }
     const double f = inv_n / n2;
     const T ft = (T)f;
     b[0] = C{a[0].x * ft, a[0].y * ft};
-    b[1] = C{a[1].x * ft, a[1].y * ft};
     const double w = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
-    acc += w * f *
-           ((double)a[0].x * a[0].x + (double)a[0].y * a[0].y + (double)a[1].x * a[1].x + (double)a[1].y * a[1].y);
+    acc += w * f * ((double)a[0].x * a[0].x + (double)a[0].y * a[0].y);
   }
-  __device__ void partial(int s, double v) const {
-    if (part && threadIdx.x == 0) part[(long long)s * gridDim.x + blockIdx.x] = v;
+  __device__ void partial(int s2, double v) const {
+    if (part && threadIdx.x == 0) part[(long long)s2 * gridDim.x + blockIdx.x] = v;
   }
 };
 

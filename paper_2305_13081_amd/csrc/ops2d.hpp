@@ -59,6 +59,24 @@ struct CgCtl {
 
 __device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
+// Voxel range of this block for the kernels that walk a grid of `rows` rows of
+// nx voxels (row = z ny + y): the rows are cut into 8 contiguous slabs, one per
+// XCD (the hardware hands block b to XCD b % 8), and the blocks of a slab walk
+// it together, so the neighbour rows a block reads were brought into the same
+// L2 by the blocks beside it.  gridDim.x must be a multiple of 8.  Grids hold
+// fewer than 2^31 voxels, so the row of voxel v is (unsigned)v / nx.
+struct SlabIter {
+  long long v0, v1, step;
+  __device__ SlabIter(int nx, long long rows) {
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int x = b & 7, q = b >> 3, nq = nb >> 3;
+    const long long r0 = rows * x / 8, r1 = rows * (x + 1) / 8;
+    v0 = r0 * nx + (long long)q * NT + threadIdx.x;
+    v1 = r1 * nx;
+    step = (long long)nq * NT;
+  }
+};
+
 __device__ __forceinline__ bool cg_running(const CgState* st, int s) {
   return !__syncthreads_or(st[s].done != 0);
 }

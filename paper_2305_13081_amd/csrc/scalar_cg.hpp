@@ -91,7 +91,8 @@ struct DiffStencil {
   }
 };
 
-// Rows (z ny + y) are distributed over blockIdx.y, x over blockIdx.x.
+// The kernels walk the rows (z ny + y) in XCD slabs (SlabIter); the grid is
+// one-dimensional with a multiple of 8 blocks.
 
 // First pass of iteration k.  band > 0: voxels with x < band are fixed
 // (p = q = 0 there).
@@ -107,17 +108,16 @@ __global__ void __launch_bounds__(NT) k_scg_dir(Op op, const T* __restrict__ r, 
   const bool first = beta == 0.0;  // beta is 0 exactly on the first iteration
   const T b = (T)beta;
   auto pn = [&](long long j, int) -> double { return first ? (double)r[j] : (double)(r[j] + b * pin[j]); };
-  const int rows = ny * nz;
   double acc = 0.0;
-  for (int row = blockIdx.y; row < rows; row += gridDim.y) {
-    for (int x = blockIdx.x * NT + threadIdx.x; x < nx; x += gridDim.x * NT) {
-      const Nbr nb = nbrs(row, x, nx, ny, nz);
-      const double p0 = pn(nb.i, x);
-      const double qv = x < band ? 0.0 : op.apply(p0, pn, nb);
-      pout[nb.i] = (T)p0;
-      q[nb.i] = (T)qv;
-      acc += p0 * qv;
-    }
+  const SlabIter it(nx, (long long)ny * nz);
+  for (long long v = it.v0; v < it.v1; v += it.step) {
+    const int row = (int)((unsigned)v / (unsigned)nx), x = (int)(v - (long long)row * nx);
+    const Nbr nb = nbrs(row, x, nx, ny, nz);
+    const double p0 = pn(nb.i, x);
+    const double qv = x < band ? 0.0 : op.apply(p0, pn, nb);
+    pout[nb.i] = (T)p0;
+    q[nb.i] = (T)qv;
+    acc += p0 * qv;
   }
   const double t = block_sum(acc, red);
   if (threadIdx.x == 0) cc.part_a[block_linear()] = t;
@@ -131,14 +131,12 @@ __global__ void __launch_bounds__(NT) k_scg_upd(T* __restrict__ x, T* __restrict
   if (!cg_begin_step(cc, 0, red, alpha)) return;
   const T a = (T)alpha;
   double acc = 0.0;
-  for (int y = blockIdx.y; y < rows; y += gridDim.y) {
-    for (int xx = blockIdx.x * NT + threadIdx.x; xx < nx; xx += gridDim.x * NT) {
-      const long long i = (long long)y * nx + xx;
-      x[i] += a * p[i];
-      const T rv = r[i] - a * q[i];
-      r[i] = rv;
-      acc += (double)rv * (double)rv;
-    }
+  const SlabIter it(nx, rows);
+  for (long long i = it.v0; i < it.v1; i += it.step) {
+    x[i] += a * p[i];
+    const T rv = r[i] - a * q[i];
+    r[i] = rv;
+    acc += (double)rv * (double)rv;
   }
   const double t = block_sum(acc, red);
   if (threadIdx.x == 0) cc.part_rr[block_linear()] = t;
@@ -156,27 +154,26 @@ __global__ void __launch_bounds__(NT) k_scg_init(Op op, const double* __restrict
   __shared__ double red[NT / 64];
   auto vt = [&](long long j, int xx) -> double { return xx < band ? c_dir : xin[j]; };
   auto vb = [&](long long, int xx) -> double { return xx < band ? c_dir : 0.0; };
-  const int rows = ny * nz;
   double acc[2] = {0.0, 0.0};
-  for (int row = blockIdx.y; row < rows; row += gridDim.y) {
-    for (int xx = blockIdx.x * NT + threadIdx.x; xx < nx; xx += gridDim.x * NT) {
-      const Nbr nb = nbrs(row, xx, nx, ny, nz);
-      const long long i = nb.i;
-      if (xx < band) {
-        x[i] = (T)0;
-        r[i] = (T)0;
-        continue;
-      }
-      const double b = bscale * bsrc[i];
-      const double ax = op.apply(vt(i, xx), vt, nb);
-      double bf = b;
-      if (band > 0) bf = b - op.apply(0.0, vb, nb);
-      const double res = b - ax;
-      x[i] = (T)xin[i];
-      r[i] = (T)res;
-      acc[0] += bf * bf;
-      acc[1] += res * res;
+  const SlabIter it(nx, (long long)ny * nz);
+  for (long long v = it.v0; v < it.v1; v += it.step) {
+    const int row = (int)((unsigned)v / (unsigned)nx), xx = (int)(v - (long long)row * nx);
+    const Nbr nb = nbrs(row, xx, nx, ny, nz);
+    const long long i = nb.i;
+    if (xx < band) {
+      x[i] = (T)0;
+      r[i] = (T)0;
+      continue;
     }
+    const double b = bscale * bsrc[i];
+    const double ax = op.apply(vt(i, xx), vt, nb);
+    double bf = b;
+    if (band > 0) bf = b - op.apply(0.0, vb, nb);
+    const double res = b - ax;
+    x[i] = (T)xin[i];
+    r[i] = (T)res;
+    acc[0] += bf * bf;
+    acc[1] += res * res;
   }
   const double t0 = block_sum(acc[0], red), t1 = block_sum(acc[1], red);
   if (threadIdx.x == 0) {
