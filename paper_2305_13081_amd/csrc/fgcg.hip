@@ -370,14 +370,15 @@ int scg_solve(fgcg_ctx* c, int which, const Key& key, const Op& op, const double
                      R, c->nx, c->ny, c->nz, c->part_b, c->part_rr);
   hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_b, nsb, 0, tol, maxit);
   HIPCHK(hipGetLastError());
-  const CgCtl cc{c->st, c->part_a, c->part_rr, nsb, nsb, 0, 0};
+  const int ndir = std::min(scg_chunks(c->nx, c->ny, c->nz), 2048);  // p.q partial sums in part_a
+  const CgCtl cc{c->st, c->part_a, c->part_rr, ndir, nsb, 0, 0};
   auto iter = [&]() -> int {
     set_kname(c, kind_dir, "k_scg_dir<%s%.0d", tname<T>(), 0);
     set_kname(c, kind_upd, "k_scg_upd<%s%.0d", tname<T>(), 0);
     T* pin = parity ? P1 : P0;
     T* pout = parity ? P0 : P1;
     parity ^= 1;
-    int r = launch(c, kind_dir, (const void*)&k_scg_dir<T, Op>, c->sgrid, op, (const T*)R, (const T*)pin, pout, Q,
+    int r = launch(c, kind_dir, (const void*)&k_scg_dir<T, Op>, dim3(ndir), op, (const T*)R, (const T*)pin, pout, Q,
                    c->nx, c->ny, c->nz, band, cc);
     r |= launch(c, kind_upd, (const void*)&k_scg_upd<T>, c->sgrid, X, R, (const T*)pout, (const T*)Q, c->nx,
                 c->rows, cc);

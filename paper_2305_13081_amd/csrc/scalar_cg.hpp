@@ -11,8 +11,8 @@
 // product (up to rounding) with one pass over the data.  CG is textbook CG;
 // one iteration is two passes:
 //   k_scg_dir : beta = rr_k / rr_{k-1} and the stop tests; p = r + beta p is
-//               formed at the voxel and at its four neighbours from r and the
-//               previous p (double-buffered by iteration parity), q = A p;
+//               formed from r and the previous p (double-buffered by iteration
+//               parity) once per voxel of an LDS tile, q = A p from the tile;
 //               writes p, q; sum p.q
 //   k_scg_upd : alpha = rr_k / p.q; x += alpha p; r -= alpha q; sum r.r
 // CG control is that of the other solves (cg_begin_dir / cg_begin_step):
@@ -56,18 +56,24 @@ __device__ __forceinline__ Nbr nbrs(int row, int x, int nx, int ny, int nz) {
   return b;
 }
 
-// Stencil operators.  v(j, x) is the value at linear index j (x coordinate x)
-// from a functor, so the CG direction p = r + beta p can be formed at the
-// neighbours on the fly.
+// Stencil operators.  apply_vals takes the value at the voxel and at its
+// neighbours vn = {x-1, x+1, y-1, y+1, z-1, z+1} (the z entries only on 3D
+// grids); apply gathers them from a functor v(j, x) (value at linear index j,
+// x coordinate x).
 struct PfStencil {
   const double* H;
   double a;     // Gc / (2 l0)
   double cih2;  // (Gc l0 / 2) / h^2
+  __device__ __forceinline__ double apply_vals(const Nbr& b, double v0, const double* vn) const {
+    double lap = (b.three ? 6.0 : 4.0) * v0 - vn[0] - vn[1] - vn[2] - vn[3];
+    if (b.three) lap = lap - vn[4] - vn[5];
+    return (a + H[b.i]) * v0 + cih2 * lap;
+  }
   template <typename V>
   __device__ __forceinline__ double apply(double v0, const V& v, const Nbr& b) const {
-    double lap = (b.three ? 6.0 : 4.0) * v0 - v(b.ixm, b.xm) - v(b.ixp, b.xp) - v(b.iym, b.x) - v(b.iyp, b.x);
-    if (b.three) lap = lap - v(b.izm, b.x) - v(b.izp, b.x);
-    return (a + H[b.i]) * v0 + cih2 * lap;
+    const double vn[6] = {v(b.ixm, b.xm), v(b.ixp, b.xp), v(b.iym, b.x), v(b.iyp, b.x),
+                          b.three ? v(b.izm, b.x) : 0.0, b.three ? v(b.izp, b.x) : 0.0};
+    return apply_vals(b, v0, vn);
   }
 };
 
@@ -80,47 +86,121 @@ struct DiffStencil {
     pick(co.dk, phase[j], d, kr);
     return d;
   }
-  template <typename V>
-  __device__ __forceinline__ double apply(double v0, const V& v, const Nbr& b) const {
+  __device__ __forceinline__ double apply_vals(const Nbr& b, double v0, const double* vn) const {
     double d0, kr;
     pick(co.dk, phase[b.i], d0, kr);
-    double flux = D(b.ixm) * (v0 - v(b.ixm, b.xm)) - d0 * (v(b.ixp, b.xp) - v0) + D(b.iym) * (v0 - v(b.iym, b.x)) -
-                  d0 * (v(b.iyp, b.x) - v0);
-    if (b.three) flux = flux + D(b.izm) * (v0 - v(b.izm, b.x)) - d0 * (v(b.izp, b.x) - v0);
+    double flux = D(b.ixm) * (v0 - vn[0]) - d0 * (vn[1] - v0) + D(b.iym) * (v0 - vn[2]) - d0 * (vn[3] - v0);
+    if (b.three) flux = flux + D(b.izm) * (v0 - vn[4]) - d0 * (vn[5] - v0);
     return (co.inv_dt + kr) * v0 + ih2 * flux;
+  }
+  template <typename V>
+  __device__ __forceinline__ double apply(double v0, const V& v, const Nbr& b) const {
+    const double vn[6] = {v(b.ixm, b.xm), v(b.ixp, b.xp), v(b.iym, b.x), v(b.iyp, b.x),
+                          b.three ? v(b.izm, b.x) : 0.0, b.three ? v(b.izp, b.x) : 0.0};
+    return apply_vals(b, v0, vn);
   }
 };
 
-// The kernels walk the rows (z ny + y) in XCD slabs (SlabIter); the grid is
-// one-dimensional with a multiple of 8 blocks.
+// k_scg_upd and k_scg_init walk the rows (z ny + y) in XCD slabs (SlabIter);
+// their grid is one-dimensional with a multiple of 8 blocks.
 
 // First pass of iteration k.  band > 0: voxels with x < band are fixed
 // (p = q = 0 there).
 // p is double-buffered (pin -> pout): the direction at the neighbours is formed
 // from the previous p, which other threads of this launch must not overwrite.
+//
+// Tiled: a block forms p = r + beta p once per voxel of an SC_TX x SC_TY tile
+// and its one-voxel halo ring into LDS and applies the stencil from there; on
+// 3D grids it marches the tile through SC_ZC planes with two LDS planes (z and
+// z + 1) and p of the plane below in registers.  Tile-chunks are ordered x, y,
+// z and each block walks a contiguous range of them, XCD by XCD.
+constexpr int SC_TX = 64, SC_TY = 16, SC_ZC = 8;
+
+inline int scg_chunks(int nx, int ny, int nz) {
+  return ((nx + SC_TX - 1) / SC_TX) * ((ny + SC_TY - 1) / SC_TY) * (nz > 1 ? (nz + SC_ZC - 1) / SC_ZC : 1);
+}
+
 template <typename T, class Op>
 __global__ void __launch_bounds__(NT) k_scg_dir(Op op, const T* __restrict__ r, const T* __restrict__ pin,
                                                 T* __restrict__ pout, T* __restrict__ q, int nx, int ny, int nz,
                                                 int band, CgCtl cc) {
+  constexpr int HX = SC_TX + 2, HY = SC_TY + 2, HP = HX * HY;
+  constexpr int RPT = SC_TY / (NT / SC_TX);  // own rows per thread
+  __shared__ double pl[2][HP];
   __shared__ double red[NT / 64];
   double beta;
   if (!cg_begin_dir(cc, 0, red, beta)) return;
   const bool first = beta == 0.0;  // beta is 0 exactly on the first iteration
   const T b = (T)beta;
-  auto pn = [&](long long j, int) -> double { return first ? (double)r[j] : (double)(r[j] + b * pin[j]); };
+  const bool three = nz > 1;
+  const long long plane = (long long)nx * ny;
+  auto pval = [&](long long j) -> double { return first ? (double)r[j] : (double)(r[j] + b * pin[j]); };
+  const int ntx = (nx + SC_TX - 1) / SC_TX, nty = (ny + SC_TY - 1) / SC_TY;
+  const int nch = ntx * nty * (three ? (nz + SC_ZC - 1) / SC_ZC : 1);
+  const int lb = xcd_block(), nb = gridDim.x;
+  const int c0 = (int)((long long)nch * lb / nb), c1 = (int)((long long)nch * (lb + 1) / nb);
+  const int tx = threadIdx.x & (SC_TX - 1), ty = threadIdx.x / SC_TX;
+  // halo tile of plane z: the tile, the columns x0 - 1 and x0 + SC_TX and the
+  // rows y0 - 1 and y0 + SC_TY (periodic); entries past the edge of a partial
+  // tile are never read and are skipped
+  auto fill = [&](double* buf, int x0, int y0, int z) {
+    for (int hp = threadIdx.x; hp < HP; hp += NT) {
+      const int hy = hp / HX, hx = hp - hy * HX;
+      int x = x0 - 1 + hx, y = y0 - 1 + hy;
+      if (x > nx || y > ny) continue;
+      x = x < 0 ? nx - 1 : (x == nx ? 0 : x);
+      y = y < 0 ? ny - 1 : (y == ny ? 0 : y);
+      buf[hp] = pval((long long)z * plane + (long long)y * nx + x);
+    }
+  };
   double acc = 0.0;
-  const SlabIter it(nx, (long long)ny * nz);
-  for (long long v = it.v0; v < it.v1; v += it.step) {
-    const int row = (int)((unsigned)v / (unsigned)nx), x = (int)(v - (long long)row * nx);
-    const Nbr nb = nbrs(row, x, nx, ny, nz);
-    const double p0 = pn(nb.i, x);
-    const double qv = x < band ? 0.0 : op.apply(p0, pn, nb);
-    pout[nb.i] = (T)p0;
-    q[nb.i] = (T)qv;
-    acc += p0 * qv;
+  for (int c = c0; c < c1; ++c) {
+    const int x0 = (c % ntx) * SC_TX, y0 = ((c / ntx) % nty) * SC_TY;
+    const int z0 = three ? (c / (ntx * nty)) * SC_ZC : 0;
+    const int z1 = three ? min(z0 + SC_ZC, nz) : 1;
+    const int xo = x0 + tx;
+    double pm[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int yo = y0 + ty + k * (NT / SC_TX);
+      pm[k] = 0.0;
+      if (three && xo < nx && yo < ny)
+        pm[k] = pval((long long)(z0 == 0 ? nz - 1 : z0 - 1) * plane + (long long)yo * nx + xo);
+    }
+    int cur = 0;
+    fill(pl[0], x0, y0, z0);
+    for (int z = z0; z < z1; ++z) {
+      if (three) fill(pl[cur ^ 1], x0, y0, z + 1 == nz ? 0 : z + 1);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int yy = ty + k * (NT / SC_TX);
+        const int yo = y0 + yy;
+        if (xo < nx && yo < ny) {
+          const int hp = (yy + 1) * HX + tx + 1;
+          const double* P = pl[cur];
+          const double v0 = P[hp];
+          const double vn[6] = {P[hp - 1], P[hp + 1], P[hp - HX], P[hp + HX], three ? pm[k] : 0.0,
+                                three ? pl[cur ^ 1][hp] : 0.0};
+          Nbr nbr;
+          nbr.i = ((long long)z * ny + yo) * nx + xo;
+          nbr.ixm = nbr.i + (xo == 0 ? nx - 1 : -1);
+          nbr.iym = nbr.i + (yo == 0 ? (long long)(ny - 1) * nx : -(long long)nx);
+          nbr.izm = nbr.i + (z == 0 ? (long long)(nz - 1) * plane : -plane);
+          nbr.three = three;
+          const double qv = xo < band ? 0.0 : op.apply_vals(nbr, v0, vn);
+          pout[nbr.i] = (T)v0;
+          q[nbr.i] = (T)qv;
+          acc += v0 * qv;
+          pm[k] = v0;
+        }
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
   }
   const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) cc.part_a[block_linear()] = t;
+  if (threadIdx.x == 0) cc.part_a[blockIdx.x] = t;
 }
 
 template <typename T>
