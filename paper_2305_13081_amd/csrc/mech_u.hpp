@@ -304,13 +304,26 @@ template <typename T, int NC = 2> struct MechUPro {
   __device__ bool begin(int s, double* red, double& sc) const {
     return mech_alpha(st + s, part_a + (long long)s * np_a, np_a, red, sc);
   }
-  __device__ void point(int s, int y, int xx, T* out, double&, double sc) const {
+  struct Ld {
+    T x[NC], r[NC], p[NC], q[NC];
+  };
+  __device__ void load(int s, int y, int xx, Ld& l) const {
+    const long long i = (long long)y * nx + xx;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      l.x[c] = x.at(s, c, i);
+      l.r[c] = r.at(s, c, i);
+      l.p[c] = p.at(s, c, i);
+      l.q[c] = q.at(s, c, i);
+    }
+  }
+  __device__ void apply(int s, int y, int xx, const Ld& l, T* out, double&, double sc) const {
     const long long i = (long long)y * nx + xx;
     const T a = (T)sc;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      x.at(s, c, i) += a * p.at(s, c, i);
-      const T rv = r.at(s, c, i) - a * q.at(s, c, i);
+      x.at(s, c, i) = l.x[c] + a * l.p[c];
+      const T rv = l.r[c] - a * l.q[c];
       r.at(s, c, i) = rv;
       out[c] = rv;
     }
@@ -419,10 +432,16 @@ template <typename T, int NC = 2> struct MechUEpi {
     }
     return true;
   }
-  __device__ void point(int s, int y, int xx, const T* z, double&, double sc) const {
+  static constexpr int NPRE = NC;  // p of the voxel, loaded before the transforms
+  __device__ void prefetch(int s, int y, int xx, T* pre) const {
     const long long i = (long long)y * nx + xx;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) p.at(s, c, i) = init ? z[c] : z[c] + (T)sc * p.at(s, c, i);
+    for (int c = 0; c < NC; ++c) pre[c] = init ? (T)0 : p.at(s, c, i);
+  }
+  __device__ void point(int s, int y, int xx, const T* z, double&, double sc, const T* pre) const {
+    const long long i = (long long)y * nx + xx;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) p.at(s, c, i) = init ? z[c] : z[c] + (T)sc * pre[c];
   }
   __device__ void partial(int, double) const {}
 };

@@ -76,6 +76,17 @@ template <typename T>
 __device__ __forceinline__ T* as_real(typename cvec<T>::type* p) { return reinterpret_cast<T*>(p); }
 
 // -------------------------------------------------------------- row forward
+// Prologues may split point() into load(s, y, x, Ld&) and apply(s, y, x,
+// const Ld&, out, acc, sc): the kernel then issues the loads of the next voxel
+// before the stores of the current one (the compiler cannot reorder them
+// itself, since the fields might alias).
+template <class P, class = void> struct ProLoads {
+  static constexpr bool value = false;
+};
+template <class P> struct ProLoads<P, decltype((void)sizeof(typename P::Ld))> {
+  static constexpr bool value = true;
+};
+
 template <typename T, int NX, int NOUT, class Pro>
 __global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type* spec, int ny,
                                                 long long spec_ss,
@@ -95,15 +106,41 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type*
   const int y0 = xcd_block() * ROWS;
   T vals[VPT][NOUT];
   double acc = 0.0;
-#pragma unroll
-  for (int i = 0; i < VPT; ++i) {
+  auto valid = [&](int i) {
     const int v = tid + i * NT;
-    const int row = v / NX, x = v - (v / NX) * NX;
-    if ((VOX % NT == 0 || v < VOX) && y0 + row < ny) {
-      pro.point(s, y0 + row, x, vals[i], acc, sc);
-    } else {
+    return (VOX % NT == 0 || v < VOX) && y0 + v / NX < ny;
+  };
+  if constexpr (ProLoads<Pro>::value) {
+    // loads of voxel i + 1 are issued before the stores of voxel i
+    typename Pro::Ld cur, nxt;
+    if (valid(0)) pro.load(s, y0 + tid / NX, tid % NX, cur);
 #pragma unroll
-      for (int c = 0; c < NOUT; ++c) vals[i][c] = (T)0;
+    for (int i = 0; i < VPT; ++i) {
+      const int v = tid + i * NT;
+      const int row = v / NX, x = v - (v / NX) * NX;
+      if (i + 1 < VPT && valid(i + 1)) {
+        const int v1 = v + NT;
+        pro.load(s, y0 + v1 / NX, v1 % NX, nxt);
+      }
+      if (valid(i)) {
+        pro.apply(s, y0 + row, x, cur, vals[i], acc, sc);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NOUT; ++c) vals[i][c] = (T)0;
+      }
+      cur = nxt;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int v = tid + i * NT;
+      const int row = v / NX, x = v - (v / NX) * NX;
+      if (valid(i)) {
+        pro.point(s, y0 + row, x, vals[i], acc, sc);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NOUT; ++c) vals[i][c] = (T)0;
+      }
     }
   }
   pro.partial(s, block_sum(acc, red));
@@ -178,6 +215,9 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
 }
 
 // Load NIN half spectra of ROWS rows, inverse transform, into registers.
+// The half spectrum of component c + 1 is loaded into registers before the
+// transform of component c (the barriers wait for LDS traffic only), so its
+// transposed reads overlap the LDS work.
 template <typename T, int NX, int NIN>
 __device__ __forceinline__ void rows_inverse(
     const typename cvec<T>::type* in, int ny, int y0, typename cvec<T>::type* buf,
@@ -188,23 +228,43 @@ __device__ __forceinline__ void rows_inverse(
   constexpr int NXH = NX / 2 + 1;
   constexpr int VOX = ROWS * NX;
   constexpr int VPT = (VOX + NT - 1) / NT;
+  constexpr int NL = (NXH * NP + NT - 1) / NT;  // (pair, kx) entries per thread
   const int tid = threadIdx.x;
   T* rb = as_real<T>(buf);
+  C ra[NL], rbv[NL];
+  auto load = [&](int c) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int idx = tid + l * NT;
+      ra[l] = C{(T)0, (T)0};
+      rbv[l] = C{(T)0, (T)0};
+      if (idx < NXH * NP) {
+        const int pair = idx % NP, kx = idx / NP;
+        const int y = y0 + 2 * pair;
+        const C* o = in + ((long long)c * NXH + kx) * ny;
+        if (y < ny) ra[l] = o[y];
+        if (y + 1 < ny) rbv[l] = o[y + 1];
+      }
+    }
+  };
+  load(0);
 #pragma unroll
   for (int c = 0; c < NIN; ++c) {
-    for (int idx = tid; idx < NXH * NP; idx += NT) {
-      const int pair = idx % NP, kx = idx / NP;
-      const int y = y0 + 2 * pair;
-      const C* o = in + ((long long)c * NXH + kx) * ny;
-      C a = y < ny ? o[y] : C{(T)0, (T)0};
-      C b = y + 1 < ny ? o[y + 1] : C{(T)0, (T)0};
-      if (kx == 0 || 2 * kx == NX) {
-        a.y = (T)0;
-        b.y = (T)0;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int idx = tid + l * NT;
+      if (idx < NXH * NP) {
+        const int pair = idx % NP, kx = idx / NP;
+        C a = ra[l], b = rbv[l];
+        if (kx == 0 || 2 * kx == NX) {
+          a.y = (T)0;
+          b.y = (T)0;
+        }
+        buf[lds(pair * NX + kx)] = C{a.x - b.y, a.y + b.x};
+        if (kx > 0 && 2 * kx < NX) buf[lds(pair * NX + NX - kx)] = C{a.x + b.y, b.x - a.y};
       }
-      buf[lds(pair * NX + kx)] = C{a.x - b.y, a.y + b.x};
-      if (kx > 0 && 2 * kx < NX) buf[lds(pair * NX + NX - kx)] = C{a.x + b.y, b.x - a.y};
     }
+    if (c + 1 < NIN) load(c + 1);
     __syncthreads();
     fft_lds<T, NX, NP, NT, true>(buf, tw);
 #pragma unroll
@@ -220,6 +280,17 @@ __device__ __forceinline__ void rows_inverse(
 }
 
 // -------------------------------------------------------------- row inverse
+// Epilogues that read fields of their own voxels may declare NPRE > 0 and a
+// prefetch(s, y, x, pre) member: those values are loaded into registers
+// before the transforms and handed to point(..., pre), so their reads overlap
+// the LDS work instead of following it.
+template <class E, class = void> struct EpiPre {
+  static constexpr int N = 0;
+};
+template <class E> struct EpiPre<E, decltype((void)E::NPRE)> {
+  static constexpr int N = E::NPRE;
+};
+
 template <typename T, int NX, int NIN, class Epi>
 __global__ void __launch_bounds__(NT) k_row_inv(Epi epi, const typename cvec<T>::type* spec, int ny,
                                                 long long spec_ss,
@@ -229,6 +300,7 @@ __global__ void __launch_bounds__(NT) k_row_inv(Epi epi, const typename cvec<T>:
   constexpr int NP = ROWS / 2;
   constexpr int VOX = ROWS * NX;
   constexpr int VPT = (VOX + NT - 1) / NT;
+  constexpr int NPRE = EpiPre<Epi>::N;
   __shared__ C buf[lds_size(NP * NX)];
   __shared__ double red[NT / 64];
   const int s = blockIdx.y;
@@ -236,6 +308,15 @@ __global__ void __launch_bounds__(NT) k_row_inv(Epi epi, const typename cvec<T>:
   double sc = 0.0;
   if (!epi.begin(s, red, sc)) return;
   const int y0 = xcd_block() * ROWS;
+  T pre[VPT][NPRE > 0 ? NPRE : 1];
+  if constexpr (NPRE > 0) {
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int v = tid + i * NT;
+      const int row = v / NX, x = v - (v / NX) * NX;
+      if ((VOX % NT == 0 || v < VOX) && y0 + row < ny) epi.prefetch(s, y0 + row, x, pre[i]);
+    }
+  }
   T vals[VPT][NIN];
   rows_inverse<T, NX, NIN>(spec + s * spec_ss, ny, y0, buf, vals, tw);
   double acc = 0.0;
@@ -243,7 +324,12 @@ __global__ void __launch_bounds__(NT) k_row_inv(Epi epi, const typename cvec<T>:
   for (int i = 0; i < VPT; ++i) {
     const int v = tid + i * NT;
     const int row = v / NX, x = v - (v / NX) * NX;
-    if ((VOX % NT == 0 || v < VOX) && y0 + row < ny) epi.point(s, y0 + row, x, vals[i], acc, sc);
+    if ((VOX % NT == 0 || v < VOX) && y0 + row < ny) {
+      if constexpr (NPRE > 0)
+        epi.point(s, y0 + row, x, vals[i], acc, sc, pre[i]);
+      else
+        epi.point(s, y0 + row, x, vals[i], acc, sc);
+    }
   }
   epi.partial(s, block_sum(acc, red));
 }
