@@ -41,10 +41,10 @@ int nslab(const fgcg_ctx* c) {
   return std::max(8, std::min(1024, rows) & ~7);
 }
 
-int ztiles(const fgcg_ctx* c) {
+template <typename T> int ztiles(const fgcg_ctx* c) {
   int nty = 0;
   with_n3(c->nz, [&](auto NZc) {
-    constexpr int YT = ztile_for(decltype(NZc)::value);
+    constexpr int YT = ztile_for<T>(decltype(NZc)::value);
     nty = (c->ny + YT - 1) / YT;
   });
   return nty;
@@ -70,7 +70,7 @@ int launch_ypass(fgcg_ctx* c, int kind, bool inv, const CgState* st, CT<T>* spec
 template <typename T, bool FWD, bool INV, class Sym>
 int launch_zpass(fgcg_ctx* c, int kind, const Sym& sym, CT<T>* spec, int ncomp) {
   int rc = 0;
-  const int nty = ztiles(c);
+  const int nty = ztiles<T>(c);
   with_n3(c->nz, [&](auto NZc) {
     constexpr int NZ = decltype(NZc)::value;
     dim3 g(ncomp * c->nxh * nty);
@@ -185,7 +185,8 @@ int alloc3d(fgcg_ctx* c) {
   HIPCHK(hipMemcpy(c->Dz, dz.data(), sizeof(double2) * c->nz, hipMemcpyHostToDevice));
   HIPCHK(hipMalloc(&c->red, sizeof(double) * 8));
   HIPCHK(hipMemset(c->red, 0, sizeof(double) * 8));
-  c->nzb = 3 * c->nxh * ztiles(c);
+  // z-pass blocks of the solver's precision (the FP64 debug transform has no partial sums)
+  c->nzb = 3 * c->nxh * (c->prec == FGCG_FP64 ? ztiles<double>(c) : ztiles<float>(c));
   HIPCHK(hipMalloc(&c->part_z, sizeof(double) * c->nzb));
   c->nslab = nslab(c);
   return 0;

@@ -20,8 +20,11 @@ namespace fgcg {
 
 // y lines per block: at least about 1024 complex values per block.
 constexpr int ylines_for(int ny, int nc) { return nc * ny >= 1024 ? 1 : 1024 / (nc * ny); }
-// ky values per z tile: 16 (256 contiguous bytes in FP64), 8 for long z lines.
-constexpr int ztile_for(int nz) { return nz > 256 ? 8 : 16; }
+// ky values per z tile: 128 contiguous bytes per z (8 in FP64, 16 in FP32),
+// half that for z lines longer than 256.
+template <typename T> constexpr int ztile_for(int nz) {
+  return (sizeof(T) == 8 ? 8 : 16) / (nz > 256 ? 2 : 1);
+}
 
 // Deterministic single-block sum of np partial sums into out[0].
 __global__ void __launch_bounds__(NT) k_reduce(const double* __restrict__ part, int np, double* out) {
@@ -64,7 +67,7 @@ __global__ void __launch_bounds__(NT) k_zpass(Sym sym, typename cvec<T>::type* s
                                               const typename cvec<T>::type* __restrict__ tw) {
   using C = typename cvec<T>::type;
   using Idx = PitchIdx<NZ>;
-  constexpr int YT = ztile_for(NZ);
+  constexpr int YT = ztile_for<T>(NZ);
   __shared__ C buf[YT * pitch_for(NZ)];
   __shared__ double red[NT / 64];
   if (!sym.begin()) return;
