@@ -102,9 +102,19 @@ const char* fgcg_last_error(void);
  *   FGCG_OPT_GRAPHS           1 (default): CG iterations are replayed as HIP
  *       graphs of FGCG_OPT_CHUNK iterations; 0: plain launches.
  *   FGCG_OPT_CHUNK            iterations per graph chunk, even, 2..256 (default 16).
+ *   FGCG_OPT_ROWS             2D grids: rows per block of the mechanics row
+ *       passes (the forward pass with the CG update, the inverse pass with the
+ *       direction update).  0 (default): autotune, i.e. time every candidate
+ *       (the default for nx times 1/2, 1 and 2, even, 2..16, at most 4096
+ *       voxels per block) on the context's own workspace before the next
+ *       mechanics solve and keep the fastest; or a candidate value, fixed.
+ *       The choice changes timing only, never results.  EUNSUPPORTED in 3D.
  * Returns EINVAL for an unknown option or value. */
-enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2 };
+enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2, FGCG_OPT_ROWS = 3 };
 int fgcg_set_option(fgcg_ctx* ctx, int option, int value);
+/* Current value of an option (FGCG_OPT_ROWS: the tuned or fixed rows per
+ * block, 0 before the first mechanics solve of an autotuned context). */
+int fgcg_get_option(fgcg_ctx* ctx, int option, int* value);
 
 /* Mechanical equilibrium with isotropic eigenstrain e(x) I (Sec. 2.3,
  * eq. solid): solves G[g C : sym(x)] = -G[g C : (eps_mac - e I)] for the

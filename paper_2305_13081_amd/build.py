@@ -6,7 +6,9 @@ compiles every translation unit under ``csrc/`` (``fgcg.hip``: the C ABI and
 the 2D solvers; ``fgcg3d.hip``: the 3D solvers) for gfx950 with hipcc, in
 parallel, and links them into ``libfgcg.so`` next to this file (the library
 the binding loads).  Packed-FP32 instruction selection is disabled for every
-HIP translation unit.  Objects go to ``_build/`` beside the package.
+HIP translation unit, and floating-point contraction is limited to single
+expressions (results do not depend on how a template is instantiated).
+Objects go to ``_build/`` beside the package.
 """
 import os
 import subprocess
@@ -25,6 +27,9 @@ COMPILE_FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused per source expression only, so every
+    # instantiation of a kernel template (rows per block, tiles) rounds alike
+    "-ffp-contract=on",
     "-I" + os.path.join(ROOT, "include"),
 ]
 LINK_FLAGS = ["--offload-arch=gfx950", "-shared", "-fPIC"]

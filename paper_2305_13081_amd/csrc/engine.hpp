@@ -108,6 +108,7 @@ struct fgcg_ctx {
   double* h_part = nullptr;
   int nrow = 0, ncol = 0, npost = 0, nkp = 0;
   int nkpt = 0;  // blocks of the tiled 2D stiffness pass (one partial sum each)
+  int rows_pick = 0;  // 2D mechanics row passes: rows per block (0: time the candidates at the next solve)
   int nsamp = 1;            // samples of this grid size (batches)
   double* ems = nullptr;    // device [nsamp][3] macro strains
   bool batch = false;            // member of a batch (owns the gather buffers below)
@@ -282,16 +283,57 @@ int launch(fgcg_ctx* c, int kind, const void* fn, dim3 grid, A... args) {
   return 0;
 }
 
-template <typename T, int NOUT, class Pro>
+// Rows per block of the tunable row passes: rows_for(NX) times 1/2, 1 or 2,
+// even, 2..16 and at most 4096 voxels per block (rows_for itself always).
+constexpr bool rows_ok(int NX, int R) {
+  return R == rows_for(NX) || (R >= 2 && R % 2 == 0 && R <= 16 && R * NX <= 4096);
+}
+
+template <int NX> inline std::vector<int> rows_candidates() {
+  constexpr int R0 = rows_for(NX);
+  std::vector<int> v;
+  if (rows_ok(NX, R0 / 2)) v.push_back(R0 / 2);
+  v.push_back(R0);
+  if (rows_ok(NX, 2 * R0)) v.push_back(2 * R0);
+  return v;
+}
+
+// Calls f(integral_constant<int, R>) with R = pick if it is a candidate, else
+// the default rows_for(NX).
+template <int NX, class F> void with_rows(int pick, F&& f) {
+  constexpr int R0 = rows_for(NX);
+  if constexpr (R0 / 2 != R0 && rows_ok(NX, R0 / 2)) {
+    if (pick == R0 / 2) {
+      f(std::integral_constant<int, R0 / 2>{});
+      return;
+    }
+  }
+  if constexpr (rows_ok(NX, 2 * R0)) {
+    if (pick == 2 * R0) {
+      f(std::integral_constant<int, 2 * R0>{});
+      return;
+    }
+  }
+  f(std::integral_constant<int, R0>{});
+}
+
+// TUNED: the rows per block come from c->rows_pick (the mechanics passes of
+// 2D contexts); otherwise rows_for(NX).
+template <typename T, int NOUT, class Pro, bool TUNED = false>
 int launch_row_fwd(fgcg_ctx* c, int kind, const Pro& pro, CT<T>* spec, int nsamp = 1, long long ss = 0) {
   int rc = 0;
   with_n(c->nx, [&](auto NXc) {
     constexpr int NX = decltype(NXc)::value;
-    constexpr int R = rows_for(NX);
-    dim3 g((c->rows + R - 1) / R, nsamp);
-    if (kind >= 0) set_kname(c, kind, "k_row_fwd<%s, %d", tname<T>(), NX);
-    rc = launch(c, kind, (const void*)&k_row_fwd<T, NX, NOUT, Pro>, g, pro, spec, c->rows, ss,
-                tw_x<T>(c));
+    auto go = [&](auto Rc) {
+      constexpr int R = decltype(Rc)::value;
+      dim3 g((c->rows + R - 1) / R, nsamp);
+      if (kind >= 0) set_kname(c, kind, "k_row_fwd<%s, %d", tname<T>(), NX);
+      rc = launch(c, kind, (const void*)&k_row_fwd<T, NX, NOUT, Pro, R>, g, pro, spec, c->rows, ss, tw_x<T>(c));
+    };
+    if constexpr (TUNED)
+      with_rows<NX>(c->rows_pick, go);
+    else
+      go(std::integral_constant<int, rows_for(NX)>{});
   });
   return rc;
 }
@@ -310,17 +352,22 @@ int launch_col(fgcg_ctx* c, int kind, const Sym& sym, const CT<T>* in, CT<T>* ou
   return rc;
 }
 
-template <typename T, int NIN, class Epi>
+template <typename T, int NIN, class Epi, bool TUNED = false>
 int launch_row_inv(fgcg_ctx* c, int kind, const Epi& epi, const CT<T>* spec, int nsamp = 1,
                    long long ss = 0) {
   int rc = 0;
   with_n(c->nx, [&](auto NXc) {
     constexpr int NX = decltype(NXc)::value;
-    constexpr int R = rows_for(NX);
-    dim3 g((c->rows + R - 1) / R, nsamp);
-    if (kind >= 0) set_kname(c, kind, "k_row_inv<%s, %d", tname<T>(), NX);
-    rc = launch(c, kind, (const void*)&k_row_inv<T, NX, NIN, Epi>, g, epi, spec, c->rows, ss,
-                tw_x<T>(c));
+    auto go = [&](auto Rc) {
+      constexpr int R = decltype(Rc)::value;
+      dim3 g((c->rows + R - 1) / R, nsamp);
+      if (kind >= 0) set_kname(c, kind, "k_row_inv<%s, %d", tname<T>(), NX);
+      rc = launch(c, kind, (const void*)&k_row_inv<T, NX, NIN, Epi, R>, g, epi, spec, c->rows, ss, tw_x<T>(c));
+    };
+    if constexpr (TUNED)
+      with_rows<NX>(c->rows_pick, go);
+    else
+      go(std::integral_constant<int, rows_for(NX)>{});
   });
   return rc;
 }

@@ -1,5 +1,7 @@
 // Entry points of the fgcg C ABI declared in include/fgcg.h and the 2D
 // solvers (3D grids are handled in fgcg3d.hip).
+#include <algorithm>
+
 #include "adjoint.hpp"
 #include "engine.hpp"
 
@@ -24,11 +26,11 @@ template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, i
   const long long ss = spec_ss(c);
   int rc;
   const CopyProN<T, 2> cp{fld<T>(c->r, c), c->nx};
-  if ((rc = launch_row_fwd<T, 2>(c, -1, cp, spec, ns, ss))) return rc;
+  if ((rc = launch_row_fwd<T, 2, CopyProN<T, 2>, true>(c, -1, cp, spec, ns, ss))) return rc;
   const MechGreen<T> g0{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
   if ((rc = launch_col<T, 1, 1>(c, -1, g0, spec, spec, 2 * ns, ss / 2))) return rc;
   const MechUEpi<T> e0{fld<T>(c->p, c), c->nx, c->st, c->part_rr, 2 * c->ncol, 1, tol, maxit};
-  if ((rc = launch_row_inv<T, 2>(c, -1, e0, spec, ns, ss))) return rc;
+  if ((rc = launch_row_inv<T, 2, MechUEpi<T>, true>(c, -1, e0, spec, ns, ss))) return rc;
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -45,19 +47,19 @@ template <typename T> int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, i
                  c->nx, c->ny, (T)(1.0 / c->h), c->st, c->part_a);
   if (!reliable) {
     const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt};
-    r |= launch_row_fwd<T, 2>(c, FGCG_K_MECH_ROW_FWD, pro, spec, ns, ss);
+    r |= launch_row_fwd<T, 2, MechUPro<T>, true>(c, FGCG_K_MECH_ROW_FWD, pro, spec, ns, ss);
   } else {
     r |= launch(c, -1, (const void*)&k_mech_fold<T>, dim3(c->npost, ns), X.p, c->xh, (const T*)P.p, 2 * c->n, c->st,
                 (const double*)c->part_a, c->nkpt);
     r |= launch(c, -1, (const void*)&k_mech_true_res<T>, dim3(c->nkp, ns), m, (const double*)c->xh,
                 (const double*)c->fh, R.p, c->n, c->nx, c->ny, 1.0 / c->h, (const CgState*)c->st);
     const CopyProN<T, 2> cp{R, c->nx};
-    r |= launch_row_fwd<T, 2>(c, -1, cp, spec, ns, ss);
+    r |= launch_row_fwd<T, 2, CopyProN<T, 2>, true>(c, -1, cp, spec, ns, ss);
   }
   const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, c->st, c->part_rr};
   r |= launch_col<T, 1, 1>(c, FGCG_K_MECH_COL, green, spec, spec, 2 * ns, ss / 2);
   const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, tol, maxit};
-  r |= launch_row_inv<T, 2>(c, FGCG_K_MECH_ROW_INV, epi, spec, ns, ss);
+  r |= launch_row_inv<T, 2, MechUEpi<T>, true>(c, FGCG_K_MECH_ROW_INV, epi, spec, ns, ss);
   return r;
 }
 
@@ -82,8 +84,77 @@ int mech_rhs(fgcg_ctx* c, const MechMat& m, const double* eig) {
 Key mech_key(const fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
   Key key;
   key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm).add(c->prec);
-  key.add(tol).add(maxit);
+  key.add(tol).add(maxit).add(c->rows_pick);
   return key;
+}
+
+// Autotuning of the rows per block of the mechanics row passes (the forward
+// pass with the CG update and the inverse pass with the direction update): each
+// candidate is timed with HIP events on the context's own workspace and
+// samples, 3 + 10 launches of the pair, and the fastest is kept.  The choice
+// does not change any result (rows are paired and transformed identically;
+// these passes carry no partial sums).  The workspace and the CG state are
+// scratch here: every solve initialises them afterwards.
+template <typename T> int tune_rows_t(fgcg_ctx* c) {
+  std::vector<int> cand;
+  with_n(c->nx, [&](auto NXc) { cand = rows_candidates<decltype(NXc)::value>(); });
+  if (cand.size() == 1) {
+    c->rows_pick = cand[0];
+    return 0;
+  }
+  const int ns = c->nsamp;
+  const long long ss = spec_ss(c);
+  std::vector<CgState> hs(ns);
+  for (CgState& t : hs) {
+    std::memset(&t, 0, sizeof t);
+    t.rz[0] = t.rz[1] = 1.0;
+    t.bnorm2 = 1.0;
+    t.maxit = 1 << 30;
+  }
+  HIPCHK(hipMemcpyAsync(c->st, hs.data(), sizeof(CgState) * ns, hipMemcpyHostToDevice, c->stream));
+  const size_t nv = sizeof(T) * 4 * (size_t)c->n * ns;
+  for (void* b : {c->x, c->r, c->p, c->tmp}) HIPCHK(hipMemsetAsync(b, 0, nv, c->stream));
+  HIPCHK(hipMemsetAsync(c->spec, 0, sizeof(CT<T>) * 4 * (size_t)c->nxh * c->rows * ns, c->stream));
+  const int npa = c->nkpt, nprz = 2 * c->ncol;
+  std::vector<double> ones((size_t)std::max(npa, nprz) * ns, 1.0);
+  HIPCHK(hipMemcpyAsync(c->part_a, ones.data(), sizeof(double) * npa * ns, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->part_rr, ones.data(), sizeof(double) * nprz * ns, hipMemcpyHostToDevice, c->stream));
+  CT<T>* spec = (CT<T>*)c->spec;
+  const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
+  const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, npa};
+  const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, nprz, 0, 0.0, 1 << 30};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 0.f;
+  int pick = cand[0], rc = 0;
+  for (int R_ : cand) {
+    c->rows_pick = R_;
+    for (int rep = 0; rep < 13 && !rc; ++rep) {
+      if (rep == 3 && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(FGCG_EHIP, "hipEventRecord");
+      rc |= launch_row_fwd<T, 2, MechUPro<T>, true>(c, -1, pro, spec, ns, ss);
+      rc |= launch_row_inv<T, 2, MechUEpi<T>, true>(c, -1, epi, spec, ns, ss);
+    }
+    float ms = 0.f;
+    if (!rc && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = fail(FGCG_EHIP, "timing a row-pass candidate failed");
+    if (rc) break;
+    if (R_ == cand[0] || ms < best) {
+      best = ms;
+      pick = R_;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(hipGetLastError());
+  c->rows_pick = pick;
+  return rc;
+}
+
+inline int tune_rows(fgcg_ctx* c) {
+  if (c->rows_pick) return 0;
+  return c->prec == FGCG_FP64 ? tune_rows_t<double>(c) : tune_rows_t<float>(c);
 }
 
 // Builds the iteration closure of a context (period RELIABLE_EVERY in FP32-mixed).
@@ -103,6 +174,7 @@ struct MechIterFn {
 
 // Solve from the right-hand side in R (X = 0); the result stays in X (FP64)
 // or X + XH (FP32-mixed, folded into XH at the end).
+// (The rows per block must have been tuned already: tuning overwrites the workspace.)
 int mech_pcg(fgcg_ctx* c, const MechMat& m, double tol, int maxit, CgState* out) {
   int rc = c->prec == FGCG_FP64 ? mech_init<double>(c, m, tol, maxit) : mech_init<float>(c, m, tol, maxit);
   if (rc) return rc;
@@ -157,7 +229,7 @@ int mech_solve_single(fgcg_ctx* c, const MechMat& m, const double* eig, const do
                       double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
   const double t0 = now();
   int rc;
-  if ((rc = upload_ems(c, em)) || (rc = mech_rhs(c, m, eig))) return rc;
+  if ((rc = tune_rows(c)) || (rc = upload_ems(c, em)) || (rc = mech_rhs(c, m, eig))) return rc;
   CgState s;
   if ((rc = mech_pcg(c, m, tol, maxit, &s))) return rc;
   double e;
@@ -625,8 +697,28 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
       c->chunk = value;
       for (auto& g : c->graphs) release_graph(c, g);
       return FGCG_OK;
+    case FGCG_OPT_ROWS: {
+      if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "rows per block are tuned on 2D grids");
+      std::vector<int> cand;
+      with_n(c->nx, [&](auto NXc) { cand = rows_candidates<decltype(NXc)::value>(); });
+      if (value != 0 && std::find(cand.begin(), cand.end(), value) == cand.end())
+        return fail(FGCG_EINVAL, "rows per block must be 0 or one of the candidates for this nx");
+      c->rows_pick = value;
+      return FGCG_OK;
+    }
     default:
       return fail(FGCG_EINVAL, "unknown option");
+  }
+}
+
+int fgcg_get_option(fgcg_ctx* c, int option, int* value) {
+  if (!c || !value) return fail(FGCG_EINVAL, "ctx/value is NULL");
+  switch (option) {
+    case FGCG_OPT_SCALAR_SPECTRAL: *value = c->scalar_spectral; return FGCG_OK;
+    case FGCG_OPT_GRAPHS: *value = c->use_graphs ? 1 : 0; return FGCG_OK;
+    case FGCG_OPT_CHUNK: *value = c->chunk; return FGCG_OK;
+    case FGCG_OPT_ROWS: *value = c->rows_pick; return FGCG_OK;
+    default: return fail(FGCG_EINVAL, "unknown option");
   }
 }
 
@@ -932,7 +1024,7 @@ int fgcg_mech_solve_batched(fgcg_batch* b, const uint8_t* const* phases, int nph
                             st));
       for (int j = 0; j < 3; ++j) em[3 * s + j] = eps_mac[3 * mem[s] + j];
     }
-    if ((rc = upload_ems(c, em.data())) || (rc = mech_rhs(c, mats[g], nullptr))) return rc;
+    if ((rc = tune_rows(c)) || (rc = upload_ems(c, em.data())) || (rc = mech_rhs(c, mats[g], nullptr))) return rc;
     rc = c->prec == FGCG_FP64 ? mech_init<double>(c, mats[g], tol, maxit) : mech_init<float>(c, mats[g], tol, maxit);
     if (rc) return rc;
   }
@@ -954,6 +1046,7 @@ int fgcg_mech_solve_batched(fgcg_batch* b, const uint8_t* const* phases, int nph
     const int K = c0->prec == FGCG_FP64 ? c0->chunk : 2 * RELIABLE_EVERY;
     Key key = mech_key(c0, mats[0], tol, maxit);
     key.add(K);
+    for (fgcg_ctx* cg : b->groups) key.add(cg->rows_pick);
     if (key.b != b->key || !b->exec[0] || !b->exec[1]) {
       for (auto& e : b->exec)
         if (e) (void)hipGraphExecDestroy(e);

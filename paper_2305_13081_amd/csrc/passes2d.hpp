@@ -56,8 +56,10 @@ __device__ __forceinline__ double block_sum_array(const double* a, int n, double
   return block_sum(t, red);
 }
 
-// Rows per block of the row passes: about 2048 voxels per block, so a 1024^2
-// grid gives 512 blocks (two per CU) instead of one block per CU.
+// Default rows per block of the row passes: about 2048 voxels per block, so a
+// 1024^2 grid gives 512 blocks (two per CU) instead of one block per CU.  The
+// mechanics passes of 2D contexts take ROWS as a template argument chosen at
+// run time among rows_for / 2, rows_for and 2 rows_for by timing them.
 constexpr int rows_for(int nx) {
   return nx >= 768 ? 2 : nx >= 384 ? 4 : nx >= 256 ? 8 : 16;
 }
@@ -87,12 +89,12 @@ template <class P> struct ProLoads<P, decltype((void)sizeof(typename P::Ld))> {
   static constexpr bool value = true;
 };
 
-template <typename T, int NX, int NOUT, class Pro>
+template <typename T, int NX, int NOUT, class Pro, int ROWS = rows_for(NX)>
 __global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type* spec, int ny,
                                                 long long spec_ss,
                                                 const typename cvec<T>::type* __restrict__ tw) {
   using C = typename cvec<T>::type;
-  constexpr int ROWS = rows_for(NX);
+  static_assert(ROWS >= 2 && ROWS % 2 == 0, "rows per block: even, at least 2");
   constexpr int NP = ROWS / 2;
   constexpr int NXH = NX / 2 + 1;
   constexpr int VOX = ROWS * NX;
@@ -218,12 +220,12 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
 // The half spectrum of component c + 1 is loaded into registers before the
 // transform of component c (the barriers wait for LDS traffic only), so its
 // transposed reads overlap the LDS work.
-template <typename T, int NX, int NIN>
+template <typename T, int NX, int NIN, int ROWS = rows_for(NX)>
 __device__ __forceinline__ void rows_inverse(
     const typename cvec<T>::type* in, int ny, int y0, typename cvec<T>::type* buf,
     T (*vals)[NIN], const typename cvec<T>::type* __restrict__ tw) {
   using C = typename cvec<T>::type;
-  constexpr int ROWS = rows_for(NX);
+  static_assert(ROWS >= 2 && ROWS % 2 == 0, "rows per block: even, at least 2");
   constexpr int NP = ROWS / 2;
   constexpr int NXH = NX / 2 + 1;
   constexpr int VOX = ROWS * NX;
@@ -291,12 +293,12 @@ template <class E> struct EpiPre<E, decltype((void)E::NPRE)> {
   static constexpr int N = E::NPRE;
 };
 
-template <typename T, int NX, int NIN, class Epi>
+template <typename T, int NX, int NIN, class Epi, int ROWS = rows_for(NX)>
 __global__ void __launch_bounds__(NT) k_row_inv(Epi epi, const typename cvec<T>::type* spec, int ny,
                                                 long long spec_ss,
                                                 const typename cvec<T>::type* __restrict__ tw) {
   using C = typename cvec<T>::type;
-  constexpr int ROWS = rows_for(NX);
+  static_assert(ROWS >= 2 && ROWS % 2 == 0, "rows per block: even, at least 2");
   constexpr int NP = ROWS / 2;
   constexpr int VOX = ROWS * NX;
   constexpr int VPT = (VOX + NT - 1) / NT;
@@ -318,7 +320,7 @@ __global__ void __launch_bounds__(NT) k_row_inv(Epi epi, const typename cvec<T>:
     }
   }
   T vals[VPT][NIN];
-  rows_inverse<T, NX, NIN>(spec + s * spec_ss, ny, y0, buf, vals, tw);
+  rows_inverse<T, NX, NIN, ROWS>(spec + s * spec_ss, ny, y0, buf, vals, tw);
   double acc = 0.0;
 #pragma unroll
   for (int i = 0; i < VPT; ++i) {

@@ -89,6 +89,7 @@ _SIGS = {
     "fgcg_strerror": (ctypes.c_char_p, [_ip]),
     "fgcg_last_error": (ctypes.c_char_p, []),
     "fgcg_set_option": (_ip, [_vp, _ip, _ip]),
+    "fgcg_get_option": (_ip, [_vp, _ip, ctypes.POINTER(ctypes.c_int)]),
     "fgcg_mech_solve": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _dp, ctypes.c_double, _ip,
                               _vp, _vp, _dp, _dp, ctypes.POINTER(Info)]),
     "fgcg_mech_adjoint": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _dp, _vp, _ip,
@@ -180,10 +181,15 @@ class Context:
         except Exception:
             pass
 
-    OPTIONS = {"scalar_spectral": 0, "graphs": 1, "chunk": 2}
+    OPTIONS = {"scalar_spectral": 0, "graphs": 1, "chunk": 2, "rows": 3}
 
     def set_option(self, name, value):
         _check(self.lib.fgcg_set_option(self.ptr, self.OPTIONS[name], int(value)), "fgcg_set_option")
+
+    def get_option(self, name):
+        v = ctypes.c_int()
+        _check(self.lib.fgcg_get_option(self.ptr, self.OPTIONS[name], ctypes.byref(v)), "fgcg_get_option")
+        return v.value
 
     # ----------------------------------------------------------- helpers
     def _sync_stream(self):
