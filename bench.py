@@ -78,7 +78,9 @@ KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "
 # recorded under profiles/ (scaled by the copy probe), valid only for the
 # kernel sources they were taken with: the key is the SHA-256 of csrc/.
 MEASURED_TRAFFIC = {
-    # source hash -> {kernel kind: bytes per launch}
+    # source hash -> {kernel kind: bytes per launch} (profiles/mech_passes_1024_fp64_hbm_traffic.md)
+    "979afb408891e534e0869dda8adb432da9beeaa40fe2ac0a00581c6a16b8fbbd": {
+        "mech_row_fwd": 114832989, "mech_row_inv": 49382578, "mech_kp": 42317164, "mech_col": 33189043},
 }
 
 
