@@ -1,10 +1,13 @@
-// Physics functors plugged into the fused 2D passes, and CG control.
+// Physics functors plugged into the fused 2D passes, CG control state, and
+// the materials.
 //
-// Mechanics (Sec. 2.3, App. A): unknown = full displacement gradient F,
-// components [F11, F12, F21, F22] with F_ij = d u_i / d x_j; stress Voigt
-// [s11, s22, s12]; sigma = g(d) (lambda tr(e) I + 2 mu e), g = (1-d)^2 + kappa
-// (Sec. 2.4); projection F_ij(k) = D_j(k) sum_l conj(D_l(k)) s_il(k) / |D(k)|^2,
-// zero at |D| = 0, with the forward-difference symbol of Sec. 2.6.
+// Mechanics in strain form (Sec. 2.3, App. A), used by the operator test hook
+// fgcg_mech_apply: unknown = full displacement gradient F, components
+// [F11, F12, F21, F22] with F_ij = d u_i / d x_j; stress Voigt [s11, s22, s12];
+// sigma = g(d) (lambda tr(e) I + 2 mu e), g = (1-d)^2 + kappa (Sec. 2.4);
+// projection F_ij(k) = D_j(k) sum_l conj(D_l(k)) s_il(k) / |D(k)|^2, zero at
+// |D| = 0, with the forward-difference symbol of Sec. 2.6.  (The mechanics
+// solver iterates on the displacement instead: mech_u.hpp, mech3.hpp.)
 //
 // Phase field (Sec. 2.4, eq. crack-fft): A d = (Gc/(2 l0) + H) d
 // + (Gc l0 / 2) F^-1[|D|^2 F d].
@@ -12,17 +15,15 @@
 // Diffusion step: A c = (1/dt + k_r) c + sum_a F^-1[conj(D_a) F[D(x) F^-1[D_a F c]]],
 // on the free voxels of a Dirichlet band x < band_width.
 //
-// CG control.  Each CG iteration k is three (mechanics, phase field) or five
-// (diffusion) launches.  The first pass of iteration k reduces the partial
-// sums of r.r left by iteration k-1, checks convergence, forms beta and
-// updates p = r + beta p in its prologue, and accumulates p.Ap partial sums
-// from the pointwise quantities it already has: p : g C : sym(p) for
-// mechanics (p lies in the range of the projection, so p.G[Cp] = p.Cp), the
-// diagonal part plus the Parseval sum of the Laplacian part for the phase
-// field, and the diagonal part plus sum D |grad p|^2 for diffusion.  The last
-// pass then knows alpha = r.r / p.Ap and applies x += alpha p, r -= alpha q
-// without ever storing q.  All sums are FP64, block-reduced in a fixed order,
-// so repeated runs are bitwise identical.
+// The CG solves of these scalar operators through the FFT passes (the
+// spectral option) take three (phase field) or five (diffusion) launches per
+// iteration: the first pass reduces the partial sums of r.r left by the
+// previous iteration, checks convergence, forms beta and p = r + beta p in its
+// prologue and accumulates p.Ap from pointwise quantities (the diagonal part
+// plus the Parseval sum of the Laplacian part, or plus sum D |grad p|^2); the
+// last pass then knows alpha = r.r / p.Ap and applies x += alpha p,
+// r -= alpha q without storing q.  All sums are FP64, block-reduced in a fixed
+// order, so repeated runs are bitwise identical.
 #pragma once
 #include <stdint.h>
 

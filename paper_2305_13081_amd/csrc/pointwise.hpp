@@ -58,50 +58,6 @@ __global__ void __launch_bounds__(PT) k_diff_finish(double* c, const T* x, long 
     c[i] = (int)(i % nx) < band ? c_dir : (double)x[i];
 }
 
-// Post-processing of a mechanical solve: eps = eps_mac + sym(x),
-// sigma = g C : (eps - e I); partial sums of sigma (3) and (eps - eI):sigma.
-template <typename T>
-__global__ void __launch_bounds__(PT) k_mech_post(MechMat m, const T* x, long long n,
-                                                  const double* eig, double em0, double em1,
-                                                  double em2, double* strain, double* stress,
-                                                  double* part) {
-  __shared__ double red[NT / 64];
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-  for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT) {
-    const double e11 = em0 + (double)x[i];
-    const double e22 = em1 + (double)x[3 * n + i];
-    const double e12 = em2 + 0.5 * ((double)x[n + i] + (double)x[2 * n + i]);
-    strain[i] = e11;
-    strain[n + i] = e22;
-    strain[2 * n + i] = e12;
-    const double e = eig ? eig[i] : 0.0;
-    double lam, mu;
-    m.get(0, i, lam, mu);
-    const double l11 = e11 - e, l22 = e22 - e;
-    const double tr = l11 + l22;
-    const double s11 = lam * tr + 2.0 * mu * l11;
-    const double s22 = lam * tr + 2.0 * mu * l22;
-    const double s12 = 2.0 * mu * e12;
-    if (stress) {
-      stress[i] = s11;
-      stress[n + i] = s22;
-      stress[2 * n + i] = s12;
-    }
-    a0 += s11;
-    a1 += s22;
-    a2 += s12;
-    a3 += l11 * s11 + l22 * s22 + 2.0 * e12 * s12;
-  }
-  const double t0 = block_sum(a0, red), t1 = block_sum(a1, red), t2 = block_sum(a2, red),
-               t3 = block_sum(a3, red);
-  if (threadIdx.x == 0) {
-    part[4 * blockIdx.x + 0] = t0;
-    part[4 * blockIdx.x + 1] = t1;
-    part[4 * blockIdx.x + 2] = t2;
-    part[4 * blockIdx.x + 3] = t3;
-  }
-}
-
 // Empty kernel (the event-gap calibration of the profiling hooks).
 static __global__ void __launch_bounds__(NT) k_noop(int) {}
 
