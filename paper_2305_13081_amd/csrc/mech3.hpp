@@ -132,7 +132,7 @@ __device__ __forceinline__ void kapply3(const MechMat& m, const T* u, long long 
 // needs no other evaluation (about 1.4 stress evaluations per voxel instead
 // of 4).  Tile-chunks are ordered x, y, then z, and each block walks a
 // contiguous range of them laid out XCD by XCD (xcd_block).
-constexpr int K3_TX = 64, K3_TY = 16, K3_ZC = 8;
+constexpr int K3_TX = 64, K3_TY = 8, K3_ZC = 8;
 
 inline int kp3_chunks(int nx, int ny, int nz) {
   return ((nx + K3_TX - 1) / K3_TX) * ((ny + K3_TY - 1) / K3_TY) * ((nz + K3_ZC - 1) / K3_ZC);
