@@ -56,8 +56,14 @@ __global__ void __launch_bounds__(NTS) k_mech_small(MechMat m, double* __restric
   const int tid = threadIdx.x;
   const double inv_n = 1.0 / (double)NN;
   double pr[J][2];
+  double lamv[J], muv[J];  // g C of the own voxels, looked up once
 #pragma unroll
-  for (int j = 0; j < J; ++j) pr[j][0] = pr[j][1] = 0.0;
+  for (int j = 0; j < J; ++j) {
+    const int i = tid + j * NTS;
+    pr[j][0] = pr[j][1] = 0.0;
+    lamv[j] = muv[j] = 0.0;
+    if (i < NN) m.get(0, i, lamv[j], muv[j]);
+  }
   // z = M r into buf (real parts), returns r.z (Parseval over the full spectrum)
   auto green = [&]() -> double {
 #pragma unroll
@@ -69,10 +75,12 @@ __global__ void __launch_bounds__(NTS) k_mech_small(MechMat m, double* __restric
       }
     }
     __syncthreads();
-    fft_lds<double, N, 2 * N, NTS, false>(buf, tw);
-    fft_lds<double, N, 2 * N, NTS, false, ColIdx<N>>(buf, tw);
+    fft_lds<double, N, 2 * N, NTS, false, FlatIdx<N>, true>(buf, tw);
+    fft_lds<double, N, 2 * N, NTS, false, ColIdx<N>, true>(buf, tw);
     double acc = 0.0;
-    for (int i = tid; i < 2 * NN; i += NTS) {
+    int t0 = tid;
+    asm volatile("" : "+v"(t0));  // symbol loads stay inside the iteration loop
+    for (int i = t0; i < 2 * NN; i += NTS) {
       const int rem = i % NN, ky = rem / N, kx = rem - ky * N;
       const double2 d1 = Dx[kx <= N / 2 ? kx : N - kx], d2 = Dy[ky];
       const double n2 = d1.x * d1.x + d1.y * d1.y + d2.x * d2.x + d2.y * d2.y;
@@ -87,8 +95,8 @@ __global__ void __launch_bounds__(NTS) k_mech_small(MechMat m, double* __restric
       buf[lds(i)] = a;
     }
     const double rz = block_sum_small(acc, red);
-    fft_lds<double, N, 2 * N, NTS, true, ColIdx<N>>(buf, tw);
-    fft_lds<double, N, 2 * N, NTS, true>(buf, tw);
+    fft_lds<double, N, 2 * N, NTS, true, ColIdx<N>, true>(buf, tw);
+    fft_lds<double, N, 2 * N, NTS, true, FlatIdx<N>, true>(buf, tw);
     return rz;
   };
   // p = z + beta p (own voxels), and p into buf for the stencil
@@ -108,20 +116,7 @@ __global__ void __launch_bounds__(NTS) k_mech_small(MechMat m, double* __restric
     __syncthreads();
   };
   auto pv = [&](int c, int y, int xx) -> double { return buf[lds(c * NN + y * N + xx)].x; };
-  // stress g C : sym(grad p) at (y, xx) from the p in buf
-  auto sigma = [&](int y, int xx, double* sg, double* e) {
-    const int xp = xx + 1 == N ? 0 : xx + 1, yp = y + 1 == N ? 0 : y + 1;
-    const double u1 = pv(0, y, xx), u2 = pv(1, y, xx);
-    const double g11 = (pv(0, y, xp) - u1) * ih, g12 = (pv(0, yp, xx) - u1) * ih;
-    const double g21 = (pv(1, y, xp) - u2) * ih, g22 = (pv(1, yp, xx) - u2) * ih;
-    e[0] = g11;
-    e[1] = g22;
-    e[2] = 0.5 * (g12 + g21);
-    double lam, mu;
-    m.get(0, (long long)y * N + xx, lam, mu);
-    stress2<double>(lam, mu, e[0], e[1], e[2], sg);
-  };
-
+  double* sgb = reinterpret_cast<double*>(buf);  // stresses [3][NN] over the p buffer
   double rz = green();
   const double thr = tol * tol * rz;
   int done = !isfinite(rz) ? 4 : (rz <= thr ? 1 : (maxit <= 0 ? 2 : 0));
@@ -130,22 +125,47 @@ __global__ void __launch_bounds__(NTS) k_mech_small(MechMat m, double* __restric
   double rr_final = rz;
   direction(0.0, true);
   for (int k = 0; done == 0; ++k) {
-    // q = K p, p.Kp
+    // q = K p, p.Kp: the stress of the own voxels from p in buf, then (with p
+    // in registers) the stresses replace p in buf and the divergence takes the
+    // x - 1 and y - 1 neighbours from there
     double acc = 0.0;
+    double sg[J][3];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = tid + j * NTS;
+      sg[j][0] = sg[j][1] = sg[j][2] = 0.0;
+      if (i < NN) {
+        const int y = i / N, xx = i - y * N;
+        const int xp = xx + 1 == N ? 0 : xx + 1, yp = y + 1 == N ? 0 : y + 1;
+        const double u1 = pv(0, y, xx), u2 = pv(1, y, xx);
+        const double g11 = (pv(0, y, xp) - u1) * ih, g12 = (pv(0, yp, xx) - u1) * ih;
+        const double g21 = (pv(1, y, xp) - u2) * ih, g22 = (pv(1, yp, xx) - u2) * ih;
+        const double e12 = 0.5 * (g12 + g21);
+        stress2<double>(lamv[j], muv[j], g11, g22, e12, sg[j]);
+        acc += g11 * sg[j][0] + g22 * sg[j][1] + 2.0 * e12 * sg[j][2];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = tid + j * NTS;
+      if (i < NN)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sgb[c * NN + i] = sg[j][c];
+    }
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int i = tid + j * NTS;
       if (i < NN) {
         const int y = i / N, xx = i - y * N;
-        const int xm = xx == 0 ? N - 1 : xx - 1, ym = y == 0 ? N - 1 : y - 1;
-        double s0[3], e0[3], sx[3], sy[3], t[3], qq[2];
-        sigma(y, xx, s0, e0);
-        sigma(y, xm, sx, t);
-        sigma(ym, xx, sy, t);
-        div_adj<double>(s0, sx, sy, ih, qq);
+        const int ixm = y * N + (xx == 0 ? N - 1 : xx - 1), iym = (y == 0 ? N - 1 : y - 1) * N + xx;
+        const double sx[3] = {sgb[ixm], sgb[NN + ixm], sgb[2 * NN + ixm]};
+        const double sy[3] = {sgb[iym], sgb[NN + iym], sgb[2 * NN + iym]};
+        double qq[2];
+        div_adj<double>(sg[j], sx, sy, ih, qq);
         q[i] = qq[0];
         q[NN + i] = qq[1];
-        acc += e0[0] * s0[0] + e0[1] * s0[1] + 2.0 * e0[2] * s0[2];
       }
     }
     const double pap = block_sum_small(acc, red);
