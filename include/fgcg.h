@@ -109,13 +109,8 @@ const char* fgcg_last_error(void);
  *       voxels per block) on the context's own workspace before the next
  *       mechanics solve and keep the fastest; or a candidate value, fixed.
  *       The choice changes timing only, never results.  EUNSUPPORTED in 3D.
- *   FGCG_OPT_FUSED_SMALL      1 (default): FP64 mechanics solves on square 2D
- *       grids of side <= 64 (one sample) run in a single workgroup and a single
- *       launch (same iteration, results equal up to rounding); 0: the
- *       multi-pass solver of the larger grids.
  * Returns EINVAL for an unknown option or value. */
-enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2, FGCG_OPT_ROWS = 3,
-       FGCG_OPT_FUSED_SMALL = 4 };
+enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2, FGCG_OPT_ROWS = 3 };
 int fgcg_set_option(fgcg_ctx* ctx, int option, int value);
 /* Current value of an option (FGCG_OPT_ROWS: the tuned or fixed rows per
  * block, 0 before the first mechanics solve of an autotuned context). */

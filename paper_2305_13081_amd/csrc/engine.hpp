@@ -109,7 +109,6 @@ struct fgcg_ctx {
   int nrow = 0, ncol = 0, npost = 0, nkp = 0;
   int nkpt = 0;  // blocks of the tiled 2D stiffness pass (one partial sum each)
   int rows_pick = 0;  // 2D mechanics row passes: rows per block (0: time the candidates at the next solve)
-  int fused_small = 1;  // square FP64 2D grids up to 64^2: single-workgroup mechanics solver
   int nsamp = 1;            // samples of this grid size (batches)
   double* ems = nullptr;    // device [nsamp][3] macro strains
   bool batch = false;            // member of a batch (owns the gather buffers below)

@@ -150,7 +150,7 @@ template <bool INV, typename T> struct Dft<8, INV, T> {
 };
 
 // ------------------------------------------------------------ one stage
-template <typename T, int N, int R, int NS, int NSIG, int NT, bool INV, class Idx, bool OPQ>
+template <typename T, int N, int R, int NS, int NSIG, int NT, bool INV, class Idx>
 __device__ __forceinline__ void stockham_stage(typename cvec<T>::type* buf,
                                                const typename cvec<T>::type* __restrict__ tw) {
   using C = typename cvec<T>::type;
@@ -159,10 +159,7 @@ __device__ __forceinline__ void stockham_stage(typename cvec<T>::type* buf,
   constexpr int PER = (TOT + NT - 1) / NT;
   constexpr int TSTEP = N / (NS * R);
   C v[PER][R];
-  int tid = threadIdx.x;
-  // OPQ: the index arithmetic is redone at every call instead of being hoisted
-  // out of a caller's loop (which would hold it in registers across the loop)
-  if constexpr (OPQ) asm volatile("" : "+v"(tid));
+  const int tid = threadIdx.x;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int b = tid + q * NT;
@@ -197,15 +194,15 @@ __device__ __forceinline__ void stockham_stage(typename cvec<T>::type* buf,
   __syncthreads();
 }
 
-template <typename T, int N, int NSIG, int NT, bool INV, int ST, int NS, class Idx, bool OPQ>
+template <typename T, int N, int NSIG, int NT, bool INV, int ST, int NS, class Idx>
 struct StageRunner {
   static __device__ __forceinline__ void run(typename cvec<T>::type* buf,
                                              const typename cvec<T>::type* __restrict__ tw) {
     constexpr Plan p = make_plan(N);
     if constexpr (ST < p.nst) {
       constexpr int R = p.r[ST];
-      stockham_stage<T, N, R, NS, NSIG, NT, INV, Idx, OPQ>(buf, tw);
-      StageRunner<T, N, NSIG, NT, INV, ST + 1, NS * R, Idx, OPQ>::run(buf, tw);
+      stockham_stage<T, N, R, NS, NSIG, NT, INV, Idx>(buf, tw);
+      StageRunner<T, N, NSIG, NT, INV, ST + 1, NS * R, Idx>::run(buf, tw);
     }
   }
 };
@@ -213,11 +210,11 @@ struct StageRunner {
 // Transform NSIG signals of length N in LDS (element i of signal g at
 // Idx::at(g, i), by default lds(g N + i)); callers synchronise before.
 // Forward uses exp(-2 pi i k x / N); inverse uses exp(+...) without 1/N.
-template <typename T, int N, int NSIG, int NT, bool INV, class Idx = FlatIdx<N>, bool OPQ = false>
+template <typename T, int N, int NSIG, int NT, bool INV, class Idx = FlatIdx<N>>
 __device__ __forceinline__ void fft_lds(typename cvec<T>::type* buf,
                                         const typename cvec<T>::type* __restrict__ tw) {
   static_assert(fft_size_ok(N), "FFT length must be 2^a 3^b");
-  StageRunner<T, N, NSIG, NT, INV, 0, 1, Idx, OPQ>::run(buf, tw);
+  StageRunner<T, N, NSIG, NT, INV, 0, 1, Idx>::run(buf, tw);
 }
 
 }  // namespace fgcg

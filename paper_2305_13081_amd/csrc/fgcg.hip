@@ -4,7 +4,6 @@
 
 #include "adjoint.hpp"
 #include "engine.hpp"
-#include "mech_small.hpp"
 
 using namespace fgcg;
 
@@ -153,42 +152,8 @@ template <typename T> int tune_rows_t(fgcg_ctx* c) {
   return rc;
 }
 
-// Square FP64 2D grids of side <= SMALL_MAX, one sample: the single-workgroup solver.
-template <class F> bool with_small(int n, F&& f) {
-  switch (n) {
-#define FGCG_SMALL(N)                    \
-  case N:                                \
-    f(std::integral_constant<int, N>{}); \
-    return true;
-    FGCG_SMALL(8) FGCG_SMALL(12) FGCG_SMALL(16) FGCG_SMALL(24) FGCG_SMALL(32) FGCG_SMALL(48) FGCG_SMALL(64)
-#undef FGCG_SMALL
-    default:
-      return false;
-  }
-}
-
-inline bool small_ok(const fgcg_ctx* c) {
-  return c->fused_small && c->ndim == 2 && c->nsamp == 1 && !c->batch && c->prec == FGCG_FP64 && c->nx == c->ny &&
-         c->nx <= SMALL_MAX && with_small(c->nx, [](auto) {});
-}
-
-// Solve from the right-hand side in R (X = 0) in one launch; the result in X.
-int mech_small(fgcg_ctx* c, const MechMat& m, double tol, int maxit, CgState* out) {
-  with_small(c->nx, [&](auto Nc) {
-    constexpr int N = decltype(Nc)::value;
-    hipLaunchKernelGGL((k_mech_small<N>), dim3(1), dim3(NTS), 0, c->stream, m, (double*)c->x, (double*)c->r,
-                       (double*)c->tmp, 1.0 / c->h, (const double2*)c->Dx, (const double2*)c->Dy, (const double2*)c->twx, tol, maxit,
-                       c->st);
-  });
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(c->h_st, c->st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  *out = *c->h_st;
-  return 0;
-}
-
 inline int tune_rows(fgcg_ctx* c) {
-  if (c->rows_pick || small_ok(c)) return 0;
+  if (c->rows_pick) return 0;
   return c->prec == FGCG_FP64 ? tune_rows_t<double>(c) : tune_rows_t<float>(c);
 }
 
@@ -211,7 +176,6 @@ struct MechIterFn {
 // or X + XH (FP32-mixed, folded into XH at the end).
 // (The rows per block must have been tuned already: tuning overwrites the workspace.)
 int mech_pcg(fgcg_ctx* c, const MechMat& m, double tol, int maxit, CgState* out) {
-  if (small_ok(c)) return mech_small(c, m, tol, maxit, out);
   int rc = c->prec == FGCG_FP64 ? mech_init<double>(c, m, tol, maxit) : mech_init<float>(c, m, tol, maxit);
   if (rc) return rc;
   MechIterFn it{c, m, tol, maxit};
@@ -733,9 +697,6 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
       c->chunk = value;
       for (auto& g : c->graphs) release_graph(c, g);
       return FGCG_OK;
-    case FGCG_OPT_FUSED_SMALL:
-      c->fused_small = value != 0;
-      return FGCG_OK;
     case FGCG_OPT_ROWS: {
       if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "rows per block are tuned on 2D grids");
       std::vector<int> cand;
@@ -757,7 +718,6 @@ int fgcg_get_option(fgcg_ctx* c, int option, int* value) {
     case FGCG_OPT_GRAPHS: *value = c->use_graphs ? 1 : 0; return FGCG_OK;
     case FGCG_OPT_CHUNK: *value = c->chunk; return FGCG_OK;
     case FGCG_OPT_ROWS: *value = c->rows_pick; return FGCG_OK;
-    case FGCG_OPT_FUSED_SMALL: *value = c->fused_small; return FGCG_OK;
     default: return fail(FGCG_EINVAL, "unknown option");
   }
 }

@@ -67,15 +67,21 @@ int launch_ypass(fgcg_ctx* c, int kind, bool inv, const CgState* st, CT<T>* spec
   return rc;
 }
 
+// Blocks of the z pass over ncomp components (zpt_for<T>() tiles per block).
+template <typename T> int zblocks(const fgcg_ctx* c, int ncomp) {
+  return (ncomp * c->nxh * ztiles<T>(c) + zpt_for<T>() - 1) / zpt_for<T>();
+}
+
 template <typename T, bool FWD, bool INV, class Sym>
 int launch_zpass(fgcg_ctx* c, int kind, const Sym& sym, CT<T>* spec, int ncomp) {
   int rc = 0;
-  const int nty = ztiles<T>(c);
+  const int ntiles = ncomp * c->nxh * ztiles<T>(c);
   with_n3(c->nz, [&](auto NZc) {
     constexpr int NZ = decltype(NZc)::value;
-    dim3 g(ncomp * c->nxh * nty);
+    dim3 g(zblocks<T>(c, ncomp));
     if (kind >= 0) set_kname(c, kind, "k_zpass<%s, %d", tname<T>(), NZ);
-    rc = launch(c, kind, (const void*)&k_zpass<T, NZ, FWD, INV, Sym>, g, sym, spec, c->nxh, c->ny, tw_z<T>(c));
+    rc = launch(c, kind, (const void*)&k_zpass<T, NZ, FWD, INV, Sym>, g, sym, spec, c->nxh, c->ny, ntiles,
+                tw_z<T>(c));
   });
   return rc;
 }
@@ -186,7 +192,7 @@ int alloc3d(fgcg_ctx* c) {
   HIPCHK(hipMalloc(&c->red, sizeof(double) * 8));
   HIPCHK(hipMemset(c->red, 0, sizeof(double) * 8));
   // z-pass blocks of the solver's precision (the FP64 debug transform has no partial sums)
-  c->nzb = 3 * c->nxh * (c->prec == FGCG_FP64 ? ztiles<double>(c) : ztiles<float>(c));
+  c->nzb = c->prec == FGCG_FP64 ? zblocks<double>(c, 3) : zblocks<float>(c, 3);
   HIPCHK(hipMalloc(&c->part_z, sizeof(double) * c->nzb));
   c->nslab = nslab(c);
   return 0;

@@ -59,46 +59,72 @@ __global__ void __launch_bounds__(NT) k_ypass(const CgState* st, typename cvec<T
   }
 }
 
-// Blocks: (component, kx, ky tile), tile fastest.  FWD / INV select the
-// transforms (the debug hook uses one of them alone); the symbol is applied
-// between them and may reduce one FP64 partial sum per block.
+// Blocks: zpt_for<T>() consecutive (component, kx, ky tile) entries each,
+// tile fastest.  The values of the next entry are loaded into registers while
+// the current one is transformed, so the loads overlap the LDS work (two per
+// block in FP64; one in FP32, where two measured slower).  FWD / INV select
+// the transforms (the debug hook uses one of them alone); the symbol is
+// applied between them and may reduce one FP64 partial sum per block.
+template <typename T> constexpr int zpt_for() { return sizeof(T) == 8 ? 2 : 1; }
+
 template <typename T, int NZ, bool FWD, bool INV, class Sym>
-__global__ void __launch_bounds__(NT) k_zpass(Sym sym, typename cvec<T>::type* spec, int nxh, int ny,
+__global__ void __launch_bounds__(NT) k_zpass(Sym sym, typename cvec<T>::type* spec, int nxh, int ny, int ntiles,
                                               const typename cvec<T>::type* __restrict__ tw) {
   using C = typename cvec<T>::type;
   using Idx = PitchIdx<NZ>;
   constexpr int YT = ztile_for<T>(NZ);
+  constexpr int PT = (YT * NZ + NT - 1) / NT;  // values per thread and tile
   __shared__ C buf[YT * pitch_for(NZ)];
   __shared__ double red[NT / 64];
   if (!sym.begin()) return;
   const int nty = (ny + YT - 1) / YT;
-  const int t = blockIdx.x % nty;
-  const int ckx = blockIdx.x / nty;
-  const int kx = ckx % nxh;
-  const int ky0 = t * YT;
-  C* base = spec + (long long)ckx * NZ * ny;  // the [z][y] plane of (component, kx)
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < YT * NZ; idx += NT) {
-    const int z = idx / YT, l = idx - z * YT;
-    buf[Idx::at(l, z)] = ky0 + l < ny ? base[(long long)z * ny + ky0 + l] : C{(T)0, (T)0};
-  }
-  __syncthreads();
-  if (FWD) fft_lds<T, NZ, YT, NT, false, Idx>(buf, tw);
-  double acc = 0.0;
-  for (int idx = tid; idx < YT * NZ; idx += NT) {
-    const int l = idx / NZ, kz = idx - l * NZ;
-    if (ky0 + l < ny) {
-      C& a = buf[Idx::at(l, kz)];
-      a = sym.mode(kx, ky0 + l, kz, a, acc);
+  constexpr int ZPT = zpt_for<T>();
+  const int e0 = blockIdx.x * ZPT, e1 = min(e0 + ZPT, ntiles);
+  C pre[PT];
+  auto load = [&](int e) {
+    const int t = e % nty, ckx = e / nty, ky0 = t * YT;
+    const C* base = spec + (long long)ckx * NZ * ny;
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int idx = tid + u * NT;
+      const int z = idx / YT, l = idx - z * YT;
+      pre[u] = (idx < YT * NZ && ky0 + l < ny) ? base[(long long)z * ny + ky0 + l] : C{(T)0, (T)0};
     }
+  };
+  double acc = 0.0;
+  load(e0);
+  for (int e = e0; e < e1; ++e) {
+    const int t = e % nty, ckx = e / nty;
+    const int kx = ckx % nxh, ky0 = t * YT;
+    C* base = spec + (long long)ckx * NZ * ny;  // the [z][y] plane of (component, kx)
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int idx = tid + u * NT;
+      if (idx < YT * NZ) {
+        const int z = idx / YT, l = idx - z * YT;
+        buf[Idx::at(l, z)] = pre[u];
+      }
+    }
+    if (e + 1 < e1) load(e + 1);
+    __syncthreads();
+    if (FWD) fft_lds<T, NZ, YT, NT, false, Idx>(buf, tw);
+    for (int idx = tid; idx < YT * NZ; idx += NT) {
+      const int l = idx / NZ, kz = idx - l * NZ;
+      if (ky0 + l < ny) {
+        C& a = buf[Idx::at(l, kz)];
+        a = sym.mode(kx, ky0 + l, kz, a, acc);
+      }
+    }
+    __syncthreads();
+    if (INV) fft_lds<T, NZ, YT, NT, true, Idx>(buf, tw);
+    for (int idx = tid; idx < YT * NZ; idx += NT) {
+      const int z = idx / YT, l = idx - z * YT;
+      if (ky0 + l < ny) base[(long long)z * ny + ky0 + l] = buf[Idx::at(l, z)];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   sym.partial(block_sum(acc, red));
-  if (INV) fft_lds<T, NZ, YT, NT, true, Idx>(buf, tw);
-  for (int idx = tid; idx < YT * NZ; idx += NT) {
-    const int z = idx / YT, l = idx - z * YT;
-    if (ky0 + l < ny) base[(long long)z * ny + ky0 + l] = buf[Idx::at(l, z)];
-  }
 }
 
 // Green operator of the unit reference medium on a 3D grid,

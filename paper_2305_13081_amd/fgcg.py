@@ -181,7 +181,7 @@ class Context:
         except Exception:
             pass
 
-    OPTIONS = {"scalar_spectral": 0, "graphs": 1, "chunk": 2, "rows": 3, "fused_small": 4}
+    OPTIONS = {"scalar_spectral": 0, "graphs": 1, "chunk": 2, "rows": 3}
 
     def set_option(self, name, value):
         _check(self.lib.fgcg_set_option(self.ptr, self.OPTIONS[name], int(value)), "fgcg_set_option")
