@@ -80,6 +80,34 @@ __global__ void __launch_bounds__(NT) k_zpass(Sym sym, typename cvec<T>::type* s
   const int nty = (ny + YT - 1) / YT;
   const int tid = threadIdx.x;
   constexpr int ZPT = zpt_for<T>();
+  if constexpr (ZPT == 1) {
+    // one tile per block, loaded straight into LDS
+    const int t = blockIdx.x % nty, ckx = blockIdx.x / nty;
+    const int kx = ckx % nxh, ky0 = t * YT;
+    C* base = spec + (long long)ckx * NZ * ny;
+    for (int idx = tid; idx < YT * NZ; idx += NT) {
+      const int z = idx / YT, l = idx - z * YT;
+      buf[Idx::at(l, z)] = ky0 + l < ny ? base[(long long)z * ny + ky0 + l] : C{(T)0, (T)0};
+    }
+    __syncthreads();
+    if (FWD) fft_lds<T, NZ, YT, NT, false, Idx>(buf, tw);
+    double acc1 = 0.0;
+    for (int idx = tid; idx < YT * NZ; idx += NT) {
+      const int l = idx / NZ, kz = idx - l * NZ;
+      if (ky0 + l < ny) {
+        C& a = buf[Idx::at(l, kz)];
+        a = sym.mode(kx, ky0 + l, kz, a, acc1);
+      }
+    }
+    __syncthreads();
+    sym.partial(block_sum(acc1, red));
+    if (INV) fft_lds<T, NZ, YT, NT, true, Idx>(buf, tw);
+    for (int idx = tid; idx < YT * NZ; idx += NT) {
+      const int z = idx / YT, l = idx - z * YT;
+      if (ky0 + l < ny) base[(long long)z * ny + ky0 + l] = buf[Idx::at(l, z)];
+    }
+    return;
+  }
   const int e0 = blockIdx.x * ZPT, e1 = min(e0 + ZPT, ntiles);
   C pre[PT];
   auto load = [&](int e) {
