@@ -118,9 +118,9 @@ template <typename T> int mech3_iter(fgcg_ctx* c, const MechMat& m, double tol, 
   const Grid3 g = grid3(c);
   const int nb = nslab(c);
   const int nkp = std::min(kp3_chunks(c->nx, c->ny, c->nz), KP3_MAX_BLOCKS);
-  set_kname(c, FGCG_K_MECH_KP, "k_mech3_kp<%s%.0d", tname<T>(), 0);
-  int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech3_kp<T>, dim3(nkp), m, (const T*)P.p, Q.p, g,
-                 (T)(1.0 / c->h), c->st, c->part_a);
+  set_kname(c, FGCG_K_MECH_KP, "k_mech3_kpx<%s%.0d", tname<T>(), 0);
+  int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech3_kpx<T, T, false>, dim3(nkp), m, (const T*)P.p, Q.p,
+                 (const double*)nullptr, g, (T)(1.0 / c->h), c->st, c->part_a);
   r |= launch_reduce(c, c->part_a, nkp, c->red);
   if (!reliable) {
     const MechUPro<T, 3> pro{X, R, P, Q, c->nx, c->st, c->red, 1};
@@ -128,8 +128,8 @@ template <typename T> int mech3_iter(fgcg_ctx* c, const MechMat& m, double tol, 
   } else {
     r |= launch(c, -1, (const void*)&k_mech_fold<T>, dim3(c->npost), X.p, c->xh, (const T*)P.p, 3 * c->n, c->st,
                 (const double*)c->red, 1);
-    r |= launch(c, -1, (const void*)&k_mech3_true_res<T>, dim3(nb), m, (const double*)c->xh, (const double*)c->fh,
-                R.p, g, 1.0 / c->h, (const CgState*)c->st);
+    r |= launch(c, -1, (const void*)&k_mech3_kpx<T, double, true>, dim3(nkp), m, (const double*)c->xh, R.p,
+                (const double*)c->fh, g, 1.0 / c->h, c->st, (double*)nullptr);
     const CopyProN<T, 3> cp{R, c->nx};
     r |= green3<T>(c, cp, c->st, false);
   }

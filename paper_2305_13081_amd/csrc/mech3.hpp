@@ -109,23 +109,7 @@ template <typename T> __device__ __forceinline__ double edots(const T* e, const 
          2.0 * ((double)e[3] * s[3] + (double)e[4] * s[4] + (double)e[5] * s[5]);
 }
 
-// q = K u at voxel i (stress at the voxel and at its three backward neighbours).
-template <typename T>
-__device__ __forceinline__ void kapply3(const MechMat& m, const T* u, long long n, long long i, const Off3& o, T ih,
-                                        T* q, double* ed) {
-  T s0[6], e0[6], sx[6], sy[6], sz[6], t[6];
-  sigma3<T>(m, u, n, i, i + o.xp, i + o.yp, i + o.zp, ih, s0, e0);
-  const long long jx = i + o.xm, jy = i + o.ym, jz = i + o.zm;
-  sigma3<T>(m, u, n, jx, i, jx + o.yp, jx + o.zp, ih, sx, t);
-  sigma3<T>(m, u, n, jy, jy + o.xp, i, jy + o.zp, ih, sy, t);
-  sigma3<T>(m, u, n, jz, jz + o.xp, jz + o.yp, i, ih, sz, t);
-  div_adj3<T>(s0, sx, sy, sz, ih, q);
-  if (ed) *ed = edots<T>(e0, s0);
-}
-
-// q = K p with partial sums of p.Kp; publishes k = k_next (see the 2D kernel).
-//
-// Tiled: a block takes an x-y tile of K3_TX x K3_TY voxels and marches it
+// q = K p, tiled: a block takes an x-y tile of K3_TX x K3_TY voxels and marches it
 // through K3_ZC planes.  On each plane the stress is computed once per voxel
 // of the tile and of its halo column x0 - 1 and halo row y0 - 1 and kept in
 // LDS; the stress of the plane below stays in registers, so the divergence
@@ -149,15 +133,20 @@ __device__ __forceinline__ void sigma3_at(const MechMat& m, const T* u, const Gr
   sigma3<T>(m, u, g.n, i, ix, iy, iz, ih, sv, e);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(NT) k_mech3_kp(MechMat m, const T* __restrict__ p, T* __restrict__ q, Grid3 g,
-                                                 T ih, CgState* st, double* part) {
+// T: type of q; TU: type of p and of the arithmetic.  RES = false: the CG
+// pass, q = K p with p.Kp partial sums, publishing k = k_next.  RES = true:
+// the FP64 true residual of the mixed-precision solve, q = (T)(f - K p)
+// (p = x_hi), nothing else.
+template <typename T, typename TU, bool RES>
+__global__ void __launch_bounds__(NT) k_mech3_kpx(MechMat m, const TU* __restrict__ p, T* __restrict__ q,
+                                                  const double* __restrict__ f, Grid3 g, TU ih, CgState* st,
+                                                  double* part) {
   constexpr int HX = K3_TX + 1, HY = K3_TY + 1, HP = HX * HY;
   constexpr int RPT = K3_TY / (NT / K3_TX);  // own rows per thread
-  __shared__ T sg[6][HP];
+  __shared__ TU sg[6][HP];
   __shared__ double red[NT / 64];
   if (!cg_running(st, 0)) return;
-  if (lead()) st->k = st->k_next;
+  if (!RES && lead()) st->k = st->k_next;
   const long long n = g.n;
   const int ntx = (g.nx + K3_TX - 1) / K3_TX, nty = (g.ny + K3_TY - 1) / K3_TY;
   const int nch = ntx * nty * ((g.nz + K3_ZC - 1) / K3_ZC);
@@ -170,13 +159,13 @@ __global__ void __launch_bounds__(NT) k_mech3_kp(MechMat m, const T* __restrict_
     const int z0 = (c / (ntx * nty)) * K3_ZC, z1 = min(z0 + K3_ZC, g.nz);
     const int xo = x0 + tx;
     // stress of the own points on the plane below the chunk
-    T below[RPT][6];
+    TU below[RPT][6];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int yo = y0 + ty + k * (NT / K3_TX);
       if (xo < g.nx && yo < g.ny) {
-        T e[6];
-        sigma3_at<T>(m, p, g, xo, yo, z0 == 0 ? g.nz - 1 : z0 - 1, ih, below[k], e);
+        TU e[6];
+        sigma3_at<TU>(m, p, g, xo, yo, z0 == 0 ? g.nz - 1 : z0 - 1, ih, below[k], e);
       }
     }
     for (int z = z0; z < z1; ++z) {
@@ -186,11 +175,11 @@ __global__ void __launch_bounds__(NT) k_mech3_kp(MechMat m, const T* __restrict_
         if (x >= g.nx || y >= g.ny) continue;  // past the edge of a partial tile: never read
         if (x < 0) x += g.nx;
         if (y < 0) y += g.ny;
-        T sv[6], e[6];
-        sigma3_at<T>(m, p, g, x, y, z, ih, sv, e);
+        TU sv[6], e[6];
+        sigma3_at<TU>(m, p, g, x, y, z, ih, sv, e);
 #pragma unroll
         for (int j = 0; j < 6; ++j) sg[j][hp] = sv[j];
-        if (hx >= 1 && hy >= 1) acc += edots<T>(e, sv);
+        if (!RES && hx >= 1 && hy >= 1) acc += edots<TU>(e, sv);
       }
       __syncthreads();
 #pragma unroll
@@ -199,18 +188,24 @@ __global__ void __launch_bounds__(NT) k_mech3_kp(MechMat m, const T* __restrict_
         const int yo = y0 + yy;
         if (xo < g.nx && yo < g.ny) {
           const int hp = (yy + 1) * HX + tx + 1;
-          T s0[6], sx[6], sy[6], qq[3];
+          TU s0[6], sx[6], sy[6], qq[3];
 #pragma unroll
           for (int j = 0; j < 6; ++j) {
             s0[j] = sg[j][hp];
             sx[j] = sg[j][hp - 1];
             sy[j] = sg[j][hp - HX];
           }
-          div_adj3<T>(s0, sx, sy, below[k], ih, qq);
+          div_adj3<TU>(s0, sx, sy, below[k], ih, qq);
           const long long i = ((long long)z * g.ny + yo) * g.nx + xo;
-          q[i] = qq[0];
-          q[n + i] = qq[1];
-          q[2 * n + i] = qq[2];
+          if (RES) {
+            q[i] = (T)(f[i] - qq[0]);
+            q[n + i] = (T)(f[n + i] - qq[1]);
+            q[2 * n + i] = (T)(f[2 * n + i] - qq[2]);
+          } else {
+            q[i] = (T)qq[0];
+            q[n + i] = (T)qq[1];
+            q[2 * n + i] = (T)qq[2];
+          }
 #pragma unroll
           for (int j = 0; j < 6; ++j) below[k][j] = s0[j];
         }
@@ -218,8 +213,10 @@ __global__ void __launch_bounds__(NT) k_mech3_kp(MechMat m, const T* __restrict_
       __syncthreads();
     }
   }
-  const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (!RES) {
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+  }
 }
 
 // r = f = -grad^H g C : (eps_mac - e I); x = 0.
@@ -242,24 +239,6 @@ __global__ void __launch_bounds__(NT) k_mech3_rhs(MechMat m, const double* eig, 
       r[a * n + i] = -qq[a];
       x[a * n + i] = (T)0;
     }
-  }
-}
-
-// Mixed precision: r = f - K x_hi with the FP64 operator.
-template <typename T>
-__global__ void __launch_bounds__(NT) k_mech3_true_res(MechMat m, const double* __restrict__ xhi,
-                                                       const double* __restrict__ f, T* __restrict__ r, Grid3 g,
-                                                       double ih, const CgState* st) {
-  if (!cg_running(st, 0)) return;
-  const long long n = g.n;
-  const SlabIter it(g.nx, (long long)g.ny * g.nz);
-  for (long long i = it.v0; i < it.v1; i += it.step) {
-    int x, y, z;
-    const Off3 o(g, i, x, y, z);
-    double qq[3];
-    kapply3<double>(m, xhi, n, i, o, ih, qq, nullptr);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) r[a * n + i] = (T)(f[a * n + i] - qq[a]);
   }
 }
 
