@@ -79,8 +79,8 @@ KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "
 # kernel sources they were taken with: the key is the SHA-256 of csrc/.
 MEASURED_TRAFFIC = {
     # source hash -> {kernel kind: bytes per launch} (profiles/mech_passes_1024_fp64_hbm_traffic.md)
-    "979afb408891e534e0869dda8adb432da9beeaa40fe2ac0a00581c6a16b8fbbd": {
-        "mech_row_fwd": 114832989, "mech_row_inv": 49382578, "mech_kp": 42317164, "mech_col": 33189043},
+    "09a38eef4f67dc81bd4223240e305c98a4afa41f6897021549f9f2ba87c380af": {
+        "mech_row_fwd": 114818297, "mech_row_inv": 49336834, "mech_kp": 42314998, "mech_col": 33140473},
 }
 
 

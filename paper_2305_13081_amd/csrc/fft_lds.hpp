@@ -6,8 +6,12 @@
 // sub-transform of length Ns), runs an R-point DFT in registers and writes
 // the results to their self-sorted positions (j / Ns) * Ns * R + k + r * Ns.
 // The transform is in place: every thread loads all of its butterflies into
-// registers, the workgroup synchronises, then stores.  Twiddles come from a
-// per-length table tw[t] = exp(-2 pi i t / N) built once on the host in FP64.
+// registers, the workgroup synchronises, then stores.  The twiddle of r = 1
+// comes from a per-length table tw[t] = exp(-2 pi i t / N) built once on the
+// host in FP64; its powers r = 2 .. R-1 are formed by complex products in
+// registers (one table load per butterfly instead of R - 1: the loads compete
+// with the streaming traffic of the passes, the products are cheap; the
+// error of w^r grows by about one rounding per product).
 //
 // Radix plan for N = 3^a 2^b: the 3s first, then radix 8, with 8*2 -> 4*4 and
 // a single trailing 4 so that no radix-2 pass is needed for b >= 2.
@@ -169,11 +173,13 @@ __device__ __forceinline__ void stockham_stage(typename cvec<T>::type* buf,
       for (int r = 0; r < R; ++r) v[q][r] = buf[Idx::at(sig, j + r * M)];
       if (NS > 1) {
         const int k = j % NS;
+        C w1 = tw[k * TSTEP];
+        if (INV) w1.y = -w1.y;
+        C w = w1;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          C w = tw[k * r * TSTEP];
-          if (INV) w.y = -w.y;
           v[q][r] = cmul(v[q][r], w);
+          if (r + 1 < R) w = cmul(w, w1);
         }
       }
       Dft<R, INV, T>::run(v[q]);
