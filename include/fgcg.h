@@ -109,11 +109,20 @@ const char* fgcg_last_error(void);
  *       voxels per block) on the context's own workspace before the next
  *       mechanics solve and keep the fastest; or a candidate value, fixed.
  *       The choice changes timing only, never results.  EUNSUPPORTED in 3D.
+ *   FGCG_OPT_ROW_PLAN, FGCG_OPT_COL_PLAN   2D grids: radix plan of the LDS
+ *       transforms in the mechanics row passes (timed jointly with the rows
+ *       per block) and in the Green column pass.  1: radix 8 (with a trailing
+ *       4); 2: radix 16 where it fits (fewer stages, larger butterflies); the
+ *       same as 1 for lengths where radix 16 does not fit.  0 (default):
+ *       autotune before the next mechanics solve, as for FGCG_OPT_ROWS.  The
+ *       plan changes the rounding of the transforms only.  EUNSUPPORTED in 3D.
  * Returns EINVAL for an unknown option or value. */
-enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2, FGCG_OPT_ROWS = 3 };
+enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2, FGCG_OPT_ROWS = 3,
+       FGCG_OPT_ROW_PLAN = 4, FGCG_OPT_COL_PLAN = 5 };
 int fgcg_set_option(fgcg_ctx* ctx, int option, int value);
-/* Current value of an option (FGCG_OPT_ROWS: the tuned or fixed rows per
- * block, 0 before the first mechanics solve of an autotuned context). */
+/* Current value of an option (FGCG_OPT_ROWS, _ROW_PLAN, _COL_PLAN: the tuned
+ * or fixed choice, 0 before the first mechanics solve of an autotuned
+ * context). */
 int fgcg_get_option(fgcg_ctx* ctx, int option, int* value);
 
 /* Mechanical equilibrium with isotropic eigenstrain e(x) I (Sec. 2.3,

@@ -109,6 +109,8 @@ struct fgcg_ctx {
   int nrow = 0, ncol = 0, npost = 0, nkp = 0;
   int nkpt = 0;  // blocks of the tiled 2D stiffness pass (one partial sum each)
   int rows_pick = 0;  // 2D mechanics row passes: rows per block (0: time the candidates at the next solve)
+  // 2D mechanics radix plans (1: plan 0, radix 8; 2: plan 1, radix 16; 0: time both at the next solve)
+  int plan_row = 0, plan_col = 0;
   int nsamp = 1;            // samples of this grid size (batches)
   double* ems = nullptr;    // device [nsamp][3] macro strains
   bool batch = false;            // member of a batch (owns the gather buffers below)
@@ -317,37 +319,59 @@ template <int NX, class F> void with_rows(int pick, F&& f) {
   f(std::integral_constant<int, R0>{});
 }
 
-// TUNED: the rows per block come from c->rows_pick (the mechanics passes of
-// 2D contexts); otherwise rows_for(NX).
+// Calls f(integral_constant<int, P>) with the radix plan of a pick (2: plan 1
+// where it differs from plan 0 for length N; anything else: plan 0).
+template <int N, class F> void with_plan(int pick, F&& f) {
+  if constexpr (plan1_differs(N)) {
+    if (pick == 2) {
+      f(std::integral_constant<int, 1>{});
+      return;
+    }
+  }
+  f(std::integral_constant<int, 0>{});
+}
+
+// TUNED: the rows per block and the radix plan come from c->rows_pick and
+// c->plan_row (the mechanics passes of 2D contexts); otherwise rows_for(NX)
+// and plan 0.
 template <typename T, int NOUT, class Pro, bool TUNED = false>
 int launch_row_fwd(fgcg_ctx* c, int kind, const Pro& pro, CT<T>* spec, int nsamp = 1, long long ss = 0) {
   int rc = 0;
   with_n(c->nx, [&](auto NXc) {
     constexpr int NX = decltype(NXc)::value;
-    auto go = [&](auto Rc) {
-      constexpr int R = decltype(Rc)::value;
+    auto go = [&](auto Rc, auto Pc) {
+      constexpr int R = decltype(Rc)::value, P = decltype(Pc)::value;
       dim3 g((c->rows + R - 1) / R, nsamp);
       if (kind >= 0) set_kname(c, kind, "k_row_fwd<%s, %d", tname<T>(), NX);
-      rc = launch(c, kind, (const void*)&k_row_fwd<T, NX, NOUT, Pro, R>, g, pro, spec, c->rows, ss, tw_x<T>(c));
+      rc = launch(c, kind, (const void*)&k_row_fwd<T, NX, NOUT, Pro, R, P>, g, pro, spec, c->rows, ss,
+                  tw_x<T>(c));
     };
     if constexpr (TUNED)
-      with_rows<NX>(c->rows_pick, go);
+      with_rows<NX>(c->rows_pick, [&](auto Rc) { with_plan<NX>(c->plan_row, [&](auto Pc) { go(Rc, Pc); }); });
     else
-      go(std::integral_constant<int, rows_for(NX)>{});
+      go(std::integral_constant<int, rows_for(NX)>{}, std::integral_constant<int, 0>{});
   });
   return rc;
 }
 
-template <typename T, int NIN, int NOUT, class Sym>
+// TUNED: the radix plan comes from c->plan_col (the mechanics Green pass).
+template <typename T, int NIN, int NOUT, class Sym, bool TUNED = false>
 int launch_col(fgcg_ctx* c, int kind, const Sym& sym, const CT<T>* in, CT<T>* out, int nsamp = 1,
                long long ss = 0) {
   int rc = 0;
   with_n(c->ny, [&](auto NYc) {
     constexpr int NY = decltype(NYc)::value;
-    dim3 g(c->nxh, nsamp);
-    if (kind >= 0) set_kname(c, kind, "k_col<%s, %d", tname<T>(), NY);
-    rc = launch(c, kind, (const void*)&k_col<T, NY, NIN, NOUT, Sym>, g, sym, in, out, c->nxh, ss, ss,
-                tw_y<T>(c));
+    auto go = [&](auto Pc) {
+      constexpr int P = decltype(Pc)::value;
+      dim3 g(c->nxh, nsamp);
+      if (kind >= 0) set_kname(c, kind, "k_col<%s, %d", tname<T>(), NY);
+      rc = launch(c, kind, (const void*)&k_col<T, NY, NIN, NOUT, Sym, P>, g, sym, in, out, c->nxh, ss, ss,
+                  tw_y<T>(c));
+    };
+    if constexpr (TUNED)
+      with_plan<NY>(c->plan_col, go);
+    else
+      go(std::integral_constant<int, 0>{});
   });
   return rc;
 }
@@ -358,16 +382,17 @@ int launch_row_inv(fgcg_ctx* c, int kind, const Epi& epi, const CT<T>* spec, int
   int rc = 0;
   with_n(c->nx, [&](auto NXc) {
     constexpr int NX = decltype(NXc)::value;
-    auto go = [&](auto Rc) {
-      constexpr int R = decltype(Rc)::value;
+    auto go = [&](auto Rc, auto Pc) {
+      constexpr int R = decltype(Rc)::value, P = decltype(Pc)::value;
       dim3 g((c->rows + R - 1) / R, nsamp);
       if (kind >= 0) set_kname(c, kind, "k_row_inv<%s, %d", tname<T>(), NX);
-      rc = launch(c, kind, (const void*)&k_row_inv<T, NX, NIN, Epi, R>, g, epi, spec, c->rows, ss, tw_x<T>(c));
+      rc = launch(c, kind, (const void*)&k_row_inv<T, NX, NIN, Epi, R, P>, g, epi, spec, c->rows, ss,
+                  tw_x<T>(c));
     };
     if constexpr (TUNED)
-      with_rows<NX>(c->rows_pick, go);
+      with_rows<NX>(c->rows_pick, [&](auto Rc) { with_plan<NX>(c->plan_row, [&](auto Pc) { go(Rc, Pc); }); });
     else
-      go(std::integral_constant<int, rows_for(NX)>{});
+      go(std::integral_constant<int, rows_for(NX)>{}, std::integral_constant<int, 0>{});
   });
   return rc;
 }

@@ -13,8 +13,13 @@
 // with the streaming traffic of the passes, the products are cheap; the
 // error of w^r grows by about one rounding per product).
 //
-// Radix plan for N = 3^a 2^b: the 3s first, then radix 8, with 8*2 -> 4*4 and
-// a single trailing 4 so that no radix-2 pass is needed for b >= 2.
+// Radix plans for N = 3^a 2^b, the 3s first.  Plan 0: radix 8, with 8*2 ->
+// 4*4 and a single trailing 4 so that no radix-2 pass is needed for b >= 2.
+// Plan 1: radix 16 where it fits (16*2 -> 8*4, then a trailing 8 or 4), one
+// LDS round trip and barrier pair fewer per four factors of 2 at the cost of
+// fewer, larger butterflies per stage.  Which is faster depends on the pass
+// and its signals per block, so the row and column passes take the plan as a
+// template parameter and the mechanics passes time both (autotuner).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -65,11 +70,27 @@ struct Plan {
   int r[16];
 };
 
-constexpr Plan make_plan(int N) {
+constexpr Plan make_plan(int N, int P = 0) {
   Plan p{N, 0, {0}};
   int a = count3(N);
   int b = log2i(N / pow3(a));
   for (int i = 0; i < a; ++i) p.r[p.nst++] = 3;
+  if (P == 1 && b >= 4) {
+    int n16 = b / 4, rem = b % 4;
+    int tail[2] = {0, 0}, nt = 0;
+    if (rem == 1) {
+      n16 -= 1;
+      tail[nt++] = 8;
+      tail[nt++] = 4;
+    } else if (rem == 2) {
+      tail[nt++] = 4;
+    } else if (rem == 3) {
+      tail[nt++] = 8;
+    }
+    for (int i = 0; i < n16; ++i) p.r[p.nst++] = 16;
+    for (int i = 0; i < nt; ++i) p.r[p.nst++] = tail[i];
+    return p;
+  }
   int n8 = b / 3, rem = b % 3;
   int n4 = 0, n2 = 0;
   if (rem == 2) n4 = 1;
@@ -153,6 +174,48 @@ template <bool INV, typename T> struct Dft<8, INV, T> {
   }
 };
 
+// 16 points as 4 x 4: DFT-4 over n1 for each n2, twiddle W16^(n2 k1), DFT-4
+// over n2; output k1 + 4 k2.  W16^m = (cos, -+sin)(2 pi m / 16).
+template <bool INV, typename T> struct Dft<16, INV, T> {
+  using C = typename cvec<T>::type;
+  static __device__ __forceinline__ C tw16(C a, int m) {
+    const T c1 = (T)0.92387953251128675612818318939679;  // cos(pi / 8)
+    const T s1 = (T)0.38268343236508977172845998403040;  // sin(pi / 8)
+    const T r2 = (T)0.70710678118654752440084436210485;
+    // forward multiplies by (c, -s); inverse by (c, +s)
+    auto rot = [&](T c, T sn) {
+      const T ss = INV ? sn : -sn;
+      return C{a.x * c - a.y * ss, a.x * ss + a.y * c};
+    };
+    switch (m) {
+      case 1: return rot(c1, s1);
+      case 2: return INV ? C{r2 * (a.x - a.y), r2 * (a.x + a.y)} : C{r2 * (a.x + a.y), r2 * (a.y - a.x)};
+      case 3: return rot(s1, c1);
+      case 4: return cmul_mi<INV>(a);
+      case 6: return INV ? C{-r2 * (a.x + a.y), r2 * (a.x - a.y)} : C{r2 * (a.y - a.x), -r2 * (a.x + a.y)};
+      case 9: return rot(-c1, -s1);
+      default: return a;
+    }
+  }
+  static __device__ __forceinline__ void run(C* v) {
+    C y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      C t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+      Dft<4, INV, T>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = tw16(t[k1], n2 * k1);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      C t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+      Dft<4, INV, T>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+  }
+};
+
 // ------------------------------------------------------------ one stage
 template <typename T, int N, int R, int NS, int NSIG, int NT, bool INV, class Idx>
 __device__ __forceinline__ void stockham_stage(typename cvec<T>::type* buf,
@@ -200,27 +263,37 @@ __device__ __forceinline__ void stockham_stage(typename cvec<T>::type* buf,
   __syncthreads();
 }
 
-template <typename T, int N, int NSIG, int NT, bool INV, int ST, int NS, class Idx>
+template <typename T, int N, int NSIG, int NT, bool INV, int ST, int NS, class Idx, int P>
 struct StageRunner {
   static __device__ __forceinline__ void run(typename cvec<T>::type* buf,
                                              const typename cvec<T>::type* __restrict__ tw) {
-    constexpr Plan p = make_plan(N);
+    constexpr Plan p = make_plan(N, P);
     if constexpr (ST < p.nst) {
       constexpr int R = p.r[ST];
       stockham_stage<T, N, R, NS, NSIG, NT, INV, Idx>(buf, tw);
-      StageRunner<T, N, NSIG, NT, INV, ST + 1, NS * R, Idx>::run(buf, tw);
+      StageRunner<T, N, NSIG, NT, INV, ST + 1, NS * R, Idx, P>::run(buf, tw);
     }
   }
 };
 
 // Transform NSIG signals of length N in LDS (element i of signal g at
-// Idx::at(g, i), by default lds(g N + i)); callers synchronise before.
-// Forward uses exp(-2 pi i k x / N); inverse uses exp(+...) without 1/N.
-template <typename T, int N, int NSIG, int NT, bool INV, class Idx = FlatIdx<N>>
+// Idx::at(g, i), by default lds(g N + i)) with radix plan P; callers
+// synchronise before.  Forward uses exp(-2 pi i k x / N); inverse uses
+// exp(+...) without 1/N.
+template <typename T, int N, int NSIG, int NT, bool INV, class Idx = FlatIdx<N>, int P = 0>
 __device__ __forceinline__ void fft_lds(typename cvec<T>::type* buf,
                                         const typename cvec<T>::type* __restrict__ tw) {
   static_assert(fft_size_ok(N), "FFT length must be 2^a 3^b");
-  StageRunner<T, N, NSIG, NT, INV, 0, 1, Idx>::run(buf, tw);
+  StageRunner<T, N, NSIG, NT, INV, 0, 1, Idx, P>::run(buf, tw);
+}
+
+// Whether plan 1 is a different schedule from plan 0 for length N.
+constexpr bool plan1_differs(int N) {
+  const Plan a = make_plan(N, 0), b = make_plan(N, 1);
+  if (a.nst != b.nst) return true;
+  for (int i = 0; i < a.nst; ++i)
+    if (a.r[i] != b.r[i]) return true;
+  return false;
 }
 
 }  // namespace fgcg

@@ -28,7 +28,7 @@ template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, i
   const CopyProN<T, 2> cp{fld<T>(c->r, c), c->nx};
   if ((rc = launch_row_fwd<T, 2, CopyProN<T, 2>, true>(c, -1, cp, spec, ns, ss))) return rc;
   const MechGreen<T> g0{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
-  if ((rc = launch_col<T, 1, 1>(c, -1, g0, spec, spec, 2 * ns, ss / 2))) return rc;
+  if ((rc = launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, g0, spec, spec, 2 * ns, ss / 2))) return rc;
   const MechUEpi<T> e0{fld<T>(c->p, c), c->nx, c->st, c->part_rr, 2 * c->ncol, 1, tol, maxit};
   if ((rc = launch_row_inv<T, 2, MechUEpi<T>, true>(c, -1, e0, spec, ns, ss))) return rc;
   HIPCHK(hipGetLastError());
@@ -57,7 +57,7 @@ template <typename T> int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, i
     r |= launch_row_fwd<T, 2, CopyProN<T, 2>, true>(c, -1, cp, spec, ns, ss);
   }
   const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, c->st, c->part_rr};
-  r |= launch_col<T, 1, 1>(c, FGCG_K_MECH_COL, green, spec, spec, 2 * ns, ss / 2);
+  r |= launch_col<T, 1, 1, MechGreen<T>, true>(c, FGCG_K_MECH_COL, green, spec, spec, 2 * ns, ss / 2);
   const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, tol, maxit};
   r |= launch_row_inv<T, 2, MechUEpi<T>, true>(c, FGCG_K_MECH_ROW_INV, epi, spec, ns, ss);
   return r;
@@ -84,24 +84,33 @@ int mech_rhs(fgcg_ctx* c, const MechMat& m, const double* eig) {
 Key mech_key(const fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
   Key key;
   key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm).add(c->prec);
-  key.add(tol).add(maxit).add(c->rows_pick);
+  key.add(tol).add(maxit).add(c->rows_pick).add(c->plan_row).add(c->plan_col);
   return key;
 }
 
-// Autotuning of the rows per block of the mechanics row passes (the forward
-// pass with the CG update and the inverse pass with the direction update): each
-// candidate is timed with HIP events on the context's own workspace and
-// samples, 3 + 10 launches of the pair, and the fastest is kept.  The choice
-// does not change any result (rows are paired and transformed identically;
-// these passes carry no partial sums).  The workspace and the CG state are
-// scratch here: every solve initialises them afterwards.
-template <typename T> int tune_rows_t(fgcg_ctx* c) {
-  std::vector<int> cand;
-  with_n(c->nx, [&](auto NXc) { cand = rows_candidates<decltype(NXc)::value>(); });
-  if (cand.size() == 1) {
-    c->rows_pick = cand[0];
-    return 0;
-  }
+// Autotuning of the 2D mechanics passes: the rows per block and the radix
+// plan of the row passes (the forward pass with the CG update and the inverse
+// pass with the direction update, timed as a pair) and the radix plan of the
+// Green column pass.  Each candidate is timed with HIP events on the context's
+// own workspace and samples, 3 + 10 launches, and the fastest is kept; values
+// fixed through the options are not tuned.  The rows choice does not change
+// any result (rows are paired and transformed identically; these passes carry
+// no partial sums); the plan changes the rounding of the transforms only.
+// The workspace and the CG state are overwritten, so this runs before the
+// right-hand side is formed.
+template <typename T> int tune_passes_t(fgcg_ctx* c) {
+  std::vector<int> rows_c, prow_c, pcol_c;
+  with_n(c->nx, [&](auto NXc) {
+    constexpr int NX = decltype(NXc)::value;
+    rows_c = rows_candidates<NX>();
+    prow_c = plan1_differs(NX) ? std::vector<int>{1, 2} : std::vector<int>{1};
+  });
+  with_n(c->ny, [&](auto NYc) {
+    pcol_c = plan1_differs(decltype(NYc)::value) ? std::vector<int>{1, 2} : std::vector<int>{1};
+  });
+  if (c->rows_pick) rows_c = {c->rows_pick};
+  if (c->plan_row) prow_c = {c->plan_row};
+  if (c->plan_col) pcol_c = {c->plan_col};
   const int ns = c->nsamp;
   const long long ss = spec_ss(c);
   std::vector<CgState> hs(ns);
@@ -123,38 +132,70 @@ template <typename T> int tune_rows_t(fgcg_ctx* c) {
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
   const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, npa};
   const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, nprz, 0, 0.0, 1 << 30};
+  // the Green pass without a CG state (timed after the row passes, whose
+  // direction update reads part_rr; 2 nxh partial sums per sample)
+  const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  float best = 0.f;
-  int pick = cand[0], rc = 0;
-  for (int R_ : cand) {
-    c->rows_pick = R_;
+  int rc = 0;
+  // times 3 + 10 launches of f, the last 10 between events
+  auto time_it = [&](auto&& f) -> float {
     for (int rep = 0; rep < 13 && !rc; ++rep) {
       if (rep == 3 && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(FGCG_EHIP, "hipEventRecord");
-      rc |= launch_row_fwd<T, 2, MechUPro<T>, true>(c, -1, pro, spec, ns, ss);
-      rc |= launch_row_inv<T, 2, MechUEpi<T>, true>(c, -1, epi, spec, ns, ss);
+      rc |= f();
     }
     float ms = 0.f;
     if (!rc && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-      rc = fail(FGCG_EHIP, "timing a row-pass candidate failed");
-    if (rc) break;
-    if (R_ == cand[0] || ms < best) {
-      best = ms;
-      pick = R_;
+      rc = fail(FGCG_EHIP, "timing a pass candidate failed");
+    return ms;
+  };
+  float best = 0.f;
+  int pick_r = rows_c[0], pick_p = prow_c[0];
+  if (rows_c.size() * prow_c.size() > 1) {
+    for (int R_ : rows_c)
+      for (int P_ : prow_c) {
+        if (rc) break;
+        c->rows_pick = R_;
+        c->plan_row = P_;
+        const float ms = time_it([&] {
+          return launch_row_fwd<T, 2, MechUPro<T>, true>(c, -1, pro, spec, ns, ss) |
+                 launch_row_inv<T, 2, MechUEpi<T>, true>(c, -1, epi, spec, ns, ss);
+        });
+        if ((R_ == rows_c[0] && P_ == prow_c[0]) || ms < best) {
+          best = ms;
+          pick_r = R_;
+          pick_p = P_;
+        }
+      }
+  }
+  int pick_c = pcol_c[0];
+  if (pcol_c.size() > 1) {
+    for (int P_ : pcol_c) {
+      if (rc) break;
+      c->plan_col = P_;
+      const float ms = time_it([&] {
+        return launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, green, spec, spec, 2 * ns, ss / 2);
+      });
+      if (P_ == pcol_c[0] || ms < best) {
+        best = ms;
+        pick_c = P_;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   HIPCHK(hipGetLastError());
-  c->rows_pick = pick;
+  c->rows_pick = pick_r;
+  c->plan_row = pick_p;
+  c->plan_col = pick_c;
   return rc;
 }
 
-inline int tune_rows(fgcg_ctx* c) {
-  if (c->rows_pick) return 0;
-  return c->prec == FGCG_FP64 ? tune_rows_t<double>(c) : tune_rows_t<float>(c);
+inline int tune_passes(fgcg_ctx* c) {
+  if (c->rows_pick && c->plan_row && c->plan_col) return 0;
+  return c->prec == FGCG_FP64 ? tune_passes_t<double>(c) : tune_passes_t<float>(c);
 }
 
 // Builds the iteration closure of a context (period RELIABLE_EVERY in FP32-mixed).
@@ -229,7 +270,7 @@ int mech_solve_single(fgcg_ctx* c, const MechMat& m, const double* eig, const do
                       double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
   const double t0 = now();
   int rc;
-  if ((rc = tune_rows(c)) || (rc = upload_ems(c, em)) || (rc = mech_rhs(c, m, eig))) return rc;
+  if ((rc = tune_passes(c)) || (rc = upload_ems(c, em)) || (rc = mech_rhs(c, m, eig))) return rc;
   CgState s;
   if ((rc = mech_pcg(c, m, tol, maxit, &s))) return rc;
   double e;
@@ -706,6 +747,12 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
       c->rows_pick = value;
       return FGCG_OK;
     }
+    case FGCG_OPT_ROW_PLAN:
+    case FGCG_OPT_COL_PLAN:
+      if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "radix plans are tuned on 2D grids");
+      if (value < 0 || value > 2) return fail(FGCG_EINVAL, "radix plan must be 0 (tune), 1 or 2");
+      (option == FGCG_OPT_ROW_PLAN ? c->plan_row : c->plan_col) = value;
+      return FGCG_OK;
     default:
       return fail(FGCG_EINVAL, "unknown option");
   }
@@ -718,6 +765,8 @@ int fgcg_get_option(fgcg_ctx* c, int option, int* value) {
     case FGCG_OPT_GRAPHS: *value = c->use_graphs ? 1 : 0; return FGCG_OK;
     case FGCG_OPT_CHUNK: *value = c->chunk; return FGCG_OK;
     case FGCG_OPT_ROWS: *value = c->rows_pick; return FGCG_OK;
+    case FGCG_OPT_ROW_PLAN: *value = c->plan_row; return FGCG_OK;
+    case FGCG_OPT_COL_PLAN: *value = c->plan_col; return FGCG_OK;
     default: return fail(FGCG_EINVAL, "unknown option");
   }
 }
@@ -1024,7 +1073,7 @@ int fgcg_mech_solve_batched(fgcg_batch* b, const uint8_t* const* phases, int nph
                             st));
       for (int j = 0; j < 3; ++j) em[3 * s + j] = eps_mac[3 * mem[s] + j];
     }
-    if ((rc = tune_rows(c)) || (rc = upload_ems(c, em.data())) || (rc = mech_rhs(c, mats[g], nullptr))) return rc;
+    if ((rc = tune_passes(c)) || (rc = upload_ems(c, em.data())) || (rc = mech_rhs(c, mats[g], nullptr))) return rc;
     rc = c->prec == FGCG_FP64 ? mech_init<double>(c, mats[g], tol, maxit) : mech_init<float>(c, mats[g], tol, maxit);
     if (rc) return rc;
   }
@@ -1046,7 +1095,7 @@ int fgcg_mech_solve_batched(fgcg_batch* b, const uint8_t* const* phases, int nph
     const int K = c0->prec == FGCG_FP64 ? c0->chunk : 2 * RELIABLE_EVERY;
     Key key = mech_key(c0, mats[0], tol, maxit);
     key.add(K);
-    for (fgcg_ctx* cg : b->groups) key.add(cg->rows_pick);
+    for (fgcg_ctx* cg : b->groups) key.add(cg->rows_pick).add(cg->plan_row).add(cg->plan_col);
     if (key.b != b->key || !b->exec[0] || !b->exec[1]) {
       for (auto& e : b->exec)
         if (e) (void)hipGraphExecDestroy(e);

@@ -89,7 +89,7 @@ template <class P> struct ProLoads<P, decltype((void)sizeof(typename P::Ld))> {
   static constexpr bool value = true;
 };
 
-template <typename T, int NX, int NOUT, class Pro, int ROWS = rows_for(NX)>
+template <typename T, int NX, int NOUT, class Pro, int ROWS = rows_for(NX), int PL = 0>
 __global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type* spec, int ny,
                                                 long long spec_ss,
                                                 const typename cvec<T>::type* __restrict__ tw) {
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type*
       }
     }
     __syncthreads();
-    fft_lds<T, NX, NP, NT, false>(buf, tw);
+    fft_lds<T, NX, NP, NT, false, FlatIdx<NX>, PL>(buf, tw);
     for (int idx = tid; idx < NXH * NP; idx += NT) {
       const int pair = idx % NP, kx = idx / NP;
       const C z = buf[lds(pair * NX + kx)];
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type*
 }
 
 // ------------------------------------------------------------------ column
-template <typename T, int NY, int NIN, int NOUT, class Sym>
+template <typename T, int NY, int NIN, int NOUT, class Sym, int PL = 0>
 __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::type* spec_in,
                                             typename cvec<T>::type* spec_out, int nxh,
                                             long long ss_in, long long ss_out,
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
     buf[lds(c * NY + y)] = in[((long long)c * nxh + kx) * NY + y];
   }
   __syncthreads();
-  fft_lds<T, NY, NIN, NT, false>(buf, tw);
+  fft_lds<T, NY, NIN, NT, false, FlatIdx<NY>, PL>(buf, tw);
   double acc = 0.0;
   for (int ky = tid; ky < NY; ky += NT) {
     C a[NIN], b[NOUT];
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
   }
   __syncthreads();
   sym.partial(s, block_sum(acc, red));
-  fft_lds<T, NY, NOUT, NT, true>(buf, tw);
+  fft_lds<T, NY, NOUT, NT, true, FlatIdx<NY>, PL>(buf, tw);
   C* out = spec_out + s * ss_out;
   for (int idx = tid; idx < NOUT * NY; idx += NT) {
     const int c = idx / NY, y = idx - (idx / NY) * NY;
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
 // The half spectrum of component c + 1 is loaded into registers before the
 // transform of component c (the barriers wait for LDS traffic only), so its
 // transposed reads overlap the LDS work.
-template <typename T, int NX, int NIN, int ROWS = rows_for(NX)>
+template <typename T, int NX, int NIN, int ROWS = rows_for(NX), int PL = 0>
 __device__ __forceinline__ void rows_inverse(
     const typename cvec<T>::type* in, int ny, int y0, typename cvec<T>::type* buf,
     T (*vals)[NIN], const typename cvec<T>::type* __restrict__ tw) {
@@ -268,7 +268,7 @@ __device__ __forceinline__ void rows_inverse(
     }
     if (c + 1 < NIN) load(c + 1);
     __syncthreads();
-    fft_lds<T, NX, NP, NT, true>(buf, tw);
+    fft_lds<T, NX, NP, NT, true, FlatIdx<NX>, PL>(buf, tw);
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int v = tid + i * NT;
@@ -293,7 +293,7 @@ template <class E> struct EpiPre<E, decltype((void)E::NPRE)> {
   static constexpr int N = E::NPRE;
 };
 
-template <typename T, int NX, int NIN, class Epi, int ROWS = rows_for(NX)>
+template <typename T, int NX, int NIN, class Epi, int ROWS = rows_for(NX), int PL = 0>
 __global__ void __launch_bounds__(NT) k_row_inv(Epi epi, const typename cvec<T>::type* spec, int ny,
                                                 long long spec_ss,
                                                 const typename cvec<T>::type* __restrict__ tw) {
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(NT) k_row_inv(Epi epi, const typename cvec<T>:
     }
   }
   T vals[VPT][NIN];
-  rows_inverse<T, NX, NIN, ROWS>(spec + s * spec_ss, ny, y0, buf, vals, tw);
+  rows_inverse<T, NX, NIN, ROWS, PL>(spec + s * spec_ss, ny, y0, buf, vals, tw);
   double acc = 0.0;
 #pragma unroll
   for (int i = 0; i < VPT; ++i) {

@@ -181,7 +181,7 @@ class Context:
         except Exception:
             pass
 
-    OPTIONS = {"scalar_spectral": 0, "graphs": 1, "chunk": 2, "rows": 3}
+    OPTIONS = {"scalar_spectral": 0, "graphs": 1, "chunk": 2, "rows": 3, "row_plan": 4, "col_plan": 5}
 
     def set_option(self, name, value):
         _check(self.lib.fgcg_set_option(self.ptr, self.OPTIONS[name], int(value)), "fgcg_set_option")

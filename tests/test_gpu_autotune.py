@@ -1,16 +1,21 @@
-"""GPU tests of the row-pass autotuner (rows per block of the 2D mechanics
-passes, FGCG_OPT_ROWS).
+"""GPU tests of the autotuner of the 2D mechanics passes: rows per block of
+the row passes (FGCG_OPT_ROWS) and the radix plans of the LDS transforms in
+the row passes and the Green column pass (FGCG_OPT_ROW_PLAN / _COL_PLAN).
 
-* an autotuned context ends its first mechanics solve with one of the
+* an autotuned context ends its first mechanics solve with one of the rows
   candidates (the default for nx times 1/2, 1, 2, even, 2..16, at most 4096
-  voxels per block);
-* every candidate gives bitwise the same solution and iteration count (the
-  choice changes timing only), FP64 and FP32-mixed;
-* values outside the candidate set are rejected.
+  voxels per block) and a plan in {1, 2} (1 where radix 16 does not fit);
+* every rows candidate gives bitwise the same solution and iteration count
+  (the choice changes timing only), FP64 and FP32-mixed;
+* every plan combination (radix 8 or radix 16 in the row and column
+  transforms) matches the FP64 oracle at fixed iterations (<= 1e-10) and the
+  FP32-mixed path with radix 16 matches the FP64 solve (<= 1e-5);
+* values outside the candidate sets, and plans on 3D contexts, are rejected.
 """
 import numpy as np
 import pytest
 
+from oracle import mech as omech
 from paper_2305_13081_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -63,3 +68,79 @@ def test_rows_option_rejects(torch_dev):
         ctx.set_option("rows", 64)
     ctx.set_option("rows", 0)
     assert ctx.get_option("rows") == 0
+
+
+def plan_differs(n):
+    """Radix 16 gives a different schedule from radix 8 for length n."""
+    a = 0
+    while n % 3 ** (a + 1) == 0:
+        a += 1
+    b = int(np.log2(n // 3 ** a))
+    return b >= 4 and b % 4 != 1 or b >= 9
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 48), (256, 128), (48, 512), (96, 32)])
+def test_plans_fixed_iteration_parity(torch_dev, nx, ny):
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    ph, _ = inputs.box_fractal(max(nx, ny), 2, 4, 1.7, 0.3, np.random.default_rng(3 * nx + ny))
+    ph = np.ascontiguousarray(ph[:ny, :nx])
+    e = np.where(ph == 0, 1e-3, 0.0)
+    phase, eg = torch.from_numpy(ph).to(dev), torch.from_numpy(e).to(dev)
+    k = 12
+    o = omech.mech_solve(ph, E_TAB, NU_TAB, (2e-4, 0.0, 1e-4), H, e=e, fixed_iters=k)
+    for pr in (1, 2):
+        for pc in (1, 2):
+            ctx = fgcg.Context(nx, ny, H)
+            ctx.set_option("row_plan", pr)
+            ctx.set_option("col_plan", pc)
+            r = ctx.mech_solve(phase, E_TAB, NU_TAB, (2e-4, 0.0, 1e-4), eig=eg, tol=0.0, maxit=k)
+            assert ctx.get_option("row_plan") == pr and ctx.get_option("col_plan") == pc
+            err = float(np.linalg.norm(r["strain"].cpu().numpy() - o["strain"]) / np.linalg.norm(o["strain"]))
+            print(f"plans {nx}x{ny} row {pr} col {pc}: fixed k={k} strain rel err {err:.2e}", flush=True)
+            assert r["info"]["iters"] == k and err < 1e-10
+
+
+def test_plans_tuned_and_fp32(torch_dev):
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    nx, ny = 512, 96
+    ph, _ = inputs.box_fractal(512, 2, 5, 1.8, 0.3, np.random.default_rng(11))
+    phase = torch.from_numpy(np.ascontiguousarray(ph[:ny, :nx])).to(dev)
+    ref_ctx = fgcg.Context(nx, ny, H)
+    ref_ctx.set_option("row_plan", 1)
+    ref_ctx.set_option("col_plan", 1)
+    ref = ref_ctx.mech_solve(phase, E_TAB, NU_TAB, (1e-3, 0.0, 0.0), tol=1e-12, maxit=50000)
+    # autotuned FP64: a plan in {1, 2} for both passes, same solution to rounding
+    ctx = fgcg.Context(nx, ny, H)
+    assert ctx.get_option("row_plan") == 0 and ctx.get_option("col_plan") == 0
+    out = ctx.mech_solve(phase, E_TAB, NU_TAB, (1e-3, 0.0, 0.0), tol=1e-12, maxit=50000)
+    pr, pc = ctx.get_option("row_plan"), ctx.get_option("col_plan")
+    print(f"tuned {nx}x{ny}: rows {ctx.get_option('rows')} row plan {pr} col plan {pc}", flush=True)
+    assert pr in ((1, 2) if plan_differs(nx) else (1,)) and pc in ((1, 2) if plan_differs(ny) else (1,))
+    err = float((out["strain"] - ref["strain"]).norm() / ref["strain"].norm())
+    assert err < 1e-10, err
+    # FP32-mixed with radix 16 in both passes against the FP64 solve
+    c32 = fgcg.Context(nx, ny, H, precision=fgcg.FP32_MIXED)
+    c32.set_option("row_plan", 2)
+    c32.set_option("col_plan", 2)
+    o32 = c32.mech_solve(phase, E_TAB, NU_TAB, (1e-3, 0.0, 0.0), tol=1e-10, maxit=50000)
+    err = float((o32["strain"] - ref["strain"]).norm() / ref["strain"].norm())
+    print(f"FP32-mixed radix-16 plans vs FP64: strain rel diff {err:.2e}", flush=True)
+    assert o32["info"]["status"] == 0 and err < 1e-5
+
+
+def test_plan_option_rejects(torch_dev):
+    from paper_2305_13081_amd import fgcg
+    ctx = fgcg.Context(256, 64, H)
+    for name in ("row_plan", "col_plan"):
+        for bad in (3, -1):
+            with pytest.raises(fgcg.FgcgError):
+                ctx.set_option(name, bad)
+        ctx.set_option(name, 2)
+        assert ctx.get_option(name) == 2
+        ctx.set_option(name, 0)
+        assert ctx.get_option(name) == 0
+    c3 = fgcg.Context(16, 16, H, nz=16)
+    with pytest.raises(fgcg.FgcgError):
+        c3.set_option("row_plan", 1)
