@@ -272,6 +272,21 @@ int fgcg_diffusion_apply(fgcg_ctx* ctx, const uint8_t* phase, int nphase, const 
 int fgcg_debug_fft(fgcg_ctx* ctx, int dir, const double* in, double* out);
 
 /* ---- profiling -------------------------------------------------------- */
+/* Measurement hook for the HBM roofline of the 2D mechanics passes (Sec. 2.6
+ * iteration): launches the pass of kind FGCG_K_MECH_ROW_FWD, _ROW_INV or
+ * _COL (enum below) reps times back to back (after 3 untimed launches) on the
+ * context's stream, between two HIP events, with the context's tuned rows per
+ * block and radix plans (tuned first if not yet tuned), and stores the
+ * average duration of one launch in microseconds (host double).  Unlike
+ * events around every launch inside the CG graphs, back-to-back launches do
+ * not add the dispatch gap of an event node to each launch.  The workspace is
+ * first set to zero fields with a running CG state, so the pass does its full
+ * work on data of the context's sizes; the previous solution in the workspace
+ * is lost (the next solve starts over as always).  Synchronises the stream.
+ * EINVAL for NULL pointers, another kind or reps outside 1..100000;
+ * EUNSUPPORTED on 3D contexts. */
+int fgcg_time_pass(fgcg_ctx* ctx, int kind, int reps, double* us_per_launch);
+
 /* Kernel kinds that can be timed with HIP events around every launch. */
 enum {
   FGCG_K_MECH_ROW_FWD = 0,

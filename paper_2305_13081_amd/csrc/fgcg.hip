@@ -98,21 +98,11 @@ Key mech_key(const fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
 // no partial sums); the plan changes the rounding of the transforms only.
 // The workspace and the CG state are overwritten, so this runs before the
 // right-hand side is formed.
-template <typename T> int tune_passes_t(fgcg_ctx* c) {
-  std::vector<int> rows_c, prow_c, pcol_c;
-  with_n(c->nx, [&](auto NXc) {
-    constexpr int NX = decltype(NXc)::value;
-    rows_c = rows_candidates<NX>();
-    prow_c = plan1_differs(NX) ? std::vector<int>{1, 2} : std::vector<int>{1};
-  });
-  with_n(c->ny, [&](auto NYc) {
-    pcol_c = plan1_differs(decltype(NYc)::value) ? std::vector<int>{1, 2} : std::vector<int>{1};
-  });
-  if (c->rows_pick) rows_c = {c->rows_pick};
-  if (c->plan_row) prow_c = {c->plan_row};
-  if (c->plan_col) pcol_c = {c->plan_col};
+// Timing workspace of the 2D mechanics passes: zero fields and spectra, a
+// running CG state per sample (unit r.z, no stop test) and unit partial sums,
+// so that every pass does its full work.
+template <typename T> int timing_workspace(fgcg_ctx* c) {
   const int ns = c->nsamp;
-  const long long ss = spec_ss(c);
   std::vector<CgState> hs(ns);
   for (CgState& t : hs) {
     std::memset(&t, 0, sizeof t);
@@ -128,6 +118,29 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   std::vector<double> ones((size_t)std::max(npa, nprz) * ns, 1.0);
   HIPCHK(hipMemcpyAsync(c->part_a, ones.data(), sizeof(double) * npa * ns, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->part_rr, ones.data(), sizeof(double) * nprz * ns, hipMemcpyHostToDevice, c->stream));
+  // the host vectors are read by the copies: wait before they go out of scope
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+template <typename T> int tune_passes_t(fgcg_ctx* c) {
+  std::vector<int> rows_c, prow_c, pcol_c;
+  with_n(c->nx, [&](auto NXc) {
+    constexpr int NX = decltype(NXc)::value;
+    rows_c = rows_candidates<NX>();
+    prow_c = plan1_differs(NX) ? std::vector<int>{1, 2} : std::vector<int>{1};
+  });
+  with_n(c->ny, [&](auto NYc) {
+    pcol_c = plan1_differs(decltype(NYc)::value) ? std::vector<int>{1, 2} : std::vector<int>{1};
+  });
+  if (c->rows_pick) rows_c = {c->rows_pick};
+  if (c->plan_row) prow_c = {c->plan_row};
+  if (c->plan_col) pcol_c = {c->plan_col};
+  const int ns = c->nsamp;
+  const long long ss = spec_ss(c);
+  int rc = timing_workspace<T>(c);
+  if (rc) return rc;
+  const int npa = c->nkpt, nprz = 2 * c->ncol;
   CT<T>* spec = (CT<T>*)c->spec;
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
   const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, npa};
@@ -138,7 +151,6 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  int rc = 0;
   // times 3 + 10 launches of f, the last 10 between events
   auto time_it = [&](auto&& f) -> float {
     for (int rep = 0; rep < 13 && !rc; ++rep) {
@@ -196,6 +208,41 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
 inline int tune_passes(fgcg_ctx* c) {
   if (c->rows_pick && c->plan_row && c->plan_col) return 0;
   return c->prec == FGCG_FP64 ? tune_passes_t<double>(c) : tune_passes_t<float>(c);
+}
+
+// Average duration of one 2D mechanics pass launched reps times back to back
+// (after 3 untimed launches) between two HIP events on the context's stream,
+// with the tuned rows per block and radix plans, on the timing workspace.
+template <typename T> int time_pass_t(fgcg_ctx* c, int kind, int reps, double* us) {
+  int rc = timing_workspace<T>(c);
+  if (rc) return rc;
+  const int ns = c->nsamp;
+  const long long ss = spec_ss(c);
+  CT<T>* spec = (CT<T>*)c->spec;
+  const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
+  const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt};
+  const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, 0.0, 1 << 30};
+  // (only one kind is launched: the Green pass's partial sums may overwrite
+  // the unit sums the direction update would read)
+  const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
+  auto one = [&]() -> int {
+    if (kind == FGCG_K_MECH_ROW_FWD) return launch_row_fwd<T, 2, MechUPro<T>, true>(c, -1, pro, spec, ns, ss);
+    if (kind == FGCG_K_MECH_ROW_INV) return launch_row_inv<T, 2, MechUEpi<T>, true>(c, -1, epi, spec, ns, ss);
+    return launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, green, spec, spec, 2 * ns, ss / 2);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(FGCG_EHIP, "hipEventCreate");
+  for (int i = 0; i < 3 && !rc; ++i) rc = one();
+  if (!rc && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(FGCG_EHIP, "hipEventRecord");
+  for (int i = 0; i < reps && !rc; ++i) rc = one();
+  float ms = 0.f;
+  if (!rc && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = fail(FGCG_EHIP, "timing the pass failed");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (!rc) *us = 1e3 * (double)ms / reps;
+  return rc;
 }
 
 // Builds the iteration closure of a context (period RELIABLE_EVERY in FP32-mixed).
@@ -956,6 +1003,21 @@ int fgcg_debug_fft(fgcg_ctx* c, int dir, const double* in, double* out) {
   int rc;
   if ((rc = enter(c))) return rc;
   return debug_fft(c, dir, in, out);
+}
+
+int fgcg_time_pass(fgcg_ctx* c, int kind, int reps, double* us_per_launch) {
+  if (!c || !us_per_launch) return fail(FGCG_EINVAL, "ctx/us_per_launch is NULL");
+  if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "pass timing covers the 2D mechanics passes");
+  if (kind != FGCG_K_MECH_ROW_FWD && kind != FGCG_K_MECH_ROW_INV && kind != FGCG_K_MECH_COL)
+    return fail(FGCG_EINVAL, "kind must be FGCG_K_MECH_ROW_FWD, _ROW_INV or _COL");
+  if (reps < 1 || reps > 100000) return fail(FGCG_EINVAL, "reps must be 1..100000");
+  int rc;
+  if ((rc = enter(c)) || (rc = tune_passes(c))) return rc;
+  rc = c->prec == FGCG_FP64 ? time_pass_t<double>(c, kind, reps, us_per_launch)
+                            : time_pass_t<float>(c, kind, reps, us_per_launch);
+  if (rc) return rc;
+  HIPCHK(hipGetLastError());
+  return FGCG_OK;
 }
 
 int fgcg_profile(fgcg_ctx* c, unsigned mask) {

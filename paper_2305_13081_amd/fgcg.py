@@ -108,6 +108,7 @@ _SIGS = {
     "fgcg_phasefield_apply": (_ip, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]),
     "fgcg_diffusion_apply": (_ip, [_vp, _vp, _ip, _dp, _dp, ctypes.c_double, _vp, _vp]),
     "fgcg_debug_fft": (_ip, [_vp, _ip, _vp, _vp]),
+    "fgcg_time_pass": (_ip, [_vp, _ip, _ip, _dp]),
     "fgcg_profile": (_ip, [_vp, ctypes.c_uint]),
     "fgcg_profile_read": (_ip, [_vp, _ip, _dp, ctypes.POINTER(ctypes.c_longlong)]),
     "fgcg_kernel_name": (ctypes.c_char_p, [_vp, _ip]),
@@ -402,6 +403,15 @@ class Context:
         for k in kinds:
             mask |= 1 << KINDS[k]
         _check(self.lib.fgcg_profile(self.ptr, mask), "fgcg_profile")
+
+    def time_pass(self, kind, reps=200):
+        """Average microseconds of one back-to-back launch of a 2D mechanics
+        pass ("mech_row_fwd", "mech_row_inv", "mech_col"); clears the
+        workspace (fgcg_time_pass)."""
+        us = ctypes.c_double()
+        self._sync_stream()
+        _check(self.lib.fgcg_time_pass(self.ptr, KINDS[kind], int(reps), ctypes.byref(us)), "fgcg_time_pass")
+        return us.value
 
     def profile_read(self, kind):
         ms = ctypes.c_double()

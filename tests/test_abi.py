@@ -47,6 +47,8 @@ def test_binding_loads_and_reports_errors(lib):
     # NULL arguments are rejected on the host before any device work
     assert L.fgcg_create(None, None, None) == -1
     assert L.fgcg_mech_solve(None, None, None, 0.0, None, None, 1e-8, 10, None, None, None, None, None) == -1
+    us = ctypes.c_double()
+    assert L.fgcg_time_pass(None, 0, 10, ctypes.byref(us)) == -1
 
 
 def test_create_rejects_bad_grids_without_gpu(lib):

@@ -10,7 +10,9 @@ the row passes and the Green column pass (FGCG_OPT_ROW_PLAN / _COL_PLAN).
 * every plan combination (radix 8 or radix 16 in the row and column
   transforms) matches the FP64 oracle at fixed iterations (<= 1e-10) and the
   FP32-mixed path with radix 16 matches the FP64 solve (<= 1e-5);
-* values outside the candidate sets, and plans on 3D contexts, are rejected.
+* values outside the candidate sets, and plans on 3D contexts, are rejected;
+* the pass-timing hook (fgcg_time_pass) returns a positive duration for each
+  2D mechanics pass and rejects other kinds, bad repetition counts and 3D.
 """
 import numpy as np
 import pytest
@@ -144,3 +146,24 @@ def test_plan_option_rejects(torch_dev):
     c3 = fgcg.Context(16, 16, H, nz=16)
     with pytest.raises(fgcg.FgcgError):
         c3.set_option("row_plan", 1)
+
+
+def test_time_pass(torch_dev):
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    ctx = fgcg.Context(256, 128, H)
+    times = {k: ctx.time_pass(k, 20) for k in ("mech_row_fwd", "mech_row_inv", "mech_col")}
+    print(f"time_pass 256x128: {times}", flush=True)
+    assert all(0.0 < t < 1e4 for t in times.values())
+    assert ctx.get_option("rows") != 0  # tuned on the way
+    for kind, reps in (("mech_kp", 10), ("mech_row_fwd", 0), ("mech_row_fwd", 100001)):
+        with pytest.raises(fgcg.FgcgError):
+            ctx.time_pass(kind, reps)
+    # the context still solves afterwards
+    ph, _ = inputs.box_fractal(256, 2, 4, 1.7, 0.3, np.random.default_rng(9))
+    out = ctx.mech_solve(torch.from_numpy(np.ascontiguousarray(ph[:128, :256])).to(dev), E_TAB, NU_TAB,
+                         (1e-3, 0.0, 0.0), tol=1e-10, maxit=20000)
+    assert out["info"]["status"] == 0
+    c3 = fgcg.Context(16, 16, H, nz=16)
+    with pytest.raises(fgcg.FgcgError):
+        c3.time_pass("mech_row_fwd", 10)
