@@ -304,6 +304,10 @@ template <typename T, int NC = 2> struct MechUPro {
   __device__ bool begin(int s, double* red, double& sc) const {
     return mech_alpha(st + s, part_a + (long long)s * np_a, np_a, red, sc);
   }
+  // 2D (two components): begin() sums the stiffness pass's partials itself,
+  // so the first loads are issued before it; the 3D passes get one
+  // pre-reduced value and keep loads after it (EARLY)
+  static constexpr bool EARLY = NC == 2;
   struct Ld {
     T x[NC], r[NC], p[NC], q[NC];
   };
@@ -433,6 +437,9 @@ template <typename T, int NC = 2> struct MechUEpi {
     return true;
   }
   static constexpr int NPRE = NC;  // p of the voxel, loaded before the transforms
+  // 2D: begin() sums the column pass's partials itself: prefetch before it
+  // (3D: one pre-reduced value, prefetch after it)
+  static constexpr bool EARLY = NC == 2;
   __device__ void prefetch(int s, int y, int xx, T* pre) const {
     const long long i = (long long)y * nx + xx;
 #pragma unroll

@@ -88,6 +88,19 @@ template <class P, class = void> struct ProLoads {
 template <class P> struct ProLoads<P, decltype((void)sizeof(typename P::Ld))> {
   static constexpr bool value = true;
 };
+// P::EARLY: issue the first loads (or the prefetch) before begin()
+template <class P, class = void> struct ProEarly {
+  static constexpr bool value = false;
+};
+template <class P> struct ProEarly<P, decltype((void)P::EARLY)> {
+  static constexpr bool value = P::EARLY;
+};
+template <class P, bool = ProLoads<P>::value> struct ProLd {
+  struct type {};
+};
+template <class P> struct ProLd<P, true> {
+  using type = typename P::Ld;
+};
 
 template <typename T, int NX, int NOUT, class Pro, int ROWS = rows_for(NX), int PL = 0>
 __global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type* spec, int ny,
@@ -103,19 +116,32 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type*
   __shared__ double red[NT / 64];
   const int s = blockIdx.y;
   const int tid = threadIdx.x;
-  double sc = 0.0;
-  if (!pro.begin(s, red, sc)) return;
   const int y0 = xcd_block() * ROWS;
-  T vals[VPT][NOUT];
-  double acc = 0.0;
   auto valid = [&](int i) {
     const int v = tid + i * NT;
     return (VOX % NT == 0 || v < VOX) && y0 + v / NX < ny;
   };
+  // The loads of the first voxel do not depend on the CG scalars.  Where
+  // begin() reduces many partial sums (Pro::EARLY), they are issued first so
+  // that the two latencies overlap (the empty asm keeps them from being sunk
+  // below the early exit; it emits no instruction).  Otherwise they follow
+  // begin(): its state check would wait for them.
+  typename ProLd<Pro>::type cur;
+  constexpr bool EARLY = ProEarly<Pro>::value;
+  if constexpr (EARLY) {
+    if (valid(0)) pro.load(s, y0 + tid / NX, tid % NX, cur);
+    asm volatile("" ::: "memory");
+  }
+  double sc = 0.0;
+  if (!pro.begin(s, red, sc)) return;
+  if constexpr (ProLoads<Pro>::value && !EARLY) {
+    if (valid(0)) pro.load(s, y0 + tid / NX, tid % NX, cur);
+  }
+  T vals[VPT][NOUT];
+  double acc = 0.0;
   if constexpr (ProLoads<Pro>::value) {
     // loads of voxel i + 1 are issued before the stores of voxel i
-    typename Pro::Ld cur, nxt;
-    if (valid(0)) pro.load(s, y0 + tid / NX, tid % NX, cur);
+    typename Pro::Ld nxt;
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int v = tid + i * NT;
@@ -307,18 +333,27 @@ __global__ void __launch_bounds__(NT) k_row_inv(Epi epi, const typename cvec<T>:
   __shared__ double red[NT / 64];
   const int s = blockIdx.y;
   const int tid = threadIdx.x;
-  double sc = 0.0;
-  if (!epi.begin(s, red, sc)) return;
   const int y0 = xcd_block() * ROWS;
+  // The prefetch of the epilogue's inputs does not depend on the CG scalars:
+  // issued before begin() where that reduces many partial sums (Epi::EARLY),
+  // after it otherwise (as in the forward pass).
   T pre[VPT][NPRE > 0 ? NPRE : 1];
-  if constexpr (NPRE > 0) {
+  auto prefetch = [&](auto& e) {
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int v = tid + i * NT;
       const int row = v / NX, x = v - (v / NX) * NX;
-      if ((VOX % NT == 0 || v < VOX) && y0 + row < ny) epi.prefetch(s, y0 + row, x, pre[i]);
+      if ((VOX % NT == 0 || v < VOX) && y0 + row < ny) e.prefetch(s, y0 + row, x, pre[i]);
     }
+  };
+  constexpr bool EARLY = NPRE > 0 && ProEarly<Epi>::value;
+  if constexpr (EARLY) {
+    prefetch(epi);
+    asm volatile("" ::: "memory");
   }
+  double sc = 0.0;
+  if (!epi.begin(s, red, sc)) return;
+  if constexpr (NPRE > 0 && !EARLY) prefetch(epi);
   T vals[VPT][NIN];
   rows_inverse<T, NX, NIN, ROWS, PL>(spec + s * spec_ss, ny, y0, buf, vals, tw);
   double acc = 0.0;
