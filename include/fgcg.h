@@ -114,8 +114,11 @@ const char* fgcg_last_error(void);
  *       per block) and in the Green column pass.  1: radix 8 (with a trailing
  *       4); 2: radix 16 where it fits (fewer stages, larger butterflies); the
  *       same as 1 for lengths where radix 16 does not fit.  0 (default):
- *       autotune before the next mechanics solve, as for FGCG_OPT_ROWS.  The
- *       plan changes the rounding of the transforms only.  EUNSUPPORTED in 3D.
+ *       autotune before the next mechanics solve, as for FGCG_OPT_ROWS, on
+ *       grids of at least 2^18 voxels (radix 8 below; radix 16 is kept only
+ *       when more than 3 % faster, so near-ties give the same schedule in
+ *       every context of a size).  The plan changes the rounding of the
+ *       transforms only.  EUNSUPPORTED in 3D.
  * Returns EINVAL for an unknown option or value. */
 enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2, FGCG_OPT_ROWS = 3,
        FGCG_OPT_ROW_PLAN = 4, FGCG_OPT_COL_PLAN = 5 };

@@ -29,8 +29,8 @@ template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, i
   if ((rc = launch_row_fwd<T, 2, CopyProN<T, 2>, true>(c, -1, cp, spec, ns, ss))) return rc;
   const MechGreen<T> g0{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
   if ((rc = launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, g0, spec, spec, 2 * ns, ss / 2))) return rc;
-  const MechUEpi<T> e0{fld<T>(c->p, c), c->nx, c->st, c->part_rr, 2 * c->ncol, 1, tol, maxit};
-  if ((rc = launch_row_inv<T, 2, MechUEpi<T>, true>(c, -1, e0, spec, ns, ss))) return rc;
+  const MechUEpi1<T> e0{{fld<T>(c->p, c), c->nx, c->st, c->part_rr, 2 * c->ncol, 1, tol, maxit}};
+  if ((rc = launch_row_inv<T, 1, MechUEpi1<T>, true>(c, -1, e0, spec, 2 * ns, ss / 2))) return rc;
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -46,8 +46,8 @@ template <typename T> int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, i
   int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech_kp<T>, dim3(c->nkpt, ns), m, (const T*)P.p, Q.p, c->n,
                  c->nx, c->ny, (T)(1.0 / c->h), c->st, c->part_a);
   if (!reliable) {
-    const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt};
-    r |= launch_row_fwd<T, 2, MechUPro<T>, true>(c, FGCG_K_MECH_ROW_FWD, pro, spec, ns, ss);
+    const MechUPro1<T> pro{{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt}};
+    r |= launch_row_fwd<T, 1, MechUPro1<T>, true>(c, FGCG_K_MECH_ROW_FWD, pro, spec, 2 * ns, ss / 2);
   } else {
     r |= launch(c, -1, (const void*)&k_mech_fold<T>, dim3(c->npost, ns), X.p, c->xh, (const T*)P.p, 2 * c->n, c->st,
                 (const double*)c->part_a, c->nkpt);
@@ -58,8 +58,8 @@ template <typename T> int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, i
   }
   const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, c->st, c->part_rr};
   r |= launch_col<T, 1, 1, MechGreen<T>, true>(c, FGCG_K_MECH_COL, green, spec, spec, 2 * ns, ss / 2);
-  const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, tol, maxit};
-  r |= launch_row_inv<T, 2, MechUEpi<T>, true>(c, FGCG_K_MECH_ROW_INV, epi, spec, ns, ss);
+  const MechUEpi1<T> epi{{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, tol, maxit}};
+  r |= launch_row_inv<T, 1, MechUEpi1<T>, true>(c, FGCG_K_MECH_ROW_INV, epi, spec, 2 * ns, ss / 2);
   return r;
 }
 
@@ -88,16 +88,6 @@ Key mech_key(const fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
   return key;
 }
 
-// Autotuning of the 2D mechanics passes: the rows per block and the radix
-// plan of the row passes (the forward pass with the CG update and the inverse
-// pass with the direction update, timed as a pair) and the radix plan of the
-// Green column pass.  Each candidate is timed with HIP events on the context's
-// own workspace and samples, 3 + 10 launches, and the fastest is kept; values
-// fixed through the options are not tuned.  The rows choice does not change
-// any result (rows are paired and transformed identically; these passes carry
-// no partial sums); the plan changes the rounding of the transforms only.
-// The workspace and the CG state are overwritten, so this runs before the
-// right-hand side is formed.
 // Timing workspace of the 2D mechanics passes: zero fields and spectra, a
 // running CG state per sample (unit r.z, no stop test) and unit partial sums,
 // so that every pass does its full work.
@@ -123,6 +113,18 @@ template <typename T> int timing_workspace(fgcg_ctx* c) {
   return 0;
 }
 
+// Autotuning of the 2D mechanics passes: the rows per block and the radix
+// plan of the row passes (the forward pass with the CG update and the inverse
+// pass with the direction update, timed as a pair) and the radix plan of the
+// Green column pass.  Each candidate is timed with HIP events on the context's
+// own workspace and samples, 3 + 10 launches; the fastest rows choice is kept,
+// and radix 16 replaces radix 8 only when more than 3 % faster (plans are
+// timed on grids of at least 2^18 voxels, radix 8 below).  Values fixed
+// through the options are not tuned.  The rows choice does not change any
+// result (rows are paired and transformed identically; these passes carry no
+// partial sums); the plan changes the rounding of the transforms only.  The
+// workspace and the CG state are overwritten, so this runs before the
+// right-hand side is formed.
 template <typename T> int tune_passes_t(fgcg_ctx* c) {
   std::vector<int> rows_c, prow_c, pcol_c;
   with_n(c->nx, [&](auto NXc) {
@@ -133,6 +135,9 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   with_n(c->ny, [&](auto NYc) {
     pcol_c = plan1_differs(decltype(NYc)::value) ? std::vector<int>{1, 2} : std::vector<int>{1};
   });
+  // below 2^18 voxels the passes are launch-bound and plan timings are
+  // noise: radix 8 (so every context of a small size has the same schedule)
+  if (c->n < (1LL << 18)) prow_c = pcol_c = {1};
   if (c->rows_pick) rows_c = {c->rows_pick};
   if (c->plan_row) prow_c = {c->plan_row};
   if (c->plan_col) pcol_c = {c->plan_col};
@@ -143,8 +148,8 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   const int npa = c->nkpt, nprz = 2 * c->ncol;
   CT<T>* spec = (CT<T>*)c->spec;
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
-  const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, npa};
-  const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, nprz, 0, 0.0, 1 << 30};
+  const MechUPro1<T> pro{{X, R, P, Q, c->nx, c->st, c->part_a, npa}};
+  const MechUEpi1<T> epi{{P, c->nx, c->st, c->part_rr, nprz, 0, 0.0, 1 << 30}};
   // the Green pass without a CG state (timed after the row passes, whose
   // direction update reads part_rr; 2 nxh partial sums per sample)
   const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
@@ -163,38 +168,46 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
       rc = fail(FGCG_EHIP, "timing a pass candidate failed");
     return ms;
   };
-  float best = 0.f;
-  int pick_r = rows_c[0], pick_p = prow_c[0];
+  // The rows choice keeps the fastest candidate (it never changes results).
+  // A radix plan other than the first candidate must win by more than 3 %:
+  // the plan changes rounding, so near-ties (timing noise) keep one schedule
+  // and contexts of the same size agree.
+  constexpr float PLAN_MARGIN = 0.97f;
+  std::vector<float> best_p(prow_c.size(), 0.f);
+  std::vector<int> rows_p(prow_c.size(), rows_c[0]);
   if (rows_c.size() * prow_c.size() > 1) {
     for (int R_ : rows_c)
-      for (int P_ : prow_c) {
+      for (size_t ip = 0; ip < prow_c.size(); ++ip) {
         if (rc) break;
         c->rows_pick = R_;
-        c->plan_row = P_;
+        c->plan_row = prow_c[ip];
         const float ms = time_it([&] {
-          return launch_row_fwd<T, 2, MechUPro<T>, true>(c, -1, pro, spec, ns, ss) |
-                 launch_row_inv<T, 2, MechUEpi<T>, true>(c, -1, epi, spec, ns, ss);
+          return launch_row_fwd<T, 1, MechUPro1<T>, true>(c, -1, pro, spec, 2 * ns, ss / 2) |
+                 launch_row_inv<T, 1, MechUEpi1<T>, true>(c, -1, epi, spec, 2 * ns, ss / 2);
         });
-        if ((R_ == rows_c[0] && P_ == prow_c[0]) || ms < best) {
-          best = ms;
-          pick_r = R_;
-          pick_p = P_;
+        if (R_ == rows_c[0] || ms < best_p[ip]) {
+          best_p[ip] = ms;
+          rows_p[ip] = R_;
         }
       }
   }
+  size_t ip_pick = 0;
+  for (size_t ip = 1; ip < prow_c.size(); ++ip)
+    if (best_p[ip] < PLAN_MARGIN * best_p[ip_pick]) ip_pick = ip;
+  const int pick_r = rows_p[ip_pick], pick_p = prow_c[ip_pick];
   int pick_c = pcol_c[0];
   if (pcol_c.size() > 1) {
-    for (int P_ : pcol_c) {
-      if (rc) break;
-      c->plan_col = P_;
-      const float ms = time_it([&] {
+    std::vector<float> tc(pcol_c.size(), 0.f);
+    for (size_t ip = 0; ip < pcol_c.size() && !rc; ++ip) {
+      c->plan_col = pcol_c[ip];
+      tc[ip] = time_it([&] {
         return launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, green, spec, spec, 2 * ns, ss / 2);
       });
-      if (P_ == pcol_c[0] || ms < best) {
-        best = ms;
-        pick_c = P_;
-      }
     }
+    size_t ic = 0;
+    for (size_t ip = 1; ip < pcol_c.size(); ++ip)
+      if (tc[ip] < PLAN_MARGIN * tc[ic]) ic = ip;
+    pick_c = pcol_c[ic];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -220,14 +233,16 @@ template <typename T> int time_pass_t(fgcg_ctx* c, int kind, int reps, double* u
   const long long ss = spec_ss(c);
   CT<T>* spec = (CT<T>*)c->spec;
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
-  const MechUPro<T> pro{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt};
-  const MechUEpi<T> epi{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, 0.0, 1 << 30};
+  const MechUPro1<T> pro{{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt}};
+  const MechUEpi1<T> epi{{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, 0.0, 1 << 30}};
   // (only one kind is launched: the Green pass's partial sums may overwrite
   // the unit sums the direction update would read)
   const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
   auto one = [&]() -> int {
-    if (kind == FGCG_K_MECH_ROW_FWD) return launch_row_fwd<T, 2, MechUPro<T>, true>(c, -1, pro, spec, ns, ss);
-    if (kind == FGCG_K_MECH_ROW_INV) return launch_row_inv<T, 2, MechUEpi<T>, true>(c, -1, epi, spec, ns, ss);
+    if (kind == FGCG_K_MECH_ROW_FWD)
+      return launch_row_fwd<T, 1, MechUPro1<T>, true>(c, -1, pro, spec, 2 * ns, ss / 2);
+    if (kind == FGCG_K_MECH_ROW_INV)
+      return launch_row_inv<T, 1, MechUEpi1<T>, true>(c, -1, epi, spec, 2 * ns, ss / 2);
     return launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, green, spec, spec, 2 * ns, ss / 2);
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
