@@ -29,8 +29,8 @@ template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, i
   if ((rc = launch_row_fwd<T, 2, CopyProN<T, 2>, true>(c, -1, cp, spec, ns, ss))) return rc;
   const MechGreen<T> g0{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
   if ((rc = launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, g0, spec, spec, 2 * ns, ss / 2))) return rc;
-  const MechUEpi1<T> e0{{fld<T>(c->p, c), c->nx, c->st, c->part_rr, 2 * c->ncol, 1, tol, maxit}};
-  if ((rc = launch_row_inv<T, 1, MechUEpi1<T>, true>(c, -1, e0, spec, 2 * ns, ss / 2))) return rc;
+  const MechUEpiC<T, 2> e0{{fld<T>(c->p, c), c->nx, c->st, c->part_rr, 2 * c->ncol, 1, tol, maxit}};
+  if ((rc = launch_row_inv<T, 1, MechUEpiC<T, 2>, true>(c, -1, e0, spec, 2 * ns, ss / 2))) return rc;
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -46,8 +46,8 @@ template <typename T> int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, i
   int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech_kp<T>, dim3(c->nkpt, ns), m, (const T*)P.p, Q.p, c->n,
                  c->nx, c->ny, (T)(1.0 / c->h), c->st, c->part_a);
   if (!reliable) {
-    const MechUPro1<T> pro{{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt}};
-    r |= launch_row_fwd<T, 1, MechUPro1<T>, true>(c, FGCG_K_MECH_ROW_FWD, pro, spec, 2 * ns, ss / 2);
+    const MechUProC<T, 2> pro{{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt}};
+    r |= launch_row_fwd<T, 1, MechUProC<T, 2>, true>(c, FGCG_K_MECH_ROW_FWD, pro, spec, 2 * ns, ss / 2);
   } else {
     r |= launch(c, -1, (const void*)&k_mech_fold<T>, dim3(c->npost, ns), X.p, c->xh, (const T*)P.p, 2 * c->n, c->st,
                 (const double*)c->part_a, c->nkpt);
@@ -58,8 +58,8 @@ template <typename T> int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, i
   }
   const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, c->st, c->part_rr};
   r |= launch_col<T, 1, 1, MechGreen<T>, true>(c, FGCG_K_MECH_COL, green, spec, spec, 2 * ns, ss / 2);
-  const MechUEpi1<T> epi{{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, tol, maxit}};
-  r |= launch_row_inv<T, 1, MechUEpi1<T>, true>(c, FGCG_K_MECH_ROW_INV, epi, spec, 2 * ns, ss / 2);
+  const MechUEpiC<T, 2> epi{{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, tol, maxit}};
+  r |= launch_row_inv<T, 1, MechUEpiC<T, 2>, true>(c, FGCG_K_MECH_ROW_INV, epi, spec, 2 * ns, ss / 2);
   return r;
 }
 
@@ -148,8 +148,8 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   const int npa = c->nkpt, nprz = 2 * c->ncol;
   CT<T>* spec = (CT<T>*)c->spec;
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
-  const MechUPro1<T> pro{{X, R, P, Q, c->nx, c->st, c->part_a, npa}};
-  const MechUEpi1<T> epi{{P, c->nx, c->st, c->part_rr, nprz, 0, 0.0, 1 << 30}};
+  const MechUProC<T, 2> pro{{X, R, P, Q, c->nx, c->st, c->part_a, npa}};
+  const MechUEpiC<T, 2> epi{{P, c->nx, c->st, c->part_rr, nprz, 0, 0.0, 1 << 30}};
   // the Green pass without a CG state (timed after the row passes, whose
   // direction update reads part_rr; 2 nxh partial sums per sample)
   const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
@@ -182,8 +182,8 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
         c->rows_pick = R_;
         c->plan_row = prow_c[ip];
         const float ms = time_it([&] {
-          return launch_row_fwd<T, 1, MechUPro1<T>, true>(c, -1, pro, spec, 2 * ns, ss / 2) |
-                 launch_row_inv<T, 1, MechUEpi1<T>, true>(c, -1, epi, spec, 2 * ns, ss / 2);
+          return launch_row_fwd<T, 1, MechUProC<T, 2>, true>(c, -1, pro, spec, 2 * ns, ss / 2) |
+                 launch_row_inv<T, 1, MechUEpiC<T, 2>, true>(c, -1, epi, spec, 2 * ns, ss / 2);
         });
         if (R_ == rows_c[0] || ms < best_p[ip]) {
           best_p[ip] = ms;
@@ -233,16 +233,16 @@ template <typename T> int time_pass_t(fgcg_ctx* c, int kind, int reps, double* u
   const long long ss = spec_ss(c);
   CT<T>* spec = (CT<T>*)c->spec;
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
-  const MechUPro1<T> pro{{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt}};
-  const MechUEpi1<T> epi{{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, 0.0, 1 << 30}};
+  const MechUProC<T, 2> pro{{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt}};
+  const MechUEpiC<T, 2> epi{{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, 0.0, 1 << 30}};
   // (only one kind is launched: the Green pass's partial sums may overwrite
   // the unit sums the direction update would read)
   const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
   auto one = [&]() -> int {
     if (kind == FGCG_K_MECH_ROW_FWD)
-      return launch_row_fwd<T, 1, MechUPro1<T>, true>(c, -1, pro, spec, 2 * ns, ss / 2);
+      return launch_row_fwd<T, 1, MechUProC<T, 2>, true>(c, -1, pro, spec, 2 * ns, ss / 2);
     if (kind == FGCG_K_MECH_ROW_INV)
-      return launch_row_inv<T, 1, MechUEpi1<T>, true>(c, -1, epi, spec, 2 * ns, ss / 2);
+      return launch_row_inv<T, 1, MechUEpiC<T, 2>, true>(c, -1, epi, spec, 2 * ns, ss / 2);
     return launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, green, spec, spec, 2 * ns, ss / 2);
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -93,9 +93,16 @@ int launch_reduce(fgcg_ctx* c, const double* part, int np, double* out) {
 template <typename T> Field<T> fld3(void* p, const fgcg_ctx* c) { return Field<T>{(T*)p, c->n, 3 * c->n}; }
 
 // z = M r (the Green operator by x, y, z transforms), r.z reduced into red[1].
-template <typename T, class Pro> int green3(fgcg_ctx* c, const Pro& pro, const CgState* st, bool timed) {
+// spectrum stride of one displacement component
+inline long long comp_stride3(const fgcg_ctx* c) { return (long long)c->nxh * c->rows; }
+
+// NOUT = 3: pro covers the three components in one block; NOUT = 1: pro is
+// a one-component functor, launched over the three components.
+template <typename T, int NOUT, class Pro>
+int green3(fgcg_ctx* c, const Pro& pro, const CgState* st, bool timed) {
   CT<T>* spec = (CT<T>*)c->spec;
-  int r = launch_row_fwd<T, 3>(c, timed ? FGCG_K_MECH_ROW_FWD : -1, pro, spec);
+  int r = NOUT == 3 ? launch_row_fwd<T, NOUT>(c, timed ? FGCG_K_MECH_ROW_FWD : -1, pro, spec)
+                    : launch_row_fwd<T, NOUT>(c, timed ? FGCG_K_MECH_ROW_FWD : -1, pro, spec, 3, comp_stride3(c));
   r |= launch_ypass<T, 3>(c, timed ? FGCG_K_MECH_Y_FWD : -1, false, st, spec);
   const Green3<T> g{c->Dx, c->Dy, c->Dz, 1.0 / (double)c->n, c->nx, st, c->part_z};
   r |= launch_zpass<T, true, true>(c, timed ? FGCG_K_MECH_COL : -1, g, spec, 3);
@@ -106,14 +113,20 @@ template <typename T, class Pro> int green3(fgcg_ctx* c, const Pro& pro, const C
 
 template <typename T> int mech3_init(fgcg_ctx* c, double tol, int maxit) {
   const CopyProN<T, 3> cp{fld3<T>(c->r, c), c->nx};
-  int r = green3<T>(c, cp, nullptr, false);
+  int r = green3<T, 3>(c, cp, nullptr, false);
   const MechUEpi<T, 3> e0{fld3<T>(c->p, c), c->nx, c->st, c->red + 1, 1, 1, tol, maxit};
   r |= launch_row_inv<T, 3>(c, -1, e0, (const CT<T>*)c->spec);
   HIPCHK(hipGetLastError());
   return r;
 }
 
+// Row passes with one displacement component per block (launched over the
+// three components) or all three in one block, per precision as measured at
+// 256^3: FP64 inverse pass 277 -> 253 us split, forward pass 556 -> 611 us
+// split (kept whole); FP32 forward pass 304 -> 284 us split, inverse pass
+// 129 -> 133 us split (kept whole).
 template <typename T> int mech3_iter(fgcg_ctx* c, const MechMat& m, double tol, int maxit, bool reliable) {
+  constexpr bool SPLIT_FWD = sizeof(T) == 4, SPLIT_INV = sizeof(T) == 8;
   const Field<T> X = fld3<T>(c->x, c), R = fld3<T>(c->r, c), P = fld3<T>(c->p, c), Q = fld3<T>(c->tmp, c);
   const Grid3 g = grid3(c);
   const int nb = nslab(c);
@@ -123,18 +136,28 @@ template <typename T> int mech3_iter(fgcg_ctx* c, const MechMat& m, double tol, 
                  (const double*)nullptr, g, (T)(1.0 / c->h), c->st, c->part_a);
   r |= launch_reduce(c, c->part_a, nkp, c->red);
   if (!reliable) {
-    const MechUPro<T, 3> pro{X, R, P, Q, c->nx, c->st, c->red, 1};
-    r |= green3<T>(c, pro, c->st, true);
+    if constexpr (SPLIT_FWD) {
+      const MechUProC<T, 3> pro{{X, R, P, Q, c->nx, c->st, c->red, 1}};
+      r |= green3<T, 1>(c, pro, c->st, true);
+    } else {
+      const MechUPro<T, 3> pro{X, R, P, Q, c->nx, c->st, c->red, 1};
+      r |= green3<T, 3>(c, pro, c->st, true);
+    }
   } else {
     r |= launch(c, -1, (const void*)&k_mech_fold<T>, dim3(c->npost), X.p, c->xh, (const T*)P.p, 3 * c->n, c->st,
                 (const double*)c->red, 1);
     r |= launch(c, -1, (const void*)&k_mech3_kpx<T, double, true>, dim3(nkp), m, (const double*)c->xh, R.p,
                 (const double*)c->fh, g, 1.0 / c->h, c->st, (double*)nullptr);
     const CopyProN<T, 3> cp{R, c->nx};
-    r |= green3<T>(c, cp, c->st, false);
+    r |= green3<T, 3>(c, cp, c->st, false);
   }
-  const MechUEpi<T, 3> epi{P, c->nx, c->st, c->red + 1, 1, 0, tol, maxit};
-  r |= launch_row_inv<T, 3>(c, FGCG_K_MECH_ROW_INV, epi, (const CT<T>*)c->spec);
+  if constexpr (SPLIT_INV) {
+    const MechUEpiC<T, 3> epi{{P, c->nx, c->st, c->red + 1, 1, 0, tol, maxit}};
+    r |= launch_row_inv<T, 1>(c, FGCG_K_MECH_ROW_INV, epi, (const CT<T>*)c->spec, 3, comp_stride3(c));
+  } else {
+    const MechUEpi<T, 3> epi{P, c->nx, c->st, c->red + 1, 1, 0, tol, maxit};
+    r |= launch_row_inv<T, 3>(c, FGCG_K_MECH_ROW_INV, epi, (const CT<T>*)c->spec);
+  }
   return r;
 }
 

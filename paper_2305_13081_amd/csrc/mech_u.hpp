@@ -453,21 +453,21 @@ template <typename T, int NC = 2> struct MechUEpi {
   __device__ void partial(int, double) const {}
 };
 
-// One displacement component per block (2D row passes): the pass runs over
-// (sample, component) pairs s2 = 2 s + c with the spectrum stride of one
-// component, as the column pass does.  Twice the blocks of the two-component
-// passes, each with half the registers for its values; the CG scalars and
-// the stop test are those of sample s (both component blocks compute and
-// store the same values).
-template <typename T> struct MechUPro1 {
-  MechUPro<T, 2> m;
-  static constexpr bool EARLY = true;
-  __device__ bool begin(int s2, double* red, double& sc) const { return m.begin(s2 >> 1, red, sc); }
+// One displacement component per block (row passes): the pass runs over
+// (sample, component) pairs s2 = NC s + c with the spectrum stride of one
+// component, as the column pass does.  NC times the blocks of the
+// all-component passes, each with 1/NC of the registers for its values; the CG
+// scalars and the stop test are those of sample s (every component block
+// computes and stores the same values).  EARLY as for MechUPro.
+template <typename T, int NC = 2> struct MechUProC {
+  MechUPro<T, NC> m;
+  static constexpr bool EARLY = MechUPro<T, NC>::EARLY;
+  __device__ bool begin(int s2, double* red, double& sc) const { return m.begin(s2 / NC, red, sc); }
   struct Ld {
     T x, r, p, q;
   };
   __device__ void load(int s2, int y, int xx, Ld& l) const {
-    const int s = s2 >> 1, c = s2 & 1;
+    const int s = s2 / NC, c = s2 - s * NC;
     const long long i = (long long)y * m.nx + xx;
     l.x = m.x.at(s, c, i);
     l.r = m.r.at(s, c, i);
@@ -475,7 +475,7 @@ template <typename T> struct MechUPro1 {
     l.q = m.q.at(s, c, i);
   }
   __device__ void apply(int s2, int y, int xx, const Ld& l, T* out, double&, double sc) const {
-    const int s = s2 >> 1, c = s2 & 1;
+    const int s = s2 / NC, c = s2 - s * NC;
     const long long i = (long long)y * m.nx + xx;
     const T a = (T)sc;
     m.x.at(s, c, i) = l.x + a * l.p;
@@ -486,18 +486,18 @@ template <typename T> struct MechUPro1 {
   __device__ void partial(int, double) const {}
 };
 
-template <typename T> struct MechUEpi1 {
-  MechUEpi<T, 2> m;
+template <typename T, int NC = 2> struct MechUEpiC {
+  MechUEpi<T, NC> m;
   static constexpr int NPRE = 1;
-  static constexpr bool EARLY = true;
-  __device__ bool begin(int s2, double* red, double& sc) const { return m.begin(s2 >> 1, red, sc); }
+  static constexpr bool EARLY = MechUEpi<T, NC>::EARLY;
+  __device__ bool begin(int s2, double* red, double& sc) const { return m.begin(s2 / NC, red, sc); }
   __device__ void prefetch(int s2, int y, int xx, T* pre) const {
     const long long i = (long long)y * m.nx + xx;
-    pre[0] = m.init ? (T)0 : m.p.at(s2 >> 1, s2 & 1, i);
+    pre[0] = m.init ? (T)0 : m.p.at(s2 / NC, s2 % NC, i);
   }
   __device__ void point(int s2, int y, int xx, const T* z, double&, double sc, const T* pre) const {
     const long long i = (long long)y * m.nx + xx;
-    m.p.at(s2 >> 1, s2 & 1, i) = m.init ? z[0] : z[0] + (T)sc * pre[0];
+    m.p.at(s2 / NC, s2 % NC, i) = m.init ? z[0] : z[0] + (T)sc * pre[0];
   }
   __device__ void partial(int, double) const {}
 };
