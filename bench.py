@@ -79,8 +79,8 @@ KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "
 # kernel sources they were taken with: the key is the SHA-256 of csrc/.
 MEASURED_TRAFFIC = {
     # source hash -> {kernel kind: bytes per launch} (profiles/mech_passes_1024_fp64_hbm_traffic.md)
-    "8dfbaccf9db233943c8cf74b3f7e214e1ada9a6bba83fd4c7be1c0f59a991447": {
-        "mech_row_fwd": 115235121, "mech_row_inv": 49361720, "mech_kp": 42323367, "mech_col": 33232307},
+    "05c016cce21187dae3ba8fa26d2f73a75833016eaf331c4274beb4dc32ccb7fe": {
+        "mech_row_fwd": 115192764, "mech_row_inv": 49815796, "mech_kp": 42373390, "mech_col": 33232260},
 }
 
 
