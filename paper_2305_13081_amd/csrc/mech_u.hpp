@@ -103,10 +103,15 @@ __global__ void __launch_bounds__(NT) k_mech_kp(MechMat m, const T* __restrict__
   double acc = 0.0;
   for (int t = t0; t < t1; ++t) {
     const int x0 = (t % ntx) * KP_TX, y0 = (t / ntx) * KP_TY;
-    for (int hp = threadIdx.x; hp < HP; hp += NT) {
+    // a fixed trip count, unrolled: the loads of all of a thread's halo
+    // points are issued together instead of one round trip per point
+#pragma unroll
+    for (int k = 0; k < (HP + NT - 1) / NT; ++k) {
+      const int hp = threadIdx.x + k * NT;
       const int hy = hp / HX, hx = hp - hy * HX;
       int x = x0 - 1 + hx, y = y0 - 1 + hy;
-      if (x >= nx || y >= ny) continue;  // past the edge of a partial tile: never read
+      // past the halo, or past the edge of a partial tile (never read)
+      if (hp >= HP || x >= nx || y >= ny) continue;
       if (x < 0) x += nx;
       if (y < 0) y += ny;
       T sv[3], e[3];
