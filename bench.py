@@ -79,8 +79,8 @@ KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "
 # kernel sources they were taken with: the key is the SHA-256 of csrc/.
 MEASURED_TRAFFIC = {
     # source hash -> {kernel kind: bytes per launch} (profiles/mech_passes_1024_fp64_hbm_traffic.md)
-    "05c016cce21187dae3ba8fa26d2f73a75833016eaf331c4274beb4dc32ccb7fe": {
-        "mech_row_fwd": 115192764, "mech_row_inv": 49815796, "mech_kp": 42373390, "mech_col": 33232260},
+    "1c54d4fa5ad3041f01b2379e6d065f521e85b0946e9d586295e9ff9496239a2b": {
+        "mech_row_fwd": 115356139, "mech_row_inv": 49808986, "mech_kp": 42417152, "mech_col": 33174008},
 }
 
 
