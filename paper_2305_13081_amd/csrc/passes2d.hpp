@@ -49,10 +49,19 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
-// Deterministic block sum of an array of partial sums.
+// Deterministic block sum of an array of partial sums.  A thread's loads
+// are issued four at a time and added in index order (the result of adding
+// them one at a time, without a memory round trip per element).
 __device__ __forceinline__ double block_sum_array(const double* a, int n, double* red) {
   double t = 0.0;
-  for (int i = threadIdx.x; i < n; i += NT) t += a[i];
+  for (int i = threadIdx.x; i < n; i += 4 * NT) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = i + k * NT < n ? a[i + k * NT] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i + k * NT < n) t += v[k];
+  }
   return block_sum(t, red);
 }
 
