@@ -50,16 +50,17 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // Deterministic block sum of an array of partial sums.  A thread's loads
-// are issued four at a time and added in index order (the result of adding
+// are issued B at a time and added in index order (the result of adding
 // them one at a time, without a memory round trip per element).
+template <int B = 4>
 __device__ __forceinline__ double block_sum_array(const double* a, int n, double* red) {
   double t = 0.0;
-  for (int i = threadIdx.x; i < n; i += 4 * NT) {
-    double v[4];
+  for (int i = threadIdx.x; i < n; i += B * NT) {
+    double v[B];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = i + k * NT < n ? a[i + k * NT] : 0.0;
+    for (int k = 0; k < B; ++k) v[k] = i + k * NT < n ? a[i + k * NT] : 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < B; ++k)
       if (i + k * NT < n) t += v[k];
   }
   return block_sum(t, red);

@@ -29,7 +29,7 @@ template <typename T> constexpr int ztile_for(int nz) {
 // Deterministic single-block sum of np partial sums into out[0].
 __global__ void __launch_bounds__(NT) k_reduce(const double* __restrict__ part, int np, double* out) {
   __shared__ double red[NT / 64];
-  const double t = block_sum_array(part, np, red);
+  const double t = block_sum_array<16>(part, np, red);  // up to 4096 partials: one round of loads
   if (threadIdx.x == 0) out[0] = t;
 }
 
