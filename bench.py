@@ -79,8 +79,8 @@ KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "
 # kernel sources they were taken with: the key is the SHA-256 of csrc/.
 MEASURED_TRAFFIC = {
     # source hash -> {kernel kind: bytes per launch} (profiles/mech_passes_1024_fp64_hbm_traffic.md)
-    "1c54d4fa5ad3041f01b2379e6d065f521e85b0946e9d586295e9ff9496239a2b": {
-        "mech_row_fwd": 115356139, "mech_row_inv": 49808986, "mech_kp": 42417152, "mech_col": 33174008},
+    "718400c84a41b3129dae0a280e03360fd4b17ef36411877abe57b5d2520ca718": {
+        "mech_row_fwd": 115269641, "mech_row_inv": 49748414, "mech_kp": 42389698, "mech_col": 33157016},
 }
 
 
