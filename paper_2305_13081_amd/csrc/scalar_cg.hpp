@@ -59,15 +59,24 @@ __device__ __forceinline__ Nbr nbrs(int row, int x, int nx, int ny, int nz) {
 // Stencil operators.  apply_vals takes the value at the voxel and at its
 // neighbours vn = {x-1, x+1, y-1, y+1, z-1, z+1} (the z entries only on 3D
 // grids); apply gathers them from a functor v(j, x) (value at linear index j,
-// x coordinate x).
+// x coordinate x).  coef(b) loads the voxel's coefficients and apply_coef
+// applies the operator with them (apply_vals is the two in a row), so the
+// stencil pass can issue the coefficient loads early.
 struct PfStencil {
   const double* H;
   double a;     // Gc / (2 l0)
   double cih2;  // (Gc l0 / 2) / h^2
-  __device__ __forceinline__ double apply_vals(const Nbr& b, double v0, const double* vn) const {
+  struct Coef {
+    double h;
+  };
+  __device__ __forceinline__ Coef coef(const Nbr& b) const { return Coef{H[b.i]}; }
+  __device__ __forceinline__ double apply_coef(const Coef& c, const Nbr& b, double v0, const double* vn) const {
     double lap = (b.three ? 6.0 : 4.0) * v0 - vn[0] - vn[1] - vn[2] - vn[3];
     if (b.three) lap = lap - vn[4] - vn[5];
-    return (a + H[b.i]) * v0 + cih2 * lap;
+    return (a + c.h) * v0 + cih2 * lap;
+  }
+  __device__ __forceinline__ double apply_vals(const Nbr& b, double v0, const double* vn) const {
+    return apply_coef(coef(b), b, v0, vn);
   }
   template <typename V>
   __device__ __forceinline__ double apply(double v0, const V& v, const Nbr& b) const {
@@ -86,12 +95,26 @@ struct DiffStencil {
     pick(co.dk, phase[j], d, kr);
     return d;
   }
-  __device__ __forceinline__ double apply_vals(const Nbr& b, double v0, const double* vn) const {
-    double d0, kr;
-    pick(co.dk, phase[b.i], d0, kr);
-    double flux = D(b.ixm) * (v0 - vn[0]) - d0 * (vn[1] - v0) + D(b.iym) * (v0 - vn[2]) - d0 * (vn[3] - v0);
-    if (b.three) flux = flux + D(b.izm) * (v0 - vn[4]) - d0 * (vn[5] - v0);
+  struct Coef {
+    uint8_t p0, pxm, pym, pzm;  // phases of the voxel and of its -x, -y, -z neighbours
+  };
+  __device__ __forceinline__ Coef coef(const Nbr& b) const {
+    return Coef{phase[b.i], phase[b.ixm], phase[b.iym], b.three ? phase[b.izm] : (uint8_t)0};
+  }
+  __device__ __forceinline__ double apply_coef(const Coef& c, const Nbr& b, double v0, const double* vn) const {
+    double d0, kr, dxm, dym, dzm, t;
+    pick(co.dk, c.p0, d0, kr);
+    pick(co.dk, c.pxm, dxm, t);
+    pick(co.dk, c.pym, dym, t);
+    double flux = dxm * (v0 - vn[0]) - d0 * (vn[1] - v0) + dym * (v0 - vn[2]) - d0 * (vn[3] - v0);
+    if (b.three) {
+      pick(co.dk, c.pzm, dzm, t);
+      flux = flux + dzm * (v0 - vn[4]) - d0 * (vn[5] - v0);
+    }
     return (co.inv_dt + kr) * v0 + ih2 * flux;
+  }
+  __device__ __forceinline__ double apply_vals(const Nbr& b, double v0, const double* vn) const {
+    return apply_coef(coef(b), b, v0, vn);
   }
   template <typename V>
   __device__ __forceinline__ double apply(double v0, const V& v, const Nbr& b) const {
@@ -171,6 +194,20 @@ __global__ void __launch_bounds__(NT) k_scg_dir(Op op, const T* __restrict__ r, 
     fill(pl[0], x0, y0, z0);
     for (int z = z0; z < z1; ++z) {
       if (three) fill(pl[cur ^ 1], x0, y0, z + 1 == nz ? 0 : z + 1);
+      // the voxels' coefficients (phases, history) are loaded before the
+      // barrier, so their latency overlaps the halo fill's
+      Nbr nbr[RPT];
+      typename Op::Coef cf[RPT];
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int yo = y0 + ty + k * (NT / SC_TX);
+        nbr[k].i = ((long long)z * ny + yo) * nx + xo;
+        nbr[k].ixm = nbr[k].i + (xo == 0 ? nx - 1 : -1);
+        nbr[k].iym = nbr[k].i + (yo == 0 ? (long long)(ny - 1) * nx : -(long long)nx);
+        nbr[k].izm = nbr[k].i + (z == 0 ? (long long)(nz - 1) * plane : -plane);
+        nbr[k].three = three;
+        if (xo < nx && yo < ny) cf[k] = op.coef(nbr[k]);
+      }
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
@@ -182,15 +219,10 @@ __global__ void __launch_bounds__(NT) k_scg_dir(Op op, const T* __restrict__ r, 
           const double v0 = P[hp];
           const double vn[6] = {P[hp - 1], P[hp + 1], P[hp - HX], P[hp + HX], three ? pm[k] : 0.0,
                                 three ? pl[cur ^ 1][hp] : 0.0};
-          Nbr nbr;
-          nbr.i = ((long long)z * ny + yo) * nx + xo;
-          nbr.ixm = nbr.i + (xo == 0 ? nx - 1 : -1);
-          nbr.iym = nbr.i + (yo == 0 ? (long long)(ny - 1) * nx : -(long long)nx);
-          nbr.izm = nbr.i + (z == 0 ? (long long)(nz - 1) * plane : -plane);
-          nbr.three = three;
-          const double qv = xo < band ? 0.0 : op.apply_vals(nbr, v0, vn);
-          pout[nbr.i] = (T)v0;
-          q[nbr.i] = (T)qv;
+          const Nbr& nb = nbr[k];
+          const double qv = xo < band ? 0.0 : op.apply_coef(cf[k], nb, v0, vn);
+          pout[nb.i] = (T)v0;
+          q[nb.i] = (T)qv;
           acc += v0 * qv;
           pm[k] = v0;
         }
