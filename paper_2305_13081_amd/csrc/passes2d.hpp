@@ -212,6 +212,17 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type*
 }
 
 // ------------------------------------------------------------------ column
+// Sym::Pre: per-mode data the symbol can take from registers (sym.pre(kx, ky)
+// loaded before the forward transform, used by sym.mode_pre).
+template <class S, class = void> struct SymPre {
+  static constexpr bool value = false;
+  struct type {};
+};
+template <class S> struct SymPre<S, decltype((void)sizeof(typename S::Pre))> {
+  static constexpr bool value = true;
+  using type = typename S::Pre;
+};
+
 template <typename T, int NY, int NIN, int NOUT, class Sym, int PL = 0>
 __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::type* spec_in,
                                             typename cvec<T>::type* spec_out, int nxh,
@@ -255,16 +266,34 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
       buf[lds(c * NY + y)] = in[((long long)c * nxh + kx) * NY + y];
     }
   }
+  // per-mode symbol data loaded before the transform (Sym::Pre), so the
+  // loads are not on the path between the two transforms
+  constexpr int KPT = (NY + NT - 1) / NT;
+  typename SymPre<Sym>::type spre[KPT];
+  if constexpr (SymPre<Sym>::value) {
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+      const int ky = tid + k * NT;
+      if (NY % NT == 0 || ky < NY) spre[k] = sym.pre(kx, ky);
+    }
+  }
   __syncthreads();
   fft_lds<T, NY, NIN, NT, false, FlatIdx<NY>, PL>(buf, tw);
   double acc = 0.0;
-  for (int ky = tid; ky < NY; ky += NT) {
-    C a[NIN], b[NOUT];
 #pragma unroll
-    for (int c = 0; c < NIN; ++c) a[c] = buf[lds(c * NY + ky)];
-    sym.mode(s, kx, ky, a, b, acc, sc);
+  for (int k = 0; k < KPT; ++k) {
+    const int ky = tid + k * NT;
+    if (NY % NT == 0 || ky < NY) {
+      C a[NIN], b[NOUT];
 #pragma unroll
-    for (int c = 0; c < NOUT; ++c) buf[lds(c * NY + ky)] = b[c];
+      for (int c = 0; c < NIN; ++c) a[c] = buf[lds(c * NY + ky)];
+      if constexpr (SymPre<Sym>::value)
+        sym.mode_pre(s, kx, ky, spre[k], a, b, acc, sc);
+      else
+        sym.mode(s, kx, ky, a, b, acc, sc);
+#pragma unroll
+      for (int c = 0; c < NOUT; ++c) buf[lds(c * NY + ky)] = b[c];
+    }
   }
   __syncthreads();
   sym.partial(s, block_sum(acc, red));
