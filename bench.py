@@ -79,8 +79,8 @@ KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "
 # kernel sources they were taken with: the key is the SHA-256 of csrc/.
 MEASURED_TRAFFIC = {
     # source hash -> {kernel kind: bytes per launch} (profiles/mech_passes_1024_fp64_hbm_traffic.md)
-    "718400c84a41b3129dae0a280e03360fd4b17ef36411877abe57b5d2520ca718": {
-        "mech_row_fwd": 115269641, "mech_row_inv": 49748414, "mech_kp": 42389698, "mech_col": 33157016},
+    "4b0b1f164472678f61258d25c3106646e60488b5518fb15ef1c50643bf5f783c": {
+        "mech_row_fwd": 115316817, "mech_row_inv": 49702399, "mech_kp": 43071857, "mech_col": 33154005},
 }
 
 

@@ -93,19 +93,14 @@ __global__ void __launch_bounds__(NT) k_mech_kp(MechMat m, const T* __restrict__
   st += s;
   p += 2 * n * s;
   q += 2 * n * s;
+  // (the state check stays first: blocks of samples whose solve has ended,
+  // in a batch, exit before loading anything)
+  if (!cg_running(st, 0)) return;
+  if (lead()) st->k = st->k_next;
   const int ntx = (nx + KP_TX - 1) / KP_TX;
   const int ntiles = ntx * ((ny + KP_TY - 1) / KP_TY);
   const int lb = xcd_block(), nb = gridDim.x;
   const int t0 = (int)((long long)ntiles * lb / nb), t1 = (int)((long long)ntiles * (lb + 1) / nb);
-  // The state check comes after the first tile's halo stresses (read-only
-  // work), so its latency overlaps their loads; a block without tiles checks
-  // at once.
-  auto start = [&]() -> bool {
-    if (!cg_running(st, 0)) return false;
-    if (lead()) st->k = st->k_next;
-    return true;
-  };
-  if (t0 >= t1 && !start()) return;
   const int tx = threadIdx.x & (KP_TX - 1), ty = threadIdx.x / KP_TX;
   double acc = 0.0;
   for (int t = t0; t < t1; ++t) {
@@ -129,7 +124,6 @@ __global__ void __launch_bounds__(NT) k_mech_kp(MechMat m, const T* __restrict__
       if (hx >= 1 && hy >= 1) acc += (double)e[0] * sv[0] + (double)e[1] * sv[1] + 2.0 * (double)e[2] * sv[2];
     }
     __syncthreads();
-    if (t == t0 && !start()) return;
 #pragma unroll
     for (int k = 0; k < KP_TY / (NT / KP_TX); ++k) {
       const int yy = ty + k * (NT / KP_TX);

@@ -235,36 +235,14 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
   const int s = blockIdx.y;
   const int kx = blockIdx.x;
   const int tid = threadIdx.x;
+  // The state check comes first: blocks of samples whose solve has ended (in
+  // a batch) exit before loading anything.
   const C* in = spec_in + s * ss_in;
   double sc = 0.0;
-  if constexpr (sizeof(T) == 4) {
-    // FP32: the column is loaded into registers before begin() (state check,
-    // CG scalars), so the two latencies overlap, then written to LDS (measured
-    // faster at 1024^2; slower in FP64, which loads straight into LDS after
-    // begin())
-    constexpr int PT = (NIN * NY + NT - 1) / NT;
-    C pre[PT];
-#pragma unroll
-    for (int u = 0; u < PT; ++u) {
-      const int idx = tid + u * NT;
-      if ((NIN * NY) % NT == 0 || idx < NIN * NY) {
-        const int c = idx / NY, y = idx - (idx / NY) * NY;
-        pre[u] = in[((long long)c * nxh + kx) * NY + y];
-      }
-    }
-    asm volatile("" ::: "memory");
-    if (!sym.begin(s, red, sc)) return;
-#pragma unroll
-    for (int u = 0; u < PT; ++u) {
-      const int idx = tid + u * NT;
-      if ((NIN * NY) % NT == 0 || idx < NIN * NY) buf[lds(idx)] = pre[u];
-    }
-  } else {
-    if (!sym.begin(s, red, sc)) return;
-    for (int idx = tid; idx < NIN * NY; idx += NT) {
-      const int c = idx / NY, y = idx - (idx / NY) * NY;
-      buf[lds(c * NY + y)] = in[((long long)c * nxh + kx) * NY + y];
-    }
+  if (!sym.begin(s, red, sc)) return;
+  for (int idx = tid; idx < NIN * NY; idx += NT) {
+    const int c = idx / NY, y = idx - (idx / NY) * NY;
+    buf[lds(c * NY + y)] = in[((long long)c * nxh + kx) * NY + y];
   }
   // per-mode symbol data loaded before the transform (Sym::Pre), so the
   // loads are not on the path between the two transforms
