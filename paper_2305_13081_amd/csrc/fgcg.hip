@@ -19,6 +19,19 @@ constexpr int RELIABLE_EVERY = 10;  // FP32-mixed: true residual every tenth ite
 template <typename T> Field<T> fld(void* p, const fgcg_ctx* c) { return Field<T>{(T*)p, c->n, 2 * c->n}; }
 inline long long spec_ss(const fgcg_ctx* c) { return 2LL * c->nxh * c->ny; }
 
+// The 2D inverse row pass of the mechanics (one component per block): the
+// p prefetch goes before the CG-state check for a single sample, after it in
+// batches (blocks of converged samples then read nothing).
+template <typename T>
+int launch_mech_row_inv(fgcg_ctx* c, int kind, const MechUEpi<T, 2>& e, CT<T>* spec, int ns, long long ss) {
+  if (ns == 1) {
+    const MechUEpiC<T, 2, true> ec{e};
+    return launch_row_inv<T, 1, MechUEpiC<T, 2, true>, true>(c, kind, ec, spec, 2 * ns, ss / 2);
+  }
+  const MechUEpiC<T, 2, false> ec{e};
+  return launch_row_inv<T, 1, MechUEpiC<T, 2, false>, true>(c, kind, ec, spec, 2 * ns, ss / 2);
+}
+
 // z = M r, p = z, r.z and the CG state of every sample (R holds f, X holds 0).
 template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
   CT<T>* spec = (CT<T>*)c->spec;
@@ -29,8 +42,8 @@ template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, i
   if ((rc = launch_row_fwd<T, 2, CopyProN<T, 2>, true>(c, -1, cp, spec, ns, ss))) return rc;
   const MechGreen<T> g0{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
   if ((rc = launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, g0, spec, spec, 2 * ns, ss / 2))) return rc;
-  const MechUEpiC<T, 2> e0{{fld<T>(c->p, c), c->nx, c->st, c->part_rr, 2 * c->ncol, 1, tol, maxit}};
-  if ((rc = launch_row_inv<T, 1, MechUEpiC<T, 2>, true>(c, -1, e0, spec, 2 * ns, ss / 2))) return rc;
+  const MechUEpi<T, 2> e0{fld<T>(c->p, c), c->nx, c->st, c->part_rr, 2 * c->ncol, 1, tol, maxit};
+  if ((rc = launch_mech_row_inv<T>(c, -1, e0, spec, ns, ss))) return rc;
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -58,8 +71,8 @@ template <typename T> int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, i
   }
   const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, c->st, c->part_rr};
   r |= launch_col<T, 1, 1, MechGreen<T>, true>(c, FGCG_K_MECH_COL, green, spec, spec, 2 * ns, ss / 2);
-  const MechUEpiC<T, 2> epi{{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, tol, maxit}};
-  r |= launch_row_inv<T, 1, MechUEpiC<T, 2>, true>(c, FGCG_K_MECH_ROW_INV, epi, spec, 2 * ns, ss / 2);
+  const MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, tol, maxit};
+  r |= launch_mech_row_inv<T>(c, FGCG_K_MECH_ROW_INV, epi, spec, ns, ss);
   return r;
 }
 
@@ -149,7 +162,7 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   CT<T>* spec = (CT<T>*)c->spec;
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
   const MechUProC<T, 2> pro{{X, R, P, Q, c->nx, c->st, c->part_a, npa}};
-  const MechUEpiC<T, 2> epi{{P, c->nx, c->st, c->part_rr, nprz, 0, 0.0, 1 << 30}};
+  const MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, nprz, 0, 0.0, 1 << 30};
   // the Green pass without a CG state (timed after the row passes, whose
   // direction update reads part_rr; 2 nxh partial sums per sample)
   const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
@@ -183,7 +196,7 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
         c->plan_row = prow_c[ip];
         const float ms = time_it([&] {
           return launch_row_fwd<T, 1, MechUProC<T, 2>, true>(c, -1, pro, spec, 2 * ns, ss / 2) |
-                 launch_row_inv<T, 1, MechUEpiC<T, 2>, true>(c, -1, epi, spec, 2 * ns, ss / 2);
+                 launch_mech_row_inv<T>(c, -1, epi, spec, ns, ss);
         });
         if (R_ == rows_c[0] || ms < best_p[ip]) {
           best_p[ip] = ms;
@@ -234,7 +247,7 @@ template <typename T> int time_pass_t(fgcg_ctx* c, int kind, int reps, double* u
   CT<T>* spec = (CT<T>*)c->spec;
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
   const MechUProC<T, 2> pro{{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt}};
-  const MechUEpiC<T, 2> epi{{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, 0.0, 1 << 30}};
+  const MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, 0.0, 1 << 30};
   // (only one kind is launched: the Green pass's partial sums may overwrite
   // the unit sums the direction update would read)
   const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
@@ -242,7 +255,7 @@ template <typename T> int time_pass_t(fgcg_ctx* c, int kind, int reps, double* u
     if (kind == FGCG_K_MECH_ROW_FWD)
       return launch_row_fwd<T, 1, MechUProC<T, 2>, true>(c, -1, pro, spec, 2 * ns, ss / 2);
     if (kind == FGCG_K_MECH_ROW_INV)
-      return launch_row_inv<T, 1, MechUEpiC<T, 2>, true>(c, -1, epi, spec, 2 * ns, ss / 2);
+      return launch_mech_row_inv<T>(c, -1, epi, spec, ns, ss);
     return launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, green, spec, spec, 2 * ns, ss / 2);
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;

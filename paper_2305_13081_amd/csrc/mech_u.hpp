@@ -500,10 +500,13 @@ template <typename T, int NC = 2> struct MechUProC {
   __device__ void partial(int, double) const {}
 };
 
-template <typename T, int NC = 2> struct MechUEpiC {
+// E: prefetch before begin() (as MechUEpi::EARLY); batches of several
+// samples take E = false, so that the blocks of samples whose solve has ended
+// exit before reading p.
+template <typename T, int NC = 2, bool E = MechUEpi<T, NC>::EARLY> struct MechUEpiC {
   MechUEpi<T, NC> m;
   static constexpr int NPRE = 1;
-  static constexpr bool EARLY = MechUEpi<T, NC>::EARLY;
+  static constexpr bool EARLY = E;
   __device__ bool begin(int s2, double* red, double& sc) const { return m.begin(s2 / NC, red, sc); }
   __device__ void prefetch(int s2, int y, int xx, T* pre) const {
     const long long i = (long long)y * m.nx + xx;
