@@ -79,8 +79,8 @@ KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "
 # kernel sources they were taken with: the key is the SHA-256 of csrc/.
 MEASURED_TRAFFIC = {
     # source hash -> {kernel kind: bytes per launch} (profiles/mech_passes_1024_fp64_hbm_traffic.md)
-    "4b0b1f164472678f61258d25c3106646e60488b5518fb15ef1c50643bf5f783c": {
-        "mech_row_fwd": 115316817, "mech_row_inv": 49702399, "mech_kp": 43071857, "mech_col": 33154005},
+    "3ac6052ea8d0ed0ffff01f2d7d9bf3ea8eb3878720ad78f0119ad21b64d8edde": {
+        "mech_row_fwd": 115311175, "mech_row_inv": 49700531, "mech_kp": 42397457, "mech_col": 33164122},
 }
 
 
