@@ -15,14 +15,17 @@
 //   k_mech_kp          q = K p as a real-space stencil (grad and grad^H are
 //                      the periodic forward/backward differences), partial
 //                      sums of p.Kp = sum_x sym(grad p) : g C : sym(grad p)
-//   row_fwd (MechUPro) alpha = r.z / p.Kp; x += alpha p; r -= alpha q; the
-//                      two components of r are transformed along x
+//   row_fwd (MechUProC) alpha = r.z / p.Kp; x += alpha p; r -= alpha q; r
+//                      transformed along x (one component per block)
 //   col (MechGreen)    z_hat = r_hat / |D|^2 / N, partial sums of r.z by
 //                      Parseval over the half spectrum (one component per
 //                      block)
-//   row_inv (MechUEpi) z back in real space; stop test on r.z; beta;
-//                      p = z + beta p
-// so q and z are never stored except q between the first two passes.
+//   row_inv (MechUEpiC) z back in real space; stop test on r.z; beta;
+//                      p = z + beta p (one component per block)
+// so q and z are never stored except q between the first two passes.  The
+// all-component functors MechUPro / MechUEpi serve the 3D passes where those
+// measured faster and the one-component wrappers MechUProC / MechUEpiC the
+// rest.
 #pragma once
 #include "ops2d.hpp"
 

@@ -23,7 +23,12 @@
 // Functors are immutable and expose begin(s, red, sc) (uniform: false = the
 // whole block exits; may set the block scalar sc, e.g. the CG beta or alpha),
 // point(..., acc, sc) and partial(s, value) (block-reduced FP64 sum, thread 0
-// stores).
+// stores).  Optional members: Ld / load / apply (row_fwd: loads issued a voxel
+// ahead), NPRE / prefetch (row_inv: inputs of the epilogue loaded before the
+// transforms), EARLY (those loads go before begin()), Pre / pre / mode_pre
+// (col: per-mode symbol data loaded before the forward transform).  The grid's
+// y index s names a sample, or a (sample, component) pair for one-component
+// functors.
 #pragma once
 #include "fft_lds.hpp"
 
