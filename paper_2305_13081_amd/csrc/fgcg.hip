@@ -9,11 +9,11 @@ using namespace fgcg;
 
 namespace {
 
-// ----------------------------------------------------------------- mech
 // ---------------------------------------------------------- mechanics
 // Every context holds nsamp samples of one grid size (1 outside a batch);
 // sample s of a 2-component field starts at s * 2n, of a spectrum at
-// s * 2 nxh ny, and kernels take the sample from blockIdx.y.
+// s * 2 nxh ny, and kernels take the sample, or for the one-component passes
+// the (sample, component) pair, from blockIdx.y.
 constexpr int RELIABLE_EVERY = 10;  // FP32-mixed: true residual every tenth iteration
 
 template <typename T> Field<T> fld(void* p, const fgcg_ctx* c) { return Field<T>{(T*)p, c->n, 2 * c->n}; }
