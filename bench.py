@@ -79,8 +79,8 @@ KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "
 # kernel sources they were taken with: the key is the SHA-256 of csrc/.
 MEASURED_TRAFFIC = {
     # source hash -> {kernel kind: bytes per launch} (profiles/mech_passes_1024_fp64_hbm_traffic.md)
-    "3ac6052ea8d0ed0ffff01f2d7d9bf3ea8eb3878720ad78f0119ad21b64d8edde": {
-        "mech_row_fwd": 115311175, "mech_row_inv": 49700531, "mech_kp": 42397457, "mech_col": 33164122},
+    "8d301cbbde4c3767e7a9541f1bed809ee4c7631450803f647895fd84a33924db": {
+        "mech_row_fwd": 115270323, "mech_row_inv": 49748638, "mech_kp": 42398901, "mech_col": 33165914},
 }
 
 
