@@ -292,7 +292,7 @@ def main():
                          "and writes MIB MiB each): the reference for scaling HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (this build has no "
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the library has no "
               f"multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 

@@ -52,7 +52,7 @@ typedef enum {
   FGCG_EBREAKDOWN = -3,   /* CG breakdown: p.Ap <= 0 or a non-finite scalar */
   FGCG_ENOMEM = -4,
   FGCG_EHIP = -5,         /* a HIP runtime call failed */
-  FGCG_EUNSUPPORTED = -6  /* valid request this build does not implement */
+  FGCG_EUNSUPPORTED = -6  /* valid request the library does not implement */
 } fgcg_status;
 
 typedef enum { FGCG_FP64 = 0, FGCG_FP32_MIXED = 1 } fgcg_precision;

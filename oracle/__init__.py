@@ -16,7 +16,7 @@ Two levels, following the paper (Pundir, Kammer, Angst, arXiv 2305.13081):
 * definition level (``direct``) -- the same discrete problems assembled as
   real-space stencils and solved by a sparse direct solver, with no FFT at all.
 
-Every module states the passage it follows.  Readings of passages that are
-ambiguous or garbled are listed in the design doc.  Functions without an
+Every module states the passage it follows, and the reading it takes where
+a passage is ambiguous or garbled.  Functions without an
 independent pin say "parity unpinned" in their docstring (none at present).
 """

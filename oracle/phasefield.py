@@ -6,7 +6,7 @@ Sec. 2.4, eq. crack and eq. crack-fft:
 
 with the Laplacian applied in Fourier space.  With the forward-difference
 gradient D of Sec. 2.6 the Laplacian symbol is taken as -D^H D = -|D|^2 (the
-reading that keeps the operator symmetric positive definite, see DESIGN.md),
+reading that keeps the operator symmetric positive definite),
 so the operator is
 
     A d = (Gc / (2 l0) + H) d + (Gc l0 / 2) F^-1[ |D|^2 F[d] ],
