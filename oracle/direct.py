@@ -123,3 +123,43 @@ def diffusion_direct(c_n, Dfield, react, dt, h, band=None, c_dir=1.0):
     c = cB.copy()
     c[free] = spla.spsolve(A[free][:, free].tocsc(), rhsF)
     return c.reshape(grid)
+
+
+def diffusion_static_direct(Dfield, grad_cmac, h):
+    """Static homogenisation (Sec. 2.1) at definition level: minimise
+    sum_x (grad c_mac + B phi) . D (grad c_mac + B phi) over periodic phi, i.e.
+    sum_a B_a^T D B_a phi = -sum_a B_a^T D grad_a c_mac, with phi pinned at voxel
+    0 and then shifted to mean zero.  Returns grad c = grad c_mac + B phi
+    (components first) and phi."""
+    Dfield = np.asarray(Dfield, dtype=np.float64)
+    grid = Dfield.shape
+    dim = Dfield.ndim
+    N = Dfield.size
+    B = [fwd_diff_matrix(grid, a, h) for a in range(dim)]
+    Dd = sps.diags(Dfield.ravel())
+    K = sps.csr_matrix((N, N))
+    f = np.zeros(N)
+    for a in range(dim):
+        K = K + B[a].T @ Dd @ B[a]
+        f = f - B[a].T @ (Dfield.ravel() * grad_cmac[a])
+    keep = np.ones(N, dtype=bool)
+    keep[0] = False
+    phi = np.zeros(N)
+    K = K.tocsr()
+    phi[keep] = spla.spsolve(K[keep][:, keep].tocsc(), f[keep])
+    phi -= phi.mean()
+    grad_c = np.array([grad_cmac[a] + (B[a] @ phi).reshape(grid) for a in range(dim)])
+    return dict(grad_c=grad_c, phi=phi.reshape(grid))
+
+
+def mech_stiffness_apply(phase, E_tab, nu_tab, u, h, d=None, kappa=0.0, E_field=None, nu=None):
+    """q = L^T C L u: the displacement-form stiffness grad^H g C : sym(grad u)
+    as the sparse stencil matrix (no FFT).  u and q are (dim, *grid)."""
+    phase = np.asarray(phase)
+    grid = phase.shape
+    dim = phase.ndim
+    lam, mu = _mech.voxel_lame(phase, E_tab, nu_tab, E_field, nu)
+    g = np.ones(grid) if d is None else _mat.degradation(np.asarray(d), kappa)
+    C = _stiffness_matrix(g * lam, g * mu)
+    L = _symgrad_matrix(grid, h)
+    return (L.T @ (C @ (L @ np.asarray(u, dtype=np.float64).reshape(-1)))).reshape((dim,) + grid)
