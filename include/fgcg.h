@@ -7,8 +7,10 @@
  *   mechanics   Sec. 2.3, eq. solid / eq. solid-final, projection of App. A:
  *               div( g(d) C(x) : (eps - e I) ) = 0, <eps> = eps_mac
  *   phase field Sec. 2.4, eq. crack / eq. crack-fft (AT2, history field H)
- *   diffusion   Sec. 2.1 (Fick's law, D mixed per phase), here one implicit
- *               time step with a first-order sink and a Dirichlet source band
+ *   diffusion   Sec. 2.1 (Fick's law, D defined voxel by voxel): the static
+ *               homogenisation in gradient-primary form with the
+ *               concentration reconstruction, and one implicit time step with
+ *               a first-order sink and Dirichlet voxels
  *   staggered   Alg. 1: diffusion -> precipitation/eigenstrain -> mechanics ->
  *               history -> phase field
  *
@@ -119,10 +121,27 @@ const char* fgcg_last_error(void);
  *       when more than 3 % faster, so near-ties give the same schedule in
  *       every context of a size).  The plan changes the rounding of the
  *       transforms only.  EUNSUPPORTED in 3D.
+ *   FGCG_OPT_PRECOND          preconditioner of the mechanics CG (Sec. 5 names
+ *       the property contrast as what limits the solver's efficiency).
+ *       0 (default): the Green operator (grad^H grad)^-1 of a unit medium,
+ *       i.e. the projected CG of eq. solid-final iterate by iterate; 1: the
+ *       Green operator K0^-1 of a homogeneous isotropic reference medium,
+ *       K0(k) = mu0 |D|^2 I + lam0 conj(D) D^T + mu0 D D^H, inverted mode by
+ *       mode (a 2 x 2 closed form in the 2D column pass with both displacement
+ *       components per block; a 3 x 3 Cholesky solve between the forward and
+ *       inverse z transforms in 3D).  Same discrete solution; the stop test
+ *       then measures r.K0^-1 r instead of the projected residual.  The
+ *       reference is fgcg_set_reference's, else the Lame ratio of the stiffest
+ *       phase (of nu_field with a per-voxel E field).  Changing it re-tunes
+ *       the 2D column plan.  EUNSUPPORTED for the groups of a batch.
  * Returns EINVAL for an unknown option or value. */
 enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2, FGCG_OPT_ROWS = 3,
-       FGCG_OPT_ROW_PLAN = 4, FGCG_OPT_COL_PLAN = 5 };
+       FGCG_OPT_ROW_PLAN = 4, FGCG_OPT_COL_PLAN = 5, FGCG_OPT_PRECOND = 6 };
 int fgcg_set_option(fgcg_ctx* ctx, int option, int value);
+/* Reference medium of FGCG_OPT_PRECOND = 1: Lame constants (only lam0 / mu0
+ * matters); (0, 0) restores the automatic choice.  EDOMAIN unless mu0 > 0 and
+ * lam0 + 2 mu0 / 3 > 0. */
+int fgcg_set_reference(fgcg_ctx* ctx, double lam0, double mu0);
 /* Current value of an option (FGCG_OPT_ROWS, _ROW_PLAN, _COL_PLAN: the tuned
  * or fixed choice, 0 before the first mechanics solve of an autotuned
  * context). */
@@ -163,7 +182,8 @@ int fgcg_mech_solve(fgcg_ctx* ctx, const fgcg_material* mat, const double* d, do
  *              FGCG_J_ENERGY: J = W (the energy of fgcg_mech_solve); lam = 0 by
  *              the envelope theorem, so no second solve is run;
  *              FGCG_J_C11: J = <sigma_11> / eps_mac[0] (eps_mac[0] != 0).
- *   grad_E     device [N] out.   J  host out or NULL.
+ *   grad_E     device [N] out, or NULL: only the forward solve and J (no
+ *              adjoint solve; info_adj zeroed).   J  host out or NULL.
  *   info_fwd / info_adj  the two solves (info_adj->iters = 0 for the energy).
  * Returns EUNSUPPORTED in FP32-mixed contexts and on 3D grids, EINVAL/EDOMAIN
  * as mech_solve. */
@@ -201,14 +221,71 @@ int fgcg_mech_solve_batched(fgcg_batch* batch, const uint8_t* const* phases, int
 int fgcg_phasefield_solve(fgcg_ctx* ctx, const double* H, double Gc, double l0, double* d,
                           double tol, int maxit, fgcg_info* info);
 
-/* One backward-Euler step of dc/dt = div(D(x) grad c) - k(x) c (Sec. 2.1
- * flux with per-phase D and sink k): [(1/dt + k) - div D grad] c = c^n/dt.
- * Voxels with x index < band_width hold c = c_dir (Dirichlet source band);
- * CG runs on the free voxels from c^n.  c: device [N], in c^n, out c^{n+1}.
- * D_tab, k_tab: host [nphase]. */
-int fgcg_diffusion_step(fgcg_ctx* ctx, const uint8_t* phase, int nphase, const double* D_tab,
-                        const double* k_tab, int band_width, double c_dir, double dt, double* c,
-                        double tol, int maxit, fgcg_info* info);
+/* One backward-Euler step of dc/dt = div(D(x) grad c) - k(x) c with the flux
+ * of Sec. 2.1 (j = -D grad c, D defined voxel by voxel through the phase
+ * indicator) and a first-order sink:
+ *     [(1/dt + k) - div D grad] c = c^n / dt,
+ * div = -grad^H with the forward-difference gradient, applied as the 5-point
+ * (7-point in 3D) flux stencil.  Voxels with dirichlet_mask != 0 hold
+ * c = c_dir; CG runs on the other voxels from c^n (stop: ||r|| <= tol ||b||).
+ *   c               device [N], in c^n, out c^{n+1}
+ *   Dfield          device [N] diffusion coefficient per voxel (m^2/s, >= 0)
+ *   krate           device [N] first-order rate per voxel (1/s, >= 0) or NULL (0)
+ *   dirichlet_mask  device [N] uint8 or NULL (no Dirichlet voxels)
+ * The fields are not checked on the host: a negative or non-finite value ends
+ * the solve with EBREAKDOWN or EDOMAIN.  EINVAL for NULL c/Dfield or bad
+ * tol/maxit, EDOMAIN for dt <= 0 or a non-finite c_dir. */
+int fgcg_diffusion_step(fgcg_ctx* ctx, double* c, const double* Dfield, const double* krate,
+                        const uint8_t* dirichlet_mask, double c_dir, double dt, double tol, int maxit,
+                        fgcg_info* info);
+
+/* The same step with per-phase tables (the fast path of the staggered step:
+ * one byte per voxel instead of seventeen): D = D_tab[phase], k = k_tab[phase]
+ * (host [nphase]), Dirichlet voxels x index < band_width with c = c_dir. */
+int fgcg_diffusion_step_phases(fgcg_ctx* ctx, const uint8_t* phase, int nphase, const double* D_tab,
+                               const double* k_tab, int band_width, double c_dir, double dt, double* c,
+                               double tol, int maxit, fgcg_info* info);
+
+/* Static diffusion homogenisation on the representative volume (Sec. 2.1,
+ * eq. diffusion / eq. diffusion-weak-form / eq. diffusion-final; the diffusion
+ * block of Alg. 1): the concentration gradient is the primary unknown,
+ * grad c = grad c_mac + x with x compatible (range of the vector projection G
+ * of App. A, forward-difference gradient of Sec. 2.6) and G[D grad c] = 0,
+ * i.e. div j = 0 with j = -D grad c and <grad c> = grad c_mac.  Solved by CG
+ * from x = 0 carried on the scalar fluctuation phi (x = grad phi), with the
+ * Green operator (grad^H grad)^-1 as preconditioner: the same iterates as the
+ * projected CG on x.  Stop when ||r|| <= tol ||b|| (norm of the projected
+ * flux residual) or after maxit iterations.  FP64 contexts, 2D and 3D.
+ *   Dfield     device [N] diffusion coefficient per voxel (> 0)
+ *   grad_cmac  host [dim] macroscopic concentration gradient
+ *   grad_c     device [dim][N] out or NULL: grad c = grad c_mac + grad phi
+ *   phi        device [N] out or NULL: the periodic fluctuation (mean zero)
+ *   mean_flux  host [dim] out or NULL: <j> = -<D grad c>
+ * EUNSUPPORTED in FP32-mixed contexts; Dfield is not checked on the host (a
+ * non-positive or non-finite value ends the solve with EBREAKDOWN/EDOMAIN). */
+int fgcg_diffusion_homogenize(fgcg_ctx* ctx, const double* Dfield, const double* grad_cmac, double tol,
+                              int maxit, double* grad_c, double* phi, double* mean_flux, fgcg_info* info);
+
+/* Effective diffusivity of the volume (the quantity of App. B's sensitivity
+ * study): <j> = -D_eff grad c_mac; column a from the homogenisation with
+ * grad c_mac = e_a.  Deff: host [dim][dim] row-major out; infos: host [dim]
+ * or NULL.  Returns the worst status of the dim solves. */
+int fgcg_diffusivity_eff(fgcg_ctx* ctx, const double* Dfield, double tol, int maxit, double* Deff,
+                         fgcg_info* infos);
+
+/* Concentration from a concentration-gradient field (eqs. micro-gradient,
+ * concentration, phi-fft, psi-two-values, concentration-correct; the
+ * "periodic fluctuations" and "concentration" lines of Alg. 1):
+ * phi_hat = (i xi)^-1 . (grad c)_hat with the inverse gradient of eq. g-42
+ * (zero at k = 0), then c(x) = grad c_mac . x + phi(x) + beta_phase with x of
+ * voxel (ix, iy, iz) = (ix, iy, iz) h, beta_pore chosen so that the pore mean
+ * is c_mac / eta and beta_solid so that the solid mean is 0 (eta = pore share;
+ * pores are phase 0).
+ *   phase  device [N] uint8;  grad_c device [dim][N];  grad_cmac host [dim]
+ *   c      device [N] out;  beta host [2] out or NULL: beta_pore, beta_solid
+ * FP64 contexts. */
+int fgcg_concentration(fgcg_ctx* ctx, const uint8_t* phase, const double* grad_c, const double* grad_cmac,
+                       double c_mac, double* c, double* beta);
 
 /* Staggered corrosion-fracture step (Alg. 1).  State fields are device [N]
  * (strain: [n_s][N]) owned by the caller and updated in place.  On 3D grids
@@ -226,11 +303,13 @@ typedef struct {
 typedef struct {
   fgcg_material mat;
   const double* D_tab; /* host [nphase] diffusion coefficient per phase */
-  const double* k_tab; /* host [nphase] first-order precipitation rate per phase */
+  const double* k_tab; /* host [nphase] first-order rate per phase: the sink of the
+                          diffusion step and the precipitation f += dt k c in the
+                          same voxels (f unchanged where k = 0) */
   int band_width;      /* Dirichlet band x < band_width, c = c_dir */
   double c_dir;
   double dt;
-  double e_per_f;      /* eigenstrain per unit precipitate fraction (pores only) */
+  double e_per_f;      /* eigenstrain e = e_per_f f per unit precipitate fraction */
   double Gc, l0, kappa;
   double eps_mac[6];   /* n_s entries used */
   double tol_diff, tol_mech, tol_pf;
@@ -254,10 +333,23 @@ int fgcg_staggered_step(fgcg_ctx* ctx, fgcg_state* state, const fgcg_params* prm
                         fgcg_step_info* info);
 
 /* ---- kernel-level test hooks ------------------------------------------ */
-/* 2D grids only (EUNSUPPORTED in 3D).
- * q = G[g C : sym(p)] for a full gradient p (device [4][N] each). */
-int fgcg_mech_apply(fgcg_ctx* ctx, const fgcg_material* mat, const double* d, double kappa,
-                    const double* p, double* q);
+/* One application of an operator of the mechanics solver through the very
+ * kernels a solve launches, in the context's precision (FP32-mixed: in is
+ * rounded to FP32, out is the FP32 result widened), on 2D and 3D grids:
+ *   FGCG_OP_MECH_K  out = K in, K = grad^H g C sym(grad) (Sec. 2.3 with the
+ *                   forward difference of Sec. 2.6), the tiled stiffness pass;
+ *   FGCG_OP_MECH_M  out = M in, M = (grad^H grad)^-1 per component (App. A's
+ *                   projection factored through the displacement; zero mean),
+ *                   the row / column (2D) or x / y / z (3D) transform passes
+ *                   with the Green symbol, tuned radix plans.
+ * in, out: device [n_u][N] displacement-like fields, n_u = 2 (2D) or 3 (3D).
+ * The workspace and CG state of the context are overwritten.  EINVAL for NULL
+ * pointers or an unknown op; material errors as fgcg_mech_solve. */
+enum { FGCG_OP_MECH_K = 0, FGCG_OP_MECH_M = 1 };
+int fgcg_debug_apply(fgcg_ctx* ctx, int op, const fgcg_material* mat, const double* d, double kappa,
+                     const double* in, double* out);
+/* 2D grids only (EUNSUPPORTED in 3D): the scalar operators through the
+ * spectral passes. */
 /* q = (Gc/(2 l0) + H) v + (Gc l0/2) F^-1 |D|^2 F v. */
 int fgcg_phasefield_apply(fgcg_ctx* ctx, const double* H, double Gc, double l0, const double* v,
                           double* q);

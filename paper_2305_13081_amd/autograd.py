@@ -13,9 +13,9 @@ _OBJ = {"energy": fgcg.J_ENERGY, "C11": fgcg.J_C11}
 class MechObjective(torch.autograd.Function):
     @staticmethod
     def forward(ctx, E_field, context, nu, eps_mac, objective, tol, maxit):
-        res = context.mech_solve(None, None, None, eps_mac, E_field=E_field.detach().contiguous(), nu_field=nu,
-                                 tol=tol, maxit=maxit, want_stress=False)
-        J = res["energy"] if objective == "energy" else res["mean_stress"][0] / eps_mac[0]
+        # the objective as the library evaluates it (forward solve only)
+        _, J, _, _ = context.mech_adjoint(E_field.detach().contiguous(), nu, eps_mac, objective=_OBJ[objective],
+                                          tol=tol, maxit=maxit, want_grad=False)
         ctx.save_for_backward(E_field)
         ctx.args = (context, nu, tuple(eps_mac), objective, tol, maxit)
         return torch.tensor(J, dtype=torch.float64, device=E_field.device)

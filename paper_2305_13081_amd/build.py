@@ -3,7 +3,8 @@
     python -m paper_2305_13081_amd.build
 
 compiles every translation unit under ``csrc/`` (``fgcg.hip``: the C ABI and
-the 2D solvers; ``fgcg3d.hip``: the 3D solvers) for gfx950 with hipcc, in
+the 2D solvers; ``fgcg3d.hip``: the 3D solvers; ``homog.hip``: the diffusion
+homogenisation and concentration reconstruction) for gfx950 with hipcc, in
 parallel, and links them into ``libfgcg.so`` next to this file (the library
 the binding loads).  Packed-FP32 instruction selection is disabled for every
 HIP translation unit, and floating-point contraction is limited to single
@@ -19,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfgcg.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fgcg.hip", "fgcg3d.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fgcg.hip", "fgcg3d.hip", "homog.hip")]
 
 COMPILE_FLAGS = [
     "--offload-arch=gfx950",

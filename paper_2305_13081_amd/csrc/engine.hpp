@@ -111,7 +111,12 @@ struct fgcg_ctx {
   int rows_pick = 0;  // 2D mechanics row passes: rows per block (0: time the candidates at the next solve)
   // 2D mechanics radix plans (1: plan 0, radix 8; 2: plan 1, radix 16; 0: time both at the next solve)
   int plan_row = 0, plan_col = 0;
+  int precond = 0;          // mechanics preconditioner: 0 unit Green operator, 1 isotropic reference medium
+  double ref_lam = 0, ref_mu = 0;  // reference medium set by the caller (0, 0: from the material)
+  double use_lam = 0, use_mu = 0;  // reference medium of the current solve (mu = 1)
   int nsamp = 1;            // samples of this grid size (batches)
+  int ncw = 2;              // components of the x, r, p, tmp and spectrum workspace (2D: 2, 3D: 3)
+  double* lm_dev = nullptr; // batches: per-sample Lame tables [nsamp][16]
   double* ems = nullptr;    // device [nsamp][3] macro strains
   bool batch = false;            // member of a batch (owns the gather buffers below)
   uint8_t* phase_buf = nullptr;  // batches: gathered phase fields [nsamp][N]
@@ -135,8 +140,11 @@ struct fgcg_ctx {
     std::vector<char> key;
     GraphSlot slot[2];
   };
-  CgGraph graphs[6];  // mechanics, phase field, diffusion (spectral), phase field, diffusion (stencil),
-                      // mechanics FP32-mixed
+  // chunk graphs per solver: 0 mechanics, 1 phase field (spectral), 2 diffusion
+  // (spectral), 3 phase field, 4 diffusion (phase tables), 5 mechanics
+  // FP32-mixed, 6 diffusion (per-voxel fields), 7 diffusion homogenisation,
+  // 8-11 spare
+  CgGraph graphs[12];
 };
 
 namespace fgcg {
@@ -551,6 +559,7 @@ inline int make_mech_mat(const fgcg_ctx* c, const fgcg_material* mat, const doub
   if (!mat->phase || !mat->E_tab || !mat->nu_tab) return fail(FGCG_EINVAL, "phase/E_tab/nu_tab is NULL");
   if (mat->nphase < 1 || mat->nphase > FGCG_MAX_PHASES) return fail(FGCG_EINVAL, "nphase outside 1..8");
   m->phase = mat->phase;
+  m->nphase = mat->nphase;
   for (int i = 0; i < mat->nphase; ++i) {
     const double E = mat->E_tab[i], nu = mat->nu_tab[i];
     if (!(E > 0.0) || !std::isfinite(E)) return fail(FGCG_EDOMAIN, "E <= 0 or not finite");
@@ -559,6 +568,49 @@ inline int make_mech_mat(const fgcg_ctx* c, const fgcg_material* mat, const doub
     m->lm.b[i] = E / (2.0 * (1.0 + nu));
   }
   return 0;
+}
+
+// A running CG state for every sample (unit r.z, no stop test), so that the
+// solver's passes do their full work outside a solve (timing, test hooks).
+inline int running_state(fgcg_ctx* c) {
+  std::vector<CgState> hs(c->nsamp);
+  for (CgState& t : hs) {
+    std::memset(&t, 0, sizeof t);
+    t.rz[0] = t.rz[1] = 1.0;
+    t.bnorm2 = 1.0;
+    t.maxit = 1 << 30;
+  }
+  HIPCHK(hipMemcpyAsync(c->st, hs.data(), sizeof(CgState) * hs.size(), hipMemcpyHostToDevice, c->stream));
+  // the host vector is read by the copy: wait before it goes out of scope
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+// The reference medium of the next mechanics solve: the caller's, or the
+// Lame ratio of the stiffest phase (the per-voxel field's Poisson ratio).
+// Only lam0 / mu0 matters to the preconditioned CG; mu0 is scaled to 1.
+inline void resolve_reference(fgcg_ctx* c, const MechMat& m) {
+  const int nphase = m.nphase;
+  double lam = c->ref_lam, mu = c->ref_mu;
+  if (!(mu > 0.0)) {
+    if (m.Efield) {
+      lam = m.lam_per_E;
+      mu = m.mu_per_E;
+    } else {
+      double best = -1.0;
+      for (int i = 0; i < nphase; ++i) {
+        const double l = m.lm.a[i], u = m.lm.b[i];
+        const double E = u * (3.0 * l + 2.0 * u) / (l + u);
+        if (E > best) {
+          best = E;
+          lam = l;
+          mu = u;
+        }
+      }
+    }
+  }
+  c->use_lam = lam / mu;
+  c->use_mu = 1.0;
 }
 
 inline int check_solver_args(double tol, int maxit) {
@@ -574,5 +626,6 @@ int mech3_solve(fgcg_ctx* c, const MechMat& m, const double* eig, const double* 
                 double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info);
 int history3(fgcg_ctx* c, const MechMat& m0, const double* strain, const double* e, double* H);
 int debug_fft(fgcg_ctx* c, int dir, const double* in, double* out);
+int debug_apply3(fgcg_ctx* c, int op, const MechMat& m, const double* in, double* out);
 
 }  // namespace fgcg

@@ -32,6 +32,22 @@ int launch_mech_row_inv(fgcg_ctx* c, int kind, const MechUEpi<T, 2>& e, CT<T>* s
   return launch_row_inv<T, 1, MechUEpiC<T, 2, false>, true>(c, kind, ec, spec, 2 * ns, ss / 2);
 }
 
+// The Green pass of the mechanics PCG (partial sums of r.z into part_rr):
+// the unit Green operator one component per block, or the reference medium
+// with both components of a column per block.  st nullable (no state check).
+template <typename T> int launch_green(fgcg_ctx* c, int kind, const CgState* st, int ns, long long ss) {
+  CT<T>* spec = (CT<T>*)c->spec;
+  if (c->precond == 1) {
+    const MechRefGreen<T> g{c->Dx, c->Dy, 1.0 / (double)c->n, c->use_lam, c->use_mu, c->nx, st, c->part_rr};
+    return launch_col<T, 2, 2, MechRefGreen<T>, true>(c, kind, g, spec, spec, ns, ss);
+  }
+  const MechGreen<T> g{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, st, c->part_rr};
+  return launch_col<T, 1, 1, MechGreen<T>, true>(c, kind, g, spec, spec, 2 * ns, ss / 2);
+}
+
+// Partial sums of r.z per sample left by the Green pass.
+inline int green_parts(const fgcg_ctx* c) { return c->precond == 1 ? c->ncol : 2 * c->ncol; }
+
 // z = M r, p = z, r.z and the CG state of every sample (R holds f, X holds 0).
 template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
   CT<T>* spec = (CT<T>*)c->spec;
@@ -40,9 +56,8 @@ template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, i
   int rc;
   const CopyProN<T, 2> cp{fld<T>(c->r, c), c->nx};
   if ((rc = launch_row_fwd<T, 2, CopyProN<T, 2>, true>(c, -1, cp, spec, ns, ss))) return rc;
-  const MechGreen<T> g0{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
-  if ((rc = launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, g0, spec, spec, 2 * ns, ss / 2))) return rc;
-  const MechUEpi<T, 2> e0{fld<T>(c->p, c), c->nx, c->st, c->part_rr, 2 * c->ncol, 1, tol, maxit};
+  if ((rc = launch_green<T>(c, -1, nullptr, ns, ss))) return rc;
+  const MechUEpi<T, 2> e0{fld<T>(c->p, c), c->nx, c->st, c->part_rr, green_parts(c), 1, tol, maxit};
   if ((rc = launch_mech_row_inv<T>(c, -1, e0, spec, ns, ss))) return rc;
   HIPCHK(hipGetLastError());
   return 0;
@@ -69,9 +84,8 @@ template <typename T> int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, i
     const CopyProN<T, 2> cp{R, c->nx};
     r |= launch_row_fwd<T, 2, CopyProN<T, 2>, true>(c, -1, cp, spec, ns, ss);
   }
-  const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, c->st, c->part_rr};
-  r |= launch_col<T, 1, 1, MechGreen<T>, true>(c, FGCG_K_MECH_COL, green, spec, spec, 2 * ns, ss / 2);
-  const MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, tol, maxit};
+  r |= launch_green<T>(c, FGCG_K_MECH_COL, c->st, ns, ss);
+  const MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, green_parts(c), 0, tol, maxit};
   r |= launch_mech_row_inv<T>(c, FGCG_K_MECH_ROW_INV, epi, spec, ns, ss);
   return r;
 }
@@ -96,8 +110,8 @@ int mech_rhs(fgcg_ctx* c, const MechMat& m, const double* eig) {
 
 Key mech_key(const fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
   Key key;
-  key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm).add(c->prec);
-  key.add(tol).add(maxit).add(c->rows_pick).add(c->plan_row).add(c->plan_col);
+  key.add(m.phase).add(m.d).add(m.Efield).add(m.lm_dev).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm);
+  key.add(c->prec).add(c->precond).add(c->use_lam).add(c->use_mu).add(tol).add(maxit).add(c->rows_pick).add(c->plan_row).add(c->plan_col);
   return key;
 }
 
@@ -106,17 +120,11 @@ Key mech_key(const fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
 // so that every pass does its full work.
 template <typename T> int timing_workspace(fgcg_ctx* c) {
   const int ns = c->nsamp;
-  std::vector<CgState> hs(ns);
-  for (CgState& t : hs) {
-    std::memset(&t, 0, sizeof t);
-    t.rz[0] = t.rz[1] = 1.0;
-    t.bnorm2 = 1.0;
-    t.maxit = 1 << 30;
-  }
-  HIPCHK(hipMemcpyAsync(c->st, hs.data(), sizeof(CgState) * ns, hipMemcpyHostToDevice, c->stream));
-  const size_t nv = sizeof(T) * 4 * (size_t)c->n * ns;
+  int rc = running_state(c);
+  if (rc) return rc;
+  const size_t nv = sizeof(T) * c->ncw * (size_t)c->n * ns;
   for (void* b : {c->x, c->r, c->p, c->tmp}) HIPCHK(hipMemsetAsync(b, 0, nv, c->stream));
-  HIPCHK(hipMemsetAsync(c->spec, 0, sizeof(CT<T>) * 4 * (size_t)c->nxh * c->rows * ns, c->stream));
+  HIPCHK(hipMemsetAsync(c->spec, 0, sizeof(CT<T>) * c->ncw * (size_t)c->nxh * c->rows * ns, c->stream));
   const int npa = c->nkpt, nprz = 2 * c->ncol;
   std::vector<double> ones((size_t)std::max(npa, nprz) * ns, 1.0);
   HIPCHK(hipMemcpyAsync(c->part_a, ones.data(), sizeof(double) * npa * ns, hipMemcpyHostToDevice, c->stream));
@@ -158,14 +166,13 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   const long long ss = spec_ss(c);
   int rc = timing_workspace<T>(c);
   if (rc) return rc;
-  const int npa = c->nkpt, nprz = 2 * c->ncol;
+  const int npa = c->nkpt, nprz = green_parts(c);
   CT<T>* spec = (CT<T>*)c->spec;
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
   const MechUProC<T, 2> pro{{X, R, P, Q, c->nx, c->st, c->part_a, npa}};
   const MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, nprz, 0, 0.0, 1 << 30};
-  // the Green pass without a CG state (timed after the row passes, whose
-  // direction update reads part_rr; 2 nxh partial sums per sample)
-  const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
+  // the Green pass (of the context's preconditioner) without a CG state,
+  // timed after the row passes, whose direction update reads part_rr
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -213,9 +220,7 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
     std::vector<float> tc(pcol_c.size(), 0.f);
     for (size_t ip = 0; ip < pcol_c.size() && !rc; ++ip) {
       c->plan_col = pcol_c[ip];
-      tc[ip] = time_it([&] {
-        return launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, green, spec, spec, 2 * ns, ss / 2);
-      });
+      tc[ip] = time_it([&] { return launch_green<T>(c, -1, nullptr, ns, ss); });
     }
     size_t ic = 0;
     for (size_t ip = 1; ip < pcol_c.size(); ++ip)
@@ -247,16 +252,15 @@ template <typename T> int time_pass_t(fgcg_ctx* c, int kind, int reps, double* u
   CT<T>* spec = (CT<T>*)c->spec;
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
   const MechUProC<T, 2> pro{{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt}};
-  const MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, 2 * c->ncol, 0, 0.0, 1 << 30};
+  const MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, green_parts(c), 0, 0.0, 1 << 30};
   // (only one kind is launched: the Green pass's partial sums may overwrite
   // the unit sums the direction update would read)
-  const MechGreen<T> green{c->Dx, c->Dy, 1.0 / (double)c->n, c->nx, nullptr, c->part_rr};
   auto one = [&]() -> int {
     if (kind == FGCG_K_MECH_ROW_FWD)
       return launch_row_fwd<T, 1, MechUProC<T, 2>, true>(c, -1, pro, spec, 2 * ns, ss / 2);
     if (kind == FGCG_K_MECH_ROW_INV)
       return launch_mech_row_inv<T>(c, -1, epi, spec, ns, ss);
-    return launch_col<T, 1, 1, MechGreen<T>, true>(c, -1, green, spec, spec, 2 * ns, ss / 2);
+    return launch_green<T>(c, -1, nullptr, ns, ss);
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(FGCG_EHIP, "hipEventCreate");
@@ -271,6 +275,32 @@ template <typename T> int time_pass_t(fgcg_ctx* c, int kind, int reps, double* u
   if (e1) (void)hipEventDestroy(e1);
   if (!rc) *us = 1e3 * (double)ms / reps;
   return rc;
+}
+
+// Kernel-level hook: q = K p through the stiffness pass of the solver
+// (k_mech_kp) or z = M r through the Green passes the solver starts every
+// solve with (row transform, k_col<MechGreen> with the tuned radix plan,
+// inverse row transform writing p = z), in the context's precision.
+template <typename T> int debug_apply_t(fgcg_ctx* c, int op, const MechMat& m, const double* in, double* out) {
+  const long long n2 = 2 * c->n;
+  int rc;
+  if (op == FGCG_OP_MECH_K) {
+    if ((rc = running_state(c))) return rc;
+    hipLaunchKernelGGL((k_convert<T, double>), dim3(c->npost), dim3(PT), 0, c->stream, (T*)c->p, in, n2);
+    hipLaunchKernelGGL((k_mech_kp<T>), dim3(c->nkpt, 1), dim3(NT), 0, c->stream, m, (const T*)c->p, (T*)c->tmp, c->n,
+                       c->nx, c->ny, (T)(1.0 / c->h), c->st, c->part_a);
+    hipLaunchKernelGGL((k_convert<double, T>), dim3(c->npost), dim3(PT), 0, c->stream, out, (const T*)c->tmp, n2);
+    HIPCHK(hipGetLastError());
+    return 0;
+  }
+  resolve_reference(c, m);
+  if ((rc = tune_passes(c))) return rc;
+  hipLaunchKernelGGL((k_convert<T, double>), dim3(c->npost), dim3(PT), 0, c->stream, (T*)c->r, in, n2);
+  HIPCHK(hipMemsetAsync(c->p, 0, sizeof(T) * n2, c->stream));  // z = 0 stays if r = 0
+  if ((rc = mech_init<T>(c, m, 0.0, 1))) return rc;
+  hipLaunchKernelGGL((k_convert<double, T>), dim3(c->npost), dim3(PT), 0, c->stream, out, (const T*)c->p, n2);
+  HIPCHK(hipGetLastError());
+  return 0;
 }
 
 // Builds the iteration closure of a context (period RELIABLE_EVERY in FP32-mixed).
@@ -345,6 +375,7 @@ int mech_solve_single(fgcg_ctx* c, const MechMat& m, const double* eig, const do
                       double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
   const double t0 = now();
   int rc;
+  resolve_reference(c, m);
   if ((rc = tune_passes(c)) || (rc = upload_ems(c, em)) || (rc = mech_rhs(c, m, eig))) return rc;
   CgState s;
   if ((rc = mech_pcg(c, m, tol, maxit, &s))) return rc;
@@ -371,6 +402,10 @@ int mech_adjoint_t(fgcg_ctx* c, const MechMat& m, const double* eig, const doubl
   if (objective == ADJ_ENERGY) scale = c->h * c->h;
   if (objective == ADJ_C11) scale = 1.0 / (N * em[0]);
   if (J) *J = objective == ADJ_ENERGY ? energy : (objective == ADJ_C11 ? mean[0] / em[0] : 0.0);
+  if (!grad) {  // the objective only
+    if (info_adj) std::memset(info_adj, 0, sizeof *info_adj);
+    return fwd_status;
+  }
   const double t0 = now();
   CgState s{};
   int have_lam = 0;
@@ -545,17 +580,16 @@ int diff_step_t(fgcg_ctx* c, const DiffCoef& co, double c_dir, double* cfield, d
 // ------------------------------------------------- stencil scalar CG
 template <typename T, class Op>
 int scg_solve(fgcg_ctx* c, int which, const Key& key, const Op& op, const double* xin, double bscale,
-              const double* bsrc, int band, double c_dir, double tol, int maxit, int kind_dir, int kind_upd,
-              CgState* out) {
+              const double* bsrc, double c_dir, double tol, int maxit, int kind_dir, int kind_upd, CgState* out) {
   T* X = (T*)c->x;
   T* R = (T*)c->r;
   T* P0 = (T*)c->p;
-  T* P1 = P0 + c->n;  // second direction buffer (p holds 4 components of room)
+  T* P1 = P0 + c->n;  // second direction buffer (p holds at least 2 components of room)
   T* Q = (T*)c->tmp;
   int parity = 0;     // iteration k reads P[k & 1] and writes P[(k + 1) & 1]
   const int nsb = (int)(c->sgrid.x * c->sgrid.y);
-  hipLaunchKernelGGL((k_scg_init<T, Op>), c->sgrid, dim3(NT), 0, c->stream, op, xin, bscale, bsrc, band, c_dir, X,
-                     R, c->nx, c->ny, c->nz, c->part_b, c->part_rr);
+  hipLaunchKernelGGL((k_scg_init<T, Op>), c->sgrid, dim3(NT), 0, c->stream, op, xin, bscale, bsrc, c_dir, X, R,
+                     c->nx, c->ny, c->nz, c->part_b, c->part_rr);
   hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_b, nsb, 0, tol, maxit);
   HIPCHK(hipGetLastError());
   const int ndir = std::min(scg_chunks(c->nx, c->ny, c->nz), 2048);  // p.q partial sums in part_a
@@ -567,7 +601,7 @@ int scg_solve(fgcg_ctx* c, int which, const Key& key, const Op& op, const double
     T* pout = parity ? P0 : P1;
     parity ^= 1;
     int r = launch(c, kind_dir, (const void*)&k_scg_dir<T, Op>, dim3(ndir), op, (const T*)R, (const T*)pin, pout, Q,
-                   c->nx, c->ny, c->nz, band, cc);
+                   c->nx, c->ny, c->nz, cc);
     r |= launch(c, kind_upd, (const void*)&k_scg_upd<T>, c->sgrid, X, R, (const T*)pout, (const T*)Q, c->nx,
                 c->rows, cc);
     return r;
@@ -586,7 +620,7 @@ int pf_solve_stencil(fgcg_ctx* c, const double* H, double Gc, double l0, double*
   Key key;
   key.add(op.H).add(op.a).add(op.cih2);
   CgState s;
-  int rc = scg_solve<T>(c, 3, key, op, d, 1.0, H, 0, 0.0, tol, maxit, FGCG_K_PF_ROW_FWD, FGCG_K_PF_ROW_INV, &s);
+  int rc = scg_solve<T>(c, 3, key, op, d, 1.0, H, 0.0, tol, maxit, FGCG_K_PF_ROW_FWD, FGCG_K_PF_ROW_INV, &s);
   if (rc) return rc;
   if (s.zero_rhs) HIPCHK(hipMemsetAsync(c->x, 0, sizeof(T) * c->n, c->stream));
   hipLaunchKernelGGL((k_convert<double, T>), dim3(c->npost), dim3(PT), 0, c->stream, d, (const T*)c->x, c->n);
@@ -596,20 +630,19 @@ int pf_solve_stencil(fgcg_ctx* c, const double* H, double Gc, double l0, double*
   return status_of(s);
 }
 
-template <typename T>
-int diff_step_stencil(fgcg_ctx* c, const DiffCoef& co, double c_dir, double* cfield, double tol, int maxit,
-                      fgcg_info* info) {
+// Diffusion step with the stencil CG; Op is DiffStencil (phase tables, band)
+// or DiffFieldStencil (per-voxel fields, mask).  which: the graph slot.
+template <typename T, class Op>
+int diff_step_stencil(fgcg_ctx* c, const Op& op, double inv_dt, int which, const Key& key, double c_dir,
+                      double* cfield, double tol, int maxit, fgcg_info* info) {
   const double t0 = now();
-  const DiffStencil op{co, co.phase, 1.0 / (c->h * c->h)};
-  Key key;
-  key.add(co.phase).add(co.dk).add(co.inv_dt).add(co.band).add(op.ih2);
   CgState s;
-  int rc = scg_solve<T>(c, 4, key, op, cfield, co.inv_dt, cfield, co.band, c_dir, tol, maxit, FGCG_K_DIFF_ROW_FWD,
+  int rc = scg_solve<T>(c, which, key, op, cfield, inv_dt, cfield, c_dir, tol, maxit, FGCG_K_DIFF_ROW_FWD,
                         FGCG_K_DIFF_ROW_INV, &s);
   if (rc) return rc;
   if (s.zero_rhs) HIPCHK(hipMemsetAsync(c->x, 0, sizeof(T) * c->n, c->stream));
-  hipLaunchKernelGGL((k_diff_finish<T>), dim3(c->npost), dim3(PT), 0, c->stream, cfield, (const T*)c->x, c->n,
-                     c->nx, co.band, c_dir);
+  hipLaunchKernelGGL((k_scg_finish<T, Op>), dim3(c->npost), dim3(NT), 0, c->stream, op, cfield, (const T*)c->x,
+                     c->n, c->nx, c_dir);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   fill_info(info, s, now() - t0);
@@ -629,16 +662,17 @@ template <typename T> int make_twiddles(int n, void** out) {
 
 template <typename T> int alloc_workspace(fgcg_ctx* c) {
   const size_t ns = (size_t)c->nsamp;
-  const size_t nr = sizeof(T) * 4 * (size_t)c->n * ns;
+  const size_t nr = sizeof(T) * c->ncw * (size_t)c->n * ns;
   HIPCHK(hipMalloc(&c->x, nr));
   HIPCHK(hipMalloc(&c->r, nr));
   HIPCHK(hipMalloc(&c->p, nr));
   HIPCHK(hipMalloc(&c->tmp, nr));
-  HIPCHK(hipMalloc(&c->spec, sizeof(CT<T>) * 4 * (size_t)c->nxh * c->rows * ns));
+  HIPCHK(hipMalloc(&c->spec, sizeof(CT<T>) * c->ncw * (size_t)c->nxh * c->rows * ns));
   HIPCHK(hipMalloc(&c->ems, sizeof(double) * 3 * ns));
   if (c->batch) {
     HIPCHK(hipMalloc(&c->phase_buf, (size_t)c->n * ns));
     HIPCHK(hipMalloc(&c->strain_buf, sizeof(double) * 3 * (size_t)c->n * ns));
+    HIPCHK(hipMalloc(&c->lm_dev, sizeof(double) * 16 * ns));
   }
   int rc;
   if ((rc = make_twiddles<double>(c->nx, &c->twx)) || (rc = make_twiddles<double>(c->ny, &c->twy))) return rc;
@@ -704,6 +738,7 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
   c->h = grid->h;
   c->prec = grid->precision;
   c->nsamp = nsamp;
+  c->ncw = c->ndim == 3 ? 3 : 2;
   c->batch = batch;
   c->user_stream = (hipStream_t)hip_stream;
   {
@@ -772,7 +807,7 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
 
 void fgcg_destroy(fgcg_ctx* c) {
   if (!c) return;
-  void* dev[] = {c->ems,  c->phase_buf, c->strain_buf, c->twx,    c->twy,    c->twx32,  c->twy32, c->twz,
+  void* dev[] = {c->lm_dev, c->ems,  c->phase_buf, c->strain_buf, c->twx,    c->twy,    c->twx32,  c->twy32, c->twz,
                  c->twz32, c->Dz,       c->red,        c->part_z, c->xh,     c->fh,     c->aux,   c->Dx,
                  c->Dy,   c->x,         c->r,          c->p,      c->tmp,    c->spec,   c->st,    c->part_a,
                  c->part_rr, c->part_b, c->part_post};
@@ -822,6 +857,12 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
       c->rows_pick = value;
       return FGCG_OK;
     }
+    case FGCG_OPT_PRECOND:
+      if (value != 0 && value != 1) return fail(FGCG_EINVAL, "preconditioner must be 0 (unit) or 1 (reference)");
+      if (c->batch) return fail(FGCG_EUNSUPPORTED, "batch groups take the unit Green operator");
+      if (value != c->precond && c->ndim == 2) c->plan_col = 0;  // the column pass changes: tune it again
+      c->precond = value;
+      return FGCG_OK;
     case FGCG_OPT_ROW_PLAN:
     case FGCG_OPT_COL_PLAN:
       if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "radix plans are tuned on 2D grids");
@@ -833,6 +874,16 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
   }
 }
 
+int fgcg_set_reference(fgcg_ctx* c, double lam0, double mu0) {
+  if (!c) return fail(FGCG_EINVAL, "ctx is NULL");
+  const bool automatic = lam0 == 0.0 && mu0 == 0.0;
+  if (!automatic && !(mu0 > 0.0 && lam0 > -2.0 * mu0 / 3.0 && std::isfinite(lam0) && std::isfinite(mu0)))
+    return fail(FGCG_EDOMAIN, "reference medium needs mu0 > 0 and a positive bulk modulus");
+  c->ref_lam = lam0;
+  c->ref_mu = mu0;
+  return FGCG_OK;
+}
+
 int fgcg_get_option(fgcg_ctx* c, int option, int* value) {
   if (!c || !value) return fail(FGCG_EINVAL, "ctx/value is NULL");
   switch (option) {
@@ -842,6 +893,7 @@ int fgcg_get_option(fgcg_ctx* c, int option, int* value) {
     case FGCG_OPT_ROWS: *value = c->rows_pick; return FGCG_OK;
     case FGCG_OPT_ROW_PLAN: *value = c->plan_row; return FGCG_OK;
     case FGCG_OPT_COL_PLAN: *value = c->plan_col; return FGCG_OK;
+    case FGCG_OPT_PRECOND: *value = c->precond; return FGCG_OK;
     default: return fail(FGCG_EINVAL, "unknown option");
   }
 }
@@ -868,7 +920,7 @@ int fgcg_mech_solve(fgcg_ctx* c, const fgcg_material* mat, const double* d, doub
 int fgcg_mech_adjoint(fgcg_ctx* c, const fgcg_material* mat, const double* d, double kappa, const double* eig,
                       const double* eps_mac, const double* dJ_dstrain, int objective, double tol, int maxit,
                       double* grad_E, double* J, fgcg_info* info_fwd, fgcg_info* info_adj) {
-  if (!c || !eps_mac || !grad_E) return fail(FGCG_EINVAL, "ctx/eps_mac/grad_E is NULL");
+  if (!c || !eps_mac) return fail(FGCG_EINVAL, "ctx/eps_mac is NULL");
   if (c->prec != FGCG_FP64) return fail(FGCG_EUNSUPPORTED, "the adjoint runs in FP64 contexts");
   if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "the adjoint is 2D only");
   if (objective != ADJ_USER && objective != ADJ_ENERGY && objective != ADJ_C11)
@@ -896,9 +948,9 @@ int fgcg_phasefield_solve(fgcg_ctx* c, const double* H, double Gc, double l0, do
   return pf_solve_t<double>(c, H, Gc, l0, d, tol, maxit, info);
 }
 
-int fgcg_diffusion_step(fgcg_ctx* c, const uint8_t* phase, int nphase, const double* D_tab, const double* k_tab,
-                        int band_width, double c_dir, double dt, double* cfield, double tol, int maxit,
-                        fgcg_info* info) {
+int fgcg_diffusion_step_phases(fgcg_ctx* c, const uint8_t* phase, int nphase, const double* D_tab,
+                               const double* k_tab, int band_width, double c_dir, double dt, double* cfield,
+                               double tol, int maxit, fgcg_info* info) {
   if (!c || !cfield) return fail(FGCG_EINVAL, "ctx/c is NULL");
   int rc;
   if ((rc = check_solver_args(tol, maxit))) return rc;
@@ -908,8 +960,28 @@ int fgcg_diffusion_step(fgcg_ctx* c, const uint8_t* phase, int nphase, const dou
   if ((rc = make_diff_coef(phase, nphase, D_tab, k_tab, dt, band_width, c->n, &co))) return rc;
   if ((rc = enter(c))) return rc;
   if (c->scalar_spectral && c->ndim == 3) return fail(FGCG_EUNSUPPORTED, "spectral scalar operators are 2D only");
-  if (!c->scalar_spectral) return diff_step_stencil<double>(c, co, c_dir, cfield, tol, maxit, info);
+  if (!c->scalar_spectral) {
+    const DiffStencil op{co, co.phase, 1.0 / (c->h * c->h)};
+    Key key;
+    key.add(co.phase).add(co.dk).add(co.inv_dt).add(co.band).add(op.ih2);
+    return diff_step_stencil<double>(c, op, co.inv_dt, 4, key, c_dir, cfield, tol, maxit, info);
+  }
   return diff_step_t<double>(c, co, c_dir, cfield, tol, maxit, info);
+}
+
+int fgcg_diffusion_step(fgcg_ctx* c, double* cfield, const double* Dfield, const double* krate,
+                        const uint8_t* dirichlet_mask, double c_dir, double dt, double tol, int maxit,
+                        fgcg_info* info) {
+  if (!c || !cfield || !Dfield) return fail(FGCG_EINVAL, "ctx/c/D is NULL");
+  int rc;
+  if ((rc = check_solver_args(tol, maxit))) return rc;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FGCG_EDOMAIN, "dt <= 0");
+  if (!std::isfinite(c_dir)) return fail(FGCG_EDOMAIN, "c_dir not finite");
+  if ((rc = enter(c))) return rc;
+  const DiffFieldStencil op{Dfield, krate, dirichlet_mask, 1.0 / dt, 1.0 / (c->h * c->h)};
+  Key key;
+  key.add(op.D).add(op.kr).add(op.mask).add(op.inv_dt).add(op.ih2);
+  return diff_step_stencil<double>(c, op, op.inv_dt, 6, key, c_dir, cfield, tol, maxit, info);
 }
 
 int fgcg_staggered_step(fgcg_ctx* c, fgcg_state* s, const fgcg_params* p, fgcg_step_info* info) {
@@ -921,14 +993,16 @@ int fgcg_staggered_step(fgcg_ctx* c, fgcg_state* s, const fgcg_params* p, fgcg_s
   int rc;
   if ((rc = enter(c))) return rc;
   if (p->diffuse) {
-    rc = fgcg_diffusion_step(c, p->mat.phase, p->mat.nphase, p->D_tab, p->k_tab, p->band_width, p->c_dir, p->dt,
-                             s->c, p->tol_diff, p->maxit, &info->diff);
+    rc = fgcg_diffusion_step_phases(c, p->mat.phase, p->mat.nphase, p->D_tab, p->k_tab, p->band_width, p->c_dir,
+                                    p->dt, s->c, p->tol_diff, p->maxit, &info->diff);
     if (rc < 0) return rc;
   }
   const double e_pres = p->n_ramp > 0 ? p->e_ramp * (double)(s->step + 1) / (double)p->n_ramp : 0.0;
-  const double kp = (p->diffuse && p->k_tab) ? p->k_tab[0] : 0.0;
-  hipLaunchKernelGGL(k_precip, dim3(c->npost), dim3(PT), 0, c->stream, p->mat.phase, s->c, s->f, s->e, c->n,
-                     p->dt * kp, p->e_per_f, p->diffuse, e_pres);
+  PhaseTab dtk{};
+  if (p->diffuse && p->k_tab)
+    for (int i = 0; i < p->mat.nphase && i < FGCG_MAX_PHASES; ++i) dtk.a[i] = p->dt * p->k_tab[i];
+  hipLaunchKernelGGL(k_precip, dim3(c->npost), dim3(PT), 0, c->stream, p->mat.phase, s->c, s->f, s->e, c->n, dtk,
+                     p->e_per_f, p->diffuse, e_pres);
   HIPCHK(hipGetLastError());
   rc = fgcg_mech_solve(c, &p->mat, s->d, p->kappa, s->e, p->eps_mac, p->tol_mech, p->maxit, s->strain, nullptr,
                        info->mean_stress, &info->energy, &info->mech);
@@ -968,21 +1042,18 @@ int fgcg_staggered_step(fgcg_ctx* c, fgcg_state* s, const fgcg_params* p, fgcg_s
   return worst;
 }
 
-int fgcg_mech_apply(fgcg_ctx* c, const fgcg_material* mat, const double* d, double kappa, const double* p,
-                    double* q) {
-  if (!c || !p || !q) return fail(FGCG_EINVAL, "ctx/p/q is NULL");
-  if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "the apply hooks are 2D only");
+int fgcg_debug_apply(fgcg_ctx* c, int op, const fgcg_material* mat, const double* d, double kappa,
+                     const double* in, double* out) {
+  if (!c || !in || !out) return fail(FGCG_EINVAL, "ctx/in/out is NULL");
+  if (op != FGCG_OP_MECH_K && op != FGCG_OP_MECH_M) return fail(FGCG_EINVAL, "unknown operator");
   MechMat m;
   int rc;
   if ((rc = make_mech_mat(c, mat, d, kappa, &m))) return rc;
+  if (c->ndim == 3 && m.Efield) return fail(FGCG_EUNSUPPORTED, "per-voxel E fields are 2D only");
   if ((rc = enter(c))) return rc;
-  CT<double>* spec = (CT<double>*)c->spec;
-  MechSrcPro<double> src{m, nullptr, Field<double>{(double*)p, c->n, 0}, {0, 0, 0}, c->nx};
-  if ((rc = launch_row_fwd<double, 3>(c, -1, src, spec))) return rc;
-  MechProj<double> proj{c->Dx, c->Dy, 1.0 / (double)c->n, nullptr};
-  if ((rc = launch_col<double, 3, 4>(c, -1, proj, spec, spec))) return rc;
-  StoreEpi<double, 4> st{Field<double>{q, c->n, 0}, Field<double>{nullptr, c->n, 0}, 1.0, c->nx, nullptr, 0};
-  if ((rc = launch_row_inv<double, 4>(c, -1, st, spec))) return rc;
+  if (c->ndim == 3) rc = debug_apply3(c, op, m, in, out);
+  else rc = c->prec == FGCG_FP64 ? debug_apply_t<double>(c, op, m, in, out) : debug_apply_t<float>(c, op, m, in, out);
+  if (rc) return rc;
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   return FGCG_OK;
@@ -1142,9 +1213,10 @@ int fgcg_batch_create(int nb, const int* nx, const int* ny, double h, int precis
 int fgcg_mech_solve_batched(fgcg_batch* b, const uint8_t* const* phases, int nphase, const double* E_tab,
                             const double* nu_tab, const double* eps_mac, double tol, int maxit,
                             double* const* strains, double* mean_stress, double* energy, fgcg_info* infos) {
-  if (!b || !phases || !eps_mac) return fail(FGCG_EINVAL, "batch/phases/eps_mac is NULL");
+  if (!b || !phases || !eps_mac || !E_tab || !nu_tab) return fail(FGCG_EINVAL, "batch/phases/tables/eps_mac is NULL");
   int rc;
   if ((rc = check_solver_args(tol, maxit))) return rc;
+  if (nphase < 1 || nphase > FGCG_MAX_PHASES) return fail(FGCG_EINVAL, "nphase outside 1..8");
   for (int i = 0; i < b->nb; ++i)
     if (!phases[i]) return fail(FGCG_EINVAL, "phase pointer is NULL");
   const double t0 = now();
@@ -1152,17 +1224,40 @@ int fgcg_mech_solve_batched(fgcg_batch* b, const uint8_t* const* phases, int nph
   hipStream_t st = c0->stream;
   if ((rc = enter(c0))) return rc;
   std::vector<MechMat> mats(b->groups.size());
+  std::vector<std::vector<double>> lm_host(b->groups.size());
   for (size_t g = 0; g < b->groups.size(); ++g) {
     fgcg_ctx* c = b->groups[g];
     const std::vector<int>& mem = b->members[g];
-    fgcg_material mat{c->phase_buf, nphase, E_tab, nu_tab, nullptr, 0.0};
+    // tables of the group's first sample go into the kernel arguments; when the
+    // members' tables differ, each sample's table is read from device memory
+    fgcg_material mat{c->phase_buf, nphase, E_tab + (size_t)nphase * mem[0], nu_tab + (size_t)nphase * mem[0],
+                      nullptr, 0.0};
     if ((rc = make_mech_mat(c, &mat, nullptr, 0.0, &mats[g]))) return rc;
+    bool same = true;
+    std::vector<double>& lh = lm_host[g];
+    lh.assign(16 * mem.size(), 0.0);
+    for (size_t s = 0; s < mem.size(); ++s) {
+      MechMat ms;
+      fgcg_material mi{c->phase_buf, nphase, E_tab + (size_t)nphase * mem[s], nu_tab + (size_t)nphase * mem[s],
+                       nullptr, 0.0};
+      if ((rc = make_mech_mat(c, &mi, nullptr, 0.0, &ms))) return rc;
+      for (int q = 0; q < FGCG_MAX_PHASES; ++q) {
+        lh[16 * s + q] = ms.lm.a[q];
+        lh[16 * s + 8 + q] = ms.lm.b[q];
+        same = same && ms.lm.a[q] == mats[g].lm.a[q] && ms.lm.b[q] == mats[g].lm.b[q];
+      }
+    }
+    if (!same) {
+      HIPCHK(hipMemcpyAsync(c->lm_dev, lh.data(), sizeof(double) * lh.size(), hipMemcpyHostToDevice, st));
+      mats[g].lm_dev = c->lm_dev;
+    }
     std::vector<double> em(3 * mem.size());
     for (size_t s = 0; s < mem.size(); ++s) {
       HIPCHK(hipMemcpyAsync(c->phase_buf + (size_t)c->n * s, phases[mem[s]], (size_t)c->n, hipMemcpyDeviceToDevice,
                             st));
       for (int j = 0; j < 3; ++j) em[3 * s + j] = eps_mac[3 * mem[s] + j];
     }
+    resolve_reference(c, mats[g]);
     if ((rc = tune_passes(c)) || (rc = upload_ems(c, em.data())) || (rc = mech_rhs(c, mats[g], nullptr))) return rc;
     rc = c->prec == FGCG_FP64 ? mech_init<double>(c, mats[g], tol, maxit) : mech_init<float>(c, mats[g], tol, maxit);
     if (rc) return rc;
@@ -1185,6 +1280,7 @@ int fgcg_mech_solve_batched(fgcg_batch* b, const uint8_t* const* phases, int nph
     const int K = c0->prec == FGCG_FP64 ? c0->chunk : 2 * RELIABLE_EVERY;
     Key key = mech_key(c0, mats[0], tol, maxit);
     key.add(K);
+    for (const MechMat& mg : mats) key.add(mg.lm).add(mg.lm_dev);
     for (fgcg_ctx* cg : b->groups) key.add(cg->rows_pick).add(cg->plan_row).add(cg->plan_col);
     if (key.b != b->key || !b->exec[0] || !b->exec[1]) {
       for (auto& e : b->exec)

@@ -4,91 +4,11 @@
 // solves use the stencil CG of the 2D engine, which handles both.
 #include "engine.hpp"
 #include "mech3.hpp"
-#include "passes3d.hpp"
+#include "launch3d.hpp"
 
 namespace fgcg {
 
 namespace {
-
-// Axis lengths of 3D grids.
-#define FGCG_SIZES3(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
-
-template <class F> bool with_n3(int n, F&& f) {
-  switch (n) {
-#define FGCG_CASE3(N)                      \
-  case N:                                  \
-    f(std::integral_constant<int, N>{});   \
-    return true;
-    FGCG_SIZES3(FGCG_CASE3)
-#undef FGCG_CASE3
-    default:
-      return false;
-  }
-}
-
-constexpr int RELIABLE_EVERY3 = 10;  // FP32-mixed: true residual every tenth iteration
-constexpr int KP3_MAX_BLOCKS = 4096;  // blocks of the tiled stiffness pass (partial sums in part_a)
-
-template <typename T> const CT<T>* tw_z(const fgcg_ctx* c) {
-  return (const CT<T>*)(std::is_same<T, double>::value ? c->twz : c->twz32);
-}
-
-Grid3 grid3(const fgcg_ctx* c) { return Grid3{c->nx, c->ny, c->nz, c->n}; }
-
-// Blocks of the slab-walking stencil kernels: a multiple of 8, at most 1024.
-int nslab(const fgcg_ctx* c) {
-  const int rows = c->ny * c->nz;
-  return std::max(8, std::min(1024, rows) & ~7);
-}
-
-template <typename T> int ztiles(const fgcg_ctx* c) {
-  int nty = 0;
-  with_n3(c->nz, [&](auto NZc) {
-    constexpr int YT = ztile_for<T>(decltype(NZc)::value);
-    nty = (c->ny + YT - 1) / YT;
-  });
-  return nty;
-}
-
-template <typename T, int NC>
-int launch_ypass(fgcg_ctx* c, int kind, bool inv, const CgState* st, CT<T>* spec) {
-  int rc = 0;
-  const int nlines = c->nxh * c->nz;
-  with_n3(c->ny, [&](auto NYc) {
-    constexpr int NY = decltype(NYc)::value;
-    constexpr int LPB = ylines_for(NY, NC);
-    dim3 g((nlines + LPB - 1) / LPB);
-    if (kind >= 0) set_kname(c, kind, inv ? "k_ypass<%s, %d, 3, true" : "k_ypass<%s, %d, 3, false", tname<T>(), NY);
-    if (inv)
-      rc = launch(c, kind, (const void*)&k_ypass<T, NY, NC, true>, g, st, spec, nlines, tw_y<T>(c));
-    else
-      rc = launch(c, kind, (const void*)&k_ypass<T, NY, NC, false>, g, st, spec, nlines, tw_y<T>(c));
-  });
-  return rc;
-}
-
-// Blocks of the z pass over ncomp components (zpt_for<T>() tiles per block).
-template <typename T> int zblocks(const fgcg_ctx* c, int ncomp) {
-  return (ncomp * c->nxh * ztiles<T>(c) + zpt_for<T>() - 1) / zpt_for<T>();
-}
-
-template <typename T, bool FWD, bool INV, class Sym>
-int launch_zpass(fgcg_ctx* c, int kind, const Sym& sym, CT<T>* spec, int ncomp) {
-  int rc = 0;
-  const int ntiles = ncomp * c->nxh * ztiles<T>(c);
-  with_n3(c->nz, [&](auto NZc) {
-    constexpr int NZ = decltype(NZc)::value;
-    dim3 g(zblocks<T>(c, ncomp));
-    if (kind >= 0) set_kname(c, kind, "k_zpass<%s, %d", tname<T>(), NZ);
-    rc = launch(c, kind, (const void*)&k_zpass<T, NZ, FWD, INV, Sym>, g, sym, spec, c->nxh, c->ny, ntiles,
-                tw_z<T>(c));
-  });
-  return rc;
-}
-
-int launch_reduce(fgcg_ctx* c, const double* part, int np, double* out) {
-  return launch(c, -1, (const void*)&k_reduce, dim3(1), part, np, out);
-}
 
 template <typename T> Field<T> fld3(void* p, const fgcg_ctx* c) { return Field<T>{(T*)p, c->n, 3 * c->n}; }
 
@@ -104,9 +24,22 @@ int green3(fgcg_ctx* c, const Pro& pro, const CgState* st, bool timed) {
   int r = NOUT == 3 ? launch_row_fwd<T, NOUT>(c, timed ? FGCG_K_MECH_ROW_FWD : -1, pro, spec)
                     : launch_row_fwd<T, NOUT>(c, timed ? FGCG_K_MECH_ROW_FWD : -1, pro, spec, 3, comp_stride3(c));
   r |= launch_ypass<T, 3>(c, timed ? FGCG_K_MECH_Y_FWD : -1, false, st, spec);
-  const Green3<T> g{c->Dx, c->Dy, c->Dz, 1.0 / (double)c->n, c->nx, st, c->part_z};
-  r |= launch_zpass<T, true, true>(c, timed ? FGCG_K_MECH_COL : -1, g, spec, 3);
-  r |= launch_reduce(c, c->part_z, c->nzb, c->red + 1);
+  if (c->precond == 1) {
+    // forward z transforms, the reference-medium solve mode by mode, inverse z
+    const StateSym ss{st};
+    r |= launch_zpass<T, true, false>(c, timed ? FGCG_K_MECH_COL : -1, ss, spec, 3);
+    const long long per = comp_stride3(c);
+    const int nref = (int)std::min<long long>((per + NT - 1) / NT, c->nzb);
+    r |= launch(c, -1, (const void*)&k_ref3<T>, dim3(nref), st, spec, (const double2*)c->Dx, (const double2*)c->Dy,
+                (const double2*)c->Dz, c->use_lam, c->use_mu, 1.0 / (double)c->n, c->nxh, c->ny, c->nz, c->nx,
+                c->part_z);
+    r |= launch_reduce(c, c->part_z, nref, c->red + 1);
+    r |= launch_zpass<T, false, true>(c, -1, ss, spec, 3);
+  } else {
+    const Green3<T> g{c->Dx, c->Dy, c->Dz, 1.0 / (double)c->n, c->nx, st, c->part_z};
+    r |= launch_zpass<T, true, true>(c, timed ? FGCG_K_MECH_COL : -1, g, spec, 3);
+    r |= launch_reduce(c, c->part_z, c->nzb, c->red + 1);
+  }
   r |= launch_ypass<T, 3>(c, timed ? FGCG_K_MECH_Y_INV : -1, true, st, spec);
   return r;
 }
@@ -224,6 +157,7 @@ int alloc3d(fgcg_ctx* c) {
 int mech3_solve(fgcg_ctx* c, const MechMat& m, const double* eig, const double* em, double tol, int maxit,
                 double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
   const double t0 = now();
+  resolve_reference(c, m);
   const Grid3 g = grid3(c);
   const int nb = nslab(c);
   Em6 e6;
@@ -245,7 +179,8 @@ int mech3_solve(fgcg_ctx* c, const MechMat& m, const double* eig, const double* 
   Mech3IterFn it{c, m, tol, maxit};
   const int K = c->prec == FGCG_FP64 ? c->chunk : 2 * RELIABLE_EVERY3;
   Key key;
-  key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm).add(c->prec);
+  key.add(m.phase).add(m.d).add(m.Efield).add(m.lm_dev).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm).add(c->prec);
+  key.add(c->precond).add(c->use_lam).add(c->use_mu);
   key.add(tol).add(maxit);
   if ((rc = run_cg(c, c->prec == FGCG_FP64 ? 0 : 5, key, c->st, c->h_st, it, maxit, K))) return rc;
   const CgState s = *c->h_st;
@@ -268,6 +203,36 @@ int mech3_solve(fgcg_ctx* c, const MechMat& m, const double* eig, const double* 
   if (energy) *energy = 0.5 * c->h * c->h * c->h * acc[6];
   fill_info(info, s, now() - t0);
   return status_of(s);
+}
+
+// Kernel-level hook on 3D grids: q = K p through the tiled stiffness pass of
+// the solver (k_mech3_kpx) or z = M r through the Green passes every solve
+// starts with (x rows, y lines, z tiles with the Green symbol, y lines, x
+// rows writing p = z), in the context's precision.
+template <typename T> int debug_apply3_t(fgcg_ctx* c, int op, const MechMat& m, const double* in, double* out) {
+  const long long n3 = 3 * c->n;
+  int rc;
+  resolve_reference(c, m);
+  if (op == FGCG_OP_MECH_K) {
+    if ((rc = running_state(c))) return rc;
+    const int nkp = std::min(kp3_chunks(c->nx, c->ny, c->nz), KP3_MAX_BLOCKS);
+    hipLaunchKernelGGL((k_convert<T, double>), dim3(c->npost), dim3(PT), 0, c->stream, (T*)c->p, in, n3);
+    hipLaunchKernelGGL((k_mech3_kpx<T, T, false>), dim3(nkp), dim3(NT), 0, c->stream, m, (const T*)c->p, (T*)c->tmp,
+                       (const double*)nullptr, grid3(c), (T)(1.0 / c->h), c->st, c->part_a);
+    hipLaunchKernelGGL((k_convert<double, T>), dim3(c->npost), dim3(PT), 0, c->stream, out, (const T*)c->tmp, n3);
+    HIPCHK(hipGetLastError());
+    return 0;
+  }
+  hipLaunchKernelGGL((k_convert<T, double>), dim3(c->npost), dim3(PT), 0, c->stream, (T*)c->r, in, n3);
+  HIPCHK(hipMemsetAsync(c->p, 0, sizeof(T) * n3, c->stream));  // z = 0 stays if r = 0
+  if ((rc = mech3_init<T>(c, 0.0, 1))) return rc;
+  hipLaunchKernelGGL((k_convert<double, T>), dim3(c->npost), dim3(PT), 0, c->stream, out, (const T*)c->p, n3);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int debug_apply3(fgcg_ctx* c, int op, const MechMat& m, const double* in, double* out) {
+  return c->prec == FGCG_FP64 ? debug_apply3_t<double>(c, op, m, in, out) : debug_apply3_t<float>(c, op, m, in, out);
 }
 
 int history3(fgcg_ctx* c, const MechMat& m0, const double* strain, const double* e, double* H) {

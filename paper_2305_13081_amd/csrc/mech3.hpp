@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(NT) k_mech3_rhs(MechMat m, const double* eig, 
 
 // eps = eps_mac + sym(grad u), sigma = g C : (eps - e I); partial sums of
 // sigma (6) and (eps - e I) : sigma, 7 per block.
-__global__ void __launch_bounds__(NT) k_mech3_post(MechMat m, const double* __restrict__ u, Grid3 g, double ih,
+static __global__ void __launch_bounds__(NT) k_mech3_post(MechMat m, const double* __restrict__ u, Grid3 g, double ih,
                                                    const double* eig, Em6 em, double* strain, double* stress,
                                                    double* part) {
   __shared__ double red[NT / 64];
@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(NT) k_mech3_post(MechMat m, const double* __re
 
 // H = max(H, psi+(eps - e I)) on 3D grids with the undegraded Lame constants:
 // psi+ = K/2 <tr>_+^2 + mu dev:dev, K = lambda + 2 mu / 3.
-__global__ void __launch_bounds__(NT) k_history3(MechMat m, const double* strain, const double* e, double* H,
+static __global__ void __launch_bounds__(NT) k_history3(MechMat m, const double* strain, const double* e, double* H,
                                                  long long n) {
   for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
     double lam, mu;
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(NT) k_history3(MechMat m, const double* strain
 
 // Debug transforms: internal half spectrum [kx][z][y] <-> the usual
 // [z][y][kx] layout of a real-input transform.
-__global__ void __launch_bounds__(NT) k_spec_out(const double2* __restrict__ in, double2* __restrict__ out, int nxh,
+static __global__ void __launch_bounds__(NT) k_spec_out(const double2* __restrict__ in, double2* __restrict__ out, int nxh,
                                                  int ny, int nz) {
   const long long tot = (long long)nxh * ny * nz;
   for (long long o = blockIdx.x * (long long)NT + threadIdx.x; o < tot; o += (long long)gridDim.x * NT) {
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(NT) k_spec_out(const double2* __restrict__ in,
   }
 }
 
-__global__ void __launch_bounds__(NT) k_spec_in(const double2* __restrict__ in, double2* __restrict__ out, int nxh,
+static __global__ void __launch_bounds__(NT) k_spec_in(const double2* __restrict__ in, double2* __restrict__ out, int nxh,
                                                 int ny, int nz) {
   const long long tot = (long long)nxh * ny * nz;
   for (long long o = blockIdx.x * (long long)NT + threadIdx.x; o < tot; o += (long long)gridDim.x * NT) {

@@ -358,17 +358,18 @@ template <typename T, int NC> struct CopyProN {
 };
 
 // Green operator of the unit reference medium with partial sums of r.z, one
-// displacement component per block: the column pass runs over (sample,
-// component) pairs s2 = 2 s + c (component stride nxh ny), and the partial sums
-// of sample s fill part[2 s gridDim.x .. (2 s + 2) gridDim.x).
-template <typename T> struct MechGreen {
+// component per block: the column pass runs over (sample, component) pairs
+// s2 = NC s + c (component stride nxh ny), and the partial sums of sample s
+// fill part[NC s gridDim.x .. NC (s + 1) gridDim.x).  NC = 2: the mechanics
+// displacement; NC = 1: the scalar fluctuation of the diffusion homogenisation.
+template <typename T, int NC = 2> struct MechGreen {
   const double2* Dx;
   const double2* Dy;
   double inv_n;
   int nx;
   const CgState* st;  // nullable
   double* part;       // nullable
-  __device__ bool begin(int s2, double*, double&) const { return st == nullptr || cg_running(st, s2 >> 1); }
+  __device__ bool begin(int s2, double*, double&) const { return st == nullptr || cg_running(st, s2 / NC); }
   // the column pass loads D_y of its modes before the forward transform
   using Pre = double2;
   __device__ Pre pre(int, int ky) const { return Dy[ky]; }
@@ -392,6 +393,63 @@ template <typename T> struct MechGreen {
   }
   __device__ void partial(int s2, double v) const {
     if (part && threadIdx.x == 0) part[(long long)s2 * gridDim.x + blockIdx.x] = v;
+  }
+};
+
+// Green operator of an isotropic reference medium (lam0, mu0), both
+// displacement components of a column in one block: per mode the 2 x 2
+// Hermitian system K0 z_hat = r_hat with
+//     K0(k) = mu0 |D|^2 I + lam0 conj(D) D^T + mu0 D D^H
+// (the stiffness of the homogeneous reference medium in Fourier space; zero at
+// k = 0), solved in closed form in FP64, and the Parseval partial sums of
+// r.z = (1/N) sum_k Re(r_hat^H z_hat) (one per block, blocks of sample s at
+// part[s gridDim.x ..]).  Only lam0 / mu0 matters to the CG; mu0 is taken
+// as 1.
+template <typename T> struct MechRefGreen {
+  const double2* Dx;
+  const double2* Dy;
+  double inv_n;
+  double lam0, mu0;
+  int nx;
+  const CgState* st;  // nullable
+  double* part;       // nullable
+  __device__ bool begin(int s, double*, double&) const { return st == nullptr || cg_running(st, s); }
+  using Pre = double2;
+  __device__ Pre pre(int, int ky) const { return Dy[ky]; }
+  template <typename C>
+  __device__ void mode(int s, int kx, int ky, const C* a, C* b, double& acc, double sc) const {
+    mode_pre(s, kx, ky, Dy[ky], a, b, acc, sc);
+  }
+  template <typename C>
+  __device__ void mode_pre(int, int kx, int, const double2 d2, const C* a, C* b, double& acc, double) const {
+    const double2 d1 = Dx[kx];
+    const double m1 = d1.x * d1.x + d1.y * d1.y, m2 = d2.x * d2.x + d2.y * d2.y;
+    const double n2 = m1 + m2;
+    if (n2 == 0.0) {
+      b[0] = C{(T)0, (T)0};
+      b[1] = C{(T)0, (T)0};
+      return;
+    }
+    const double lm = lam0 + mu0;
+    const double a11 = mu0 * n2 + lm * m1, a22 = mu0 * n2 + lm * m2;
+    // a12 = lam0 conj(D1) D2 + mu0 D1 conj(D2)
+    const double c1r = d1.x * d2.x + d1.y * d2.y, c1i = d1.x * d2.y - d1.y * d2.x;  // conj(D1) D2
+    const double a12r = (lam0 + mu0) * c1r, a12i = (lam0 - mu0) * c1i;
+    const double det = a11 * a22 - (a12r * a12r + a12i * a12i);
+    const double f = inv_n / det;
+    const double r1x = a[0].x, r1y = a[0].y, r2x = a[1].x, r2y = a[1].y;
+    // z1 = (a22 r1 - a12 r2) / det, z2 = (a11 r2 - conj(a12) r1) / det
+    const double z1x = f * (a22 * r1x - (a12r * r2x - a12i * r2y));
+    const double z1y = f * (a22 * r1y - (a12r * r2y + a12i * r2x));
+    const double z2x = f * (a11 * r2x - (a12r * r1x + a12i * r1y));
+    const double z2y = f * (a11 * r2y - (a12r * r1y - a12i * r1x));
+    b[0] = C{(T)z1x, (T)z1y};
+    b[1] = C{(T)z2x, (T)z2y};
+    const double w = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+    acc += w * (r1x * z1x + r1y * z1y + r2x * z2x + r2y * z2y);
+  }
+  __device__ void partial(int s, double v) const {
+    if (part && threadIdx.x == 0) part[(long long)s * gridDim.x + blockIdx.x] = v;
   }
 };
 

@@ -1,13 +1,9 @@
 // Physics functors plugged into the fused 2D passes, CG control state, and
 // the materials.
 //
-// Mechanics in strain form (Sec. 2.3, App. A), used by the operator test hook
-// fgcg_mech_apply: unknown = full displacement gradient F, components
-// [F11, F12, F21, F22] with F_ij = d u_i / d x_j; stress Voigt [s11, s22, s12];
-// sigma = g(d) (lambda tr(e) I + 2 mu e), g = (1-d)^2 + kappa (Sec. 2.4);
-// projection F_ij(k) = D_j(k) sum_l conj(D_l(k)) s_il(k) / |D(k)|^2, zero at
-// |D| = 0, with the forward-difference symbol of Sec. 2.6.  (The mechanics
-// solver iterates on the displacement instead: mech_u.hpp, mech3.hpp.)
+// Materials of the mechanics (Sec. 2.3): isotropic per phase or per voxel,
+// degraded by g = (1-d)^2 + kappa (Sec. 2.4); the solvers themselves are in
+// mech_u.hpp (2D) and mech3.hpp (3D).
 //
 // Phase field (Sec. 2.4, eq. crack-fft): A d = (Gc/(2 l0) + H) d
 // + (Gc l0 / 2) F^-1[|D|^2 F d].
@@ -165,7 +161,9 @@ struct MechMat {
   const uint8_t* phase;
   const double* d;       // nullable
   const double* Efield;  // nullable: per-voxel Young's modulus
+  const double* lm_dev;  // nullable: per-sample tables [s][lambda[8], mu[8]] (batches)
   long long ss;          // per-sample stride of the scalar fields
+  int nphase;            // entries of lm in use (0 with Efield)
   double kappa;
   double lam_per_E, mu_per_E;  // used with Efield
   PhaseTab lm;                 // a = lambda, b = mu per phase
@@ -174,6 +172,10 @@ struct MechMat {
       const double E = Efield[s * ss + i];
       lam = E * lam_per_E;
       mu = E * mu_per_E;
+    } else if (lm_dev) {
+      const int ph = phase[s * ss + i];
+      lam = lm_dev[16 * s + ph];
+      mu = lm_dev[16 * s + 8 + ph];
     } else {
       pick(lm, phase[s * ss + i], lam, mu);
     }
@@ -194,59 +196,6 @@ __device__ __forceinline__ void stress2(double lam, double mu, T e11, T e22, T e
   sg[1] = l * tr + m2 * e22;
   sg[2] = m2 * e12;
 }
-
-// ------------------------------------------------------------- mechanics
-// Stress of (eps_mac - e I) [rhs] or of sym(v) for a given full gradient v [apply].
-template <typename T> struct MechSrcPro {
-  MechMat m;
-  const double* eig;  // nullable, scalar eigenstrain
-  Field<T> v;         // used when v.p != nullptr
-  double em[3];
-  int nx;
-  __device__ bool begin(int, double*, double&) const { return true; }
-  __device__ void point(int s, int y, int x, T* out, double&, double) const {
-    const long long i = (long long)y * nx + x;
-    double lam, mu;
-    m.get(s, i, lam, mu);
-    if (v.p) {
-      stress2<T>(lam, mu, v.at(s, 0, i), v.at(s, 3, i), (T)0.5 * (v.at(s, 1, i) + v.at(s, 2, i)), out);
-    } else {
-      const double e = eig ? eig[m.ss * s + i] : 0.0;
-      stress2<T>(lam, mu, (T)(em[0] - e), (T)(em[1] - e), (T)em[2], out);
-    }
-  }
-  __device__ void partial(int, double) const {}
-};
-
-template <typename T> struct MechProj {
-  const double2* Dx;  // [nx/2+1]
-  const double2* Dy;  // [ny]
-  double inv_n;
-  const CgState* st;  // nullable
-  __device__ bool begin(int s, double*, double&) const { return st == nullptr || cg_running(st, s); }
-  template <typename C>
-  __device__ void mode(int, int kx, int ky, const C* a, C* b, double&, double) const {
-    const double2 d1 = Dx[kx], d2 = Dy[ky];
-    const double n2 = d1.x * d1.x + d1.y * d1.y + d2.x * d2.x + d2.y * d2.y;
-    if (n2 == 0.0) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) b[q] = C{(T)0, (T)0};
-      return;
-    }
-    const C D1 = C{(T)d1.x, (T)d1.y}, D2 = C{(T)d2.x, (T)d2.y};
-    const T sc = (T)(inv_n / n2);
-    // t_i = sum_l conj(D_l) s_il ; s = [s11, s22, s12]
-    C t1 = cadd(cmul(cconj(D1), a[0]), cmul(cconj(D2), a[2]));
-    C t2 = cadd(cmul(cconj(D1), a[2]), cmul(cconj(D2), a[1]));
-    t1 = C{t1.x * sc, t1.y * sc};
-    t2 = C{t2.x * sc, t2.y * sc};
-    b[0] = cmul(t1, D1);
-    b[1] = cmul(t1, D2);
-    b[2] = cmul(t2, D1);
-    b[3] = cmul(t2, D2);
-  }
-  __device__ void partial(int, double) const {}
-};
 
 // out = sign * q ; optionally x = 0 ; partial |out|^2 into part
 template <typename T, int NC> struct StoreEpi {

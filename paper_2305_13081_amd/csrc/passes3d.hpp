@@ -27,7 +27,7 @@ template <typename T> constexpr int ztile_for(int nz) {
 }
 
 // Deterministic single-block sum of np partial sums into out[0].
-__global__ void __launch_bounds__(NT) k_reduce(const double* __restrict__ part, int np, double* out) {
+static __global__ void __launch_bounds__(NT) k_reduce(const double* __restrict__ part, int np, double* out) {
   __shared__ double red[NT / 64];
   const double t = block_sum_array<16>(part, np, red);  // up to 4096 partials: one round of loads
   if (threadIdx.x == 0) out[0] = t;
@@ -181,6 +181,92 @@ template <typename T> struct Green3 {
     if (part && threadIdx.x == 0) part[blockIdx.x] = v;
   }
 };
+
+// Identity symbol that skips the pass once the CG solve has ended (st
+// nullable: never skip).
+struct StateSym {
+  const CgState* st;
+  __device__ bool begin() const { return st == nullptr || cg_running(st, 0); }
+  template <typename C> __device__ C mode(int, int, int, C a, double&) const { return a; }
+  __device__ void partial(double) const {}
+};
+
+// Green operator of an isotropic reference medium (lam0, mu0) on the 3D half
+// spectrum [comp][kx][z][y] of the three displacement components: per mode
+// the Hermitian positive definite system
+//     K0(k) z_hat = r_hat,  K0 = mu0 |D|^2 I + lam0 conj(D) D^T + mu0 D D^H
+// (zero at k = 0), solved by a 3 x 3 Cholesky factorisation in FP64, with
+// the 1/N of the inverse transform folded in and the Parseval partial sum of
+// r.z (weight 2 except on the kx = 0 and Nyquist planes), one per block.
+struct Cd {
+  double x, y;
+};
+__device__ __forceinline__ Cd cd_mul(Cd a, Cd b) { return Cd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ Cd cd_conj_mul(Cd a, Cd b) { return Cd{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x}; }
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_ref3(const CgState* st, typename cvec<T>::type* spec,
+                                             const double2* __restrict__ Dx, const double2* __restrict__ Dy,
+                                             const double2* __restrict__ Dz, double lam0, double mu0, double inv_n,
+                                             int nxh, int ny, int nz, int nx, double* part) {
+  using C = typename cvec<T>::type;
+  __shared__ double red[NT / 64];
+  if (st && !cg_running(st, 0)) return;
+  const long long per = (long long)nxh * nz * ny;
+  double acc = 0.0;
+  for (long long o = blockIdx.x * (long long)NT + threadIdx.x; o < per; o += (long long)gridDim.x * NT) {
+    const int y = (int)(o % ny);
+    const long long rz = o / ny;
+    const int z = (int)(rz % nz), kx = (int)(rz / nz);
+    const double2 d1 = Dx[kx], d2 = Dy[y], d3 = Dz[z];
+    const Cd D[3] = {{d1.x, d1.y}, {d2.x, d2.y}, {d3.x, d3.y}};
+    const double n2 = D[0].x * D[0].x + D[0].y * D[0].y + D[1].x * D[1].x + D[1].y * D[1].y + D[2].x * D[2].x +
+                      D[2].y * D[2].y;
+    C* v[3] = {spec + o, spec + per + o, spec + 2 * per + o};
+    if (n2 == 0.0) {
+      for (int a = 0; a < 3; ++a) *v[a] = C{(T)0, (T)0};
+      continue;
+    }
+    // A_ij = mu0 n2 d_ij + lam0 conj(D_i) D_j + mu0 D_i conj(D_j), lower triangle
+    Cd A[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j <= i; ++j) {
+        const Cd a = cd_conj_mul(D[i], D[j]);  // conj(D_i) D_j
+        // D_i conj(D_j) = conj(conj(D_i) D_j)
+        A[i][j] = Cd{(lam0 + mu0) * a.x + (i == j ? mu0 * n2 : 0.0), (lam0 - mu0) * a.y};
+      }
+    // Cholesky A = L L^H (real positive diagonal)
+    const double l11 = sqrt(A[0][0].x);
+    const Cd l21{A[1][0].x / l11, A[1][0].y / l11}, l31{A[2][0].x / l11, A[2][0].y / l11};
+    const double l22 = sqrt(A[1][1].x - (l21.x * l21.x + l21.y * l21.y));
+    const Cd t32 = cd_mul(l31, Cd{l21.x, -l21.y});  // l31 conj(l21)
+    const Cd l32{(A[2][1].x - t32.x) / l22, (A[2][1].y - t32.y) / l22};
+    const double l33 = sqrt(A[2][2].x - (l31.x * l31.x + l31.y * l31.y) - (l32.x * l32.x + l32.y * l32.y));
+    const Cd r[3] = {{(double)v[0]->x, (double)v[0]->y}, {(double)v[1]->x, (double)v[1]->y},
+                     {(double)v[2]->x, (double)v[2]->y}};
+    // L w = r
+    const Cd w1{r[0].x / l11, r[0].y / l11};
+    const Cd u2 = cd_mul(l21, w1);
+    const Cd w2{(r[1].x - u2.x) / l22, (r[1].y - u2.y) / l22};
+    const Cd u31 = cd_mul(l31, w1), u32 = cd_mul(l32, w2);
+    const Cd w3{(r[2].x - u31.x - u32.x) / l33, (r[2].y - u31.y - u32.y) / l33};
+    // L^H z = w
+    const Cd z3{w3.x / l33, w3.y / l33};
+    const Cd e32 = cd_conj_mul(l32, z3);  // conj(l32) z3
+    const Cd z2{(w2.x - e32.x) / l22, (w2.y - e32.y) / l22};
+    const Cd e21 = cd_conj_mul(l21, z2), e31 = cd_conj_mul(l31, z3);
+    const Cd z1{(w1.x - e21.x - e31.x) / l11, (w1.y - e21.y - e31.y) / l11};
+    const Cd zz[3] = {z1, z2, z3};
+    const double wgt = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+    for (int a = 0; a < 3; ++a) {
+      const double zx = zz[a].x * inv_n, zy = zz[a].y * inv_n;
+      acc += wgt * (r[a].x * zx + r[a].y * zy);
+      *v[a] = C{(T)zx, (T)zy};
+    }
+  }
+  const double t = block_sum(acc, red);
+  if (part && threadIdx.x == 0) part[blockIdx.x] = t;
+}
 
 // Identity symbol (the debug transforms).
 struct NoSym {

@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(PT) k_convert(TO* out, const TI* in, long long
     out[i] = (TO)in[i];
 }
 
-// c = c_dir on the band, x elsewhere
+// c = c_dir on the band, x elsewhere (spectral diffusion step)
 template <typename T>
 __global__ void __launch_bounds__(PT) k_diff_finish(double* c, const T* x, long long n, int nx,
                                                     int band, double c_dir) {
@@ -61,19 +61,24 @@ __global__ void __launch_bounds__(PT) k_diff_finish(double* c, const T* x, long 
 // Empty kernel (the event-gap calibration of the profiling hooks).
 static __global__ void __launch_bounds__(NT) k_noop(int) {}
 
-// Precipitation in the pores (phase 0): f = min(1, f + dt k c); e = e_per_f f.
-// With diffuse = 0 the eigenstrain follows the prescribed ramp value e_pres.
+// Precipitation (first-order, the same rate as the sink of the diffusion
+// step): f = min(1, f + dt k(phase) c) wherever the phase's rate k is
+// positive (f unchanged elsewhere); e = e_per_f f (eq. eigen-simplify with a
+// linear precipitate-to-strain map).  With diffuse = 0 the eigenstrain of the
+// pores (phase 0) follows the prescribed ramp value e_pres instead.
 static __global__ void __launch_bounds__(PT) k_precip(const uint8_t* phase, const double* c, double* f,
-                                               double* e, long long n, double dtk, double e_per_f,
+                                               double* e, long long n, PhaseTab dtk, double e_per_f,
                                                int diffuse, double e_pres) {
   for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT) {
-    const bool pore = phase[i] == 0;
+    const int ph = phase[i];
     if (diffuse) {
-      const double fv = pore ? fmin(1.0, f[i] + dtk * c[i]) : 0.0;
+      double rate, unused;
+      pick(dtk, ph, rate, unused);
+      const double fv = rate > 0.0 ? fmin(1.0, f[i] + rate * c[i]) : f[i];
       f[i] = fv;
-      e[i] = pore ? e_per_f * fv : 0.0;
+      e[i] = e_per_f * fv;
     } else {
-      e[i] = pore ? e_pres : 0.0;
+      e[i] = ph == 0 ? e_pres : 0.0;
     }
   }
 }

@@ -66,6 +66,8 @@ struct PfStencil {
   const double* H;
   double a;     // Gc / (2 l0)
   double cih2;  // (Gc l0 / 2) / h^2
+  __device__ __forceinline__ bool fixed(long long, int) const { return false; }
+  __device__ __forceinline__ bool has_fixed() const { return false; }
   struct Coef {
     double h;
   };
@@ -90,6 +92,9 @@ struct DiffStencil {
   DiffCoef co;
   const uint8_t* phase;
   double ih2;
+  // Dirichlet voxels: the band x < co.band
+  __device__ __forceinline__ bool fixed(long long, int x) const { return x < co.band; }
+  __device__ __forceinline__ bool has_fixed() const { return co.band > 0; }
   __device__ __forceinline__ double D(long long j) const {
     double d, kr;
     pick(co.dk, phase[j], d, kr);
@@ -124,11 +129,43 @@ struct DiffStencil {
   }
 };
 
+// Diffusion step with per-voxel fields (Sec. 2.1 defines D point by point):
+// D and the first-order rate k_r are device arrays, the Dirichlet voxels are
+// those with mask != 0 (no mask: none).
+struct DiffFieldStencil {
+  const double* D;
+  const double* kr;       // nullable: no sink
+  const uint8_t* mask;    // nullable: no Dirichlet voxels
+  double inv_dt;
+  double ih2;
+  __device__ __forceinline__ bool fixed(long long i, int) const { return mask != nullptr && mask[i] != 0; }
+  __device__ __forceinline__ bool has_fixed() const { return mask != nullptr; }
+  struct Coef {
+    double d0, dxm, dym, dzm, k;
+  };
+  __device__ __forceinline__ Coef coef(const Nbr& b) const {
+    return Coef{D[b.i], D[b.ixm], D[b.iym], b.three ? D[b.izm] : 0.0, kr ? kr[b.i] : 0.0};
+  }
+  __device__ __forceinline__ double apply_coef(const Coef& c, const Nbr& b, double v0, const double* vn) const {
+    double flux = c.dxm * (v0 - vn[0]) - c.d0 * (vn[1] - v0) + c.dym * (v0 - vn[2]) - c.d0 * (vn[3] - v0);
+    if (b.three) flux = flux + c.dzm * (v0 - vn[4]) - c.d0 * (vn[5] - v0);
+    return (inv_dt + c.k) * v0 + ih2 * flux;
+  }
+  __device__ __forceinline__ double apply_vals(const Nbr& b, double v0, const double* vn) const {
+    return apply_coef(coef(b), b, v0, vn);
+  }
+  template <typename V>
+  __device__ __forceinline__ double apply(double v0, const V& v, const Nbr& b) const {
+    const double vn[6] = {v(b.ixm, b.xm), v(b.ixp, b.xp), v(b.iym, b.x), v(b.iyp, b.x),
+                          b.three ? v(b.izm, b.x) : 0.0, b.three ? v(b.izp, b.x) : 0.0};
+    return apply_vals(b, v0, vn);
+  }
+};
+
 // k_scg_upd and k_scg_init walk the rows (z ny + y) in XCD slabs (SlabIter);
 // their grid is one-dimensional with a multiple of 8 blocks.
 
-// First pass of iteration k.  band > 0: voxels with x < band are fixed
-// (p = q = 0 there).
+// First pass of iteration k.  Dirichlet voxels (op.fixed) keep p = q = 0.
 // p is double-buffered (pin -> pout): the direction at the neighbours is formed
 // from the previous p, which other threads of this launch must not overwrite.
 //
@@ -146,7 +183,7 @@ inline int scg_chunks(int nx, int ny, int nz) {
 template <typename T, class Op>
 __global__ void __launch_bounds__(NT) k_scg_dir(Op op, const T* __restrict__ r, const T* __restrict__ pin,
                                                 T* __restrict__ pout, T* __restrict__ q, int nx, int ny, int nz,
-                                                int band, CgCtl cc) {
+                                                CgCtl cc) {
   constexpr int HX = SC_TX + 2, HY = SC_TY + 2, HP = HX * HY;
   constexpr int RPT = SC_TY / (NT / SC_TX);  // own rows per thread
   __shared__ double pl[2][HP];
@@ -220,7 +257,7 @@ __global__ void __launch_bounds__(NT) k_scg_dir(Op op, const T* __restrict__ r, 
           const double vn[6] = {P[hp - 1], P[hp + 1], P[hp - HX], P[hp + HX], three ? pm[k] : 0.0,
                                 three ? pl[cur ^ 1][hp] : 0.0};
           const Nbr& nb = nbr[k];
-          const double qv = xo < band ? 0.0 : op.apply_coef(cf[k], nb, v0, vn);
+          const double qv = op.fixed(nb.i, xo) ? 0.0 : op.apply_coef(cf[k], nb, v0, vn);
           pout[nb.i] = (T)v0;
           q[nb.i] = (T)qv;
           acc += v0 * qv;
@@ -254,25 +291,26 @@ __global__ void __launch_bounds__(NT) k_scg_upd(T* __restrict__ x, T* __restrict
   if (threadIdx.x == 0) cc.part_rr[block_linear()] = t;
 }
 
-// Initial residual r = b - A x0 with x0 = xin (mask band), partial sums of
-// ||b||^2 and r.r (k_cg_init then sets the state).  b = bsrc: the phase field passes H; the diffusion step
-// passes c^n / dt on the free voxels, with A applied to c~ (c^n, band = c_dir)
+// Initial residual r = b - A x0 with x0 = xin (zero on the Dirichlet voxels),
+// partial sums of ||b||^2 and r.r (k_cg_init then sets the state).
+// b = bsrc: the phase field passes H; the diffusion step passes c^n / dt on
+// the free voxels, with A applied to c~ (c^n, c_dir on the Dirichlet voxels)
 // and b_F = M(c^n/dt - A c_B).
 template <typename T, class Op>
 __global__ void __launch_bounds__(NT) k_scg_init(Op op, const double* __restrict__ xin, double bscale,
-                                                 const double* __restrict__ bsrc, int band, double c_dir,
+                                                 const double* __restrict__ bsrc, double c_dir,
                                                  T* __restrict__ x, T* __restrict__ r, int nx, int ny, int nz,
                                                  double* part_b, double* part_rr) {
   __shared__ double red[NT / 64];
-  auto vt = [&](long long j, int xx) -> double { return xx < band ? c_dir : xin[j]; };
-  auto vb = [&](long long, int xx) -> double { return xx < band ? c_dir : 0.0; };
+  auto vt = [&](long long j, int xx) -> double { return op.fixed(j, xx) ? c_dir : xin[j]; };
+  auto vb = [&](long long j, int xx) -> double { return op.fixed(j, xx) ? c_dir : 0.0; };
   double acc[2] = {0.0, 0.0};
   const SlabIter it(nx, (long long)ny * nz);
   for (long long v = it.v0; v < it.v1; v += it.step) {
     const int row = (int)((unsigned)v / (unsigned)nx), xx = (int)(v - (long long)row * nx);
     const Nbr nb = nbrs(row, xx, nx, ny, nz);
     const long long i = nb.i;
-    if (xx < band) {
+    if (op.fixed(i, xx)) {
       x[i] = (T)0;
       r[i] = (T)0;
       continue;
@@ -280,7 +318,7 @@ __global__ void __launch_bounds__(NT) k_scg_init(Op op, const double* __restrict
     const double b = bscale * bsrc[i];
     const double ax = op.apply(vt(i, xx), vt, nb);
     double bf = b;
-    if (band > 0) bf = b - op.apply(0.0, vb, nb);
+    if (op.has_fixed()) bf = b - op.apply(0.0, vb, nb);
     const double res = b - ax;
     x[i] = (T)xin[i];
     r[i] = (T)res;
@@ -292,6 +330,13 @@ __global__ void __launch_bounds__(NT) k_scg_init(Op op, const double* __restrict
     part_b[block_linear()] = t0;
     part_rr[block_linear()] = t1;
   }
+}
+
+// c = c_dir on the Dirichlet voxels, x elsewhere
+template <typename T, class Op>
+__global__ void __launch_bounds__(NT) k_scg_finish(Op op, double* c, const T* x, long long n, int nx, double c_dir) {
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+    c[i] = op.fixed(i, (int)(i % nx)) ? c_dir : (double)x[i];
 }
 
 }  // namespace fgcg

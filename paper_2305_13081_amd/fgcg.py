@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfgcg.so")
 FGCG_OK, FGCG_NOT_CONVERGED = 0, 1
 FP64, FP32_MIXED = 0, 1
 J_USER, J_ENERGY, J_C11 = 0, 1, 2
+OP_MECH_K, OP_MECH_M = 0, 1
 MAX_PHASES = 8
 KINDS = {
     "mech_row_fwd": 0, "mech_col": 1, "mech_row_inv": 2,
@@ -90,6 +91,7 @@ _SIGS = {
     "fgcg_last_error": (ctypes.c_char_p, []),
     "fgcg_set_option": (_ip, [_vp, _ip, _ip]),
     "fgcg_get_option": (_ip, [_vp, _ip, ctypes.POINTER(ctypes.c_int)]),
+    "fgcg_set_reference": (_ip, [_vp, ctypes.c_double, ctypes.c_double]),
     "fgcg_mech_solve": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _dp, ctypes.c_double, _ip,
                               _vp, _vp, _dp, _dp, ctypes.POINTER(Info)]),
     "fgcg_mech_adjoint": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _dp, _vp, _ip,
@@ -101,10 +103,15 @@ _SIGS = {
                                       ctypes.POINTER(_vp), _dp, _dp, ctypes.POINTER(Info)]),
     "fgcg_phasefield_solve": (_ip, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, ctypes.c_double, _ip,
                                     ctypes.POINTER(Info)]),
-    "fgcg_diffusion_step": (_ip, [_vp, _vp, _ip, _dp, _dp, _ip, ctypes.c_double, ctypes.c_double, _vp,
-                                  ctypes.c_double, _ip, ctypes.POINTER(Info)]),
+    "fgcg_diffusion_step": (_ip, [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _ip,
+                                  ctypes.POINTER(Info)]),
+    "fgcg_diffusion_step_phases": (_ip, [_vp, _vp, _ip, _dp, _dp, _ip, ctypes.c_double, ctypes.c_double, _vp,
+                                         ctypes.c_double, _ip, ctypes.POINTER(Info)]),
+    "fgcg_diffusion_homogenize": (_ip, [_vp, _vp, _dp, ctypes.c_double, _ip, _vp, _vp, _dp, ctypes.POINTER(Info)]),
+    "fgcg_diffusivity_eff": (_ip, [_vp, _vp, ctypes.c_double, _ip, _dp, ctypes.POINTER(Info)]),
+    "fgcg_concentration": (_ip, [_vp, _vp, _vp, _dp, ctypes.c_double, _vp, _dp]),
     "fgcg_staggered_step": (_ip, [_vp, ctypes.POINTER(State), ctypes.POINTER(Params), ctypes.POINTER(StepInfo)]),
-    "fgcg_mech_apply": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _vp]),
+    "fgcg_debug_apply": (_ip, [_vp, _ip, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _vp]),
     "fgcg_phasefield_apply": (_ip, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]),
     "fgcg_diffusion_apply": (_ip, [_vp, _vp, _ip, _dp, _dp, ctypes.c_double, _vp, _vp]),
     "fgcg_debug_fft": (_ip, [_vp, _ip, _vp, _vp]),
@@ -182,10 +189,14 @@ class Context:
         except Exception:
             pass
 
-    OPTIONS = {"scalar_spectral": 0, "graphs": 1, "chunk": 2, "rows": 3, "row_plan": 4, "col_plan": 5}
+    OPTIONS = {"scalar_spectral": 0, "graphs": 1, "chunk": 2, "rows": 3, "row_plan": 4, "col_plan": 5, "precond": 6}
 
     def set_option(self, name, value):
         _check(self.lib.fgcg_set_option(self.ptr, self.OPTIONS[name], int(value)), "fgcg_set_option")
+
+    def set_reference(self, lam0=0.0, mu0=0.0):
+        """Reference medium of the "precond" = 1 option ((0, 0): automatic)."""
+        _check(self.lib.fgcg_set_reference(self.ptr, float(lam0), float(mu0)), "fgcg_set_reference")
 
     def get_option(self, name):
         v = ctypes.c_int()
@@ -267,15 +278,16 @@ class Context:
                     info=info.as_dict())
 
     def mech_adjoint(self, E_field, nu, eps_mac, objective=J_ENERGY, dJ_dstrain=None, d=None, kappa=0.0,
-                     eig=None, tol=1e-12, maxit=50000, phase=None, E_tab=None, nu_tab=None):
+                     eig=None, tol=1e-12, maxit=50000, phase=None, E_tab=None, nu_tab=None, want_grad=True):
         """dJ/dE per voxel.  With E_field given the material is (E_field, nu);
-        otherwise (phase, E_tab, nu_tab).  Returns (grad_E, J, info_fwd, info_adj)."""
+        otherwise (phase, E_tab, nu_tab).  Returns (grad_E, J, info_fwd,
+        info_adj); want_grad=False runs the forward solve only (grad_E None)."""
         torch = _torch()
         m, keep = self._material(phase, E_tab, nu_tab, E_field, nu)
         self._t(d, "d", torch.float64, allow_none=True)
         self._t(eig, "eig", torch.float64, allow_none=True)
         self._t(dJ_dstrain, "dJ_dstrain", torch.float64, comps=3, allow_none=True)
-        grad = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        grad = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device) if want_grad else None
         J = ctypes.c_double(0.0)
         i1, i2 = Info(), Info()
         self._sync_stream()
@@ -298,19 +310,76 @@ class Context:
         _check(st, "fgcg_phasefield_solve", allow_nc=True)
         return info.as_dict()
 
-    def diffusion_step(self, phase, D_tab, k_tab, band_width, c_dir, dt, c, tol=1e-10, maxit=20000):
+    def diffusion_step(self, c, Dfield, dt, krate=None, mask=None, c_dir=0.0, tol=1e-10, maxit=20000):
+        """One implicit step with per-voxel D (float64), optional rate field
+        (float64) and Dirichlet mask (uint8, nonzero = fixed at c_dir)."""
+        torch = _torch()
+        self._t(c, "c", torch.float64)
+        self._t(Dfield, "Dfield", torch.float64)
+        self._t(krate, "krate", torch.float64, allow_none=True)
+        self._t(mask, "mask", torch.uint8, allow_none=True)
+        info = Info()
+        self._sync_stream()
+        st = self.lib.fgcg_diffusion_step(self.ptr, self._ptr(c), self._ptr(Dfield), self._ptr(krate), self._ptr(mask),
+                                          float(c_dir), float(dt), float(tol), int(maxit), ctypes.byref(info))
+        _check(st, "fgcg_diffusion_step", allow_nc=True)
+        return info.as_dict()
+
+    def diffusion_step_phases(self, phase, D_tab, k_tab, band_width, c_dir, dt, c, tol=1e-10, maxit=20000):
         torch = _torch()
         self._t(phase, "phase", torch.uint8)
         self._t(c, "c", torch.float64)
         if len(D_tab) != len(k_tab) or not 1 <= len(D_tab) <= MAX_PHASES:
-            raise FgcgError(-1, "diffusion_step", "D_tab/k_tab must have equal length 1..8")
+            raise FgcgError(-1, "diffusion_step_phases", "D_tab/k_tab must have equal length 1..8")
         info = Info()
         self._sync_stream()
-        st = self.lib.fgcg_diffusion_step(self.ptr, self._ptr(phase), len(D_tab), _dvec(D_tab), _dvec(k_tab),
-                                          int(band_width), float(c_dir), float(dt), self._ptr(c), float(tol),
-                                          int(maxit), ctypes.byref(info))
-        _check(st, "fgcg_diffusion_step", allow_nc=True)
+        st = self.lib.fgcg_diffusion_step_phases(self.ptr, self._ptr(phase), len(D_tab), _dvec(D_tab), _dvec(k_tab),
+                                                 int(band_width), float(c_dir), float(dt), self._ptr(c), float(tol),
+                                                 int(maxit), ctypes.byref(info))
+        _check(st, "fgcg_diffusion_step_phases", allow_nc=True)
         return info.as_dict()
+
+    def diffusion_homogenize(self, Dfield, grad_cmac, tol=1e-10, maxit=20000, want_fields=True):
+        """Static homogenisation: returns grad_c (dim, *grid), phi, the mean
+        flux and the CG info."""
+        torch = _torch()
+        self._t(Dfield, "Dfield", torch.float64)
+        dim = self.ndim
+        if len(grad_cmac) != dim:
+            raise FgcgError(-1, "diffusion_homogenize", f"grad_cmac needs {dim} components")
+        gc = torch.empty((dim,) + self.shape, dtype=torch.float64, device=self.device) if want_fields else None
+        phi = torch.empty(self.shape, dtype=torch.float64, device=self.device) if want_fields else None
+        mf = (ctypes.c_double * dim)()
+        info = Info()
+        self._sync_stream()
+        st = self.lib.fgcg_diffusion_homogenize(self.ptr, self._ptr(Dfield), _dvec(grad_cmac), float(tol), int(maxit),
+                                                self._ptr(gc), self._ptr(phi), mf, ctypes.byref(info))
+        _check(st, "fgcg_diffusion_homogenize", allow_nc=True)
+        return dict(grad_c=gc, phi=phi, mean_flux=np.array(list(mf)), info=info.as_dict())
+
+    def diffusivity_eff(self, Dfield, tol=1e-10, maxit=20000):
+        torch = _torch()
+        self._t(Dfield, "Dfield", torch.float64)
+        dim = self.ndim
+        D = (ctypes.c_double * (dim * dim))()
+        infos = (Info * dim)()
+        self._sync_stream()
+        st = self.lib.fgcg_diffusivity_eff(self.ptr, self._ptr(Dfield), float(tol), int(maxit), D, infos)
+        _check(st, "fgcg_diffusivity_eff", allow_nc=True)
+        return np.array(list(D)).reshape(dim, dim), [i.as_dict() for i in infos]
+
+    def concentration(self, phase, grad_c, grad_cmac, c_mac):
+        """c(x) from a concentration-gradient field (eq. concentration-correct);
+        returns (c, beta_pore, beta_solid)."""
+        torch = _torch()
+        self._t(phase, "phase", torch.uint8)
+        self._t(grad_c, "grad_c", torch.float64, comps=self.ndim)
+        c = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        beta = (ctypes.c_double * 2)()
+        self._sync_stream()
+        _check(self.lib.fgcg_concentration(self.ptr, self._ptr(phase), self._ptr(grad_c), _dvec(grad_cmac),
+                                           float(c_mac), self._ptr(c), beta), "fgcg_concentration")
+        return c, beta[0], beta[1]
 
     def new_state(self, band_width=0, c_dir=1.0):
         torch = _torch()
@@ -366,15 +435,19 @@ class Context:
         _check(self.lib.fgcg_debug_fft(self.ptr, -1 if inverse else 1, self._ptr(x), self._ptr(out)),
                "fgcg_debug_fft")
         return out
-    def mech_apply(self, phase, E_tab, nu_tab, p, d=None, kappa=0.0, E_field=None, nu_field=0.2):
+    def debug_apply(self, op, phase, E_tab, nu_tab, v, d=None, kappa=0.0, E_field=None, nu_field=0.2):
+        """One application of the solver's K (op OP_MECH_K) or M (OP_MECH_M)
+        to a displacement-like float64 field v of shape (n_u, *grid)."""
         torch = _torch()
         m, keep = self._material(phase, E_tab, nu_tab, E_field, nu_field)
-        self._t(p, "p", torch.float64, comps=4)
+        nu = self.ndim
+        self._t(v, "v", torch.float64, comps=nu)
         self._t(d, "d", torch.float64, allow_none=True)
-        q = torch.empty_like(p)
+        q = torch.empty_like(v)
         self._sync_stream()
-        _check(self.lib.fgcg_mech_apply(self.ptr, ctypes.byref(m), self._ptr(d), float(kappa), self._ptr(p),
-                                        self._ptr(q)), "fgcg_mech_apply")
+        _check(self.lib.fgcg_debug_apply(self.ptr, int(op), ctypes.byref(m), self._ptr(d), float(kappa), self._ptr(v),
+                                         self._ptr(q)), "fgcg_debug_apply")
+        del keep
         return q
 
     def phasefield_apply(self, H, Gc, l0, v):
@@ -460,8 +533,15 @@ class Batch:
             if not (isinstance(ph, torch.Tensor) and ph.dtype == torch.uint8 and ph.device == self.device
                     and tuple(ph.shape) == (ny, nx) and ph.is_contiguous()):
                 raise FgcgError(-1, "Batch.mech_solve", f"phase must be a contiguous uint8 ({ny}, {nx}) tensor")
-        if not (1 <= len(E_tab) <= MAX_PHASES and len(E_tab) == len(nu_tab)):
-            raise FgcgError(-1, "Batch.mech_solve", "E_tab/nu_tab must have equal length 1..8")
+        # one table for every sample, or one row per sample
+        per = isinstance(E_tab[0], (list, tuple, np.ndarray))
+        Et = [list(r) for r in E_tab] if per else [list(E_tab)] * self.nb
+        Nt = [list(r) for r in nu_tab] if per else [list(nu_tab)] * self.nb
+        if len(Et) != self.nb or len(Nt) != self.nb:
+            raise FgcgError(-1, "Batch.mech_solve", "per-sample tables need one row per sample")
+        nph = len(Et[0])
+        if not (1 <= nph <= MAX_PHASES and all(len(r) == nph for r in Et + Nt)):
+            raise FgcgError(-1, "Batch.mech_solve", "E_tab/nu_tab rows must have equal length 1..8")
         strains = [torch.empty((3, ny, nx), dtype=torch.float64, device=self.device) for nx, ny in self.sizes] \
             if want_strain else None
         ph = (_vp * self.nb)(*[p.data_ptr() for p in phases])
@@ -470,8 +550,9 @@ class Batch:
         mean = (ctypes.c_double * (3 * self.nb))()
         en = (ctypes.c_double * self.nb)()
         infos = (Info * self.nb)()
-        st = self.lib.fgcg_mech_solve_batched(self.ptr, ph, len(E_tab), _dvec(E_tab), _dvec(nu_tab), em, float(tol),
-                                              int(maxit), sp, mean, en, infos)
+        st = self.lib.fgcg_mech_solve_batched(self.ptr, ph, nph, _dvec([v for r in Et for v in r]),
+                                              _dvec([v for r in Nt for v in r]), em, float(tol), int(maxit), sp, mean,
+                                              en, infos)
         _check(st, "fgcg_mech_solve_batched", allow_nc=True)
         return dict(strains=strains, mean_stress=np.array(list(mean)).reshape(self.nb, 3),
                     energy=np.array(list(en)), infos=[i.as_dict() for i in infos])

@@ -3,9 +3,13 @@ small cases), through the C ABI.
 
 * transforms: the solver passes (x rows, y lines, z tiles) against the
   oracle's recursive DFT, forward and inverse, 2D and 3D shapes with ragged
-  tiles;
+  tiles and thin grids with one 256-long axis (the kernels of the 256^3
+  workload);
+* the solver's K and M element-wise against the sparse stencil matrix and the
+  oracle transforms, FP64 and FP32-mixed, on the same shapes;
 * mechanics: fixed-iteration parity (the displacement-form PCG iterates equal
-  the oracle's projected-CG iterates), converged parity at tol 1e-13 in FP64
+  the oracle's projected-CG iterates; FP64 and FP32-mixed, also on the thin
+  256-long grids), converged parity at tol 1e-13 in FP64
   (1e-10) and FP32-mixed (1e-5), with damage, eigenstrain and all six macro
   strain components;
 * phase field and diffusion (7-point stencil CG) against the oracle;
@@ -43,7 +47,10 @@ def _ctx(shape, prec=0):
     return fgcg.Context(shape[2], shape[1], H, precision=prec, nz=shape[0])
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 16), (24, 16, 32), (8, 12, 48), (64, 48, 32), (48, 64), (12, 1024)])
+THIN = [(256, 16, 16), (16, 256, 16), (16, 16, 256)]  # (nz, ny, nx): the 256-length kernels of the 256^3 workload
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (24, 16, 32), (8, 12, 48), (64, 48, 32), (48, 64), (12, 1024)] + THIN)
 def test_transform_matches_oracle(torch_dev, shape):
     torch, dev = torch_dev
     x = np.random.default_rng(sum(shape)).standard_normal(shape)
@@ -66,19 +73,50 @@ def _mech_case(shape, seed):
     return phase, d, e, em
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 16), (24, 16, 32)])
-def test_mech3_fixed_iterations(torch_dev, shape):
+def maxrel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("shape,k", [((16, 16, 16), 20), ((24, 16, 32), 20)] + [(t, 8) for t in THIN])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mech3_fixed_iterations(torch_dev, shape, k, prec):
     torch, dev = torch_dev
     phase, d, e, em = _mech_case(shape, 7)
-    k = 20
+    print(f"mech3 fixed {shape} k={k} prec={prec}", flush=True)
     o = omech.mech_solve(phase, E_TAB, NU_TAB, em, H, d=d, kappa=1e-6, e=e, tol=0.0, maxit=k, fixed_iters=k)
-    ctx = _ctx(shape)
+    ctx = _ctx(shape, prec)
     r = ctx.mech_solve(torch.from_numpy(phase).to(dev), E_TAB, NU_TAB, em, d=torch.from_numpy(d).to(dev),
                        kappa=1e-6, eig=torch.from_numpy(e).to(dev), tol=0.0, maxit=k)
-    err = rel(r["strain"].cpu().numpy(), o["strain"])
-    print(f"mech3 {shape} after {k} iterations: rel err {err:.2e}", flush=True)
+    err, emax = rel(r["strain"].cpu().numpy(), o["strain"]), maxrel(r["strain"].cpu().numpy(), o["strain"])
+    print(f"mech3 {shape} prec={prec} after {k} iterations: rel err {err:.2e}, max rel {emax:.2e}", flush=True)
     assert r["info"]["iters"] == k
-    assert err < 1e-12
+    bar = 1e-12 if prec == 0 else 1e-5
+    assert err < bar and emax < bar
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (24, 16, 32)] + THIN)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solver_operators3(torch_dev, shape, prec):
+    """K (tiled stiffness pass) and M (x / y / z Green passes) of the 3D
+    solver, element-wise against the sparse stencil matrix and the oracle
+    transforms."""
+    from oracle import direct as odir, precond as opc, spectral as osp
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    phase, d, _, _ = _mech_case(shape, 13)
+    u = np.random.default_rng(17).standard_normal((3,) + shape)
+    q_ref = odir.mech_stiffness_apply(phase, E_TAB, NU_TAB, u, H, d=d, kappa=1e-6)
+    z_ref = opc.apply_green(u, osp.grad_symbols(shape, H))
+    ctx = _ctx(shape, prec)
+    args = (torch.from_numpy(phase).to(dev), E_TAB, NU_TAB, torch.from_numpy(u).to(dev))
+    q = ctx.debug_apply(fgcg.OP_MECH_K, *args, d=torch.from_numpy(d).to(dev), kappa=1e-6).cpu().numpy()
+    z = ctx.debug_apply(fgcg.OP_MECH_M, *args).cpu().numpy()
+    eq, ez = maxrel(q, q_ref), maxrel(z, z_ref)
+    print(f"3D operators {shape} prec={prec}: K max rel {eq:.2e}, M max rel {ez:.2e}", flush=True)
+    bar = 1e-12 if prec == 0 else 1e-5
+    assert eq < bar and ez < bar
 
 
 @pytest.fixture(scope="module")
@@ -136,10 +174,21 @@ def test_diffusion3(torch_dev, shape, band):
     o = odiff.diffusion_step(c0, Dfield, react, 40.0, H, band=bm, c_dir=1.0, tol=1e-13, maxit=20000)
     ctx = _ctx(shape)
     cg = torch.from_numpy(c0.copy()).to(dev)
-    info = ctx.diffusion_step(torch.from_numpy(phase).to(dev), D_tab, k_tab, band, 1.0, 40.0, cg, tol=1e-13)
+    info = ctx.diffusion_step_phases(torch.from_numpy(phase).to(dev), D_tab, k_tab, band, 1.0, 40.0, cg, tol=1e-13)
     err = rel(cg.cpu().numpy(), o["c"])
     print(f"diff3 {shape} band {band}: iters {info['iters']} (oracle {o['iters']}), rel err {err:.2e}", flush=True)
     assert err < 1e-10
+    # per-voxel fields and an arbitrary Dirichlet mask
+    Df = 10.0 ** rng.uniform(-12.0, -9.0, shape)
+    kr = 1e-3 * rng.random(shape)
+    mask = (rng.random(shape) < 0.1).astype(np.uint8)
+    o = odiff.diffusion_step(c0, Df, kr, 40.0, H, band=mask.astype(bool), c_dir=0.3, tol=1e-13, maxit=20000)
+    cg = torch.from_numpy(c0.copy()).to(dev)
+    info = ctx.diffusion_step(cg, torch.from_numpy(Df).to(dev), 40.0, krate=torch.from_numpy(kr).to(dev),
+                              mask=torch.from_numpy(mask).to(dev), c_dir=0.3, tol=1e-13)
+    err = rel(cg.cpu().numpy(), o["c"])
+    print(f"diff3 field form {shape}: iters {info['iters']} (oracle {o['iters']}), rel err {err:.2e}", flush=True)
+    assert err < 1e-10 and maxrel(cg.cpu().numpy(), o["c"]) < 1e-10
 
 
 def test_staggered3_ramp(torch_dev):
@@ -164,8 +213,8 @@ def test_staggered3_ramp(torch_dev):
         print(f"staggered3 step {step}: mech iters {info['mech']['iters']} pf iters {info['pf']['iters']}, "
               f"max d {info['max_d']:.3e} (oracle {st.info['max_d']:.3e}), "
               + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
-        assert max(errs.values()) < 1e-9
-        assert abs(info["energy"] - st.info["energy"]) < 1e-9 * abs(st.info["energy"])
+        assert max(errs.values()) < 1e-10
+        assert abs(info["energy"] - st.info["energy"]) < 1e-10 * abs(st.info["energy"])
 
 
 def test_c5_full_size(torch_dev):

@@ -1,7 +1,7 @@
 """GPU parity of the hand-written adjoint (dJ/dE per voxel).
 
 * small grids: GPU gradient vs the oracle's adjoint gradient, energy and C11
-  objectives, with damage (both solves at tol 1e-13, <= 1e-9 relative);
+  objectives, with damage (both solves at tol 1e-13, <= 1e-10 relative);
 * user objective J = sum_x w_x eps_11(x): GPU gradient vs central
   differences of the oracle's forward solves;
 * torch.autograd: E.grad equals the adjoint gradient;
@@ -56,8 +56,13 @@ def test_adjoint_matches_oracle(torch_dev, objective, nx, ny):
     err = rel(g.cpu().numpy(), go)
     print(f"adjoint {objective} {nx}x{ny}: J rel err {abs(J - Jo) / abs(Jo):.2e}, grad rel err {err:.2e}, "
           f"iters fwd {i1['iters']} adj {i2['iters']}", flush=True)
-    assert abs(J - Jo) < 1e-9 * abs(Jo)
-    assert err < 1e-9
+    assert abs(J - Jo) < 1e-10 * abs(Jo)
+    assert err < 1e-10
+    # the objective alone (no adjoint solve) gives the same J
+    _, J1, _, i3 = ctx.mech_adjoint(torch.from_numpy(E).to(dev), NU, em,
+                                    objective=fgcg.J_ENERGY if objective == "W" else fgcg.J_C11,
+                                    d=torch.from_numpy(d).to(dev), kappa=1e-6, tol=1e-13, want_grad=False)
+    assert J1 == J and i3["iters"] == 0
 
 
 def test_adjoint_user_objective_finite_differences(torch_dev):
@@ -97,8 +102,8 @@ def test_autograd_function(torch_dev):
     J = autograd.mech_objective(E, ctx, NU, (1e-3, 0.0, 0.0), objective="C11", tol=1e-13)
     J.backward()
     g, Jd, _, _ = ctx.mech_adjoint(E.detach(), NU, (1e-3, 0.0, 0.0), objective=fgcg.J_C11, tol=1e-13)
-    assert abs(float(J) - Jd) < 1e-10 * abs(Jd)
-    assert torch.allclose(E.grad, g, rtol=1e-9, atol=1e-9 * float(g.abs().max()))
+    assert float(J.detach()) == Jd  # the forward value is the library's J
+    assert float((E.grad - g).abs().max()) <= 1e-10 * float(g.abs().max())
 
 
 def test_adjoint_c4_full_size(torch_dev):

@@ -5,6 +5,7 @@ launch per chunk).
   on its own context (same kernels, same reduction order);
 * small samples against the FP64 oracle (1e-10 at tol 1e-13);
 * FP32-mixed batch within 1e-5 of the FP64 oracle;
+* per-sample material tables: each sample matches its own single solve;
 * a 256-sample batch with the sizes, porosities and fractal exponents of the
   batched workload: every sample converges, <eps> = eps_mac, and the oracle's
   projected residual of the GPU strain is below 1e-7 on sampled small samples.
@@ -98,3 +99,27 @@ def test_batched_c3_workload(torch_dev):
             res = omech.mech_residual(r["strains"][i].cpu().numpy(), samples[i][0], E_TAB, NU_TAB, H)
             assert res < (1e-7 if prec == 0 else 1e-6), (i, res)
         b.close()
+
+
+def test_batched_per_sample_tables(torch_dev):
+    """Every sample with its own phase tables (device-side tables in the
+    kernels) equals the single solve with that sample's tables."""
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    sizes = [(32, 32), (32, 32), (64, 64), (32, 32)]
+    phases = _samples(sizes, 5)
+    Et = [(3e6, 30e9), (3e7, 20e9), (3e6, 30e9), (1e8, 40e9)]
+    Nt = [(0.2, 0.2), (0.3, 0.25), (0.2, 0.2), (0.1, 0.3)]
+    em = [(1e-3, 0.0, 0.0)] * len(sizes)
+    b = fgcg.Batch(sizes, H)
+    tph = [torch.from_numpy(p).to(dev) for p in phases]
+    r = b.mech_solve(tph, Et, Nt, em, tol=1e-13)
+    for i, ((nx, ny), p) in enumerate(zip(sizes, tph)):
+        one = fgcg.Context(nx, ny, H).mech_solve(p, Et[i], Nt[i], em[i], tol=1e-13)
+        err = rel(r["strains"][i].cpu().numpy(), one["strain"].cpu().numpy())
+        print(f"per-sample tables sample {i}: iters {r['infos'][i]['iters']} / {one['info']['iters']}, "
+              f"rel diff {err:.2e}", flush=True)
+        assert r["infos"][i]["iters"] == one["info"]["iters"]
+        assert err < 1e-13
+        o = omech.mech_solve(phases[i], Et[i], Nt[i], em[i], H, tol=1e-13, maxit=20000)
+        assert rel(r["strains"][i].cpu().numpy(), o["strain"]) < 1e-10
