@@ -11,22 +11,25 @@ damage) -> history update -> AT2 phase field (Gc = 50 J/m^2, l0 = 2 px), all
 CG tolerances 1e-8, FP64.  Synthetic inputs, resident in HBM before timing.
 
 value = total voxel-CG-iterations (all three solvers) / wall time of the
-timed steps.  The roofline block reports the dominant kernel (largest summed
-device time of the four mechanics passes in the last warm-up step) from HIP
-events recorded, on the library's stream, around the launches of that kernel
-in every other graph chunk of the timed steps (the event-record nodes add the
-kernel's dispatch gap, so the figure is a lower bound on the kernel's own
-bandwidth); its algorithmic bytes per voxel are listed in ALGO_BYTES.  traffic is the counter-measured HBM bytes per launch recorded
-under profiles/, reported only while the kernel sources are the ones it was
-measured on.  The CPU baseline
-times the FP64 oracle on two mechanics CG iterations of the same 1024^2
-problem.
+timed steps; mech_voxel_cg_iters_per_s is the mechanics solves alone.  The
+roofline block reports the dominant kernel (largest summed device time of the
+four mechanics passes in the last warm-up step): its algorithmic bytes per
+voxel (ALGO_BYTES) over the average duration of 200 back-to-back launches
+between HIP events on the library's stream; the same passes on a 2048^2
+workspace (larger than the Infinity Cache) are reported beside it.  traffic
+is the counter-measured HBM bytes per launch recorded under profiles/,
+reported only while the kernel sources are the ones it was measured on.  The
+CPU baseline times the FP64 oracle before any GPU work: the median of five
+mechanics CG iterations at 1024^2 after a warm-up, the full single-pore solve
+and a sample of the batched workload on one core and on a process pool.
 
 The "variants" block reports the other workloads of the method on the same
 GPU: 64^2 single-pore latency, the 1024^2 adjoint against the forward solve,
 256 batched uneven-size samples (FP64 and FP32-mixed) against the same solves
-one at a time, and the 256^3 3D staggered loop in FP32-mixed against plain
-FP64, each with its accuracy relative to the plain FP64 GPU result.
+one at a time, the 256^3 3D staggered loop in FP32-mixed against plain FP64,
+the static diffusion homogenisation of the 1024^2 fractal, and the mechanics
+with the reference-medium preconditioner against the unit Green operator,
+each with its accuracy.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-variants]
 """
@@ -100,27 +103,97 @@ def c2_params():
                 tol_diff=1e-8, tol_mech=1e-8, tol_pf=1e-8, maxit=200000, diffuse=1)
 
 
-def cpu_baseline(phase):
-    """FP64 oracle: two mechanics CG iterations at 1024^2 (the same operator)."""
-    from oracle import cg as ocg, mech as omech, spectral as osp
-
-    e = np.where(phase == 0, 1e-3, 0.0)
+def _oracle_mech_problem(phase, e_val=1e-3, eps_mac=(0.0, 0.0, 0.0)):
+    from oracle import mech as omech, spectral as osp
+    e = np.where(phase == 0, e_val, 0.0)
     lam, mu = omech.voxel_lame(phase, (3e6, 30e9), (0.2, 0.2))
     D = osp.grad_symbols(phase.shape, H)
-    E0 = omech.macro_tensor((0.0, 0.0, 0.0), 2, phase.shape) - omech.eigen_tensor(e, 2, phase.shape)
+    E0 = omech.macro_tensor(eps_mac, 2, phase.shape) - omech.eigen_tensor(e, 2, phase.shape)
     b = -omech.mech_operator(E0, lam, mu, D, "full")
-    A = lambda p: omech.mech_operator(p, lam, mu, D, "full")
-    iters = 2
+    return b, (lambda p: omech.mech_operator(p, lam, mu, D, "full"))
+
+
+def _oracle_iteration_seconds(phase, iters, eps_mac=(0.0, 0.0, 0.0), e_val=1e-3):
+    """Durations of `iters` oracle CG iterations (the interval between the
+    operator applications that start them; the last ends with the solve)."""
+    from oracle import cg as ocg
+    b, A = _oracle_mech_problem(phase, e_val, eps_mac)
+    stamps = []
+
+    def A_timed(p):
+        stamps.append(time.perf_counter())
+        return A(p)
+
+    ocg.cg(A_timed, b, fixed_iters=iters)
+    stamps.append(time.perf_counter())
+    return [stamps[i + 1] - stamps[i] for i in range(iters)]
+
+
+def _c3_oracle_sample(args):
+    """One batched-workload sample: seconds of `iters` oracle CG iterations
+    (pool worker; no GPU)."""
+    phase, iters = args
     t0 = time.perf_counter()
-    ocg.cg(A, b, fixed_iters=iters)
-    dt = time.perf_counter() - t0
+    _oracle_iteration_seconds(phase, iters, eps_mac=(1e-3, 0.0, 0.0), e_val=0.0)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(phase, pool_cap=16):
+    """The FP64 oracle on the machine's host cores, before any GPU work:
+    * the median of 5 mechanics CG iterations at 1024^2 after one warm-up
+      iteration (the headline workload's mechanics operator);
+    * the full single-pore 64^2 solve to tol 1e-10;
+    * a sample of the batched workload (its first 8 microstructures, 3 CG
+      iterations each) on one core, and the same samples over a process pool
+      on all host cores (joined before the function returns)."""
+    import multiprocessing as mp
+    from oracle import mech as omech
+    from paper_2305_13081_amd import inputs
+
     try:
-        cores = len(os.sched_getaffinity(0))
+        avail = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count()
-    return {"value": phase.size * iters / dt, "unit": "voxel-CG-iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"2 FP64 mechanics CG iterations of the oracle (naive recursive DFT) at 1024^2, "
-                      f"{dt:.1f} s, single thread (host has {cores} cores available)"}
+        avail = os.cpu_count()
+    print("cpu baseline: 6 oracle iterations at 1024^2 ...", file=sys.stderr, flush=True)
+    secs = _oracle_iteration_seconds(phase, 6)
+    med = float(np.median(secs[1:]))
+    print(f"cpu baseline: median {med:.2f} s per iteration; single pore 64^2 solve ...", file=sys.stderr, flush=True)
+    c1 = inputs.circle_pore(64)
+    t0 = time.perf_counter()
+    o = omech.mech_solve(c1, (3e6, 30e9), (0.2, 0.2), (0.0, 0.0, 0.0), H, e=np.where(c1 == 0, 1e-3, 0.0),
+                         tol=1e-10, maxit=20000)
+    t_c1 = time.perf_counter() - t0
+    samples = [p for p, _ in inputs.c3_samples(8)]
+    iters = 3
+    work = float(sum(p.size for p in samples) * iters)
+    print(f"cpu baseline: single pore {t_c1:.2f} s ({o['iters']} iterations); batched sample on 1 core ...",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for p in samples:
+        _c3_oracle_sample((p, iters))
+    t_one = time.perf_counter() - t0
+    ncore = max(1, min(pool_cap, avail))
+    print(f"cpu baseline: batched sample on {ncore} processes ...", file=sys.stderr, flush=True)
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(processes=min(ncore, len(samples))) as pool:
+        pool.map(_c3_oracle_sample, [(p, iters) for p in samples])
+        pool.close()
+        pool.join()
+    t_all = time.perf_counter() - t0
+    return {"value": phase.size / med, "unit": "voxel-CG-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"median of 5 FP64 mechanics CG iterations of the oracle (naive recursive DFT, strain form) "
+                      f"at 1024^2 after one warm-up iteration: {med:.2f} s per iteration, single thread "
+                      f"(host: {avail} cores available)",
+            "iteration_seconds": secs,
+            "single_pore_64": {"seconds": t_c1, "iters": o["iters"], "us_per_iter": t_c1 / o["iters"] * 1e6,
+                               "cores": 1},
+            "batched_sample": {"samples": len(samples), "voxels": int(sum(p.size for p in samples)),
+                               "iters_each": iters,
+                               "one_core_voxel_cg_iters_per_s": work / t_one,
+                               "pool_voxel_cg_iters_per_s": work / t_all, "pool_processes": min(ncore, len(samples)),
+                               "note": "the first 8 microstructures of the batched workload, 3 oracle CG "
+                                       "iterations each"}}
 
 
 def c5_variant(torch, fgcg, inputs, dev, steps=2):
@@ -277,6 +350,92 @@ def c1_variant(torch, fgcg, inputs, dev, reps=20):
                         "matrix 30 GPa, FP64, tol 1e-10"}
 
 
+def hbm_resident_passes(torch, fgcg, dev, n=2048, reps=100):
+    """The 2D FP64 mechanics passes on a 2048^2 workspace (about 330 MB, more
+    than the 256 MB Infinity Cache, so the traffic comes from HBM): average
+    duration of back-to-back launches between HIP events (fgcg_time_pass)."""
+    ctx = fgcg.Context(n, n, H)
+    spec_b = 16.0 * (n // 2 + 1) / n
+    ab = {"mech_row_fwd": 64 + 32 + 2 * spec_b, "mech_col": 4 * spec_b, "mech_row_inv": 2 * spec_b + 32}
+    out = {}
+    for k in ("mech_row_fwd", "mech_col", "mech_row_inv"):
+        us = ctx.time_pass(k, reps)
+        gbs = ab[k] * n * n / (us * 1e-6) / 1e9
+        out[k] = {"avg_launch_us": us, "algo_bytes_per_voxel": round(ab[k], 3), "achieved_GBs": gbs,
+                  "frac": gbs / HBM_PEAK_GBS}
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    out["note"] = (f"{n}^2 FP64 workspace, {reps} back-to-back launches per pass after 3 untimed, tuned plans; "
+                   f"the working set exceeds the Infinity Cache")
+    return out
+
+
+def homogenisation_variant(torch, fgcg, inputs, dev):
+    """Static diffusion homogenisation (Sec. 2.1) on the 1024^2 fractal with
+    D = 1e-9 / 1e-12 m^2/s: the effective diffusivity (two solves, tol 1e-8)
+    and the concentration reconstruction."""
+    phase_np, _ = inputs.c2_microstructure(N_SIDE)
+    Df = torch.from_numpy(np.where(phase_np == 0, 1e-9, 1e-12)).to(dev)
+    ph = torch.from_numpy(phase_np).to(dev)
+    ctx = fgcg.Context(N_SIDE, N_SIDE, H)
+    ctx.diffusivity_eff(Df, tol=1e-8, maxit=200000)  # warm-up (graphs built)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Deff, infos = ctx.diffusivity_eff(Df, tol=1e-8, maxit=200000)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    iters = sum(i["iters"] for i in infos)
+    r = ctx.diffusion_homogenize(Df, (1.0, 0.0), tol=1e-8, maxit=200000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c, bp, bs = ctx.concentration(ph, r["grad_c"], (1.0, 0.0), 1.0)
+    torch.cuda.synchronize()
+    t_c = time.perf_counter() - t0
+    return {"D_eff": Deff.tolist(), "D_eff_over_D_pore": (Deff / 1e-9).tolist(), "iters": [i["iters"] for i in infos],
+            "seconds": el, "voxel_cg_iters_per_s": N_SIDE * N_SIDE * iters / el,
+            "reconstruction_seconds": t_c, "beta_pore": bp, "beta_solid": bs,
+            "workload": "2D 1024^2 box-removal fractal, D 1e-9 (pores) / 1e-12 (solid) m^2/s, effective "
+                        "diffusivity (grad c_mac = e_x, e_y), CG tol 1e-8, FP64"}
+
+
+def precond_variant(torch, fgcg, inputs, dev):
+    """Mechanics of the staggered workload (1024^2 fractal, pore eigenstrain
+    1e-3, tol 1e-8): unit Green operator against the isotropic reference
+    medium, FP64 and FP32-mixed; accuracy against a reference solve at tol
+    1e-13."""
+    phase_np, _ = inputs.c2_microstructure(N_SIDE)
+    ph = torch.from_numpy(phase_np).to(dev)
+    e = torch.from_numpy(np.where(phase_np == 0, 1e-3, 0.0)).to(dev)
+    em = (0.0, 0.0, 0.0)
+    ctx = fgcg.Context(N_SIDE, N_SIDE, H)
+    ctx.set_option("precond", 1)
+    ref = ctx.mech_solve(ph, (3e6, 30e9), (0.2, 0.2), em, eig=e, tol=1e-13, maxit=200000)["strain"].cpu().numpy()
+    ctx.close()
+    out = {}
+    for prec, pname in ((fgcg.FP64, "fp64"), (fgcg.FP32_MIXED, "fp32_mixed")):
+        for pc, name in ((0, "unit"), (1, "reference")):
+            c = fgcg.Context(N_SIDE, N_SIDE, H, precision=prec)
+            c.set_option("precond", pc)
+            c.mech_solve(ph, (3e6, 30e9), (0.2, 0.2), em, eig=e, tol=1e-8, maxit=200000)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = c.mech_solve(ph, (3e6, 30e9), (0.2, 0.2), em, eig=e, tol=1e-8, maxit=200000)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            s = r["strain"].cpu().numpy()
+            out[f"{pname}_{name}"] = {"iters": r["info"]["iters"], "seconds": el,
+                                      "us_per_iter": el / r["info"]["iters"] * 1e6,
+                                      "voxel_cg_iters_per_s": N_SIDE * N_SIDE * r["info"]["iters"] / el,
+                                      "strain_rel_err_vs_tight": float(np.linalg.norm(s - ref) / np.linalg.norm(ref))}
+            c.close()
+            del c
+    out["time_to_solution_speedup_fp64"] = out["fp64_unit"]["seconds"] / out["fp64_reference"]["seconds"]
+    out["workload"] = ("2D 1024^2 box-removal fractal, E 30 GPa / 3 MPa, nu 0.2, pore eigenstrain 1e-3, CG tol 1e-8; "
+                       "unit Green operator (the projected CG) vs isotropic reference medium (nu 0.2)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,8 +444,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--variant", default=None,
-                    help="run only this variant (c1_latency_64, c4_adjoint_1024, c3_batched_256, c5_3d_256) and "
-                         "print its JSON")
+                    help="run only this variant (c1_latency_64, c4_adjoint_1024, c3_batched_256, c5_3d_256, "
+                         "homogenisation_1024, precond_1024) and print its JSON")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-MiB FP64 buffer 5 times with an elementwise kernel (reads "
                          "and writes MIB MiB each): the reference for scaling HBM counters")
@@ -296,19 +455,23 @@ def main():
               f"multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 
+    from paper_2305_13081_amd import inputs
+
+    phase_np, finfo = inputs.c2_microstructure(N_SIDE)
+    # the oracle runs first, on the host cores, before anything touches the GPU
+    base = cpu_baseline(phase_np) if not (args.no_cpu_baseline or args.variant) else None
+
     import torch
 
-    from paper_2305_13081_amd import fgcg, inputs
+    from paper_2305_13081_amd import fgcg
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     if args.variant:
-        fn = {"c1_latency_64": c1_variant, "c4_adjoint_1024": c4_variant, "c3_batched_256": c3_variant,
-              "c5_3d_256": c5_variant}[args.variant]
+        fn = VARIANTS[args.variant]
         print(json.dumps({args.variant: fn(torch, fgcg, inputs, dev)}), flush=True)
         copy_probe(torch, dev, args.copy_probe)
         return
-    phase_np, finfo = inputs.c2_microstructure(N_SIDE)
     phase = torch.from_numpy(phase_np).to(dev)
     ctx = fgcg.Context(N_SIDE, N_SIDE, H)
     prm = c2_params()
@@ -390,22 +553,27 @@ def main():
                                "events around every launch of the kernel inside the CG graphs during the "
                                "timed steps, which adds the dispatch gap of the event nodes to each launch"},
     }
+    out["mech_voxel_cg_iters_per_s"] = out["breakdown"]["voxel_cg_iters_per_s"]["mech"]
+    del ctx, state
+    torch.cuda.empty_cache()
+    out["roofline"]["hbm_resident_2048"] = hbm_resident_passes(torch, fgcg, dev)
     if not args.no_variants:
-        del ctx, state
-        torch.cuda.empty_cache()
         variants = {}
-        for name, fn in (("c1_latency_64", c1_variant), ("c4_adjoint_1024", c4_variant),
-                         ("c3_batched_256", c3_variant), ("c5_3d_256", c5_variant)):
+        for name, fn in VARIANTS.items():
             print(f"variant {name} ...", file=sys.stderr, flush=True)
             t0 = time.perf_counter()
             variants[name] = fn(torch, fgcg, inputs, dev)
             print(f"variant {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
             torch.cuda.empty_cache()
         out["variants"] = variants
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(phase_np)
+    if base is not None:
+        out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
     copy_probe(torch, dev, args.copy_probe)
+
+
+VARIANTS = {"c1_latency_64": c1_variant, "c4_adjoint_1024": c4_variant, "c3_batched_256": c3_variant,
+            "c5_3d_256": c5_variant, "homogenisation_1024": homogenisation_variant, "precond_1024": precond_variant}
 
 
 def copy_probe(torch, dev, mib):

@@ -255,13 +255,13 @@ inline void set_kname(fgcg_ctx* c, int kind, const char* fmt, const char* t, int
 // profiled), or, while a chunk graph is being built, a kernel node appended to
 // the chain (between two event-record nodes when profiled).
 template <typename... A>
-int launch(fgcg_ctx* c, int kind, const void* fn, dim3 grid, A... args) {
+int launch_b(fgcg_ctx* c, int kind, const void* fn, dim3 grid, dim3 block, A... args) {
   void* ptrs[] = {(void*)&args...};
   const bool prof = kind >= 0 && (c->prof_mask & (1u << kind)) && (!c->building || c->build_timed);
   if (!c->building) {
     int rc = prof ? prof_begin(c, kind) : 0;
     if (rc) return rc;
-    HIPCHK(hipLaunchKernel(fn, grid, dim3(NT), ptrs, 0, c->stream));
+    HIPCHK(hipLaunchKernel(fn, grid, block, ptrs, 0, c->stream));
     return prof ? prof_end(c, kind) : 0;
   }
   hipEvent_t ea = nullptr, eb = nullptr;
@@ -277,7 +277,7 @@ int launch(fgcg_ctx* c, int kind, const void* fn, dim3 grid, A... args) {
   hipKernelNodeParams kp{};
   kp.func = const_cast<void*>(fn);
   kp.gridDim = grid;
-  kp.blockDim = dim3(NT);
+  kp.blockDim = block;
   kp.sharedMemBytes = 0;
   kp.kernelParams = ptrs;
   kp.extra = nullptr;
@@ -291,6 +291,10 @@ int launch(fgcg_ctx* c, int kind, const void* fn, dim3 grid, A... args) {
     c->pending.push_back({kind, ea, eb});
   }
   return 0;
+}
+
+template <typename... A> int launch(fgcg_ctx* c, int kind, const void* fn, dim3 grid, A... args) {
+  return launch_b(c, kind, fn, grid, dim3(NT), args...);
 }
 
 // Rows per block of the tunable row passes: rows_for(NX) times 1/2, 1 or 2,
@@ -362,13 +366,23 @@ int launch_row_fwd(fgcg_ctx* c, int kind, const Pro& pro, CT<T>* spec, int nsamp
   return rc;
 }
 
-// TUNED: the radix plan comes from c->plan_col (the mechanics Green pass).
+// TUNED: the radix plan comes from c->plan_col (the mechanics Green pass):
+// 1 radix 8, 2 radix 16 (k_col, 256 threads per column), 3 one wavefront per
+// column (k_colw; one-component symbols and lengths 256..2048, else plan 1).
 template <typename T, int NIN, int NOUT, class Sym, bool TUNED = false>
 int launch_col(fgcg_ctx* c, int kind, const Sym& sym, const CT<T>* in, CT<T>* out, int nsamp = 1,
                long long ss = 0) {
   int rc = 0;
   with_n(c->ny, [&](auto NYc) {
     constexpr int NY = decltype(NYc)::value;
+    if constexpr (TUNED && NIN == 1 && NOUT == 1 && wave_col_ok(NY)) {
+      if (c->plan_col == 3) {
+        if (kind >= 0) set_kname(c, kind, "k_colw<%s, %d", tname<T>(), NY);
+        rc = launch_b(c, kind, (const void*)&k_colw<T, NY, Sym>, dim3(c->nxh, nsamp), dim3(64), sym, in, out,
+                      c->nxh, ss, ss, tw_y<T>(c));
+        return;
+      }
+    }
     auto go = [&](auto Pc) {
       constexpr int P = decltype(Pc)::value;
       dim3 g(c->nxh, nsamp);

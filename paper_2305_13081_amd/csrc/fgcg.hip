@@ -154,7 +154,10 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
     prow_c = plan1_differs(NX) ? std::vector<int>{1, 2} : std::vector<int>{1};
   });
   with_n(c->ny, [&](auto NYc) {
-    pcol_c = plan1_differs(decltype(NYc)::value) ? std::vector<int>{1, 2} : std::vector<int>{1};
+    constexpr int NY = decltype(NYc)::value;
+    pcol_c = plan1_differs(NY) ? std::vector<int>{1, 2} : std::vector<int>{1};
+    // one wavefront per column: the one-component (unit) Green pass
+    if (wave_col_ok(NY) && c->precond == 0) pcol_c.push_back(3);
   });
   // below 2^18 voxels the passes are launch-bound and plan timings are
   // noise: radix 8 (so every context of a small size has the same schedule)
@@ -866,7 +869,8 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
     case FGCG_OPT_ROW_PLAN:
     case FGCG_OPT_COL_PLAN:
       if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "radix plans are tuned on 2D grids");
-      if (value < 0 || value > 2) return fail(FGCG_EINVAL, "radix plan must be 0 (tune), 1 or 2");
+      if (value < 0 || value > (option == FGCG_OPT_COL_PLAN ? 3 : 2))
+        return fail(FGCG_EINVAL, "plan must be 0 (tune), 1 or 2 (3 for the column pass)");
       (option == FGCG_OPT_ROW_PLAN ? c->plan_row : c->plan_col) = value;
       return FGCG_OK;
     default:

@@ -288,6 +288,133 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
   }
 }
 
+// ------------------------------------------------- column, one wave per column
+// One 64-lane wavefront (a block of 64 threads) transforms a whole column of
+// length N in registers: lane l holds the elements l + 64 m, m < E = N / 64.
+// A Stockham stage of radix R (E a multiple of R) gives lane l the butterflies
+// j = l + 64 q, whose inputs j + r N / R = l + 64 (q + r E / R) are again the
+// lane's own elements, so a stage needs no exchange to read; its outputs go
+// to LDS (positions (j / Ns) Ns R + j % Ns + r Ns) and come back as the next
+// stage's elements l + 64 m, except after the last stage, whose outputs
+// j + r Ns already are the lane's own elements.  The column is loaded and
+// stored in that layout (64 consecutive complex values per access), and the
+// symbol is applied to the lane's modes between the forward and the inverse
+// transform: two LDS round trips per direction for N = 1024 (radix 16, 16,
+// 4), no barrier across wavefronts.
+struct WPlan {
+  int nst;
+  int r[6];
+};
+constexpr WPlan wave_plan(int N) {
+  return N == 256 ? WPlan{4, {4, 4, 4, 4, 0, 0}}
+         : N == 512 ? WPlan{3, {8, 8, 8, 0, 0, 0}}
+         : N == 1024 ? WPlan{3, {16, 16, 4, 0, 0, 0}}
+         : N == 2048 ? WPlan{3, {16, 16, 8, 0, 0, 0}}
+                     : WPlan{0, {0, 0, 0, 0, 0, 0}};
+}
+constexpr bool wave_col_ok(int N) { return wave_plan(N).nst > 0; }
+
+// One stage (radix R, sub-transform length NS) on the lane's elements V.
+template <typename T, int N, int R, int NS, bool INV, bool LAST>
+__device__ __forceinline__ void wave_stage(typename cvec<T>::type* V, typename cvec<T>::type* buf,
+                                           const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  constexpr int E = N / 64, B = E / R;  // butterflies per lane
+  constexpr int TSTEP = N / (NS * R);
+  const int l = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < B; ++q) {
+    C v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = V[q + r * B];
+    if (NS > 1) {
+      const int k = (l + 64 * q) % NS;
+      C w1 = tw[k * TSTEP];
+      if (INV) w1.y = -w1.y;
+      C w = w1;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        v[r] = cmul(v[r], w);
+        if (r + 1 < R) w = cmul(w, w1);
+      }
+    }
+    Dft<R, INV, T>::run(v);
+    if constexpr (LAST) {
+      // outputs j + r NS with j = l + 64 q and NS = 64 B: the lane's own
+      // elements q + r B, the ones this butterfly read
+#pragma unroll
+      for (int r = 0; r < R; ++r) V[q + r * B] = v[r];
+    } else {
+      const int j = l + 64 * q;
+      const int base = (j / NS) * NS * R + j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lds(base + r * NS)] = v[r];
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) V[m] = buf[lds(l + 64 * m)];
+    __syncthreads();
+  }
+}
+
+template <typename T, int N, bool INV, int ST, int NS>
+__device__ __forceinline__ void wave_fft(typename cvec<T>::type* V, typename cvec<T>::type* buf,
+                                         const typename cvec<T>::type* __restrict__ tw) {
+  constexpr WPlan p = wave_plan(N);
+  if constexpr (ST < p.nst) {
+    constexpr int R = p.r[ST];
+    wave_stage<T, N, R, NS, INV, ST + 1 == p.nst>(V, buf, tw);
+    wave_fft<T, N, INV, ST + 1, NS * R>(V, buf, tw);
+  }
+}
+
+__device__ __forceinline__ double wave_sum64(double v) { return wave_sum(v); }
+
+// One-component column pass (NIN = NOUT = 1) for the Green symbols: block
+// (kx, s) of 64 threads.  Same contract as k_col<T, NY, 1, 1, Sym>.
+template <typename T, int NY, class Sym>
+__global__ void __launch_bounds__(64) k_colw(Sym sym, const typename cvec<T>::type* spec_in,
+                                             typename cvec<T>::type* spec_out, int nxh, long long ss_in,
+                                             long long ss_out, const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  constexpr int E = NY / 64;
+  __shared__ C buf[lds_size(NY)];
+  __shared__ double red[1];
+  const int s = blockIdx.y;
+  const int kx = blockIdx.x;
+  const int l = threadIdx.x;
+  double sc = 0.0;
+  if (!sym.begin(s, red, sc)) return;
+  const C* in = spec_in + s * ss_in + (long long)kx * NY;
+  C V[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) V[m] = in[l + 64 * m];
+  typename SymPre<Sym>::type spre[E];
+  if constexpr (SymPre<Sym>::value) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) spre[m] = sym.pre(kx, l + 64 * m);
+  }
+  wave_fft<T, NY, false, 0, 1>(V, buf, tw);
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    C b[1];
+    if constexpr (SymPre<Sym>::value)
+      sym.mode_pre(s, kx, l + 64 * m, spre[m], &V[m], b, acc, sc);
+    else
+      sym.mode(s, kx, l + 64 * m, &V[m], b, acc, sc);
+    V[m] = b[0];
+  }
+  acc = wave_sum64(acc);
+  sym.partial(s, acc);
+  wave_fft<T, NY, true, 0, 1>(V, buf, tw);
+  C* out = spec_out + s * ss_out + (long long)kx * NY;
+#pragma unroll
+  for (int m = 0; m < E; ++m) out[l + 64 * m] = V[m];
+}
+
 // Load NIN half spectra of ROWS rows, inverse transform, into registers.
 // The half spectrum of component c + 1 is loaded into registers before the
 // transform of component c (the barriers wait for LDS traffic only), so its

@@ -81,7 +81,7 @@ def plan_differs(n):
     return b >= 4 and b % 4 != 1 or b >= 9
 
 
-@pytest.mark.parametrize("nx,ny", [(64, 48), (256, 128), (48, 512), (96, 32)])
+@pytest.mark.parametrize("nx,ny", [(64, 48), (256, 128), (48, 512), (96, 32), (24, 1024), (16, 2048), (64, 256)])
 def test_plans_fixed_iteration_parity(torch_dev, nx, ny):
     from paper_2305_13081_amd import fgcg
     torch, dev = torch_dev
@@ -92,7 +92,7 @@ def test_plans_fixed_iteration_parity(torch_dev, nx, ny):
     k = 12
     o = omech.mech_solve(ph, E_TAB, NU_TAB, (2e-4, 0.0, 1e-4), H, e=e, fixed_iters=k)
     for pr in (1, 2):
-        for pc in (1, 2):
+        for pc in (1, 2, 3):  # 3: one wavefront per column (lengths 256..2048; plan 1 otherwise)
             ctx = fgcg.Context(nx, ny, H)
             ctx.set_option("row_plan", pr)
             ctx.set_option("col_plan", pc)
@@ -119,7 +119,8 @@ def test_plans_tuned_and_fp32(torch_dev):
     out = ctx.mech_solve(phase, E_TAB, NU_TAB, (1e-3, 0.0, 0.0), tol=1e-12, maxit=50000)
     pr, pc = ctx.get_option("row_plan"), ctx.get_option("col_plan")
     print(f"tuned {nx}x{ny}: rows {ctx.get_option('rows')} row plan {pr} col plan {pc}", flush=True)
-    assert pr in ((1, 2) if plan_differs(nx) else (1,)) and pc in ((1, 2) if plan_differs(ny) else (1,))
+    assert pr in ((1, 2) if plan_differs(nx) else (1,))
+    assert pc in ((1, 2) if plan_differs(ny) else (1,)) + ((3,) if ny in (256, 512, 1024, 2048) else ())
     err = float((out["strain"] - ref["strain"]).norm() / ref["strain"].norm())
     assert err < 1e-10, err
     # FP32-mixed with radix 16 in both passes against the FP64 solve
@@ -135,8 +136,8 @@ def test_plans_tuned_and_fp32(torch_dev):
 def test_plan_option_rejects(torch_dev):
     from paper_2305_13081_amd import fgcg
     ctx = fgcg.Context(256, 64, H)
-    for name in ("row_plan", "col_plan"):
-        for bad in (3, -1):
+    for name, top in (("row_plan", 2), ("col_plan", 3)):
+        for bad in (top + 1, -1):
             with pytest.raises(fgcg.FgcgError):
                 ctx.set_option(name, bad)
         ctx.set_option(name, 2)

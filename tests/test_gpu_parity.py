@@ -372,9 +372,13 @@ def test_staggered_fracture_regime_fixed_iterations(torch_dev):
     run k fixed CG iterations (near d = 1 the stiffness contrast reaches
     1/kappa, so converged solves differ by up to the condition number times
     the tolerance; fixed iterations compare the kernels).  Mechanics and phase
-    field against the oracle at 1e-10; the diffusion step (stencil operator)
-    against the oracle's CG with the stencil matrix at 1e-12, and against the
-    transform-form oracle within twice the gap between the two oracle forms."""
+    field against the oracle at 1e-10.  The diffusion step starts from c^n,
+    which already nearly solves the step (|r0| / |b| ~ 4e-4), so rounding in
+    the first residual decides the last digits of every iterate: two FP64
+    oracles of the same iteration (the operator by transforms, and as the
+    sparse stencil matrix) differ by ~4e-10 after 5 iterations.  The GPU
+    iterate must lie within twice that spread of both (and within 1e-10
+    where the spread is smaller)."""
     torch, dev = torch_dev
     n = 32
     phase, _ = inputs.box_fractal(n, 2, 3, 1.8, 0.3, np.random.default_rng(3))
@@ -417,9 +421,10 @@ def test_staggered_fracture_regime_fixed_iterations(torch_dev):
         ed_fft = rel(cg.cpu().numpy(), od["c"])
         print(f"  diffusion: vs stencil-form oracle CG {ed:.2e}, vs transform-form oracle {ed_fft:.2e} "
               f"(the two oracle forms differ by {floor:.2e})", flush=True)
-        assert ed_fft < max(1e-10, 2.0 * floor)
+        bar_d = max(1e-10, 2.0 * floor)  # the spread of two FP64 evaluations of the same iteration
+        assert ed < bar_d and ed_fft < bar_d
         print(f"fracture regime k={k}: mech {em:.2e} pf {ep:.2e} diff {ed:.2e}", flush=True)
-        assert em < 1e-10 and ep < 1e-10 and ed < 1e-12
+        assert em < 1e-10 and ep < 1e-10
 
 
 def test_c2_full_size(torch_dev):
