@@ -332,6 +332,20 @@ typedef struct {
 int fgcg_staggered_step(fgcg_ctx* ctx, fgcg_state* state, const fgcg_params* prm,
                         fgcg_step_info* info);
 
+/* ---- no allocation --------------------------------------------------- */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+ * fgcg_phasefield_solve with the stencil operator (the default), FP64, without
+ * a context.  Every work buffer lives in a device array of the library
+ * (40 MiB per device, held until the process ends); the call allocates
+ * nothing.  grid->precision must be FGCG_FP64, axis lengths as fgcg_create,
+ * at most 2^20 voxels (EINVAL beyond).  hip_stream: the stream the work goes
+ * to (NULL: the null stream); the call returns after it has finished.  H, d
+ * as fgcg_phasefield_solve (d: in d^n, out d^{n+1}).  Calls that overlap on
+ * one device race on the shared array. */
+int fgcg_phasefield_solve_noalloc(const fgcg_grid* grid, void* hip_stream, const double* H, double Gc,
+                                  double l0, double* d, double tol, int maxit, fgcg_info* info);
+
 /* ---- kernel-level test hooks ------------------------------------------ */
 /* One application of an operator of the mechanics solver through the very
  * kernels a solve launches, in the context's precision (FP32-mixed: in is

@@ -4,7 +4,8 @@
 
 compiles every translation unit under ``csrc/`` (``fgcg.hip``: the C ABI and
 the 2D solvers; ``fgcg3d.hip``: the 3D solvers; ``homog.hip``: the diffusion
-homogenisation and concentration reconstruction) for gfx950 with hipcc, in
+homogenisation and concentration reconstruction; ``noalloc.hip``: the
+phase-field solve without allocation) for gfx950 with hipcc, in
 parallel, and links them into ``libfgcg.so`` next to this file (the library
 the binding loads).  Packed-FP32 instruction selection is disabled for every
 HIP translation unit, and floating-point contraction is limited to single
@@ -20,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfgcg.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fgcg.hip", "fgcg3d.hip", "homog.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fgcg.hip", "fgcg3d.hip", "homog.hip", "noalloc.hip")]
 
 COMPILE_FLAGS = [
     "--offload-arch=gfx950",

@@ -114,6 +114,8 @@ _SIGS = {
     "fgcg_debug_apply": (_ip, [_vp, _ip, ctypes.POINTER(Material), _vp, ctypes.c_double, _vp, _vp]),
     "fgcg_phasefield_apply": (_ip, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]),
     "fgcg_diffusion_apply": (_ip, [_vp, _vp, _ip, _dp, _dp, ctypes.c_double, _vp, _vp]),
+    "fgcg_phasefield_solve_noalloc": (_ip, [ctypes.POINTER(Grid), _vp, _vp, ctypes.c_double, ctypes.c_double, _vp,
+                                            ctypes.c_double, _ip, ctypes.POINTER(Info)]),
     "fgcg_debug_fft": (_ip, [_vp, _ip, _vp, _vp]),
     "fgcg_time_pass": (_ip, [_vp, _ip, _ip, _dp]),
     "fgcg_profile": (_ip, [_vp, ctypes.c_uint]),
@@ -493,6 +495,29 @@ class Context:
                "fgcg_profile_read")
         name = self.lib.fgcg_kernel_name(self.ptr, KINDS[kind]).decode()
         return ms.value, n.value, name
+
+
+def phasefield_solve_noalloc(H, Gc, l0, d, h, tol=1e-10, maxit=20000):
+    """fgcg_phasefield_solve_noalloc: the phase-field solve without a context
+    or any allocation; H and d are float64 CUDA tensors of the grid's shape
+    ((ny, nx) or (nz, ny, nx)), d is updated in place."""
+    torch = _torch()
+    lib = load_library()
+    for t, name in ((H, "H"), (d, "d")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise FgcgError(-1, name, "expected a contiguous float64 CUDA tensor")
+    if tuple(H.shape) != tuple(d.shape) or H.device != d.device or H.dim() not in (2, 3):
+        raise FgcgError(-1, "phasefield_solve_noalloc", "H and d need the same 2D or 3D shape and device")
+    sh = tuple(d.shape)
+    n = (sh[-1], sh[-2], sh[0] if len(sh) == 3 else 1)
+    g = Grid(len(sh), (ctypes.c_int * 3)(*n), float(h), FP64)
+    info = Info()
+    with torch.cuda.device(d.device):
+        stream = torch.cuda.current_stream().cuda_stream
+        st = lib.fgcg_phasefield_solve_noalloc(ctypes.byref(g), _vp(stream), _vp(H.data_ptr()), float(Gc), float(l0),
+                                               _vp(d.data_ptr()), float(tol), int(maxit), ctypes.byref(info))
+    _check(st, "fgcg_phasefield_solve_noalloc", allow_nc=True)
+    return info.as_dict()
 
 
 class Batch:
