@@ -33,9 +33,9 @@ def diffusion_operator(c, Dfield, react, dt, D):
 
 
 def diffusion_step(c_n, Dfield, react, dt, h, band=None, c_dir=1.0,
-                   tol=1e-10, maxit=20000, fixed_iters=None):
+                   tol=1e-10, maxit=20000, fixed_iters=None, op="forward"):
     c_n = np.asarray(c_n, dtype=np.float64)
-    D = _sp.grad_symbols(c_n.shape, h)
+    D = _sp.grad_symbols(c_n.shape, h, op)
     if band is None:
         M = np.ones(c_n.shape)
         cB = np.zeros(c_n.shape)

@@ -163,3 +163,92 @@ def mech_stiffness_apply(phase, E_tab, nu_tab, u, h, d=None, kappa=0.0, E_field=
     C = _stiffness_matrix(g * lam, g * mu)
     L = _symgrad_matrix(grid, h)
     return (L.T @ (C @ (L @ np.asarray(u, dtype=np.float64).reshape(-1)))).reshape((dim,) + grid)
+
+
+def diff_matrix(grid, alpha, h, op="forward"):
+    """Real-space matrix of the gradient along axis alpha for the operators of
+    Sec. 2.6: forward (f(x+h) - f(x))/h, central (f(x+h) - f(x-h))/(2h),
+    central8 (sum_m a_m (f(x+mh) - f(x-mh))/h, a = 4/5, -1/5, 4/105, -1/280)
+    and fourier (the periodic spectral differentiation matrix: entries
+    (pi / L) (-1)^(j-k) csc(pi (j-k) / n) for odd n, cot for even n, with the
+    Nyquist mode differentiated to zero; L = n h).  Built from shifts and
+    closed forms, no transform."""
+    if op == "forward":
+        return fwd_diff_matrix(grid, alpha, h)
+    grid = tuple(grid)
+    dim = len(grid)
+    N = int(np.prod(grid))
+    axis = dim - 1 - alpha
+    idx = np.arange(N).reshape(grid)
+
+    def shift(m):  # (S_m f)(x) = f(x + m e_alpha)
+        nbr = np.roll(idx, -m, axis=axis)
+        return sps.csr_matrix((np.ones(N), (idx.ravel(), nbr.ravel())), shape=(N, N))
+
+    if op == "central":
+        return ((shift(1) - shift(-1)) / (2.0 * h)).tocsr()
+    if op == "central8":
+        coef = (4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0)
+        M = sps.csr_matrix((N, N))
+        for m, a in enumerate(coef, start=1):
+            M = M + a * (shift(m) - shift(-m))
+        return (M / h).tocsr()
+    if op == "fourier":
+        n = grid[axis]
+        j = np.arange(n)
+        dj = (j[:, None] - j[None, :]) % n
+        with np.errstate(divide="ignore"):
+            ang = np.pi * dj / n
+            core = 1.0 / np.tan(ang) if n % 2 == 0 else 1.0 / np.sin(ang)
+        D1 = np.where(dj == 0, 0.0, (np.pi / (n * h)) * (-1.0) ** dj * core)
+        # D1 acts along `axis`: Kronecker product with identities on the other axes
+        mats = [np.eye(g) for g in grid]
+        mats[axis] = D1
+        M = mats[0]
+        for m in mats[1:]:
+            M = np.kron(M, m)
+        return sps.csr_matrix(M)
+    raise ValueError(op)
+
+
+def mech_direct_op(phase, E_tab, nu_tab, eps_mac, h, op, d=None, kappa=0.0, e=None):
+    """mech_direct with the gradient operator `op`: the strain is unique even
+    where the operator has more null modes than the translations (least
+    squares on the normal equations)."""
+    phase = np.asarray(phase)
+    grid = phase.shape
+    dim = phase.ndim
+    N = phase.size
+    lam, mu = _mech.voxel_lame(phase, E_tab, nu_tab)
+    g = np.ones(grid) if d is None else _mat.degradation(np.asarray(d), kappa)
+    C = _stiffness_matrix(g * lam, g * mu)
+    B = [diff_matrix(grid, a, h, op) for a in range(dim)]
+    Z = sps.csr_matrix((N, N))
+    rows = []
+    for i in range(dim):
+        for j in range(dim):
+            row = [Z] * dim
+            row[i] = row[i] + 0.5 * B[j]
+            row[j] = row[j] + 0.5 * B[i]
+            rows.append(row)
+    L = sps.bmat(rows, format="csr")
+    E0 = _mech.macro_tensor(eps_mac, dim, grid) - _mech.eigen_tensor(e, dim, grid)
+    K = (L.T @ C @ L).toarray()
+    f = -(L.T @ (C @ E0.reshape(-1)))
+    u = np.linalg.lstsq(K, f, rcond=1e-13)[0]
+    eps = _mech.macro_tensor(eps_mac, dim, grid) + (L @ u).reshape((dim, dim) + grid)
+    return dict(strain=_mat.to_voigt(eps))
+
+
+def diffusion_static_direct_op(Dfield, grad_cmac, h, op):
+    """diffusion_static_direct with the gradient operator `op` (least squares,
+    so extra null modes of the operator do not matter)."""
+    Dfield = np.asarray(Dfield, dtype=np.float64)
+    grid = Dfield.shape
+    dim = Dfield.ndim
+    B = [diff_matrix(grid, a, h, op) for a in range(dim)]
+    Dd = sps.diags(Dfield.ravel())
+    K = sum((B[a].T @ Dd @ B[a]) for a in range(dim)).toarray()
+    f = -sum(B[a].T @ (Dfield.ravel() * grad_cmac[a]) for a in range(dim))
+    phi = np.linalg.lstsq(K, f, rcond=1e-13)[0]
+    return np.array([grad_cmac[a] + (B[a] @ phi).reshape(grid) for a in range(dim)])

@@ -57,14 +57,14 @@ def projected_flux_operator(x, Dfield, D):
     return _fft.ifftn(_sp.project_vector(j_hat, D), _axes(dim)).real
 
 
-def diffusion_homogenise(Dfield, grad_cmac, h, tol=1e-10, maxit=20000, fixed_iters=None):
+def diffusion_homogenise(Dfield, grad_cmac, h, tol=1e-10, maxit=20000, fixed_iters=None, op="forward"):
     """Projected CG for the compatible gradient fluctuation (Sec. 2.1).
 
     Returns grad_c (dim, *grid), the flux j = -D grad c, its mean, the CG
     iteration count, the final relative residual and the status."""
     Dfield = np.asarray(Dfield, dtype=np.float64)
     grid = Dfield.shape
-    D = _sp.grad_symbols(grid, h)
+    D = _sp.grad_symbols(grid, h, op)
     g0 = macro_gradient_field(grad_cmac, grid)
     A = lambda v: projected_flux_operator(v, Dfield, D)
     b = -A(g0)
@@ -75,12 +75,12 @@ def diffusion_homogenise(Dfield, grad_cmac, h, tol=1e-10, maxit=20000, fixed_ite
                 iters=iters, rel_res=rel, status=status)
 
 
-def fluctuation_from_gradient(grad_c, h):
+def fluctuation_from_gradient(grad_c, h, op="forward"):
     """phi with grad phi = the fluctuation of grad_c (eq. phi-fft through the
     inverse gradient of eq. g-42); mean zero."""
     grad_c = np.asarray(grad_c, dtype=np.float64)
     dim = grad_c.shape[0]
-    D = _sp.grad_symbols(grad_c.shape[1:], h)
+    D = _sp.grad_symbols(grad_c.shape[1:], h, op)
     g_hat = _fft.fftn(grad_c, _axes(dim))
     phi_hat = np.sum(_sp.inverse_gradient(D) * g_hat, axis=0)
     return _fft.ifftn(phi_hat, _axes(dim)).real
@@ -98,7 +98,7 @@ def position_dot(grad_cmac, grid, h):
     return out
 
 
-def concentration(phase, grad_c, grad_cmac, c_mac, h):
+def concentration(phase, grad_c, grad_cmac, c_mac, h, op="forward"):
     """c(x) = grad c_mac . x + phi(x) + beta_phase (eqs. concentration,
     psi-two-values, concentration-correct).  Returns c, phi, beta_pore,
     beta_solid."""
@@ -107,7 +107,7 @@ def concentration(phase, grad_c, grad_cmac, c_mac, h):
     pore = phase == 0
     solid = ~pore
     eta = float(np.mean(pore))
-    phi = fluctuation_from_gradient(grad_c, h)
+    phi = fluctuation_from_gradient(grad_c, h, op)
     lin = position_dot(grad_cmac, grid, h)
     beta_pore = (c_mac / eta - float(np.mean(lin[pore])) - float(np.mean(phi[pore]))) if pore.any() else 0.0
     beta_solid = (-float(np.mean(lin[solid])) - float(np.mean(phi[solid]))) if solid.any() else 0.0
@@ -115,7 +115,7 @@ def concentration(phase, grad_c, grad_cmac, c_mac, h):
     return dict(c=c, phi=phi, beta_pore=beta_pore, beta_solid=beta_solid)
 
 
-def effective_diffusivity(Dfield, h, tol=1e-12, maxit=20000):
+def effective_diffusivity(Dfield, h, tol=1e-12, maxit=20000, op="forward"):
     """D_eff with <j> = -D_eff grad c_mac, one homogenisation per axis."""
     Dfield = np.asarray(Dfield, dtype=np.float64)
     dim = Dfield.ndim
@@ -124,7 +124,7 @@ def effective_diffusivity(Dfield, h, tol=1e-12, maxit=20000):
     for a in range(dim):
         e = np.zeros(dim)
         e[a] = 1.0
-        r = diffusion_homogenise(Dfield, e, h, tol=tol, maxit=maxit)
+        r = diffusion_homogenise(Dfield, e, h, tol=tol, maxit=maxit, op=op)
         Deff[:, a] = -r["mean_flux"]
         iters.append(r["iters"])
     return Deff, iters

@@ -71,14 +71,14 @@ def eigen_tensor(e, dim, grid):
 
 def mech_solve(phase, E_tab, nu_tab, eps_mac, h, d=None, kappa=0.0, e=None,
                tol=1e-10, maxit=20000, storage="full", E_field=None, nu=None,
-               fixed_iters=None, return_x=False):
+               fixed_iters=None, return_x=False, op="forward"):
     phase = np.asarray(phase)
     grid = phase.shape
     dim = phase.ndim
     lam, mu = voxel_lame(phase, E_tab, nu_tab, E_field, nu)
     g = np.ones(grid) if d is None else _mat.degradation(np.asarray(d), kappa)
     glam, gmu = g * lam, g * mu
-    D = _sp.grad_symbols(grid, h)
+    D = _sp.grad_symbols(grid, h, op)
     E0 = macro_tensor(eps_mac, dim, grid) - eigen_tensor(e, dim, grid)
     b = -mech_operator(E0, glam, gmu, D, storage)
     A = lambda p: mech_operator(p, glam, gmu, D, storage)

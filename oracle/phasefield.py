@@ -30,9 +30,9 @@ def pf_operator(d, H, Gc, l0, n2):
 
 
 def phasefield_solve(H, Gc, l0, h, d0=None, tol=1e-10, maxit=20000,
-                     fixed_iters=None):
+                     fixed_iters=None, op="forward"):
     H = np.asarray(H, dtype=np.float64)
-    n2 = _sp.norm2(_sp.grad_symbols(H.shape, h))
+    n2 = _sp.norm2(_sp.grad_symbols(H.shape, h, op))
     A = lambda v: pf_operator(v, H, Gc, l0, n2)
     x, iters, rel, status = _cg.cg(A, H.copy(), x0=d0, tol=tol, maxit=maxit,
                                    fixed_iters=fixed_iters)

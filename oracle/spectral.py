@@ -8,6 +8,14 @@ field has shape (dim, dim) + grid, index [i, j] meaning component x_i x_j.
 * Forward-difference gradient symbol, Sec. 2.6: D_a(k) = (exp(i theta_a) - 1)/h
   with theta_a = 2 pi k_a / n_a, which is the transform of the stencil
   (f(x + h e_a) - f(x)) / h under the forward DFT sign of ``oracle.fft``.
+  The other operators of Sec. 2.6 (the Gibbs-ringing comparison):
+  "central": i sin(theta)/h, the transform of (f(x + h) - f(x - h)) / (2 h)
+  (the printed form "(i sin(xi Delta) - 1)/Delta" is read as this);
+  "central8": the eighth-order central difference,
+  sum_{m=1..4} a_m (f(x + m h) - f(x - m h)) / h with
+  a = (4/5, -1/5, 4/105, -1/280), symbol (2 i / h) sum a_m sin(m theta);
+  "fourier": i xi = i 2 pi k / (n h) with the signed wavenumber k in
+  (-n/2, n/2), zero at the Nyquist wavenumber of even n.
 * Inverse gradient, App. A eq. g-42: (iXi)^{-1} = conj(D) / (D . conj(D)),
   zero where D . conj(D) = 0.
 * Vector projection, App. A: A_i = g_ij f_j with g_ij = D_i (iXi)^{-1}_j.
@@ -21,14 +29,29 @@ field has shape (dim, dim) + grid, index [i, j] meaning component x_i x_j.
 import numpy as np
 
 
-def diff_symbol_1d(n, h):
-    """Forward-difference symbol on n points of spacing h (Sec. 2.6)."""
+CENTRAL8 = (4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0)
+OPERATORS = ("forward", "central", "central8", "fourier")
+
+
+def diff_symbol_1d(n, h, op="forward"):
+    """Gradient symbol on n points of spacing h for the operators of Sec. 2.6."""
     k = np.arange(n)
     theta = 2.0 * np.pi * k / n
-    return (np.exp(1j * theta) - 1.0) / h
+    if op == "forward":
+        return (np.exp(1j * theta) - 1.0) / h
+    if op == "central":
+        return 1j * np.sin(theta) / h
+    if op == "central8":
+        return 2j * sum(a * np.sin((m + 1) * theta) for m, a in enumerate(CENTRAL8)) / h
+    if op == "fourier":
+        ks = np.where(k < (n + 1) // 2, k, k - n).astype(np.float64)
+        if n % 2 == 0:
+            ks[n // 2] = 0.0
+        return 1j * 2.0 * np.pi * ks / (n * h)
+    raise ValueError(op)
 
 
-def grad_symbols(grid_shape, h):
+def grad_symbols(grid_shape, h, op="forward"):
     """D_alpha over the whole grid, shape (dim,) + grid; alpha = 0 is x."""
     dim = len(grid_shape)
     out = []
@@ -36,7 +59,7 @@ def grad_symbols(grid_shape, h):
         axis = dim - 1 - alpha
         shape = [1] * dim
         shape[axis] = grid_shape[axis]
-        d1 = diff_symbol_1d(grid_shape[axis], h).reshape(shape)
+        d1 = diff_symbol_1d(grid_shape[axis], h, op).reshape(shape)
         out.append(np.broadcast_to(d1, grid_shape))
     return np.array(out)
 

@@ -132,3 +132,67 @@ def test_vector_projection_and_inverse_gradient():
     u = rng.standard_normal(grid)
     gu = np.array([_stencil(u, a, h) for a in range(2)])
     assert abs(np.sum((f - Gf.real) * gu)) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# Gradient operators of Sec. 2.6 (the Gibbs-ringing comparison)
+
+@pytest.mark.parametrize("op", ["central", "central8"])
+def test_difference_symbols_are_their_stencils(op):
+    from oracle import direct
+    grid, h = (10, 14), 0.3
+    f = np.random.default_rng(4).standard_normal(grid)
+    D = sp.grad_symbols(grid, h, op)
+    for a in range(2):
+        via_fft = fft.ifftn(D[a] * fft.fftn(f, (0, 1)), (0, 1)).real
+        stencil = (direct.diff_matrix(grid, a, h, op) @ f.ravel()).reshape(grid)
+        assert np.max(np.abs(via_fft - stencil)) < 1e-12 * np.max(np.abs(stencil))
+
+
+@pytest.mark.parametrize("n", [9, 16])
+def test_fourier_symbol_exact_on_trig_polynomials(n):
+    from oracle import direct
+    h = 0.1
+    L = n * h
+    x = h * np.arange(n)
+    f = np.sin(2 * np.pi * 2 * x / L) + 0.5 * np.cos(2 * np.pi * 3 * x / L)
+    df = (2 * np.pi / L) * (2 * np.cos(2 * np.pi * 2 * x / L) - 1.5 * np.sin(2 * np.pi * 3 * x / L))
+    D = sp.diff_symbol_1d(n, h, "fourier")
+    got = fft.ifftn(D * fft.fftn(f, (0,)), (0,)).real
+    assert np.max(np.abs(got - df)) < 1e-12 * np.max(np.abs(df))
+    # the closed-form differentiation matrix agrees (independent of the transform)
+    M = direct.diff_matrix((1, n), 0, h, "fourier").toarray()
+    assert np.max(np.abs(M @ f - df)) < 1e-11 * np.max(np.abs(df))
+
+
+def test_central8_is_eighth_order():
+    errs = []
+    for n in (16, 32):
+        h = 1.0 / n
+        x = h * np.arange(n)
+        f = np.sin(2 * np.pi * x)
+        df = 2 * np.pi * np.cos(2 * np.pi * x)
+        D = sp.diff_symbol_1d(n, h, "central8")
+        errs.append(np.max(np.abs(fft.ifftn(D * fft.fftn(f, (0,)), (0,)).real - df)))
+    assert errs[0] / errs[1] > 240  # 2^8 = 256
+
+
+@pytest.mark.parametrize("op", ["central", "central8", "fourier"])
+def test_operator_variants_reach_their_direct_solutions(op):
+    """Mechanics (symmetric storage) and the diffusion homogenisation with each
+    operator against least-squares solves of the real-space systems built
+    from the difference matrices (odd grid: the central operators have no
+    spurious Nyquist null modes there)."""
+    from oracle import direct, homogenisation as hm, mech
+    grid = (9, 15)
+    rng = np.random.default_rng(5)
+    phase = (rng.random(grid) < 0.6).astype(np.uint8)
+    e = 1e-3 * (phase == 0)
+    em = (1e-3, -2e-4, 3e-4)
+    r = mech.mech_solve(phase, (3e7, 30e9), (0.2, 0.2), em, 5e-6, e=e, tol=1e-14, maxit=20000, storage="sym", op=op)
+    q = direct.mech_direct_op(phase, (3e7, 30e9), (0.2, 0.2), em, 5e-6, op, e=e)
+    assert np.linalg.norm(r["strain"] - q["strain"]) < 1e-10 * np.linalg.norm(q["strain"])
+    Df = np.where(phase == 0, 1e-9, 1e-11)
+    g = hm.diffusion_homogenise(Df, (0.6, -0.3), 5e-6, tol=1e-14, maxit=20000, op=op)["grad_c"]
+    gd = direct.diffusion_static_direct_op(Df, (0.6, -0.3), 5e-6, op)
+    assert np.linalg.norm(g - gd) < 1e-10 * np.linalg.norm(gd)
