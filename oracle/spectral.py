@@ -39,10 +39,13 @@ def diff_symbol_1d(n, h, op="forward"):
     theta = 2.0 * np.pi * k / n
     if op == "forward":
         return (np.exp(1j * theta) - 1.0) / h
+    # sin(m theta) is exactly zero where 2 m k is a multiple of n (k = 0 and
+    # the Nyquist wavenumber): set so, rather than the rounding of sin(pi)
+    sinm = lambda m: np.where((2 * m * k) % n == 0, 0.0, np.sin(m * theta))
     if op == "central":
-        return 1j * np.sin(theta) / h
+        return 1j * sinm(1) / h
     if op == "central8":
-        return 2j * sum(a * np.sin((m + 1) * theta) for m, a in enumerate(CENTRAL8)) / h
+        return 2j * sum(a * sinm(m + 1) for m, a in enumerate(CENTRAL8)) / h
     if op == "fourier":
         ks = np.where(k < (n + 1) // 2, k, k - n).astype(np.float64)
         if n % 2 == 0:
