@@ -115,7 +115,9 @@ const char* fgcg_last_error(void);
  *       transforms in the mechanics row passes (timed jointly with the rows
  *       per block) and in the Green column pass.  1: radix 8 (with a trailing
  *       4); 2: radix 16 where it fits (fewer stages, larger butterflies); the
- *       same as 1 for lengths where radix 16 does not fit.  0 (default):
+ *       same as 1 for lengths where radix 16 does not fit; column pass only,
+ *       3: one 64-lane wavefront per column holding the column in registers
+ *       (lengths 256..2048, unit Green operator; plan 1 otherwise).  0 (default):
  *       autotune before the next mechanics solve, as for FGCG_OPT_ROWS, on
  *       grids of at least 2^18 voxels (radix 8 below; radix 16 is kept only
  *       when more than 3 % faster, so near-ties give the same schedule in
@@ -134,9 +136,28 @@ const char* fgcg_last_error(void);
  *       reference is fgcg_set_reference's, else the Lame ratio of the stiffest
  *       phase (of nu_field with a per-voxel E field).  Changing it re-tunes
  *       the 2D column plan.  EUNSUPPORTED for the groups of a batch.
+ *   FGCG_OPT_GRADIENT         the gradient operator of every solve (Sec. 2.6):
+ *       0 (default) forward difference (exp(i theta) - 1)/h; 1 central
+ *       difference i sin(theta)/h; 2 eighth-order central difference
+ *       (2 i / h) sum_m a_m sin(m theta), a = 4/5, -1/5, 4/105, -1/280; 3
+ *       Fourier i xi (signed wavenumber, zero at Nyquist).  2D grids only
+ *       (EUNSUPPORTED in 3D).  With 1..3 the mechanics and the diffusion
+ *       homogenisation run the paper's projected CG on the strain / the
+ *       concentration gradient through the transform passes (FP64), and the
+ *       phase field and the phase-table diffusion step their spectral form;
+ *       the adjoint, the per-voxel diffusion step, the operator hooks and
+ *       batches take the forward difference only (EUNSUPPORTED).  The central
+ *       operators vanish at the Nyquist wavenumber of even grids, which the
+ *       projections then leave out (checkerboard modes are not controlled).
+ *   FGCG_OPT_STRAIN_FORM      1: the strain / gradient-form solvers of
+ *       FGCG_OPT_GRADIENT with the forward difference too (2D, FP64); 0
+ *       (default): the displacement-form solvers.  Setting either option away
+ *       from its default allocates that solver's workspace (9 N doubles and
+ *       three half spectra).
  * Returns EINVAL for an unknown option or value. */
-enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2, FGCG_OPT_ROWS = 3,
-       FGCG_OPT_ROW_PLAN = 4, FGCG_OPT_COL_PLAN = 5, FGCG_OPT_PRECOND = 6 };
+enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2,
+       FGCG_OPT_ROWS = 3, FGCG_OPT_ROW_PLAN = 4, FGCG_OPT_COL_PLAN = 5, FGCG_OPT_PRECOND = 6, FGCG_OPT_GRADIENT = 7,
+       FGCG_OPT_STRAIN_FORM = 8 };
 int fgcg_set_option(fgcg_ctx* ctx, int option, int value);
 /* Reference medium of FGCG_OPT_PRECOND = 1: Lame constants (only lam0 / mu0
  * matters); (0, 0) restores the automatic choice.  EDOMAIN unless mu0 > 0 and

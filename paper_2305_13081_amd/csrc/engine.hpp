@@ -112,6 +112,10 @@ struct fgcg_ctx {
   // 2D mechanics radix plans (1: plan 0, radix 8; 2: plan 1, radix 16; 0: time both at the next solve)
   int plan_row = 0, plan_col = 0;
   int precond = 0;          // mechanics preconditioner: 0 unit Green operator, 1 isotropic reference medium
+  int gradop = 0;           // gradient operator: 0 forward, 1 central, 2 eighth-order central, 3 Fourier
+  int strain_form = 0;      // 1: mechanics and homogenisation in the paper's strain / gradient form
+  double* sf_buf = nullptr; // strain form: x, r, p (3 components each), allocated with the option
+  void* sf_spec = nullptr;  // strain form: 3 half spectra
   double ref_lam = 0, ref_mu = 0;  // reference medium set by the caller (0, 0: from the material)
   double use_lam = 0, use_mu = 0;  // reference medium of the current solve (mu = 1)
   int nsamp = 1;            // samples of this grid size (batches)
@@ -625,6 +629,37 @@ inline void resolve_reference(fgcg_ctx* c, const MechMat& m) {
   }
   c->use_lam = lam / mu;
   c->use_mu = 1.0;
+}
+
+// Gradient symbol D(k) on n points of spacing h for the operators of
+// Sec. 2.6: forward (exp(i theta) - 1)/h; central i sin(theta)/h; eighth-order
+// central (2 i / h) sum_m a_m sin(m theta), a = 4/5, -1/5, 4/105, -1/280;
+// Fourier i 2 pi k / (n h) with the signed wavenumber, zero at Nyquist.
+inline std::vector<double2> grad_symbol(int n, double h, int op) {
+  std::vector<double2> d(n);
+  for (int k = 0; k < n; ++k) {
+    const double th = 2.0 * M_PI * k / n, sh = std::sin(0.5 * th);
+    double re = 0.0, im = 0.0;
+    if (op == 0) {
+      re = -2.0 * sh * sh / h;
+      im = std::sin(th) / h;
+    } else if (op == 1 || op == 2) {
+      // sin(m theta) is exactly zero where 2 m k is a multiple of n (k = 0 and Nyquist)
+      auto sinm = [&](int m) { return (2LL * m * k) % n == 0 ? 0.0 : std::sin(m * th); };
+      if (op == 1) {
+        im = sinm(1) / h;
+      } else {
+        const double a[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+        for (int m = 0; m < 4; ++m) im += 2.0 * a[m] * sinm(m + 1);
+        im /= h;
+      }
+    } else {
+      const int ks = k < (n + 1) / 2 ? k : k - n;
+      im = (n % 2 == 0 && 2 * k == n) ? 0.0 : 2.0 * M_PI * ks / (n * h);
+    }
+    d[k] = double2{re, im};
+  }
+  return d;
 }
 
 inline int check_solver_args(double tol, int maxit) {

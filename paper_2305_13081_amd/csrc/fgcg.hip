@@ -4,6 +4,7 @@
 
 #include "adjoint.hpp"
 #include "engine.hpp"
+#include "strain_form.hpp"
 
 using namespace fgcg;
 
@@ -368,6 +369,58 @@ int mech_post(fgcg_ctx* c, const MechMat& m, const double* eig, double* strain, 
   }
   return 0;
 }
+
+// ---------------------------------------------------- strain form (2D, FP64)
+// The paper's projected CG on the symmetric strain (any gradient operator):
+// b = -G[g C : (eps_mac - e I)], then three passes per iteration (see
+// strain_form.hpp), then the post-processing of the strain.
+int mech_sf_solve(fgcg_ctx* c, const MechMat& m, const double* eig, const double* em, double tol, int maxit,
+                  double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
+  const double t0 = now();
+  const long long n = c->n;
+  CT<double>* spec = (CT<double>*)c->sf_spec;
+  const Field<double> X{c->sf_buf, n, 0}, R{c->sf_buf + 3 * n, n, 0}, P{c->sf_buf + 6 * n, n, 0};
+  int rc;
+  const VecSrcPro<double, 3, StrainLaw> src{{m}, eig, {em[0], em[1], em[2]}, c->nx, n};
+  if ((rc = launch_row_fwd<double, 3>(c, -1, src, spec))) return rc;
+  const SymProj<double> pj0{c->Dx, c->Dy, 1.0 / (double)n, nullptr};
+  if ((rc = launch_col<double, 3, 3>(c, -1, pj0, spec, spec))) return rc;
+  const VecRhsEpi<double, 3> rhs{X, R, c->nx, c->part_rr, c->part_b};
+  if ((rc = launch_row_inv<double, 3>(c, -1, rhs, spec))) return rc;
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_b, c->nrow, 0, tol, maxit);
+  HIPCHK(hipGetLastError());
+  const CgCtl cc{c->st, c->part_a, c->part_rr, c->nrow, c->nrow, 0, 0};
+  const VecCgPro<double, 3, StrainLaw> pro{P, R, {m}, c->nx, cc};
+  const SymProj<double> pj{c->Dx, c->Dy, 1.0 / (double)n, c->st};
+  const VecCgEpi<double, 3> epi{X, R, P, c->nx, cc};
+  auto iter = [&]() -> int {
+    int r = launch_row_fwd<double, 3>(c, FGCG_K_MECH_ROW_FWD, pro, spec);
+    r |= launch_col<double, 3, 3>(c, FGCG_K_MECH_COL, pj, spec, spec);
+    r |= launch_row_inv<double, 3>(c, FGCG_K_MECH_ROW_INV, epi, spec);
+    return r;
+  };
+  Key key;
+  key.add(m.phase).add(m.d).add(m.Efield).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm).add(c->gradop);
+  key.add(tol).add(maxit);
+  if ((rc = run_cg(c, 8, key, c->st, c->h_st, iter, maxit))) return rc;
+  const CgState s = *c->h_st;
+  hipLaunchKernelGGL(k_sf_post, dim3(c->npost), dim3(NT), 0, c->stream, m, (const double*)X.p, n, eig, em[0], em[1],
+                     em[2], strain, stress, c->part_post);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->h_part, c->part_post, sizeof(double) * 4 * c->npost, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double acc[4] = {0, 0, 0, 0};
+  for (int b = 0; b < c->npost; ++b)
+    for (int j = 0; j < 4; ++j) acc[j] += c->h_part[4 * b + j];
+  if (mean_stress)
+    for (int j = 0; j < 3; ++j) mean_stress[j] = acc[j] / (double)n;
+  if (energy) *energy = 0.5 * c->h * c->h * acc[3];
+  fill_info(info, s, now() - t0);
+  return status_of(s);
+}
+
+// The paths that need the forward difference's local stencil.
+inline bool forward_only(const fgcg_ctx* c) { return c->gradop != 0; }
 
 int upload_ems(fgcg_ctx* c, const double* em_host) {
   HIPCHK(hipMemcpyAsync(c->ems, em_host, sizeof(double) * 3 * c->nsamp, hipMemcpyHostToDevice, c->stream));
@@ -786,16 +839,9 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
     chk(hipHostMalloc(&c->h_part, sizeof(double) * npp, hipHostMallocDefault));
   }
   if (!rc) {
-    // forward-difference symbols D(k) = (exp(i theta) - 1)/h = (-2 sin^2(theta/2) + i sin theta)/h
-    std::vector<double2> dx(c->nxh), dy(c->ny);
-    for (int k = 0; k < c->nxh; ++k) {
-      const double th = 2.0 * M_PI * k / c->nx, sh = std::sin(0.5 * th);
-      dx[k] = double2{-2.0 * sh * sh / c->h, std::sin(th) / c->h};
-    }
-    for (int k = 0; k < c->ny; ++k) {
-      const double th = 2.0 * M_PI * k / c->ny, sh = std::sin(0.5 * th);
-      dy[k] = double2{-2.0 * sh * sh / c->h, std::sin(th) / c->h};
-    }
+    // gradient symbols, the forward difference by default:
+    // D(k) = (exp(i theta) - 1)/h = (-2 sin^2(theta/2) + i sin theta)/h
+    const std::vector<double2> dx = grad_symbol(c->nx, c->h, 0), dy = grad_symbol(c->ny, c->h, 0);
     chk(hipMemcpy(c->Dx, dx.data(), sizeof(double2) * c->nxh, hipMemcpyHostToDevice));
     chk(hipMemcpy(c->Dy, dy.data(), sizeof(double2) * c->ny, hipMemcpyHostToDevice));
   }
@@ -810,7 +856,7 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
 
 void fgcg_destroy(fgcg_ctx* c) {
   if (!c) return;
-  void* dev[] = {c->lm_dev, c->ems,  c->phase_buf, c->strain_buf, c->twx,    c->twy,    c->twx32,  c->twy32, c->twz,
+  void* dev[] = {c->sf_buf, c->sf_spec, c->lm_dev, c->ems,  c->phase_buf, c->strain_buf, c->twx,    c->twy,    c->twx32,  c->twy32, c->twz,
                  c->twz32, c->Dz,       c->red,        c->part_z, c->xh,     c->fh,     c->aux,   c->Dx,
                  c->Dy,   c->x,         c->r,          c->p,      c->tmp,    c->spec,   c->st,    c->part_a,
                  c->part_rr, c->part_b, c->part_post};
@@ -860,6 +906,32 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
       c->rows_pick = value;
       return FGCG_OK;
     }
+    case FGCG_OPT_GRADIENT:
+    case FGCG_OPT_STRAIN_FORM: {
+      const int top = option == FGCG_OPT_GRADIENT ? 3 : 1;
+      if (value < 0 || value > top) return fail(FGCG_EINVAL, "gradient 0..3, strain form 0 or 1");
+      if (c->batch) return fail(FGCG_EUNSUPPORTED, "batch groups take the forward difference");
+      if (option == FGCG_OPT_GRADIENT && value != 0 && c->ndim == 3)
+        return fail(FGCG_EUNSUPPORTED, "3D grids take the forward difference");
+      if (option == FGCG_OPT_STRAIN_FORM && value != 0 && c->ndim == 3)
+        return fail(FGCG_EUNSUPPORTED, "the strain form is 2D");
+      const int grad = option == FGCG_OPT_GRADIENT ? value : c->gradop;
+      const int sf = option == FGCG_OPT_STRAIN_FORM ? value : c->strain_form;
+      if ((grad != 0 || sf) && !c->sf_buf) {
+        // the strain form's own workspace: x, r, p of 3 components and 3 spectra
+        if (hipMalloc(&c->sf_buf, sizeof(double) * 9 * (size_t)c->n) != hipSuccess ||
+            hipMalloc(&c->sf_spec, sizeof(double2) * 3 * (size_t)c->nxh * c->ny) != hipSuccess)
+          return fail(FGCG_ENOMEM, "strain-form workspace");
+      }
+      if (option == FGCG_OPT_GRADIENT && value != c->gradop) {
+        const std::vector<double2> dx = grad_symbol(c->nx, c->h, value), dy = grad_symbol(c->ny, c->h, value);
+        HIPCHK(hipMemcpy(c->Dx, dx.data(), sizeof(double2) * c->nxh, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->Dy, dy.data(), sizeof(double2) * c->ny, hipMemcpyHostToDevice));
+        for (auto& g : c->graphs) release_graph(c, g);
+      }
+      (option == FGCG_OPT_GRADIENT ? c->gradop : c->strain_form) = value;
+      return FGCG_OK;
+    }
     case FGCG_OPT_PRECOND:
       if (value != 0 && value != 1) return fail(FGCG_EINVAL, "preconditioner must be 0 (unit) or 1 (reference)");
       if (c->batch) return fail(FGCG_EUNSUPPORTED, "batch groups take the unit Green operator");
@@ -898,6 +970,8 @@ int fgcg_get_option(fgcg_ctx* c, int option, int* value) {
     case FGCG_OPT_ROW_PLAN: *value = c->plan_row; return FGCG_OK;
     case FGCG_OPT_COL_PLAN: *value = c->plan_col; return FGCG_OK;
     case FGCG_OPT_PRECOND: *value = c->precond; return FGCG_OK;
+    case FGCG_OPT_GRADIENT: *value = c->gradop; return FGCG_OK;
+    case FGCG_OPT_STRAIN_FORM: *value = c->strain_form; return FGCG_OK;
     default: return fail(FGCG_EINVAL, "unknown option");
   }
 }
@@ -916,7 +990,12 @@ int fgcg_mech_solve(fgcg_ctx* c, const fgcg_material* mat, const double* d, doub
   if ((rc = enter(c))) return rc;
   if (c->ndim == 3) {
     if (m.Efield) return fail(FGCG_EUNSUPPORTED, "per-voxel E fields are 2D only");
+    if (c->gradop != 0 || c->strain_form) return fail(FGCG_EUNSUPPORTED, "3D mechanics takes the forward difference");
     return mech3_solve(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
+  }
+  if (c->gradop != 0 || c->strain_form) {
+    if (c->prec != FGCG_FP64) return fail(FGCG_EUNSUPPORTED, "the strain-form solver runs in FP64 contexts");
+    return mech_sf_solve(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
   }
   return mech_solve_single(c, m, eig, eps_mac, tol, maxit, strain, stress, mean_stress, energy, info);
 }
@@ -930,6 +1009,7 @@ int fgcg_mech_adjoint(fgcg_ctx* c, const fgcg_material* mat, const double* d, do
   if (objective != ADJ_USER && objective != ADJ_ENERGY && objective != ADJ_C11)
     return fail(FGCG_EINVAL, "unknown objective");
   if (objective == ADJ_USER && !dJ_dstrain) return fail(FGCG_EINVAL, "dJ_dstrain is NULL");
+  if (forward_only(c) || c->strain_form) return fail(FGCG_EUNSUPPORTED, "the adjoint takes the forward difference");
   if (objective == ADJ_C11 && !(eps_mac[0] != 0.0)) return fail(FGCG_EDOMAIN, "C11 needs eps_mac[0] != 0");
   int rc;
   if ((rc = check_solver_args(tol, maxit))) return rc;
@@ -947,8 +1027,9 @@ int fgcg_phasefield_solve(fgcg_ctx* c, const double* H, double Gc, double l0, do
   if (!(Gc > 0.0) || !std::isfinite(Gc)) return fail(FGCG_EDOMAIN, "Gc <= 0");
   if (!(l0 > 0.0) || !std::isfinite(l0)) return fail(FGCG_EDOMAIN, "l0 <= 0");
   if ((rc = enter(c))) return rc;
-  if (c->scalar_spectral && c->ndim == 3) return fail(FGCG_EUNSUPPORTED, "spectral scalar operators are 2D only");
-  if (!c->scalar_spectral) return pf_solve_stencil<double>(c, H, Gc, l0, d, tol, maxit, info);
+  const bool spectral = c->scalar_spectral || forward_only(c);
+  if (spectral && c->ndim == 3) return fail(FGCG_EUNSUPPORTED, "spectral scalar operators are 2D only");
+  if (!spectral) return pf_solve_stencil<double>(c, H, Gc, l0, d, tol, maxit, info);
   return pf_solve_t<double>(c, H, Gc, l0, d, tol, maxit, info);
 }
 
@@ -963,8 +1044,9 @@ int fgcg_diffusion_step_phases(fgcg_ctx* c, const uint8_t* phase, int nphase, co
   DiffCoef co;
   if ((rc = make_diff_coef(phase, nphase, D_tab, k_tab, dt, band_width, c->n, &co))) return rc;
   if ((rc = enter(c))) return rc;
-  if (c->scalar_spectral && c->ndim == 3) return fail(FGCG_EUNSUPPORTED, "spectral scalar operators are 2D only");
-  if (!c->scalar_spectral) {
+  const bool spectral = c->scalar_spectral || forward_only(c);
+  if (spectral && c->ndim == 3) return fail(FGCG_EUNSUPPORTED, "spectral scalar operators are 2D only");
+  if (!spectral) {
     const DiffStencil op{co, co.phase, 1.0 / (c->h * c->h)};
     Key key;
     key.add(co.phase).add(co.dk).add(co.inv_dt).add(co.band).add(op.ih2);
@@ -981,6 +1063,7 @@ int fgcg_diffusion_step(fgcg_ctx* c, double* cfield, const double* Dfield, const
   if ((rc = check_solver_args(tol, maxit))) return rc;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FGCG_EDOMAIN, "dt <= 0");
   if (!std::isfinite(c_dir)) return fail(FGCG_EDOMAIN, "c_dir not finite");
+  if (forward_only(c)) return fail(FGCG_EUNSUPPORTED, "the per-voxel diffusion step takes the forward difference");
   if ((rc = enter(c))) return rc;
   const DiffFieldStencil op{Dfield, krate, dirichlet_mask, 1.0 / dt, 1.0 / (c->h * c->h)};
   Key key;
@@ -1050,6 +1133,7 @@ int fgcg_debug_apply(fgcg_ctx* c, int op, const fgcg_material* mat, const double
                      const double* in, double* out) {
   if (!c || !in || !out) return fail(FGCG_EINVAL, "ctx/in/out is NULL");
   if (op != FGCG_OP_MECH_K && op != FGCG_OP_MECH_M) return fail(FGCG_EINVAL, "unknown operator");
+  if (forward_only(c)) return fail(FGCG_EUNSUPPORTED, "the solver operators take the forward difference");
   MechMat m;
   int rc;
   if ((rc = make_mech_mat(c, mat, d, kappa, &m))) return rc;

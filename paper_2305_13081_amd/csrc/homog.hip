@@ -7,6 +7,7 @@
 // and the inverse x transform with the direction update.
 #include "homog.hpp"
 #include "launch3d.hpp"
+#include "strain_form.hpp"
 
 using namespace fgcg;
 
@@ -89,10 +90,67 @@ int iter3(fgcg_ctx* c, const double* Df, double tol, int maxit) {
   return r;
 }
 
+// The paper's projected CG on the concentration-gradient fluctuation (2D,
+// any gradient operator): b = -G[D grad c_mac], three passes per iteration.
+// x (2 components) in c->x; phi (optional) by the inverse gradient of x.
+int homogenize_gf(fgcg_ctx* c, const double* Df, const double* gmac, double tol, int maxit, double* grad_c,
+                  double* phi, double* mean_flux, fgcg_info* info) {
+  const double t0 = now();
+  const long long n = c->n;
+  CT<double>* spec = (CT<double>*)c->spec;
+  const Field<double> X{(double*)c->x, n, 0}, R{(double*)c->r, n, 0}, P{(double*)c->p, n, 0};
+  int rc;
+  const VecSrcPro<double, 2, FluxLaw> src{{Df}, nullptr, {gmac[0], gmac[1], 0.0}, c->nx, n};
+  if ((rc = launch_row_fwd<double, 2>(c, -1, src, spec))) return rc;
+  const VecProj<double> pj0{c->Dx, c->Dy, 1.0 / (double)n, nullptr};
+  if ((rc = launch_col<double, 2, 2>(c, -1, pj0, spec, spec))) return rc;
+  const VecRhsEpi<double, 2> rhs{X, R, c->nx, c->part_rr, c->part_b};
+  if ((rc = launch_row_inv<double, 2>(c, -1, rhs, spec))) return rc;
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_b, c->nrow, 0, tol, maxit);
+  HIPCHK(hipGetLastError());
+  const CgCtl cc{c->st, c->part_a, c->part_rr, c->nrow, c->nrow, 0, 0};
+  const VecCgPro<double, 2, FluxLaw> pro{P, R, {Df}, c->nx, cc};
+  const VecProj<double> pj{c->Dx, c->Dy, 1.0 / (double)n, c->st};
+  const VecCgEpi<double, 2> epi{X, R, P, c->nx, cc};
+  auto iter = [&]() -> int {
+    int r = launch_row_fwd<double, 2>(c, -1, pro, spec);
+    r |= launch_col<double, 2, 2>(c, -1, pj, spec, spec);
+    r |= launch_row_inv<double, 2>(c, -1, epi, spec);
+    return r;
+  };
+  Key key;
+  key.add(Df).add(tol).add(maxit).add(c->gradop);
+  if ((rc = run_cg(c, 9, key, c->st, c->h_st, iter, maxit))) return rc;
+  const CgState s = *c->h_st;
+  hipLaunchKernelGGL(k_hg_post, dim3(c->npost), dim3(NT), 0, c->stream, Df, (const double*)X.p, n, gmac[0], gmac[1],
+                     grad_c, c->part_post);
+  HIPCHK(hipGetLastError());
+  if (phi) {
+    const CopyProN<double, 1> cp{Field<double>{X.p, n, n}, c->nx};
+    const long long cs = (long long)c->nxh * c->rows;
+    if ((rc = launch_row_fwd<double, 1>(c, -1, cp, spec, 2, cs))) return rc;
+    const InvGradSym<double> ig{c->Dx, c->Dy, 1.0 / (double)n};
+    if ((rc = launch_col<double, 2, 1>(c, -1, ig, spec, spec))) return rc;
+    const StoreEpi<double, 1> st{Field<double>{phi, n, 0}, Field<double>{nullptr, n, 0}, 1.0, c->nx, nullptr, 0};
+    if ((rc = launch_row_inv<double, 1>(c, -1, st, spec))) return rc;
+  }
+  HIPCHK(hipMemcpyAsync(c->h_part, c->part_post, sizeof(double) * 4 * c->npost, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double acc[4] = {0, 0, 0, 0};
+  for (int b = 0; b < c->npost; ++b)
+    for (int j = 0; j < 4; ++j) acc[j] += c->h_part[4 * b + j];
+  if (mean_flux)
+    for (int j = 0; j < 2; ++j) mean_flux[j] = acc[j] / (double)n;
+  fill_info(info, s, now() - t0);
+  return status_of(s);
+}
+
 // One homogenisation solve: phi in c->x.  Writes the mean flux (host [dim])
 // and optional grad c / phi fields.
 int homogenize(fgcg_ctx* c, const double* Df, const double* gmac, double tol, int maxit, double* grad_c,
                double* phi, double* mean_flux, double* energy_density, fgcg_info* info) {
+  if (c->ndim == 2 && (c->gradop != 0 || c->strain_form))
+    return homogenize_gf(c, Df, gmac, tol, maxit, grad_c, phi, mean_flux, info);
   const double t0 = now();
   const Vec3 gm = vec3(c, gmac);
   const int nb = c->ndim == 3 ? nslab(c) : (int)c->sgrid.x;

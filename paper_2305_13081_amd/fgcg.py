@@ -191,7 +191,9 @@ class Context:
         except Exception:
             pass
 
-    OPTIONS = {"scalar_spectral": 0, "graphs": 1, "chunk": 2, "rows": 3, "row_plan": 4, "col_plan": 5, "precond": 6}
+    OPTIONS = {"scalar_spectral": 0, "graphs": 1, "chunk": 2, "rows": 3, "row_plan": 4, "col_plan": 5, "precond": 6,
+               "gradient": 7, "strain_form": 8}
+    GRADIENTS = {"forward": 0, "central": 1, "central8": 2, "fourier": 3}
 
     def set_option(self, name, value):
         _check(self.lib.fgcg_set_option(self.ptr, self.OPTIONS[name], int(value)), "fgcg_set_option")
