@@ -353,6 +353,75 @@ typedef struct {
 int fgcg_staggered_step(fgcg_ctx* ctx, fgcg_state* state, const fgcg_params* prm,
                         fgcg_step_info* info);
 
+/* ---- multiscale coupling (Sec. 3.2) ------------------------------------ */
+/* A macroscopic bar from the steel interface Y = 0 (ion influx J_in) to
+ * Y = L (no flux) whose material points carry copies of one representative
+ * volume, the volume of a context.  The bar runs along the volume's y axis.
+ * Its flux is the volume's upscaled flux <j> = -D_eff grad c_mac (D_eff of
+ * fgcg_diffusivity_eff, computed at creation); it is advanced by finite
+ * volumes (ncell cells of width L / ncell, backward Euler, face conductance
+ * D_eff,yy / dY) and hands the volume of cell i its concentration c_mac and
+ * gradient g (the mean of the cell's two face gradients, -J_in / D_eff,yy at
+ * Y = 0).  The volume's local concentration follows eq.
+ * concentration-correct, c = g u + [pore] c_mac / eta, u the concentration of
+ * the unit gradient along y (fgcg_concentration of the homogenisation with
+ * grad c_mac = e_y and c_mac = 0, computed at creation); ions above the
+ * solubility limit S precipitate irreversibly, c_ppt = max(c_ppt, (c - S)_+)
+ * in the pores; the eigenstrain is e = (c_ppt M_ppt - 1)_+ (eq.
+ * eigen-simplify); then, as in Alg. 1, the mechanics with eps_mac = 0 and the
+ * damage of the previous step, the history and the phase field. */
+typedef struct {
+  int ncell;           /* bar cells, >= 2 */
+  double length;       /* bar length L (m), > 0 */
+  double dt;           /* time step (s), > 0 */
+  double J_in;         /* influx at Y = 0 (mol / (m^2 s)), >= 0 */
+  double solubility;   /* S (mol / m^3), >= 0 */
+  double molar_volume; /* M_ppt (m^3 / mol), >= 0 */
+  double Gc, l0;       /* phase field, > 0 */
+  double kappa;        /* residual stiffness, >= 0 */
+  double tol;          /* CG tolerance of the mechanics and phase-field solves */
+  double tol_homog;    /* CG tolerance of the homogenisations at creation */
+  int maxit;           /* CG iteration cap of every solve, >= 1 */
+} fgcg_ms_params;
+
+typedef struct {
+  double c_mac, grad_mac;  /* concentration and gradient of the volume's cell */
+  double mean_cppt;        /* volume mean of c_ppt */
+  double max_e, max_d;     /* maxima of the eigenstrain and of the damage */
+  double mean_stress[6];   /* n_s entries used */
+  double energy;
+  fgcg_info mech, pf;
+} fgcg_ms_info;
+
+typedef struct fgcg_ms fgcg_ms;
+
+/* Create the bar (c_bar = 0) and nrve volumes placed in the cells rve_cells
+ * (host [nrve], 0..ncell-1; several volumes may share a cell), all of them
+ * with zero precipitate, history and damage.  ctx: an FP64 context of the
+ * volume's grid (2D or 3D), used by every call and to outlive the object;
+ * mat: phase tables (E_field NULL; mat->phase device [N], kept by pointer,
+ * pores are phase 0 and must exist); D_rve: device [N] diffusion coefficient
+ * per voxel, read at creation only.  Allocates 8 N (2D) or 11 N (3D) doubles
+ * per volume.  EINVAL for NULL pointers or a cell outside the bar; EDOMAIN for
+ * a parameter outside its domain, a volume without pores or D_eff,yy <= 0;
+ * EUNSUPPORTED for FP32-mixed or batch contexts; homogenisation errors as
+ * fgcg_diffusion_homogenize. */
+int fgcg_ms_create(fgcg_ctx* ctx, const fgcg_material* mat, const double* D_rve, const fgcg_ms_params* prm,
+                   int nrve, const int* rve_cells, fgcg_ms** out);
+/* One time step: the bar, then every volume in turn.  infos: host [nrve] or
+ * NULL.  Returns FGCG_OK, the worst non-converged status of the volume solves,
+ * or the first error. */
+int fgcg_ms_step(fgcg_ms* ms, fgcg_ms_info* infos);
+/* The bar: c_bar, grad_bar host [ncell], D_eff host [dim][dim], time host [1];
+ * each may be NULL. */
+int fgcg_ms_read(const fgcg_ms* ms, double* c_bar, double* grad_bar, double* D_eff, double* time);
+/* Copy the state of volume rve into device buffers (each may be NULL): the
+ * local concentration, c_ppt, e, H, d [N] and the strain [n_s][N] of the
+ * last step. */
+int fgcg_ms_volume(const fgcg_ms* ms, int rve, double* c, double* cppt, double* e, double* H, double* d,
+                   double* strain);
+void fgcg_ms_destroy(fgcg_ms* ms);
+
 /* ---- no allocation --------------------------------------------------- */
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of

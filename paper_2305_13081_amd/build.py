@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfgcg.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fgcg.hip", "fgcg3d.hip", "homog.hip", "noalloc.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fgcg.hip", "fgcg3d.hip", "homog.hip", "noalloc.hip", "multiscale.hip")]
 
 COMPILE_FLAGS = [
     "--offload-arch=gfx950",

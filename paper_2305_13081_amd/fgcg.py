@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfgcg.so")
 
 FGCG_OK, FGCG_NOT_CONVERGED = 0, 1
+FGCG_EINVAL, FGCG_EDOMAIN, FGCG_EBREAKDOWN, FGCG_ENOMEM, FGCG_EHIP, FGCG_EUNSUPPORTED = -1, -2, -3, -4, -5, -6
 FP64, FP32_MIXED = 0, 1
 J_USER, J_ENERGY, J_C11 = 0, 1, 2
 OP_MECH_K, OP_MECH_M = 0, 1
@@ -81,6 +82,24 @@ class StepInfo(ctypes.Structure):
                     total_precipitate=self.total_precipitate)
 
 
+class MsParams(ctypes.Structure):
+    _fields_ = [("ncell", ctypes.c_int), ("length", ctypes.c_double), ("dt", ctypes.c_double),
+                ("J_in", ctypes.c_double), ("solubility", ctypes.c_double), ("molar_volume", ctypes.c_double),
+                ("Gc", ctypes.c_double), ("l0", ctypes.c_double), ("kappa", ctypes.c_double), ("tol", ctypes.c_double),
+                ("tol_homog", ctypes.c_double), ("maxit", ctypes.c_int)]
+
+
+class MsInfo(ctypes.Structure):
+    _fields_ = [("c_mac", ctypes.c_double), ("grad_mac", ctypes.c_double), ("mean_cppt", ctypes.c_double),
+                ("max_e", ctypes.c_double), ("max_d", ctypes.c_double), ("mean_stress", ctypes.c_double * 6),
+                ("energy", ctypes.c_double), ("mech", Info), ("pf", Info)]
+
+    def as_dict(self, ns):
+        return dict(c_mac=self.c_mac, grad_mac=self.grad_mac, mean_cppt=self.mean_cppt, max_e=self.max_e,
+                    max_d=self.max_d, mean_stress=list(self.mean_stress)[:ns], energy=self.energy,
+                    mech=self.mech.as_dict(), pf=self.pf.as_dict())
+
+
 _lib = None
 _vp, _dp, _ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
 _SIGS = {
@@ -121,6 +140,12 @@ _SIGS = {
     "fgcg_profile": (_ip, [_vp, ctypes.c_uint]),
     "fgcg_profile_read": (_ip, [_vp, _ip, _dp, ctypes.POINTER(ctypes.c_longlong)]),
     "fgcg_kernel_name": (ctypes.c_char_p, [_vp, _ip]),
+    "fgcg_ms_create": (_ip, [_vp, ctypes.POINTER(Material), _vp, ctypes.POINTER(MsParams), _ip,
+                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_vp)]),
+    "fgcg_ms_step": (_ip, [_vp, ctypes.POINTER(MsInfo)]),
+    "fgcg_ms_read": (_ip, [_vp, _dp, _dp, _dp, _dp]),
+    "fgcg_ms_volume": (_ip, [_vp, _ip, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fgcg_ms_destroy": (None, [_vp]),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -583,3 +608,69 @@ class Batch:
         _check(st, "fgcg_mech_solve_batched", allow_nc=True)
         return dict(strains=strains, mean_stress=np.array(list(mean)).reshape(self.nb, 3),
                     energy=np.array(list(en)), infos=[i.as_dict() for i in infos])
+
+
+class Multiscale:
+    """The multiscale coupling of Sec. 3.2 (fgcg_ms_*): a bar of prm["ncell"]
+    cells carrying copies of the context's volume in the cells `cells`.
+    prm: the fields of fgcg_ms_params (oracle.multiscale's BarParams and
+    RveParams hold the same names).  The context must outlive the object."""
+
+    FIELDS = ("c", "cppt", "e", "H", "d", "strain")
+
+    def __init__(self, ctx, phase, E_tab, nu_tab, D_field, prm, cells):
+        torch = _torch()
+        self.ctx, self.lib = ctx, ctx.lib
+        ctx._t(D_field, "D_field", torch.float64)
+        m, keep = ctx._material(phase, E_tab, nu_tab)
+        self._phase = phase  # the library keeps the phase by pointer
+        self.ncell, self.nrve = int(prm["ncell"]), len(cells)
+        p = MsParams(self.ncell, float(prm["length"]), float(prm["dt"]), float(prm["J_in"]),
+                     float(prm["solubility"]), float(prm["molar_volume"]), float(prm["Gc"]), float(prm["l0"]),
+                     float(prm.get("kappa", 0.0)), float(prm.get("tol", 1e-10)), float(prm.get("tol_homog", 1e-12)),
+                     int(prm.get("maxit", 20000)))
+        cl = (ctypes.c_int * max(1, self.nrve))(*[int(c) for c in cells])
+        out = _vp()
+        ctx._sync_stream()
+        _check(self.lib.fgcg_ms_create(ctx.ptr, ctypes.byref(m), ctx._ptr(D_field), ctypes.byref(p), self.nrve, cl,
+                                       ctypes.byref(out)), "fgcg_ms_create")
+        self.ptr = out
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            self.lib.fgcg_ms_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self):
+        infos = (MsInfo * max(1, self.nrve))()
+        self.ctx._sync_stream()
+        _check(self.lib.fgcg_ms_step(self.ptr, infos), "fgcg_ms_step", allow_nc=True)
+        return [infos[i].as_dict(self.ctx.ns) for i in range(self.nrve)]
+
+    def bar(self):
+        dim = self.ctx.ndim
+        c = (ctypes.c_double * self.ncell)()
+        g = (ctypes.c_double * self.ncell)()
+        D = (ctypes.c_double * (dim * dim))()
+        t = ctypes.c_double()
+        _check(self.lib.fgcg_ms_read(self.ptr, c, g, D, ctypes.byref(t)), "fgcg_ms_read")
+        return dict(c=np.array(list(c)), grad=np.array(list(g)), D_eff=np.array(list(D)).reshape(dim, dim),
+                    time=t.value)
+
+    def volume(self, rve):
+        """The state of volume rve after the last step: a dict of float64
+        CUDA tensors (strain with a leading component axis)."""
+        torch = _torch()
+        ctx = self.ctx
+        f = {k: torch.empty(((ctx.ns,) if k == "strain" else ()) + ctx.shape, dtype=torch.float64,
+                            device=ctx.device) for k in self.FIELDS}
+        ctx._sync_stream()
+        _check(self.lib.fgcg_ms_volume(self.ptr, int(rve), *[ctx._ptr(f[k]) for k in self.FIELDS]),
+               "fgcg_ms_volume")
+        return f
