@@ -117,8 +117,15 @@ def rve_setup(phase, prm):
     phase = np.asarray(phase)
     Df = np.asarray(prm.D_tab)[phase]
     Deff, _ = _hm.effective_diffusivity(Df, prm.h, tol=prm.tol, maxit=prm.maxit)
-    unit = _hm.diffusion_homogenise(Df, (0.0, 1.0), prm.h, tol=prm.tol, maxit=prm.maxit)
+    unit = _hm.diffusion_homogenise(Df, _along_y(1.0, phase.ndim), prm.h, tol=prm.tol, maxit=prm.maxit)
     return Deff, unit["grad_c"]
+
+
+def _along_y(g, dim):
+    """The vector g e_y (components ordered x, y[, z])."""
+    v = [0.0] * dim
+    v[1] = g
+    return tuple(v)
 
 
 def rve_initial(phase):
@@ -127,20 +134,21 @@ def rve_initial(phase):
 
 
 def rve_step(phase, st, grad_c_unit, g, c_mac, prm):
-    """One RVE update for the macroscopic gradient g (along y) and
+    """One RVE update (2D or 3D) for the macroscopic gradient g (along y) and
     concentration c_mac: local concentration (eq. concentration-correct with
     grad c = g grad_c_unit), precipitation, eigenstrain (eq. eigen-simplify),
     mechanics with the previous damage, history, phase field."""
     phase = np.asarray(phase)
+    dim = phase.ndim
     pore = phase == 0
-    rec = _hm.concentration(phase, g * np.asarray(grad_c_unit), (0.0, g), c_mac, prm.h)
+    rec = _hm.concentration(phase, g * np.asarray(grad_c_unit), _along_y(g, dim), c_mac, prm.h)
     c = rec["c"]
     cppt = np.where(pore, np.maximum(st.cppt, np.maximum(c - prm.solubility, 0.0)), 0.0)
     e = np.where(pore, np.maximum(cppt * prm.molar_volume - 1.0, 0.0), 0.0)
-    m = _mech.mech_solve(phase, prm.E_tab, prm.nu_tab, (0.0, 0.0, 0.0), prm.h, d=st.d, kappa=prm.kappa, e=e,
-                         tol=prm.tol, maxit=prm.maxit)
+    m = _mech.mech_solve(phase, prm.E_tab, prm.nu_tab, (0.0,) * (3 if dim == 2 else 6), prm.h, d=st.d,
+                         kappa=prm.kappa, e=e, tol=prm.tol, maxit=prm.maxit)
     lam, mu = _mech.voxel_lame(phase, prm.E_tab, prm.nu_tab)
-    el = _mat.from_voigt(m["strain"], 2) - _mech.eigen_tensor(e, 2, phase.shape)
+    el = _mat.from_voigt(m["strain"], dim) - _mech.eigen_tensor(e, dim, phase.shape)
     H = np.maximum(st.H, _mat.psi_plus(el, lam, mu))
     p = _pf.phasefield_solve(H, prm.Gc, prm.l0, prm.h, d0=st.d, tol=prm.tol, maxit=prm.maxit)
     info = dict(c=c, mean_stress=m["mean_stress"], mean_cppt=float(cppt.mean()), max_d=float(p["d"].max()))

@@ -7,7 +7,7 @@
 * one RVE update equals the same update assembled from the reconstruction
   formula written out, the sparse direct solvers and eq. energy by hand; the
   eigenstrain switches on only past the threshold of eq. eigen-simplify, and
-  only in the pores.
+  only in the pores; the same in 3D on a sphere pore.
 """
 import numpy as np
 import pytest
@@ -94,3 +94,42 @@ def test_rve_step_matches_assembled(c_mac, g):
         assert st.e.max() > 0 and st.d.max() > 1e-2
     else:
         assert st.e.max() == 0.0  # below the threshold c_ppt M_ppt = 1: no eigenstrain
+
+
+def _psi_plus_3d_by_hand(strain, e, lam, mu):
+    """Amor split in 3D written out: K/2 <tr>_+^2 + mu dev:dev, K = lam + 2 mu / 3,
+    strain in Voigt order 11, 22, 33, 23, 13, 12 (tensor shear components)."""
+    l = [strain[0] - e, strain[1] - e, strain[2] - e]
+    tr = l[0] + l[1] + l[2]
+    dev = sum((li - tr / 3.0) ** 2 for li in l) + 2.0 * (strain[3] ** 2 + strain[4] ** 2 + strain[5] ** 2)
+    return 0.5 * (lam + 2.0 * mu / 3.0) * np.maximum(tr, 0.0) ** 2 + mu * dev
+
+
+def test_rve_step_3d_matches_assembled():
+    n = 8
+    z, y, x = np.meshgrid(*(np.arange(n),) * 3, indexing="ij")
+    phase = np.where((x - 3.5) ** 2 + (y - 3.5) ** 2 + (z - 3.5) ** 2 <= 2.6 ** 2, 0, 1).astype(np.uint8)
+    prm = ms.RveParams(E_tab=(3e8, 30e9), Gc=10.0, tol=1e-14)
+    _, gcu = ms.rve_setup(phase, prm)
+    assert gcu.shape == (3, n, n, n)
+    st = ms.rve_initial(phase)
+    pore = phase == 0
+    eta = pore.mean()
+    cm, g = 9e3 * eta / 0.2, -1e7
+    nxt = ms.rve_step(phase, st, gcu, g, cm, prm)
+    Df = np.asarray(prm.D_tab)[phase]
+    phi = direct.diffusion_static_direct(Df, (0.0, 1.0, 0.0), prm.h)["phi"]
+    u = prm.h * y + phi
+    c = g * u + np.where(pore, cm / eta - g * u[pore].mean(), -g * u[~pore].mean())
+    cppt = np.where(pore, np.maximum(c - prm.solubility, 0.0), 0.0)
+    e = np.where(pore, np.maximum(cppt * prm.molar_volume - 1.0, 0.0), 0.0)
+    m = direct.mech_direct(phase, prm.E_tab, prm.nu_tab, (0.0,) * 6, prm.h, kappa=prm.kappa, e=e)
+    E, nu = np.asarray(prm.E_tab)[phase], np.asarray(prm.nu_tab)[phase]
+    lam, mu = E * nu / ((1 + nu) * (1 - 2 * nu)), E / (2 * (1 + nu))
+    H = _psi_plus_3d_by_hand(m["strain"], e, lam, mu)
+    d = direct.phasefield_direct(H, prm.Gc, prm.l0, prm.h)
+    assert np.max(np.abs(nxt.info["c"] - c)) < 1e-10 * np.max(np.abs(c))
+    assert e.max() > 0
+    for k, ref in (("cppt", cppt), ("e", e), ("H", H), ("d", d), ("strain", m["strain"])):
+        got = getattr(nxt, k)
+        assert np.linalg.norm(got - ref) <= 1e-10 * max(np.linalg.norm(ref), 1e-300), k
