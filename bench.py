@@ -36,6 +36,7 @@ each with its accuracy.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -81,17 +82,29 @@ KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "
 # recorded under profiles/ (scaled by the copy probe), valid only for the
 # kernel sources they were taken with: the key is the SHA-256 of csrc/.
 MEASURED_TRAFFIC = {
-    # source hash -> {kernel kind: bytes per launch} (profiles/mech_passes_1024_fp64_hbm_traffic.md)
-    "8d301cbbde4c3767e7a9541f1bed809ee4c7631450803f647895fd84a33924db": {
-        "mech_row_fwd": 115270323, "mech_row_inv": 49748638, "mech_kp": 42398901, "mech_col": 33165914},
+    # hash of the 2D pass sources -> {kernel kind: HBM bytes per launch}
+    # (profiles/mech_passes_1024_fp64_hbm_traffic.md)
+    "6f1f5b4865647e0a01d6dc8f0bc2a84dc43e112fee035d60aedc7569465e5c2e": {
+        "mech_row_fwd": 115252675, "mech_row_inv": 49761511, "mech_kp": 42384179, "mech_col": 33274118},
 }
 
 
 def csrc_hash():
+    """SHA-256 over the translation unit of the 2D passes: fgcg.hip and every
+    header it includes (transitively), so that a change to another source
+    keeps the measured traffic valid and a change to these voids it."""
     import hashlib
     d = os.path.join(ROOT, "paper_2305_13081_amd", "csrc")
+    seen, todo = set(), ["fgcg.hip"]
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(os.path.join(d, f)):
+            continue
+        seen.add(f)
+        with open(os.path.join(d, f)) as fh:
+            todo += [m for m in re.findall(r'^#include "([^"]+)"', fh.read(), re.M)]
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
+    for f in sorted(seen):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
