@@ -382,8 +382,8 @@ int launch_col(fgcg_ctx* c, int kind, const Sym& sym, const CT<T>* in, CT<T>* ou
     if constexpr (TUNED && NIN == 1 && NOUT == 1 && wave_col_ok(NY)) {
       if (c->plan_col == 3) {
         if (kind >= 0) set_kname(c, kind, "k_colw<%s, %d", tname<T>(), NY);
-        rc = launch_b(c, kind, (const void*)&k_colw<T, NY, Sym>, dim3(c->nxh, nsamp), dim3(64), sym, in, out,
-                      c->nxh, ss, ss, tw_y<T>(c));
+        const void* fn = c->nsamp == 1 ? (const void*)&k_colw<T, NY, Sym, true> : (const void*)&k_colw<T, NY, Sym, false>;
+        rc = launch_b(c, kind, fn, dim3(c->nxh, nsamp), dim3(64), sym, in, out, c->nxh, ss, ss, tw_y<T>(c));
         return;
       }
     }

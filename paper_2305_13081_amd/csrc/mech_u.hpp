@@ -370,17 +370,20 @@ template <typename T, int NC = 2> struct MechGreen {
   const CgState* st;  // nullable
   double* part;       // nullable
   __device__ bool begin(int s2, double*, double&) const { return st == nullptr || cg_running(st, s2 / NC); }
-  // the column pass loads D_y of its modes before the forward transform
-  using Pre = double2;
-  __device__ Pre pre(int, int ky) const { return Dy[ky]; }
-  template <typename C>
-  __device__ void mode(int s2, int kx, int ky, const C* a, C* b, double& acc, double sc) const {
-    mode_pre(s2, kx, ky, Dy[ky], a, b, acc, sc);
+  // the column pass loads |D_y|^2 of its modes before the forward transform
+  using Pre = double;
+  __device__ Pre pre(int, int ky) const {
+    const double2 d = Dy[ky];
+    return d.x * d.x + d.y * d.y;
   }
   template <typename C>
-  __device__ void mode_pre(int, int kx, int, const double2 d2, const C* a, C* b, double& acc, double) const {
+  __device__ void mode(int s2, int kx, int ky, const C* a, C* b, double& acc, double sc) const {
+    mode_pre(s2, kx, ky, pre(kx, ky), a, b, acc, sc);
+  }
+  template <typename C>
+  __device__ void mode_pre(int, int kx, int, const double dy2, const C* a, C* b, double& acc, double) const {
     const double2 d1 = Dx[kx];
-    const double n2 = d1.x * d1.x + d1.y * d1.y + d2.x * d2.x + d2.y * d2.y;
+    const double n2 = (d1.x * d1.x + d1.y * d1.y) + dy2;
     if (n2 == 0.0) {
       b[0] = C{(T)0, (T)0};
       return;

@@ -314,13 +314,39 @@ constexpr WPlan wave_plan(int N) {
 }
 constexpr bool wave_col_ok(int N) { return wave_plan(N).nst > 0; }
 
-// One stage (radix R, sub-transform length NS) on the lane's elements V.
+// Twiddles of the stages before stage ST: a lane holds B = E / R of them for
+// every stage after the first (one per butterfly), loaded once per kernel;
+// the inverse transform uses their conjugates.
+constexpr int wave_tw_before(int N, int ST) {
+  int t = 0;
+  for (int i = 1; i < ST; ++i) t += N / 64 / wave_plan(N).r[i];
+  return t;
+}
+constexpr int wave_tw_count(int N) { return wave_tw_before(N, wave_plan(N).nst); }
+
+// Load the lane's twiddles: stage ST (sub-transform length NS, radix R),
+// butterfly q takes w = exp(-2 pi i k / (NS R)), k = (l + 64 q) mod NS.
+template <typename T, int N, int ST, int NS>
+__device__ __forceinline__ void wave_tw_load(typename cvec<T>::type* W, const typename cvec<T>::type* __restrict__ tw) {
+  constexpr WPlan p = wave_plan(N);
+  if constexpr (ST < p.nst) {
+    constexpr int R = p.r[ST];
+    if constexpr (ST > 0) {
+      constexpr int B = N / 64 / R, TSTEP = N / (NS * R), OFF = wave_tw_before(N, ST);
+#pragma unroll
+      for (int q = 0; q < B; ++q) W[OFF + q] = tw[((threadIdx.x + 64 * q) % NS) * TSTEP];
+    }
+    wave_tw_load<T, N, ST + 1, NS * R>(W, tw);
+  }
+}
+
+// One stage (radix R, sub-transform length NS) on the lane's elements V, with
+// the lane's twiddles of this stage in W[0 .. B).
 template <typename T, int N, int R, int NS, bool INV, bool LAST>
 __device__ __forceinline__ void wave_stage(typename cvec<T>::type* V, typename cvec<T>::type* buf,
-                                           const typename cvec<T>::type* __restrict__ tw) {
+                                           const typename cvec<T>::type* W) {
   using C = typename cvec<T>::type;
   constexpr int E = N / 64, B = E / R;  // butterflies per lane
-  constexpr int TSTEP = N / (NS * R);
   const int l = threadIdx.x;
 #pragma unroll
   for (int q = 0; q < B; ++q) {
@@ -328,8 +354,7 @@ __device__ __forceinline__ void wave_stage(typename cvec<T>::type* V, typename c
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = V[q + r * B];
     if (NS > 1) {
-      const int k = (l + 64 * q) % NS;
-      C w1 = tw[k * TSTEP];
+      C w1 = W[q];
       if (INV) w1.y = -w1.y;
       C w = w1;
 #pragma unroll
@@ -361,42 +386,52 @@ __device__ __forceinline__ void wave_stage(typename cvec<T>::type* V, typename c
 
 template <typename T, int N, bool INV, int ST, int NS>
 __device__ __forceinline__ void wave_fft(typename cvec<T>::type* V, typename cvec<T>::type* buf,
-                                         const typename cvec<T>::type* __restrict__ tw) {
+                                         const typename cvec<T>::type* W) {
   constexpr WPlan p = wave_plan(N);
   if constexpr (ST < p.nst) {
     constexpr int R = p.r[ST];
-    wave_stage<T, N, R, NS, INV, ST + 1 == p.nst>(V, buf, tw);
-    wave_fft<T, N, INV, ST + 1, NS * R>(V, buf, tw);
+    wave_stage<T, N, R, NS, INV, ST + 1 == p.nst>(V, buf, W + (ST > 0 ? wave_tw_before(N, ST) : 0));
+    wave_fft<T, N, INV, ST + 1, NS * R>(V, buf, W);
   }
 }
 
 __device__ __forceinline__ double wave_sum64(double v) { return wave_sum(v); }
 
 // One-component column pass (NIN = NOUT = 1) for the Green symbols: block
-// (kx, s) of 64 threads.  Same contract as k_col<T, NY, 1, 1, Sym>.
-template <typename T, int NY, class Sym>
+// (kx, s) of 64 threads.  Same contract as k_col<T, NY, 1, 1, Sym>.  The
+// lane's column elements, twiddles and symbol data are loaded together at the
+// start; with EARLY (single-sample contexts, where no block can find its
+// sample's solve ended while others run) before the state check, so its
+// latency overlaps theirs.
+template <typename T, int NY, class Sym, bool EARLY>
 __global__ void __launch_bounds__(64) k_colw(Sym sym, const typename cvec<T>::type* spec_in,
                                              typename cvec<T>::type* spec_out, int nxh, long long ss_in,
                                              long long ss_out, const typename cvec<T>::type* __restrict__ tw) {
   using C = typename cvec<T>::type;
   constexpr int E = NY / 64;
+  constexpr int NW = wave_tw_count(NY) > 0 ? wave_tw_count(NY) : 1;
   __shared__ C buf[lds_size(NY)];
   __shared__ double red[1];
   const int s = blockIdx.y;
   const int kx = blockIdx.x;
   const int l = threadIdx.x;
-  double sc = 0.0;
-  if (!sym.begin(s, red, sc)) return;
   const C* in = spec_in + s * ss_in + (long long)kx * NY;
-  C V[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) V[m] = in[l + 64 * m];
+  C V[E], W[NW];
   typename SymPre<Sym>::type spre[E];
-  if constexpr (SymPre<Sym>::value) {
+  auto load = [&]() {
 #pragma unroll
-    for (int m = 0; m < E; ++m) spre[m] = sym.pre(kx, l + 64 * m);
-  }
-  wave_fft<T, NY, false, 0, 1>(V, buf, tw);
+    for (int m = 0; m < E; ++m) V[m] = in[l + 64 * m];
+    wave_tw_load<T, NY, 0, 1>(W, tw);
+    if constexpr (SymPre<Sym>::value) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) spre[m] = sym.pre(kx, l + 64 * m);
+    }
+  };
+  double sc = 0.0;
+  if constexpr (EARLY) load();
+  if (!sym.begin(s, red, sc)) return;
+  if constexpr (!EARLY) load();
+  wave_fft<T, NY, false, 0, 1>(V, buf, W);
   double acc = 0.0;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -409,7 +444,7 @@ __global__ void __launch_bounds__(64) k_colw(Sym sym, const typename cvec<T>::ty
   }
   acc = wave_sum64(acc);
   sym.partial(s, acc);
-  wave_fft<T, NY, true, 0, 1>(V, buf, tw);
+  wave_fft<T, NY, true, 0, 1>(V, buf, W);
   C* out = spec_out + s * ss_out + (long long)kx * NY;
 #pragma unroll
   for (int m = 0; m < E; ++m) out[l + 64 * m] = V[m];
