@@ -65,6 +65,17 @@ ALGO_BYTES = {
 }
 
 
+# The residual-spectrum PCG (FP64 2D contexts with nx a multiple of 256, the
+# library's default there): three passes per iteration,
+#   row_fwd (k_kp_fwd): read p (16), phase (1), damage (8); write 2 spectra
+#            (the timing hook reads an 8-byte E field instead of phase and damage)
+#   col    : read 2 spectra of q and 2 of r, write 2 of r and 2 of z
+#   row_inv: read 2 spectra, p and x (32); write p and x (32)
+def algo_bytes_sr(n, timing=False):
+    sp = 16.0 * (n // 2 + 1) / n
+    return {"mech_row_fwd": 16 + (8 if timing else 9) + 2 * sp, "mech_col": 8 * sp, "mech_row_inv": 2 * sp + 64}
+
+
 # 3D (256^3) mechanics passes, bytes per voxel with w-byte words (3
 # displacement components; half spectrum 129/256 of a word per component and
 # direction of storage, complex = 2 words): kp reads p, phase, damage and
@@ -370,7 +381,10 @@ def hbm_resident_passes(torch, fgcg, dev, n=2048, reps=100):
     ctx = fgcg.Context(n, n, H)
     spec_b = 16.0 * (n // 2 + 1) / n
     ab = {"mech_row_fwd": 64 + 32 + 2 * spec_b, "mech_col": 4 * spec_b, "mech_row_inv": 2 * spec_b + 32}
-    out = {}
+    sr = ctx.get_option("spectral_residual") == 1
+    if sr:
+        ab = algo_bytes_sr(n, timing=True)
+    out = {"iteration": "three passes, residual spectrum" if sr else "four passes"}
     for k in ("mech_row_fwd", "mech_col", "mech_row_inv"):
         us = ctx.time_pass(k, reps)
         gbs = ab[k] * n * n / (us * 1e-6) / 1e9
@@ -489,7 +503,11 @@ def main():
     ctx = fgcg.Context(N_SIDE, N_SIDE, H)
     prm = c2_params()
     state = ctx.new_state(band_width=prm["band_width"], c_dir=prm["c_dir"])
-    mech_kinds = ["mech_kp", "mech_row_fwd", "mech_col", "mech_row_inv"]
+    sr = ctx.get_option("spectral_residual") == 1
+    mech_kinds = ["mech_row_fwd", "mech_col", "mech_row_inv"] if sr else \
+        ["mech_kp", "mech_row_fwd", "mech_col", "mech_row_inv"]
+    algo = algo_bytes_sr(N_SIDE) if sr else ALGO_BYTES
+    algo_timing = algo_bytes_sr(N_SIDE, timing=True) if sr else ALGO_BYTES
     for w in range(args.warmup):
         if w == args.warmup - 1:
             ctx.profile(mech_kinds)  # last warm-up step: find the dominant pass
@@ -525,14 +543,17 @@ def main():
     # back to back between two events right after the timed steps: no event
     # node between launches, so no dispatch gap is added to each launch
     avg_s = in_graph_s
-    if dom in ("mech_row_fwd", "mech_row_inv", "mech_col"):
+    by_hook = dom in ("mech_row_fwd", "mech_row_inv", "mech_col")
+    if by_hook:
         avg_s = ctx.time_pass(dom, 200) * 1e-6
-    achieved = ALGO_BYTES[dom] * nvox / avg_s / 1e9
+    # (the timing hook's stiffness pass reads a per-voxel E field: its bytes)
+    dom_bytes = (algo_timing if by_hook else algo)[dom]
+    achieved = dom_bytes * nvox / avg_s / 1e9
     tr = MEASURED_TRAFFIC.get(csrc_hash(), {}).get(dom)
     per_kernel = {k: {"avg_us": prof[k][0] * 1e3 / max(prof[k][1], 1), "launches": prof[k][1],
                       "timed_in": "timed steps" if k == dom else "last warm-up step",
-                      "algo_bytes_per_voxel": round(ALGO_BYTES[k], 3),
-                      "achieved_GBs": ALGO_BYTES[k] * nvox / (prof[k][0] / 1e3 / max(prof[k][1], 1)) / 1e9,
+                      "algo_bytes_per_voxel": round(algo[k], 3),
+                      "achieved_GBs": algo[k] * nvox / (prof[k][0] / 1e3 / prof[k][1]) / 1e9 if prof[k][1] else None,
                       "kernel": prof[k][2]} for k in mech_kinds}
     out = {
         "metric": "voxel-CG-iters/s",
@@ -558,7 +579,8 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kname,
-                     "algo_bytes_per_launch": ALGO_BYTES[dom] * nvox, "avg_launch_us": avg_s * 1e6,
+                     "algo_bytes_per_launch": dom_bytes * nvox, "avg_launch_us": avg_s * 1e6,
+                     "iteration": "three passes, residual spectrum" if sr else "four passes",
                      "in_graph_event_us": in_graph_s * 1e6,
                      "timing": "avg_launch_us: HIP events on the library stream around 200 back-to-back "
                                "launches of the kernel (the tuned configuration, on the workspace of this "

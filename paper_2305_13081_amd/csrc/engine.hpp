@@ -114,6 +114,8 @@ struct fgcg_ctx {
   int precond = 0;          // mechanics preconditioner: 0 unit Green operator, 1 isotropic reference medium
   int gradop = 0;           // gradient operator: 0 forward, 1 central, 2 eighth-order central, 3 Fourier
   int strain_form = 0;      // 1: mechanics and homogenisation in the paper's strain / gradient form
+  int sr_opt = 1;           // 1: the residual-spectrum mechanics PCG where it applies (sr_active)
+  void* rhat = nullptr;     // residual-spectrum PCG: the residual's half spectra [nsamp][2][nxh][ny]
   double* sf_buf = nullptr; // strain form: x, r, p (3 components each), allocated with the option
   void* sf_spec = nullptr;  // strain form: 3 half spectra
   double ref_lam = 0, ref_mu = 0;  // reference medium set by the caller (0, 0: from the material)
@@ -590,6 +592,15 @@ inline int make_mech_mat(const fgcg_ctx* c, const fgcg_material* mat, const doub
 
 // A running CG state for every sample (unit r.z, no stop test), so that the
 // solver's passes do their full work outside a solve (timing, test hooks).
+// The residual-spectrum mechanics PCG (sr2d.hpp) runs in 2D FP64 contexts
+// with the unit Green operator and the forward difference, on rows whose
+// length is a multiple of the block size; every other mechanics solve keeps
+// the four-pass form.
+inline bool sr_active(const fgcg_ctx* c) {
+  return c->sr_opt && c->ndim == 2 && c->prec == FGCG_FP64 && c->precond == 0 && c->gradop == 0 &&
+         !c->strain_form && c->nx % NT == 0;
+}
+
 inline int running_state(fgcg_ctx* c) {
   std::vector<CgState> hs(c->nsamp);
   for (CgState& t : hs) {

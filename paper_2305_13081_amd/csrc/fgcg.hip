@@ -1,9 +1,14 @@
 // Entry points of the fgcg C ABI declared in include/fgcg.h and the 2D
 // solvers (3D grids are handled in fgcg3d.hip).
 #include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "adjoint.hpp"
 #include "engine.hpp"
+#include "sr2d.hpp"
 #include "strain_form.hpp"
 
 using namespace fgcg;
@@ -49,6 +54,67 @@ template <typename T> int launch_green(fgcg_ctx* c, int kind, const CgState* st,
 // Partial sums of r.z per sample left by the Green pass.
 inline int green_parts(const fgcg_ctx* c) { return c->precond == 1 ? c->ncol : 2 * c->ncol; }
 
+// ---------------------------------------------- residual-spectrum PCG (2D FP64)
+inline int ensure_rhat(fgcg_ctx* c) {
+  if (c->rhat) return 0;
+  const size_t bytes = sizeof(double2) * 2 * (size_t)c->nxh * c->rows * c->nsamp;
+  if (hipMalloc(&c->rhat, bytes) != hipSuccess) return fail(FGCG_ENOMEM, "residual spectra");
+  return 0;
+}
+
+// q = K p, its x transforms and the p.Kp partial sums (k_kp_fwd), tuned rows
+// per block and radix plan.
+template <typename T> int launch_kp_fwd(fgcg_ctx* c, int kind, const MechMat& m, const T* p, int ns) {
+  int rc = 0;
+  with_n(c->nx, [&](auto NXc) {
+    constexpr int NX = decltype(NXc)::value;
+    if constexpr (NX % NT == 0) {
+      with_rows<NX>(c->rows_pick, [&](auto Rc) {
+        with_plan<NX>(c->plan_row, [&](auto Pc) {
+          constexpr int R = decltype(Rc)::value, P = decltype(Pc)::value;
+          dim3 g((c->rows + R - 1) / R, 2 * ns);
+          if (kind >= 0) set_kname(c, kind, "k_kp_fwd<%s, %d", tname<T>(), NX);
+          rc = launch(c, kind, (const void*)&k_kp_fwd<T, NX, R, P>, g, m, p, c->st, c->part_a, (CT<T>*)c->spec,
+                      c->rows, (long long)c->nxh * c->rows, (T)(1.0 / c->h), tw_x<T>(c));
+        });
+      });
+    } else {
+      rc = fail(FGCG_EUNSUPPORTED, "residual-spectrum PCG needs nx a multiple of 256");
+    }
+  });
+  return rc;
+}
+
+// The Green pass on the residual spectrum (init: r_hat = FFT(f)).
+template <typename T> int launch_green_sr(fgcg_ctx* c, int kind, int init, int ns) {
+  const MechGreenSR<T> g{c->Dx,     c->Dy,      1.0 / (double)c->n, c->nx, c->st, c->part_rr, c->part_a,
+                         2 * c->rows, (CT<T>*)c->rhat, (long long)c->nxh * c->rows, c->rows, init};
+  CT<T>* spec = (CT<T>*)c->spec;
+  return launch_col<T, 1, 1, MechGreenSR<T>, true>(c, kind, g, spec, spec, 2 * ns, (long long)c->nxh * c->rows);
+}
+
+// The inverse pass with the direction and the (deferred) solution update.
+template <typename T>
+int launch_sr_row_inv(fgcg_ctx* c, int kind, const MechUEpi<T, 2>& e, const Field<T>& X, int ns) {
+  CT<T>* spec = (CT<T>*)c->spec;
+  const long long ss = (long long)c->nxh * c->rows;
+  if (ns == 1) {
+    const MechUEpiSRC<T, true> ec{e, X};
+    return launch_row_inv<T, 1, MechUEpiSRC<T, true>, true>(c, kind, ec, spec, 2 * ns, ss);
+  }
+  const MechUEpiSRC<T, false> ec{e, X};
+  return launch_row_inv<T, 1, MechUEpiSRC<T, false>, true>(c, kind, ec, spec, 2 * ns, ss);
+}
+
+// The last solution update, when the stop test ended the solve in the inverse pass.
+inline int sr_finish(fgcg_ctx* c) {
+  if (!sr_active(c)) return 0;
+  hipLaunchKernelGGL((k_sr_finish<double>), dim3(c->npost, c->nsamp), dim3(PT), 0, c->stream, (double*)c->x,
+                     (const double*)c->p, (const CgState*)c->st, 2 * c->n);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
 // z = M r, p = z, r.z and the CG state of every sample (R holds f, X holds 0).
 template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
   CT<T>* spec = (CT<T>*)c->spec;
@@ -57,6 +123,15 @@ template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, i
   int rc;
   const CopyProN<T, 2> cp{fld<T>(c->r, c), c->nx};
   if ((rc = launch_row_fwd<T, 2, CopyProN<T, 2>, true>(c, -1, cp, spec, ns, ss))) return rc;
+  if constexpr (std::is_same<T, double>::value) if (sr_active(c)) {
+    // r_hat = FFT(f) stored, z = M r, p = z
+    if ((rc = ensure_rhat(c)) || (rc = launch_green_sr<T>(c, -1, 1, ns))) return rc;
+    MechUEpi<T, 2> e0{fld<T>(c->p, c), c->nx, c->st, c->part_rr, green_parts(c), 1, tol, maxit};
+    e0.sr = 1;
+    if ((rc = launch_sr_row_inv<T>(c, -1, e0, fld<T>(c->x, c), ns))) return rc;
+    HIPCHK(hipGetLastError());
+    return 0;
+  }
   if ((rc = launch_green<T>(c, -1, nullptr, ns, ss))) return rc;
   const MechUEpi<T, 2> e0{fld<T>(c->p, c), c->nx, c->st, c->part_rr, green_parts(c), 1, tol, maxit};
   if ((rc = launch_mech_row_inv<T>(c, -1, e0, spec, ns, ss))) return rc;
@@ -71,6 +146,14 @@ template <typename T> int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, i
   const int ns = c->nsamp;
   const long long ss = spec_ss(c);
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
+  if constexpr (std::is_same<T, double>::value) if (sr_active(c)) {
+    int r = launch_kp_fwd<T>(c, FGCG_K_MECH_ROW_FWD, m, (const T*)P.p, ns);
+    r |= launch_green_sr<T>(c, FGCG_K_MECH_COL, 0, ns);
+    MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, green_parts(c), 0, tol, maxit};
+    epi.sr = 1;
+    r |= launch_sr_row_inv<T>(c, FGCG_K_MECH_ROW_INV, epi, X, ns);
+    return r;
+  }
   set_kname(c, FGCG_K_MECH_KP, "k_mech_kp<%s%.0d", tname<T>(), 0);
   int r = launch(c, FGCG_K_MECH_KP, (const void*)&k_mech_kp<T>, dim3(c->nkpt, ns), m, (const T*)P.p, Q.p, c->n,
                  c->nx, c->ny, (T)(1.0 / c->h), c->st, c->part_a);
@@ -113,6 +196,7 @@ Key mech_key(const fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
   Key key;
   key.add(m.phase).add(m.d).add(m.Efield).add(m.lm_dev).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm);
   key.add(c->prec).add(c->precond).add(c->use_lam).add(c->use_mu).add(tol).add(maxit).add(c->rows_pick).add(c->plan_row).add(c->plan_col);
+  key.add(sr_active(c));
   return key;
 }
 
@@ -126,7 +210,12 @@ template <typename T> int timing_workspace(fgcg_ctx* c) {
   const size_t nv = sizeof(T) * c->ncw * (size_t)c->n * ns;
   for (void* b : {c->x, c->r, c->p, c->tmp}) HIPCHK(hipMemsetAsync(b, 0, nv, c->stream));
   HIPCHK(hipMemsetAsync(c->spec, 0, sizeof(CT<T>) * c->ncw * (size_t)c->nxh * c->rows * ns, c->stream));
-  const int npa = c->nkpt, nprz = 2 * c->ncol;
+  if (sr_active(c)) {
+    if ((rc = ensure_rhat(c))) return rc;
+    HIPCHK(hipMemsetAsync(c->rhat, 0, sizeof(CT<T>) * 2 * (size_t)c->nxh * c->rows * ns, c->stream));
+  }
+  // (k_kp_fwd leaves two partial sums per grid row and sample)
+  const int npa = std::max(c->nkpt, 2 * c->rows), nprz = 2 * c->ncol;
   std::vector<double> ones((size_t)std::max(npa, nprz) * ns, 1.0);
   HIPCHK(hipMemcpyAsync(c->part_a, ones.data(), sizeof(double) * npa * ns, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->part_rr, ones.data(), sizeof(double) * nprz * ns, hipMemcpyHostToDevice, c->stream));
@@ -147,6 +236,17 @@ template <typename T> int timing_workspace(fgcg_ctx* c) {
 // partial sums); the plan changes the rounding of the transforms only.  The
 // workspace and the CG state are overwritten, so this runs before the
 // right-hand side is formed.
+// Material of the timing workspace for the residual-spectrum stiffness pass:
+// a per-voxel E field read from the zeroed solution buffer (no phase needed).
+inline MechMat timing_material(const fgcg_ctx* c) {
+  MechMat m;
+  std::memset(&m, 0, sizeof m);
+  m.Efield = (const double*)c->x;
+  m.ss = c->n;
+  m.lam_per_E = m.mu_per_E = 1.0;
+  return m;
+}
+
 template <typename T> int tune_passes_t(fgcg_ctx* c) {
   std::vector<int> rows_c, prow_c, pcol_c;
   with_n(c->nx, [&](auto NXc) {
@@ -175,6 +275,10 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
   const MechUProC<T, 2> pro{{X, R, P, Q, c->nx, c->st, c->part_a, npa}};
   const MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, nprz, 0, 0.0, 1 << 30};
+  const bool sr = sr_active(c);
+  MechUEpi<T, 2> epi_sr = epi;
+  epi_sr.sr = 1;
+  const MechMat tmat = timing_material(c);
   // the Green pass (of the context's preconditioner) without a CG state,
   // timed after the row passes, whose direction update reads part_rr
   hipEvent_t e0, e1;
@@ -206,6 +310,9 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
         c->rows_pick = R_;
         c->plan_row = prow_c[ip];
         const float ms = time_it([&] {
+          if constexpr (std::is_same<T, double>::value)
+            if (sr)
+              return launch_kp_fwd<T>(c, -1, tmat, (const T*)P.p, ns) | launch_sr_row_inv<T>(c, -1, epi_sr, X, ns);
           return launch_row_fwd<T, 1, MechUProC<T, 2>, true>(c, -1, pro, spec, 2 * ns, ss / 2) |
                  launch_mech_row_inv<T>(c, -1, epi, spec, ns, ss);
         });
@@ -222,9 +329,20 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   int pick_c = pcol_c[0];
   if (pcol_c.size() > 1) {
     std::vector<float> tc(pcol_c.size(), 0.f);
+    if (sr) {
+      // the residual-spectrum Green pass forms alpha from the stiffness
+      // pass's partial sums, which the row timings left at zero: unit sums
+      std::vector<double> ones((size_t)2 * c->rows * ns, 1.0);
+      HIPCHK(hipMemcpyAsync(c->part_a, ones.data(), sizeof(double) * ones.size(), hipMemcpyHostToDevice, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+    }
     for (size_t ip = 0; ip < pcol_c.size() && !rc; ++ip) {
       c->plan_col = pcol_c[ip];
-      tc[ip] = time_it([&] { return launch_green<T>(c, -1, nullptr, ns, ss); });
+      tc[ip] = time_it([&] {
+        if constexpr (std::is_same<T, double>::value)
+          if (sr) return launch_green_sr<T>(c, -1, 0, ns);
+        return launch_green<T>(c, -1, nullptr, ns, ss);
+      });
     }
     size_t ic = 0;
     for (size_t ip = 1; ip < pcol_c.size(); ++ip)
@@ -240,9 +358,41 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   return rc;
 }
 
+// Tuned picks are kept per process, keyed by the device and everything the
+// timings depend on (grid, precision, preconditioner, iteration form, samples
+// and the values pinned through the options), so later contexts of the same
+// shape take them without timing again.
+struct TuneKey {
+  int dev, nx, ny, prec, precond, sr, nsamp, rows, prow, pcol;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dev, nx, ny, prec, precond, sr, nsamp, rows, prow, pcol) <
+           std::tie(o.dev, o.nx, o.ny, o.prec, o.precond, o.sr, o.nsamp, o.rows, o.prow, o.pcol);
+  }
+};
+std::mutex tune_mu;
+std::map<TuneKey, std::array<int, 3>> tune_cache;
+
 inline int tune_passes(fgcg_ctx* c) {
   if (c->rows_pick && c->plan_row && c->plan_col) return 0;
-  return c->prec == FGCG_FP64 ? tune_passes_t<double>(c) : tune_passes_t<float>(c);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  const TuneKey key{dev, c->nx, c->ny, c->prec, c->precond, sr_active(c) ? 1 : 0, c->nsamp,
+                    c->rows_pick, c->plan_row, c->plan_col};
+  {
+    std::lock_guard<std::mutex> g(tune_mu);
+    auto it = tune_cache.find(key);
+    if (it != tune_cache.end()) {
+      c->rows_pick = it->second[0];
+      c->plan_row = it->second[1];
+      c->plan_col = it->second[2];
+      return 0;
+    }
+  }
+  const int rc = c->prec == FGCG_FP64 ? tune_passes_t<double>(c) : tune_passes_t<float>(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(tune_mu);
+  tune_cache[key] = {c->rows_pick, c->plan_row, c->plan_col};
+  return 0;
 }
 
 // Average duration of one 2D mechanics pass launched reps times back to back
@@ -259,7 +409,17 @@ template <typename T> int time_pass_t(fgcg_ctx* c, int kind, int reps, double* u
   const MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, green_parts(c), 0, 0.0, 1 << 30};
   // (only one kind is launched: the Green pass's partial sums may overwrite
   // the unit sums the direction update would read)
+  const bool sr = sr_active(c);
+  MechUEpi<T, 2> epi_sr = epi;
+  epi_sr.sr = 1;
+  const MechMat tmat = timing_material(c);
   auto one = [&]() -> int {
+    if constexpr (std::is_same<T, double>::value)
+      if (sr) {
+        if (kind == FGCG_K_MECH_ROW_FWD) return launch_kp_fwd<T>(c, -1, tmat, (const T*)P.p, ns);
+        if (kind == FGCG_K_MECH_ROW_INV) return launch_sr_row_inv<T>(c, -1, epi_sr, X, ns);
+        return launch_green_sr<T>(c, -1, 0, ns);
+      }
     if (kind == FGCG_K_MECH_ROW_FWD)
       return launch_row_fwd<T, 1, MechUProC<T, 2>, true>(c, -1, pro, spec, 2 * ns, ss / 2);
     if (kind == FGCG_K_MECH_ROW_INV)
@@ -291,8 +451,25 @@ template <typename T> int debug_apply_t(fgcg_ctx* c, int op, const MechMat& m, c
   if (op == FGCG_OP_MECH_K) {
     if ((rc = running_state(c))) return rc;
     hipLaunchKernelGGL((k_convert<T, double>), dim3(c->npost), dim3(PT), 0, c->stream, (T*)c->p, in, n2);
-    hipLaunchKernelGGL((k_mech_kp<T>), dim3(c->nkpt, 1), dim3(NT), 0, c->stream, m, (const T*)c->p, (T*)c->tmp, c->n,
-                       c->nx, c->ny, (T)(1.0 / c->h), c->st, c->part_a);
+    bool via_sr = false;
+    if constexpr (std::is_same<T, double>::value) {
+      if (sr_active(c)) {
+        // the stiffness of the residual-spectrum PCG (k_kp_fwd) returns x
+        // transforms of q: back to real space through the column and row passes
+        CT<T>* spec = (CT<T>*)c->spec;
+        const long long ss = (long long)c->nxh * c->rows;
+        const ScaleSym<T> id{1.0 / (double)c->n};
+        const StoreCompEpi<T> store{fld<T>(c->tmp, c), c->nx};
+        if ((rc = launch_kp_fwd<T>(c, -1, m, (const T*)c->p, 1)) ||
+            (rc = launch_col<T, 1, 1, ScaleSym<T>>(c, -1, id, spec, spec, 2, ss)) ||
+            (rc = launch_row_inv<T, 1, StoreCompEpi<T>>(c, -1, store, spec, 2, ss)))
+          return rc;
+        via_sr = true;
+      }
+    }
+    if (!via_sr)
+      hipLaunchKernelGGL((k_mech_kp<T>), dim3(c->nkpt, 1), dim3(NT), 0, c->stream, m, (const T*)c->p, (T*)c->tmp,
+                         c->n, c->nx, c->ny, (T)(1.0 / c->h), c->st, c->part_a);
     hipLaunchKernelGGL((k_convert<double, T>), dim3(c->npost), dim3(PT), 0, c->stream, out, (const T*)c->tmp, n2);
     HIPCHK(hipGetLastError());
     return 0;
@@ -333,6 +510,7 @@ int mech_pcg(fgcg_ctx* c, const MechMat& m, double tol, int maxit, CgState* out)
   if ((rc = run_cg(c, c->prec == FGCG_FP64 ? 0 : 5, mech_key(c, m, tol, maxit), c->st, c->h_st, it, maxit, K)))
     return rc;
   *out = *c->h_st;
+  if ((rc = sr_finish(c))) return rc;
   if (c->prec != FGCG_FP64) {
     hipLaunchKernelGGL((k_fold_final<float>), dim3(c->npost, c->nsamp), dim3(PT), 0, c->stream,
                        (const float*)c->x, c->xh, 2 * c->n);
@@ -856,7 +1034,7 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
 
 void fgcg_destroy(fgcg_ctx* c) {
   if (!c) return;
-  void* dev[] = {c->sf_buf, c->sf_spec, c->lm_dev, c->ems,  c->phase_buf, c->strain_buf, c->twx,    c->twy,    c->twx32,  c->twy32, c->twz,
+  void* dev[] = {c->rhat, c->sf_buf, c->sf_spec, c->lm_dev, c->ems,  c->phase_buf, c->strain_buf, c->twx,    c->twy,    c->twx32,  c->twy32, c->twz,
                  c->twz32, c->Dz,       c->red,        c->part_z, c->xh,     c->fh,     c->aux,   c->Dx,
                  c->Dy,   c->x,         c->r,          c->p,      c->tmp,    c->spec,   c->st,    c->part_a,
                  c->part_rr, c->part_b, c->part_post};
@@ -932,6 +1110,10 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
       (option == FGCG_OPT_GRADIENT ? c->gradop : c->strain_form) = value;
       return FGCG_OK;
     }
+    case FGCG_OPT_SPECTRAL_RES:
+      if (value != 0 && value != 1) return fail(FGCG_EINVAL, "spectral residual must be 0 or 1");
+      c->sr_opt = value;
+      return FGCG_OK;
     case FGCG_OPT_PRECOND:
       if (value != 0 && value != 1) return fail(FGCG_EINVAL, "preconditioner must be 0 (unit) or 1 (reference)");
       if (c->batch) return fail(FGCG_EUNSUPPORTED, "batch groups take the unit Green operator");
@@ -972,6 +1154,7 @@ int fgcg_get_option(fgcg_ctx* c, int option, int* value) {
     case FGCG_OPT_PRECOND: *value = c->precond; return FGCG_OK;
     case FGCG_OPT_GRADIENT: *value = c->gradop; return FGCG_OK;
     case FGCG_OPT_STRAIN_FORM: *value = c->strain_form; return FGCG_OK;
+    case FGCG_OPT_SPECTRAL_RES: *value = c->sr_opt; return FGCG_OK;
     default: return fail(FGCG_EINVAL, "unknown option");
   }
 }
@@ -1422,6 +1605,7 @@ int fgcg_mech_solve_batched(fgcg_batch* b, const uint8_t* const* phases, int nph
   for (size_t g = 0; g < b->groups.size(); ++g) {
     fgcg_ctx* c = b->groups[g];
     const std::vector<int>& mem = b->members[g];
+    if ((rc = sr_finish(c))) return rc;
     if (c->prec != FGCG_FP64) {
       hipLaunchKernelGGL((k_fold_final<float>), dim3(c->npost, c->nsamp), dim3(PT), 0, st, (const float*)c->x, c->xh,
                          2 * c->n);

@@ -372,13 +372,13 @@ template <typename T, int NC = 2> struct MechGreen {
   __device__ bool begin(int s2, double*, double&) const { return st == nullptr || cg_running(st, s2 / NC); }
   // the column pass loads |D_y|^2 of its modes before the forward transform
   using Pre = double;
-  __device__ Pre pre(int, int ky) const {
+  __device__ Pre pre(int, int, int ky) const {
     const double2 d = Dy[ky];
     return d.x * d.x + d.y * d.y;
   }
   template <typename C>
   __device__ void mode(int s2, int kx, int ky, const C* a, C* b, double& acc, double sc) const {
-    mode_pre(s2, kx, ky, pre(kx, ky), a, b, acc, sc);
+    mode_pre(s2, kx, ky, pre(s2, kx, ky), a, b, acc, sc);
   }
   template <typename C>
   __device__ void mode_pre(int, int kx, int, const double dy2, const C* a, C* b, double& acc, double) const {
@@ -418,7 +418,7 @@ template <typename T> struct MechRefGreen {
   double* part;       // nullable
   __device__ bool begin(int s, double*, double&) const { return st == nullptr || cg_running(st, s); }
   using Pre = double2;
-  __device__ Pre pre(int, int ky) const { return Dy[ky]; }
+  __device__ Pre pre(int, int, int ky) const { return Dy[ky]; }
   template <typename C>
   __device__ void mode(int s, int kx, int ky, const C* a, C* b, double& acc, double sc) const {
     mode_pre(s, kx, ky, Dy[ky], a, b, acc, sc);
@@ -468,6 +468,7 @@ template <typename T, int NC = 2> struct MechUEpi {
   int init;
   double tol;
   int maxit;
+  int sr = 0;  // the solution update of the iteration happens in this pass (sr2d.hpp)
   __device__ bool begin(int s, double* red, double& sc) const {
     CgState* S = st + s;
     if (!init && !cg_running(st, s)) return false;
@@ -489,6 +490,8 @@ template <typename T, int NC = 2> struct MechUEpi {
         t.iter = 0;
         t.done = done;
         t.zero_rhs = rz == 0.0;
+        t.alpha = 0.0;
+        t.x_pending = 0;
         *S = t;
       }
       sc = 0.0;
@@ -504,6 +507,7 @@ template <typename T, int NC = 2> struct MechUEpi {
         S->done = code;
         S->iter = k + 1;
         S->rr_final = rz;
+        if (sr) S->x_pending = 1;
       }
       return false;
     }

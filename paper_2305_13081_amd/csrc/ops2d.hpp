@@ -40,6 +40,8 @@ struct CgState {
   int iter;        // iterations taken when the solve ended
   int done;        // 0 running, 1 converged, 2 iteration limit, 3 breakdown, 4 non-finite rhs
   int zero_rhs;
+  double alpha;    // residual-spectrum PCG: step of the current direction
+  int x_pending;   // residual-spectrum PCG: the last x update is still due
 };
 
 // The iteration number lives in device memory so that a chunk of iterations

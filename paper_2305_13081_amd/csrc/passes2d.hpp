@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Pro pro, typename cvec<T>::type*
 }
 
 // ------------------------------------------------------------------ column
-// Sym::Pre: per-mode data the symbol can take from registers (sym.pre(kx, ky)
+// Sym::Pre: per-mode data the symbol can take from registers (sym.pre(s, kx, ky)
 // loaded before the forward transform, used by sym.mode_pre).
 template <class S, class = void> struct SymPre {
   static constexpr bool value = false;
@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(NT) k_col(Sym sym, const typename cvec<T>::typ
 #pragma unroll
     for (int k = 0; k < KPT; ++k) {
       const int ky = tid + k * NT;
-      if (NY % NT == 0 || ky < NY) spre[k] = sym.pre(kx, ky);
+      if (NY % NT == 0 || ky < NY) spre[k] = sym.pre(s, kx, ky);
     }
   }
   __syncthreads();
@@ -424,7 +424,7 @@ __global__ void __launch_bounds__(64) k_colw(Sym sym, const typename cvec<T>::ty
     wave_tw_load<T, NY, 0, 1>(W, tw);
     if constexpr (SymPre<Sym>::value) {
 #pragma unroll
-      for (int m = 0; m < E; ++m) spre[m] = sym.pre(kx, l + 64 * m);
+      for (int m = 0; m < E; ++m) spre[m] = sym.pre(s, kx, l + 64 * m);
     }
   };
   double sc = 0.0;

@@ -30,6 +30,8 @@ static __global__ void __launch_bounds__(NT) k_cg_init(CgState* st, const double
     t.done = !isfinite(b2) ? 4 : (b2 == 0.0 ? 1 : 0);
     t.rz[0] = t.rz[1] = 0.0;
     t.k_next = 0;
+    t.alpha = 0.0;
+    t.x_pending = 0;
     st[s] = t;
   }
 }

@@ -1,0 +1,305 @@
+// Mechanics PCG of 2D FP64 contexts with the residual kept in Fourier space.
+//
+// The displacement-form PCG of mech_u.hpp (K u = f, M = (grad^H grad)^-1,
+// Sec. 2.3 / App. A) needs r only through r_hat: the Green operator is applied
+// to r_hat, r.z is a Parseval sum over r_hat, and r -= alpha q is linear, so
+// it can be carried out on the spectra, r_hat -= alpha FFT(q).  The solution
+// update x += alpha p can wait until the pass that forms the next direction,
+// which reads p anyway.  One iteration is then three passes instead of four:
+//   k_kp_fwd           q = K p as a real-space stencil for the rows of the
+//                      block (one displacement component per block), the
+//                      forward x transform of q, partial sums of p.Kp in the
+//                      energy form sum sym(grad p) : g C : sym(grad p)
+//   col (MechGreenSR)  alpha = r.z / p.Kp; y transforms; r_hat -= alpha q_hat
+//                      (stored); z_hat = r_hat / |D|^2 / N; partial sums of
+//                      r.z; inverse y transforms of z_hat
+//   row_inv (MechUEpiSRC) inverse x transforms; stop test on r.z; beta;
+//                      x += alpha p; p = z + beta p
+// with the alpha, beta and stop test of the four-pass form, iterate by
+// iterate.  When the stop test ends the solve inside the inverse pass, the
+// last x update is still due; k_sr_finish applies it after the solve.
+// Algorithmic bytes per voxel (FP64, 2 components, half spectra
+// (nx/2+1)/nx * 16 B per component): 41 + 64.1 + 80.0 = 185 against 233 for
+// the four-pass form.
+#pragma once
+#include "mech_u.hpp"
+
+namespace fgcg {
+
+// Sum of an array of partial sums by a block of 64 or NT threads (fixed order
+// for a given block size).
+__device__ __forceinline__ double group_sum_array(const double* a, int n, double* red) {
+  if (blockDim.x == 64) {
+    double t = 0.0;
+    for (int i = threadIdx.x; i < n; i += 64) t += a[i];
+    return wave_sum(t);
+  }
+  return block_sum_array(a, n, red);
+}
+
+// q = K p for the ROWS rows y0 .. y0 + ROWS - 1 of displacement component
+// c = blockIdx.y % 2 (sample blockIdx.y / 2), transformed along x and stored
+// transposed as k_row_fwd does; partial sums of this component's share of the
+// energy form of p.Kp (c = 0: e11 s11 + e12 s12, c = 1: e22 s22 + e12 s12),
+// one per grid row at part[blockIdx.y * ny + y], so that the sum does not
+// depend on the rows per block.
+//
+// Thread t owns the XPT = NX / NT consecutive columns x = t XPT + j.  Every
+// global load of the block is issued first: p (both components) on the rows
+// y0 - 1 .. y0 + ROWS, the right neighbour p(y, (t + 1) XPT) on the rows
+// y0 - 1 .. y0 + ROWS - 1 and the material there.  The rows are then walked
+// with registers only: the stress at (y, x) takes p at (y, x), (y, x + 1) and
+// (y + 1, x); the divergence at (y, x) takes the stress at (y, x - 1) (the
+// thread's own column j - 1, or for j = 0 the left thread's last column
+// through LDS, double-buffered: one barrier per row) and at (y - 1, x) (the
+// previous row).  The two component blocks of a row strip share an XCD, so the
+// second reads p and the material from L2.
+template <typename T, int NX, int ROWS, int PL>
+__global__ void __launch_bounds__(NT) k_kp_fwd(MechMat m, const T* __restrict__ p, CgState* st, double* part,
+                                               typename cvec<T>::type* spec, int ny, long long spec_ss, T ih,
+                                               const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  static_assert(NX % NT == 0, "k_kp_fwd: NX must be a multiple of the block size");
+  static_assert(ROWS >= 2 && ROWS % 2 == 0, "rows per block: even, at least 2");
+  constexpr int XPT = NX / NT;
+  constexpr int NP = ROWS / 2;
+  constexpr int NXH = NX / 2 + 1;
+  __shared__ C buf[lds_size(NP * NX)];
+  __shared__ T edge[2][NT];             // x flux of each thread's last column, per row parity
+  __shared__ double rsum[ROWS][NT / 64];  // per-row energy sums of each wavefront
+  const int s2 = blockIdx.y, s = s2 >> 1, c = s2 & 1;
+  const int tid = threadIdx.x;
+  const int y0 = xcd_block() * ROWS;
+  if (!cg_running(st, s)) return;
+  if (lead() && c == 0) st[s].k = st[s].k_next;
+  const long long n = m.ss;
+  const T* ps = p + 2 * n * s;
+  // periodic row index (a block's rows may pass the last row more than once on
+  // grids of fewer rows than a block holds)
+  auto wrap = [&](int y) { return ((y % ny) + ny) % ny; };
+  const int x0 = tid * XPT, xr = (x0 + XPT) % NX;
+  T p0[ROWS + 2][XPT], p1[ROWS + 2][XPT], r0[ROWS + 1], r1[ROWS + 1];
+  double lam[ROWS + 1][XPT], mu[ROWS + 1][XPT];
+#pragma unroll
+  for (int k = 0; k < ROWS + 2; ++k) {
+    const long long row = (long long)wrap(y0 - 1 + k) * NX;
+#pragma unroll
+    for (int j = 0; j < XPT; ++j) {
+      p0[k][j] = ps[row + x0 + j];
+      p1[k][j] = ps[n + row + x0 + j];
+    }
+    if (k < ROWS + 1) {
+      r0[k] = ps[row + xr];
+      r1[k] = ps[n + row + xr];
+#pragma unroll
+      for (int j = 0; j < XPT; ++j) m.get(s, row + x0 + j, lam[k][j], mu[k][j]);
+    }
+  }
+  T* rb = as_real<T>(buf);
+  T fy_prev[XPT];
+#pragma unroll
+  for (int k = 0; k < ROWS + 1; ++k) {  // row y0 - 1 + k
+    const int rr = k - 1;
+    const bool own = rr >= 0 && y0 + rr < ny;  // a row of this block (not the halo row, not past the grid)
+    T fx[XPT], fy[XPT];
+    double e_row = 0.0;
+#pragma unroll
+    for (int j = 0; j < XPT; ++j) {
+      const T px0 = j + 1 < XPT ? p0[k][j + 1] : r0[k];
+      const T px1 = j + 1 < XPT ? p1[k][j + 1] : r1[k];
+      const T g11 = (px0 - p0[k][j]) * ih;
+      const T g12 = (p0[k + 1][j] - p0[k][j]) * ih;
+      const T g21 = (px1 - p1[k][j]) * ih;
+      const T g22 = (p1[k + 1][j] - p1[k][j]) * ih;
+      const T e0 = g11, e1 = g22, e2 = (T)0.5 * (g12 + g21);
+      T sg[3];
+      stress2<T>(lam[k][j], mu[k][j], e0, e1, e2, sg);
+      fx[j] = c == 0 ? sg[0] : sg[2];
+      fy[j] = c == 0 ? sg[2] : sg[1];
+      e_row += c == 0 ? (double)e0 * sg[0] + (double)e2 * sg[2] : (double)e1 * sg[1] + (double)e2 * sg[2];
+    }
+    edge[k & 1][tid] = fx[XPT - 1];
+    __syncthreads();
+    if (rr >= 0) {
+      const T left = edge[k & 1][tid == 0 ? NT - 1 : tid - 1];
+#pragma unroll
+      for (int j = 0; j < XPT; ++j) {
+        const T fxm = j > 0 ? fx[j - 1] : left;
+        const T q = ((fxm - fx[j]) + (fy_prev[j] - fy[j])) * ih;
+        rb[2 * lds((rr >> 1) * NX + x0 + j) + (rr & 1)] = own ? q : (T)0;
+      }
+      const double w = wave_sum(own ? e_row : 0.0);
+      if ((tid & 63) == 0) rsum[rr][tid >> 6] = w;
+    }
+#pragma unroll
+    for (int j = 0; j < XPT; ++j) fy_prev[j] = fy[j];
+  }
+  __syncthreads();
+  if (tid < ROWS && y0 + tid < ny) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) t += rsum[tid][w];
+    part[(long long)s2 * ny + y0 + tid] = t;
+  }
+  fft_lds<T, NX, NP, NT, false, FlatIdx<NX>, PL>(buf, tw);
+  C* out = spec + s2 * spec_ss;
+  for (int idx = tid; idx < NXH * NP; idx += NT) {
+    const int pair = idx % NP, kx = idx / NP;
+    const C z = buf[lds(pair * NX + kx)];
+    const C zm = buf[lds(pair * NX + (NX - kx) % NX)];
+    const C a = C{(T)0.5 * (z.x + zm.x), (T)0.5 * (z.y - zm.y)};
+    const C b = C{(T)0.5 * (z.y + zm.y), (T)0.5 * (zm.x - z.x)};
+    const int yy = y0 + 2 * pair;
+    C* o = out + (long long)kx * ny;
+    if (yy < ny) o[yy] = a;
+    if (yy + 1 < ny) o[yy + 1] = b;
+  }
+}
+
+// Green operator of the unit reference medium on the residual spectrum, one
+// displacement component per block (s2 = 2 s + c; spectra of (s, c) at
+// s2 * rs).  init: r_hat = q_hat (the transform of f) is stored and no alpha
+// is formed; otherwise alpha = rz_k / p.Kp (the partial sums of k_kp_fwd) and
+// r_hat -= alpha q_hat.  Then z_hat = r_hat / (N |D|^2) (zero at k = 0) and
+// the partial sums of r.z by Parseval over the half spectrum.
+template <typename T> struct MechGreenSR {
+  const double2* Dx;
+  const double2* Dy;
+  double inv_n;
+  int nx;
+  CgState* st;
+  double* part;          // r.z partial sums
+  const double* part_a;  // p.Kp partial sums of k_kp_fwd (two per grid row), np_a per sample
+  int np_a;
+  typename cvec<T>::type* rhat;
+  long long rs;  // per (sample, component) stride of rhat
+  int ny;
+  int init;
+  __device__ bool begin(int s2, double* red, double& sc) const {
+    const int s = s2 >> 1;
+    if (init) {
+      sc = 0.0;
+      return true;
+    }
+    if (!cg_running(st, s)) return false;
+    CgState* S = st + s;
+    const int k = S->k;
+    const double pap = group_sum_array(part_a + (long long)s * np_a, np_a, red);
+    const double rz = S->rz[k & 1];
+    const bool w = blockIdx.x == 0 && threadIdx.x == 0 && (s2 & 1) == 0;
+    if (!(pap > 0.0) || !isfinite(pap)) {
+      if (w) {
+        S->done = 3;
+        S->iter = k;
+        S->rr_final = rz;
+      }
+      return false;
+    }
+    sc = rz / pap;
+    if (w) S->alpha = sc;
+    return true;
+  }
+  // |D_y|^2 and the stored r_hat of the mode, loaded before the forward transform
+  struct Pre {
+    double dy2;
+    typename cvec<T>::type rh;
+  };
+  __device__ Pre pre(int s2, int kx, int ky) const {
+    const double2 d = Dy[ky];
+    Pre v;
+    v.dy2 = d.x * d.x + d.y * d.y;
+    v.rh = init ? typename cvec<T>::type{(T)0, (T)0} : rhat[s2 * rs + (long long)kx * ny + ky];
+    return v;
+  }
+  template <typename CC>
+  __device__ void mode(int s2, int kx, int ky, const CC* a, CC* b, double& acc, double sc) const {
+    mode_pre(s2, kx, ky, pre(s2, kx, ky), a, b, acc, sc);
+  }
+  template <typename CC>
+  __device__ void mode_pre(int s2, int kx, int ky, const Pre& v, const CC* a, CC* b, double& acc, double sc) const {
+    const CC rh = init ? a[0] : CC{v.rh.x - (T)sc * a[0].x, v.rh.y - (T)sc * a[0].y};
+    rhat[s2 * rs + (long long)kx * ny + ky] = rh;
+    const double2 d1 = Dx[kx];
+    const double n2 = (d1.x * d1.x + d1.y * d1.y) + v.dy2;
+    if (n2 == 0.0) {
+      b[0] = CC{(T)0, (T)0};
+      return;
+    }
+    const double f = inv_n / n2;
+    const T ft = (T)f;
+    b[0] = CC{rh.x * ft, rh.y * ft};
+    const double w = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+    acc += w * f * ((double)rh.x * rh.x + (double)rh.y * rh.y);
+  }
+  __device__ void partial(int s2, double v) const {
+    if (part && threadIdx.x == 0) part[(long long)s2 * gridDim.x + blockIdx.x] = v;
+  }
+};
+
+// Inverse pass of the iteration, one component per block: p = z + beta p and
+// x += alpha p (p of the previous direction, prefetched with x); init: p = z.
+// m.sr must be 1 (the stop test then marks the last x update as due).
+// E: prefetch before begin() (single-sample contexts, as MechUEpiC).
+template <typename T, bool E> struct MechUEpiSRC {
+  MechUEpi<T, 2> m;
+  Field<T> x;
+  static constexpr int NPRE = 2;
+  static constexpr bool EARLY = E;
+  __device__ bool begin(int s2, double* red, double& sc) const { return m.begin(s2 / 2, red, sc); }
+  __device__ void prefetch(int s2, int y, int xx, T* pre) const {
+    const long long i = (long long)y * m.nx + xx;
+    pre[0] = m.init ? (T)0 : m.p.at(s2 / 2, s2 % 2, i);
+    pre[1] = m.init ? (T)0 : x.at(s2 / 2, s2 % 2, i);
+  }
+  __device__ void point(int s2, int y, int xx, const T* z, double&, double sc, const T* pre) const {
+    const int s = s2 / 2, c = s2 % 2;
+    const long long i = (long long)y * m.nx + xx;
+    if (m.init) {
+      m.p.at(s, c, i) = z[0];
+    } else {
+      m.p.at(s, c, i) = z[0] + (T)sc * pre[0];
+      x.at(s, c, i) = pre[1] + (T)m.st[s].alpha * pre[0];
+    }
+  }
+  __device__ void partial(int, double) const {}
+};
+
+// The x update still due when the stop test ended the solve in the inverse
+// pass: x += alpha p for every sample whose state says so (one launch after
+// the solve; p is the last direction, alpha its step).
+template <typename T>
+__global__ void __launch_bounds__(PT) k_sr_finish(T* __restrict__ x, const T* __restrict__ p, const CgState* st,
+                                                  long long n2) {
+  const int s = blockIdx.y;
+  if (!st[s].x_pending) return;
+  const T a = (T)st[s].alpha;
+  x += n2 * s;
+  p += n2 * s;
+  for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n2; i += (long long)gridDim.x * PT)
+    x[i] += a * p[i];
+}
+
+// Identity symbol with the 1/N of the inverse transform (the kernel-level
+// hook that brings q back to real space), one component per block.
+template <typename T> struct ScaleSym {
+  double inv_n;
+  __device__ bool begin(int, double*, double&) const { return true; }
+  template <typename CC>
+  __device__ void mode(int, int, int, const CC* a, CC* b, double&, double) const {
+    b[0] = CC{a[0].x * (T)inv_n, a[0].y * (T)inv_n};
+  }
+  __device__ void partial(int, double) const {}
+};
+
+// out = z, one component per block (the same hook's inverse row pass).
+template <typename T> struct StoreCompEpi {
+  Field<T> out;
+  int nx;
+  __device__ bool begin(int, double*, double&) const { return true; }
+  __device__ void point(int s2, int y, int xx, const T* z, double&, double) const {
+    out.at(s2 / 2, s2 % 2, (long long)y * nx + xx) = z[0];
+  }
+  __device__ void partial(int, double) const {}
+};
+
+}  // namespace fgcg

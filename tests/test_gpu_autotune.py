@@ -170,3 +170,28 @@ def test_time_pass(torch_dev):
     c3 = fgcg.Context(16, 16, H, nz=16)
     with pytest.raises(fgcg.FgcgError):
         c3.time_pass("mech_row_fwd", 10)
+
+
+def test_tuned_picks_cached(torch_dev):
+    """A second context of the same shape and settings takes the first one's
+    tuned picks (no timing), and its solves equal the first context's bitwise;
+    another preconditioner or iteration form is tuned on its own."""
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    nx, ny = 512, 256
+    ph, _ = inputs.box_fractal(512, 2, 5, 1.7, 0.3, np.random.default_rng(4))
+    phase = torch.from_numpy(np.ascontiguousarray(ph[:ny, :nx])).to(dev)
+    picks, outs = [], []
+    for _ in range(2):
+        ctx = fgcg.Context(nx, ny, H)
+        outs.append(ctx.mech_solve(phase, E_TAB, NU_TAB, (1e-3, 0.0, 0.0), tol=1e-10, maxit=20000))
+        picks.append(tuple(ctx.get_option(o) for o in ("rows", "row_plan", "col_plan")))
+        ctx.close()
+    print(f"cached picks {picks}", flush=True)
+    assert picks[0] == picks[1] and all(v != 0 for v in picks[0])
+    assert torch.equal(outs[0]["strain"], outs[1]["strain"])
+    ctx = fgcg.Context(nx, ny, H)
+    ctx.set_option("spectral_residual", 0)
+    out = ctx.mech_solve(phase, E_TAB, NU_TAB, (1e-3, 0.0, 0.0), tol=1e-10, maxit=20000)
+    assert out["info"]["status"] == 0 and all(ctx.get_option(o) != 0 for o in ("rows", "row_plan", "col_plan"))
+    ctx.close()

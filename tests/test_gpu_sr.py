@@ -1,0 +1,140 @@
+"""GPU parity of the residual-spectrum mechanics PCG through the C ABI.
+
+2D FP64 contexts with nx a multiple of 256 keep the CG residual as its half
+spectra (the stiffness stencil fused into the forward row transform, the
+solution update in the pass that forms the next direction).  The iterates are
+those of the projected CG of Sec. 2.3 / App. A:
+* fixed-iteration parity with the oracle's projected CG (k = 1, 2, 7, 20;
+  the solve ends by the iteration limit, so the last solution update is the
+  deferred one), <= 1e-12, on square, non-square and ragged grids (ny not a
+  multiple of the rows per block, fewer rows than a block holds);
+* converged solves equal the four-pass form (option off) to 1e-10 with the
+  same iteration count, and the oracle to 1e-10;
+* the stiffness of the fused pass, brought back to real space, equals the
+  sparse stencil matrix element-wise (<= 1e-12);
+* zero right-hand side, and a solve that converges at the first test.
+"""
+import numpy as np
+import pytest
+
+from oracle import mech as omech
+
+pytestmark = pytest.mark.gpu
+E_TAB, NU_TAB, H = (3e6, 30e9), (0.2, 0.2), 5e-6
+E_MILD = (3e9, 30e9)  # converged comparisons with the oracle: fewer CPU iterations
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda", 0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def maxrel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(np.asarray(b))), 1e-300))
+
+
+def _case(ny, nx, seed):
+    rng = np.random.default_rng(seed)
+    phase = (rng.random((ny, nx)) < 0.6).astype(np.uint8)
+    d = 0.3 * rng.random((ny, nx))
+    e = np.where(phase == 0, 1e-3, 0.0)
+    return phase, d, e
+
+
+SHAPES = [(256, 256), (512, 96), (768, 48), (1024, 8), (256, 12)]
+
+
+@pytest.mark.parametrize("nx,ny", SHAPES)
+def test_sr_fixed_iterations(torch_dev, nx, ny):
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    phase, d, e = _case(ny, nx, nx + ny)
+    T = lambda a: torch.from_numpy(a).to(dev)
+    ctx = fgcg.Context(nx, ny, H)
+    assert ctx.get_option("spectral_residual") == 1
+    em = (1e-3, -2e-4, 3e-4)
+    for k in (1, 2, 7, 20):
+        print(f"SR fixed {nx}x{ny} k={k}", flush=True)
+        r = ctx.mech_solve(T(phase), E_TAB, NU_TAB, em, d=T(d), kappa=1e-6, eig=T(e), tol=0.0, maxit=k)
+        o = omech.mech_solve(phase, E_TAB, NU_TAB, em, H, d=d, kappa=1e-6, e=e, fixed_iters=k)
+        err = rel(r["strain"].cpu().numpy(), o["strain"])
+        print(f"  iters {r['info']['iters']} strain rel {err:.2e}", flush=True)
+        assert r["info"]["iters"] == k and r["info"]["status"] == 1 and err < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("nx,ny,with_oracle", [(256, 256, False), (1024, 96, False), (256, 8, True)])
+def test_sr_equals_four_pass_form(torch_dev, nx, ny, with_oracle):
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    phase, d, e = _case(ny, nx, 3 * nx + ny)
+    T = lambda a: torch.from_numpy(a).to(dev)
+    et = E_MILD if with_oracle else E_TAB
+    args = (T(phase), et, NU_TAB, (1e-3, 0.0, 0.0))
+    kw = dict(d=T(d), kappa=1e-6, eig=T(e), tol=1e-13, maxit=50000)
+    out = {}
+    for sr in (1, 0):
+        ctx = fgcg.Context(nx, ny, H)
+        ctx.set_option("spectral_residual", sr)
+        out[sr] = ctx.mech_solve(*args, **kw)
+        ctx.close()
+    a, b = out[1], out[0]
+    errs = dict(strain=rel(a["strain"].cpu().numpy(), b["strain"].cpu().numpy()),
+                stress=rel(a["stress"].cpu().numpy(), b["stress"].cpu().numpy()),
+                energy=abs(a["energy"] - b["energy"]) / abs(b["energy"]))
+    print(f"SR vs four-pass {nx}x{ny}: iters {a['info']['iters']} / {b['info']['iters']}, {errs}", flush=True)
+    if with_oracle:
+        o = omech.mech_solve(phase, et, NU_TAB, (1e-3, 0.0, 0.0), H, d=d, kappa=1e-6, e=e, tol=1e-13,
+                             maxit=50000)
+        errs["oracle"] = rel(a["strain"].cpu().numpy(), o["strain"])
+        print(f"  oracle: iters {o['iters']}, strain rel {errs['oracle']:.2e}", flush=True)
+    assert a["info"]["status"] == 0 and b["info"]["status"] == 0
+    assert abs(a["info"]["iters"] - b["info"]["iters"]) <= 1
+    assert max(errs.values()) < 1e-10
+
+
+def test_sr_stiffness_hook(torch_dev):
+    from oracle import direct as odir
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    nx, ny = 512, 48
+    phase, d, _ = _case(ny, nx, 11)
+    u = np.random.default_rng(12).standard_normal((2, ny, nx))
+    q_ref = odir.mech_stiffness_apply(phase, E_TAB, NU_TAB, u, H, d=d, kappa=1e-6)
+    T = lambda a: torch.from_numpy(a).to(dev)
+    for sr in (1, 0):
+        ctx = fgcg.Context(nx, ny, H)
+        ctx.set_option("spectral_residual", sr)
+        q = ctx.debug_apply(fgcg.OP_MECH_K, T(phase), E_TAB, NU_TAB, T(u), d=T(d), kappa=1e-6).cpu().numpy()
+        err = maxrel(q, q_ref)
+        print(f"K hook spectral_residual={sr}: max rel {err:.2e}", flush=True)
+        assert err < 1e-12
+        ctx.close()
+
+
+def test_sr_edge_cases(torch_dev):
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    nx, ny = 256, 8
+    phase, d, e = _case(ny, nx, 21)
+    T = lambda a: torch.from_numpy(a).to(dev)
+    ctx = fgcg.Context(nx, ny, H)
+    # zero right-hand side: x = 0 after 0 iterations
+    r = ctx.mech_solve(T(phase), E_TAB, NU_TAB, (0.0, 0.0, 0.0), tol=1e-10)
+    assert r["info"]["iters"] == 0 and float(r["strain"].abs().max()) == 0.0
+    # a loose tolerance met after few iterations, then a tight one on the same context
+    r1 = ctx.mech_solve(T(phase), E_TAB, NU_TAB, (1e-3, 0, 0), d=T(d), kappa=1e-6, eig=T(e), tol=1e-2)
+    r2 = ctx.mech_solve(T(phase), E_MILD, NU_TAB, (1e-3, 0, 0), d=T(d), kappa=1e-6, eig=T(e), tol=1e-13,
+                        maxit=50000)
+    print(f"edge cases: loose solve {r1['info']['iters']} iters, tight {r2['info']['iters']}", flush=True)
+    o = omech.mech_solve(phase, E_TAB, NU_TAB, (1e-3, 0, 0), H, d=d, kappa=1e-6, e=e, fixed_iters=r1["info"]["iters"])
+    assert rel(r1["strain"].cpu().numpy(), o["strain"]) < 1e-12
+    o2 = omech.mech_solve(phase, E_MILD, NU_TAB, (1e-3, 0, 0), H, d=d, kappa=1e-6, e=e, tol=1e-13, maxit=50000)
+    assert rel(r2["strain"].cpu().numpy(), o2["strain"]) < 1e-10
+    ctx.close()
