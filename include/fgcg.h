@@ -164,11 +164,18 @@ const char* fgcg_last_error(void);
  *       185 instead of 233 bytes per voxel).  The same alpha, beta and stop
  *       test as the projected CG of eq. solid-final (rounding aside); 0: the
  *       four-pass form everywhere.  Allocates two half spectra on the first
- *       solve that uses it.
+ *       solve that uses it.  On grids of at least 2^18 voxels the autotuner
+ *       (before the first mechanics solve) tunes the passes of both forms,
+ *       times one whole iteration of each and keeps the faster; smaller grids
+ *       take the residual-spectrum form.
+ *   FGCG_OPT_MECH_PASSES      read only (fgcg_get_option): transform and
+ *       stencil passes per mechanics CG iteration of a 2D context's current
+ *       form, 3 or 4 (after the first mechanics solve, which tunes it); 0 in
+ *       3D.  EINVAL to set.
  * Returns EINVAL for an unknown option or value. */
 enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2,
        FGCG_OPT_ROWS = 3, FGCG_OPT_ROW_PLAN = 4, FGCG_OPT_COL_PLAN = 5, FGCG_OPT_PRECOND = 6, FGCG_OPT_GRADIENT = 7,
-       FGCG_OPT_STRAIN_FORM = 8, FGCG_OPT_SPECTRAL_RES = 9 };
+       FGCG_OPT_STRAIN_FORM = 8, FGCG_OPT_SPECTRAL_RES = 9, FGCG_OPT_MECH_PASSES = 10 };
 int fgcg_set_option(fgcg_ctx* ctx, int option, int value);
 /* Reference medium of FGCG_OPT_PRECOND = 1: Lame constants (only lam0 / mu0
  * matters); (0, 0) restores the automatic choice.  EDOMAIN unless mu0 > 0 and

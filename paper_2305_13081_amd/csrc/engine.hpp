@@ -115,6 +115,8 @@ struct fgcg_ctx {
   int gradop = 0;           // gradient operator: 0 forward, 1 central, 2 eighth-order central, 3 Fourier
   int strain_form = 0;      // 1: mechanics and homogenisation in the paper's strain / gradient form
   int sr_opt = 1;           // 1: the residual-spectrum mechanics PCG where it applies (sr_active)
+  int sr_pick = 0;          // tuned form: 0 not decided, 1 residual spectrum, 2 four passes
+  double* timing_E = nullptr;  // E = 1 field of the iteration timings (tuner), allocated on first use
   void* rhat = nullptr;     // residual-spectrum PCG: the residual's half spectra [nsamp][2][nxh][ny]
   double* sf_buf = nullptr; // strain form: x, r, p (3 components each), allocated with the option
   void* sf_spec = nullptr;  // strain form: 3 half spectra
@@ -596,10 +598,13 @@ inline int make_mech_mat(const fgcg_ctx* c, const fgcg_material* mat, const doub
 // with the unit Green operator and the forward difference, on rows whose
 // length is a multiple of the block size; every other mechanics solve keeps
 // the four-pass form.
-inline bool sr_active(const fgcg_ctx* c) {
+inline bool sr_eligible(const fgcg_ctx* c) {
   return c->sr_opt && c->ndim == 2 && c->prec == FGCG_FP64 && c->precond == 0 && c->gradop == 0 &&
          !c->strain_form && c->nx % NT == 0;
 }
+// (on grids of at least 2^18 voxels the tuner times both forms and may keep
+// the four-pass form: sr_pick = 2)
+inline bool sr_active(const fgcg_ctx* c) { return sr_eligible(c) && c->sr_pick != 2; }
 
 inline int running_state(fgcg_ctx* c) {
   std::vector<CgState> hs(c->nsamp);

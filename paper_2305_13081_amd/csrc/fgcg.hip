@@ -74,8 +74,10 @@ template <typename T> int launch_kp_fwd(fgcg_ctx* c, int kind, const MechMat& m,
           constexpr int R = decltype(Rc)::value, P = decltype(Pc)::value;
           dim3 g((c->rows + R - 1) / R, 2 * ns);
           if (kind >= 0) set_kname(c, kind, "k_kp_fwd<%s, %d", tname<T>(), NX);
-          rc = launch(c, kind, (const void*)&k_kp_fwd<T, NX, R, P>, g, m, p, c->st, c->part_a, (CT<T>*)c->spec,
-                      c->rows, (long long)c->nxh * c->rows, (T)(1.0 / c->h), tw_x<T>(c));
+          const void* fn = m.Efield ? (const void*)&k_kp_fwd<T, NX, R, P, true>
+                                    : (const void*)&k_kp_fwd<T, NX, R, P, false>;
+          rc = launch_b(c, kind, fn, g, dim3(kp_threads(NX)), m, p, c->st, c->part_a, (CT<T>*)c->spec, c->rows,
+                        (long long)c->nxh * c->rows, (T)(1.0 / c->h), tw_x<T>(c));
         });
       });
     } else {
@@ -236,15 +238,22 @@ template <typename T> int timing_workspace(fgcg_ctx* c) {
 // partial sums); the plan changes the rounding of the transforms only.  The
 // workspace and the CG state are overwritten, so this runs before the
 // right-hand side is formed.
-// Material of the timing workspace for the residual-spectrum stiffness pass:
-// a per-voxel E field read from the zeroed solution buffer (no phase needed).
-inline MechMat timing_material(const fgcg_ctx* c) {
-  MechMat m;
-  std::memset(&m, 0, sizeof m);
-  m.Efield = (const double*)c->x;
-  m.ss = c->n;
-  m.lam_per_E = m.mu_per_E = 1.0;
-  return m;
+// Material of the pass and iteration timings: phase 0 everywhere with unit
+// Lame constants and zero damage (the phase-table and damage paths of the
+// staggered solves), from zeroed buffers allocated on first use.
+inline int timing_material(fgcg_ctx* c, MechMat* m) {
+  const size_t nv = (size_t)c->n * c->nsamp;
+  if (!c->timing_E) {
+    if (hipMalloc(&c->timing_E, sizeof(double) * nv + nv) != hipSuccess) return fail(FGCG_ENOMEM, "timing fields");
+    HIPCHK(hipMemsetAsync(c->timing_E, 0, sizeof(double) * nv + nv, c->stream));
+  }
+  std::memset(m, 0, sizeof *m);
+  m->phase = (const uint8_t*)(c->timing_E + nv);
+  m->d = c->timing_E;
+  m->ss = c->n;
+  m->nphase = 1;
+  m->lm.a[0] = m->lm.b[0] = 1.0;
+  return 0;
 }
 
 template <typename T> int tune_passes_t(fgcg_ctx* c) {
@@ -278,7 +287,8 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   const bool sr = sr_active(c);
   MechUEpi<T, 2> epi_sr = epi;
   epi_sr.sr = 1;
-  const MechMat tmat = timing_material(c);
+  MechMat tmat;
+  if ((rc = timing_material(c, &tmat))) return rc;
   // the Green pass (of the context's preconditioner) without a CG state,
   // timed after the row passes, whose direction update reads part_rr
   hipEvent_t e0, e1;
@@ -358,6 +368,69 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   return rc;
 }
 
+// A fixed, mean-free-ish pattern for the direction of the iteration timings.
+template <typename T>
+__global__ void __launch_bounds__(PT) k_pattern(T* __restrict__ v, long long n) {
+  for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n; i += (long long)gridDim.x * PT)
+    v[i] = (T)((double)((unsigned long long)(i * 2654435761ULL) & 0xffffULL) / 65536.0 - 0.5);
+}
+
+// Average time of one whole mechanics CG iteration (form 1: residual
+// spectrum, 2: four passes) launched back to back, 3 + 10 iterations between
+// HIP events, on a workspace that runs genuine CG steps: the timing material
+// (unit Lame constants), a fixed pattern as the first direction, zero x and
+// r, a state that never converges (threshold -1).  Overwrites the workspace
+// and the CG state.
+template <typename T> int time_iteration(fgcg_ctx* c, int form, float* ms_per_iter) {
+  int rc = timing_workspace<T>(c);
+  if (rc) return rc;
+  const int ns = c->nsamp;
+  const long long ss = spec_ss(c);
+  std::vector<CgState> hs(ns);
+  for (CgState& t : hs) {
+    std::memset(&t, 0, sizeof t);
+    t.rz[0] = t.rz[1] = 1.0;
+    t.bnorm2 = 1.0;
+    t.thr = -1.0;
+    t.maxit = 1 << 30;
+  }
+  HIPCHK(hipMemcpyAsync(c->st, hs.data(), sizeof(CgState) * ns, hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL((k_pattern<T>), dim3(c->npost), dim3(PT), 0, c->stream, (T*)c->p, 2 * c->n * ns);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  MechMat tm;
+  if ((rc = timing_material(c, &tm))) return rc;
+  const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
+  MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, green_parts(c), 0, 0.0, 1 << 30};
+  auto one = [&]() -> int {
+    if constexpr (std::is_same<T, double>::value) {
+      if (form == 1) {
+        MechUEpi<T, 2> e = epi;
+        e.sr = 1;
+        return launch_kp_fwd<T>(c, -1, tm, (const T*)P.p, ns) | launch_green_sr<T>(c, -1, 0, ns) |
+               launch_sr_row_inv<T>(c, -1, e, X, ns);
+      }
+    }
+    const MechUProC<T, 2> pro{{X, R, P, Q, c->nx, c->st, c->part_a, c->nkpt}};
+    return launch(c, -1, (const void*)&k_mech_kp<T>, dim3(c->nkpt, ns), tm, (const T*)P.p, Q.p, c->n, c->nx, c->ny,
+                  (T)(1.0 / c->h), c->st, c->part_a) |
+           launch_row_fwd<T, 1, MechUProC<T, 2>, true>(c, -1, pro, (CT<T>*)c->spec, 2 * ns, ss / 2) |
+           launch_green<T>(c, -1, c->st, ns, ss) | launch_mech_row_inv<T>(c, -1, epi, (CT<T>*)c->spec, ns, ss);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(FGCG_EHIP, "hipEventCreate");
+  for (int i = 0; i < 3 && !rc; ++i) rc = one();
+  if (!rc && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(FGCG_EHIP, "hipEventRecord");
+  for (int i = 0; i < 10 && !rc; ++i) rc = one();
+  float ms = 0.f;
+  if (!rc && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = fail(FGCG_EHIP, "timing an iteration failed");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (!rc) *ms_per_iter = ms / 10.f;
+  return rc;
+}
+
 // Tuned picks are kept per process, keyed by the device and everything the
 // timings depend on (grid, precision, preconditioner, iteration form, samples
 // and the values pinned through the options), so later contexts of the same
@@ -370,13 +443,19 @@ struct TuneKey {
   }
 };
 std::mutex tune_mu;
-std::map<TuneKey, std::array<int, 3>> tune_cache;
 
+std::map<TuneKey, std::array<int, 4>> tune_cache;
+
+// The passes of the context's mechanics form, and on grids of at least 2^18
+// voxels where the residual-spectrum form applies, the form itself: each
+// form's passes are tuned, one whole iteration of each is timed and the
+// faster is kept (smaller grids take the residual-spectrum form).
 inline int tune_passes(fgcg_ctx* c) {
   if (c->rows_pick && c->plan_row && c->plan_col) return 0;
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
-  const TuneKey key{dev, c->nx, c->ny, c->prec, c->precond, sr_active(c) ? 1 : 0, c->nsamp,
+  const bool forms = sr_eligible(c) && c->sr_pick == 0;
+  const TuneKey key{dev, c->nx, c->ny, c->prec, c->precond, forms ? 1 : (sr_active(c) ? 2 : 0), c->nsamp,
                     c->rows_pick, c->plan_row, c->plan_col};
   {
     std::lock_guard<std::mutex> g(tune_mu);
@@ -385,13 +464,35 @@ inline int tune_passes(fgcg_ctx* c) {
       c->rows_pick = it->second[0];
       c->plan_row = it->second[1];
       c->plan_col = it->second[2];
+      if (forms) c->sr_pick = it->second[3];
       return 0;
     }
   }
-  const int rc = c->prec == FGCG_FP64 ? tune_passes_t<double>(c) : tune_passes_t<float>(c);
-  if (rc) return rc;
+  auto tune = [&]() { return c->prec == FGCG_FP64 ? tune_passes_t<double>(c) : tune_passes_t<float>(c); };
+  int rc;
+  if (forms && c->n >= (1LL << 18)) {
+    const int r0 = c->rows_pick, p0 = c->plan_row, q0 = c->plan_col;
+    float t[2] = {0.f, 0.f};
+    std::array<int, 3> pk[2];
+    for (int f = 1; f <= 2; ++f) {
+      c->rows_pick = r0;
+      c->plan_row = p0;
+      c->plan_col = q0;
+      c->sr_pick = f;
+      if ((rc = tune()) || (rc = time_iteration<double>(c, f, &t[f - 1]))) return rc;
+      pk[f - 1] = {c->rows_pick, c->plan_row, c->plan_col};
+    }
+    const int f = t[0] <= t[1] ? 1 : 2;
+    c->sr_pick = f;
+    c->rows_pick = pk[f - 1][0];
+    c->plan_row = pk[f - 1][1];
+    c->plan_col = pk[f - 1][2];
+  } else {
+    if (forms) c->sr_pick = 1;
+    if ((rc = tune())) return rc;
+  }
   std::lock_guard<std::mutex> g(tune_mu);
-  tune_cache[key] = {c->rows_pick, c->plan_row, c->plan_col};
+  tune_cache[key] = {c->rows_pick, c->plan_row, c->plan_col, c->sr_pick};
   return 0;
 }
 
@@ -412,7 +513,8 @@ template <typename T> int time_pass_t(fgcg_ctx* c, int kind, int reps, double* u
   const bool sr = sr_active(c);
   MechUEpi<T, 2> epi_sr = epi;
   epi_sr.sr = 1;
-  const MechMat tmat = timing_material(c);
+  MechMat tmat;
+  if ((rc = timing_material(c, &tmat))) return rc;
   auto one = [&]() -> int {
     if constexpr (std::is_same<T, double>::value)
       if (sr) {
@@ -1034,7 +1136,7 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
 
 void fgcg_destroy(fgcg_ctx* c) {
   if (!c) return;
-  void* dev[] = {c->rhat, c->sf_buf, c->sf_spec, c->lm_dev, c->ems,  c->phase_buf, c->strain_buf, c->twx,    c->twy,    c->twx32,  c->twy32, c->twz,
+  void* dev[] = {c->timing_E, c->rhat, c->sf_buf, c->sf_spec, c->lm_dev, c->ems,  c->phase_buf, c->strain_buf, c->twx,    c->twy,    c->twx32,  c->twy32, c->twz,
                  c->twz32, c->Dz,       c->red,        c->part_z, c->xh,     c->fh,     c->aux,   c->Dx,
                  c->Dy,   c->x,         c->r,          c->p,      c->tmp,    c->spec,   c->st,    c->part_a,
                  c->part_rr, c->part_b, c->part_post};
@@ -1114,6 +1216,8 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
       if (value != 0 && value != 1) return fail(FGCG_EINVAL, "spectral residual must be 0 or 1");
       c->sr_opt = value;
       return FGCG_OK;
+    case FGCG_OPT_MECH_PASSES:
+      return fail(FGCG_EINVAL, "the number of mechanics passes is read-only");
     case FGCG_OPT_PRECOND:
       if (value != 0 && value != 1) return fail(FGCG_EINVAL, "preconditioner must be 0 (unit) or 1 (reference)");
       if (c->batch) return fail(FGCG_EUNSUPPORTED, "batch groups take the unit Green operator");
@@ -1155,6 +1259,7 @@ int fgcg_get_option(fgcg_ctx* c, int option, int* value) {
     case FGCG_OPT_GRADIENT: *value = c->gradop; return FGCG_OK;
     case FGCG_OPT_STRAIN_FORM: *value = c->strain_form; return FGCG_OK;
     case FGCG_OPT_SPECTRAL_RES: *value = c->sr_opt; return FGCG_OK;
+    case FGCG_OPT_MECH_PASSES: *value = c->ndim != 2 ? 0 : (sr_active(c) ? 3 : 4); return FGCG_OK;
     default: return fail(FGCG_EINVAL, "unknown option");
   }
 }

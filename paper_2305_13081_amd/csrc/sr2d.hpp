@@ -44,7 +44,9 @@ __device__ __forceinline__ double group_sum_array(const double* a, int n, double
 // one per grid row at part[blockIdx.y * ny + y], so that the sum does not
 // depend on the rows per block.
 //
-// Thread t owns the XPT = NX / NT consecutive columns x = t XPT + j.  Every
+// EF: the material is a per-voxel E field (else phase tables).  KT threads
+// per block (kp_threads: four columns per thread on rows of 1024 and more);
+// thread t owns the XPT = NX / KT consecutive columns x = t XPT + j.  Every
 // global load of the block is issued first: p (both components) on the rows
 // y0 - 1 .. y0 + ROWS, the right neighbour p(y, (t + 1) XPT) on the rows
 // y0 - 1 .. y0 + ROWS - 1 and the material there.  The rows are then walked
@@ -54,47 +56,95 @@ __device__ __forceinline__ double group_sum_array(const double* a, int n, double
 // through LDS, double-buffered: one barrier per row) and at (y - 1, x) (the
 // previous row).  The two component blocks of a row strip share an XCD, so the
 // second reads p and the material from L2.
-template <typename T, int NX, int ROWS, int PL>
-__global__ void __launch_bounds__(NT) k_kp_fwd(MechMat m, const T* __restrict__ p, CgState* st, double* part,
+constexpr int kp_threads(int nx) { return nx >= 2048 ? nx / 4 : NT; }
+
+template <typename T, int NX, int ROWS, int PL, bool EF, int KT = kp_threads(NX)>
+__global__ void __launch_bounds__(KT) k_kp_fwd(MechMat m, const T* __restrict__ p, CgState* st, double* part,
                                                typename cvec<T>::type* spec, int ny, long long spec_ss, T ih,
                                                const typename cvec<T>::type* __restrict__ tw) {
   using C = typename cvec<T>::type;
-  static_assert(NX % NT == 0, "k_kp_fwd: NX must be a multiple of the block size");
+  static_assert(NX % KT == 0 && KT % 64 == 0, "k_kp_fwd: NX must be a multiple of the block size");
   static_assert(ROWS >= 2 && ROWS % 2 == 0, "rows per block: even, at least 2");
-  constexpr int XPT = NX / NT;
+  constexpr int XPT = NX / KT;
   constexpr int NP = ROWS / 2;
   constexpr int NXH = NX / 2 + 1;
   __shared__ C buf[lds_size(NP * NX)];
-  __shared__ T edge[2][NT];             // x flux of each thread's last column, per row parity
-  __shared__ double rsum[ROWS][NT / 64];  // per-row energy sums of each wavefront
+  __shared__ T edge[2][KT];             // x flux of each thread's last column, per row parity
+  __shared__ double rsum[ROWS][KT / 64];  // per-row energy sums of each wavefront
   const int s2 = blockIdx.y, s = s2 >> 1, c = s2 & 1;
   const int tid = threadIdx.x;
   const int y0 = xcd_block() * ROWS;
-  if (!cg_running(st, s)) return;
-  if (lead() && c == 0) st[s].k = st[s].k_next;
   const long long n = m.ss;
   const T* ps = p + 2 * n * s;
   // periodic row index (a block's rows may pass the last row more than once on
   // grids of fewer rows than a block holds)
   auto wrap = [&](int y) { return ((y % ny) + ny) % ny; };
   const int x0 = tid * XPT, xr = (x0 + XPT) % NX;
+  long long rowi[ROWS + 2];
+#pragma unroll
+  for (int k = 0; k < ROWS + 2; ++k) rowi[k] = (long long)wrap(y0 - 1 + k) * NX;
+  // Loads in straight-line groups (the material's kind is uniform: branches
+  // around whole groups, not per voxel), so that they are all in flight
+  // before the first use.  A single sample (two component blocks) issues them
+  // before the state check: no block can find its solve ended while others
+  // run; in batches the blocks of converged samples exit first.
   T p0[ROWS + 2][XPT], p1[ROWS + 2][XPT], r0[ROWS + 1], r1[ROWS + 1];
-  double lam[ROWS + 1][XPT], mu[ROWS + 1][XPT];
+  uint8_t ph[EF ? 1 : ROWS + 1][XPT];
+  double ev[EF ? ROWS + 1 : 1][XPT], dd[ROWS + 1][XPT];
+  const bool dmg = m.d != nullptr;
+  auto load = [&]() {
 #pragma unroll
-  for (int k = 0; k < ROWS + 2; ++k) {
-    const long long row = (long long)wrap(y0 - 1 + k) * NX;
+    for (int k = 0; k < ROWS + 2; ++k)
 #pragma unroll
-    for (int j = 0; j < XPT; ++j) {
-      p0[k][j] = ps[row + x0 + j];
-      p1[k][j] = ps[n + row + x0 + j];
+      for (int j = 0; j < XPT; ++j) {
+        p0[k][j] = ps[rowi[k] + x0 + j];
+        p1[k][j] = ps[n + rowi[k] + x0 + j];
+      }
+#pragma unroll
+    for (int k = 0; k < ROWS + 1; ++k) {
+      r0[k] = ps[rowi[k] + xr];
+      r1[k] = ps[n + rowi[k] + xr];
     }
-    if (k < ROWS + 1) {
-      r0[k] = ps[row + xr];
-      r1[k] = ps[n + row + xr];
+    const long long so = s * n;
 #pragma unroll
-      for (int j = 0; j < XPT; ++j) m.get(s, row + x0 + j, lam[k][j], mu[k][j]);
+    for (int k = 0; k < ROWS + 1; ++k)
+#pragma unroll
+      for (int j = 0; j < XPT; ++j) {
+        if constexpr (EF)
+          ev[k][j] = m.Efield[so + rowi[k] + x0 + j];
+        else
+          ph[k][j] = m.phase[so + rowi[k] + x0 + j];
+      }
+    if (dmg) {
+#pragma unroll
+      for (int k = 0; k < ROWS + 1; ++k)
+#pragma unroll
+        for (int j = 0; j < XPT; ++j) dd[k][j] = m.d[so + rowi[k] + x0 + j];
     }
-  }
+  };
+  const bool early = gridDim.y == 2;
+  if (early) load();
+  if (!cg_running(st, s)) return;
+  if (lead() && c == 0) st[s].k = st[s].k_next;
+  if (!early) load();
+  // Lame constants of voxel (row k, column j), degraded (the per-sample
+  // tables of a batch are read per voxel)
+  auto lame = [&](int k, int j, double& lam, double& mu) {
+    if constexpr (EF) {
+      lam = ev[k][j] * m.lam_per_E;
+      mu = ev[k][j] * m.mu_per_E;
+    } else if (m.lm_dev) {
+      lam = m.lm_dev[16 * s + ph[k][j]];
+      mu = m.lm_dev[16 * s + 8 + ph[k][j]];
+    } else {
+      pick(m.lm, ph[k][j], lam, mu);
+    }
+    if (dmg) {
+      const double g = (1.0 - dd[k][j]) * (1.0 - dd[k][j]) + m.kappa;
+      lam *= g;
+      mu *= g;
+    }
+  };
   T* rb = as_real<T>(buf);
   T fy_prev[XPT];
 #pragma unroll
@@ -112,8 +162,10 @@ __global__ void __launch_bounds__(NT) k_kp_fwd(MechMat m, const T* __restrict__ 
       const T g21 = (px1 - p1[k][j]) * ih;
       const T g22 = (p1[k + 1][j] - p1[k][j]) * ih;
       const T e0 = g11, e1 = g22, e2 = (T)0.5 * (g12 + g21);
+      double lam, mu;
+      lame(k, j, lam, mu);
       T sg[3];
-      stress2<T>(lam[k][j], mu[k][j], e0, e1, e2, sg);
+      stress2<T>(lam, mu, e0, e1, e2, sg);
       fx[j] = c == 0 ? sg[0] : sg[2];
       fy[j] = c == 0 ? sg[2] : sg[1];
       e_row += c == 0 ? (double)e0 * sg[0] + (double)e2 * sg[2] : (double)e1 * sg[1] + (double)e2 * sg[2];
@@ -121,7 +173,7 @@ __global__ void __launch_bounds__(NT) k_kp_fwd(MechMat m, const T* __restrict__ 
     edge[k & 1][tid] = fx[XPT - 1];
     __syncthreads();
     if (rr >= 0) {
-      const T left = edge[k & 1][tid == 0 ? NT - 1 : tid - 1];
+      const T left = edge[k & 1][tid == 0 ? KT - 1 : tid - 1];
 #pragma unroll
       for (int j = 0; j < XPT; ++j) {
         const T fxm = j > 0 ? fx[j - 1] : left;
@@ -138,12 +190,12 @@ __global__ void __launch_bounds__(NT) k_kp_fwd(MechMat m, const T* __restrict__ 
   if (tid < ROWS && y0 + tid < ny) {
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < NT / 64; ++w) t += rsum[tid][w];
+    for (int w = 0; w < KT / 64; ++w) t += rsum[tid][w];
     part[(long long)s2 * ny + y0 + tid] = t;
   }
-  fft_lds<T, NX, NP, NT, false, FlatIdx<NX>, PL>(buf, tw);
+  fft_lds<T, NX, NP, KT, false, FlatIdx<NX>, PL>(buf, tw);
   C* out = spec + s2 * spec_ss;
-  for (int idx = tid; idx < NXH * NP; idx += NT) {
+  for (int idx = tid; idx < NXH * NP; idx += KT) {
     const int pair = idx % NP, kx = idx / NP;
     const C z = buf[lds(pair * NX + kx)];
     const C zm = buf[lds(pair * NX + (NX - kx) % NX)];

@@ -47,7 +47,7 @@ def _case(ny, nx, seed):
     return phase, d, e
 
 
-SHAPES = [(256, 256), (512, 96), (768, 48), (1024, 8), (256, 12)]
+SHAPES = [(256, 256), (512, 96), (768, 48), (1024, 8), (256, 12), (2048, 16)]
 
 
 @pytest.mark.parametrize("nx,ny", SHAPES)
