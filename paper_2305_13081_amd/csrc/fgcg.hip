@@ -69,6 +69,21 @@ template <typename T> int launch_kp_fwd(fgcg_ctx* c, int kind, const MechMat& m,
   with_n(c->nx, [&](auto NXc) {
     constexpr int NX = decltype(NXc)::value;
     if constexpr (NX % NT == 0) {
+      if (c->kp_both) {
+        // both components per block, rows_for(NX) rows (the partial sums are
+        // per grid row, so this need not match the inverse pass's rows)
+        constexpr int R = rows_for(NX);
+        with_plan<NX>(c->plan_row, [&](auto Pc) {
+          constexpr int P = decltype(Pc)::value;
+          dim3 g((c->rows + R - 1) / R, ns);
+          if (kind >= 0) set_kname(c, kind, "k_kp_fwd2<%s, %d", tname<T>(), NX);
+          const void* fn = m.Efield ? (const void*)&k_kp_fwd2<T, NX, R, P, true>
+                                    : (const void*)&k_kp_fwd2<T, NX, R, P, false>;
+          rc = launch_b(c, kind, fn, g, dim3(kp_threads(NX)), m, p, c->st, c->part_a, (CT<T>*)c->spec, c->rows,
+                        (long long)c->nxh * c->rows, (T)(1.0 / c->h), tw_x<T>(c));
+        });
+        return;
+      }
       with_rows<NX>(c->rows_pick, [&](auto Rc) {
         with_plan<NX>(c->plan_row, [&](auto Pc) {
           constexpr int R = decltype(Rc)::value, P = decltype(Pc)::value;
@@ -90,7 +105,8 @@ template <typename T> int launch_kp_fwd(fgcg_ctx* c, int kind, const MechMat& m,
 // The Green pass on the residual spectrum (init: r_hat = FFT(f)).
 template <typename T> int launch_green_sr(fgcg_ctx* c, int kind, int init, int ns) {
   const MechGreenSR<T> g{c->Dx,     c->Dy,      1.0 / (double)c->n, c->nx, c->st, c->part_rr, c->part_a,
-                         2 * c->rows, (CT<T>*)c->rhat, (long long)c->nxh * c->rows, c->rows, init};
+                         (c->kp_both ? 1 : 2) * c->rows, (CT<T>*)c->rhat, (long long)c->nxh * c->rows, c->rows,
+                         init};
   CT<T>* spec = (CT<T>*)c->spec;
   return launch_col<T, 1, 1, MechGreenSR<T>, true>(c, kind, g, spec, spec, 2 * ns, (long long)c->nxh * c->rows);
 }

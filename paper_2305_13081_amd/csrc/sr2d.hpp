@@ -208,6 +208,161 @@ __global__ void __launch_bounds__(KT) k_kp_fwd(MechMat m, const T* __restrict__ 
   }
 }
 
+// The same pass with both displacement components in one block (grid (row
+// blocks, samples)): the stress of a voxel is evaluated once for both
+// components' divergences, p and the material are read once, and the 2 ROWS
+// real rows of q (ROWS of each component) are transformed as ROWS complex
+// signals.  The p.Kp partial sums are the full energy sum e11 s11 + e22 s22
+// + 2 e12 s12 of each grid row, at part[sample * ny + y].
+template <typename T, int NX, int ROWS, int PL, bool EF, int KT = kp_threads(NX)>
+__global__ void __launch_bounds__(KT) k_kp_fwd2(MechMat m, const T* __restrict__ p, CgState* st, double* part,
+                                                typename cvec<T>::type* spec, int ny, long long spec_ss, T ih,
+                                                const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  static_assert(NX % KT == 0 && KT % 64 == 0, "k_kp_fwd2: NX must be a multiple of the block size");
+  static_assert(ROWS >= 2 && ROWS % 2 == 0, "rows per block: even, at least 2");
+  constexpr int XPT = NX / KT;
+  constexpr int NP = ROWS / 2;  // complex signals per component
+  constexpr int NXH = NX / 2 + 1;
+  __shared__ C buf[lds_size(2 * NP * NX)];
+  __shared__ T edge[2][2][KT];
+  __shared__ double rsum[ROWS][KT / 64];
+  const int s = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int y0 = xcd_block() * ROWS;
+  const long long n = m.ss;
+  const T* ps = p + 2 * n * s;
+  auto wrap = [&](int y) { return ((y % ny) + ny) % ny; };
+  const int x0 = tid * XPT, xr = (x0 + XPT) % NX;
+  long long rowi[ROWS + 2];
+#pragma unroll
+  for (int k = 0; k < ROWS + 2; ++k) rowi[k] = (long long)wrap(y0 - 1 + k) * NX;
+  T p0[ROWS + 2][XPT], p1[ROWS + 2][XPT], r0[ROWS + 1], r1[ROWS + 1];
+  uint8_t ph[EF ? 1 : ROWS + 1][XPT];
+  double ev[EF ? ROWS + 1 : 1][XPT], dd[ROWS + 1][XPT];
+  const bool dmg = m.d != nullptr;
+  auto load = [&]() {
+#pragma unroll
+    for (int k = 0; k < ROWS + 2; ++k)
+#pragma unroll
+      for (int j = 0; j < XPT; ++j) {
+        p0[k][j] = ps[rowi[k] + x0 + j];
+        p1[k][j] = ps[n + rowi[k] + x0 + j];
+      }
+#pragma unroll
+    for (int k = 0; k < ROWS + 1; ++k) {
+      r0[k] = ps[rowi[k] + xr];
+      r1[k] = ps[n + rowi[k] + xr];
+    }
+    const long long so = s * n;
+#pragma unroll
+    for (int k = 0; k < ROWS + 1; ++k)
+#pragma unroll
+      for (int j = 0; j < XPT; ++j) {
+        if constexpr (EF)
+          ev[k][j] = m.Efield[so + rowi[k] + x0 + j];
+        else
+          ph[k][j] = m.phase[so + rowi[k] + x0 + j];
+      }
+    if (dmg) {
+#pragma unroll
+      for (int k = 0; k < ROWS + 1; ++k)
+#pragma unroll
+        for (int j = 0; j < XPT; ++j) dd[k][j] = m.d[so + rowi[k] + x0 + j];
+    }
+  };
+  const bool early = gridDim.y == 1;
+  if (early) load();
+  if (!cg_running(st, s)) return;
+  if (lead()) st[s].k = st[s].k_next;
+  if (!early) load();
+  auto lame = [&](int k, int j, double& lam, double& mu) {
+    if constexpr (EF) {
+      lam = ev[k][j] * m.lam_per_E;
+      mu = ev[k][j] * m.mu_per_E;
+    } else if (m.lm_dev) {
+      lam = m.lm_dev[16 * s + ph[k][j]];
+      mu = m.lm_dev[16 * s + 8 + ph[k][j]];
+    } else {
+      pick(m.lm, ph[k][j], lam, mu);
+    }
+    if (dmg) {
+      const double g = (1.0 - dd[k][j]) * (1.0 - dd[k][j]) + m.kappa;
+      lam *= g;
+      mu *= g;
+    }
+  };
+  T* rb = as_real<T>(buf);
+  T s12_prev[XPT], s22_prev[XPT];
+#pragma unroll
+  for (int k = 0; k < ROWS + 1; ++k) {  // row y0 - 1 + k
+    const int rr = k - 1;
+    const bool own = rr >= 0 && y0 + rr < ny;
+    T s11[XPT], s22[XPT], s12[XPT];
+    double e_row = 0.0;
+#pragma unroll
+    for (int j = 0; j < XPT; ++j) {
+      const T px0 = j + 1 < XPT ? p0[k][j + 1] : r0[k];
+      const T px1 = j + 1 < XPT ? p1[k][j + 1] : r1[k];
+      const T g11 = (px0 - p0[k][j]) * ih;
+      const T g12 = (p0[k + 1][j] - p0[k][j]) * ih;
+      const T g21 = (px1 - p1[k][j]) * ih;
+      const T g22 = (p1[k + 1][j] - p1[k][j]) * ih;
+      const T e0 = g11, e1 = g22, e2 = (T)0.5 * (g12 + g21);
+      double lam, mu;
+      lame(k, j, lam, mu);
+      T sg[3];
+      stress2<T>(lam, mu, e0, e1, e2, sg);
+      s11[j] = sg[0];
+      s22[j] = sg[1];
+      s12[j] = sg[2];
+      e_row += (double)e0 * sg[0] + (double)e1 * sg[1] + 2.0 * (double)e2 * sg[2];
+    }
+    edge[k & 1][0][tid] = s11[XPT - 1];
+    edge[k & 1][1][tid] = s12[XPT - 1];
+    __syncthreads();
+    if (rr >= 0) {
+      const int tl = tid == 0 ? KT - 1 : tid - 1;
+      const T l11 = edge[k & 1][0][tl], l12 = edge[k & 1][1][tl];
+#pragma unroll
+      for (int j = 0; j < XPT; ++j) {
+        const T m11 = j > 0 ? s11[j - 1] : l11, m12 = j > 0 ? s12[j - 1] : l12;
+        const T q0 = ((m11 - s11[j]) + (s12_prev[j] - s12[j])) * ih;
+        const T q1 = ((m12 - s12[j]) + (s22_prev[j] - s22[j])) * ih;
+        rb[2 * lds((rr >> 1) * NX + x0 + j) + (rr & 1)] = own ? q0 : (T)0;
+        rb[2 * lds((NP + (rr >> 1)) * NX + x0 + j) + (rr & 1)] = own ? q1 : (T)0;
+      }
+      const double w = wave_sum(own ? e_row : 0.0);
+      if ((tid & 63) == 0) rsum[rr][tid >> 6] = w;
+    }
+#pragma unroll
+    for (int j = 0; j < XPT; ++j) {
+      s12_prev[j] = s12[j];
+      s22_prev[j] = s22[j];
+    }
+  }
+  __syncthreads();
+  if (tid < ROWS && y0 + tid < ny) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < KT / 64; ++w) t += rsum[tid][w];
+    part[(long long)s * ny + y0 + tid] = t;
+  }
+  fft_lds<T, NX, 2 * NP, KT, false, FlatIdx<NX>, PL>(buf, tw);
+  for (int idx = tid; idx < NXH * 2 * NP; idx += KT) {
+    const int sig = idx % (2 * NP), kx = idx / (2 * NP);
+    const int comp = sig / NP, pair = sig % NP;
+    const C z = buf[lds(sig * NX + kx)];
+    const C zm = buf[lds(sig * NX + (NX - kx) % NX)];
+    const C a = C{(T)0.5 * (z.x + zm.x), (T)0.5 * (z.y - zm.y)};
+    const C b = C{(T)0.5 * (z.y + zm.y), (T)0.5 * (zm.x - z.x)};
+    const int yy = y0 + 2 * pair;
+    C* o = spec + (2LL * s + comp) * spec_ss + (long long)kx * ny;
+    if (yy < ny) o[yy] = a;
+    if (yy + 1 < ny) o[yy + 1] = b;
+  }
+}
+
 // Green operator of the unit reference medium on the residual spectrum, one
 // displacement component per block (s2 = 2 s + c; spectra of (s, c) at
 // s2 * rs).  init: r_hat = q_hat (the transform of f) is stored and no alpha
