@@ -94,9 +94,10 @@ KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "
 # kernel sources they were taken with: the key is the SHA-256 of csrc/.
 MEASURED_TRAFFIC = {
     # hash of the 2D pass sources -> {kernel kind: HBM bytes per launch}
-    # (profiles/mech_passes_1024_fp64_hbm_traffic.md)
-    "6f1f5b4865647e0a01d6dc8f0bc2a84dc43e112fee035d60aedc7569465e5c2e": {
-        "mech_row_fwd": 115252675, "mech_row_inv": 49761511, "mech_kp": 42384179, "mech_col": 33274118},
+    # (profiles/mech_passes_1024_fp64_hbm_traffic.md); the residual-spectrum
+    # form: mech_row_fwd is the fused stiffness + transform pass
+    "401b928545c63373c9bbc4a37b5101774e90ba832d5a8acee74a9e741b725c26": {
+        "mech_row_fwd": 43200963, "mech_col": 66186972, "mech_row_inv": 82755107},
 }
 
 

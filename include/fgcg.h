@@ -69,7 +69,8 @@ typedef struct {
 /* Isotropic elastic material mixed voxel by voxel (Sec. 2.3):
  * C(x) = lambda(x) I (x) I + 2 mu(x) II, plane strain in 2D. */
 typedef struct {
-  const uint8_t* phase;  /* device [N], phase id per voxel */
+  const uint8_t* phase;  /* device [N], phase id per voxel, 0..nphase-1 (not checked; other
+                            values give undefined moduli) */
   int nphase;            /* 1..FGCG_MAX_PHASES */
   const double* E_tab;   /* host [nphase], Young's modulus per phase (Pa) */
   const double* nu_tab;  /* host [nphase], Poisson ratio per phase */

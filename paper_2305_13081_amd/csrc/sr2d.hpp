@@ -136,6 +136,9 @@ __global__ void __launch_bounds__(KT) k_kp_fwd(MechMat m, const T* __restrict__ 
     } else if (m.lm_dev) {
       lam = m.lm_dev[16 * s + ph[k][j]];
       mu = m.lm_dev[16 * s + 8 + ph[k][j]];
+    } else if (m.nphase <= 2) {  // (uniform) one selection instead of the eight-way one
+      lam = ph[k][j] ? m.lm.a[1] : m.lm.a[0];
+      mu = ph[k][j] ? m.lm.b[1] : m.lm.b[0];
     } else {
       pick(m.lm, ph[k][j], lam, mu);
     }
@@ -283,6 +286,9 @@ __global__ void __launch_bounds__(KT) k_kp_fwd2(MechMat m, const T* __restrict__
     } else if (m.lm_dev) {
       lam = m.lm_dev[16 * s + ph[k][j]];
       mu = m.lm_dev[16 * s + 8 + ph[k][j]];
+    } else if (m.nphase <= 2) {  // (uniform) one selection instead of the eight-way one
+      lam = ph[k][j] ? m.lm.a[1] : m.lm.a[0];
+      mu = ph[k][j] ? m.lm.b[1] : m.lm.b[0];
     } else {
       pick(m.lm, ph[k][j], lam, mu);
     }
