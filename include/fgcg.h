@@ -173,10 +173,17 @@ const char* fgcg_last_error(void);
  *       stencil passes per mechanics CG iteration of a 2D context's current
  *       form, 3 or 4 (after the first mechanics solve, which tunes it); 0 in
  *       3D.  EINVAL to set.
+ *   FGCG_OPT_SCALAR_CG        the CG of the stencil phase-field and diffusion
+ *       solves on 2D grids: 1 (default) the one-reduction form of Chronopoulos
+ *       and Gear (w = A r and s = A p carried along; one pass per iteration
+ *       updates p, s, x, r and applies the stencil to the new r, with both dot
+ *       products of the next iteration), the alpha, beta and stop test of
+ *       textbook CG in exact arithmetic; 0: textbook CG in two passes (the 3D
+ *       grids' form).
  * Returns EINVAL for an unknown option or value. */
 enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2,
        FGCG_OPT_ROWS = 3, FGCG_OPT_ROW_PLAN = 4, FGCG_OPT_COL_PLAN = 5, FGCG_OPT_PRECOND = 6, FGCG_OPT_GRADIENT = 7,
-       FGCG_OPT_STRAIN_FORM = 8, FGCG_OPT_SPECTRAL_RES = 9, FGCG_OPT_MECH_PASSES = 10 };
+       FGCG_OPT_STRAIN_FORM = 8, FGCG_OPT_SPECTRAL_RES = 9, FGCG_OPT_MECH_PASSES = 10, FGCG_OPT_SCALAR_CG = 11 };
 int fgcg_set_option(fgcg_ctx* ctx, int option, int value);
 /* Reference medium of FGCG_OPT_PRECOND = 1: Lame constants (only lam0 / mu0
  * matters); (0, 0) restores the automatic choice.  EDOMAIN unless mu0 > 0 and
@@ -444,7 +451,8 @@ void fgcg_ms_destroy(fgcg_ms* ms);
 /* ---- no allocation --------------------------------------------------- */
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
- * fgcg_phasefield_solve with the stencil operator (the default), FP64, without
+ * fgcg_phasefield_solve with the stencil operator (the default) in textbook CG
+ * form (FGCG_OPT_SCALAR_CG = 0 on 2D grids), FP64, without
  * a context.  Every work buffer lives in a device array of the library
  * (40 MiB per device, held until the process ends); the call allocates
  * nothing.  grid->precision must be FGCG_FP64, axis lengths as fgcg_create,

@@ -117,6 +117,7 @@ struct fgcg_ctx {
   int sr_opt = 1;           // 1: the residual-spectrum mechanics PCG where it applies (sr_active)
   int sr_pick = 0;          // tuned form: 0 not decided, 1 residual spectrum, 2 four passes
   int kp_both = 1;          // residual-spectrum stiffness pass: 1 both components per block, 0 one
+  int scg_onered = 1;       // stencil scalar CG on 2D grids: 1 one-reduction form (one pass), 0 textbook
   double* timing_E = nullptr;  // E = 1 field of the iteration timings (tuner), allocated on first use
   void* rhat = nullptr;     // residual-spectrum PCG: the residual's half spectra [nsamp][2][nxh][ny]
   double* sf_buf = nullptr; // strain form: x, r, p (3 components each), allocated with the option

@@ -944,6 +944,31 @@ int scg_solve(fgcg_ctx* c, int which, const Key& key, const Op& op, const double
                      c->nx, c->ny, c->nz, c->part_b, c->part_rr);
   hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(NT), 0, c->stream, c->st, c->part_b, nsb, 0, tol, maxit);
   HIPCHK(hipGetLastError());
+  if (c->ndim == 2 && c->scg_onered) {
+    // one-reduction form: x, p in the two components of x; r, w, s double-buffered
+    // by iteration parity in r, p and tmp
+    T* Px = X + c->n;
+    T* Rb[2] = {R, R + c->n};
+    T* Wb[2] = {P0, P1};
+    T* Sb[2] = {Q, Q + c->n};
+    const int np = std::min(scg_chunks(c->nx, c->ny, 1), 1024);
+    Key k2 = key;
+    k2.add(1);
+    int rc = launch(c, -1, (const void*)&k_scg_cg<T, Op>, dim3(np), op, X, Px, (const T*)Rb[0], Rb[1],
+                    (const T*)Wb[0], Wb[0], (const T*)Sb[0], Sb[1], c->nx, c->ny, c->st, c->part_a, np, 0, 1);
+    if (rc) return rc;
+    auto iter1 = [&]() -> int {
+      set_kname(c, kind_dir, "k_scg_cg<%s%.0d", tname<T>(), 0);
+      const int q = parity;
+      parity ^= 1;
+      return launch(c, kind_dir, (const void*)&k_scg_cg<T, Op>, dim3(np), op, X, Px, (const T*)Rb[q], Rb[q ^ 1],
+                    (const T*)Wb[q], Wb[q ^ 1], (const T*)Sb[q], Sb[q ^ 1], c->nx, c->ny, c->st, c->part_a, np, q,
+                    0);
+    };
+    if ((rc = run_cg(c, which, k2, c->st, c->h_st, iter1, maxit))) return rc;
+    *out = c->h_st[0];
+    return 0;
+  }
   const int ndir = std::min(scg_chunks(c->nx, c->ny, c->nz), 2048);  // p.q partial sums in part_a
   const CgCtl cc{c->st, c->part_a, c->part_rr, ndir, nsb, 0, 0};
   auto iter = [&]() -> int {
@@ -1234,6 +1259,10 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
       return FGCG_OK;
     case FGCG_OPT_MECH_PASSES:
       return fail(FGCG_EINVAL, "the number of mechanics passes is read-only");
+    case FGCG_OPT_SCALAR_CG:
+      if (value != 0 && value != 1) return fail(FGCG_EINVAL, "scalar CG form must be 0 or 1");
+      c->scg_onered = value;
+      return FGCG_OK;
     case FGCG_OPT_PRECOND:
       if (value != 0 && value != 1) return fail(FGCG_EINVAL, "preconditioner must be 0 (unit) or 1 (reference)");
       if (c->batch) return fail(FGCG_EUNSUPPORTED, "batch groups take the unit Green operator");
@@ -1275,6 +1304,7 @@ int fgcg_get_option(fgcg_ctx* c, int option, int* value) {
     case FGCG_OPT_GRADIENT: *value = c->gradop; return FGCG_OK;
     case FGCG_OPT_STRAIN_FORM: *value = c->strain_form; return FGCG_OK;
     case FGCG_OPT_SPECTRAL_RES: *value = c->sr_opt; return FGCG_OK;
+    case FGCG_OPT_SCALAR_CG: *value = c->scg_onered; return FGCG_OK;
     case FGCG_OPT_MECH_PASSES: *value = c->ndim != 2 ? 0 : (sr_active(c) ? 3 : 4); return FGCG_OK;
     default: return fail(FGCG_EINVAL, "unknown option");
   }

@@ -42,6 +42,11 @@ struct CgState {
   int zero_rhs;
   double alpha;    // residual-spectrum PCG: step of the current direction
   int x_pending;   // residual-spectrum PCG: the last x update is still due
+  // one-reduction scalar CG: iteration counter, r.r and step of the previous
+  // iteration, by the parity of the launch that reads them (the launch of
+  // parity P reads slot P and its lead writes slot P ^ 1)
+  int kk[2];
+  double gam[2], stp[2];
 };
 
 // The iteration number lives in device memory so that a chunk of iterations

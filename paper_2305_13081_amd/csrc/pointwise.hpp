@@ -32,6 +32,8 @@ static __global__ void __launch_bounds__(NT) k_cg_init(CgState* st, const double
     t.k_next = 0;
     t.alpha = 0.0;
     t.x_pending = 0;
+    t.kk[0] = t.kk[1] = 0;
+    t.gam[0] = t.gam[1] = t.stp[0] = t.stp[1] = 0.0;
     st[s] = t;
   }
 }

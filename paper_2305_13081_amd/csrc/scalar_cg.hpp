@@ -332,6 +332,161 @@ __global__ void __launch_bounds__(NT) k_scg_init(Op op, const double* __restrict
   }
 }
 
+// ------------------------------------------- one-reduction form (2D grids)
+// CG in the one-reduction form of Chronopoulos and Gear: with w = A r and
+// s = A p carried along, gamma_k = r_k.r_k and delta_k = w_k.r_k give
+//     beta_k = gamma_k / gamma_{k-1},
+//     alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1})
+// (beta_0 = 0, alpha_0 = gamma_0 / delta_0), the alpha and beta of textbook
+// CG in exact arithmetic, and one pass per iteration:
+//     p = r + beta p, s = w + beta s, x += alpha p, r -= alpha s, w = A r,
+// with gamma_{k+1} and delta_{k+1} summed on the way.  The stencil of the new
+// r takes its values on the tile's halo, formed there from the old r, w and s
+// (double-buffered by iteration parity, as are the partial sums and the
+// scalars of CgState that every block reads: see CgState::kk).  The stop test
+// (||r_k||^2 <= tol^2 ||b||^2, k < maxit) is textbook CG's, before the
+// update of iteration k.  Dirichlet voxels (op.fixed) keep r = w = s = p = 0.
+// init: only w_0 = A r_0 and the partial sums of gamma_0, delta_0.
+// Partial sums: part[parity][0][block] = gamma, part[parity][1][block] = delta
+// (np blocks).  2D grids (nz = 1).
+template <typename T, class Op>
+__global__ void __launch_bounds__(NT) k_scg_cg(Op op, T* __restrict__ x, T* __restrict__ p,
+                                               const T* __restrict__ rin, T* __restrict__ rout,
+                                               const T* __restrict__ win, T* __restrict__ wout,
+                                               const T* __restrict__ sin, T* __restrict__ sout, int nx, int ny,
+                                               CgState* st, double* part, int np, int parity, int init) {
+  constexpr int HX = SC_TX + 2, HY = SC_TY + 2, HP = HX * HY;
+  constexpr int RPT = SC_TY / (NT / SC_TX);  // own rows per thread
+  __shared__ double rl[HP];  // new r on the tile and its halo
+  __shared__ double r0l[HP], s1l[HP];  // old r and new s there (the own voxels' updates read them)
+  __shared__ double red[NT / 64];
+  double alpha = 0.0, beta = 0.0;
+  int k = 0;
+  if (!init) {
+    // scalars of this iteration (every block computes them alike)
+    if (!cg_running(st, 0)) return;
+    CgState* S = st;
+    k = S->kk[parity];
+    const double* pin = part + (long long)parity * 2 * np;
+    const double g = block_sum_array(pin, np, red), dl = block_sum_array(pin + np, np, red);
+    int code = 0;
+    if (!isfinite(g)) code = 3;
+    else if (g <= S->thr) code = 1;
+    else if (k >= S->maxit) code = 2;
+    double den = dl;
+    if (!code) {
+      if (k > 0) {
+        beta = g / S->gam[parity];
+        den = dl - beta * g / S->stp[parity];
+      }
+      if (!(den > 0.0) || !isfinite(den)) code = 3;
+    }
+    if (code) {
+      if (lead()) {
+        S->done = code;
+        S->iter = k;
+        S->rr_final = g;
+      }
+      return;
+    }
+    alpha = g / den;
+    if (lead()) {
+      S->kk[parity ^ 1] = k + 1;
+      S->gam[parity ^ 1] = g;
+      S->stp[parity ^ 1] = alpha;
+      S->k = k + 1;
+    }
+  }
+  const bool first = k == 0;  // (p and s of the previous iteration are not read)
+  const T a = (T)alpha, b = (T)beta;
+  // at linear index j: old r, new s = w + beta s and new r = r - alpha s
+  auto fillpt = [&](int hp, long long j) {
+    const T r0 = rin[j];
+    if (init) {
+      rl[hp] = (double)r0;
+      return;
+    }
+    const T sv = first ? win[j] : (T)(win[j] + b * sin[j]);
+    r0l[hp] = (double)r0;
+    s1l[hp] = (double)sv;
+    rl[hp] = (double)(r0 - a * sv);
+  };
+  const int ntx = (nx + SC_TX - 1) / SC_TX, nty = (ny + SC_TY - 1) / SC_TY;
+  const int nch = ntx * nty;
+  const int lb = xcd_block(), nb = gridDim.x;
+  const int c0 = (int)((long long)nch * lb / nb), c1 = (int)((long long)nch * (lb + 1) / nb);
+  const int tx = threadIdx.x & (SC_TX - 1), ty = threadIdx.x / SC_TX;
+  double accg = 0.0, accd = 0.0;
+  for (int c = c0; c < c1; ++c) {
+    const int x0 = (c % ntx) * SC_TX, y0 = (c / ntx) * SC_TY;
+    const int xo = x0 + tx;
+    for (int hp = threadIdx.x; hp < HP; hp += NT) {
+      const int hy = hp / HX, hx = hp - hy * HX;
+      int xx = x0 - 1 + hx, yy = y0 - 1 + hy;
+      if (xx > nx || yy > ny) continue;  // past the edge of a partial tile (never read)
+      xx = xx < 0 ? nx - 1 : (xx == nx ? 0 : xx);
+      yy = yy < 0 ? ny - 1 : (yy == ny ? 0 : yy);
+      fillpt(hp, (long long)yy * nx + xx);
+    }
+    // the voxels' coefficients, previous direction and solution are loaded
+    // before the barrier
+    Nbr nbr[RPT];
+    typename Op::Coef cf[RPT];
+    T pold[RPT], xold[RPT];
+#pragma unroll
+    for (int kk = 0; kk < RPT; ++kk) {
+      const int yo = y0 + ty + kk * (NT / SC_TX);
+      nbr[kk].i = (long long)yo * nx + xo;
+      nbr[kk].ixm = nbr[kk].i + (xo == 0 ? nx - 1 : -1);
+      nbr[kk].iym = nbr[kk].i + (yo == 0 ? (long long)(ny - 1) * nx : -(long long)nx);
+      nbr[kk].izm = nbr[kk].i;
+      nbr[kk].three = false;
+      pold[kk] = xold[kk] = (T)0;
+      if (xo < nx && yo < ny) {
+        cf[kk] = op.coef(nbr[kk]);
+        if (!init) {
+          if (!first) pold[kk] = p[nbr[kk].i];
+          xold[kk] = x[nbr[kk].i];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < RPT; ++kk) {
+      const int yy = ty + kk * (NT / SC_TX);
+      const int yo = y0 + yy;
+      if (xo < nx && yo < ny) {
+        const int hp = (yy + 1) * HX + tx + 1;
+        const Nbr& nb = nbr[kk];
+        const long long i = nb.i;
+        const double r1 = rl[hp];
+        const double vn[6] = {rl[hp - 1], rl[hp + 1], rl[hp - HX], rl[hp + HX], 0.0, 0.0};
+        const double w1 = op.fixed(i, xo) ? 0.0 : op.apply_coef(cf[kk], nb, r1, vn);
+        if (init) {
+          wout[i] = (T)w1;
+        } else {
+          const T r0 = (T)r0l[hp];
+          const T pv = first ? r0 : (T)(r0 + b * pold[kk]);
+          p[i] = pv;
+          sout[i] = (T)s1l[hp];
+          x[i] = xold[kk] + a * pv;
+          rout[i] = (T)r1;
+          wout[i] = (T)w1;
+        }
+        accg += r1 * r1;
+        accd += w1 * r1;
+      }
+    }
+    __syncthreads();
+  }
+  const double tg = block_sum(accg, red), td = block_sum(accd, red);
+  if (threadIdx.x == 0) {
+    double* po = part + (long long)(init ? 0 : parity ^ 1) * 2 * np;
+    po[blockIdx.x] = tg;
+    po[np + blockIdx.x] = td;
+  }
+}
+
 // c = c_dir on the Dirichlet voxels, x elsewhere
 template <typename T, class Op>
 __global__ void __launch_bounds__(NT) k_scg_finish(Op op, double* c, const T* x, long long n, int nx, double c_dir) {

@@ -1,7 +1,9 @@
 """The no-allocation phase-field entry point against the context entry point
-(the same stencil CG kernels and launch shapes): two calls in a row, the
-second on a smaller grid, each equal to fgcg_phasefield_solve bitwise and to
-the FP64 oracle within 1e-10; 2D and 3D; sizes beyond the limit rejected."""
+(the same textbook stencil CG kernels and launch shapes): two calls in a row,
+the second on a smaller grid, each equal bitwise to fgcg_phasefield_solve in
+textbook form (FGCG_OPT_SCALAR_CG = 0 on 2D grids, the only form in 3D), to
+the default one-reduction form within 1e-11 and to the FP64 oracle within
+1e-10; 2D and 3D; sizes beyond the limit rejected."""
 import ctypes
 
 import numpy as np
@@ -35,15 +37,19 @@ def test_noalloc_matches_context_solve(torch_dev, shapes):
         a = torch.from_numpy(d0.copy()).to(dev)
         info = fgcg.phasefield_solve_noalloc(Ht, GC, L0, a, H, tol=1e-13)
         ctx = fgcg.Context(shape[-1], shape[-2], H, nz=shape[0] if len(shape) == 3 else None)
+        bd = torch.from_numpy(d0.copy()).to(dev)
+        ctx.phasefield_solve(Ht, GC, L0, bd, tol=1e-13)  # the default form
+        ctx.set_option("scalar_cg", 0)
         b = torch.from_numpy(d0.copy()).to(dev)
         ref = ctx.phasefield_solve(Ht, GC, L0, b, tol=1e-13)
+        ed = float(torch.linalg.norm(a - bd) / torch.linalg.norm(bd))
         o = opf.phasefield_solve(Hf, GC, L0, H, d0=d0, tol=1e-13)
         err = float(np.linalg.norm(a.cpu().numpy() - o["d"]) / np.linalg.norm(o["d"]))
         print(f"no-alloc {shape}: iters {info['iters']} (context {ref['iters']}, oracle {o['iters']}), "
               f"bitwise equal {bool(torch.equal(a, b))}, oracle rel err {err:.2e}", flush=True)
         assert info["status"] == 0 and info["iters"] == ref["iters"]
         assert torch.equal(a, b)
-        assert err < 1e-10
+        assert err < 1e-10 and ed < 1e-11
         ctx.close()
 
 
