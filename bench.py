@@ -255,7 +255,8 @@ def c5_variant(torch, fgcg, inputs, dev, steps=2):
         out[name] = {"voxel_cg_iters_per_s": n ** 3 * sum(it.values()) / el, "steps": steps, "seconds": el,
                      "iters": it, "mech_voxel_cg_iters_per_s": n ** 3 * it["mech"] / secs["mech"],
                      "pf_voxel_cg_iters_per_s": n ** 3 * it["pf"] / secs["pf"],
-                     "kernels_warmup_step": kern, "max_d": infos[-1]["max_d"]}
+                     "kernels_warmup_step": kern, "max_d": infos[-1]["max_d"],
+                     "tuned": {"row_split": ctx.get_option("row_split"), "ztiles": ctx.get_option("ztiles")}}
         fields[name] = (st["strain"].cpu().numpy(), st["d"].cpu().numpy())
         del ctx, st
         torch.cuda.empty_cache()

@@ -180,18 +180,33 @@ const char* fgcg_last_error(void);
  *       products of the next iteration), the alpha, beta and stop test of
  *       textbook CG in exact arithmetic; 0: textbook CG in two passes (the 3D
  *       grids' form).
+ *   FGCG_OPT_ROW_SPLIT        3D grids: displacement components per block of
+ *       the mechanics row passes, 1 + f + 2 i with f (forward pass with the CG
+ *       update) and i (inverse pass with the direction update) 1 for one
+ *       component per block (three launches' worth of blocks), 0 for all
+ *       three in one block.  0 (default): autotune before the next mechanics
+ *       solve on grids of at least 2^18 voxels (each pass timed both ways on
+ *       the context's workspace, the faster kept), else 3 (FP64) or 2
+ *       (FP32-mixed).  Changes timing only, never results.  EUNSUPPORTED in 2D.
+ *   FGCG_OPT_ZTILES           3D grids: z tiles per block of the z pass, 1 or
+ *       2 (the second tile's loads overlap the first's transforms).  0
+ *       (default): autotune as FGCG_OPT_ROW_SPLIT (the non-default choice kept
+ *       only when more than 3 % faster), else 2 (FP64) or 1 (FP32-mixed).  The
+ *       block count orders the r.z partial sums, so results change by
+ *       rounding.  EUNSUPPORTED in 2D.
  * Returns EINVAL for an unknown option or value. */
 enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2,
        FGCG_OPT_ROWS = 3, FGCG_OPT_ROW_PLAN = 4, FGCG_OPT_COL_PLAN = 5, FGCG_OPT_PRECOND = 6, FGCG_OPT_GRADIENT = 7,
-       FGCG_OPT_STRAIN_FORM = 8, FGCG_OPT_SPECTRAL_RES = 9, FGCG_OPT_MECH_PASSES = 10, FGCG_OPT_SCALAR_CG = 11 };
+       FGCG_OPT_STRAIN_FORM = 8, FGCG_OPT_SPECTRAL_RES = 9, FGCG_OPT_MECH_PASSES = 10, FGCG_OPT_SCALAR_CG = 11,
+       FGCG_OPT_ROW_SPLIT = 12, FGCG_OPT_ZTILES = 13 };
 int fgcg_set_option(fgcg_ctx* ctx, int option, int value);
 /* Reference medium of FGCG_OPT_PRECOND = 1: Lame constants (only lam0 / mu0
  * matters); (0, 0) restores the automatic choice.  EDOMAIN unless mu0 > 0 and
  * lam0 + 2 mu0 / 3 > 0. */
 int fgcg_set_reference(fgcg_ctx* ctx, double lam0, double mu0);
-/* Current value of an option (FGCG_OPT_ROWS, _ROW_PLAN, _COL_PLAN: the tuned
- * or fixed choice, 0 before the first mechanics solve of an autotuned
- * context). */
+/* Current value of an option (FGCG_OPT_ROWS, _ROW_PLAN, _COL_PLAN,
+ * _ROW_SPLIT, _ZTILES: the tuned or fixed choice, 0 before the first
+ * mechanics solve of an autotuned context). */
 int fgcg_get_option(fgcg_ctx* ctx, int option, int* value);
 
 /* Mechanical equilibrium with isotropic eigenstrain e(x) I (Sec. 2.3,

@@ -90,7 +90,9 @@ struct fgcg_ctx {
   void* twz32 = nullptr;  // 3D FP32-mixed: float2[nz]
   double* red = nullptr;  // 3D: device [8] partial sums reduced by a single block
   double* part_z = nullptr;  // 3D: partial sums of the z pass (one per block)
-  int nzb = 0;               // 3D: blocks of the z pass
+  int nzb = 0;               // 3D: partial-sum slots of the z pass (its most blocks: one tile per block)
+  int zpt_pick = 0;          // 3D: z tiles per block of the z pass, 1 or 2 (0: tune before the next solve)
+  int split3 = 0;            // 3D: 1 + (forward row pass split) + 2 (inverse split); 0: tune
   int nslab = 0;             // 3D: blocks of the stencil kernels
   void* x = nullptr;
   void* r = nullptr;

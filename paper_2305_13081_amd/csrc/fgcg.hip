@@ -1269,6 +1269,17 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
       if (value != c->precond && c->ndim == 2) c->plan_col = 0;  // the column pass changes: tune it again
       c->precond = value;
       return FGCG_OK;
+    case FGCG_OPT_ROW_SPLIT:
+    case FGCG_OPT_ZTILES: {
+      if (c->ndim != 3) return fail(FGCG_EUNSUPPORTED, "row splits and z tiles are tuned on 3D grids");
+      const int top = option == FGCG_OPT_ROW_SPLIT ? 4 : 2;
+      if (value < 0 || value > top) return fail(FGCG_EINVAL, "row split 0..4, z tiles 0..2");
+      int& v = option == FGCG_OPT_ROW_SPLIT ? c->split3 : c->zpt_pick;
+      if (v != value)
+        for (auto& g : c->graphs) release_graph(c, g);  // captured launches use the old choice
+      v = value;
+      return FGCG_OK;
+    }
     case FGCG_OPT_ROW_PLAN:
     case FGCG_OPT_COL_PLAN:
       if (c->ndim != 2) return fail(FGCG_EUNSUPPORTED, "radix plans are tuned on 2D grids");
@@ -1306,6 +1317,8 @@ int fgcg_get_option(fgcg_ctx* c, int option, int* value) {
     case FGCG_OPT_SPECTRAL_RES: *value = c->sr_opt; return FGCG_OK;
     case FGCG_OPT_SCALAR_CG: *value = c->scg_onered; return FGCG_OK;
     case FGCG_OPT_MECH_PASSES: *value = c->ndim != 2 ? 0 : (sr_active(c) ? 3 : 4); return FGCG_OK;
+    case FGCG_OPT_ROW_SPLIT: *value = c->split3; return FGCG_OK;
+    case FGCG_OPT_ZTILES: *value = c->zpt_pick; return FGCG_OK;
     default: return fail(FGCG_EINVAL, "unknown option");
   }
 }

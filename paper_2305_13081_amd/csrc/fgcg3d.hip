@@ -6,6 +6,11 @@
 #include "mech3.hpp"
 #include "launch3d.hpp"
 
+#include <array>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace fgcg {
 
 namespace {
@@ -38,7 +43,7 @@ int green3(fgcg_ctx* c, const Pro& pro, const CgState* st, bool timed) {
   } else {
     const Green3<T> g{c->Dx, c->Dy, c->Dz, 1.0 / (double)c->n, c->nx, st, c->part_z};
     r |= launch_zpass<T, true, true>(c, timed ? FGCG_K_MECH_COL : -1, g, spec, 3);
-    r |= launch_reduce(c, c->part_z, c->nzb, c->red + 1);
+    r |= launch_reduce(c, c->part_z, zblocks<T>(c, 3), c->red + 1);
   }
   r |= launch_ypass<T, 3>(c, timed ? FGCG_K_MECH_Y_INV : -1, true, st, spec);
   return r;
@@ -54,12 +59,15 @@ template <typename T> int mech3_init(fgcg_ctx* c, double tol, int maxit) {
 }
 
 // Row passes with one displacement component per block (launched over the
-// three components) or all three in one block, per precision as measured at
-// 256^3: FP64 inverse pass 277 -> 253 us split, forward pass 556 -> 611 us
-// split (kept whole); FP32 forward pass 304 -> 284 us split, inverse pass
-// 129 -> 133 us split (kept whole).
+// three components) or all three in one block, as the context's split3 says
+// (tuned on large grids; the default per precision as measured at 256^3:
+// FP64 inverse pass 277 -> 253 us split, forward pass 556 -> 611 us split;
+// FP32 forward pass 304 -> 284 us split, inverse pass 129 -> 133 us split).
+inline int split_bits(const fgcg_ctx* c) { return c->split3 ? c->split3 - 1 : (c->prec == FGCG_FP64 ? 2 : 1); }
+
 template <typename T> int mech3_iter(fgcg_ctx* c, const MechMat& m, double tol, int maxit, bool reliable) {
-  constexpr bool SPLIT_FWD = sizeof(T) == 4, SPLIT_INV = sizeof(T) == 8;
+  const int sp = split_bits(c);
+  const bool split_fwd = (sp & 1) != 0, split_inv = (sp & 2) != 0;
   const Field<T> X = fld3<T>(c->x, c), R = fld3<T>(c->r, c), P = fld3<T>(c->p, c), Q = fld3<T>(c->tmp, c);
   const Grid3 g = grid3(c);
   const int nb = nslab(c);
@@ -69,7 +77,7 @@ template <typename T> int mech3_iter(fgcg_ctx* c, const MechMat& m, double tol, 
                  (const double*)nullptr, g, (T)(1.0 / c->h), c->st, c->part_a);
   r |= launch_reduce(c, c->part_a, nkp, c->red);
   if (!reliable) {
-    if constexpr (SPLIT_FWD) {
+    if (split_fwd) {
       const MechUProC<T, 3> pro{{X, R, P, Q, c->nx, c->st, c->red, 1}};
       r |= green3<T, 1>(c, pro, c->st, true);
     } else {
@@ -84,7 +92,7 @@ template <typename T> int mech3_iter(fgcg_ctx* c, const MechMat& m, double tol, 
     const CopyProN<T, 3> cp{R, c->nx};
     r |= green3<T, 3>(c, cp, c->st, false);
   }
-  if constexpr (SPLIT_INV) {
+  if (split_inv) {
     const MechUEpiC<T, 3> epi{{P, c->nx, c->st, c->red + 1, 1, 0, tol, maxit}};
     r |= launch_row_inv<T, 1>(c, FGCG_K_MECH_ROW_INV, epi, (const CT<T>*)c->spec, 3, comp_stride3(c));
   } else {
@@ -107,6 +115,121 @@ struct Mech3IterFn {
     return mech3_iter<float>(c, m, tol, maxit, rel);
   }
 };
+
+// Autotuning of the 3D mechanics passes, before the first solve of a grid of
+// at least 2^18 voxels: the forward and the inverse row pass each with one
+// displacement component per block or all three (timed separately; the
+// choice never changes results), and one or two z tiles per block in the
+// Green z pass (a different block count orders the r.z partial sums
+// differently, so the other choice must win by more than 3 %).  Each
+// candidate is timed over 3 + 10 back-to-back launches between HIP events on
+// the context's own workspace: zero fields and spectra, a running CG state
+// and unit scalars (so every launch does its full work).  Smaller grids take
+// the defaults.  Picks are kept per process, keyed by the device, the grid,
+// the precision, the preconditioner and the values fixed through the options.
+template <typename T> int timing3(fgcg_ctx* c) {
+  int rc = running_state(c);
+  if (rc) return rc;
+  const size_t nv = sizeof(T) * 3 * (size_t)c->n;
+  for (void* b : {c->x, c->r, c->p, c->tmp}) HIPCHK(hipMemsetAsync(b, 0, nv, c->stream));
+  HIPCHK(hipMemsetAsync(c->spec, 0, sizeof(CT<T>) * 3 * (size_t)c->nxh * c->rows, c->stream));
+  const double ones[8] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
+  HIPCHK(hipMemcpyAsync(c->red, ones, sizeof ones, hipMemcpyHostToDevice, c->stream));
+  // the host array is read by the copy: wait before it goes out of scope
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+template <typename T> int tune3_t(fgcg_ctx* c) {
+  int rc = timing3<T>(c);
+  if (rc) return rc;
+  const Field<T> X = fld3<T>(c->x, c), R = fld3<T>(c->r, c), P = fld3<T>(c->p, c), Q = fld3<T>(c->tmp, c);
+  CT<T>* spec = (CT<T>*)c->spec;
+  const long long cs = comp_stride3(c);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(FGCG_EHIP, "hipEventCreate");
+  auto time_it = [&](auto&& f) -> float {
+    for (int rep = 0; rep < 13 && !rc; ++rep) {
+      if (rep == 3 && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(FGCG_EHIP, "hipEventRecord");
+      rc |= f();
+    }
+    float ms = 0.f;
+    if (!rc && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = fail(FGCG_EHIP, "timing a 3D pass candidate failed");
+    return ms;
+  };
+  int split = c->split3 ? c->split3 - 1 : -1;
+  if (split < 0 && !rc) {
+    const MechUPro<T, 3> pw{X, R, P, Q, c->nx, c->st, c->red, 1};
+    const MechUProC<T, 3> pc{{X, R, P, Q, c->nx, c->st, c->red, 1}};
+    const MechUEpi<T, 3> ew{P, c->nx, c->st, c->red + 1, 1, 0, 0.0, 1 << 30};
+    const MechUEpiC<T, 3> ec{{P, c->nx, c->st, c->red + 1, 1, 0, 0.0, 1 << 30}};
+    const float fw = time_it([&] { return launch_row_fwd<T, 3>(c, -1, pw, spec); });
+    const float fs = time_it([&] { return launch_row_fwd<T, 1>(c, -1, pc, spec, 3, cs); });
+    const float iw = time_it([&] { return launch_row_inv<T, 3>(c, -1, ew, (const CT<T>*)spec); });
+    const float is = time_it([&] { return launch_row_inv<T, 1>(c, -1, ec, (const CT<T>*)spec, 3, cs); });
+    split = (fs < fw ? 1 : 0) | (is < iw ? 2 : 0);
+  }
+  int zpt = c->zpt_pick;
+  if (!zpt && !rc) {
+    const Green3<T> g{c->Dx, c->Dy, c->Dz, 1.0 / (double)c->n, c->nx, c->st, c->part_z};
+    float tz[3] = {0.f, 0.f, 0.f};
+    for (int z = 1; z <= 2 && !rc; ++z) {
+      c->zpt_pick = z;
+      tz[z] = time_it([&] { return launch_zpass<T, true, true>(c, -1, g, spec, 3); });
+    }
+    constexpr float MARGIN = 0.97f;
+    const int def = zpt_for<T>(), alt = 3 - def;
+    zpt = tz[alt] < MARGIN * tz[def] ? alt : def;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  HIPCHK(hipGetLastError());
+  if (rc) return rc;
+  c->split3 = 1 + split;
+  c->zpt_pick = zpt;
+  return 0;
+}
+
+struct Tune3Key {
+  int dev, nx, ny, nz, prec, precond, split, zpt;
+  bool operator<(const Tune3Key& o) const {
+    return std::tie(dev, nx, ny, nz, prec, precond, split, zpt) <
+           std::tie(o.dev, o.nx, o.ny, o.nz, o.prec, o.precond, o.split, o.zpt);
+  }
+};
+std::mutex tune3_mu;
+std::map<Tune3Key, std::array<int, 2>> tune3_cache;
+
+// Overwrites the workspace and the CG state: runs before a solve forms its
+// right-hand side.
+int tune3(fgcg_ctx* c) {
+  if (c->split3 && c->zpt_pick) return 0;
+  const bool f64 = c->prec == FGCG_FP64;
+  if (c->n < (1LL << 18)) {
+    if (!c->split3) c->split3 = 1 + split_bits(c);
+    if (!c->zpt_pick) c->zpt_pick = f64 ? zpt_for<double>() : zpt_for<float>();
+    return 0;
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  const Tune3Key key{dev, c->nx, c->ny, c->nz, c->prec, c->precond, c->split3, c->zpt_pick};
+  {
+    std::lock_guard<std::mutex> g(tune3_mu);
+    auto it = tune3_cache.find(key);
+    if (it != tune3_cache.end()) {
+      c->split3 = it->second[0];
+      c->zpt_pick = it->second[1];
+      return 0;
+    }
+  }
+  const int rc = f64 ? tune3_t<double>(c) : tune3_t<float>(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(tune3_mu);
+  tune3_cache[key] = {c->split3, c->zpt_pick};
+  return 0;
+}
 
 }  // namespace
 
@@ -147,8 +270,9 @@ int alloc3d(fgcg_ctx* c) {
   HIPCHK(hipMemcpy(c->Dz, dz.data(), sizeof(double2) * c->nz, hipMemcpyHostToDevice));
   HIPCHK(hipMalloc(&c->red, sizeof(double) * 8));
   HIPCHK(hipMemset(c->red, 0, sizeof(double) * 8));
-  // z-pass blocks of the solver's precision (the FP64 debug transform has no partial sums)
-  c->nzb = c->prec == FGCG_FP64 ? zblocks<double>(c, 3) : zblocks<float>(c, 3);
+  // partial sums of the z passes: the most blocks any of them launches (one
+  // tile per block, three components, either precision's tile width)
+  c->nzb = std::max(zblocks<double>(c, 3, 1), zblocks<float>(c, 3, 1));
   HIPCHK(hipMalloc(&c->part_z, sizeof(double) * c->nzb));
   c->nslab = nslab(c);
   return 0;
@@ -158,6 +282,8 @@ int mech3_solve(fgcg_ctx* c, const MechMat& m, const double* eig, const double* 
                 double* strain, double* stress, double* mean_stress, double* energy, fgcg_info* info) {
   const double t0 = now();
   resolve_reference(c, m);
+  int rc = tune3(c);
+  if (rc) return rc;
   const Grid3 g = grid3(c);
   const int nb = nslab(c);
   Em6 e6;
@@ -174,7 +300,7 @@ int mech3_solve(fgcg_ctx* c, const MechMat& m, const double* eig, const double* 
     HIPCHK(hipMemsetAsync(c->x, 0, sizeof(float) * 3 * c->n, c->stream));
   }
   HIPCHK(hipGetLastError());
-  int rc = c->prec == FGCG_FP64 ? mech3_init<double>(c, tol, maxit) : mech3_init<float>(c, tol, maxit);
+  rc = c->prec == FGCG_FP64 ? mech3_init<double>(c, tol, maxit) : mech3_init<float>(c, tol, maxit);
   if (rc) return rc;
   Mech3IterFn it{c, m, tol, maxit};
   const int K = c->prec == FGCG_FP64 ? c->chunk : 2 * RELIABLE_EVERY3;
@@ -223,6 +349,7 @@ template <typename T> int debug_apply3_t(fgcg_ctx* c, int op, const MechMat& m, 
     HIPCHK(hipGetLastError());
     return 0;
   }
+  if ((rc = tune3(c))) return rc;  // (overwrites the workspace)
   hipLaunchKernelGGL((k_convert<T, double>), dim3(c->npost), dim3(PT), 0, c->stream, (T*)c->r, in, n3);
   HIPCHK(hipMemsetAsync(c->p, 0, sizeof(T) * n3, c->stream));  // z = 0 stays if r = 0
   if ((rc = mech3_init<T>(c, 0.0, 1))) return rc;

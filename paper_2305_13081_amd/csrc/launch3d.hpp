@@ -64,21 +64,29 @@ int launch_ypass(fgcg_ctx* c, int kind, bool inv, const CgState* st, CT<T>* spec
   return rc;
 }
 
-// Blocks of the z pass over ncomp components (zpt_for<T>() tiles per block).
-template <typename T> inline int zblocks(const fgcg_ctx* c, int ncomp) {
-  return (ncomp * c->nxh * ztiles<T>(c) + zpt_for<T>() - 1) / zpt_for<T>();
+// z tiles per block of the context's z passes: the tuned or fixed choice,
+// else zpt_for<T>().
+template <typename T> inline int zpt_of(const fgcg_ctx* c) { return c->zpt_pick ? c->zpt_pick : zpt_for<T>(); }
+
+// Blocks of the z pass over ncomp components (zpt tiles per block; by
+// default the context's).
+template <typename T> inline int zblocks(const fgcg_ctx* c, int ncomp, int zpt = 0) {
+  const int z = zpt ? zpt : zpt_of<T>(c);
+  return (ncomp * c->nxh * ztiles<T>(c) + z - 1) / z;
 }
 
 template <typename T, bool FWD, bool INV, class Sym>
 int launch_zpass(fgcg_ctx* c, int kind, const Sym& sym, CT<T>* spec, int ncomp) {
   int rc = 0;
   const int ntiles = ncomp * c->nxh * ztiles<T>(c);
+  const int zpt = zpt_of<T>(c);
   with_n3(c->nz, [&](auto NZc) {
     constexpr int NZ = decltype(NZc)::value;
     dim3 g(zblocks<T>(c, ncomp));
     if (kind >= 0) set_kname(c, kind, "k_zpass<%s, %d", tname<T>(), NZ);
-    rc = launch(c, kind, (const void*)&k_zpass<T, NZ, FWD, INV, Sym>, g, sym, spec, c->nxh, c->ny, ntiles,
-                tw_z<T>(c));
+    const void* fn = zpt == 1 ? (const void*)&k_zpass<T, NZ, FWD, INV, Sym, 1>
+                              : (const void*)&k_zpass<T, NZ, FWD, INV, Sym, 2>;
+    rc = launch(c, kind, fn, g, sym, spec, c->nxh, c->ny, ntiles, tw_z<T>(c));
   });
   return rc;
 }

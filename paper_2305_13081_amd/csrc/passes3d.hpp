@@ -59,15 +59,17 @@ __global__ void __launch_bounds__(NT) k_ypass(const CgState* st, typename cvec<T
   }
 }
 
-// Blocks: zpt_for<T>() consecutive (component, kx, ky tile) entries each,
-// tile fastest.  The values of the next entry are loaded into registers while
-// the current one is transformed, so the loads overlap the LDS work (two per
-// block in FP64; one in FP32, where two measured slower).  FWD / INV select
-// the transforms (the debug hook uses one of them alone); the symbol is
-// applied between them and may reduce one FP64 partial sum per block.
+// Blocks: ZPT consecutive (component, kx, ky tile) entries each, tile
+// fastest.  With ZPT = 2 the values of the next entry are loaded into
+// registers while the current one is transformed, so the loads overlap the LDS
+// work; ZPT = 1 loads its one tile straight into LDS.  zpt_for<T>() is the
+// default where the context does not tune it (two in FP64, one in FP32, as
+// measured on 256^3 grids).  FWD / INV select the transforms (the debug hook
+// uses one of them alone); the symbol is applied between them and may reduce
+// one FP64 partial sum per block.
 template <typename T> constexpr int zpt_for() { return sizeof(T) == 8 ? 2 : 1; }
 
-template <typename T, int NZ, bool FWD, bool INV, class Sym>
+template <typename T, int NZ, bool FWD, bool INV, class Sym, int ZPT = zpt_for<T>()>
 __global__ void __launch_bounds__(NT) k_zpass(Sym sym, typename cvec<T>::type* spec, int nxh, int ny, int ntiles,
                                               const typename cvec<T>::type* __restrict__ tw) {
   using C = typename cvec<T>::type;
@@ -79,7 +81,7 @@ __global__ void __launch_bounds__(NT) k_zpass(Sym sym, typename cvec<T>::type* s
   if (!sym.begin()) return;
   const int nty = (ny + YT - 1) / YT;
   const int tid = threadIdx.x;
-  constexpr int ZPT = zpt_for<T>();
+  static_assert(ZPT == 1 || ZPT == 2, "one or two z tiles per block");
   if constexpr (ZPT == 1) {
     // one tile per block, loaded straight into LDS
     const int t = blockIdx.x % nty, ckx = blockIdx.x / nty;
