@@ -66,14 +66,33 @@ ALGO_BYTES = {
 
 
 # The residual-spectrum PCG (FP64 2D contexts with nx a multiple of 256, the
-# library's default there): three passes per iteration,
-#   row_fwd (k_kp_fwd): read p (16), phase (1), damage (8); write 2 spectra
-#            (the timing hook reads an 8-byte E field instead of phase and damage)
+# library's default there), bytes per voxel (sp: one component's half
+# spectrum per voxel):
+# three passes per iteration,
+#   row_fwd (k_kp_fwd2): read p (16), phase (1), damage (8); write 2 spectra
 #   col    : read 2 spectra of q and 2 of r, write 2 of r and 2 of z
 #   row_inv: read 2 spectra, p and x (32); write p and x (32)
-def algo_bytes_sr(n, timing=False):
+# two passes per iteration (the row stage fused: k_sr_row),
+#   row_fwd: read 2 spectra of z, p, x, phase and damage; write x, p and 2
+#            spectra of q (the halo rows it also transforms are re-reads of
+#            lines its neighbours own: not algorithmic bytes)
+#   col    : as above
+# (the timing hooks use phase and damage fields too)
+def algo_bytes_sr(n, timing=False, passes=3):
     sp = 16.0 * (n // 2 + 1) / n
-    return {"mech_row_fwd": 16 + (8 if timing else 9) + 2 * sp, "mech_col": 8 * sp, "mech_row_inv": 2 * sp + 64}
+    if passes == 2:
+        return {"mech_row_fwd": 2 * sp + 16 + 32 + 16 + 9 + 2 * sp, "mech_col": 8 * sp}
+    return {"mech_row_fwd": 16 + 9 + 2 * sp, "mech_col": 8 * sp, "mech_row_inv": 2 * sp + 64}
+
+
+ITERATION_FORM = {2: "two passes, residual spectrum, row stage fused", 3: "three passes, residual spectrum",
+                  4: "four passes"}
+
+
+def kinds_of(passes):
+    """The timed mechanics kinds of an iteration form."""
+    return {2: ["mech_row_fwd", "mech_col"], 3: ["mech_row_fwd", "mech_col", "mech_row_inv"],
+            4: ["mech_kp", "mech_row_fwd", "mech_col", "mech_row_inv"]}[passes]
 
 
 # 3D (256^3) mechanics passes, bytes per voxel with w-byte words (3
@@ -384,12 +403,12 @@ def hbm_resident_passes(torch, fgcg, dev, n=2048, reps=100):
     spec_b = 16.0 * (n // 2 + 1) / n
     ab = {"mech_row_fwd": 64 + 32 + 2 * spec_b, "mech_col": 4 * spec_b, "mech_row_inv": 2 * spec_b + 32}
     first = ctx.time_pass("mech_col", 3)  # tunes the passes and the iteration form first
-    sr = ctx.get_option("mech_passes") == 3
-    if sr:
-        ab = algo_bytes_sr(n, timing=True)
-    out = {"iteration": "three passes, residual spectrum" if sr else "four passes (the faster form on this grid)"}
+    passes = ctx.get_option("mech_passes")
+    if passes < 4:
+        ab = algo_bytes_sr(n, timing=True, passes=passes)
+    out = {"iteration": ITERATION_FORM[passes] + " (the tuned form on this grid)"}
     del first
-    for k in ("mech_row_fwd", "mech_col", "mech_row_inv"):
+    for k in [k for k in kinds_of(passes) if k != "mech_kp"]:
         us = ctx.time_pass(k, reps)
         gbs = ab[k] * n * n / (us * 1e-6) / 1e9
         out[k] = {"avg_launch_us": us, "algo_bytes_per_voxel": round(ab[k], 3), "achieved_GBs": gbs,
@@ -514,12 +533,13 @@ def main():
         info = ctx.staggered_step(state, phase, prm)
         print(f"warmup step {w}: iters diff {info['diff']['iters']} mech {info['mech']['iters']} "
               f"pf {info['pf']['iters']}", file=sys.stderr, flush=True)
-    # the iteration form the tuner kept (three passes: no separate stiffness pass)
-    sr = ctx.get_option("mech_passes") == 3
-    if sr:
-        mech_kinds = ["mech_row_fwd", "mech_col", "mech_row_inv"]
-    algo = algo_bytes_sr(N_SIDE) if sr else ALGO_BYTES
-    algo_timing = algo_bytes_sr(N_SIDE, timing=True) if sr else ALGO_BYTES
+    # the iteration form the tuner kept (two or three passes: no separate
+    # stiffness pass; two: no inverse row pass either)
+    passes = ctx.get_option("mech_passes")
+    sr = passes < 4
+    mech_kinds = kinds_of(passes)
+    algo = algo_bytes_sr(N_SIDE, passes=passes) if sr else ALGO_BYTES
+    algo_timing = algo_bytes_sr(N_SIDE, timing=True, passes=passes) if sr else ALGO_BYTES
     warm = {k: ctx.profile_read(k) for k in mech_kinds}
     dom = max(mech_kinds, key=lambda k: warm[k][0]) if args.warmup > 0 else "mech_row_fwd"
     # time only the dominant pass during the timed steps: every event-record
@@ -586,7 +606,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kname,
                      "algo_bytes_per_launch": dom_bytes * nvox, "avg_launch_us": avg_s * 1e6,
-                     "iteration": "three passes, residual spectrum" if sr else "four passes",
+                     "iteration": ITERATION_FORM[passes],
                      "in_graph_event_us": in_graph_s * 1e6,
                      "timing": "avg_launch_us: HIP events on the library stream around 200 back-to-back "
                                "launches of the kernel (the tuned configuration, on the workspace of this "

@@ -171,8 +171,20 @@ const char* fgcg_last_error(void);
  *       take the residual-spectrum form.
  *   FGCG_OPT_MECH_PASSES      read only (fgcg_get_option): transform and
  *       stencil passes per mechanics CG iteration of a 2D context's current
- *       form, 3 or 4 (after the first mechanics solve, which tunes it); 0 in
- *       3D.  EINVAL to set.
+ *       form, 2, 3 or 4 (after the first mechanics solve, which tunes it); 0
+ *       in 3D.  EINVAL to set.
+ *   FGCG_OPT_MECH_FORM        2D contexts where FGCG_OPT_SPECTRAL_RES applies:
+ *       the form of the mechanics PCG, by its passes per iteration.  0
+ *       (default): tuned as FGCG_OPT_SPECTRAL_RES says (grids below 2^18
+ *       voxels take 2); 2: the residual spectra with the row stage fused (the
+ *       inverse x transforms and direction update of iteration k and the
+ *       stiffness stencil and forward x transforms of iteration k + 1 in one
+ *       pass, beside the Green column pass; each block transforms one extra
+ *       row above and below its own, the direction is double-buffered and
+ *       K p gets its own half spectra: one more direction field and two more
+ *       half spectra of memory); 3: the residual spectra in three passes; 4:
+ *       four passes.  EUNSUPPORTED for 2 and 3 where FGCG_OPT_SPECTRAL_RES
+ *       does not apply.  All forms give the same iterates up to rounding.
  *   FGCG_OPT_SCALAR_CG        the CG of the stencil phase-field and diffusion
  *       solves on 2D grids: 1 (default) the one-reduction form of Chronopoulos
  *       and Gear (w = A r and s = A p carried along; one pass per iteration
@@ -198,7 +210,7 @@ const char* fgcg_last_error(void);
 enum { FGCG_OPT_SCALAR_SPECTRAL = 0, FGCG_OPT_GRAPHS = 1, FGCG_OPT_CHUNK = 2,
        FGCG_OPT_ROWS = 3, FGCG_OPT_ROW_PLAN = 4, FGCG_OPT_COL_PLAN = 5, FGCG_OPT_PRECOND = 6, FGCG_OPT_GRADIENT = 7,
        FGCG_OPT_STRAIN_FORM = 8, FGCG_OPT_SPECTRAL_RES = 9, FGCG_OPT_MECH_PASSES = 10, FGCG_OPT_SCALAR_CG = 11,
-       FGCG_OPT_ROW_SPLIT = 12, FGCG_OPT_ZTILES = 13 };
+       FGCG_OPT_ROW_SPLIT = 12, FGCG_OPT_ZTILES = 13, FGCG_OPT_MECH_FORM = 14 };
 int fgcg_set_option(fgcg_ctx* ctx, int option, int value);
 /* Reference medium of FGCG_OPT_PRECOND = 1: Lame constants (only lam0 / mu0
  * matters); (0, 0) restores the automatic choice.  EDOMAIN unless mu0 > 0 and

@@ -117,11 +117,14 @@ struct fgcg_ctx {
   int gradop = 0;           // gradient operator: 0 forward, 1 central, 2 eighth-order central, 3 Fourier
   int strain_form = 0;      // 1: mechanics and homogenisation in the paper's strain / gradient form
   int sr_opt = 1;           // 1: the residual-spectrum mechanics PCG where it applies (sr_active)
-  int sr_pick = 0;          // tuned form: 0 not decided, 1 residual spectrum, 2 four passes
+  int sr_pick = 0;          // tuned form: 0 not decided, 1 residual spectrum (three passes), 2 four
+                            // passes, 3 residual spectrum with the row stage fused (two passes)
   int kp_both = 1;          // residual-spectrum stiffness pass: 1 both components per block, 0 one
   int scg_onered = 1;       // stencil scalar CG on 2D grids: 1 one-reduction form (one pass), 0 textbook
   double* timing_E = nullptr;  // E = 1 field of the iteration timings (tuner), allocated on first use
   void* rhat = nullptr;     // residual-spectrum PCG: the residual's half spectra [nsamp][2][nxh][ny]
+  void* p_odd = nullptr;    // two-pass form: the direction of odd iterations (p holds the even ones)
+  void* spec_q = nullptr;   // two-pass form: the x spectra of K p [nsamp][2][nxh][ny]
   double* sf_buf = nullptr; // strain form: x, r, p (3 components each), allocated with the option
   void* sf_spec = nullptr;  // strain form: 3 half spectra
   double ref_lam = 0, ref_mu = 0;  // reference medium set by the caller (0, 0: from the material)
@@ -609,6 +612,7 @@ inline bool sr_eligible(const fgcg_ctx* c) {
 // (on grids of at least 2^18 voxels the tuner times both forms and may keep
 // the four-pass form: sr_pick = 2)
 inline bool sr_active(const fgcg_ctx* c) { return sr_eligible(c) && c->sr_pick != 2; }
+inline bool fused_active(const fgcg_ctx* c) { return sr_eligible(c) && c->sr_pick == 3; }
 
 inline int running_state(fgcg_ctx* c) {
   std::vector<CgState> hs(c->nsamp);

@@ -56,10 +56,45 @@ inline int green_parts(const fgcg_ctx* c) { return c->precond == 1 ? c->ncol : 2
 
 // ---------------------------------------------- residual-spectrum PCG (2D FP64)
 inline int ensure_rhat(fgcg_ctx* c) {
-  if (c->rhat) return 0;
-  const size_t bytes = sizeof(double2) * 2 * (size_t)c->nxh * c->rows * c->nsamp;
-  if (hipMalloc(&c->rhat, bytes) != hipSuccess) return fail(FGCG_ENOMEM, "residual spectra");
+  if (!c->rhat) {
+    const size_t bytes = sizeof(double2) * 2 * (size_t)c->nxh * c->rows * c->nsamp;
+    if (hipMalloc(&c->rhat, bytes) != hipSuccess) return fail(FGCG_ENOMEM, "residual spectra");
+  }
+  if (fused_active(c) && !c->p_odd) {
+    if (hipMalloc(&c->p_odd, sizeof(double) * 2 * (size_t)c->n * c->nsamp) != hipSuccess ||
+        hipMalloc(&c->spec_q, sizeof(double2) * 2 * (size_t)c->nxh * c->rows * c->nsamp) != hipSuccess)
+      return fail(FGCG_ENOMEM, "two-pass form buffers");
+  }
   return 0;
+}
+
+// The fused row stage of the two-pass form (k_sr_row): init (p_0 = z_0 into
+// p) or iteration k with parity k & 1 (p_k from p or p_odd, p_{k+1} into the
+// other).
+inline int launch_sr_row(fgcg_ctx* c, int kind, const MechMat& m, int init, double tol, int maxit, int parity,
+                         int ns) {
+  int rc = 0;
+  with_n(c->nx, [&](auto NXc) {
+    constexpr int NX = decltype(NXc)::value;
+    if constexpr (NX % NT == 0) {
+      double* pe = (double*)c->p;
+      double* po = (double*)c->p_odd;
+      const SrRowArgs<double> a{(const double2*)c->spec, (double2*)c->spec_q, parity ? po : pe,
+                                init ? pe : (parity ? pe : po), (double*)c->x, c->st, c->part_rr, green_parts(c),
+                                c->part_a, c->rows, (long long)c->nxh * c->rows, 1.0 / c->h, init, tol, maxit};
+      with_plan<NX>(c->plan_row, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        dim3 g((c->rows + SR_ROWS - 1) / SR_ROWS, ns);
+        if (kind >= 0) set_kname(c, kind, "k_sr_row<%s, %d", "double", NX);
+        const void* fn = m.Efield ? (const void*)&k_sr_row<double, NX, P, true>
+                                  : (const void*)&k_sr_row<double, NX, P, false>;
+        rc = launch_b(c, kind, fn, g, dim3(sr_threads(NX)), a, m, tw_x<double>(c));
+      });
+    } else {
+      rc = fail(FGCG_EUNSUPPORTED, "residual-spectrum PCG needs nx a multiple of 256");
+    }
+  });
+  return rc;
 }
 
 // q = K p, its x transforms and the p.Kp partial sums (k_kp_fwd), tuned rows
@@ -108,7 +143,9 @@ template <typename T> int launch_green_sr(fgcg_ctx* c, int kind, int init, int n
                          (c->kp_both ? 1 : 2) * c->rows, (CT<T>*)c->rhat, (long long)c->nxh * c->rows, c->rows,
                          init};
   CT<T>* spec = (CT<T>*)c->spec;
-  return launch_col<T, 1, 1, MechGreenSR<T>, true>(c, kind, g, spec, spec, 2 * ns, (long long)c->nxh * c->rows);
+  // the two-pass form's row stage leaves the x spectra of K p in spec_q
+  CT<T>* in = fused_active(c) && !init ? (CT<T>*)c->spec_q : spec;
+  return launch_col<T, 1, 1, MechGreenSR<T>, true>(c, kind, g, in, spec, 2 * ns, (long long)c->nxh * c->rows);
 }
 
 // The inverse pass with the direction and the (deferred) solution update.
@@ -127,8 +164,9 @@ int launch_sr_row_inv(fgcg_ctx* c, int kind, const MechUEpi<T, 2>& e, const Fiel
 // The last solution update, when the stop test ended the solve in the inverse pass.
 inline int sr_finish(fgcg_ctx* c) {
   if (!sr_active(c)) return 0;
+  const double* po = (const double*)(fused_active(c) ? c->p_odd : c->p);
   hipLaunchKernelGGL((k_sr_finish<double>), dim3(c->npost, c->nsamp), dim3(PT), 0, c->stream, (double*)c->x,
-                     (const double*)c->p, (const CgState*)c->st, 2 * c->n);
+                     (const double*)c->p, po, (const CgState*)c->st, 2 * c->n);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -144,6 +182,12 @@ template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, i
   if constexpr (std::is_same<T, double>::value) if (sr_active(c)) {
     // r_hat = FFT(f) stored, z = M r, p = z
     if ((rc = ensure_rhat(c)) || (rc = launch_green_sr<T>(c, -1, 1, ns))) return rc;
+    if (fused_active(c)) {
+      // p_0 = z_0, and the stiffness and forward transforms of p_0
+      if ((rc = launch_sr_row(c, -1, m, 1, tol, maxit, 0, ns))) return rc;
+      HIPCHK(hipGetLastError());
+      return 0;
+    }
     MechUEpi<T, 2> e0{fld<T>(c->p, c), c->nx, c->st, c->part_rr, green_parts(c), 1, tol, maxit};
     e0.sr = 1;
     if ((rc = launch_sr_row_inv<T>(c, -1, e0, fld<T>(c->x, c), ns))) return rc;
@@ -159,11 +203,18 @@ template <typename T> int mech_init(fgcg_ctx* c, const MechMat& m, double tol, i
 
 // The launches of one CG iteration (all samples).  reliable: FP32-mixed
 // reliable update (fold into the FP64 solution, FP64 true residual).
-template <typename T> int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, int maxit, bool reliable) {
+// parity: k & 1 of the iteration (the two-pass form's direction buffers).
+template <typename T>
+int mech_iter(fgcg_ctx* c, const MechMat& m, double tol, int maxit, bool reliable, int parity) {
   CT<T>* spec = (CT<T>*)c->spec;
   const int ns = c->nsamp;
   const long long ss = spec_ss(c);
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
+  if constexpr (std::is_same<T, double>::value) if (fused_active(c)) {
+    int r = launch_green_sr<T>(c, FGCG_K_MECH_COL, 0, ns);
+    r |= launch_sr_row(c, FGCG_K_MECH_ROW_FWD, m, 0, tol, maxit, parity, ns);
+    return r;
+  }
   if constexpr (std::is_same<T, double>::value) if (sr_active(c)) {
     int r = launch_kp_fwd<T>(c, FGCG_K_MECH_ROW_FWD, m, (const T*)P.p, ns);
     r |= launch_green_sr<T>(c, FGCG_K_MECH_COL, 0, ns);
@@ -214,7 +265,7 @@ Key mech_key(const fgcg_ctx* c, const MechMat& m, double tol, int maxit) {
   Key key;
   key.add(m.phase).add(m.d).add(m.Efield).add(m.lm_dev).add(m.kappa).add(m.lam_per_E).add(m.mu_per_E).add(m.lm);
   key.add(c->prec).add(c->precond).add(c->use_lam).add(c->use_mu).add(tol).add(maxit).add(c->rows_pick).add(c->plan_row).add(c->plan_col);
-  key.add(sr_active(c));
+  key.add(sr_active(c)).add(fused_active(c));
   return key;
 }
 
@@ -230,7 +281,12 @@ template <typename T> int timing_workspace(fgcg_ctx* c) {
   HIPCHK(hipMemsetAsync(c->spec, 0, sizeof(CT<T>) * c->ncw * (size_t)c->nxh * c->rows * ns, c->stream));
   if (sr_active(c)) {
     if ((rc = ensure_rhat(c))) return rc;
-    HIPCHK(hipMemsetAsync(c->rhat, 0, sizeof(CT<T>) * 2 * (size_t)c->nxh * c->rows * ns, c->stream));
+    const size_t sb = sizeof(CT<T>) * 2 * (size_t)c->nxh * c->rows * ns;
+    HIPCHK(hipMemsetAsync(c->rhat, 0, sb, c->stream));
+    if (fused_active(c)) {
+      HIPCHK(hipMemsetAsync(c->spec_q, 0, sb, c->stream));
+      HIPCHK(hipMemsetAsync(c->p_odd, 0, nv, c->stream));
+    }
   }
   // (k_kp_fwd leaves two partial sums per grid row and sample)
   const int npa = std::max(c->nkpt, 2 * c->rows), nprz = 2 * c->ncol;
@@ -291,6 +347,7 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
   if (c->rows_pick) rows_c = {c->rows_pick};
   if (c->plan_row) prow_c = {c->plan_row};
   if (c->plan_col) pcol_c = {c->plan_col};
+  if (fused_active(c)) rows_c = {rows_c[0]};  // the fused row stage has a fixed tile
   const int ns = c->nsamp;
   const long long ss = spec_ss(c);
   int rc = timing_workspace<T>(c);
@@ -336,9 +393,11 @@ template <typename T> int tune_passes_t(fgcg_ctx* c) {
         c->rows_pick = R_;
         c->plan_row = prow_c[ip];
         const float ms = time_it([&] {
-          if constexpr (std::is_same<T, double>::value)
+          if constexpr (std::is_same<T, double>::value) {
+            if (fused_active(c)) return launch_sr_row(c, -1, tmat, 0, 0.0, 1 << 30, 0, ns);
             if (sr)
               return launch_kp_fwd<T>(c, -1, tmat, (const T*)P.p, ns) | launch_sr_row_inv<T>(c, -1, epi_sr, X, ns);
+          }
           return launch_row_fwd<T, 1, MechUProC<T, 2>, true>(c, -1, pro, spec, 2 * ns, ss / 2) |
                  launch_mech_row_inv<T>(c, -1, epi, spec, ns, ss);
         });
@@ -392,7 +451,8 @@ __global__ void __launch_bounds__(PT) k_pattern(T* __restrict__ v, long long n) 
 }
 
 // Average time of one whole mechanics CG iteration (form 1: residual
-// spectrum, 2: four passes) launched back to back, 3 + 10 iterations between
+// spectrum, 2: four passes, 3: residual spectrum in two passes) launched back
+// to back, 3 + 10 iterations between
 // HIP events, on a workspace that runs genuine CG steps: the timing material
 // (unit Lame constants), a fixed pattern as the first direction, zero x and
 // r, a state that never converges (threshold -1).  Overwrites the workspace
@@ -412,13 +472,25 @@ template <typename T> int time_iteration(fgcg_ctx* c, int form, float* ms_per_it
   }
   HIPCHK(hipMemcpyAsync(c->st, hs.data(), sizeof(CgState) * ns, hipMemcpyHostToDevice, c->stream));
   hipLaunchKernelGGL((k_pattern<T>), dim3(c->npost), dim3(PT), 0, c->stream, (T*)c->p, 2 * c->n * ns);
+  // the two-pass form starts an iteration at the Green pass, whose input
+  // q_hat is zero here: a residual spectrum to work on (else r = 0 after the
+  // first iteration, and the second ends the solve on p.Kp = 0)
+  if (form == 3)
+    hipLaunchKernelGGL((k_pattern<double>), dim3(c->npost), dim3(PT), 0, c->stream, (double*)c->rhat,
+                       4LL * c->nxh * c->rows * ns);
   HIPCHK(hipStreamSynchronize(c->stream));
   MechMat tm;
   if ((rc = timing_material(c, &tm))) return rc;
   const Field<T> X = fld<T>(c->x, c), R = fld<T>(c->r, c), P = fld<T>(c->p, c), Q = fld<T>(c->tmp, c);
   MechUEpi<T, 2> epi{P, c->nx, c->st, c->part_rr, green_parts(c), 0, 0.0, 1 << 30};
+  int par = 0;
   auto one = [&]() -> int {
     if constexpr (std::is_same<T, double>::value) {
+      if (form == 3) {
+        const int r = launch_green_sr<T>(c, -1, 0, ns) | launch_sr_row(c, -1, tm, 0, 0.0, 1 << 30, par, ns);
+        par ^= 1;
+        return r;
+      }
       if (form == 1) {
         MechUEpi<T, 2> e = epi;
         e.sr = 1;
@@ -465,13 +537,17 @@ std::map<TuneKey, std::array<int, 4>> tune_cache;
 // The passes of the context's mechanics form, and on grids of at least 2^18
 // voxels where the residual-spectrum form applies, the form itself: each
 // form's passes are tuned, one whole iteration of each is timed and the
-// faster is kept (smaller grids take the residual-spectrum form).
+// fastest is kept (smaller grids take SR_DEFAULT_FORM).
+constexpr int SR_DEFAULT_FORM = 3;
 inline int tune_passes(fgcg_ctx* c) {
-  if (c->rows_pick && c->plan_row && c->plan_col) return 0;
+  const bool forms = sr_eligible(c) && c->sr_pick == 0;
+  if (c->rows_pick && c->plan_row && c->plan_col) {
+    if (forms) c->sr_pick = SR_DEFAULT_FORM;
+    return 0;
+  }
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
-  const bool forms = sr_eligible(c) && c->sr_pick == 0;
-  const TuneKey key{dev, c->nx, c->ny, c->prec, c->precond, forms ? 1 : (sr_active(c) ? 2 : 0), c->nsamp,
+  const TuneKey key{dev, c->nx, c->ny, c->prec, c->precond, forms ? 1 : (sr_eligible(c) ? 10 + c->sr_pick : 0), c->nsamp,
                     c->rows_pick, c->plan_row, c->plan_col};
   {
     std::lock_guard<std::mutex> g(tune_mu);
@@ -488,23 +564,26 @@ inline int tune_passes(fgcg_ctx* c) {
   int rc;
   if (forms && c->n >= (1LL << 18)) {
     const int r0 = c->rows_pick, p0 = c->plan_row, q0 = c->plan_col;
-    float t[2] = {0.f, 0.f};
-    std::array<int, 3> pk[2];
-    for (int f = 1; f <= 2; ++f) {
+    float t[3] = {0.f, 0.f, 0.f};
+    std::array<int, 3> pk[3];
+    for (int f = 1; f <= 3; ++f) {
       c->rows_pick = r0;
       c->plan_row = p0;
       c->plan_col = q0;
       c->sr_pick = f;
-      if ((rc = tune()) || (rc = time_iteration<double>(c, f, &t[f - 1]))) return rc;
+      if ((rc = ensure_rhat(c)) || (rc = tune()) || (rc = time_iteration<double>(c, f, &t[f - 1]))) return rc;
       pk[f - 1] = {c->rows_pick, c->plan_row, c->plan_col};
     }
-    const int f = t[0] <= t[1] ? 1 : 2;
+    int f = SR_DEFAULT_FORM;
+    for (int g = 1; g <= 3; ++g)
+      if (t[g - 1] < t[f - 1]) f = g;
     c->sr_pick = f;
     c->rows_pick = pk[f - 1][0];
     c->plan_row = pk[f - 1][1];
     c->plan_col = pk[f - 1][2];
   } else {
-    if (forms) c->sr_pick = 1;
+    if (forms) c->sr_pick = SR_DEFAULT_FORM;
+    if (forms && (rc = ensure_rhat(c))) return rc;
     if ((rc = tune())) return rc;
   }
   std::lock_guard<std::mutex> g(tune_mu);
@@ -532,6 +611,13 @@ template <typename T> int time_pass_t(fgcg_ctx* c, int kind, int reps, double* u
   MechMat tmat;
   if ((rc = timing_material(c, &tmat))) return rc;
   auto one = [&]() -> int {
+    if constexpr (std::is_same<T, double>::value) {
+      if (fused_active(c)) {
+        if (kind == FGCG_K_MECH_ROW_FWD) return launch_sr_row(c, -1, tmat, 0, 0.0, 1 << 30, 0, ns);
+        if (kind == FGCG_K_MECH_ROW_INV) return fail(FGCG_EUNSUPPORTED, "the two-pass form has no inverse row pass");
+        return launch_green_sr<T>(c, -1, 0, ns);
+      }
+    }
     if constexpr (std::is_same<T, double>::value)
       if (sr) {
         if (kind == FGCG_K_MECH_ROW_FWD) return launch_kp_fwd<T>(c, -1, tmat, (const T*)P.p, ns);
@@ -603,17 +689,22 @@ template <typename T> int debug_apply_t(fgcg_ctx* c, int op, const MechMat& m, c
 }
 
 // Builds the iteration closure of a context (period RELIABLE_EVERY in FP32-mixed).
+// Called once per iteration, from k = 0 (graph chunks have an even length,
+// so a chunk always starts at an even k and the parity baked into it holds).
 struct MechIterFn {
   fgcg_ctx* c;
   MechMat m;
   double tol;
   int maxit;
   int j = 0;
+  int par = 0;
   int operator()() {
-    if (c->prec == FGCG_FP64) return mech_iter<double>(c, m, tol, maxit, false);
+    const int parity = par;
+    par ^= 1;
+    if (c->prec == FGCG_FP64) return mech_iter<double>(c, m, tol, maxit, false, parity);
     const bool rel = j == RELIABLE_EVERY - 1;
     j = rel ? 0 : j + 1;
-    return mech_iter<float>(c, m, tol, maxit, rel);
+    return mech_iter<float>(c, m, tol, maxit, rel, parity);
   }
 };
 
@@ -1177,7 +1268,7 @@ static int create_ctx(const fgcg_grid* grid, void* hip_stream, int nsamp, bool b
 
 void fgcg_destroy(fgcg_ctx* c) {
   if (!c) return;
-  void* dev[] = {c->timing_E, c->rhat, c->sf_buf, c->sf_spec, c->lm_dev, c->ems,  c->phase_buf, c->strain_buf, c->twx,    c->twy,    c->twx32,  c->twy32, c->twz,
+  void* dev[] = {c->timing_E, c->rhat, c->p_odd, c->spec_q, c->sf_buf, c->sf_spec, c->lm_dev, c->ems,  c->phase_buf, c->strain_buf, c->twx,    c->twy,    c->twx32,  c->twy32, c->twz,
                  c->twz32, c->Dz,       c->red,        c->part_z, c->xh,     c->fh,     c->aux,   c->Dx,
                  c->Dy,   c->x,         c->r,          c->p,      c->tmp,    c->spec,   c->st,    c->part_a,
                  c->part_rr, c->part_b, c->part_post};
@@ -1259,6 +1350,17 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
       return FGCG_OK;
     case FGCG_OPT_MECH_PASSES:
       return fail(FGCG_EINVAL, "the number of mechanics passes is read-only");
+    case FGCG_OPT_MECH_FORM: {
+      if (value != 0 && (value < 2 || value > 4)) return fail(FGCG_EINVAL, "mechanics form 0 (tune), 2, 3 or 4");
+      if (value != 0 && value != 4 && !sr_eligible(c))
+        return fail(FGCG_EUNSUPPORTED, "the residual-spectrum forms need a 2D FP64 context with nx a multiple of 256");
+      const int pick = value == 0 ? 0 : value == 2 ? 3 : value == 3 ? 1 : 2;
+      if (pick != c->sr_pick) {
+        c->sr_pick = pick;
+        c->rows_pick = c->plan_row = c->plan_col = 0;  // the passes change: tune them again
+      }
+      return FGCG_OK;
+    }
     case FGCG_OPT_SCALAR_CG:
       if (value != 0 && value != 1) return fail(FGCG_EINVAL, "scalar CG form must be 0 or 1");
       c->scg_onered = value;
@@ -1316,7 +1418,11 @@ int fgcg_get_option(fgcg_ctx* c, int option, int* value) {
     case FGCG_OPT_STRAIN_FORM: *value = c->strain_form; return FGCG_OK;
     case FGCG_OPT_SPECTRAL_RES: *value = c->sr_opt; return FGCG_OK;
     case FGCG_OPT_SCALAR_CG: *value = c->scg_onered; return FGCG_OK;
-    case FGCG_OPT_MECH_PASSES: *value = c->ndim != 2 ? 0 : (sr_active(c) ? 3 : 4); return FGCG_OK;
+    case FGCG_OPT_MECH_PASSES: *value = c->ndim != 2 ? 0 : (fused_active(c) ? 2 : sr_active(c) ? 3 : 4); return FGCG_OK;
+    case FGCG_OPT_MECH_FORM:
+      *value = c->ndim != 2 || !sr_eligible(c) ? (c->ndim == 2 ? 4 : 0)
+                                                : (c->sr_pick == 0 ? 0 : c->sr_pick == 3 ? 2 : c->sr_pick == 1 ? 3 : 4);
+      return FGCG_OK;
     case FGCG_OPT_ROW_SPLIT: *value = c->split3; return FGCG_OK;
     case FGCG_OPT_ZTILES: *value = c->zpt_pick; return FGCG_OK;
     default: return fail(FGCG_EINVAL, "unknown option");

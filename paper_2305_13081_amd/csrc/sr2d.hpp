@@ -396,10 +396,13 @@ template <typename T> struct MechGreenSR {
     }
     if (!cg_running(st, s)) return false;
     CgState* S = st + s;
-    const int k = S->k;
+    // the iteration starts here: k = k_next (the row passes set k_next; no
+    // block of this pass reads k)
+    const int k = S->k_next;
+    const bool w = blockIdx.x == 0 && threadIdx.x == 0 && (s2 & 1) == 0;
+    if (w) S->k = k;
     const double pap = group_sum_array(part_a + (long long)s * np_a, np_a, red);
     const double rz = S->rz[k & 1];
-    const bool w = blockIdx.x == 0 && threadIdx.x == 0 && (s2 & 1) == 0;
     if (!(pap > 0.0) || !isfinite(pap)) {
       if (w) {
         S->done = 3;
@@ -477,15 +480,342 @@ template <typename T, bool E> struct MechUEpiSRC {
   __device__ void partial(int, double) const {}
 };
 
+// ------------------------------------------------------- two-pass form
+// The row stage of the residual-spectrum PCG in one pass: the inverse x
+// transforms of z_hat and the direction update that end iteration k, then
+// the stiffness stencil, its forward x transforms and the p.Kp partial sums
+// that start iteration k + 1 (with the Green column pass, two passes per
+// iteration).  A block owns SR_ROWS grid rows and transforms one more row
+// above and below them, so that the stencil finds the new direction of its
+// neighbour rows without waiting for the blocks that own them; every row is
+// one complex signal z_x + i z_y (the two displacement components of the
+// row), so a halo row is computed exactly as its owner computes it.  Hence p
+// is double-buffered (blocks read halo rows of p_k while owners write
+// p_{k+1}) and q_hat goes to a spectrum buffer of its own (blocks read halo
+// rows of z_hat while owners write q_hat).  init: p_0 = z_0 and the state of
+// the solve, as MechUEpi's init; otherwise the stop test, beta, x += alpha p_k
+// (own rows) and p_{k+1} = z + beta p_k.  When the stop test ends the solve
+// the pass does nothing but mark the last x update as due (k_sr_finish).
+// The iteration counter k is advanced by the Green pass (k = k_next), since
+// the lead block here sets k_next while other blocks still read k.
+constexpr int SR_ROWS = 2;
+// Threads per block: two columns per thread on rows of 1024, four on longer
+// rows (whose LDS allows one block per CU anyway), else NT.
+constexpr int sr_threads(int nx) { return nx >= 1024 ? nx / 2 : NT; }
+
+template <typename T> struct SrRowArgs {
+  const typename cvec<T>::type* zs;  // z_hat, [(2 s + c) spec_ss + kx ny + y]
+  typename cvec<T>::type* qs;        // q_hat, same layout, another buffer
+  const T* pin;                      // p_k, [s][c][y][x] (2 n per sample)
+  T* pout;                           // p_{k+1}
+  T* x;
+  CgState* st;
+  const double* part_rz;  // r.z partial sums of the Green pass, np_rz per sample
+  int np_rz;
+  double* part_a;  // p.Kp of every grid row, ny per sample
+  int ny;
+  long long spec_ss;
+  T ih;
+  int init;
+  double tol;
+  int maxit;
+};
+
+// Fixed-order sum of n partial sums by a block of KT threads (every block
+// gets the same value).
+template <int KT> __device__ __forceinline__ double kt_sum_array(const double* a, int n, double* red) {
+  double t = 0.0;
+  for (int i = threadIdx.x; i < n; i += KT) t += a[i];
+  t = wave_sum(t);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < KT / 64; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+
+template <typename T, int NX, int PL, bool EF, int KT = sr_threads(NX)>
+__global__ void __launch_bounds__(KT) k_sr_row(SrRowArgs<T> a, MechMat m,
+                                               const typename cvec<T>::type* __restrict__ tw) {
+  using C = typename cvec<T>::type;
+  static_assert(NX % KT == 0 && KT % 64 == 0, "k_sr_row: NX must be a multiple of the block size");
+  constexpr int R = SR_ROWS;
+  constexpr int NR = R + 2;  // transformed rows: y0 - 1 .. y0 + R
+  constexpr int XPT = NX / KT;
+  constexpr int NXH = NX / 2 + 1;
+  constexpr int ITEMS = (NR * NXH + KT - 1) / KT;
+  __shared__ C buf[lds_size(NR * NX)];
+  __shared__ double red[KT / 64];
+  __shared__ double rsum[R][KT / 64];
+  const int s = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int ny = a.ny;
+  const int y0 = xcd_block() * R;
+  const long long n = m.ss;
+  int rowy[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) rowy[r] = (((y0 - 1 + r) % ny) + ny) % ny;
+  // z_hat of the NR rows (both components), issued before the CG scalars
+  const C* z0 = a.zs + 2LL * s * a.spec_ss;
+  const C* z1 = z0 + a.spec_ss;
+  C za[ITEMS], zb[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const int idx = tid + i * KT;
+    if ((NR * NXH) % KT == 0 || idx < NR * NXH) {
+      const int r = idx % NR, kx = idx / NR;
+      const long long o = (long long)kx * ny + rowy[r];
+      za[i] = z0[o];
+      zb[i] = z1[o];
+    }
+  }
+  CgState* S = a.st + s;
+  if (!a.init && !cg_running(a.st, s)) return;
+  const double rz = kt_sum_array<KT>(a.part_rz + (long long)s * a.np_rz, a.np_rz, red);
+  double beta = 0.0;
+  if (a.init) {
+    const double thr = a.tol * a.tol * rz;
+    const int done = !isfinite(rz) ? 4 : (rz <= thr ? 1 : (a.maxit <= 0 ? 2 : 0));
+    if (lead()) {
+      CgState t;
+      t.rr_cur = t.rr_prev = 0.0;
+      t.bnorm2 = rz;
+      t.thr = thr;
+      t.rr_final = rz;
+      t.rz[0] = rz;
+      t.rz[1] = 0.0;
+      t.maxit = a.maxit;
+      t.k = 0;
+      t.k_next = 0;
+      t.iter = 0;
+      t.done = done;
+      t.zero_rhs = rz == 0.0;
+      t.alpha = 0.0;
+      t.x_pending = 0;
+      t.kk[0] = t.kk[1] = 0;
+      t.gam[0] = t.gam[1] = t.stp[0] = t.stp[1] = 0.0;
+      *S = t;
+    }
+    if (done) return;
+  } else {
+    const int k = S->k;
+    int code = 0;
+    if (!isfinite(rz)) code = 3;
+    else if (rz <= S->thr) code = 1;
+    else if (k + 1 >= S->maxit) code = 2;
+    if (code) {
+      if (lead()) {
+        S->done = code;
+        S->iter = k + 1;
+        S->rr_final = rz;
+        S->x_pending = 1;
+      }
+      return;
+    }
+    beta = rz / S->rz[k & 1];
+    if (lead()) {
+      S->rz[(k + 1) & 1] = rz;
+      S->k_next = k + 1;
+    }
+  }
+  // the rows as complex signals z_x + i z_y over the full spectrum (Hermitian
+  // extension of the half spectra; the imaginary parts at kx = 0 and NX / 2
+  // are not part of a real field's spectrum and are dropped)
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const int idx = tid + i * KT;
+    if ((NR * NXH) % KT == 0 || idx < NR * NXH) {
+      const int r = idx % NR, kx = idx / NR;
+      const C A = za[i], B = zb[i];
+      if (kx == 0 || 2 * kx == NX) {
+        buf[lds(r * NX + kx)] = C{A.x, B.x};
+      } else {
+        buf[lds(r * NX + kx)] = C{A.x - B.y, A.y + B.x};
+        buf[lds(r * NX + NX - kx)] = C{A.x + B.y, B.x - A.y};
+      }
+    }
+  }
+  const T alpha = a.init ? (T)0 : (T)S->alpha;
+  // p_k of the NR rows at the thread's columns, issued before the transforms
+  const int x0 = tid * XPT;
+  const T* pin = a.pin + 2 * n * s;
+  T* pout = a.pout + 2 * n * s;
+  T* xs = a.x + 2 * n * s;
+  T po0[NR][XPT], po1[NR][XPT], xo0[R][XPT], xo1[R][XPT];
+  if (!a.init) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int j = 0; j < XPT; ++j) {
+        const long long i = (long long)rowy[r] * NX + x0 + j;
+        po0[r][j] = pin[i];
+        po1[r][j] = pin[n + i];
+      }
+  }
+  __syncthreads();
+  fft_lds<T, NX, NR, KT, true, FlatIdx<NX>, PL>(buf, tw);
+  // x of the own rows and the material of the stress points (rows
+  // y0 - 1 .. y0 + R - 1, columns x0 - 1 .. x0 + XPT - 1), issued after the
+  // transforms (fewer registers held across them)
+  if (!a.init) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < XPT; ++j) {
+        const long long i = (long long)rowy[r + 1] * NX + x0 + j;
+        xo0[r][j] = xs[i];
+        xo1[r][j] = xs[n + i];
+      }
+  }
+  const long long so = s * n;
+  const bool dmg = m.d != nullptr;
+  uint8_t ph[EF ? 1 : R + 1][XPT + 1];
+  double ev[EF ? R + 1 : 1][XPT + 1], dd[R + 1][XPT + 1];
+#pragma unroll
+  for (int r = 0; r < R + 1; ++r)
+#pragma unroll
+    for (int j = 0; j < XPT + 1; ++j) {
+      const long long i = so + (long long)rowy[r] * NX + (x0 - 1 + j + NX) % NX;
+      if constexpr (EF)
+        ev[r][j] = m.Efield[i];
+      else
+        ph[r][j] = m.phase[i];
+      if (dmg) dd[r][j] = m.d[i];
+    }
+  // p_{k+1} = z + beta p_k on the NR rows (into LDS for the stencil), x and p
+  // of the own rows to memory
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const bool own = r >= 1 && r <= R && y0 + r - 1 < ny;
+#pragma unroll
+    for (int j = 0; j < XPT; ++j) {
+      const int li = lds(r * NX + x0 + j);
+      const C z = buf[li];
+      const T p0 = a.init ? z.x : (T)(z.x + (T)beta * po0[r][j]);
+      const T p1 = a.init ? z.y : (T)(z.y + (T)beta * po1[r][j]);
+      buf[li] = C{p0, p1};
+      if (own) {
+        const long long i = (long long)rowy[r] * NX + x0 + j;
+        pout[i] = p0;
+        pout[n + i] = p1;
+        if (!a.init) {
+          xs[i] = xo0[r - 1][j] + alpha * po0[r][j];
+          xs[n + i] = xo1[r - 1][j] + alpha * po1[r][j];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  auto lame = [&](int r, int j, double& lam, double& mu) {
+    if constexpr (EF) {
+      lam = ev[r][j] * m.lam_per_E;
+      mu = ev[r][j] * m.mu_per_E;
+    } else if (m.lm_dev) {
+      lam = m.lm_dev[16 * s + ph[r][j]];
+      mu = m.lm_dev[16 * s + 8 + ph[r][j]];
+    } else if (m.nphase <= 2) {
+      lam = ph[r][j] ? m.lm.a[1] : m.lm.a[0];
+      mu = ph[r][j] ? m.lm.b[1] : m.lm.b[0];
+    } else {
+      pick(m.lm, ph[r][j], lam, mu);
+    }
+    if (dmg) {
+      const double g = (1.0 - dd[r][j]) * (1.0 - dd[r][j]) + m.kappa;
+      lam *= g;
+      mu *= g;
+    }
+  };
+  // stress row by row (rows y0 - 1 .. y0 + R - 1, columns x0 - 1 ..
+  // x0 + XPT - 1, p from LDS), q = K p_{k+1} and the energy form of p.Kp on
+  // the own rows
+  const T ih = a.ih;
+  T q0[R][XPT], q1[R][XPT];
+  T s12p[XPT + 1], s22p[XPT + 1];
+#pragma unroll
+  for (int r = 0; r < R + 1; ++r) {
+    C pc[XPT + 2], pd[XPT + 1];
+#pragma unroll
+    for (int j = 0; j < XPT + 2; ++j) pc[j] = buf[lds(r * NX + (x0 - 1 + j + NX) % NX)];
+#pragma unroll
+    for (int j = 0; j < XPT + 1; ++j) pd[j] = buf[lds((r + 1) * NX + (x0 - 1 + j + NX) % NX)];
+    T s11[XPT + 1], s22[XPT + 1], s12[XPT + 1];
+    double e_row = 0.0;
+#pragma unroll
+    for (int j = 0; j < XPT + 1; ++j) {
+      const T g11 = (pc[j + 1].x - pc[j].x) * ih;
+      const T g12 = (pd[j].x - pc[j].x) * ih;
+      const T g21 = (pc[j + 1].y - pc[j].y) * ih;
+      const T g22 = (pd[j].y - pc[j].y) * ih;
+      const T e0 = g11, e1 = g22, e2 = (T)0.5 * (g12 + g21);
+      double lam, mu;
+      lame(r, j, lam, mu);
+      T sg[3];
+      stress2<T>(lam, mu, e0, e1, e2, sg);
+      s11[j] = sg[0];
+      s22[j] = sg[1];
+      s12[j] = sg[2];
+      if (j >= 1) e_row += (double)e0 * sg[0] + (double)e1 * sg[1] + 2.0 * (double)e2 * sg[2];
+    }
+    if (r >= 1) {
+      const int rr = r - 1;
+      const bool own = y0 + rr < ny;
+#pragma unroll
+      for (int j = 0; j < XPT; ++j) {
+        q0[rr][j] = own ? ((s11[j] - s11[j + 1]) + (s12p[j + 1] - s12[j + 1])) * ih : (T)0;
+        q1[rr][j] = own ? ((s12[j] - s12[j + 1]) + (s22p[j + 1] - s22[j + 1])) * ih : (T)0;
+      }
+      const double w = wave_sum(own ? e_row : 0.0);
+      if ((tid & 63) == 0) rsum[rr][tid >> 6] = w;
+    }
+#pragma unroll
+    for (int j = 0; j < XPT + 1; ++j) {
+      s12p[j] = s12[j];
+      s22p[j] = s22[j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+    for (int j = 0; j < XPT; ++j) buf[lds(rr * NX + x0 + j)] = C{q0[rr][j], q1[rr][j]};
+  if (tid < R && y0 + tid < ny) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < KT / 64; ++w) t += rsum[tid][w];
+    a.part_a[(long long)s * ny + y0 + tid] = t;
+  }
+  __syncthreads();
+  fft_lds<T, NX, R, KT, false, FlatIdx<NX>, PL>(buf, tw);
+  // the two components' half spectra from each row's signal, stored
+  // transposed (R consecutive y of a (component, kx) together)
+  C* q0s = a.qs + 2LL * s * a.spec_ss;
+  for (int idx = tid; idx < NXH * 2 * R; idx += KT) {
+    const int rr = idx % R, comp = (idx / R) & 1, kx = idx / (2 * R);
+    const int y = y0 + rr;
+    if (y < ny) {
+      const C z = buf[lds(rr * NX + kx)];
+      const C zm = buf[lds(rr * NX + (NX - kx) % NX)];
+      const C v = comp == 0 ? C{(T)0.5 * (z.x + zm.x), (T)0.5 * (z.y - zm.y)}
+                            : C{(T)0.5 * (z.y + zm.y), (T)0.5 * (zm.x - z.x)};
+      q0s[comp * a.spec_ss + (long long)kx * ny + y] = v;
+    }
+  }
+}
+
 // The x update still due when the stop test ended the solve in the inverse
 // pass: x += alpha p for every sample whose state says so (one launch after
 // the solve; p is the last direction, alpha its step).
+// p_odd: the direction buffer of odd iterations (the two-pass form keeps p
+// double-buffered; the same buffer as p otherwise).
 template <typename T>
-__global__ void __launch_bounds__(PT) k_sr_finish(T* __restrict__ x, const T* __restrict__ p, const CgState* st,
+__global__ void __launch_bounds__(PT) k_sr_finish(T* __restrict__ x, const T* p, const T* p_odd, const CgState* st,
                                                   long long n2) {
   const int s = blockIdx.y;
   if (!st[s].x_pending) return;
   const T a = (T)st[s].alpha;
+  if (st[s].k & 1) p = p_odd;
   x += n2 * s;
   p += n2 * s;
   for (long long i = blockIdx.x * (long long)PT + threadIdx.x; i < n2; i += (long long)gridDim.x * PT)

@@ -218,7 +218,7 @@ class Context:
 
     OPTIONS = {"scalar_spectral": 0, "graphs": 1, "chunk": 2, "rows": 3, "row_plan": 4, "col_plan": 5, "precond": 6,
                "gradient": 7, "strain_form": 8, "spectral_residual": 9, "mech_passes": 10, "scalar_cg": 11,
-               "row_split": 12, "ztiles": 13}
+               "row_split": 12, "ztiles": 13, "mech_form": 14}
     GRADIENTS = {"forward": 0, "central": 1, "central8": 2, "fourier": 3}
 
     def set_option(self, name, value):

@@ -154,11 +154,19 @@ def test_plan_option_rejects(torch_dev):
 def test_time_pass(torch_dev):
     from paper_2305_13081_amd import fgcg
     torch, dev = torch_dev
-    ctx = fgcg.Context(256, 128, H)
-    times = {k: ctx.time_pass(k, 20) for k in ("mech_row_fwd", "mech_row_inv", "mech_col")}
-    print(f"time_pass 256x128: {times}", flush=True)
-    assert all(0.0 < t < 1e4 for t in times.values())
-    assert ctx.get_option("rows") != 0  # tuned on the way
+    for form in (3, 2):
+        ctx = fgcg.Context(256, 128, H)
+        ctx.set_option("mech_form", form)
+        times = {k: ctx.time_pass(k, 20) for k in ("mech_row_fwd", "mech_col")}
+        if form == 3:
+            times["mech_row_inv"] = ctx.time_pass("mech_row_inv", 20)
+        else:  # the two-pass form has no inverse row pass
+            with pytest.raises(fgcg.FgcgError) as ei:
+                ctx.time_pass("mech_row_inv", 20)
+            assert ei.value.status == fgcg.FGCG_EUNSUPPORTED
+        print(f"time_pass 256x128 form {form}: {times}", flush=True)
+        assert all(0.0 < t < 1e4 for t in times.values())
+        assert ctx.get_option("rows") != 0  # tuned on the way
     for kind, reps in (("mech_kp", 10), ("mech_row_fwd", 0), ("mech_row_fwd", 100001)):
         with pytest.raises(fgcg.FgcgError):
             ctx.time_pass(kind, reps)
@@ -185,7 +193,7 @@ def test_tuned_picks_cached(torch_dev):
     for _ in range(2):
         ctx = fgcg.Context(nx, ny, H)
         outs.append(ctx.mech_solve(phase, E_TAB, NU_TAB, (1e-3, 0.0, 0.0), tol=1e-10, maxit=20000))
-        picks.append(tuple(ctx.get_option(o) for o in ("rows", "row_plan", "col_plan")))
+        picks.append(tuple(ctx.get_option(o) for o in ("rows", "row_plan", "col_plan", "mech_form")))
         ctx.close()
     print(f"cached picks {picks}", flush=True)
     assert picks[0] == picks[1] and all(v != 0 for v in picks[0])

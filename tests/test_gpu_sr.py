@@ -2,8 +2,11 @@
 
 2D FP64 contexts with nx a multiple of 256 keep the CG residual as its half
 spectra (the stiffness stencil fused into the forward row transform, the
-solution update in the pass that forms the next direction).  The iterates are
-those of the projected CG of Sec. 2.3 / App. A:
+solution update in the pass that forms the next direction), in three passes
+per iteration (form 3) or two (form 2: the inverse row stage of one
+iteration and the stiffness + forward row stage of the next in one pass).
+Both forms are tested.  The iterates are those of the projected CG of
+Sec. 2.3 / App. A:
 * fixed-iteration parity with the oracle's projected CG (k = 1, 2, 7, 20;
   the solve ends by the iteration limit, so the last solution update is the
   deferred one), <= 1e-12, on square, non-square and ragged grids (ny not a
@@ -47,30 +50,38 @@ def _case(ny, nx, seed):
     return phase, d, e
 
 
-SHAPES = [(256, 256), (512, 96), (768, 48), (1024, 8), (256, 12), (2048, 16)]
+# (nx, ny): square, non-square, ny not a multiple of the rows per block of
+# the three-pass form, fewer rows than a block (every supported length is even,
+# so the two rows of a two-pass block are always both in the grid)
+SHAPES = [(256, 256), (512, 96), (768, 48), (1024, 8), (256, 12), (512, 24), (2048, 16)]
+FORMS = [2, 3]
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("nx,ny", SHAPES)
-def test_sr_fixed_iterations(torch_dev, nx, ny):
+def test_sr_fixed_iterations(torch_dev, nx, ny, form):
     from paper_2305_13081_amd import fgcg
     torch, dev = torch_dev
     phase, d, e = _case(ny, nx, nx + ny)
     T = lambda a: torch.from_numpy(a).to(dev)
     ctx = fgcg.Context(nx, ny, H)
     assert ctx.get_option("spectral_residual") == 1
+    ctx.set_option("mech_form", form)
     em = (1e-3, -2e-4, 3e-4)
     for k in (1, 2, 7, 20):
-        print(f"SR fixed {nx}x{ny} k={k}", flush=True)
+        print(f"SR fixed {nx}x{ny} form {form} k={k}", flush=True)
         r = ctx.mech_solve(T(phase), E_TAB, NU_TAB, em, d=T(d), kappa=1e-6, eig=T(e), tol=0.0, maxit=k)
         o = omech.mech_solve(phase, E_TAB, NU_TAB, em, H, d=d, kappa=1e-6, e=e, fixed_iters=k)
         err = rel(r["strain"].cpu().numpy(), o["strain"])
         print(f"  iters {r['info']['iters']} strain rel {err:.2e}", flush=True)
         assert r["info"]["iters"] == k and r["info"]["status"] == 1 and err < 1e-12
+    assert ctx.get_option("mech_passes") == form
     ctx.close()
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("nx,ny,with_oracle", [(256, 256, False), (1024, 96, False), (256, 8, True)])
-def test_sr_equals_four_pass_form(torch_dev, nx, ny, with_oracle):
+def test_sr_equals_four_pass_form(torch_dev, nx, ny, with_oracle, form):
     from paper_2305_13081_amd import fgcg
     torch, dev = torch_dev
     phase, d, e = _case(ny, nx, 3 * nx + ny)
@@ -82,13 +93,16 @@ def test_sr_equals_four_pass_form(torch_dev, nx, ny, with_oracle):
     for sr in (1, 0):
         ctx = fgcg.Context(nx, ny, H)
         ctx.set_option("spectral_residual", sr)
+        if sr:
+            ctx.set_option("mech_form", form)
         out[sr] = ctx.mech_solve(*args, **kw)
+        assert ctx.get_option("mech_passes") == (form if sr else 4)
         ctx.close()
     a, b = out[1], out[0]
     errs = dict(strain=rel(a["strain"].cpu().numpy(), b["strain"].cpu().numpy()),
                 stress=rel(a["stress"].cpu().numpy(), b["stress"].cpu().numpy()),
                 energy=abs(a["energy"] - b["energy"]) / abs(b["energy"]))
-    print(f"SR vs four-pass {nx}x{ny}: iters {a['info']['iters']} / {b['info']['iters']}, {errs}", flush=True)
+    print(f"SR form {form} vs four-pass {nx}x{ny}: iters {a['info']['iters']} / {b['info']['iters']}, {errs}", flush=True)
     if with_oracle:
         o = omech.mech_solve(phase, et, NU_TAB, (1e-3, 0.0, 0.0), H, d=d, kappa=1e-6, e=e, tol=1e-13,
                              maxit=50000)
@@ -118,13 +132,15 @@ def test_sr_stiffness_hook(torch_dev):
         ctx.close()
 
 
-def test_sr_edge_cases(torch_dev):
+@pytest.mark.parametrize("form", FORMS)
+def test_sr_edge_cases(torch_dev, form):
     from paper_2305_13081_amd import fgcg
     torch, dev = torch_dev
     nx, ny = 256, 8
     phase, d, e = _case(ny, nx, 21)
     T = lambda a: torch.from_numpy(a).to(dev)
     ctx = fgcg.Context(nx, ny, H)
+    ctx.set_option("mech_form", form)
     # zero right-hand side: x = 0 after 0 iterations
     r = ctx.mech_solve(T(phase), E_TAB, NU_TAB, (0.0, 0.0, 0.0), tol=1e-10)
     assert r["info"]["iters"] == 0 and float(r["strain"].abs().max()) == 0.0
@@ -137,4 +153,26 @@ def test_sr_edge_cases(torch_dev):
     assert rel(r1["strain"].cpu().numpy(), o["strain"]) < 1e-12
     o2 = omech.mech_solve(phase, E_MILD, NU_TAB, (1e-3, 0, 0), H, d=d, kappa=1e-6, e=e, tol=1e-13, maxit=50000)
     assert rel(r2["strain"].cpu().numpy(), o2["strain"]) < 1e-10
+    ctx.close()
+
+
+def test_form_option(torch_dev):
+    """Forms 2 and 3 need the residual-spectrum conditions; 4 is always
+    accepted; out-of-range values are rejected."""
+    from paper_2305_13081_amd import fgcg
+    ctx = fgcg.Context(256, 64, H)
+    assert ctx.get_option("mech_form") == 0
+    for f in (2, 3, 4, 0):
+        ctx.set_option("mech_form", f)
+        assert ctx.get_option("mech_form") == f
+    for bad in (1, 5, -1):
+        with pytest.raises(fgcg.FgcgError) as ei:
+            ctx.set_option("mech_form", bad)
+        assert ei.value.status == fgcg.FGCG_EINVAL
+    ctx.close()
+    ctx = fgcg.Context(96, 64, H)  # nx not a multiple of 256
+    with pytest.raises(fgcg.FgcgError) as ei:
+        ctx.set_option("mech_form", 2)
+    assert ei.value.status == fgcg.FGCG_EUNSUPPORTED
+    ctx.set_option("mech_form", 4)
     ctx.close()
