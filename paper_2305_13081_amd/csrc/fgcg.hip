@@ -657,7 +657,31 @@ template <typename T> int debug_apply_t(fgcg_ctx* c, int op, const MechMat& m, c
     hipLaunchKernelGGL((k_convert<T, double>), dim3(c->npost), dim3(PT), 0, c->stream, (T*)c->p, in, n2);
     bool via_sr = false;
     if constexpr (std::is_same<T, double>::value) {
-      if (sr_active(c)) {
+      if (fused_active(c)) {
+        // the two-pass form's row stage in its init mode: z_hat = FFT_x(u) / nx
+        // (x transforms, then the identity symbol with 1/N between the y
+        // transforms) gives p_0 = u and the x spectra of K u in spec_q, which
+        // the column and row passes bring back to real space
+        if ((rc = ensure_rhat(c))) return rc;  // (allocates spec_q on first use)
+        if (!c->spec_q || !c->p_odd) return fail(FGCG_EHIP, "two-pass form buffers missing");
+        CT<T>* spec = (CT<T>*)c->spec;
+        CT<T>* sq = (CT<T>*)c->spec_q;
+        const long long ss = (long long)c->nxh * c->rows;
+        const ScaleSym<T> id{1.0 / (double)c->n};
+        const CopyProN<T, 2> cp{fld<T>(c->p, c), c->nx};
+        const StoreCompEpi<T> store{fld<T>(c->tmp, c), c->nx};
+        std::vector<double> ones((size_t)green_parts(c), 1.0);  // r.z > 0: the init does not stop
+        HIPCHK(hipMemcpyAsync(c->part_rr, ones.data(), sizeof(double) * ones.size(), hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if ((rc = launch_row_fwd<T, 2, CopyProN<T, 2>, true>(c, -1, cp, spec, 1, 2 * ss)) ||
+            (rc = launch_col<T, 1, 1, ScaleSym<T>>(c, -1, id, spec, spec, 2, ss)) ||
+            (rc = launch_sr_row(c, -1, m, 1, 0.0, 1, 0, 1)) ||
+            (rc = launch_col<T, 1, 1, ScaleSym<T>>(c, -1, id, sq, sq, 2, ss)) ||
+            (rc = launch_row_inv<T, 1, StoreCompEpi<T>>(c, -1, store, sq, 2, ss)))
+          return rc;
+        via_sr = true;
+      } else if (sr_active(c)) {
         // the stiffness of the residual-spectrum PCG (k_kp_fwd) returns x
         // transforms of q: back to real space through the column and row passes
         CT<T>* spec = (CT<T>*)c->spec;

@@ -91,7 +91,11 @@ def test_solver_operators_parity(torch_dev, nx, ny):
 
 
 def test_solver_operators_full_size(torch_dev):
-    """The 1024^2 instantiations of the staggered workload (tuned plans)."""
+    """The 1024^2 instantiations of the staggered workload (tuned plans): in
+    FP64 each mechanics form's own kernels (mech_form 2: the fused row stage,
+    whose init mode applies M's last step and whose stiffness gives K; 3: the
+    stiffness + transform pass and the inverse pass; 4: the stencil pass and
+    the four-pass transforms), and the form the tuner keeps."""
     from paper_2305_13081_amd import fgcg
     torch, dev = torch_dev
     n = 1024
@@ -100,15 +104,20 @@ def test_solver_operators_full_size(torch_dev):
     d = 0.5 * rng.random((n, n))
     u = rng.standard_normal((2, n, n))
     q_ref, z_ref = _k_m_refs(phase, d, u)
-    for prec, bar in ((fgcg.FP64, 1e-12), (fgcg.FP32_MIXED, 1e-5)):
+    cases = [(fgcg.FP64, 1e-12, f) for f in (0, 2, 3, 4)] + [(fgcg.FP32_MIXED, 1e-5, 0)]
+    for prec, bar, form in cases:
         ctx = fgcg.Context(n, n, H, precision=prec)
+        if form:
+            ctx.set_option("mech_form", form)
         args = (torch.from_numpy(phase).to(dev), E_TAB, NU_TAB, torch.from_numpy(u).to(dev))
+        z = ctx.debug_apply(fgcg.OP_MECH_M, *args).cpu().numpy()  # (tunes the passes and the form)
         q = ctx.debug_apply(fgcg.OP_MECH_K, *args, d=torch.from_numpy(d).to(dev), kappa=1e-6).cpu().numpy()
-        z = ctx.debug_apply(fgcg.OP_MECH_M, *args).cpu().numpy()
         eq, ez = maxrel(q, q_ref), maxrel(z, z_ref)
-        print(f"1024^2 prec {prec} plans {ctx.get_option('row_plan')}/{ctx.get_option('col_plan')}: "
-              f"K max rel {eq:.2e}, M max rel {ez:.2e}", flush=True)
+        print(f"1024^2 prec {prec} form {ctx.get_option('mech_passes')} plans {ctx.get_option('row_plan')}/"
+              f"{ctx.get_option('col_plan')}: K max rel {eq:.2e}, M max rel {ez:.2e}", flush=True)
         assert eq < bar and ez < bar
+        if form:
+            assert ctx.get_option("mech_passes") == form
         ctx.close()
 
 

@@ -13,7 +13,8 @@ Sec. 2.3 / App. A:
   multiple of the rows per block, fewer rows than a block holds);
 * converged solves equal the four-pass form (option off) to 1e-10 with the
   same iteration count, and the oracle to 1e-10;
-* the stiffness of the fused pass, brought back to real space, equals the
+* the stiffness of each form's own kernel (the fused row stage, the stiffness
+  + transform pass, the stencil pass), brought back to real space, equals the
   sparse stencil matrix element-wise (<= 1e-12);
 * zero right-hand side, and a solve that converges at the first test.
 """
@@ -122,12 +123,12 @@ def test_sr_stiffness_hook(torch_dev):
     u = np.random.default_rng(12).standard_normal((2, ny, nx))
     q_ref = odir.mech_stiffness_apply(phase, E_TAB, NU_TAB, u, H, d=d, kappa=1e-6)
     T = lambda a: torch.from_numpy(a).to(dev)
-    for sr in (1, 0):
+    for form in (2, 3, 4):  # the fused row stage, the stiffness + transform pass, the stencil pass
         ctx = fgcg.Context(nx, ny, H)
-        ctx.set_option("spectral_residual", sr)
+        ctx.set_option("mech_form", form)
         q = ctx.debug_apply(fgcg.OP_MECH_K, T(phase), E_TAB, NU_TAB, T(u), d=T(d), kappa=1e-6).cpu().numpy()
         err = maxrel(q, q_ref)
-        print(f"K hook spectral_residual={sr}: max rel {err:.2e}", flush=True)
+        print(f"K hook form {form}: max rel {err:.2e}", flush=True)
         assert err < 1e-12
         ctx.close()
 
