@@ -113,10 +113,10 @@ KINDS_3D = ["mech_kp", "mech_row_fwd", "mech_y_fwd", "mech_col", "mech_y_inv", "
 # kernel sources they were taken with: the key is the SHA-256 of csrc/.
 MEASURED_TRAFFIC = {
     # hash of the 2D pass sources -> {kernel kind: HBM bytes per launch}
-    # (profiles/mech_passes_1024_fp64_hbm_traffic.md); the residual-spectrum
-    # form: mech_row_fwd is the fused stiffness + transform pass
-    "401b928545c63373c9bbc4a37b5101774e90ba832d5a8acee74a9e741b725c26": {
-        "mech_row_fwd": 43200963, "mech_col": 66186972, "mech_row_inv": 82755107},
+    # (profiles/mech_passes_1024_fp64_hbm_traffic.md); the two-pass
+    # residual-spectrum form: mech_row_fwd is the fused row stage
+    "024a96f7b009c4a976e22696f87e9515f996ffbcdb528a6fb8dd77f9e149198c": {
+        "mech_row_fwd": 110673000, "mech_col": 65986294},
 }
 
 
