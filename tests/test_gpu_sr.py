@@ -16,7 +16,9 @@ Sec. 2.3 / App. A:
 * the stiffness of each form's own kernel (the fused row stage, the stiffness
   + transform pass, the stencil pass), brought back to real space, equals the
   sparse stencil matrix element-wise (<= 1e-12);
-* zero right-hand side, and a solve that converges at the first test.
+* zero right-hand side, and a solve that converges at the first test;
+* the fracture regime: a band with d up to 0.999 (g(d) down to about kappa),
+  fixed-iteration parity.
 """
 import numpy as np
 import pytest
@@ -77,6 +79,31 @@ def test_sr_fixed_iterations(torch_dev, nx, ny, form):
         print(f"  iters {r['info']['iters']} strain rel {err:.2e}", flush=True)
         assert r["info"]["iters"] == k and r["info"]["status"] == 1 and err < 1e-12
     assert ctx.get_option("mech_passes") == form
+    ctx.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_sr_fracture_regime(torch_dev, form):
+    """A cracked band (d up to 0.999: g(d) down to about kappa) across the
+    grid, fixed-iteration parity with the oracle's projected CG."""
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    nx, ny = 512, 64
+    phase, d, e = _case(ny, nx, 31)
+    yy = np.arange(ny)[:, None] * np.ones((1, nx))
+    d = np.where(np.abs(yy - ny / 2) < 3, 0.9 + 0.099 * np.random.default_rng(32).random((ny, nx)), d)
+    T = lambda a: torch.from_numpy(a).to(dev)
+    ctx = fgcg.Context(nx, ny, H)
+    ctx.set_option("mech_form", form)
+    em = (1e-3, 2e-4, -3e-4)
+    for k in (1, 5, 20):
+        print(f"SR fracture form {form} k={k}", flush=True)
+        r = ctx.mech_solve(T(phase), E_TAB, NU_TAB, em, d=T(d), kappa=1e-6, eig=T(e), tol=0.0, maxit=k)
+        o = omech.mech_solve(phase, E_TAB, NU_TAB, em, H, d=d, kappa=1e-6, e=e, fixed_iters=k)
+        err = rel(r["strain"].cpu().numpy(), o["strain"])
+        emax = maxrel(r["strain"].cpu().numpy(), o["strain"])
+        print(f"  strain rel {err:.2e}, max rel {emax:.2e}", flush=True)
+        assert r["info"]["iters"] == k and err < 1e-12 and emax < 1e-12
     ctx.close()
 
 
