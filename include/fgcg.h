@@ -157,18 +157,20 @@ const char* fgcg_last_error(void);
  *       three half spectra).
  *   FGCG_OPT_SPECTRAL_RES     1 (default): the mechanics PCG of 2D FP64
  *       contexts with the unit Green operator and the forward difference, on
- *       grids whose nx is a multiple of 256, keeps the residual as its half
+ *       grids whose nx is a multiple of 64, keeps the residual as its half
  *       spectra: r_hat -= alpha FFT(K p) in the Green column pass and the
  *       solution update x += alpha p in the pass that forms the next
- *       direction, so that the stiffness stencil is applied inside the
- *       forward row transform (three passes per iteration instead of four,
- *       185 instead of 233 bytes per voxel).  The same alpha, beta and stop
- *       test as the projected CG of eq. solid-final (rounding aside); 0: the
- *       four-pass form everywhere.  Allocates two half spectra on the first
- *       solve that uses it.  On grids of at least 2^18 voxels the autotuner
- *       (before the first mechanics solve) tunes the passes of both forms,
- *       times one whole iteration of each and keeps the faster; smaller grids
- *       take the residual-spectrum form.
+ *       direction, so that the stiffness stencil is applied inside a row
+ *       transform: two passes per iteration (the row stage fused, see
+ *       FGCG_OPT_MECH_FORM) or, where nx is a multiple of 256, three (185
+ *       instead of 233 bytes per voxel).  The same alpha, beta and stop test
+ *       as the projected CG of eq. solid-final (rounding aside); 0: the
+ *       four-pass form everywhere.  Allocates the residual's half spectra
+ *       (and the two-pass form's buffers) on the first solve that uses them.
+ *       On grids of at least 2^18 voxels the autotuner (before the first
+ *       mechanics solve) tunes the passes of every available form, times one
+ *       whole iteration of each and keeps the fastest; smaller grids take the
+ *       two-pass form.
  *   FGCG_OPT_MECH_PASSES      read only (fgcg_get_option): transform and
  *       stencil passes per mechanics CG iteration of a 2D context's current
  *       form, 2, 3 or 4 (after the first mechanics solve, which tunes it); 0
@@ -184,7 +186,8 @@ const char* fgcg_last_error(void);
  *       K p gets its own half spectra: one more direction field and two more
  *       half spectra of memory); 3: the residual spectra in three passes; 4:
  *       four passes.  EUNSUPPORTED for 2 and 3 where FGCG_OPT_SPECTRAL_RES
- *       does not apply.  All forms give the same iterates up to rounding.
+ *       does not apply, and for 3 where nx is not a multiple of 256.  All
+ *       forms give the same iterates up to rounding.
  *   FGCG_OPT_SCALAR_CG        the CG of the stencil phase-field and diffusion
  *       solves on 2D grids: 1 (default) the one-reduction form of Chronopoulos
  *       and Gear (w = A r and s = A p carried along; one pass per iteration

@@ -603,16 +603,22 @@ inline int make_mech_mat(const fgcg_ctx* c, const fgcg_material* mat, const doub
 // solver's passes do their full work outside a solve (timing, test hooks).
 // The residual-spectrum mechanics PCG (sr2d.hpp) runs in 2D FP64 contexts
 // with the unit Green operator and the forward difference, on rows whose
-// length is a multiple of the block size; every other mechanics solve keeps
-// the four-pass form.
+// length is a multiple of 64 (of 256 for its three-pass form); every other
+// mechanics solve keeps the four-pass form.
 inline bool sr_eligible(const fgcg_ctx* c) {
   return c->sr_opt && c->ndim == 2 && c->prec == FGCG_FP64 && c->precond == 0 && c->gradop == 0 &&
-         !c->strain_form && c->nx % NT == 0;
+         !c->strain_form && c->nx % 64 == 0;
 }
-// (on grids of at least 2^18 voxels the tuner times both forms and may keep
+// The three-pass form's stiffness + transform pass needs rows of a multiple
+// of 256; the two-pass form's row stage one of 64.
+inline bool sr3_ok(const fgcg_ctx* c) { return sr_eligible(c) && c->nx % NT == 0; }
+// The form in use: 2 (four passes) where the residual spectra do not apply,
+// else the tuned or pinned pick, the two-pass form (3) before tuning.
+inline int sr_form(const fgcg_ctx* c) { return !sr_eligible(c) ? 2 : c->sr_pick ? c->sr_pick : 3; }
+// (on grids of at least 2^18 voxels the tuner times the forms and may keep
 // the four-pass form: sr_pick = 2)
-inline bool sr_active(const fgcg_ctx* c) { return sr_eligible(c) && c->sr_pick != 2; }
-inline bool fused_active(const fgcg_ctx* c) { return sr_eligible(c) && c->sr_pick == 3; }
+inline bool sr_active(const fgcg_ctx* c) { return sr_form(c) != 2; }
+inline bool fused_active(const fgcg_ctx* c) { return sr_form(c) == 3; }
 
 inline int running_state(fgcg_ctx* c) {
   std::vector<CgState> hs(c->nsamp);

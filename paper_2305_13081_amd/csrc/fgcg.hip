@@ -76,7 +76,7 @@ inline int launch_sr_row(fgcg_ctx* c, int kind, const MechMat& m, int init, doub
   int rc = 0;
   with_n(c->nx, [&](auto NXc) {
     constexpr int NX = decltype(NXc)::value;
-    if constexpr (NX % NT == 0) {
+    if constexpr (NX % 64 == 0) {
       double* pe = (double*)c->p;
       double* po = (double*)c->p_odd;
       const SrRowArgs<double> a{(const double2*)c->spec, (double2*)c->spec_q, parity ? po : pe,
@@ -91,7 +91,7 @@ inline int launch_sr_row(fgcg_ctx* c, int kind, const MechMat& m, int init, doub
         rc = launch_b(c, kind, fn, g, dim3(sr_threads(NX)), a, m, tw_x<double>(c));
       });
     } else {
-      rc = fail(FGCG_EUNSUPPORTED, "residual-spectrum PCG needs nx a multiple of 256");
+      rc = fail(FGCG_EUNSUPPORTED, "the two-pass form needs nx a multiple of 64");
     }
   });
   return rc;
@@ -567,6 +567,10 @@ inline int tune_passes(fgcg_ctx* c) {
     float t[3] = {0.f, 0.f, 0.f};
     std::array<int, 3> pk[3];
     for (int f = 1; f <= 3; ++f) {
+      if (f == 1 && !sr3_ok(c)) {
+        t[0] = 3.0e38f;  // no three-pass form on these rows
+        continue;
+      }
       c->rows_pick = r0;
       c->plan_row = p0;
       c->plan_col = q0;
@@ -1377,7 +1381,8 @@ int fgcg_set_option(fgcg_ctx* c, int option, int value) {
     case FGCG_OPT_MECH_FORM: {
       if (value != 0 && (value < 2 || value > 4)) return fail(FGCG_EINVAL, "mechanics form 0 (tune), 2, 3 or 4");
       if (value != 0 && value != 4 && !sr_eligible(c))
-        return fail(FGCG_EUNSUPPORTED, "the residual-spectrum forms need a 2D FP64 context with nx a multiple of 256");
+        return fail(FGCG_EUNSUPPORTED, "the residual-spectrum forms need a 2D FP64 context with nx a multiple of 64");
+      if (value == 3 && !sr3_ok(c)) return fail(FGCG_EUNSUPPORTED, "the three-pass form needs nx a multiple of 256");
       const int pick = value == 0 ? 0 : value == 2 ? 3 : value == 3 ? 1 : 2;
       if (pick != c->sr_pick) {
         c->sr_pick = pick;

@@ -499,9 +499,13 @@ template <typename T, bool E> struct MechUEpiSRC {
 // The iteration counter k is advanced by the Green pass (k = k_next), since
 // the lead block here sets k_next while other blocks still read k.
 constexpr int SR_ROWS = 2;
-// Threads per block: two columns per thread on rows of 1024, four on longer
-// rows (whose LDS allows one block per CU anyway), else NT.
-constexpr int sr_threads(int nx) { return nx >= 1024 ? nx / 2 : NT; }
+// Threads per block: two columns per thread on rows of 1024 and more (the
+// registers of NR rows of p per column bound occupancy); shorter rows: NT
+// threads where they divide the row, else 128 or one wavefront (rows that
+// are a multiple of 64).
+constexpr int sr_threads(int nx) {
+  return nx >= 1024 ? nx / 2 : nx % NT == 0 ? NT : nx % 128 == 0 ? 128 : 64;
+}
 
 template <typename T> struct SrRowArgs {
   const typename cvec<T>::type* zs;  // z_hat, [(2 s + c) spec_ss + kx ny + y]

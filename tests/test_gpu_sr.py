@@ -1,11 +1,12 @@
 """GPU parity of the residual-spectrum mechanics PCG through the C ABI.
 
-2D FP64 contexts with nx a multiple of 256 keep the CG residual as its half
+2D FP64 contexts with nx a multiple of 64 keep the CG residual as its half
 spectra (the stiffness stencil fused into the forward row transform, the
 solution update in the pass that forms the next direction), in three passes
 per iteration (form 3) or two (form 2: the inverse row stage of one
-iteration and the stiffness + forward row stage of the next in one pass).
-Both forms are tested.  The iterates are those of the projected CG of
+iteration and the stiffness + forward row stage of the next in one pass;
+the only residual-spectrum form where nx is not a multiple of 256).  Both
+forms are tested.  The iterates are those of the projected CG of
 Sec. 2.3 / App. A:
 * fixed-iteration parity with the oracle's projected CG (k = 1, 2, 7, 20;
   the solve ends by the iteration limit, so the last solution update is the
@@ -58,10 +59,12 @@ def _case(ny, nx, seed):
 # so the two rows of a two-pass block are always both in the grid)
 SHAPES = [(256, 256), (512, 96), (768, 48), (1024, 8), (256, 12), (512, 24), (2048, 16)]
 FORMS = [2, 3]
+# rows that are a multiple of 64 but not of 256: the two-pass form only (one
+# wavefront or 128 threads per block)
+SHAPES_64 = [(64, 64), (128, 48), (192, 24), (384, 32)]
 
 
-@pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("nx,ny", SHAPES)
+@pytest.mark.parametrize("nx,ny,form", [s + (f,) for f in FORMS for s in SHAPES] + [s + (2,) for s in SHAPES_64])
 def test_sr_fixed_iterations(torch_dev, nx, ny, form):
     from paper_2305_13081_amd import fgcg
     torch, dev = torch_dev
@@ -107,8 +110,9 @@ def test_sr_fracture_regime(torch_dev, form):
     ctx.close()
 
 
-@pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("nx,ny,with_oracle", [(256, 256, False), (1024, 96, False), (256, 8, True)])
+@pytest.mark.parametrize("nx,ny,with_oracle,form", [(256, 256, False, 2), (1024, 96, False, 2), (256, 8, True, 2),
+                                                     (256, 256, False, 3), (1024, 96, False, 3), (256, 8, True, 3),
+                                                     (64, 64, True, 2), (384, 32, False, 2)])
 def test_sr_equals_four_pass_form(torch_dev, nx, ny, with_oracle, form):
     from paper_2305_13081_amd import fgcg
     torch, dev = torch_dev
@@ -198,9 +202,15 @@ def test_form_option(torch_dev):
             ctx.set_option("mech_form", bad)
         assert ei.value.status == fgcg.FGCG_EINVAL
     ctx.close()
-    ctx = fgcg.Context(96, 64, H)  # nx not a multiple of 256
+    ctx = fgcg.Context(96, 64, H)  # nx not a multiple of 64
     with pytest.raises(fgcg.FgcgError) as ei:
         ctx.set_option("mech_form", 2)
     assert ei.value.status == fgcg.FGCG_EUNSUPPORTED
     ctx.set_option("mech_form", 4)
+    ctx.close()
+    ctx = fgcg.Context(128, 64, H)  # a multiple of 64, not of 256: no three-pass form
+    ctx.set_option("mech_form", 2)
+    with pytest.raises(fgcg.FgcgError) as ei:
+        ctx.set_option("mech_form", 3)
+    assert ei.value.status == fgcg.FGCG_EUNSUPPORTED
     ctx.close()
