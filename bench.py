@@ -115,8 +115,8 @@ MEASURED_TRAFFIC = {
     # hash of the 2D pass sources -> {kernel kind: HBM bytes per launch}
     # (profiles/mech_passes_1024_fp64_hbm_traffic.md); the two-pass
     # residual-spectrum form: mech_row_fwd is the fused row stage
-    "024a96f7b009c4a976e22696f87e9515f996ffbcdb528a6fb8dd77f9e149198c": {
-        "mech_row_fwd": 110673000, "mech_col": 65986294},
+    "48cb673b8604369364b17baef4517164cb8b399cef232548d3dceab354610938": {
+        "mech_row_fwd": 110689548, "mech_col": 65986421},
 }
 
 
