@@ -115,8 +115,8 @@ MEASURED_TRAFFIC = {
     # hash of the 2D pass sources -> {kernel kind: HBM bytes per launch}
     # (profiles/mech_passes_1024_fp64_hbm_traffic.md); the two-pass
     # residual-spectrum form: mech_row_fwd is the fused row stage
-    "48cb673b8604369364b17baef4517164cb8b399cef232548d3dceab354610938": {
-        "mech_row_fwd": 110689548, "mech_col": 65986421},
+    "656aa0d4b0023065ef3a7d5530a041da0f584925a16c0e199e4142353b5cd033": {
+        "mech_row_fwd": 110683231, "mech_col": 65986538},
 }
 
 

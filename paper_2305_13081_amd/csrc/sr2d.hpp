@@ -6,10 +6,11 @@
 // it can be carried out on the spectra, r_hat -= alpha FFT(q).  The solution
 // update x += alpha p can wait until the pass that forms the next direction,
 // which reads p anyway.  One iteration is then three passes instead of four:
-//   k_kp_fwd           q = K p as a real-space stencil for the rows of the
-//                      block (one displacement component per block), the
-//                      forward x transform of q, partial sums of p.Kp in the
-//                      energy form sum sym(grad p) : g C : sym(grad p)
+//   k_kp_fwd2          q = K p as a real-space stencil for the rows of the
+//                      block (both displacement components; k_kp_fwd: one
+//                      per block), the forward x transforms of q, partial
+//                      sums of p.Kp in the energy form
+//                      sum sym(grad p) : g C : sym(grad p)
 //   col (MechGreenSR)  alpha = r.z / p.Kp; y transforms; r_hat -= alpha q_hat
 //                      (stored); z_hat = r_hat / |D|^2 / N; partial sums of
 //                      r.z; inverse y transforms of z_hat
@@ -20,7 +21,9 @@
 // last x update is still due; k_sr_finish applies it after the solve.
 // Algorithmic bytes per voxel (FP64, 2 components, half spectra
 // (nx/2+1)/nx * 16 B per component): 41 + 64.1 + 80.0 = 185 against 233 for
-// the four-pass form.
+// the four-pass form.  The two-pass form (k_sr_row, below) does the inverse
+// pass of one iteration and the stiffness pass of the next in one kernel:
+// 105.1 + 64.1 = 169.2 bytes per voxel and one launch fewer.
 #pragma once
 #include "mech_u.hpp"
 
