@@ -64,3 +64,29 @@ def test_create_rejects_bad_grids_without_gpu(lib):
     assert L.fgcg_create(ctypes.byref(g), None, ctypes.byref(out)) == -1
     g = fgcg.Grid(4, (ctypes.c_int * 3)(64, 64, 64), 1.0, 0)
     assert L.fgcg_create(ctypes.byref(g), None, ctypes.byref(out)) == -1
+
+
+def header_enum(prefix):
+    """Name -> value of the enum constants of include/fgcg.h with a prefix."""
+    text = open(os.path.join(ROOT, "include", "fgcg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return {m.group(1): int(m.group(2)) for m in re.finditer(rf"\b({prefix}[A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+
+
+def test_binding_options_match_header():
+    """Every context option of the header has a binding name with the same
+    value, and no binding name points at a value the header lacks."""
+    hdr = header_enum("FGCG_OPT_")
+    assert sorted(hdr.values()) == sorted(fgcg.Context.OPTIONS.values())
+    by_value = {v: k for k, v in fgcg.Context.OPTIONS.items()}
+    for name, v in hdr.items():
+        words = name[len("FGCG_OPT_"):].lower()
+        assert by_value[v].replace("_", "") .startswith(words.replace("_", "")[:4]), (name, by_value[v])
+
+
+def test_binding_status_and_precision_constants_match_header():
+    for name, v in header_enum("FGCG_E").items():
+        assert getattr(fgcg, name) == v, name
+    assert fgcg.FGCG_OK == header_enum("FGCG_OK")["FGCG_OK"]
+    prec = header_enum("FGCG_FP")
+    assert (fgcg.FP64, fgcg.FP32_MIXED) == (prec["FGCG_FP64"], prec["FGCG_FP32_MIXED"])
