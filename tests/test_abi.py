@@ -87,6 +87,6 @@ def test_binding_options_match_header():
 def test_binding_status_and_precision_constants_match_header():
     for name, v in header_enum("FGCG_E").items():
         assert getattr(fgcg, name) == v, name
-    assert fgcg.FGCG_OK == header_enum("FGCG_OK")["FGCG_OK"]
+    assert fgcg.FGCG_OK == header_enum("FGCG_O")["FGCG_OK"]
     prec = header_enum("FGCG_FP")
     assert (fgcg.FP64, fgcg.FP32_MIXED) == (prec["FGCG_FP64"], prec["FGCG_FP32_MIXED"])
