@@ -530,7 +530,10 @@ int fgcg_debug_fft(fgcg_ctx* ctx, int dir, const double* in, double* out);
 /* ---- profiling -------------------------------------------------------- */
 /* Measurement hook for the HBM roofline of the 2D mechanics passes (Sec. 2.6
  * iteration): launches the pass of kind FGCG_K_MECH_ROW_FWD, _ROW_INV or
- * _COL (enum below) reps times back to back (after 3 untimed launches) on the
+ * _COL (enum below; of the context's iteration form: in the two-pass form
+ * _ROW_FWD is the fused row stage and there is no _ROW_INV, EUNSUPPORTED;
+ * in the three-pass form _ROW_FWD is the stiffness + transform pass) reps
+ * times back to back (after 3 untimed launches) on the
  * context's stream, between two HIP events, with the context's tuned rows per
  * block and radix plans (tuned first if not yet tuned), and stores the
  * average duration of one launch in microseconds (host double).  Unlike
