@@ -239,3 +239,27 @@ def test_two_pass_graph_chunks(torch_dev):
         ctx.close()
     for it, st in outs[1:]:
         assert it == outs[0][0] and np.array_equal(st, outs[0][1])
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_sr_three_phases(torch_dev, form):
+    """Three phases (the general per-phase table lookup of the stiffness
+    stencil, not the two-phase selection), fixed-iteration parity."""
+    from paper_2305_13081_amd import fgcg
+    torch, dev = torch_dev
+    nx, ny = 256, 32
+    rng = np.random.default_rng(51)
+    phase = rng.integers(0, 3, (ny, nx)).astype(np.uint8)
+    d = 0.3 * rng.random((ny, nx))
+    e = np.where(phase == 0, 1e-3, 0.0)
+    E3, NU3 = (3e6, 30e9, 5e9), (0.2, 0.2, 0.3)
+    T = lambda a: torch.from_numpy(a).to(dev)
+    ctx = fgcg.Context(nx, ny, H)
+    ctx.set_option("mech_form", form)
+    for k in (3, 12):
+        r = ctx.mech_solve(T(phase), E3, NU3, (1e-3, -2e-4, 1e-4), d=T(d), kappa=1e-6, eig=T(e), tol=0.0, maxit=k)
+        o = omech.mech_solve(phase, E3, NU3, (1e-3, -2e-4, 1e-4), H, d=d, kappa=1e-6, e=e, fixed_iters=k)
+        err = maxrel(r["strain"].cpu().numpy(), o["strain"])
+        print(f"SR three phases form {form} k={k}: max rel {err:.2e}", flush=True)
+        assert r["info"]["iters"] == k and err < 1e-12
+    ctx.close()
